@@ -1,0 +1,477 @@
+/*
+ * CPU oracle for time-vectorized backward-Euler integration.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include, link,
+ * load or call this file; only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark use it.  It shares no code with the HIP
+ * library.
+ *
+ * What it computes is the plain definition of the result the chunked method
+ * reaches (Section 2.2, Eq. backward-euler): for every series, the sequence
+ * y_1..y_N with
+ *
+ *     y_k - y_{k-1} - (t_k - t_{k-1}) h(y_k, t_k; p) = 0,
+ *
+ * found one step at a time by Newton's method started from the previous
+ * converged state (Section 2.2, the zero-order-hold starting guess), with a
+ * dense LU solve of the discrete Jacobian I - dt j (Section 2.2) at every
+ * iteration.  The gradient is the discrete adjoint of that computed map
+ * (Appendix A: the same scheme for the forward and the backward problem).
+ *
+ * Everything is IEEE double, no fast-math.  Series are independent
+ * (Section 2.1) and are distributed over a pthread pool, longest first.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NMAX 16
+#define HMAX 512
+
+/* ------------------------------------------------------------------------ */
+/* Dense LU with partial pivoting (ties go to the lowest row index).         */
+/* Solves A x = b in place for an n x n row-major A; returns 0 on success,   */
+/* 1 when a pivot is zero or not finite.                                     */
+/* ------------------------------------------------------------------------ */
+static int lu_solve(int n, double *A, double *b)
+{
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        double best = fabs(A[c * n + c]);
+        for (int r = c + 1; r < n; ++r) {
+            double v = fabs(A[r * n + c]);
+            if (v > best) { best = v; piv = r; }
+        }
+        if (!(best > 0.0) || !isfinite(best)) return 1;
+        if (piv != c) {
+            for (int k = 0; k < n; ++k) {
+                double t = A[c * n + k]; A[c * n + k] = A[piv * n + k]; A[piv * n + k] = t;
+            }
+            double t = b[c]; b[c] = b[piv]; b[piv] = t;
+        }
+        double inv = 1.0 / A[c * n + c];
+        for (int r = c + 1; r < n; ++r) {
+            double l = A[r * n + c] * inv;
+            if (l == 0.0) continue;
+            for (int k = c + 1; k < n; ++k) A[r * n + k] -= l * A[c * n + k];
+            b[r] -= l * b[c];
+        }
+    }
+    for (int r = n - 1; r >= 0; --r) {
+        double s = b[r];
+        for (int k = r + 1; k < n; ++k) s -= A[r * n + k] * b[k];
+        b[r] = s / A[r * n + r];
+    }
+    return 0;
+}
+
+int oracle_lu_solve(int n, double *A, double *b) { return lu_solve(n, A, b); }
+
+/* ------------------------------------------------------------------------ */
+/* Model right-hand sides h(y, t; p), their state Jacobians j = dh/dy and     */
+/* the parameter vector-Jacobian products (dh/dp)^T w.                        */
+/* ------------------------------------------------------------------------ */
+
+int oracle_param_count(int kind, int n, int hidden)
+{
+    switch (kind) {
+    case ORACLE_LINEAR:    return n * n;
+    case ORACLE_VANDERPOL: return 1;
+    case ORACLE_ROBERTSON: return 3;
+    case ORACLE_MLP:       return hidden * n + hidden + hidden * hidden + hidden + n * hidden + n;
+    default:               return -1;
+    }
+}
+
+/* MLP forward: a1 = tanh(W1 y + b1), a2 = tanh(W2 a1 + b2), f = W3 a2 + b3. */
+static void mlp_forward(int n, int H, const double *th, const double *y,
+                        double *a1, double *a2, double *f)
+{
+    const double *W1 = th, *b1 = W1 + H * n, *W2 = b1 + H, *b2 = W2 + H * H,
+                 *W3 = b2 + H, *b3 = W3 + n * H;
+    for (int i = 0; i < H; ++i) {
+        double s = b1[i];
+        for (int k = 0; k < n; ++k) s += W1[i * n + k] * y[k];
+        a1[i] = tanh(s);
+    }
+    for (int i = 0; i < H; ++i) {
+        double s = b2[i];
+        for (int k = 0; k < H; ++k) s += W2[i * H + k] * a1[k];
+        a2[i] = tanh(s);
+    }
+    for (int i = 0; i < n; ++i) {
+        double s = b3[i];
+        for (int k = 0; k < H; ++k) s += W3[i * H + k] * a2[k];
+        f[i] = s;
+    }
+}
+
+/* f = h(y,t;p); if J != NULL also J = dh/dy (row-major n x n). */
+static void rhs(int kind, int n, int H, const double *y, double t, const double *p,
+                double *f, double *J)
+{
+    (void)t;
+    switch (kind) {
+    case ORACLE_LINEAR:
+        for (int i = 0; i < n; ++i) {
+            double s = 0.0;
+            for (int k = 0; k < n; ++k) s += p[i * n + k] * y[k];
+            f[i] = s;
+        }
+        if (J) memcpy(J, p, sizeof(double) * n * n);
+        break;
+    case ORACLE_VANDERPOL: {
+        double mu = p[0];
+        f[0] = y[1];
+        f[1] = mu * (1.0 - y[0] * y[0]) * y[1] - y[0];
+        if (J) {
+            J[0] = 0.0;                          J[1] = 1.0;
+            J[2] = -2.0 * mu * y[0] * y[1] - 1.0; J[3] = mu * (1.0 - y[0] * y[0]);
+        }
+        break;
+    }
+    case ORACLE_ROBERTSON: {
+        double k1 = 0.04 * p[0], k2 = 3.0e7 * p[1], k3 = 1.0e4 * p[2];
+        f[0] = -k1 * y[0] + k3 * y[1] * y[2];
+        f[1] = k1 * y[0] - k3 * y[1] * y[2] - k2 * y[1] * y[1];
+        f[2] = k2 * y[1] * y[1];
+        if (J) {
+            J[0] = -k1; J[1] = k3 * y[2];                     J[2] = k3 * y[1];
+            J[3] = k1;  J[4] = -k3 * y[2] - 2.0 * k2 * y[1];  J[5] = -k3 * y[1];
+            J[6] = 0.0; J[7] = 2.0 * k2 * y[1];               J[8] = 0.0;
+        }
+        break;
+    }
+    case ORACLE_MLP: {
+        double a1[HMAX], a2[HMAX];
+        mlp_forward(n, H, p, y, a1, a2, f);
+        if (J) {
+            /* J = W3 diag(1-a2^2) W2 diag(1-a1^2) W1, built column by column
+               as the Jacobian-vector product with each unit vector. */
+            const double *W1 = p, *W2 = W1 + H * n + H, *W3 = W2 + H * H + H;
+            double u1[HMAX], u2[HMAX];
+            for (int c = 0; c < n; ++c) {
+                for (int i = 0; i < H; ++i) u1[i] = (1.0 - a1[i] * a1[i]) * W1[i * n + c];
+                for (int i = 0; i < H; ++i) {
+                    double s = 0.0;
+                    for (int k = 0; k < H; ++k) s += W2[i * H + k] * u1[k];
+                    u2[i] = (1.0 - a2[i] * a2[i]) * s;
+                }
+                for (int i = 0; i < n; ++i) {
+                    double s = 0.0;
+                    for (int k = 0; k < H; ++k) s += W3[i * H + k] * u2[k];
+                    J[i * n + c] = s;
+                }
+            }
+        }
+        break;
+    }
+    }
+}
+
+/* gp += (dh/dp (y,t;p))^T w */
+static void vjp_p(int kind, int n, int H, const double *y, double t, const double *p,
+                  const double *w, double *gp)
+{
+    (void)t;
+    switch (kind) {
+    case ORACLE_LINEAR: /* h_i = sum_k A_ik y_k  ->  dL/dA_ik = w_i y_k */
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k) gp[i * n + k] += w[i] * y[k];
+        break;
+    case ORACLE_VANDERPOL: /* dh/dmu = (0, (1-y1^2) y2) */
+        gp[0] += w[1] * (1.0 - y[0] * y[0]) * y[1];
+        break;
+    case ORACLE_ROBERTSON: {
+        double d1 = 0.04 * (-w[0] * y[0] + w[1] * y[0]);
+        double d2 = 3.0e7 * (-w[1] * y[1] * y[1] + w[2] * y[1] * y[1]);
+        double d3 = 1.0e4 * (w[0] * y[1] * y[2] - w[1] * y[1] * y[2]);
+        gp[0] += d1; gp[1] += d2; gp[2] += d3;
+        break;
+    }
+    case ORACLE_MLP: {
+        /* Back-propagation of w through the network. */
+        double a1[HMAX], a2[HMAX], d2[HMAX], d1[HMAX], f[NMAX];
+        mlp_forward(n, H, p, y, a1, a2, f);
+        const double *W2 = p + H * n + H, *W3 = W2 + H * H + H;
+        double *gW1 = gp, *gb1 = gW1 + H * n, *gW2 = gb1 + H, *gb2 = gW2 + H * H,
+               *gW3 = gb2 + H, *gb3 = gW3 + n * H;
+        for (int i = 0; i < n; ++i) {
+            for (int k = 0; k < H; ++k) gW3[i * H + k] += w[i] * a2[k];
+            gb3[i] += w[i];
+        }
+        for (int k = 0; k < H; ++k) {
+            double s = 0.0;
+            for (int i = 0; i < n; ++i) s += W3[i * H + k] * w[i];
+            d2[k] = s * (1.0 - a2[k] * a2[k]);
+        }
+        for (int i = 0; i < H; ++i) {
+            for (int k = 0; k < H; ++k) gW2[i * H + k] += d2[i] * a1[k];
+            gb2[i] += d2[i];
+        }
+        for (int k = 0; k < H; ++k) {
+            double s = 0.0;
+            for (int i = 0; i < H; ++i) s += W2[i * H + k] * d2[i];
+            d1[k] = s * (1.0 - a1[k] * a1[k]);
+        }
+        for (int i = 0; i < H; ++i) {
+            for (int k = 0; k < n; ++k) gW1[i * n + k] += d1[i] * y[k];
+            gb1[i] += d1[i];
+        }
+        break;
+    }
+    }
+}
+
+int oracle_rhs(int kind, int n, int hidden, const double *y, double t, const double *p,
+               double *f, double *J)
+{
+    if (n < 1 || n > NMAX || oracle_param_count(kind, n, hidden) < 0) return -1;
+    rhs(kind, n, hidden, y, t, p, f, J);
+    return 0;
+}
+
+int oracle_vjp_p(int kind, int n, int hidden, const double *y, double t, const double *p,
+                 const double *w, double *gp)
+{
+    if (n < 1 || n > NMAX || oracle_param_count(kind, n, hidden) < 0) return -1;
+    vjp_p(kind, n, hidden, y, t, p, w, gp);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Problem description shared by the forward and adjoint drivers.          */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int kind, n, H, P, params_shared;
+    int64_t B, N;
+    const int64_t *offsets; /* point offsets [B+1] or NULL (uniform: N+1 points each) */
+    const double *times, *y0, *params;
+    double tol_a, tol_r;
+    int max_newton;
+    /* forward outputs */
+    double *y;
+    int32_t *status, *iters;
+    /* adjoint inputs/outputs */
+    const double *g;
+    double *dLdp, *dLdy0;
+    /* scheduling */
+    const int64_t *order;
+    int64_t next;
+    pthread_mutex_t lock;
+} problem_t;
+
+static int64_t first_point(const problem_t *pb, int64_t b)
+{
+    return pb->offsets ? pb->offsets[b] : b * (pb->N + 1);
+}
+static int64_t n_steps(const problem_t *pb, int64_t b)
+{
+    return pb->offsets ? pb->offsets[b + 1] - pb->offsets[b] - 1 : pb->N;
+}
+static const double *series_times(const problem_t *pb, int64_t b)
+{
+    return pb->offsets ? pb->times + pb->offsets[b] : pb->times;
+}
+static const double *series_params(const problem_t *pb, int64_t b)
+{
+    return pb->params_shared ? pb->params : pb->params + b * pb->P;
+}
+
+/* Sequential backward Euler for one series (Section 2.2). */
+static void forward_series(problem_t *pb, int64_t b)
+{
+    const int n = pb->n, H = pb->H, kind = pb->kind;
+    const int64_t Nb = n_steps(pb, b);
+    const double *t = series_times(pb, b), *p = series_params(pb, b);
+    double *Y = pb->y + first_point(pb, b) * n;
+    double yprev[NMAX], yk[NMAX], f[NMAX], r[NMAX], J[NMAX * NMAX];
+    int32_t status = ORACLE_OK, total = 0;
+
+    for (int i = 0; i < n; ++i) Y[i] = yprev[i] = pb->y0[b * n + i];
+    for (int64_t k = 1; k <= Nb && status == ORACLE_OK; ++k) {
+        const double dt = t[k] - t[k - 1];
+        memcpy(yk, yprev, sizeof(double) * n);        /* start from y_{k-1} */
+        double nu0 = 0.0;
+        for (int it = 0;; ++it) {
+            rhs(kind, n, H, yk, t[k], p, f, NULL);
+            double nu = 0.0;
+            for (int i = 0; i < n; ++i) {
+                r[i] = yk[i] - yprev[i] - dt * f[i];
+                nu += r[i] * r[i];
+            }
+            nu = sqrt(nu);
+            if (!isfinite(nu)) { status = ORACLE_NONFINITE; break; }
+            if (it == 0) nu0 = nu;
+            if (nu <= pb->tol_a || nu <= pb->tol_r * nu0) break;
+            if (it == pb->max_newton) { status = ORACLE_NOT_CONVERGED; break; }
+            /* discrete Jacobian I - dt j and the Newton correction */
+            rhs(kind, n, H, yk, t[k], p, f, J);
+            for (int i = 0; i < n; ++i) {
+                for (int c = 0; c < n; ++c) J[i * n + c] = (i == c ? 1.0 : 0.0) - dt * J[i * n + c];
+                r[i] = -r[i];
+            }
+            if (lu_solve(n, J, r)) { status = ORACLE_SINGULAR; break; }
+            for (int i = 0; i < n; ++i) yk[i] += r[i];
+            ++total;
+        }
+        if (status != ORACLE_OK) {
+            /* a failed series stops: this and every later state is NaN */
+            for (int64_t q = k * n; q <= Nb * n + n - 1; ++q) Y[q] = NAN;
+            break;
+        }
+        memcpy(yprev, yk, sizeof(double) * n);
+        memcpy(Y + k * n, yk, sizeof(double) * n);
+    }
+    pb->status[b] = status;
+    if (pb->iters) pb->iters[b] = total;
+}
+
+/* Discrete adjoint of the backward-Euler map for one series (Appendix A):
+ *   (I - dt_k j_k)^T lam_k = lam_{k+1} + g_k,   k = N..1,  lam_{N+1} = 0,
+ *   dL/dp += dt_k (dh/dp (y_k))^T lam_k,        dL/dy0 = g_0 + lam_1,
+ * with j_k evaluated at the converged y_k. */
+static void adjoint_series(problem_t *pb, int64_t b, double *gp)
+{
+    const int n = pb->n, H = pb->H, kind = pb->kind;
+    const int64_t Nb = n_steps(pb, b), p0 = first_point(pb, b);
+    const double *t = series_times(pb, b), *p = series_params(pb, b);
+    const double *Y = pb->y + p0 * n, *G = pb->g + p0 * n;
+    double lam[NMAX], f[NMAX], J[NMAX * NMAX], Dt[NMAX * NMAX], w[NMAX];
+    int32_t status = ORACLE_OK;
+
+    memset(lam, 0, sizeof(lam));
+    for (int64_t k = Nb; k >= 1; --k) {
+        const double dt = t[k] - t[k - 1];
+        rhs(kind, n, H, Y + k * n, t[k], p, f, J);
+        for (int i = 0; i < n; ++i)
+            for (int c = 0; c < n; ++c) Dt[c * n + i] = (i == c ? 1.0 : 0.0) - dt * J[i * n + c];
+        for (int i = 0; i < n; ++i) lam[i] += G[k * n + i];
+        if (lu_solve(n, Dt, lam)) { status = ORACLE_SINGULAR; break; }
+        for (int i = 0; i < n; ++i) w[i] = dt * lam[i];
+        vjp_p(kind, n, H, Y + k * n, t[k], p, w, gp);
+    }
+    for (int i = 0; i < n; ++i) pb->dLdy0[b * n + i] = G[i] + lam[i];
+    pb->status[b] = status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Thread pool over series, longest series first.                           */
+/* ------------------------------------------------------------------------ */
+typedef struct { problem_t *pb; int adjoint; double *gp_series; } job_t;
+
+static void *worker(void *arg)
+{
+    job_t *job = arg;
+    problem_t *pb = job->pb;
+    for (;;) {
+        pthread_mutex_lock(&pb->lock);
+        int64_t i = pb->next++;
+        pthread_mutex_unlock(&pb->lock);
+        if (i >= pb->B) break;
+        int64_t b = pb->order[i];
+        if (job->adjoint) adjoint_series(pb, b, job->gp_series + b * pb->P);
+        else forward_series(pb, b);
+    }
+    return NULL;
+}
+
+static const problem_t *sort_ctx;
+static int cmp_len(const void *a, const void *b)
+{
+    int64_t la = n_steps(sort_ctx, *(const int64_t *)a), lb = n_steps(sort_ctx, *(const int64_t *)b);
+    if (la != lb) return la > lb ? -1 : 1;
+    int64_t ia = *(const int64_t *)a, ib = *(const int64_t *)b;
+    return ia < ib ? -1 : (ia > ib);
+}
+
+static pthread_mutex_t sort_lock = PTHREAD_MUTEX_INITIALIZER;
+
+static int run_pool(problem_t *pb, int threads, int adjoint, double *gp_series)
+{
+    int64_t *order = malloc(sizeof(int64_t) * (pb->B > 0 ? pb->B : 1));
+    if (!order) return -3;
+    for (int64_t b = 0; b < pb->B; ++b) order[b] = b;
+    pthread_mutex_lock(&sort_lock);
+    sort_ctx = pb;
+    qsort(order, (size_t)pb->B, sizeof(int64_t), cmp_len);
+    pthread_mutex_unlock(&sort_lock);
+    pb->order = order;
+    pb->next = 0;
+    pthread_mutex_init(&pb->lock, NULL);
+    if (threads < 1) threads = 1;
+    if (threads > pb->B) threads = pb->B > 0 ? (int)pb->B : 1;
+    pthread_t *tid = malloc(sizeof(pthread_t) * threads);
+    job_t job = { pb, adjoint, gp_series };
+    for (int i = 1; i < threads; ++i) pthread_create(&tid[i], NULL, worker, &job);
+    worker(&job);
+    for (int i = 1; i < threads; ++i) pthread_join(tid[i], NULL);
+    free(tid);
+    pthread_mutex_destroy(&pb->lock);
+    free(order);
+    return 0;
+}
+
+static int validate(int kind, int n, int hidden, int64_t B, int64_t N, const int64_t *offsets)
+{
+    if (n < 1 || n > NMAX || B < 0) return -1;
+    if (oracle_param_count(kind, n, hidden) < 0) return -1;
+    if (kind == ORACLE_VANDERPOL && n != 2) return -1;
+    if (kind == ORACLE_ROBERTSON && n != 3) return -1;
+    if (kind == ORACLE_MLP && (hidden < 1 || hidden > HMAX)) return -1;
+    if (!offsets && N < 0) return -1;
+    if (offsets)
+        for (int64_t b = 0; b < B; ++b)
+            if (offsets[b + 1] - offsets[b] < 1) return -1;
+    return 0;
+}
+
+int oracle_forward(int kind, int n, int hidden, int64_t B, int64_t N, const int64_t *offsets,
+                   const double *times, const double *y0, const double *params, int params_shared,
+                   double tol_a, double tol_r, int max_newton, int threads,
+                   double *y_out, int32_t *status, int32_t *iters)
+{
+    if (validate(kind, n, hidden, B, N, offsets)) return -1;
+    problem_t pb;
+    memset(&pb, 0, sizeof(pb));
+    pb.kind = kind; pb.n = n; pb.H = hidden; pb.P = oracle_param_count(kind, n, hidden);
+    pb.params_shared = params_shared; pb.B = B; pb.N = N; pb.offsets = offsets;
+    pb.times = times; pb.y0 = y0; pb.params = params;
+    pb.tol_a = tol_a; pb.tol_r = tol_r; pb.max_newton = max_newton;
+    pb.y = y_out; pb.status = status; pb.iters = iters;
+    return run_pool(&pb, threads, 0, NULL);
+}
+
+int oracle_adjoint(int kind, int n, int hidden, int64_t B, int64_t N, const int64_t *offsets,
+                   const double *times, const double *y, const double *params, int params_shared,
+                   const double *g, int threads, double *dLdp, double *dLdy0, int32_t *status)
+{
+    if (validate(kind, n, hidden, B, N, offsets)) return -1;
+    problem_t pb;
+    memset(&pb, 0, sizeof(pb));
+    pb.kind = kind; pb.n = n; pb.H = hidden; pb.P = oracle_param_count(kind, n, hidden);
+    pb.params_shared = params_shared; pb.B = B; pb.N = N; pb.offsets = offsets;
+    pb.times = times; pb.params = params;
+    pb.y = (double *)y; pb.g = g; pb.dLdy0 = dLdy0; pb.status = status;
+    /* Per-series partial gradients; a shared parameter vector is their sum in
+       series order, so the result does not depend on the thread count. */
+    double *gp_series;
+    if (params_shared) {
+        gp_series = calloc((size_t)(B > 0 ? B : 1) * pb.P, sizeof(double));
+        if (!gp_series) return -3;
+    } else {
+        gp_series = dLdp;
+        memset(dLdp, 0, sizeof(double) * (size_t)B * pb.P);
+    }
+    int rc = run_pool(&pb, threads, 1, gp_series);
+    if (params_shared) {
+        memset(dLdp, 0, sizeof(double) * pb.P);
+        for (int64_t b = 0; b < B; ++b)
+            for (int i = 0; i < pb.P; ++i) dLdp[i] += gp_series[b * pb.P + i];
+        free(gp_series);
+    }
+    return rc;
+}

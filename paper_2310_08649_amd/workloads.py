@@ -1,0 +1,100 @@
+"""Seeded synthetic workloads.
+
+Input generators only: they draw initial states, time grids and model
+parameters with ``numpy.random.default_rng(seed)`` in a fixed order and hold
+none of the integration method's arithmetic.  The same arrays feed the HIP
+library and the CPU oracle.
+
+The paper measures on its own synthetic ODE problems (Section 5.1); there is
+no dataset to stand in for.  The five workloads below are those the library
+is benchmarked and tested on:
+
+* ``linear``     stiff linear system dy/dt = A y, n = 4, A = -Q diag(lam) Q^T with
+                 Q Haar-orthogonal and lam log-uniform in [0.1, 1000]
+* ``vanderpol``  Van der Pol, n = 2, mu log-uniform in [1, 1000], y0 ~ U(-2, 2)
+* ``mlp``        neural ODE dy/dt = MLP(y; theta), n = 8, two tanh layers of 64,
+                 theta ~ N(0, 0.1^2), y0 ~ N(0, 1)
+* ``robertson``  Robertson kinetics, n = 3, rate scale factors log-uniform in
+                 [0.5, 2], series lengths log-uniform in [100, 20000] on
+                 log-spaced grids over [1e-5, 1e4], y0 = (1, 0, 0)
+
+Every generator returns a dict of contiguous numpy arrays in the library's
+series-major layouts (see ``include/tvi.h``).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def haar_orthogonal(rng, n):
+    """A Haar-distributed orthogonal matrix: QR of a Gaussian matrix with the signs fixed by diag(R)."""
+    G = rng.standard_normal((n, n))
+    Q, R = np.linalg.qr(G)
+    return Q * np.sign(np.diag(R))[None, :]
+
+
+def linear(B=8, N=200, n=4, seed=101, t_end=1.0, lam_range=(0.1, 1000.0)):
+    """Stiff linear system; returns A [B,n,n] (as params [B,n*n]) with its Q and lam."""
+    rng = np.random.default_rng(seed)
+    Q = np.empty((B, n, n))
+    lam = np.empty((B, n))
+    lo, hi = np.log10(lam_range[0]), np.log10(lam_range[1])
+    for b in range(B):
+        Q[b] = haar_orthogonal(rng, n)
+        lam[b] = 10.0 ** rng.uniform(lo, hi, size=n)
+    y0 = rng.standard_normal((B, n))
+    A = -np.einsum("bij,bj,bkj->bik", Q, lam, Q)
+    times = np.linspace(0.0, t_end, N + 1)
+    return dict(kind="linear", n=n, y0=y0, times=times, params=A.reshape(B, n * n).copy(),
+                Q=Q, lam=lam, offsets=None)
+
+
+def vanderpol(B=512, N=5000, seed=102, t_end=10.0, mu_range=(1.0, 1000.0)):
+    rng = np.random.default_rng(seed)
+    mu = 10.0 ** rng.uniform(np.log10(mu_range[0]), np.log10(mu_range[1]), size=B)
+    y0 = rng.uniform(-2.0, 2.0, size=(B, 2))
+    times = np.linspace(0.0, t_end, N + 1)
+    return dict(kind="vanderpol", n=2, y0=y0, times=times, params=mu.reshape(B, 1).copy(), offsets=None)
+
+
+def mlp_theta(rng, n=8, hidden=64, scale=0.1):
+    """theta packed as W1[H][n], b1[H], W2[H][H], b2[H], W3[n][H], b3[n], each drawn in that order."""
+    parts = [
+        scale * rng.standard_normal(hidden * n),
+        scale * rng.standard_normal(hidden),
+        scale * rng.standard_normal(hidden * hidden),
+        scale * rng.standard_normal(hidden),
+        scale * rng.standard_normal(n * hidden),
+        scale * rng.standard_normal(n),
+    ]
+    return np.concatenate(parts)
+
+
+def mlp(B=64, N=10000, n=8, hidden=64, seed=103, t_end=1.0):
+    rng = np.random.default_rng(seed)
+    theta = mlp_theta(rng, n, hidden)
+    y0 = rng.standard_normal((B, n))
+    times = np.linspace(0.0, t_end, N + 1)
+    return dict(kind="mlp", n=n, hidden=hidden, y0=y0, times=times, params=theta, offsets=None)
+
+
+def robertson(B=2000, seed=104, n_range=(100, 20000), t_range=(1e-5, 1e4), s_range=(0.5, 2.0)):
+    """Ragged Robertson series: point offsets [B+1], times [points] (log-spaced per series)."""
+    rng = np.random.default_rng(seed)
+    s = 10.0 ** rng.uniform(np.log10(s_range[0]), np.log10(s_range[1]), size=(B, 3))
+    Nb = np.rint(np.exp(rng.uniform(np.log(n_range[0]), np.log(n_range[1]), size=B))).astype(np.int64)
+    Nb = np.maximum(Nb, 1)
+    offsets = np.zeros(B + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum(Nb + 1)
+    lt0, lt1 = np.log10(t_range[0]), np.log10(t_range[1])
+    times = np.empty(int(offsets[-1]))
+    for b in range(B):
+        k = np.arange(Nb[b] + 1, dtype=np.float64)
+        times[offsets[b]:offsets[b + 1]] = 10.0 ** (lt0 + (lt1 - lt0) * k / Nb[b])
+    y0 = np.tile(np.array([1.0, 0.0, 0.0]), (B, 1))
+    return dict(kind="robertson", n=3, y0=y0, times=times, params=s, offsets=offsets, steps=Nb)
+
+
+def observed_steps(N, every=100):
+    """Observed step indices of the sampled mean-squared loss: k = every, 2 every, ..., N."""
+    return np.arange(every, N + 1, every, dtype=np.int64)

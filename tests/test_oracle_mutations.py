@@ -1,0 +1,59 @@
+"""Plant plausible mistakes in a copy of the C oracle and show that the pins
+catch each of them.  Runs entirely on the CPU; the real oracle is untouched."""
+import os
+import subprocess
+
+import pytest
+
+import oracle
+from tests import test_oracle_pins as pins
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
+
+# (name, exact text in oracle.c, replacement, pins expected to catch it)
+MUTATIONS = [
+    ("vdp_jacobian_sign", "J[2] = -2.0 * mu * y[0] * y[1] - 1.0;", "J[2] = 2.0 * mu * y[0] * y[1] - 1.0;",
+     [lambda: pins.test_model_jacobian_matches_central_differences(pins._model_cases()[1])]),
+    ("robertson_dropped_term", "f[1] = k1 * y[0] - k3 * y[1] * y[2] - k2 * y[1] * y[1];",
+     "f[1] = k1 * y[0] - k3 * y[1] * y[2];",
+     [pins.test_robertson_mass_conservation, pins.test_robertson_first_order_convergence]),
+    ("newton_dt_sign", "J[i * n + c] = (i == c ? 1.0 : 0.0) - dt * J[i * n + c];",
+     "J[i * n + c] = (i == c ? 1.0 : 0.0) + dt * J[i * n + c];",
+     [pins.test_lin_exact_be_recurrence]),
+    ("adjoint_untransposed", "Dt[c * n + i] = (i == c ? 1.0 : 0.0) - dt * J[i * n + c];",
+     "Dt[i * n + c] = (i == c ? 1.0 : 0.0) - dt * J[i * n + c];",
+     [pins.test_lin_adjoint_closed_form, pins.test_adjoint_fd_vanderpol]),
+    ("adjoint_dropped_g0", "pb->dLdy0[b * n + i] = G[i] + lam[i];", "pb->dLdy0[b * n + i] = lam[i];",
+     [pins.test_lin_adjoint_closed_form]),
+    ("mlp_vjp_dropped_tanh_derivative", "d1[k] = s * (1.0 - a1[k] * a1[k]);", "d1[k] = s;",
+     [lambda: pins.test_model_param_vjp_matches_central_differences(pins._model_cases()[3])]),
+    ("mlp_w2_transposed", "for (int k = 0; k < H; ++k) s += W2[i * H + k] * a1[k];",
+     "for (int k = 0; k < H; ++k) s += W2[k * H + i] * a1[k];",
+     [pins.test_model_rates_match_independent_definitions]),
+    ("lu_wrong_pivot", "if (v > best) { best = v; piv = r; }", "if (v < best) { best = v; piv = r; }",
+     [pins.test_lu_matches_numpy_and_pivots]),
+    ("vdp_param_vjp_wrong_component", "gp[0] += w[1] * (1.0 - y[0] * y[0]) * y[1];",
+     "gp[0] += w[0] * (1.0 - y[0] * y[0]) * y[1];",
+     [lambda: pins.test_model_param_vjp_matches_central_differences(pins._model_cases()[1])]),
+]
+
+
+@pytest.mark.parametrize("mut", MUTATIONS, ids=lambda m: m[0])
+def test_pins_catch_planted_mistake(mut, tmp_path):
+    name, old, new, checks = mut
+    src = open(SRC).read()
+    assert src.count(old) == 1, "mutation anchor not found exactly once: " + name
+    path = tmp_path / "oracle.c"
+    path.write_text(src.replace(old, new))
+    (tmp_path / "oracle.h").write_text(open(SRC[:-2] + ".h").read())
+    lib = tmp_path / ("liboracle_%s.so" % name)
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-shared", "-fPIC", "-o", str(lib), str(path),
+                           "-lm", "-lpthread"])
+    caught = 0
+    with oracle.using_library(str(lib)):
+        for check in checks:
+            try:
+                check()
+            except Exception:  # an assertion or a failure status the pin turns into an error
+                caught += 1
+    assert caught == len(checks), "%s: only %d of %d pins caught it" % (name, caught, len(checks))

@@ -1,0 +1,375 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these tests compares the oracle with itself: each checks it against
+a closed form, an independent solver, a finite difference or an invariant, so
+that a dropped term, a wrong sign or index or a transposed operand in the
+oracle's model, Newton, LU or adjoint code fails at least one of them.
+"""
+import numpy as np
+import pytest
+from scipy.integrate import solve_ivp
+from scipy.optimize import root
+
+import oracle
+from paper_2310_08649_amd import workloads as W
+
+TIGHT = (1e-14, 1e-13)
+
+
+# --------------------------------------------------------------------------
+# Independent transcriptions of the model definitions (from the workload
+# definitions, not from the oracle) for scipy's integrators and root finder.
+# --------------------------------------------------------------------------
+def vdp_ref(y, mu):
+    return np.array([y[1], mu * (1.0 - y[0] ** 2) * y[1] - y[0]])
+
+
+def rob_ref(y, s):
+    a, b, c = 0.04 * s[0], 3.0e7 * s[1], 1.0e4 * s[2]
+    return np.array([-a * y[0] + c * y[1] * y[2],
+                     a * y[0] - c * y[1] * y[2] - b * y[1] ** 2,
+                     b * y[1] ** 2])
+
+
+def mlp_ref_torch(theta, n, H):
+    import torch
+    th = torch.tensor(theta, dtype=torch.float64)
+    sizes = [H * n, H, H * H, H, n * H, n]
+    W1, b1, W2, b2, W3, b3 = torch.split(th, sizes)
+    l1 = torch.nn.Linear(n, H).double()
+    l2 = torch.nn.Linear(H, H).double()
+    l3 = torch.nn.Linear(H, n).double()
+    with torch.no_grad():
+        l1.weight.copy_(W1.view(H, n)); l1.bias.copy_(b1)
+        l2.weight.copy_(W2.view(H, H)); l2.bias.copy_(b2)
+        l3.weight.copy_(W3.view(n, H)); l3.bias.copy_(b3)
+    net = torch.nn.Sequential(l1, torch.nn.Tanh(), l2, torch.nn.Tanh(), l3)
+    return net
+
+
+# --------------------------------------------------------------------------
+# LU with partial pivoting
+# --------------------------------------------------------------------------
+def test_lu_matches_numpy_and_pivots():
+    rng = np.random.default_rng(0)
+    for n in range(1, 9):
+        A = rng.standard_normal((n, n))
+        b = rng.standard_normal(n)
+        np.testing.assert_allclose(oracle.lu_solve(A, b), np.linalg.solve(A, b), rtol=1e-12, atol=1e-12)
+    # needs a row exchange: zero leading pivot
+    A = np.array([[0.0, 2.0, 1.0], [1.0, 1.0, 0.0], [3.0, 0.0, 1.0]])
+    b = np.array([1.0, 2.0, 3.0])
+    np.testing.assert_allclose(oracle.lu_solve(A, b), np.linalg.solve(A, b), rtol=1e-14)
+    with pytest.raises(np.linalg.LinAlgError):
+        oracle.lu_solve(np.array([[1.0, 2.0], [2.0, 4.0]]), np.ones(2))
+
+
+# --------------------------------------------------------------------------
+# LIN: exact backward-Euler recurrence and O(h) approach to expm (P1-P3, P13)
+# --------------------------------------------------------------------------
+def lin_closed_form(w):
+    h = w["times"][1] - w["times"][0]
+    k = np.arange(w["times"].shape[0])
+    c = np.einsum("bji,bj->bi", w["Q"], w["y0"])
+    fac = (1.0 + h * w["lam"])[:, None, :] ** (-k[None, :, None])
+    return np.einsum("bij,bkj,bj->bki", w["Q"], fac, c)
+
+
+def test_lin_exact_be_recurrence():
+    w = W.linear()
+    y, st, it = oracle.forward("linear", w["y0"], w["times"], w["params"], tol=(1e-8, 1e-6))
+    assert (st == 0).all()
+    yc = lin_closed_form(w)
+    assert np.abs(y - yc).max() / np.abs(yc).max() <= 1e-13
+    # Newton solves a linear step with a single correction (P3)
+    assert (it == w["times"].shape[0] - 1).all()
+
+
+def test_lin_first_order_convergence_to_expm():
+    errs = []
+    for N in (200, 400, 800, 1600):
+        w = W.linear(N=N)
+        y, st, _ = oracle.forward("linear", w["y0"], w["times"], w["params"], tol=TIGHT)
+        exact = np.einsum("bij,bj,bkj,bk->bi", w["Q"], np.exp(-w["lam"]), w["Q"], w["y0"])
+        errs.append(np.abs(y[:, -1] - exact).max())
+    ratios = np.array(errs[:-1]) / np.array(errs[1:])
+    assert np.all(np.abs(ratios - 2.0) < 0.02), ratios
+
+
+def test_lin_adjoint_closed_form():
+    """dL/dy0 = sum_k (S^k)^T g_k with S = (I - hA)^{-1} (P13)."""
+    w = W.linear(B=3, N=40)
+    # a non-symmetric A, so that a transposition mistake cannot hide
+    rng = np.random.default_rng(5)
+    params = w["params"] + 3.0 * rng.standard_normal(w["params"].shape)
+    y, st, _ = oracle.forward("linear", w["y0"], w["times"], params, tol=TIGHT)
+    g = rng.standard_normal(y.shape)
+    dLdp, dLdy0, ast = oracle.adjoint("linear", y, w["times"], params, g)
+    h = w["times"][1] - w["times"][0]
+    for b in range(3):
+        A = params[b].reshape(4, 4)
+        S = np.linalg.inv(np.eye(4) - h * A)
+        acc = np.zeros(4)
+        Sk = np.eye(4)
+        for k in range(y.shape[1]):
+            acc += Sk.T @ g[b, k]
+            Sk = S @ Sk
+        np.testing.assert_allclose(dLdy0[b], acc, rtol=1e-12, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# VDP: mu = 0 is the harmonic oscillator (P10); O(h) to a Radau solution
+# --------------------------------------------------------------------------
+def test_vdp_mu_zero_is_harmonic_oscillator():
+    N, T = 500, 5.0
+    times = np.linspace(0, T, N + 1)
+    y0 = np.array([[1.2, -0.4], [-0.3, 0.9]])
+    y, st, _ = oracle.forward("vanderpol", y0, times, np.zeros((2, 1)), tol=TIGHT)
+    h = T / N
+    S = np.linalg.inv(np.eye(2) - h * np.array([[0.0, 1.0], [-1.0, 0.0]]))
+    ref = np.empty_like(y)
+    for b in range(2):
+        v = y0[b].copy()
+        for k in range(N + 1):
+            ref[b, k] = v
+            v = S @ v
+    assert np.abs(y - ref).max() <= 1e-12
+
+
+@pytest.mark.parametrize("mu", [1.0, 5.0])
+def test_vdp_first_order_convergence(mu):
+    y0 = np.array([1.5, 0.3])
+    ref = solve_ivp(lambda t, y: vdp_ref(y, mu), (0, 2), y0, method="Radau", rtol=1e-12, atol=1e-12).y[:, -1]
+    errs = []
+    for N in (400, 800, 1600, 3200):
+        y, st, _ = oracle.forward("vanderpol", y0[None], np.linspace(0, 2, N + 1), np.array([[mu]]), tol=TIGHT)
+        errs.append(np.abs(y[0, -1] - ref).max())
+    ratios = np.array(errs[:-1]) / np.array(errs[1:])
+    assert np.all(np.abs(ratios - 2.0) < 0.03), ratios
+
+
+# --------------------------------------------------------------------------
+# ROB: mass conservation (P11) and O(h) to a Radau solution
+# --------------------------------------------------------------------------
+def test_robertson_mass_conservation():
+    w = W.robertson(B=24, n_range=(100, 3000))
+    y, st, _ = oracle.forward("robertson", w["y0"], w["times"], w["params"], offsets=w["offsets"],
+                              tol=(1e-8, 1e-6))
+    assert (st == 0).all()
+    assert np.abs(y.sum(axis=1) - 1.0).max() <= 1e-12
+
+
+def test_robertson_first_order_convergence():
+    s = np.array([1.3, 0.7, 1.1])
+    ref = solve_ivp(lambda t, y: rob_ref(y, s), (0, 1), [1.0, 0.0, 0.0], method="Radau",
+                    rtol=1e-12, atol=1e-14).y[:, -1]
+    errs = []
+    for N in (1000, 2000, 4000, 8000):
+        y, st, _ = oracle.forward("robertson", np.array([[1.0, 0, 0]]), np.linspace(0, 1, N + 1), s[None],
+                                  tol=(1e-15, 1e-13))
+        errs.append(np.abs(y[0, -1] - ref) / np.abs(ref))
+    ratios = np.array(errs[:-1]) / np.array(errs[1:])
+    assert np.all(np.abs(ratios - 2.0) < 0.01), ratios
+
+
+# --------------------------------------------------------------------------
+# Model rate, Jacobian and parameter VJP
+# --------------------------------------------------------------------------
+def _model_cases():
+    rng = np.random.default_rng(7)
+    A = -np.eye(4) * 3.0 + 0.5 * rng.standard_normal((4, 4))
+    theta = W.mlp_theta(rng, n=8, hidden=64, scale=0.3)
+    return [
+        ("linear", rng.standard_normal(4), A.ravel(), 64),
+        ("vanderpol", np.array([0.7, -1.3]), np.array([37.0]), 64),
+        ("robertson", np.array([0.8, 3e-5, 0.2]), np.array([1.2, 0.9, 1.4]), 64),
+        ("mlp", rng.standard_normal(8), theta, 64),
+    ]
+
+
+@pytest.mark.parametrize("case", _model_cases(), ids=lambda c: c[0])
+def test_model_jacobian_matches_central_differences(case):
+    kind, y, p, H = case
+    f, J = oracle.rhs(kind, y, 0.3, p, hidden=H)
+    n = y.shape[0]
+    Jfd = np.empty((n, n))
+    for c in range(n):
+        e = max(abs(y[c]), 1e-3) * 1e-6
+        yp, ym = y.copy(), y.copy()
+        yp[c] += e
+        ym[c] -= e
+        Jfd[:, c] = (oracle.rhs(kind, yp, 0.3, p, H)[0] - oracle.rhs(kind, ym, 0.3, p, H)[0]) / (2 * e)
+    scale = np.abs(J).max()
+    assert np.abs(J - Jfd).max() <= 1e-6 * scale
+
+
+@pytest.mark.parametrize("case", _model_cases(), ids=lambda c: c[0])
+def test_model_param_vjp_matches_central_differences(case):
+    kind, y, p, H = case
+    w = np.random.default_rng(3).standard_normal(y.shape[0])
+    gp = oracle.vjp_p(kind, y, 0.3, p, w, hidden=H)
+    d = np.random.default_rng(4).standard_normal(p.shape[0])
+    e = 1e-6 * max(1.0, np.abs(p).max()) / np.linalg.norm(d)
+    fp = oracle.rhs(kind, y, 0.3, p + e * d, H)[0]
+    fm = oracle.rhs(kind, y, 0.3, p - e * d, H)[0]
+    fd = w @ (fp - fm) / (2 * e)
+    assert abs(gp @ d - fd) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_model_rates_match_independent_definitions():
+    import torch
+    for kind, y, p, H in _model_cases():
+        f, _ = oracle.rhs(kind, y, 0.0, p, H)
+        if kind == "linear":
+            ref = p.reshape(4, 4) @ y
+        elif kind == "vanderpol":
+            ref = vdp_ref(y, p[0])
+        elif kind == "robertson":
+            ref = rob_ref(y, p)
+        else:
+            with torch.no_grad():
+                ref = mlp_ref_torch(p, 8, H)(torch.tensor(y)).numpy()
+        np.testing.assert_allclose(f, ref, rtol=1e-13, atol=1e-15)
+
+
+def test_mlp_jacobian_and_vjp_match_torch_autograd():
+    import torch
+    kind, y, p, H = _model_cases()[3]
+    f, J = oracle.rhs(kind, y, 0.0, p, H)
+    net = mlp_ref_torch(p, 8, H)
+    Jt = torch.autograd.functional.jacobian(net, torch.tensor(y)).numpy()
+    np.testing.assert_allclose(J, Jt, rtol=1e-12, atol=1e-14)
+    w = np.random.default_rng(9).standard_normal(8)
+    out = net(torch.tensor(y))
+    out.backward(torch.tensor(w))
+    grads = torch.cat([net[0].weight.grad.ravel(), net[0].bias.grad, net[2].weight.grad.ravel(),
+                       net[2].bias.grad, net[4].weight.grad.ravel(), net[4].bias.grad]).numpy()
+    np.testing.assert_allclose(oracle.vjp_p(kind, y, 0.0, p, w, H), grads, rtol=1e-12, atol=1e-14)
+
+
+def test_mlp_first_order_convergence():
+    rng = np.random.default_rng(11)
+    theta = W.mlp_theta(rng, 8, 64, scale=0.3)
+    y0 = rng.standard_normal(8)
+    net = mlp_ref_torch(theta, 8, 64)
+    import torch
+
+    def fun(t, y):
+        with torch.no_grad():
+            return net(torch.tensor(y)).numpy()
+
+    ref = solve_ivp(fun, (0, 1), y0, method="Radau", rtol=1e-12, atol=1e-12).y[:, -1]
+    errs = []
+    for N in (100, 200, 400):
+        y, st, _ = oracle.forward("mlp", y0[None], np.linspace(0, 1, N + 1), theta, tol=TIGHT)
+        errs.append(np.abs(y[0, -1] - ref).max())
+    ratios = np.array(errs[:-1]) / np.array(errs[1:])
+    assert np.all(np.abs(ratios - 2.0) < 0.05), ratios
+
+
+# --------------------------------------------------------------------------
+# Each backward-Euler step against scipy's root finder (P9)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("kind,y0,p,T", [
+    ("vanderpol", [1.1, -0.5], [3.0], 1.0),
+    ("robertson", [1.0, 0.0, 0.0], [1.0, 1.0, 1.0], 0.002),
+])
+def test_each_step_solves_backward_euler_equation(kind, y0, p, T):
+    N = 20
+    times = np.linspace(0, T, N + 1)
+    y, st, _ = oracle.forward(kind, np.array([y0]), times, np.array([p]), tol=TIGHT)
+    pp = np.asarray(p, dtype=np.float64)
+    fref = (lambda v: vdp_ref(v, pp[0])) if kind == "vanderpol" else (lambda v: rob_ref(v, pp))
+    for k in range(1, N + 1):
+        h = times[k] - times[k - 1]
+        F = lambda v: v - y[0, k - 1] - h * fref(v)
+        sol = root(F, y[0, k - 1], method="hybr", options={"xtol": 1e-13})
+        assert np.abs(F(sol.x)).max() <= 1e-13
+        np.testing.assert_allclose(y[0, k], sol.x, rtol=1e-10, atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# Adjoint against central finite differences of the forward map (P12)
+# --------------------------------------------------------------------------
+def _frob_grad(y):
+    L = np.sqrt(np.sum(y ** 2))
+    return L, y / L
+
+
+def _adjoint_fd_case(kind, y0, times, params, offsets=None, hidden=64, dirs=6, eps=1e-6):
+    fwd = lambda y0_, p_: oracle.forward(kind, y0_, times, p_, offsets=offsets, tol=(1e-14, 1e-12),
+                                        hidden=hidden, params_shared=(params.ndim == 1))[0]
+    y = fwd(y0, params)
+    L, g = _frob_grad(y)
+    dLdp, dLdy0, st = oracle.adjoint(kind, y, times, params, g, offsets=offsets, hidden=hidden,
+                                     params_shared=(params.ndim == 1))
+    assert (st == 0).all()
+    rng = np.random.default_rng(21)
+    for _ in range(dirs):
+        dp = rng.standard_normal(params.shape) * np.maximum(np.abs(params), 1e-3)
+        dy = rng.standard_normal(y0.shape)
+        if offsets is not None and kind == "robertson":
+            dy[:] = 0.0
+        Lp = _frob_grad(fwd(y0 + eps * dy, params + eps * dp))[0]
+        Lm = _frob_grad(fwd(y0 - eps * dy, params - eps * dp))[0]
+        fd = (Lp - Lm) / (2 * eps)
+        an = np.sum(dLdp * dp) + np.sum(dLdy0 * dy)
+        assert abs(an - fd) <= 1e-6 * max(abs(fd), 1e-8), (an, fd)
+
+
+def test_adjoint_fd_linear():
+    w = W.linear(B=3, N=60)
+    _adjoint_fd_case("linear", w["y0"], w["times"], w["params"])
+
+
+def test_adjoint_fd_vanderpol():
+    w = W.vanderpol(B=4, N=300, mu_range=(1.0, 30.0))
+    w["times"] = np.linspace(0, 1.5, 301)
+    _adjoint_fd_case("vanderpol", w["y0"], w["times"], w["params"])
+
+
+def test_adjoint_fd_robertson_ragged():
+    w = W.robertson(B=4, n_range=(50, 300))
+    _adjoint_fd_case("robertson", w["y0"], w["times"], w["params"], offsets=w["offsets"], eps=1e-6)
+
+
+def test_adjoint_fd_mlp_shared_params():
+    w = W.mlp(B=3, N=50, hidden=16)
+    _adjoint_fd_case("mlp", w["y0"], w["times"], w["params"], hidden=16, eps=1e-5)
+
+
+# --------------------------------------------------------------------------
+# Layout, threading and failure reporting
+# --------------------------------------------------------------------------
+def test_ragged_equals_individual_uniform_runs_and_threads_do_not_matter():
+    w = W.robertson(B=6, n_range=(20, 200))
+    y, st, it = oracle.forward("robertson", w["y0"], w["times"], w["params"], offsets=w["offsets"], threads=4)
+    y1, st1, it1 = oracle.forward("robertson", w["y0"], w["times"], w["params"], offsets=w["offsets"], threads=1)
+    assert np.array_equal(y, y1) and np.array_equal(it, it1)
+    off = w["offsets"]
+    for b in range(6):
+        yb, _, _ = oracle.forward("robertson", w["y0"][b:b + 1], w["times"][off[b]:off[b + 1]], w["params"][b:b + 1])
+        assert np.array_equal(yb[0], y[off[b]:off[b + 1]])
+
+
+def test_failure_statuses():
+    # NaN initial state -> NONFINITE, rest of the series NaN
+    times = np.linspace(0, 1, 11)
+    y, st, _ = oracle.forward("vanderpol", np.array([[np.nan, 0.0], [0.5, 0.5]]), times, np.array([[1.0], [1.0]]))
+    assert st[0] == 3 and st[1] == 0 and np.isnan(y[0, 1:]).all() and np.isfinite(y[1]).all()
+    # I - hA singular: A = (1/h) I  -> SINGULAR
+    h = 0.1
+    A = (np.eye(2) / h).ravel()[None]
+    y, st, _ = oracle.forward("linear", np.array([[1.0, 2.0]]), np.linspace(0, 1, 11), A)
+    assert st[0] == 2
+    # a single Newton correction is not enough for a nonlinear step at a tight tolerance
+    y, st, _ = oracle.forward("vanderpol", np.array([[1.5, 0.3]]), times, np.array([[10.0]]),
+                              tol=(1e-15, 1e-15), max_newton=1)
+    assert st[0] == 1
+
+
+def test_zero_steps_and_empty_batch():
+    y, st, it = oracle.forward("vanderpol", np.array([[0.3, 0.1]]), np.array([0.0]), np.array([[2.0]]))
+    assert y.shape == (1, 1, 2) and np.array_equal(y[0, 0], [0.3, 0.1]) and st[0] == 0
+    y, st, it = oracle.forward("vanderpol", np.zeros((0, 2)), np.linspace(0, 1, 5), np.zeros((0, 1)))
+    assert y.shape == (0, 5, 2)
