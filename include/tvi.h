@@ -1,0 +1,200 @@
+/*
+ * tvi.h -- C ABI of the time-vectorized backward-Euler library for MI355X
+ * (gfx950).  Plain C: no C++ types, no exceptions cross this boundary.
+ *
+ * The library integrates batches of ODE systems  dy/dt = h(y, t; p)  with
+ * backward Euler (Section 2.2, Eq. backward-euler) and computes the adjoint
+ * gradient of a loss of the computed trajectory (Appendix A).  Instead of
+ * stepping one time step at a time it solves a chunk of steps of a series at
+ * once (Section 2.3, Eq. batched-backward-euler): every Newton iteration
+ * assembles the residuals and n x n diagonal blocks D_j = I - dt_j j_j of
+ * the chunk Jacobian for all steps of the chunk in one pass and solves the
+ * block lower-bidiagonal system (sub-diagonal blocks -I) by parallel cyclic
+ * reduction (Section 3.2) inside one wavefront; the adjoint solves the
+ * transposed, block upper-bidiagonal system the same way (Appendix A.2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Pointers.  Every array argument is a DEVICE pointer to memory the caller
+ *   owns (for example a contiguous torch tensor); the library keeps no
+ *   pointer after a call returns.  Arrays are row-major and series-major.
+ * Streams.  `stream` is a hipStream_t (NULL = the default stream).  Work is
+ *   enqueued on it and the call returns without waiting: results, and the
+ *   per-series status codes, are ready once the stream reaches them.
+ * Errors.  Arguments are checked on the host before anything is enqueued; a
+ *   negative tvi_status is returned synchronously and nothing is launched.
+ *   A launch failure returns TVI_EHIP.  Per-series outcomes (converged, not
+ *   converged, singular block, non-finite value) are written to the device
+ *   array `status[B]` asynchronously.
+ * Precision.  TVI_F64 keeps everything in IEEE double.  TVI_F32 stores the
+ *   inputs and outputs in float; the linear, Van der Pol and Robertson models
+ *   still evaluate the residual, the blocks, their inverses and the
+ *   reduction in double (stiff problems), the MLP model computes in float.
+ *
+ * Layouts
+ * -------
+ *   y0       [B][n]
+ *   times    uniform grid: [N+1], shared by every series;
+ *            ragged series: the points of series b at times[offsets[b] .. offsets[b+1]-1]
+ *   offsets  NULL (uniform grid) or int64 point offsets [B+1] (device), offsets[0] = 0;
+ *            series b has N_b = offsets[b+1] - offsets[b] - 1 >= 0 steps
+ *   params   per series [B][P], or one shared [P] (model.params_shared)
+ *   y        trajectory, uniform: [B][N+1][n]; ragged: [offsets[B]][n];
+ *            the first point of each series is its y0
+ *   ckpt     chunk-boundary checkpoints, always double, [B][K][n] with
+ *            K = ceil(N / chunk) + 1: ckpt[b][c] = y of series b at step c * chunk
+ *            (c * chunk <= N_b); entry ceil(N_b / chunk) is the final state
+ *   g        dL/dy in the layout of y
+ *   dLdp     [B][P], or [P] for shared parameters
+ *   dLdy0    [B][n]
+ *
+ * Models and parameter vectors P
+ *   TVI_LINEAR     h = A y,  n in {2, 3, 4}, p = A [n][n] (P = n^2)
+ *   TVI_VANDERPOL  n = 2, h = (y2, mu (1 - y1^2) y2 - y1), p = (mu)
+ *   TVI_ROBERTSON  n = 3, rate constants 0.04 s1, 3e7 s2 (on y2^2), 1e4 s3 (on y2 y3),
+ *                  p = (s1, s2, s3)
+ */
+#ifndef TVI_H
+#define TVI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TVI_LINEAR = 0,
+    TVI_VANDERPOL = 1,
+    TVI_ROBERTSON = 2,
+    TVI_MLP = 3
+} tvi_model_kind;
+
+typedef enum { TVI_F32 = 0, TVI_F64 = 1 } tvi_dtype;
+
+typedef enum {
+    /* per series, written to status[] on the device */
+    TVI_OK = 0,
+    TVI_NOT_CONVERGED = 1, /* max_newton corrections at the shortest chunk allowed */
+    TVI_SINGULAR = 2,      /* a diagonal block had a zero or non-finite pivot       */
+    TVI_NONFINITE = 3,     /* a residual became NaN or infinite                     */
+    /* returned by the host entry points */
+    TVI_EINVAL = -1,
+    TVI_EHIP = -2,
+    TVI_ENOMEM = -3,
+    TVI_EUNSUPPORTED = -4
+} tvi_status;
+
+typedef enum {
+    TVI_INIT_ZERO = 0,  /* Delta y = 0 over the chunk (Section 2.3)                  */
+    TVI_INIT_EXTRAP = 1 /* extrapolate the last step's slope over the chunk          */
+} tvi_init;
+
+typedef struct {
+    int32_t kind;          /* tvi_model_kind                                   */
+    int32_t n;             /* state size                                       */
+    int32_t dtype;         /* tvi_dtype of every floating-point array          */
+    int32_t params_shared; /* 1: one parameter vector [P] for all series       */
+    int32_t hidden;        /* MLP hidden width (ignored by the other models)   */
+} tvi_model;
+
+typedef struct {
+    int32_t chunk;          /* steps solved together, >= 1 (Section 2.3)           */
+    int32_t lanes;          /* lanes of a wavefront per series S: 1,4,8,16,32,64;
+                               0 = choose from chunk                                 */
+    int32_t steps_per_lane; /* steps a lane composes serially T: 1,2,4,8; 0 = choose;
+                               chunk <= lanes * steps_per_lane                       */
+    int32_t max_newton;     /* Newton corrections per attempt, >= 1                   */
+    double tol_a, tol_r;    /* converged iff ||R|| <= tol_a or ||R|| <= tol_r ||R0||,
+                               R the chunk residual (Algorithm 1)                     */
+    int32_t init;           /* tvi_init                                              */
+    int32_t halving;        /* 1: retry a failed chunk at half its length, down to 1 */
+} tvi_options;
+
+/* Fills `opt` with the defaults: chunk 64, tol_a 1e-8, tol_r 1e-6 (Section 2.3),
+ * max_newton 50, lanes/steps chosen from chunk, TVI_INIT_ZERO, halving on. */
+void tvi_default_options(tvi_options *opt);
+
+const char *tvi_status_str(int32_t status);
+const char *tvi_version(void);
+int32_t tvi_param_count(const tvi_model *model);
+
+/*
+ * tvi_pcr_solve -- batched block-bidiagonal solve (Section 3), the linear
+ * kernel of the chunked Newton update (Eq. batched-update).
+ *
+ * For each of B independent systems of m block rows with n x n diagonal
+ * blocks D[b][j] and sub-diagonal blocks -I, solves
+ *   transpose = 0:  D_1 x_1 = r_1,          D_j x_j - x_{j-1} = r_j  (j = 2..m)
+ *   transpose = 1:  D_m^T x_m = r_m,        D_j^T x_j - x_{j+1} = r_j (j = m-1..1)
+ * by parallel cyclic reduction: every block is inverted (Gauss-Jordan with
+ * partial pivoting), a lane composes `steps_per_lane` consecutive rows, and
+ * ceil(log2(lanes)) reduction levels run across the lanes of the system.
+ *
+ *   D  [B][m][n][n]   r, x  [B][m][n]     (dtype float or double, device)
+ *   n in {2, 3, 4}, 1 <= m <= 512.
+ * A system with a singular block gets NaN in x.  Returns TVI_OK once enqueued,
+ * TVI_EINVAL on bad sizes or null pointers, TVI_EHIP on a launch failure.
+ */
+tvi_status tvi_pcr_solve(int32_t dtype, int32_t n, int64_t B, int64_t m, const void *D, const void *r,
+                         void *x, int32_t transpose, void *stream);
+
+/*
+ * tvi_solve_forward -- chunked backward Euler (Algorithm 1).
+ *
+ * Integrates every series over its grid; each chunk of opt->chunk steps is
+ * solved by Newton iterations on the chunk residual (Eq. batched-backward-
+ * euler) started from opt->init.  A chunk whose Newton iteration fails is
+ * retried at half its length when opt->halving is set (the result -- the
+ * backward-Euler trajectory -- does not depend on the chunk length); a
+ * failure at length 1 stops the series: status[b] gets the code and y from
+ * the failed step on is NaN.
+ *
+ *   y_out   [B][N+1][n] or ragged (required)
+ *   ckpt    [B][ceil(N_max/chunk)+1][n] or NULL
+ *   status  int32 [B] (required), iters int32 [B] total Newton corrections (or NULL)
+ * N is the number of steps of the uniform grid, or, with offsets, the largest
+ * N_b (it sizes the checkpoint array).  y_out may be NULL when ckpt is given.
+ */
+tvi_status tvi_solve_forward(const tvi_model *model, const tvi_options *opt, int64_t B, int64_t N,
+                             const int64_t *offsets, const void *times, const void *y0,
+                             const void *params, void *y_out, void *ckpt, int32_t *status,
+                             int32_t *iters, void *stream);
+
+/*
+ * tvi_solve_adjoint -- discrete adjoint of tvi_solve_forward (Appendix A).
+ *
+ * With F_k = y_k - y_{k-1} - dt_k h(y_k, t_k; p) the backward-Euler map and
+ * g_k = dL/dy_k, computes
+ *   (I - dt_k j_k)^T lam_k = lam_{k+1} + g_k   (k = N_b..1, lam_{N_b+1} = 0),
+ *   dL/dp  = sum_k dt_k (dh/dp (y_k))^T lam_k,   dL/dy0 = g_0 + lam_1,
+ * with j_k = dh/dy at the converged y_k, chunk by chunk in reverse order: each
+ * chunk is the transposed block-bidiagonal system of Appendix A.2, solved by
+ * the same reduction run backwards.
+ *
+ * The states come either from the full trajectory `y` (then ckpt may be
+ * NULL) or, when y is NULL, are recomputed chunk by chunk from the
+ * checkpoints `ckpt` written by tvi_solve_forward with the same options;
+ * recomputed states are bitwise those of the forward pass.  Recomputation
+ * needs `workspace` of tvi_adjoint_workspace_bytes() bytes (device); with the
+ * trajectory given, workspace may be NULL.
+ *
+ *   g       dL/dy [B][N+1][n] or ragged (required)
+ *   dLdp    [B][P] (per-series parameters; shared parameters are not supported by
+ *           this entry point for the analytic models)
+ *   dLdy0   [B][n]
+ *   status  int32 [B]: SINGULAR if a transposed block could not be inverted
+ */
+size_t tvi_adjoint_workspace_bytes(const tvi_model *model, const tvi_options *opt, int64_t B);
+
+tvi_status tvi_solve_adjoint(const tvi_model *model, const tvi_options *opt, int64_t B, int64_t N,
+                             const int64_t *offsets, const void *times, const void *params,
+                             const void *y, const void *ckpt, const void *g, void *dLdp,
+                             void *dLdy0, int32_t *status, void *workspace, size_t workspace_bytes,
+                             void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TVI_H */

@@ -1,0 +1,250 @@
+// C ABI entry points (declared in tvi.h): argument checks on the host, choice
+// of the lane tiling, and the launch on the caller's stream.
+#include <string.h>
+
+#include "dispatch.hpp"
+
+using namespace tvi;
+
+namespace {
+
+bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
+
+int next_pow2(int v)
+{
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+// Lanes per series S and steps per lane T for a chunk of C steps: the fewest
+// steps per lane that fit the chunk in one wavefront, then the fewest lanes.
+void choose_tiling(int C, int &S, int &T)
+{
+    if (C <= 1) { S = 1; T = 1; return; }
+    T = 1;
+    while (T < 8 && T * kWave < C) T <<= 1;
+    S = next_pow2((C + T - 1) / T);
+    if (S < 4) S = 4;
+    if (S > kWave) S = kWave;
+}
+
+int model_params(const tvi_model *m)
+{
+    switch (m->kind) {
+    case TVI_LINEAR: return m->n * m->n;
+    case TVI_VANDERPOL: return 1;
+    case TVI_ROBERTSON: return 3;
+    case TVI_MLP: {
+        const int n = m->n, H = m->hidden;
+        return H * n + H + H * H + H + n * H + n;
+    }
+    default: return -1;
+    }
+}
+
+tvi_status check_model(const tvi_model *m)
+{
+    if (!m) return TVI_EINVAL;
+    if (m->dtype != TVI_F32 && m->dtype != TVI_F64) return TVI_EINVAL;
+    switch (m->kind) {
+    case TVI_LINEAR: return (m->n >= 2 && m->n <= 4) ? TVI_OK : TVI_EUNSUPPORTED;
+    case TVI_VANDERPOL: return m->n == 2 ? TVI_OK : TVI_EINVAL;
+    case TVI_ROBERTSON: return m->n == 3 ? TVI_OK : TVI_EINVAL;
+    case TVI_MLP: return TVI_EUNSUPPORTED;
+    default: return TVI_EINVAL;
+    }
+}
+
+tvi_status resolve_tiling(const tvi_options *o, int &S, int &T)
+{
+    if (o->lanes == 0 && o->steps_per_lane == 0) {
+        choose_tiling(o->chunk, S, T);
+    } else {
+        S = o->lanes;
+        T = o->steps_per_lane;
+        if (!(S == 1 || pow2_in(S, 4, kWave)) || !pow2_in(T, 1, 8)) return TVI_EINVAL;
+    }
+    if ((int64_t)S * T < o->chunk) return TVI_EINVAL;
+    return TVI_OK;
+}
+
+tvi_status check_options(const tvi_options *o)
+{
+    if (!o) return TVI_EINVAL;
+    if (o->chunk < 1 || o->chunk > 8 * kWave) return TVI_EINVAL;
+    if (o->max_newton < 1) return TVI_EINVAL;
+    if (!(o->tol_a >= 0.0) || !(o->tol_r >= 0.0)) return TVI_EINVAL;
+    if (o->init != TVI_INIT_ZERO && o->init != TVI_INIT_EXTRAP) return TVI_EINVAL;
+    return TVI_OK;
+}
+
+template <class IO>
+SolveArgs<IO> make_args(const tvi_model *model, const tvi_options *opt, int64_t B, int64_t N, const int64_t *offsets,
+                        const void *times, const void *y0, const void *params)
+{
+    SolveArgs<IO> a;
+    memset(&a, 0, sizeof(a));
+    a.B = B;
+    a.N = N;
+    a.K = (N + opt->chunk - 1) / opt->chunk + 1;
+    a.offsets = offsets;
+    a.times = static_cast<const IO *>(times);
+    a.y0 = static_cast<const IO *>(y0);
+    a.params = static_cast<const IO *>(params);
+    a.params_shared = model->params_shared;
+    a.chunk = opt->chunk;
+    a.max_newton = opt->max_newton;
+    a.init = opt->init;
+    a.halving = opt->halving;
+    a.tol_a = opt->tol_a;
+    a.tol_r = opt->tol_r;
+    return a;
+}
+
+tvi_status dispatch(int pass, const tvi_model *model, const void *args, int S, int T, hipStream_t stream)
+{
+    switch (model->kind) {
+    case TVI_VANDERPOL: return launch_vanderpol(pass, model->dtype, args, S, T, stream);
+    case TVI_ROBERTSON: return launch_robertson(pass, model->dtype, args, S, T, stream);
+    case TVI_LINEAR:
+        switch (model->n) {
+        case 2: return launch_linear2(pass, model->dtype, args, S, T, stream);
+        case 3: return launch_linear3(pass, model->dtype, args, S, T, stream);
+        case 4: return launch_linear4(pass, model->dtype, args, S, T, stream);
+        default: return TVI_EUNSUPPORTED;
+        }
+    default: return TVI_EUNSUPPORTED;
+    }
+}
+
+} // namespace
+
+extern "C" {
+
+void tvi_default_options(tvi_options *opt)
+{
+    if (!opt) return;
+    memset(opt, 0, sizeof(*opt));
+    opt->chunk = 64;
+    opt->lanes = 0;
+    opt->steps_per_lane = 0;
+    opt->max_newton = 50;
+    opt->tol_a = 1e-8;
+    opt->tol_r = 1e-6;
+    opt->init = TVI_INIT_ZERO;
+    opt->halving = 1;
+}
+
+const char *tvi_status_str(int32_t s)
+{
+    switch (s) {
+    case TVI_OK: return "ok";
+    case TVI_NOT_CONVERGED: return "Newton iteration did not converge";
+    case TVI_SINGULAR: return "singular diagonal block";
+    case TVI_NONFINITE: return "non-finite residual";
+    case TVI_EINVAL: return "invalid argument";
+    case TVI_EHIP: return "HIP launch or runtime error";
+    case TVI_ENOMEM: return "out of memory";
+    case TVI_EUNSUPPORTED: return "unsupported model, size or tiling";
+    default: return "unknown status";
+    }
+}
+
+const char *tvi_version(void) { return "tvi 0.1 gfx950"; }
+
+int32_t tvi_param_count(const tvi_model *model) { return model ? model_params(model) : -1; }
+
+tvi_status tvi_pcr_solve(int32_t dtype, int32_t n, int64_t B, int64_t m, const void *D, const void *r, void *x,
+                         int32_t transpose, void *stream)
+{
+    if (dtype != TVI_F32 && dtype != TVI_F64) return TVI_EINVAL;
+    if (n < 2 || n > 4) return TVI_EUNSUPPORTED;
+    if (B < 0 || m < 1 || m > 8 * kWave) return TVI_EINVAL;
+    if (B == 0) return TVI_OK;
+    if (!D || !r || !x) return TVI_EINVAL;
+    int S, T;
+    choose_tiling((int)m, S, T);
+    if (m == 1) { S = 4; T = 1; }
+    return launch_pcr(dtype, n, B, (int)m, D, r, x, transpose ? 1 : 0, S, T, static_cast<hipStream_t>(stream));
+}
+
+tvi_status tvi_solve_forward(const tvi_model *model, const tvi_options *opt, int64_t B, int64_t N,
+                             const int64_t *offsets, const void *times, const void *y0, const void *params,
+                             void *y_out, void *ckpt, int32_t *status, int32_t *iters, void *stream)
+{
+    tvi_status e = check_model(model);
+    if (e != TVI_OK) return e;
+    if ((e = check_options(opt)) != TVI_OK) return e;
+    if (B < 0 || N < 0) return TVI_EINVAL;
+    if (B == 0) return TVI_OK;
+    if (!times || !y0 || !params || !status || (!y_out && !ckpt)) return TVI_EINVAL;
+    int S, T;
+    if ((e = resolve_tiling(opt, S, T)) != TVI_OK) return e;
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    if (model->dtype == TVI_F64) {
+        SolveArgs<double> a = make_args<double>(model, opt, B, N, offsets, times, y0, params);
+        a.y = static_cast<double *>(y_out);
+        a.ckpt = static_cast<double *>(ckpt);
+        a.status = status;
+        a.iters = iters;
+        return dispatch(PASS_FORWARD, model, &a, S, T, st);
+    }
+    SolveArgs<float> a = make_args<float>(model, opt, B, N, offsets, times, y0, params);
+    a.y = static_cast<float *>(y_out);
+    a.ckpt = static_cast<double *>(ckpt);
+    a.status = status;
+    a.iters = iters;
+    return dispatch(PASS_FORWARD, model, &a, S, T, st);
+}
+
+size_t tvi_adjoint_workspace_bytes(const tvi_model *model, const tvi_options *opt, int64_t B)
+{
+    if (!model || !opt || B < 0 || model->n < 1) return 0;
+    return (size_t)B * (size_t)opt->chunk * (size_t)model->n * sizeof(double);
+}
+
+tvi_status tvi_solve_adjoint(const tvi_model *model, const tvi_options *opt, int64_t B, int64_t N,
+                             const int64_t *offsets, const void *times, const void *params, const void *y,
+                             const void *ckpt, const void *g, void *dLdp, void *dLdy0, int32_t *status,
+                             void *workspace, size_t workspace_bytes, void *stream)
+{
+    tvi_status e = check_model(model);
+    if (e != TVI_OK) return e;
+    if ((e = check_options(opt)) != TVI_OK) return e;
+    if (model->params_shared) return TVI_EUNSUPPORTED;
+    if (B < 0 || N < 0) return TVI_EINVAL;
+    if (B == 0) return TVI_OK;
+    if (!times || !params || !g || !dLdp || !dLdy0 || !status) return TVI_EINVAL;
+    const bool recompute = (y == nullptr);
+    if (recompute) {
+        if (!ckpt || !workspace) return TVI_EINVAL;
+        if (workspace_bytes < tvi_adjoint_workspace_bytes(model, opt, B)) return TVI_EINVAL;
+    }
+    int S, T;
+    if ((e = resolve_tiling(opt, S, T)) != TVI_OK) return e;
+    const int pass = recompute ? PASS_ADJOINT_RECOMPUTE : PASS_ADJOINT;
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    if (model->dtype == TVI_F64) {
+        SolveArgs<double> a = make_args<double>(model, opt, B, N, offsets, times, nullptr, params);
+        a.y = const_cast<double *>(static_cast<const double *>(y));
+        a.ckpt = const_cast<double *>(static_cast<const double *>(ckpt));
+        a.g = static_cast<const double *>(g);
+        a.dLdp = static_cast<double *>(dLdp);
+        a.dLdy0 = static_cast<double *>(dLdy0);
+        a.status = status;
+        a.ws = static_cast<double *>(workspace);
+        return dispatch(pass, model, &a, S, T, st);
+    }
+    SolveArgs<float> a = make_args<float>(model, opt, B, N, offsets, times, nullptr, params);
+    a.y = const_cast<float *>(static_cast<const float *>(y));
+    a.ckpt = const_cast<double *>(static_cast<const double *>(ckpt));
+    a.g = static_cast<const float *>(g);
+    a.dLdp = static_cast<float *>(dLdp);
+    a.dLdy0 = static_cast<float *>(dLdy0);
+    a.status = status;
+    a.ws = static_cast<double *>(workspace);
+    return dispatch(pass, model, &a, S, T, st);
+}
+
+} // extern "C"

@@ -1,0 +1,255 @@
+// Device building blocks for gfx950 (wave64): cross-lane moves, small dense
+// block algebra held in registers, and the segmented scans that carry the
+// parallel cyclic reduction of a block-bidiagonal chunk system (Section 3.2).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tvi {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+__device__ __forceinline__ bool finite(double x) { return __builtin_isfinite(x); }
+
+// Read `x` from lane `src` (0..63) of the wave.  All lanes must execute it.
+__device__ __forceinline__ double lane_read(double x, int src)
+{
+    const int addr = src << 2;
+    int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(x));
+    int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(x));
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ int lane_read(int x, int src)
+{
+    return __builtin_amdgcn_ds_bpermute(src << 2, x);
+}
+
+// Wave-uniform "does any lane satisfy p".
+__device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
+
+// Sum of x over the S-lane segment of this lane (butterfly; every lane of the
+// segment gets the same, order-fixed result).
+template <int S>
+__device__ __forceinline__ double seg_sum(double x)
+{
+#pragma unroll
+    for (int d = 1; d < S; d <<= 1) x += __shfl_xor(x, d, S);
+    return x;
+}
+
+template <int S>
+__device__ __forceinline__ int seg_and(int x)
+{
+#pragma unroll
+    for (int d = 1; d < S; d <<= 1) x &= __shfl_xor(x, d, S);
+    return x;
+}
+
+// ---------------------------------------------------------------------------
+// n x n blocks in registers (row-major, compile-time n: every index is static,
+// so nothing is spilled to scratch).
+// ---------------------------------------------------------------------------
+template <int N>
+__device__ __forceinline__ void set_identity(double (&A)[N][N])
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int k = 0; k < N; ++k) A[i][k] = (i == k) ? 1.0 : 0.0;
+}
+
+// C = A * B
+template <int N>
+__device__ __forceinline__ void matmul(const double (&A)[N][N], const double (&B)[N][N], double (&C)[N][N])
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            double s = A[i][0] * B[0][k];
+#pragma unroll
+            for (int l = 1; l < N; ++l) s = fma(A[i][l], B[l][k], s);
+            C[i][k] = s;
+        }
+}
+
+// y = A x + c   (y may alias c)
+template <int N>
+__device__ __forceinline__ void matvec_add(const double (&A)[N][N], const double (&x)[N], const double (&c)[N],
+                                           double (&y)[N])
+{
+    double t[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        double s = c[i];
+#pragma unroll
+        for (int l = 0; l < N; ++l) s = fma(A[i][l], x[l], s);
+        t[i] = s;
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) y[i] = t[i];
+}
+
+// y = A^T x + c
+template <int N>
+__device__ __forceinline__ void matTvec_add(const double (&A)[N][N], const double (&x)[N], const double (&c)[N],
+                                            double (&y)[N])
+{
+    double t[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        double s = c[i];
+#pragma unroll
+        for (int l = 0; l < N; ++l) s = fma(A[l][i], x[l], s);
+        t[i] = s;
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) y[i] = t[i];
+}
+
+// X = A^{-1} by Gauss-Jordan elimination with partial pivoting: for each
+// column the row of largest magnitude among the remaining ones is moved to the
+// pivot position by conditional (select) row exchanges, so every register
+// index stays static.  A is destroyed.  Returns false if a pivot is zero or
+// not finite.
+template <int N>
+__device__ __forceinline__ bool invert(double (&A)[N][N], double (&X)[N][N])
+{
+    set_identity(X);
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+#pragma unroll
+        for (int r = c + 1; r < N; ++r) {
+            const bool sw = fabs(A[r][c]) > fabs(A[c][c]);
+#pragma unroll
+            for (int k = c; k < N; ++k) {
+                const double a = A[r][k], b = A[c][k];
+                A[r][k] = sw ? b : a;
+                A[c][k] = sw ? a : b;
+            }
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const double a = X[r][k], b = X[c][k];
+                X[r][k] = sw ? b : a;
+                X[c][k] = sw ? a : b;
+            }
+        }
+        const double piv = A[c][c];
+        ok = ok && (piv != 0.0) && finite(piv);
+        const double ip = 1.0 / piv;
+#pragma unroll
+        for (int k = c; k < N; ++k) A[c][k] *= ip;
+#pragma unroll
+        for (int k = 0; k < N; ++k) X[c][k] *= ip;
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            if (r == c) continue;
+            const double f = A[r][c];
+#pragma unroll
+            for (int k = c; k < N; ++k) A[r][k] = fma(-f, A[c][k], A[r][k]);
+#pragma unroll
+            for (int k = 0; k < N; ++k) X[r][k] = fma(-f, X[c][k], X[r][k]);
+        }
+    }
+    return ok;
+}
+
+// ---------------------------------------------------------------------------
+// Affine maps v -> M v + z over a segment of S lanes.
+//
+// A block lower-bidiagonal system with sub-diagonal blocks -I,
+//   D_j x_j - x_{j-1} = r_j,
+// is the affine recurrence x_j = M_j x_{j-1} + z_j with M_j = D_j^{-1},
+// z_j = D_j^{-1} r_j and x_0 = 0.  One level of parallel cyclic reduction at
+// stride d replaces row j's dependence on x_{j-1..} by one on x_{j-d..}:
+// z_j <- z_j + M_j z_{j-d},  M_j <- M_j M_{j-d}  (the split of Section 3.2
+// with B = -I), i.e. a Kogge-Stone scan with map composition.
+// ---------------------------------------------------------------------------
+template <int N>
+struct Affine {
+    double M[N][N];
+    double z[N];
+};
+
+template <int N>
+__device__ __forceinline__ void affine_identity(Affine<N> &a)
+{
+    set_identity(a.M);
+#pragma unroll
+    for (int i = 0; i < N; ++i) a.z[i] = 0.0;
+}
+
+// a <- a o b  (apply b first, then a):  M = Ma Mb,  z = Ma zb + za
+template <int N>
+__device__ __forceinline__ void affine_after(Affine<N> &a, const Affine<N> &b)
+{
+    matvec_add(a.M, b.z, a.z, a.z);
+    double t[N][N];
+    matmul(a.M, b.M, t);
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int k = 0; k < N; ++k) a.M[i][k] = t[i][k];
+}
+
+template <int N>
+__device__ __forceinline__ void affine_read(const Affine<N> &a, int src, Affine<N> &out)
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) out.M[i][k] = lane_read(a.M[i][k], src);
+        out.z[i] = lane_read(a.z[i], src);
+    }
+}
+
+// Inclusive prefix composition over the segment, lowest lane first:
+// lane q ends with A_q o A_{q-1} o ... o A_0.
+template <int N, int S>
+__device__ __forceinline__ void seg_scan_up(Affine<N> &a)
+{
+    const int lane = lane_id();
+    const int q = lane & (S - 1);
+#pragma unroll
+    for (int d = 1; d < S; d <<= 1) {
+        Affine<N> o;
+        affine_read(a, q >= d ? lane - d : lane, o);
+        if (q >= d) affine_after(a, o);
+    }
+}
+
+// Inclusive suffix composition, highest lane first:
+// lane q ends with A_q o A_{q+1} o ... o A_{S-1}.
+template <int N, int S>
+__device__ __forceinline__ void seg_scan_down(Affine<N> &a)
+{
+    const int lane = lane_id();
+    const int q = lane & (S - 1);
+#pragma unroll
+    for (int d = 1; d < S; d <<= 1) {
+        Affine<N> o;
+        affine_read(a, q + d < S ? lane + d : lane, o);
+        if (q + d < S) affine_after(a, o);
+    }
+}
+
+// Vector of N doubles from lane src.
+template <int N>
+__device__ __forceinline__ void vec_read(const double (&v)[N], int src, double (&out)[N])
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) out[i] = lane_read(v[i], src);
+}
+
+// IO conversions
+template <class IO>
+__device__ __forceinline__ double ld(const IO *p) { return static_cast<double>(*p); }
+template <class IO>
+__device__ __forceinline__ void st(IO *p, double v) { *p = static_cast<IO>(v); }
+
+} // namespace tvi

@@ -1,0 +1,68 @@
+// Host-side selection of the kernel instance for a (model, storage type,
+// lanes per series S, steps per lane T) combination.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "solver.hpp"
+#include "tvi.h"
+
+namespace tvi {
+
+enum Pass : int { PASS_FORWARD = 0, PASS_ADJOINT = 1, PASS_ADJOINT_RECOMPUTE = 2 };
+
+template <class Model, class IO, int S, int T>
+static tvi_status launch_st(int pass, const SolveArgs<IO> &a, hipStream_t stream)
+{
+    const int64_t per_block = kWave / S;
+    const int64_t blocks = (a.B + per_block - 1) / per_block;
+    if (blocks == 0) return TVI_OK;
+    if (blocks > 0x7fffffffLL) return TVI_EINVAL;
+    dim3 grid((unsigned)blocks), block(kWave);
+    switch (pass) {
+    case PASS_FORWARD: hipLaunchKernelGGL((forward_kernel<Model, IO, S, T>), grid, block, 0, stream, a); break;
+    case PASS_ADJOINT: hipLaunchKernelGGL((adjoint_kernel<Model, IO, S, T, false>), grid, block, 0, stream, a); break;
+    case PASS_ADJOINT_RECOMPUTE:
+        hipLaunchKernelGGL((adjoint_kernel<Model, IO, S, T, true>), grid, block, 0, stream, a);
+        break;
+    default: return TVI_EINVAL;
+    }
+    return hipGetLastError() == hipSuccess ? TVI_OK : TVI_EHIP;
+}
+
+template <class Model, class IO, int S>
+static tvi_status launch_s(int pass, const SolveArgs<IO> &a, int T, hipStream_t stream)
+{
+    switch (T) {
+    case 1: return launch_st<Model, IO, S, 1>(pass, a, stream);
+    case 2: return launch_st<Model, IO, S, 2>(pass, a, stream);
+    case 4: return launch_st<Model, IO, S, 4>(pass, a, stream);
+    case 8: return launch_st<Model, IO, S, 8>(pass, a, stream);
+    default: return TVI_EUNSUPPORTED;
+    }
+}
+
+template <class Model, class IO>
+tvi_status launch_solver(int pass, const SolveArgs<IO> &a, int S, int T, hipStream_t stream)
+{
+    switch (S) {
+    case 1: return launch_s<Model, IO, 1>(pass, a, T, stream);
+    case 4: return launch_s<Model, IO, 4>(pass, a, T, stream);
+    case 8: return launch_s<Model, IO, 8>(pass, a, T, stream);
+    case 16: return launch_s<Model, IO, 16>(pass, a, T, stream);
+    case 32: return launch_s<Model, IO, 32>(pass, a, T, stream);
+    case 64: return launch_s<Model, IO, 64>(pass, a, T, stream);
+    default: return TVI_EUNSUPPORTED;
+    }
+}
+
+// One entry per model family, defined in its own translation unit.
+tvi_status launch_vanderpol(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
+tvi_status launch_robertson(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
+tvi_status launch_linear2(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
+tvi_status launch_linear3(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
+tvi_status launch_linear4(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
+tvi_status launch_pcr(int dtype, int n, int64_t B, int m, const void *D, const void *r, void *x, int transpose,
+                      int S, int T, hipStream_t stream);
+
+} // namespace tvi

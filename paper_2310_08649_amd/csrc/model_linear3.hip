@@ -1,0 +1,13 @@
+// Kernel instances for the linear model h = A y with n = 3.
+#include "dispatch.hpp"
+
+namespace tvi {
+
+tvi_status launch_linear3(int pass, int dtype, const void *args, int S, int T, hipStream_t stream)
+{
+    if (dtype == TVI_F64)
+        return launch_solver<Linear<3>, double>(pass, *static_cast<const SolveArgs<double> *>(args), S, T, stream);
+    return launch_solver<Linear<3>, float>(pass, *static_cast<const SolveArgs<float> *>(args), S, T, stream);
+}
+
+} // namespace tvi

@@ -1,0 +1,164 @@
+// Standalone batched block-bidiagonal solve (Section 3): the linear kernel of
+// the chunked Newton update with its blocks materialised in HBM.
+//
+// System b (of B), m block rows, diagonal blocks D[b][j] (n x n), sub-diagonal
+// blocks -I:
+//   forward:    D_j x_j - x_{j-1} = r_j          (x_0 = 0)
+//   transposed: D_j^T x_j - x_{j+1} = r_j        (x_{m+1} = 0)
+// One segment of S lanes per system; lane q owns rows q*T .. q*T+T-1.  Each
+// lane inverts its blocks, composes its rows into one affine map, the segment
+// runs log2(S) reduction levels (Section 3.2 with B = -I), and each lane
+// replays its rows from the value entering it.  Every byte of D and r is read
+// once and every byte of x written once.
+#include "dispatch.hpp"
+
+namespace tvi {
+
+template <int N, class IO, int S, int T, bool TR>
+__global__ __launch_bounds__(kWave) void pcr_kernel(int64_t B, int m, const IO *__restrict__ D,
+                                                   const IO *__restrict__ r, IO *__restrict__ x)
+{
+    const int lane = lane_id();
+    const int q = lane & (S - 1);
+    const int64_t b = (int64_t)blockIdx.x * (kWave / S) + lane / S;
+    const bool valid = b < B;
+    const IO *Db = D + (valid ? b : 0) * (int64_t)m * N * N;
+    const IO *rb = r + (valid ? b : 0) * (int64_t)m * N;
+
+    double Mi[T][N][N], zi[T][N];
+    Affine<N> map;
+    affine_identity(map);
+    int ok = 1;
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+        const int i = TR ? T - 1 - u : u;  // composition order: along the recurrence
+        const int j = q * T + i;
+        if (valid && j < m) {
+            double A[N][N], rv[N];
+#pragma unroll
+            for (int e = 0; e < N; ++e) {
+#pragma unroll
+                for (int c = 0; c < N; ++c) {
+                    const double v = ld(Db + ((int64_t)j * N + e) * N + c);
+                    if (TR) A[c][e] = v;
+                    else A[e][c] = v;
+                }
+                rv[e] = ld(rb + (int64_t)j * N + e);
+            }
+            ok &= invert(A, Mi[i]) ? 1 : 0;
+            const double zero[N] = {};
+            matvec_add(Mi[i], rv, zero, zi[i]);
+            Affine<N> stp;
+#pragma unroll
+            for (int e = 0; e < N; ++e) {
+#pragma unroll
+                for (int c = 0; c < N; ++c) stp.M[e][c] = Mi[i][e][c];
+                stp.z[e] = zi[i][e];
+            }
+            affine_after(stp, map);
+            map = stp;
+        }
+    }
+    double din[N];
+    if (!TR) {
+        seg_scan_up<N, S>(map);
+        vec_read(map.z, q > 0 ? lane - 1 : lane, din);
+        if (q == 0) {
+#pragma unroll
+            for (int e = 0; e < N; ++e) din[e] = 0.0;
+        }
+    } else {
+        seg_scan_down<N, S>(map);
+        vec_read(map.z, q < S - 1 ? lane + 1 : lane, din);
+        if (q == S - 1) {
+#pragma unroll
+            for (int e = 0; e < N; ++e) din[e] = 0.0;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+        const int i = TR ? T - 1 - u : u;
+        const int j = q * T + i;
+        if (valid && j < m) {
+            matvec_add(Mi[i], din, zi[i], din);
+#pragma unroll
+            for (int e = 0; e < N; ++e) zi[i][e] = din[e];
+        }
+    }
+    ok = seg_and<S>(ok);
+    const double nan = __builtin_nan("");
+    IO *xb = x + (valid ? b : 0) * (int64_t)m * N;
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+        const int j = q * T + i;
+        if (valid && j < m) {
+#pragma unroll
+            for (int e = 0; e < N; ++e) st(xb + (int64_t)j * N + e, ok ? zi[i][e] : nan);
+        }
+    }
+}
+
+template <int N, class IO, int S, int T>
+static tvi_status pcr_launch_st(int64_t B, int m, const void *D, const void *r, void *x, int transpose,
+                                hipStream_t stream)
+{
+    const int64_t per_block = kWave / S;
+    const int64_t blocks = (B + per_block - 1) / per_block;
+    if (blocks == 0) return TVI_OK;
+    if (blocks > 0x7fffffffLL) return TVI_EINVAL;
+    const IO *Dp = static_cast<const IO *>(D);
+    const IO *rp = static_cast<const IO *>(r);
+    IO *xp = static_cast<IO *>(x);
+    if (transpose)
+        hipLaunchKernelGGL((pcr_kernel<N, IO, S, T, true>), dim3((unsigned)blocks), dim3(kWave), 0, stream, B, m,
+                           Dp, rp, xp);
+    else
+        hipLaunchKernelGGL((pcr_kernel<N, IO, S, T, false>), dim3((unsigned)blocks), dim3(kWave), 0, stream, B, m,
+                           Dp, rp, xp);
+    return hipGetLastError() == hipSuccess ? TVI_OK : TVI_EHIP;
+}
+
+template <int N, class IO, int S>
+static tvi_status pcr_launch_s(int64_t B, int m, const void *D, const void *r, void *x, int transpose, int T,
+                               hipStream_t stream)
+{
+    switch (T) {
+    case 1: return pcr_launch_st<N, IO, S, 1>(B, m, D, r, x, transpose, stream);
+    case 2: return pcr_launch_st<N, IO, S, 2>(B, m, D, r, x, transpose, stream);
+    case 4: return pcr_launch_st<N, IO, S, 4>(B, m, D, r, x, transpose, stream);
+    case 8: return pcr_launch_st<N, IO, S, 8>(B, m, D, r, x, transpose, stream);
+    default: return TVI_EUNSUPPORTED;
+    }
+}
+
+template <int N, class IO>
+static tvi_status pcr_launch(int64_t B, int m, const void *D, const void *r, void *x, int transpose, int S, int T,
+                             hipStream_t stream)
+{
+    switch (S) {
+    case 1: return pcr_launch_s<N, IO, 1>(B, m, D, r, x, transpose, T, stream);
+    case 4: return pcr_launch_s<N, IO, 4>(B, m, D, r, x, transpose, T, stream);
+    case 8: return pcr_launch_s<N, IO, 8>(B, m, D, r, x, transpose, T, stream);
+    case 16: return pcr_launch_s<N, IO, 16>(B, m, D, r, x, transpose, T, stream);
+    case 32: return pcr_launch_s<N, IO, 32>(B, m, D, r, x, transpose, T, stream);
+    case 64: return pcr_launch_s<N, IO, 64>(B, m, D, r, x, transpose, T, stream);
+    default: return TVI_EUNSUPPORTED;
+    }
+}
+
+tvi_status launch_pcr(int dtype, int n, int64_t B, int m, const void *D, const void *r, void *x, int transpose,
+                      int S, int T, hipStream_t stream)
+{
+    const bool f64 = dtype == TVI_F64;
+    switch (n) {
+    case 2: return f64 ? pcr_launch<2, double>(B, m, D, r, x, transpose, S, T, stream)
+                       : pcr_launch<2, float>(B, m, D, r, x, transpose, S, T, stream);
+    case 3: return f64 ? pcr_launch<3, double>(B, m, D, r, x, transpose, S, T, stream)
+                       : pcr_launch<3, float>(B, m, D, r, x, transpose, S, T, stream);
+    case 4: return f64 ? pcr_launch<4, double>(B, m, D, r, x, transpose, S, T, stream)
+                       : pcr_launch<4, float>(B, m, D, r, x, transpose, S, T, stream);
+    default: return TVI_EUNSUPPORTED;
+    }
+}
+
+} // namespace tvi

@@ -1,0 +1,513 @@
+// Chunked backward-Euler Newton solver and its discrete adjoint, one
+// wavefront segment of S lanes per series.
+//
+// Tiling.  A chunk of m <= S*T steps is spread over the S lanes of a segment,
+// lane q owning the T consecutive steps q*T+1 .. q*T+T.  Every Newton
+// iteration (Algorithm 1, Eq. batched-update):
+//   1. each lane evaluates the residual of its steps (Eq. batched-backward-
+//      euler), R_j = dy_j - dy_{j-1} - dt_j h(y_s + dy_j, t_{s+j});
+//      ||R|| is a butterfly sum over the segment;
+//   2. each lane forms its diagonal blocks D_j = I - dt_j j_j, inverts them
+//      (partial pivoting) and composes its T rows serially into one affine map
+//      (the in-lane part is Thomas's algorithm, Alg. thomas);
+//   3. log2(S) parallel-cyclic-reduction levels (Section 3.2) compose the
+//      lane maps across the segment through cross-lane reads;
+//   4. each lane replays its T rows from the reduced value entering it and
+//      adds the Newton correction to dy.
+// S = 1 is the one-series-per-lane sequential solver (chunk = 1) or
+// per-lane Thomas; T = 1 is pure PCR.
+//
+// Control flow is flattened into one wave-uniform loop so that series of a
+// wave that converge, fail, halve their chunk or finish at different times
+// never leave a cross-lane read divergent.
+#pragma once
+
+#include "device.hpp"
+#include "models.hpp"
+
+namespace tvi {
+
+enum : int { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_SINGULAR = 2, ST_NONFINITE = 3 };
+enum : int { INIT_ZERO = 0, INIT_EXTRAP = 1 };
+
+template <class IO>
+struct SolveArgs {
+    int64_t B, N, K;           // series, steps (uniform) / max steps, checkpoints per series
+    const int64_t *offsets;    // point offsets [B+1] or null
+    const IO *times, *y0, *params;
+    int32_t params_shared;
+    IO *y;                     // trajectory (forward output / adjoint input) or null
+    double *ckpt;              // [B][K][n] or null
+    int32_t *status, *iters;
+    int32_t chunk, max_newton, init, halving;
+    double tol_a, tol_r;
+    const IO *g;               // adjoint: dL/dy
+    IO *dLdp, *dLdy0;
+    double *ws;                // adjoint recompute workspace [B][chunk][n]
+};
+
+template <class IO>
+struct SeriesView {
+    int64_t b, p0, Nb;
+    const IO *t;
+    bool valid;
+    __device__ __forceinline__ SeriesView(const SolveArgs<IO> &a, int64_t b_) : b(b_)
+    {
+        valid = b < a.B;
+        if (!valid) { p0 = 0; Nb = 0; t = a.times; return; }
+        if (a.offsets) {
+            p0 = a.offsets[b];
+            Nb = a.offsets[b + 1] - p0 - 1;
+            t = a.times + p0;
+        } else {
+            p0 = b * (a.N + 1);
+            Nb = a.N;
+            t = a.times;
+        }
+    }
+};
+
+// Where converged states go: the trajectory and checkpoints (forward) or the
+// per-series recompute workspace (adjoint).
+template <class IO, int N>
+struct TrajectorySink {
+    IO *y;       // series' first point, or null
+    double *ck;  // series' checkpoints, or null
+    int64_t Nb;
+    int64_t K;   // checkpoints per series
+    int32_t C;
+    __device__ __forceinline__ void put(int64_t k, const double (&v)[N]) const
+    {
+        if (y) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) st(y + k * N + i, v[i]);
+        }
+    }
+    __device__ __forceinline__ void boundary(int64_t s, const double (&v)[N], int q) const
+    {
+        const int64_t c = (s + C - 1) / C;
+        if (ck && q == 0 && c < K) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) ck[c * N + i] = v[i];
+        }
+    }
+    template <int S>
+    __device__ __forceinline__ void fail(int64_t s, int q) const
+    {
+        if (!y) return;
+        const double nan = __builtin_nan("");
+        for (int64_t k = s + 1 + q; k <= Nb; k += S)
+#pragma unroll
+            for (int i = 0; i < N; ++i) st(y + k * N + i, nan);
+    }
+};
+
+template <int N>
+struct WorkspaceSink {
+    double *w;   // series' workspace [chunk][N]
+    int64_t c0;  // first step of the nominal chunk being recomputed
+    __device__ __forceinline__ void put(int64_t k, const double (&v)[N]) const
+    {
+#pragma unroll
+        for (int i = 0; i < N; ++i) w[(k - c0 - 1) * N + i] = v[i];
+    }
+    __device__ __forceinline__ void boundary(int64_t, const double (&)[N], int) const {}
+    template <int S>
+    __device__ __forceinline__ void fail(int64_t, int) const {}
+};
+
+// Per-lane state of the chunked Newton solve of one series.
+template <class Model, int S, int T>
+struct ChunkNewton {
+    static constexpr int n = Model::N;
+
+    double ys[n];      // state at the chunk start
+    int64_t s;         // chunk start step
+    int64_t s_end;     // the solve ends when s reaches s_end
+    int m, mcur;       // attempt length and the current limit (halved on failure)
+    int it, total;     // corrections in this attempt / in total
+    double nrm0;
+    bool active, start, sing;
+    int status;
+    double dy[T][n];   // Newton iterate Delta y of the owned steps
+    double tt[T], hh[T];
+
+    __device__ __forceinline__ bool owned(int q, int i) const { return active && (q * T + i + 1 <= m); }
+
+    // Solve steps s..s_end from ys (already set).  C is the nominal chunk
+    // length: attempts never cross a multiple of C, so a checkpoint at every
+    // multiple of C restarts the identical sequence of attempts.
+    template <class IO, class Sink>
+    __device__ void run(const Model &model, const IO *t, int C, int max_newton, double tol_a, double tol_r,
+                        int init, bool halving, const Sink &sink)
+    {
+        const int lane = lane_id();
+        const int q = lane & (S - 1);
+        const int base = lane - q;
+        start = true;
+        sing = false;
+        it = 0;
+        nrm0 = 0.0;
+        m = 0;
+        mcur = C;
+        double Mi[T][n][n], zi[T][n], R[T][n];
+
+        while (wave_any(active)) {
+            // ---- attempt set-up: owned times and the initial iterate (lane-local)
+            if (active && start) {
+                const int64_t nom_end = min((s / C + 1) * (int64_t)C, s_end);
+                m = (int)min((int64_t)mcur, nom_end - s);
+                const double ts = ld(t + s);
+                double slope[n];
+                if (init == INIT_EXTRAP) {
+                    model.rhs(ys, ts, slope);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < n; ++k) slope[k] = 0.0;
+                }
+#pragma unroll
+                for (int i = 0; i < T; ++i) {
+                    const int j = q * T + i + 1;
+                    const bool v = j <= m;
+                    const int64_t kk = v ? s + j : s;
+                    tt[i] = ld(t + kk);
+                    const double tp = (i == 0) ? ld(t + (v ? kk - 1 : s)) : tt[i - 1];
+                    hh[i] = v ? tt[i] - tp : 0.0;
+#pragma unroll
+                    for (int k = 0; k < n; ++k) dy[i][k] = v ? (tt[i] - ts) * slope[k] : 0.0;
+                }
+                it = 0;
+                sing = false;
+                start = false;
+            }
+
+            // ---- residual of the owned steps and its segment norm
+            double prev[n];
+            vec_read(dy[T - 1], q > 0 ? lane - 1 : lane, prev);
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i < T; ++i) {
+                double yv[n], f[n];
+#pragma unroll
+                for (int k = 0; k < n; ++k) yv[k] = ys[k] + dy[i][k];
+                model.rhs(yv, tt[i], f);
+                const bool v = owned(q, i);
+#pragma unroll
+                for (int k = 0; k < n; ++k) {
+                    const double dp = (i == 0) ? (q > 0 ? prev[k] : 0.0) : dy[i - 1][k];
+                    const double r = (dy[i][k] - dp) - hh[i] * f[k];
+                    R[i][k] = v ? r : 0.0;
+                    acc = fma(R[i][k], R[i][k], acc);
+                }
+            }
+            const double nrm = sqrt(seg_sum<S>(acc));
+
+            // ---- per-series decision (uniform within the segment)
+            int act = 0; // 1 converged, 2 failed, 3 correct
+            int code = ST_OK;
+            if (active) {
+                if (it == 0) nrm0 = nrm;
+                if (sing) { act = 2; code = ST_SINGULAR; }
+                else if (!finite(nrm)) { act = 2; code = ST_NONFINITE; }
+                else if (nrm <= tol_a || nrm <= tol_r * nrm0) act = 1;
+                else if (it >= max_newton) { act = 2; code = ST_NOT_CONVERGED; }
+                else act = 3;
+            }
+
+            // ---- commit converged chunks
+            if (wave_any(act == 1)) {
+                const int mm = (act == 1) ? m : 1;
+                const int im = (mm - 1) % T, qm = (mm - 1) / T;
+                double cand[n];
+#pragma unroll
+                for (int k = 0; k < n; ++k) cand[k] = dy[0][k];
+#pragma unroll
+                for (int i = 1; i < T; ++i)
+#pragma unroll
+                    for (int k = 0; k < n; ++k) cand[k] = (i == im) ? dy[i][k] : cand[k];
+                double last[n];
+                vec_read(cand, (act == 1) ? base + qm : lane, last);
+                if (act == 1) {
+#pragma unroll
+                    for (int i = 0; i < T; ++i) {
+                        if (owned(q, i)) {
+                            double v[n];
+#pragma unroll
+                            for (int k = 0; k < n; ++k) v[k] = ys[k] + dy[i][k];
+                            sink.put(s + q * T + i + 1, v);
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < n; ++k) ys[k] += last[k];
+                    s += m;
+                    if (s % C == 0 || s >= s_end) sink.boundary(s, ys, q);
+                    if (s % C == 0) mcur = C;
+                    if (s >= s_end) active = false;
+                    start = true;
+                }
+            }
+            if (act == 2) {
+                if (halving && m > 1) {
+                    mcur = (m + 1) / 2;
+                    start = true;
+                } else {
+                    status = code;
+                    active = false;
+                    sink.template fail<S>(s, q);
+                }
+            }
+
+            // ---- Newton correction: blocks, in-lane composition, PCR, replay
+            if (wave_any(act == 3)) {
+                const bool corr = act == 3;
+                Affine<n> map;
+                affine_identity(map);
+                int ok = 1;
+#pragma unroll
+                for (int i = 0; i < T; ++i) {
+                    if (corr && owned(q, i)) {
+                        double yv[n], J[n][n], D[n][n];
+#pragma unroll
+                        for (int k = 0; k < n; ++k) yv[k] = ys[k] + dy[i][k];
+                        model.jac(yv, tt[i], J);
+#pragma unroll
+                        for (int r = 0; r < n; ++r)
+#pragma unroll
+                            for (int c = 0; c < n; ++c) D[r][c] = ((r == c) ? 1.0 : 0.0) - hh[i] * J[r][c];
+                        ok &= invert(D, Mi[i]) ? 1 : 0;
+                        const double zero[n] = {};
+                        double negR[n];
+#pragma unroll
+                        for (int k = 0; k < n; ++k) negR[k] = -R[i][k];
+                        matvec_add(Mi[i], negR, zero, zi[i]);
+                        if (i == 0) {
+#pragma unroll
+                            for (int r = 0; r < n; ++r) {
+#pragma unroll
+                                for (int c = 0; c < n; ++c) map.M[r][c] = Mi[0][r][c];
+                                map.z[r] = zi[0][r];
+                            }
+                        } else {
+                            Affine<n> step;
+#pragma unroll
+                            for (int r = 0; r < n; ++r) {
+#pragma unroll
+                                for (int c = 0; c < n; ++c) step.M[r][c] = Mi[i][r][c];
+                                step.z[r] = zi[i][r];
+                            }
+                            affine_after(step, map);
+                            map = step;
+                        }
+                    }
+                }
+                seg_scan_up<n, S>(map);
+                double din[n];
+                vec_read(map.z, q > 0 ? lane - 1 : lane, din);
+                if (q == 0) {
+#pragma unroll
+                    for (int k = 0; k < n; ++k) din[k] = 0.0;
+                }
+#pragma unroll
+                for (int i = 0; i < T; ++i) {
+                    if (corr && owned(q, i)) {
+                        matvec_add(Mi[i], din, zi[i], din);
+#pragma unroll
+                        for (int k = 0; k < n; ++k) dy[i][k] += din[k];
+                    }
+                }
+                ok = seg_and<S>(ok);
+                if (corr) {
+                    ++it;
+                    ++total;
+                    if (!ok) sing = true;
+                }
+            }
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Forward kernel: one segment of S lanes per series, 64 / S series per wave.
+// ---------------------------------------------------------------------------
+template <class Model, class IO, int S, int T>
+__global__ __launch_bounds__(kWave) void forward_kernel(SolveArgs<IO> a)
+{
+    constexpr int n = Model::N;
+    const int lane = lane_id();
+    const int q = lane & (S - 1);
+    const SeriesView<IO> sv(a, (int64_t)blockIdx.x * (kWave / S) + lane / S);
+
+    Model model;
+    if (sv.valid) model.load(a.params_shared ? a.params : a.params + sv.b * Model::P);
+
+    ChunkNewton<Model, S, T> cn;
+    if (sv.valid) {
+#pragma unroll
+        for (int k = 0; k < n; ++k) cn.ys[k] = ld(a.y0 + sv.b * n + k);
+    } else {
+#pragma unroll
+        for (int k = 0; k < n; ++k) cn.ys[k] = 0.0;
+    }
+    TrajectorySink<IO, n> sink{a.y ? a.y + sv.p0 * n : nullptr, a.ckpt ? a.ckpt + sv.b * a.K * n : nullptr,
+                               sv.Nb, a.K, a.chunk};
+    if (sv.valid && q == 0) {
+        sink.put(0, cn.ys);
+        sink.boundary(0, cn.ys, 0);
+    }
+    cn.s = 0;
+    cn.s_end = sv.Nb;
+    cn.total = 0;
+    cn.status = ST_OK;
+    cn.active = sv.valid && sv.Nb > 0;
+    cn.run(model, sv.t, a.chunk, a.max_newton, a.tol_a, a.tol_r, a.init, a.halving != 0, sink);
+    if (sv.valid && q == 0) {
+        a.status[sv.b] = cn.status;
+        if (a.iters) a.iters[sv.b] = cn.total;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint kernel (Appendix A): nominal chunks in reverse order; the chunk's
+// transposed block upper-bidiagonal system (D_j^T lam_j - lam_{j+1} = g_j) is
+// the affine recurrence lam_j = D_j^{-T} lam_{j+1} + D_j^{-T} g_j, reduced by
+// the same segment scan run from the highest lane down.  With RECOMPUTE the
+// chunk's states are re-solved from its checkpoint by the forward code.
+// ---------------------------------------------------------------------------
+template <class Model, class IO, int S, int T, bool RECOMPUTE>
+__global__ __launch_bounds__(kWave) void adjoint_kernel(SolveArgs<IO> a)
+{
+    constexpr int n = Model::N;
+    constexpr int P = Model::P;
+    const int lane = lane_id();
+    const int q = lane & (S - 1);
+    const int base = lane - q;
+    const SeriesView<IO> sv(a, (int64_t)blockIdx.x * (kWave / S) + lane / S);
+    const int C = a.chunk;
+
+    Model model;
+    if (sv.valid) model.load(a.params + sv.b * P);
+
+    double lam[n], gp[P];
+#pragma unroll
+    for (int k = 0; k < n; ++k) lam[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < P; ++k) gp[k] = 0.0;
+
+    const IO *gb = a.g + sv.p0 * n;
+    const IO *yb = a.y ? a.y + sv.p0 * n : nullptr;
+    double *wsb = RECOMPUTE ? a.ws + sv.b * (int64_t)C * n : nullptr;
+    int64_t c = sv.valid ? (sv.Nb + C - 1) / C - 1 : -1;
+    bool active = c >= 0;
+    int status = ST_OK;
+
+    while (wave_any(active)) {
+        const int64_t s = active ? c * C : 0;
+        const int m = active ? (int)min((int64_t)C, sv.Nb - s) : 0;
+
+        if (RECOMPUTE) {
+            ChunkNewton<Model, S, T> cn;
+            const bool have_ckpt = active && c < a.K;
+            if (active && !have_ckpt) status = ST_NONFINITE;
+            cn.active = have_ckpt;
+            cn.s = s;
+            cn.s_end = s + m;
+            cn.total = 0;
+            cn.status = ST_OK;
+#pragma unroll
+            for (int k = 0; k < n; ++k) cn.ys[k] = have_ckpt ? a.ckpt[(sv.b * a.K + c) * n + k] : 0.0;
+            WorkspaceSink<n> wsink{wsb, s};
+            cn.run(model, sv.t, C, a.max_newton, a.tol_a, a.tol_r, a.init, a.halving != 0, wsink);
+            if (active && cn.status != ST_OK) status = cn.status;
+            __syncthreads(); // one wave per block: makes the workspace writes visible to the wave
+        }
+
+        // ---- transposed blocks and the in-lane reverse composition
+        double Ni[T][n][n], wi[T][n], yl[T][n], hl[T], tl[T];
+        Affine<n> map;
+        affine_identity(map);
+        int ok = 1;
+#pragma unroll
+        for (int i = T - 1; i >= 0; --i) {
+            const int j = q * T + i + 1;
+            const bool v = active && j <= m;
+            const int64_t k = s + (v ? j : 1);
+            double gk[n];
+#pragma unroll
+            for (int e = 0; e < n; ++e) {
+                if (RECOMPUTE) yl[i][e] = v ? wsb[(j - 1) * n + e] : 0.0;
+                else yl[i][e] = v ? ld(yb + k * n + e) : 0.0;
+                gk[e] = v ? ld(gb + k * n + e) : 0.0;
+            }
+            tl[i] = v ? ld(sv.t + k) : 0.0;
+            hl[i] = v ? tl[i] - ld(sv.t + k - 1) : 0.0;
+            if (v) {
+                double J[n][n], D[n][n], Mi[n][n];
+                model.jac(yl[i], tl[i], J);
+#pragma unroll
+                for (int r = 0; r < n; ++r)
+#pragma unroll
+                    for (int cc = 0; cc < n; ++cc) D[r][cc] = ((r == cc) ? 1.0 : 0.0) - hl[i] * J[r][cc];
+                ok &= invert(D, Mi) ? 1 : 0;
+#pragma unroll
+                for (int r = 0; r < n; ++r)
+#pragma unroll
+                    for (int cc = 0; cc < n; ++cc) Ni[i][r][cc] = Mi[cc][r];
+                const double zero[n] = {};
+                matvec_add(Ni[i], gk, zero, wi[i]);
+                Affine<n> stp;
+#pragma unroll
+                for (int r = 0; r < n; ++r) {
+#pragma unroll
+                    for (int cc = 0; cc < n; ++cc) stp.M[r][cc] = Ni[i][r][cc];
+                    stp.z[r] = wi[i][r];
+                }
+                affine_after(stp, map);
+                map = stp;
+            }
+        }
+        seg_scan_down<n, S>(map);
+        // lam at the first owned step of every lane, then the value entering from the right
+        double vq[n], lin[n];
+        matvec_add(map.M, lam, map.z, vq);
+        vec_read(vq, q < S - 1 ? lane + 1 : lane, lin);
+        if (q == S - 1) {
+#pragma unroll
+            for (int k = 0; k < n; ++k) lin[k] = lam[k];
+        }
+#pragma unroll
+        for (int i = T - 1; i >= 0; --i) {
+            const int j = q * T + i + 1;
+            if (active && j <= m) {
+                matvec_add(Ni[i], lin, wi[i], lin);
+                double w[n];
+#pragma unroll
+                for (int k = 0; k < n; ++k) w[k] = hl[i] * lin[k];
+                model.vjp_p(yl[i], tl[i], w, gp);
+            }
+        }
+        double first[n];
+        vec_read(vq, base, first);
+        ok = seg_and<S>(ok);
+        if (active) {
+#pragma unroll
+            for (int k = 0; k < n; ++k) lam[k] = first[k];
+            if (!ok && status == ST_OK) status = ST_SINGULAR;
+            --c;
+            if (c < 0) active = false;
+        }
+    }
+
+    // dL/dy0 = g_0 + lam_1; dL/dp summed over the segment in a fixed order
+#pragma unroll
+    for (int k = 0; k < P; ++k) gp[k] = seg_sum<S>(gp[k]);
+    if (sv.valid && q == 0) {
+        const double nan = __builtin_nan("");
+#pragma unroll
+        for (int k = 0; k < n; ++k) st(a.dLdy0 + sv.b * n + k, status == ST_OK ? ld(gb + k) + lam[k] : nan);
+#pragma unroll
+        for (int k = 0; k < P; ++k) st(a.dLdp + sv.b * P + k, status == ST_OK ? gp[k] : nan);
+        a.status[sv.b] = status;
+    }
+}
+
+} // namespace tvi

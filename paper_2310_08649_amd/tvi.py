@@ -1,0 +1,276 @@
+"""Python binding of the C ABI in ``include/tvi.h`` (ctypes).
+
+Argument marshalling only: every step of the integration runs in the HIP
+kernels of ``libtvi.so``.  Tensors are torch CUDA tensors (ROCm), contiguous,
+series-major; work is enqueued on torch's current stream.  There is no CPU
+fallback: when the library or a GPU is missing these functions raise.
+
+Entry points with the C names:
+  ``pcr_solve``      batched block-bidiagonal solve (Section 3)
+  ``solve_forward``  chunked backward Euler (Algorithm 1)
+  ``solve_adjoint``  its discrete adjoint (Appendix A)
+and, on top of them,
+  ``odeint``         forward integration returning the trajectory
+  ``odeint_adjoint`` the same inside ``torch.autograd`` (gradients for y0 and
+                     the parameters from ``solve_adjoint``, chunk-boundary
+                     checkpoints saved in the forward pass)
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtvi.so")
+
+KINDS = {"linear": 0, "vanderpol": 1, "robertson": 2, "mlp": 3}
+F32, F64 = 0, 1
+INIT = {"zero": 0, "extrap": 1}
+STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "SINGULAR", 3: "NONFINITE"}
+
+
+class TviError(RuntimeError):
+    pass
+
+
+class Model(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("params_shared", ctypes.c_int32), ("hidden", ctypes.c_int32)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_int32), ("lanes", ctypes.c_int32), ("steps_per_lane", ctypes.c_int32),
+                ("max_newton", ctypes.c_int32), ("tol_a", ctypes.c_double), ("tol_r", ctypes.c_double),
+                ("init", ctypes.c_int32), ("halving", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """Load ``libtvi.so`` (built in-tree by ``paper_2310_08649_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise TviError("libtvi.so is not built: run paper_2310_08649_amd.build.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        MP, OP = ctypes.POINTER(Model), ctypes.POINTER(Options)
+        lib.tvi_default_options.argtypes = [OP]
+        lib.tvi_default_options.restype = None
+        lib.tvi_status_str.argtypes = [i32]
+        lib.tvi_status_str.restype = ctypes.c_char_p
+        lib.tvi_version.argtypes = []
+        lib.tvi_version.restype = ctypes.c_char_p
+        lib.tvi_param_count.argtypes = [MP]
+        lib.tvi_param_count.restype = i32
+        lib.tvi_pcr_solve.argtypes = [i32, i32, i64, i64, P, P, P, i32, P]
+        lib.tvi_pcr_solve.restype = i32
+        lib.tvi_solve_forward.argtypes = [MP, OP, i64, i64, P, P, P, P, P, P, P, P, P]
+        lib.tvi_solve_forward.restype = i32
+        lib.tvi_adjoint_workspace_bytes.argtypes = [MP, OP, i64]
+        lib.tvi_adjoint_workspace_bytes.restype = sz
+        lib.tvi_solve_adjoint.argtypes = [MP, OP, i64, i64, P, P, P, P, P, P, P, P, P, P, sz, P]
+        lib.tvi_solve_adjoint.restype = i32
+        _lib = lib
+    return _lib
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise TviError("%s: %s (%d)" % (what, load().tvi_status_str(rc).decode(), rc))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TviError("%s must be a CUDA (ROCm) tensor" % name)
+    if t.dtype != dtype:
+        raise TviError("%s must have dtype %s, got %s" % (name, dtype, t.dtype))
+    return t.contiguous()
+
+
+def _io_dtype(t):
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise TviError("floating-point arrays must be float32 or float64")
+
+
+def param_count(kind, n, hidden=64):
+    m = Model(KINDS[kind], n, F64, 0, hidden)
+    return load().tvi_param_count(ctypes.byref(m))
+
+
+def make_options(chunk=64, tol=(1e-8, 1e-6), max_newton=50, lanes=0, steps_per_lane=0, init="zero",
+                 halving=True):
+    o = Options()
+    load().tvi_default_options(ctypes.byref(o))
+    o.chunk = int(chunk)
+    o.tol_a, o.tol_r = float(tol[0]), float(tol[1])
+    o.max_newton = int(max_newton)
+    o.lanes, o.steps_per_lane = int(lanes), int(steps_per_lane)
+    o.init = INIT[init] if isinstance(init, str) else int(init)
+    o.halving = 1 if halving else 0
+    return o
+
+
+def pcr_solve(D, r, transpose=False, out=None):
+    """x [B, m, n] with D_j x_j - x_{j-1} = r_j (or the transposed system)."""
+    dt = D.dtype
+    D = _dev(D, dt, "D")
+    r = _dev(r, dt, "r")
+    B, m, n, n2 = D.shape
+    if n != n2 or r.shape != (B, m, n):
+        raise TviError("D must be [B, m, n, n] and r [B, m, n]")
+    x = out if out is not None else torch.empty_like(r)
+    _check(load().tvi_pcr_solve(_io_dtype(D), n, B, m, _ptr(D), _ptr(r), _ptr(x), 1 if transpose else 0,
+                                _stream()), "tvi_pcr_solve")
+    return x
+
+
+def _geometry(y0, times, offsets):
+    B, n = y0.shape
+    if offsets is None:
+        N = times.shape[0] - 1
+        return B, n, N, (B, N + 1, n)
+    if offsets.shape != (B + 1,):
+        raise TviError("offsets must be [B+1] point offsets")
+    N = int((offsets[1:] - offsets[:-1]).max().item()) - 1 if B else 0
+    return B, n, N, (times.shape[0], n)
+
+
+def solve_forward(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e-6), max_newton=50, lanes=0,
+                  steps_per_lane=0, init="zero", halving=True, checkpoints=False, y_out=None, iters=True):
+    """Chunked backward Euler.  Returns ``(y, status, iters, ckpt)`` (device tensors;
+    ``iters`` and ``ckpt`` may be None).  Asynchronous: nothing is synchronised."""
+    dt = y0.dtype
+    y0 = _dev(y0, dt, "y0")
+    times = _dev(times, dt, "times")
+    params = _dev(params, dt, "params")
+    if offsets is not None:
+        offsets = _dev(offsets, torch.int64, "offsets")
+    B, n, N, yshape = _geometry(y0, times, offsets)
+    model = Model(KINDS[kind], n, _io_dtype(y0), 1 if params.dim() == 1 else 0, 64)
+    opt = make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, halving)
+    dev = y0.device
+    y = y_out if y_out is not None else torch.empty(yshape, dtype=dt, device=dev)
+    status = torch.empty(B, dtype=torch.int32, device=dev)
+    it = torch.empty(B, dtype=torch.int32, device=dev) if iters else None
+    ck = None
+    if checkpoints:
+        K = (N + chunk - 1) // chunk + 1
+        ck = torch.empty((B, K, n), dtype=torch.float64, device=dev)
+    _check(load().tvi_solve_forward(ctypes.byref(model), ctypes.byref(opt), B, N, _ptr(offsets), _ptr(times),
+                                    _ptr(y0), _ptr(params), _ptr(y), _ptr(ck), _ptr(status), _ptr(it), _stream()),
+           "tvi_solve_forward")
+    return y, status, it, ck
+
+
+def solve_adjoint(kind, times, params, g, y=None, ckpt=None, offsets=None, chunk=64, tol=(1e-8, 1e-6),
+                  max_newton=50, lanes=0, steps_per_lane=0, init="zero", halving=True, n=None):
+    """Discrete adjoint.  Returns ``(dLdp [B,P], dLdy0 [B,n], status [B])``.
+
+    States come from the trajectory ``y`` or, when ``y`` is None, are recomputed
+    from ``ckpt`` (then the options must equal those of the forward pass)."""
+    dt = g.dtype
+    times = _dev(times, dt, "times")
+    params = _dev(params, dt, "params")
+    g = _dev(g, dt, "g")
+    if y is not None:
+        y = _dev(y, dt, "y")
+    if ckpt is not None:
+        ckpt = _dev(ckpt, torch.float64, "ckpt")
+    if offsets is not None:
+        offsets = _dev(offsets, torch.int64, "offsets")
+    if offsets is None:
+        B, n = g.shape[0], g.shape[2]
+        N = times.shape[0] - 1
+    else:
+        B, n = offsets.shape[0] - 1, g.shape[1]
+        N = int((offsets[1:] - offsets[:-1]).max().item()) - 1 if B else 0
+    if params.dim() != 2 or params.shape[0] != B:
+        raise TviError("the adjoint needs per-series parameters [B, P]")
+    model = Model(KINDS[kind], n, _io_dtype(g), 0, 64)
+    opt = make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, halving)
+    lib = load()
+    dev = g.device
+    P = lib.tvi_param_count(ctypes.byref(model))
+    dLdp = torch.empty((B, P), dtype=dt, device=dev)
+    dLdy0 = torch.empty((B, n), dtype=dt, device=dev)
+    status = torch.empty(B, dtype=torch.int32, device=dev)
+    ws, wsb = None, 0
+    if y is None:
+        wsb = lib.tvi_adjoint_workspace_bytes(ctypes.byref(model), ctypes.byref(opt), B)
+        ws = torch.empty(max(1, wsb), dtype=torch.uint8, device=dev)
+    _check(lib.tvi_solve_adjoint(ctypes.byref(model), ctypes.byref(opt), B, N, _ptr(offsets), _ptr(times),
+                                 _ptr(params), _ptr(y), _ptr(ckpt), _ptr(g), _ptr(dLdp), _ptr(dLdy0), _ptr(status),
+                                 _ptr(ws), wsb, _stream()), "tvi_solve_adjoint")
+    return dLdp, dLdy0, status
+
+
+def check_status(status, what="integration"):
+    """Synchronises and raises TviError if any series failed."""
+    st = status.cpu()
+    bad = torch.nonzero(st != 0).flatten()
+    if bad.numel():
+        b = int(bad[0])
+        raise TviError("%s failed for %d series (first: series %d, %s)"
+                       % (what, bad.numel(), b, STATUS.get(int(st[b]), str(int(st[b])))))
+
+
+def odeint(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e-6), check=True, **kw):
+    """Backward-Euler trajectory y [B, N+1, n] (or ragged [points, n])."""
+    y, status, _, _ = solve_forward(kind, y0, times, params, offsets=offsets, chunk=chunk, tol=tol, iters=False,
+                                    **kw)
+    if check:
+        check_status(status)
+    return y
+
+
+class _OdeintAdjoint(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, y0, params, kind, times, offsets, chunk, tol, recompute, check, kw):
+        y, status, _, ck = solve_forward(kind, y0, times, params, offsets=offsets, chunk=chunk, tol=tol,
+                                         checkpoints=True, iters=False, **kw)
+        if check:
+            check_status(status)
+        ctx.kind, ctx.chunk, ctx.tol, ctx.kw, ctx.check = kind, chunk, tol, kw, check
+        ctx.recompute = recompute
+        if recompute:
+            ctx.save_for_backward(times, params, ck, offsets if offsets is not None else torch.empty(0))
+        else:
+            ctx.save_for_backward(times, params, y, offsets if offsets is not None else torch.empty(0))
+        ctx.has_offsets = offsets is not None
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        times, params, saved, offsets = ctx.saved_tensors
+        offsets = offsets if ctx.has_offsets else None
+        y, ck = (None, saved) if ctx.recompute else (saved, None)
+        dLdp, dLdy0, status = solve_adjoint(ctx.kind, times, params, gy.contiguous(), y=y, ckpt=ck,
+                                            offsets=offsets, chunk=ctx.chunk, tol=ctx.tol, **ctx.kw)
+        if ctx.check:
+            check_status(status, "adjoint")
+        return dLdy0, dLdp, None, None, None, None, None, None, None, None
+
+
+def odeint_adjoint(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e-6), recompute=True, check=True,
+                   **kw):
+    """``odeint`` with gradients for ``y0`` and ``params`` by the hand-written
+    adjoint kernel.  With ``recompute`` the forward pass keeps only the
+    chunk-boundary checkpoints for the backward pass, which re-solves each
+    chunk's interior states (bitwise those of the forward pass)."""
+    return _OdeintAdjoint.apply(y0, params, kind, times, offsets, chunk, tol, recompute, check, kw)

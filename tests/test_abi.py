@@ -1,0 +1,116 @@
+"""The C-ABI library loads and exports every symbol tvi.h declares; host-side
+argument checks reject bad calls synchronously, before any launch.  CPU only:
+no call here reaches a kernel."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tvi.h")
+LIB = os.path.join(ROOT, "paper_2310_08649_amd", "libtvi.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tvi_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.skip("libtvi.so not built")
+    from paper_2310_08649_amd import tvi
+    return tvi.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for f in ("tvi_pcr_solve", "tvi_solve_forward", "tvi_solve_adjoint", "tvi_adjoint_workspace_bytes",
+              "tvi_default_options", "tvi_status_str", "tvi_version", "tvi_param_count"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings_and_defaults(lib):
+    from paper_2310_08649_amd import tvi
+    assert lib.tvi_status_str(0) == b"ok"
+    assert lib.tvi_status_str(-1) == b"invalid argument"
+    assert b"gfx950" in lib.tvi_version()
+    o = tvi.make_options()
+    assert o.chunk == 64 and o.tol_a == 1e-8 and o.tol_r == 1e-6 and o.halving == 1
+    assert tvi.param_count("linear", 4) == 16
+    assert tvi.param_count("vanderpol", 2) == 1
+    assert tvi.param_count("robertson", 3) == 3
+    assert tvi.param_count("mlp", 8, 64) == 5256
+
+
+def _fake():
+    return ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
+
+
+@pytest.mark.parametrize("field,value", [("chunk", 0), ("chunk", 513), ("max_newton", 0), ("tol_a", -1.0),
+                                         ("init", 7), ("lanes", 3), ("steps_per_lane", 16)])
+def test_forward_rejects_bad_options(lib, field, value):
+    from paper_2310_08649_amd import tvi
+    m = tvi.Model(tvi.KINDS["vanderpol"], 2, tvi.F64, 0, 64)
+    o = tvi.make_options(chunk=64)
+    if field in ("lanes", "steps_per_lane"):
+        o.lanes, o.steps_per_lane = 64, 1
+    setattr(o, field, value)
+    f = _fake()
+    rc = lib.tvi_solve_forward(ctypes.byref(m), ctypes.byref(o), 4, 10, None, f, f, f, f, None, f, None, None)
+    assert rc == -1
+
+
+def test_forward_rejects_bad_model_and_sizes(lib):
+    from paper_2310_08649_amd import tvi
+    o = tvi.make_options(chunk=16)
+    f = _fake()
+    bad_models = [tvi.Model(1, 3, tvi.F64, 0, 64),   # Van der Pol with n = 3
+                  tvi.Model(2, 2, tvi.F64, 0, 64),   # Robertson with n = 2
+                  tvi.Model(9, 2, tvi.F64, 0, 64),   # unknown kind
+                  tvi.Model(1, 2, 5, 0, 64)]         # unknown dtype
+    for m in bad_models:
+        assert lib.tvi_solve_forward(ctypes.byref(m), ctypes.byref(o), 4, 10, None, f, f, f, f, None, f, None,
+                                     None) == -1
+    m = tvi.Model(1, 2, tvi.F64, 0, 64)
+    # negative sizes, missing outputs
+    assert lib.tvi_solve_forward(ctypes.byref(m), ctypes.byref(o), -1, 10, None, f, f, f, f, None, f, None, None) == -1
+    assert lib.tvi_solve_forward(ctypes.byref(m), ctypes.byref(o), 4, 10, None, f, f, f, None, None, f, None, None) == -1
+    assert lib.tvi_solve_forward(ctypes.byref(m), ctypes.byref(o), 4, 10, None, f, f, f, f, None, None, None, None) == -1
+    # linear model beyond the supported sizes
+    m = tvi.Model(0, 8, tvi.F64, 0, 64)
+    assert lib.tvi_solve_forward(ctypes.byref(m), ctypes.byref(o), 4, 10, None, f, f, f, f, None, f, None, None) == -4
+    # an empty batch is a no-op
+    m = tvi.Model(1, 2, tvi.F64, 0, 64)
+    assert lib.tvi_solve_forward(ctypes.byref(m), ctypes.byref(o), 0, 10, None, None, None, None, None, None, None,
+                                 None, None) == 0
+
+
+def test_adjoint_and_pcr_reject_bad_arguments(lib):
+    from paper_2310_08649_amd import tvi
+    o = tvi.make_options(chunk=16)
+    f = _fake()
+    m = tvi.Model(1, 2, tvi.F64, 0, 64)
+    # recomputation needs checkpoints and a large enough workspace
+    assert lib.tvi_solve_adjoint(ctypes.byref(m), ctypes.byref(o), 4, 10, None, f, f, None, None, f, f, f, f, f, 10**9,
+                                 None) == -1
+    assert lib.tvi_solve_adjoint(ctypes.byref(m), ctypes.byref(o), 4, 10, None, f, f, None, f, f, f, f, f, f, 8,
+                                 None) == -1
+    assert lib.tvi_adjoint_workspace_bytes(ctypes.byref(m), ctypes.byref(o), 4) == 4 * 16 * 2 * 8
+    # shared parameters are not supported by the analytic adjoint
+    ms = tvi.Model(1, 2, tvi.F64, 1, 64)
+    assert lib.tvi_solve_adjoint(ctypes.byref(ms), ctypes.byref(o), 4, 10, None, f, f, f, None, f, f, f, f, None, 0,
+                                 None) == -4
+    assert lib.tvi_pcr_solve(tvi.F64, 2, 4, 0, f, f, f, 0, None) == -1
+    assert lib.tvi_pcr_solve(tvi.F64, 2, 4, 513, f, f, f, 0, None) == -1
+    assert lib.tvi_pcr_solve(tvi.F64, 9, 4, 8, f, f, f, 0, None) == -4
+    assert lib.tvi_pcr_solve(7, 2, 4, 8, f, f, f, 0, None) == -1
+    assert lib.tvi_pcr_solve(tvi.F64, 2, 4, 8, None, f, f, 0, None) == -1

@@ -1,0 +1,330 @@
+"""Parity of the HIP path with the CPU oracle, element by element on the same
+seeded inputs, through the C ABI (via the thin ctypes binding).
+
+Gates: FP64 <= 1e-10 relative per series (max over series); FP32 storage
+<= 1e-5 relative against the FP64 oracle run on the same float-rounded inputs.
+At the paper's timing tolerance the gate is the backward-Euler residual
+invariant of every step plus closeness to the oracle within what the
+tolerance allows.  Van der Pol steps with mu up to 1000 can have several
+backward-Euler roots: a GPU series that differs from the oracle's but whose
+every step satisfies the backward-Euler equation is counted as an
+alternate root (bounded), not as a mismatch.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import blockbidiag as bb
+from paper_2310_08649_amd import workloads as W
+from tests.helpers import (PARITY_TOL, TIMING_TOL, be_step_residual, be_step_residual_ragged, rhs_np,
+                           series_rel_err)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def tvi():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2310_08649_amd import tvi as t
+    t.load()
+    return t
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+# --------------------------------------------------------------------------
+# Standalone block-bidiagonal solve vs the dense definition
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [2, 3, 4])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_pcr_solve_matches_dense(tvi, n, transpose):
+    rng = np.random.default_rng(100 + n)
+    ms = list(range(1, 66)) + [100, 127, 128, 129, 255, 256, 300, 511, 512]
+    for m in ms:
+        B = 5
+        # blocks like I - dt j of a dissipative step (||D^-1|| < 1): a well-conditioned chain
+        D = 1.6 * np.eye(n)[None, None] + (0.3 / np.sqrt(n)) * rng.standard_normal((B, m, n, n))
+        r = rng.standard_normal((B, m, n))
+        ref = bb.dense_solve(D, r, transpose=transpose)
+        x = host(tvi.pcr_solve(dev(D), dev(r), transpose=transpose))
+        scale = np.abs(ref).max()
+        assert np.abs(x - ref).max() <= 1e-12 * scale, (m, np.abs(x - ref).max() / scale)
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_pcr_solve_growing_chain(tvi, transpose):
+    """Blocks with ||D^-1|| > 1 (an expanding step): the solution grows along the
+    chain, so the forward error is not a fair gate; the residual of the
+    computed solution (backward error) is."""
+    rng = np.random.default_rng(11)
+    for m in (64, 255, 512):
+        D = np.eye(2)[None, None] + 0.2 * rng.standard_normal((4, m, 2, 2))
+        r = rng.standard_normal((4, m, 2))
+        x = host(tvi.pcr_solve(dev(D), dev(r), transpose=transpose))
+        res = np.zeros_like(x)
+        for j in range(m):
+            if transpose:
+                res[:, j] = np.einsum("bki,bk->bi", D[:, j], x[:, j]) - (x[:, j + 1] if j + 1 < m else 0.0) - r[:, j]
+            else:
+                res[:, j] = np.einsum("bik,bk->bi", D[:, j], x[:, j]) - (x[:, j - 1] if j > 0 else 0.0) - r[:, j]
+        scale = np.abs(x).max(axis=(1, 2)) * 3.0
+        assert (np.abs(res).max(axis=(1, 2)) <= 1e-13 * scale * np.log2(m)).all(), m
+
+
+def test_pcr_solve_fp32_and_singular_block(tvi):
+    rng = np.random.default_rng(7)
+    B, m, n = 6, 96, 2
+    D = (np.eye(n)[None, None] + 0.2 * rng.standard_normal((B, m, n, n))).astype(np.float32)
+    r = rng.standard_normal((B, m, n)).astype(np.float32)
+    ref = bb.dense_solve(D.astype(np.float64), r.astype(np.float64))
+    x = host(tvi.pcr_solve(dev(D, torch.float32), dev(r, torch.float32)))
+    assert np.abs(x - ref).max() <= 1e-5 * np.abs(ref).max()
+    D64 = D.astype(np.float64)
+    D64[2, 40] = 0.0  # a zero block: that system (only) is NaN
+    x = host(tvi.pcr_solve(dev(D64), dev(r.astype(np.float64))))
+    assert np.isnan(x[2]).all() and np.isfinite(np.delete(x, 2, axis=0)).all()
+
+
+# --------------------------------------------------------------------------
+# Linear model: closed form, one Newton update per chunk, oracle parity
+# --------------------------------------------------------------------------
+def lin_closed_form(w):
+    h = w["times"][1] - w["times"][0]
+    k = np.arange(w["times"].shape[0])
+    c = np.einsum("bji,bj->bi", w["Q"], w["y0"])
+    fac = (1.0 + h * w["lam"])[:, None, :] ** (-k[None, :, None])
+    return np.einsum("bij,bkj,bj->bki", w["Q"], fac, c)
+
+
+@pytest.mark.parametrize("chunk", [1, 7, 20, 64, 200])
+def test_linear_forward_closed_form_and_oracle(tvi, chunk):
+    w = W.linear()  # 8 series, n = 4, 200 steps
+    y, st, it, _ = tvi.solve_forward("linear", dev(w["y0"]), dev(w["times"]), dev(w["params"]), chunk=chunk,
+                                     tol=TIMING_TOL)
+    y, st, it = host(y), host(st), host(it)
+    assert (st == 0).all()
+    yc = lin_closed_form(w)
+    assert series_rel_err(y, yc).max() <= 1e-10
+    yo, _, _ = oracle.forward("linear", w["y0"], w["times"], w["params"], tol=TIMING_TOL)
+    assert series_rel_err(y, yo).max() <= 1e-10
+    # a linear chunk is solved by exactly one Newton correction
+    assert (it == -(-200 // chunk)).all()
+
+
+def test_linear_nonsymmetric_n2_n3(tvi):
+    rng = np.random.default_rng(31)
+    for n in (2, 3, 4):
+        B, N = 9, 150
+        A = -3.0 * np.eye(n)[None] + rng.standard_normal((B, n, n))
+        y0 = rng.standard_normal((B, n))
+        times = np.linspace(0, 1, N + 1)
+        yo, so, _ = oracle.forward("linear", y0, times, A.reshape(B, -1), tol=PARITY_TOL)
+        y, st, _, _ = tvi.solve_forward("linear", dev(y0), dev(times), dev(A.reshape(B, -1)), chunk=37,
+                                        tol=PARITY_TOL)
+        assert (host(st) == 0).all()
+        assert series_rel_err(host(y), yo).max() <= 1e-10
+
+
+# --------------------------------------------------------------------------
+# Van der Pol at full size (512 series x 5000 steps), every chunk length
+# --------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def vdp_oracle():
+    w = W.vanderpol()
+    yo, so, io = oracle.forward("vanderpol", w["y0"], w["times"], w["params"], tol=PARITY_TOL)
+    return w, yo, so
+
+
+def classify_vdp(y, st, w, yo, so, gate, resid_gate):
+    rel = series_rel_err(np.nan_to_num(y, nan=1e300), np.nan_to_num(yo, nan=0.0))
+    both_ok = (so == 0) & (st == 0)
+    res = be_step_residual("vanderpol", y, w["times"], w["params"])
+    match = both_ok & (rel <= gate)
+    alt = both_ok & (rel > gate) & (res <= resid_gate)
+    bad = both_ok & ~match & ~alt
+    return match, alt, bad, res
+
+
+@pytest.mark.parametrize("chunk", [1, 10, 50, 100, 500])
+def test_vanderpol_full_size_parity(tvi, vdp_oracle, chunk):
+    w, yo, so = vdp_oracle
+    y, st, it, _ = tvi.solve_forward("vanderpol", dev(w["y0"]), dev(w["times"]), dev(w["params"]), chunk=chunk,
+                                     tol=PARITY_TOL)
+    y, st = host(y), host(st)
+    match, alt, bad, res = classify_vdp(y, st, w, yo, so, 1e-10, 1e-9)
+    assert not bad.any(), np.nonzero(bad)[0][:10]
+    assert alt.sum() <= 0.05 * len(st), alt.sum()
+    assert match.sum() >= 0.9 * len(st)
+    # a series the GPU reports as solved satisfies backward Euler at every step
+    assert (res[st == 0] <= 1e-9).all()
+
+
+def test_vanderpol_fp32_storage(tvi):
+    w = W.vanderpol(B=128, N=2000)
+    y0, times, mu = (w[k].astype(np.float32) for k in ("y0", "times", "params"))
+    yo, so, _ = oracle.forward("vanderpol", y0, times, mu, tol=PARITY_TOL)
+    y, st, _, _ = tvi.solve_forward("vanderpol", dev(y0, torch.float32), dev(times, torch.float32),
+                                    dev(mu, torch.float32), chunk=100, tol=PARITY_TOL)
+    y, st = host(y).astype(np.float64), host(st)
+    ok = (st == 0) & (so == 0)
+    rel = series_rel_err(y, yo)
+    res = be_step_residual("vanderpol", y, times.astype(np.float64), mu.astype(np.float64))
+    # float storage: the stored states satisfy backward Euler to float rounding
+    alt = ok & (rel > 1e-5)
+    assert alt.sum() <= 0.05 * ok.sum()
+    assert (rel[ok & ~alt] <= 1e-5).all()
+
+
+def test_vanderpol_timing_tolerance_residual_invariant(tvi, vdp_oracle):
+    w, yo, so = vdp_oracle
+    y, st, it, _ = tvi.solve_forward("vanderpol", dev(w["y0"]), dev(w["times"]), dev(w["params"]), chunk=100,
+                                     tol=TIMING_TOL)
+    y, st = host(y), host(st)
+    res = be_step_residual("vanderpol", y, w["times"], w["params"])
+    ok = st == 0
+    assert ok.sum() >= 0.97 * len(st)
+    # A converged chunk has ||R|| <= max(tol_a, tol_r ||R0||) (Algorithm 1).  From
+    # Delta y = 0, R0_j = -dt f(y_s), so ||R0|| <= dt sqrt(C) max_k ||f(y_k)||, and
+    # every step residual is bounded by the chunk's.
+    h, C = w["times"][1] - w["times"][0], 100
+    f = np.linalg.norm(rhs_np("vanderpol", y, w["params"][:, None, :]), axis=2).max(axis=1)
+    bound = np.maximum(TIMING_TOL[0], TIMING_TOL[1] * h * np.sqrt(C) * f)
+    assert (res[ok] <= 1.0001 * bound[ok]).all()
+    # and the solution is the oracle's to within what that tolerance allows
+    rel = series_rel_err(y, yo)
+    close = ok & (so == 0) & (rel <= 1e-3)
+    assert close.sum() >= 0.8 * len(st)
+
+
+def test_chunk_invariance_and_iteration_drop(tvi):
+    w = W.vanderpol(B=64, N=2000, mu_range=(1.0, 50.0))
+    outs, iters = [], []
+    for chunk in (1, 3, 7, 20, 64, 100, 500):
+        y, st, it, _ = tvi.solve_forward("vanderpol", dev(w["y0"]), dev(w["times"]), dev(w["params"]), chunk=chunk,
+                                         tol=PARITY_TOL)
+        assert (host(st) == 0).all()
+        outs.append(host(y))
+        iters.append(host(it).mean())
+    for o in outs[1:]:
+        assert series_rel_err(o, outs[0]).max() <= 1e-10
+    # chunking replaces N sequential solves by N / C chunk solves of a few iterations each
+    assert iters[0] > iters[-1]
+
+
+# --------------------------------------------------------------------------
+# Robertson, ragged grids
+# --------------------------------------------------------------------------
+def test_robertson_ragged_parity(tvi):
+    w = W.robertson(B=96, n_range=(100, 4000))
+    yo, so, _ = oracle.forward("robertson", w["y0"], w["times"], w["params"], offsets=w["offsets"], tol=PARITY_TOL)
+    assert (so == 0).all()
+    for chunk in (1, 16, 64, 256):
+        y, st, it, _ = tvi.solve_forward("robertson", dev(w["y0"]), dev(w["times"]), dev(w["params"]),
+                                         offsets=dev(w["offsets"], torch.int64), chunk=chunk, tol=PARITY_TOL)
+        y, st = host(y), host(st)
+        assert (st == 0).all()
+        assert series_rel_err(y, yo, w["offsets"]).max() <= 1e-10, chunk
+        assert np.abs(y.sum(axis=1) - 1.0).max() <= 1e-12
+
+
+# --------------------------------------------------------------------------
+# Adjoint: oracle parity, trajectory vs checkpoint recomputation
+# --------------------------------------------------------------------------
+def _adjoint_case(tvi, kind, w, chunk, offsets=None, gate=1e-10):
+    off_d = None if offsets is None else dev(offsets, torch.int64)
+    kw = dict(offsets=off_d, chunk=chunk, tol=PARITY_TOL, max_newton=50)
+    y, st, _, ck = tvi.solve_forward(kind, dev(w["y0"]), dev(w["times"]), dev(w["params"]), checkpoints=True, **kw)
+    st = host(st)
+    # a series whose steps cannot all reach the parity tolerance is left out (and counted)
+    assert (st == 0).mean() >= 0.95
+    yh = host(y)
+    okp = np.repeat(st == 0, np.diff(offsets)) if offsets is not None else None
+    yz = np.where(okp[:, None], yh, 0.0) if offsets is not None else np.where((st == 0)[:, None, None], yh, 0.0)
+    L = np.sqrt(np.sum(yz ** 2))
+    g = yz / L  # Frobenius loss over the series that converged
+    dp, dy0, sa = tvi.solve_adjoint(kind, dev(w["times"]), dev(w["params"]), dev(g), y=dev(yz), **kw)
+    dp2, dy02, sa2 = tvi.solve_adjoint(kind, dev(w["times"]), dev(w["params"]), dev(g), ckpt=ck, **kw)
+    ok = st == 0
+    assert (host(sa)[ok] == 0).all() and (host(sa2)[ok] == 0).all()
+    # recomputed interior states are bitwise the forward's: identical gradients
+    assert np.array_equal(host(dp)[ok], host(dp2)[ok]) and np.array_equal(host(dy0)[ok], host(dy02)[ok])
+    op, oy0, ost = oracle.adjoint(kind, yz, w["times"], w["params"], g, offsets=offsets)
+    assert (ost[ok] == 0).all()
+    for a, b in ((host(dp)[ok], op[ok]), (host(dy0)[ok], oy0[ok])):
+        err = np.abs(a - b).max(axis=1) / np.maximum(np.abs(b).max(axis=1), 1e-300)
+        assert err.max() <= gate, err.max()
+
+
+@pytest.mark.parametrize("chunk", [1, 16, 50])
+def test_adjoint_linear(tvi, chunk):
+    w = W.linear(B=8, N=200)
+    rng = np.random.default_rng(2)
+    w["params"] = w["params"] + rng.standard_normal(w["params"].shape)  # non-symmetric A
+    _adjoint_case(tvi, "linear", w, chunk)
+
+
+@pytest.mark.parametrize("chunk", [1, 32, 100, 500])
+def test_adjoint_vanderpol(tvi, chunk):
+    w = W.vanderpol(B=64, N=1000, mu_range=(1.0, 100.0))
+    _adjoint_case(tvi, "vanderpol", w, chunk)
+
+
+@pytest.mark.parametrize("chunk", [8, 64, 256])
+def test_adjoint_robertson_ragged(tvi, chunk):
+    w = W.robertson(B=48, n_range=(100, 2000))
+    _adjoint_case(tvi, "robertson", w, chunk, offsets=w["offsets"])
+
+
+def test_adjoint_autograd_function(tvi):
+    w = W.vanderpol(B=16, N=400, mu_range=(1.0, 20.0))
+    y0 = dev(w["y0"]).requires_grad_(True)
+    mu = dev(w["params"]).requires_grad_(True)
+    y = tvi.odeint_adjoint("vanderpol", y0, dev(w["times"]), mu, chunk=64, tol=PARITY_TOL)
+    loss = torch.sqrt((y ** 2).sum())
+    loss.backward()
+    yo, _, _ = oracle.forward("vanderpol", w["y0"], w["times"], w["params"], tol=PARITY_TOL)
+    g = yo / np.sqrt(np.sum(yo ** 2))
+    op, oy0, _ = oracle.adjoint("vanderpol", yo, w["times"], w["params"], g)
+    assert np.abs(host(mu.grad) - op).max() <= 1e-9 * np.abs(op).max()
+    assert np.abs(host(y0.grad) - oy0).max() <= 1e-9 * np.abs(oy0).max()
+
+
+# --------------------------------------------------------------------------
+# Failure reporting, edge cases
+# --------------------------------------------------------------------------
+def test_failure_statuses(tvi):
+    times = np.linspace(0, 1, 41)
+    y0 = np.array([[np.nan, 0.0], [0.5, 0.5]])
+    y, st, _, _ = tvi.solve_forward("vanderpol", dev(y0), dev(times), dev([[1.0], [1.0]]), chunk=8)
+    y, st = host(y), host(st)
+    assert st[0] == 3 and st[1] == 0 and np.isnan(y[0, 1:]).all() and np.isfinite(y[1]).all()
+    # I - hA = 0 exactly (h = 1/4 and A = 4 I are exact in binary): a zero pivot
+    A = (4.0 * np.eye(2)).reshape(1, 4)
+    y, st, _, _ = tvi.solve_forward("linear", dev([[1.0, 2.0]]), dev(np.linspace(0, 1, 5)), dev(A), chunk=8)
+    assert host(st)[0] == 2 and np.isnan(host(y)[0, 1:]).all()
+    y, st, _, _ = tvi.solve_forward("vanderpol", dev([[1.5, 0.3]]), dev(times), dev([[10.0]]), chunk=8,
+                                    tol=(1e-15, 1e-15), max_newton=1, halving=False)
+    assert host(st)[0] == 1
+
+
+def test_edge_sizes(tvi):
+    # zero steps, one step, chunk longer than the series, a batch that is not a multiple of the wave
+    for N, chunk, B in ((0, 4, 3), (1, 4, 3), (5, 64, 67), (130, 500, 5)):
+        w = W.vanderpol(B=B, N=N, mu_range=(1.0, 10.0))
+        w["times"] = np.linspace(0, 0.01 * max(N, 1), N + 1)
+        yo, so, _ = oracle.forward("vanderpol", w["y0"], w["times"], w["params"], tol=PARITY_TOL)
+        y, st, _, ck = tvi.solve_forward("vanderpol", dev(w["y0"]), dev(w["times"]), dev(w["params"]), chunk=chunk,
+                                         tol=PARITY_TOL, checkpoints=True)
+        assert (host(st) == 0).all()
+        assert series_rel_err(host(y), yo).max() <= 1e-10
+        ck, y = host(ck), host(y)
+        assert np.array_equal(ck[:, 0], w["y0"]) and np.array_equal(ck[:, -1], y[:, -1])
