@@ -53,6 +53,10 @@
  *   TVI_VANDERPOL  n = 2, h = (y2, mu (1 - y1^2) y2 - y1), p = (mu)
  *   TVI_ROBERTSON  n = 3, rate constants 0.04 s1, 3e7 s2 (on y2^2), 1e4 s3 (on y2 y3),
  *                  p = (s1, s2, s3)
+ *   TVI_MLP        neural ODE (Section 5.1.4 without forcing): n = 8, hidden = 64,
+ *                  h = W3 tanh(W2 tanh(W1 y + b1) + b2) + b3, one shared
+ *                  p = (W1[64][8], b1[64], W2[64][64], b2[64], W3[8][64], b3[8]) (P = 5256);
+ *                  computed in float on MFMA (bf16x3 products for h)
  */
 #ifndef TVI_H
 #define TVI_H
@@ -119,6 +123,19 @@ void tvi_default_options(tvi_options *opt);
 const char *tvi_status_str(int32_t status);
 const char *tvi_version(void);
 int32_t tvi_param_count(const tvi_model *model);
+
+/*
+ * tvi_model_eval -- the model rate h(y, t; p) and its state Jacobian
+ * j = dh/dy for M independent states: the assembly of the chunk system's
+ * residual and diagonal blocks (Section 2.3) as an entry point of its own.
+ *
+ *   states [M][n], times [M] or NULL (t = 0; every model here is autonomous),
+ *   params [M][P] or shared [P] (model->params_shared; required for TVI_MLP),
+ *   f [M][n] or NULL, J [M][n][n] or NULL (not both NULL).
+ * Returns TVI_OK once enqueued, TVI_EINVAL / TVI_EUNSUPPORTED on bad arguments.
+ */
+tvi_status tvi_model_eval(const tvi_model *model, int64_t M, const void *states, const void *times,
+                          const void *params, void *f, void *J, void *stream);
 
 /*
  * tvi_pcr_solve -- batched block-bidiagonal solve (Section 3), the linear

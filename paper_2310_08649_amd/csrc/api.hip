@@ -51,7 +51,9 @@ tvi_status check_model(const tvi_model *m)
     case TVI_LINEAR: return (m->n >= 2 && m->n <= 4) ? TVI_OK : TVI_EUNSUPPORTED;
     case TVI_VANDERPOL: return m->n == 2 ? TVI_OK : TVI_EINVAL;
     case TVI_ROBERTSON: return m->n == 3 ? TVI_OK : TVI_EINVAL;
-    case TVI_MLP: return TVI_EUNSUPPORTED;
+    case TVI_MLP:
+        if (m->n != 8) return TVI_EINVAL;
+        return m->hidden == 64 ? TVI_OK : TVI_EUNSUPPORTED;
     default: return TVI_EINVAL;
     }
 }
@@ -107,6 +109,7 @@ tvi_status dispatch(int pass, const tvi_model *model, const void *args, int S, i
     switch (model->kind) {
     case TVI_VANDERPOL: return launch_vanderpol(pass, model->dtype, args, S, T, stream);
     case TVI_ROBERTSON: return launch_robertson(pass, model->dtype, args, S, T, stream);
+    case TVI_MLP: return launch_mlp(pass, model->dtype, args, stream);
     case TVI_LINEAR:
         switch (model->n) {
         case 2: return launch_linear2(pass, model->dtype, args, S, T, stream);
@@ -155,6 +158,22 @@ const char *tvi_version(void) { return "tvi 0.1 gfx950"; }
 
 int32_t tvi_param_count(const tvi_model *model) { return model ? model_params(model) : -1; }
 
+tvi_status tvi_model_eval(const tvi_model *model, int64_t M, const void *states, const void *times,
+                          const void *params, void *f, void *J, void *stream)
+{
+    tvi_status e = check_model(model);
+    if (e != TVI_OK) return e;
+    if (M < 0) return TVI_EINVAL;
+    if (M == 0) return TVI_OK;
+    if (!states || !params || (!f && !J)) return TVI_EINVAL;
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    if (model->kind == TVI_MLP) {
+        if (!model->params_shared) return TVI_EUNSUPPORTED;
+        return launch_mlp_eval(model->dtype, M, states, params, f, J, st);
+    }
+    return launch_eval(model->kind, model->n, model->dtype, M, states, times, params, model->params_shared, f, J, st);
+}
+
 tvi_status tvi_pcr_solve(int32_t dtype, int32_t n, int64_t B, int64_t m, const void *D, const void *r, void *x,
                          int32_t transpose, void *stream)
 {
@@ -179,8 +198,12 @@ tvi_status tvi_solve_forward(const tvi_model *model, const tvi_options *opt, int
     if (B < 0 || N < 0) return TVI_EINVAL;
     if (B == 0) return TVI_OK;
     if (!times || !y0 || !params || !status || (!y_out && !ckpt)) return TVI_EINVAL;
-    int S, T;
-    if ((e = resolve_tiling(opt, S, T)) != TVI_OK) return e;
+    int S = 0, T = 0;
+    if (model->kind == TVI_MLP) {
+        if (opt->chunk > 128) return TVI_EUNSUPPORTED;
+    } else if ((e = resolve_tiling(opt, S, T)) != TVI_OK) {
+        return e;
+    }
     const hipStream_t st = static_cast<hipStream_t>(stream);
     if (model->dtype == TVI_F64) {
         SolveArgs<double> a = make_args<double>(model, opt, B, N, offsets, times, y0, params);

@@ -13,6 +13,7 @@ constexpr int kWave = 64;
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
 __device__ __forceinline__ bool finite(double x) { return __builtin_isfinite(x); }
+__device__ __forceinline__ bool finite(float x) { return __builtin_isfinite(x); }
 
 // Read `x` from lane `src` (0..63) of the wave.  All lanes must execute it.
 __device__ __forceinline__ double lane_read(double x, int src)
@@ -28,13 +29,18 @@ __device__ __forceinline__ int lane_read(int x, int src)
     return __builtin_amdgcn_ds_bpermute(src << 2, x);
 }
 
+__device__ __forceinline__ float lane_read(float x, int src)
+{
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(x)));
+}
+
 // Wave-uniform "does any lane satisfy p".
 __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
 
 // Sum of x over the S-lane segment of this lane (butterfly; every lane of the
 // segment gets the same, order-fixed result).
-template <int S>
-__device__ __forceinline__ double seg_sum(double x)
+template <int S, class R>
+__device__ __forceinline__ R seg_sum(R x)
 {
 #pragma unroll
     for (int d = 1; d < S; d <<= 1) x += __shfl_xor(x, d, S);
@@ -53,24 +59,24 @@ __device__ __forceinline__ int seg_and(int x)
 // n x n blocks in registers (row-major, compile-time n: every index is static,
 // so nothing is spilled to scratch).
 // ---------------------------------------------------------------------------
-template <int N>
-__device__ __forceinline__ void set_identity(double (&A)[N][N])
+template <int N, class R>
+__device__ __forceinline__ void set_identity(R (&A)[N][N])
 {
 #pragma unroll
     for (int i = 0; i < N; ++i)
 #pragma unroll
-        for (int k = 0; k < N; ++k) A[i][k] = (i == k) ? 1.0 : 0.0;
+        for (int k = 0; k < N; ++k) A[i][k] = (i == k) ? R(1) : R(0);
 }
 
 // C = A * B
-template <int N>
-__device__ __forceinline__ void matmul(const double (&A)[N][N], const double (&B)[N][N], double (&C)[N][N])
+template <int N, class R>
+__device__ __forceinline__ void matmul(const R (&A)[N][N], const R (&B)[N][N], R (&C)[N][N])
 {
 #pragma unroll
     for (int i = 0; i < N; ++i)
 #pragma unroll
         for (int k = 0; k < N; ++k) {
-            double s = A[i][0] * B[0][k];
+            R s = A[i][0] * B[0][k];
 #pragma unroll
             for (int l = 1; l < N; ++l) s = fma(A[i][l], B[l][k], s);
             C[i][k] = s;
@@ -78,14 +84,13 @@ __device__ __forceinline__ void matmul(const double (&A)[N][N], const double (&B
 }
 
 // y = A x + c   (y may alias c)
-template <int N>
-__device__ __forceinline__ void matvec_add(const double (&A)[N][N], const double (&x)[N], const double (&c)[N],
-                                           double (&y)[N])
+template <int N, class R>
+__device__ __forceinline__ void matvec_add(const R (&A)[N][N], const R (&x)[N], const R (&c)[N], R (&y)[N])
 {
-    double t[N];
+    R t[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-        double s = c[i];
+        R s = c[i];
 #pragma unroll
         for (int l = 0; l < N; ++l) s = fma(A[i][l], x[l], s);
         t[i] = s;
@@ -95,14 +100,13 @@ __device__ __forceinline__ void matvec_add(const double (&A)[N][N], const double
 }
 
 // y = A^T x + c
-template <int N>
-__device__ __forceinline__ void matTvec_add(const double (&A)[N][N], const double (&x)[N], const double (&c)[N],
-                                            double (&y)[N])
+template <int N, class R>
+__device__ __forceinline__ void matTvec_add(const R (&A)[N][N], const R (&x)[N], const R (&c)[N], R (&y)[N])
 {
-    double t[N];
+    R t[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-        double s = c[i];
+        R s = c[i];
 #pragma unroll
         for (int l = 0; l < N; ++l) s = fma(A[l][i], x[l], s);
         t[i] = s;
@@ -116,8 +120,8 @@ __device__ __forceinline__ void matTvec_add(const double (&A)[N][N], const doubl
 // pivot position by conditional (select) row exchanges, so every register
 // index stays static.  A is destroyed.  Returns false if a pivot is zero or
 // not finite.
-template <int N>
-__device__ __forceinline__ bool invert(double (&A)[N][N], double (&X)[N][N])
+template <int N, class R>
+__device__ __forceinline__ bool invert(R (&A)[N][N], R (&X)[N][N])
 {
     set_identity(X);
     bool ok = true;
@@ -128,20 +132,20 @@ __device__ __forceinline__ bool invert(double (&A)[N][N], double (&X)[N][N])
             const bool sw = fabs(A[r][c]) > fabs(A[c][c]);
 #pragma unroll
             for (int k = c; k < N; ++k) {
-                const double a = A[r][k], b = A[c][k];
+                const R a = A[r][k], b = A[c][k];
                 A[r][k] = sw ? b : a;
                 A[c][k] = sw ? a : b;
             }
 #pragma unroll
             for (int k = 0; k < N; ++k) {
-                const double a = X[r][k], b = X[c][k];
+                const R a = X[r][k], b = X[c][k];
                 X[r][k] = sw ? b : a;
                 X[c][k] = sw ? a : b;
             }
         }
-        const double piv = A[c][c];
-        ok = ok && (piv != 0.0) && finite(piv);
-        const double ip = 1.0 / piv;
+        const R piv = A[c][c];
+        ok = ok && (piv != R(0)) && finite(piv);
+        const R ip = R(1) / piv;
 #pragma unroll
         for (int k = c; k < N; ++k) A[c][k] *= ip;
 #pragma unroll
@@ -149,7 +153,7 @@ __device__ __forceinline__ bool invert(double (&A)[N][N], double (&X)[N][N])
 #pragma unroll
         for (int r = 0; r < N; ++r) {
             if (r == c) continue;
-            const double f = A[r][c];
+            const R f = A[r][c];
 #pragma unroll
             for (int k = c; k < N; ++k) A[r][k] = fma(-f, A[c][k], A[r][k]);
 #pragma unroll
@@ -170,26 +174,26 @@ __device__ __forceinline__ bool invert(double (&A)[N][N], double (&X)[N][N])
 // z_j <- z_j + M_j z_{j-d},  M_j <- M_j M_{j-d}  (the split of Section 3.2
 // with B = -I), i.e. a Kogge-Stone scan with map composition.
 // ---------------------------------------------------------------------------
-template <int N>
+template <int N, class R = double>
 struct Affine {
-    double M[N][N];
-    double z[N];
+    R M[N][N];
+    R z[N];
 };
 
-template <int N>
-__device__ __forceinline__ void affine_identity(Affine<N> &a)
+template <int N, class R>
+__device__ __forceinline__ void affine_identity(Affine<N, R> &a)
 {
     set_identity(a.M);
 #pragma unroll
-    for (int i = 0; i < N; ++i) a.z[i] = 0.0;
+    for (int i = 0; i < N; ++i) a.z[i] = R(0);
 }
 
 // a <- a o b  (apply b first, then a):  M = Ma Mb,  z = Ma zb + za
-template <int N>
-__device__ __forceinline__ void affine_after(Affine<N> &a, const Affine<N> &b)
+template <int N, class R>
+__device__ __forceinline__ void affine_after(Affine<N, R> &a, const Affine<N, R> &b)
 {
     matvec_add(a.M, b.z, a.z, a.z);
-    double t[N][N];
+    R t[N][N];
     matmul(a.M, b.M, t);
 #pragma unroll
     for (int i = 0; i < N; ++i)
@@ -197,8 +201,8 @@ __device__ __forceinline__ void affine_after(Affine<N> &a, const Affine<N> &b)
         for (int k = 0; k < N; ++k) a.M[i][k] = t[i][k];
 }
 
-template <int N>
-__device__ __forceinline__ void affine_read(const Affine<N> &a, int src, Affine<N> &out)
+template <int N, class R>
+__device__ __forceinline__ void affine_read(const Affine<N, R> &a, int src, Affine<N, R> &out)
 {
 #pragma unroll
     for (int i = 0; i < N; ++i) {
@@ -210,14 +214,14 @@ __device__ __forceinline__ void affine_read(const Affine<N> &a, int src, Affine<
 
 // Inclusive prefix composition over the segment, lowest lane first:
 // lane q ends with A_q o A_{q-1} o ... o A_0.
-template <int N, int S>
-__device__ __forceinline__ void seg_scan_up(Affine<N> &a)
+template <int N, int S, class R>
+__device__ __forceinline__ void seg_scan_up(Affine<N, R> &a)
 {
     const int lane = lane_id();
     const int q = lane & (S - 1);
 #pragma unroll
     for (int d = 1; d < S; d <<= 1) {
-        Affine<N> o;
+        Affine<N, R> o;
         affine_read(a, q >= d ? lane - d : lane, o);
         if (q >= d) affine_after(a, o);
     }
@@ -225,22 +229,22 @@ __device__ __forceinline__ void seg_scan_up(Affine<N> &a)
 
 // Inclusive suffix composition, highest lane first:
 // lane q ends with A_q o A_{q+1} o ... o A_{S-1}.
-template <int N, int S>
-__device__ __forceinline__ void seg_scan_down(Affine<N> &a)
+template <int N, int S, class R>
+__device__ __forceinline__ void seg_scan_down(Affine<N, R> &a)
 {
     const int lane = lane_id();
     const int q = lane & (S - 1);
 #pragma unroll
     for (int d = 1; d < S; d <<= 1) {
-        Affine<N> o;
+        Affine<N, R> o;
         affine_read(a, q + d < S ? lane + d : lane, o);
         if (q + d < S) affine_after(a, o);
     }
 }
 
 // Vector of N doubles from lane src.
-template <int N>
-__device__ __forceinline__ void vec_read(const double (&v)[N], int src, double (&out)[N])
+template <int N, class R>
+__device__ __forceinline__ void vec_read(const R (&v)[N], int src, R (&out)[N])
 {
 #pragma unroll
     for (int i = 0; i < N; ++i) out[i] = lane_read(v[i], src);

@@ -64,5 +64,10 @@ tvi_status launch_linear3(int pass, int dtype, const void *args, int S, int T, h
 tvi_status launch_linear4(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
 tvi_status launch_pcr(int dtype, int n, int64_t B, int m, const void *D, const void *r, void *x, int transpose,
                       int S, int T, hipStream_t stream);
+tvi_status launch_mlp(int pass, int dtype, const void *args, hipStream_t stream);
+tvi_status launch_mlp_eval(int dtype, int64_t M, const void *states, const void *params, void *f, void *J,
+                           hipStream_t stream);
+tvi_status launch_eval(int kind, int n, int dtype, int64_t M, const void *states, const void *times,
+                       const void *params, int shared, void *f, void *J, hipStream_t stream);
 
 } // namespace tvi

@@ -1,0 +1,269 @@
+// Neural-ODE right-hand side h(y) = W3 tanh(W2 tanh(W1 y + b1) + b2) + b3
+// (n = 8 states, 64 hidden units, shared parameters) evaluated on MFMA:
+// v_mfma_f32_16x16x32_bf16 with hidden units along M and samples (time steps
+// of a chunk) along N.
+//
+// Precision.  The rate h(y) that enters the Newton residual is computed as a
+// "bf16x3" product (every operand split into a bf16 high and low part, three
+// MFMAs ah*bh + ah*bl + al*bh accumulated in float), which is about as
+// accurate as float arithmetic; the Jacobian used only inside Newton's method
+// may take plain bf16 products (an approximate Jacobian changes the
+// convergence rate, not the root); the adjoint uses bf16x3 everywhere.
+//
+// Operand layout (16x16x32, lane l, group g = l / 16, r = l % 16): the A
+// operand of a lane is row r of the 16-row tile, the B operand column r of
+// the 16-column tile, each with eight k-elements e = 0..7; the accumulator
+// holds D[4g + i][r], i = 0..3.  The contraction only needs A and B to use
+// the same lane-to-k assignment, so a chained product takes its B operand
+// straight from the previous accumulators: for K-step ks (32 hidden units,
+// the previous M-tiles 2ks and 2ks+1) element e of lane l is the previous
+// output element (tile 2ks + e/4, entry e%4), i.e. hidden unit
+// k(ks, g, e) = 32 ks + 16 (e / 4) + 4 g + e % 4, and the weights are stored
+// in LDS already permuted to that order.
+#pragma once
+
+#include "device.hpp"
+
+namespace tvi {
+namespace mlp {
+
+constexpr int NS = 8;   // state size
+constexpr int H = 64;   // hidden width
+constexpr int P = H * NS + H + H * H + H + NS * H + NS;  // 5256
+constexpr int kWaves = 4;
+constexpr int kSPW = 32;                  // samples (chunk steps) per wave
+constexpr int kMaxChunk = kWaves * kSPW;  // 128
+constexpr int kThreads = kWaves * kWave;
+
+// offsets of the parameter blocks in theta
+constexpr int oW1 = 0, ob1 = H * NS, oW2 = ob1 + H, ob2 = oW2 + H * H, oW3 = ob2 + H, ob3 = oW3 + NS * H;
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+__device__ __forceinline__ f32x4 mma(const bf16x8 &a, const bf16x8 &b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+struct Split {
+    bf16x8 hi, lo;
+};
+
+__device__ __forceinline__ Split split8(const float (&x)[8])
+{
+    Split s;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const __bf16 h = (__bf16)x[e];
+        s.hi[e] = h;
+        s.lo[e] = (__bf16)(x[e] - (float)h);
+    }
+    return s;
+}
+
+// c += a * b with bf16x3 (EXACT3) or plain bf16 products
+template <bool EXACT3>
+__device__ __forceinline__ f32x4 mma_acc(const Split &a, const Split &b, f32x4 c)
+{
+    if (EXACT3) {
+        c = mma(a.lo, b.hi, c);
+        c = mma(a.hi, b.lo, c);
+    }
+    return mma(a.hi, b.hi, c);
+}
+
+__device__ __forceinline__ int kchain(int ks, int g, int e) { return 32 * ks + 16 * (e >> 2) + 4 * g + (e & 3); }
+
+// Weights in LDS, stored per (tile, lane) in operand order (hi and lo parts).
+struct Weights {
+    Split w1[4][kWave];        // W1   [64 x 8]:  M-tiles 0..3, one K-step (k = 8 g + e, k < 8)
+    Split w2[4][2][kWave];     // W2   [64 x 64]: M-tiles, chained K-steps
+    Split w3[2][kWave];        // W3   [8 x 64]:  one M-tile (rows 8..15 zero), chained K-steps
+    Split w3t[4][kWave];       // W3^T [64 x 8]:  M-tiles, one K-step (k = 8 g + e, k < 8)
+    Split w2t[4][2][kWave];    // W2^T [64 x 64]
+    float w1p[2][4][8][NS];    // W1[k(ks, g, e)][c]: the Jacobian's first factor
+    float b1[H], b2[H], b3[NS];
+};
+
+// Fill the operand tiles from theta (all threads of the block cooperate).
+template <class IO>
+__device__ void load_weights(Weights &W, const IO *th)
+{
+    const int t = threadIdx.x;
+    for (int idx = t; idx < 4 * kWave; idx += kThreads) {
+        const int mt = idx / kWave, l = idx % kWave, g = l >> 4, r = l & 15;
+        float a[8], b[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = 8 * g + e;
+            a[e] = k < NS ? (float)th[oW1 + (16 * mt + r) * NS + k] : 0.f;   // W1[m][k]
+            b[e] = k < NS ? (float)th[oW3 + k * H + 16 * mt + r] : 0.f;     // W3^T[m][k] = W3[k][m]
+        }
+        W.w1[mt][l] = split8(a);
+        W.w3t[mt][l] = split8(b);
+    }
+    for (int idx = t; idx < 8 * kWave; idx += kThreads) {
+        const int mt = idx / (2 * kWave), ks = (idx / kWave) & 1, l = idx % kWave, g = l >> 4, r = l & 15;
+        float a[8], b[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = kchain(ks, g, e);
+            a[e] = (float)th[oW2 + (16 * mt + r) * H + k];   // W2[m][k]
+            b[e] = (float)th[oW2 + k * H + 16 * mt + r];     // W2^T[m][k] = W2[k][m]
+        }
+        W.w2[mt][ks][l] = split8(a);
+        W.w2t[mt][ks][l] = split8(b);
+    }
+    for (int idx = t; idx < 2 * kWave; idx += kThreads) {
+        const int ks = idx / kWave, l = idx % kWave, g = l >> 4, r = l & 15;
+        float a[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) a[e] = r < NS ? (float)th[oW3 + r * H + kchain(ks, g, e)] : 0.f;
+        W.w3[ks][l] = split8(a);
+    }
+    for (int idx = t; idx < 2 * 4 * 8 * NS; idx += kThreads) {
+        const int c = idx % NS, e = (idx / NS) % 8, g = (idx / (NS * 8)) % 4, ks = idx / (NS * 32);
+        W.w1p[ks][g][e][c] = (float)th[oW1 + kchain(ks, g, e) * NS + c];
+    }
+    for (int idx = t; idx < H; idx += kThreads) {
+        W.b1[idx] = (float)th[ob1 + idx];
+        W.b2[idx] = (float)th[ob2 + idx];
+    }
+    if (t < NS) W.b3[t] = (float)th[ob3 + t];
+}
+
+// Activations of one wave's 32 samples (two 16-sample N-tiles u), in
+// accumulator layout: a1[mt][u][i] is hidden unit 16 mt + 4 g + i of sample
+// 16 u + r.
+struct Acts {
+    f32x4 a1[4][2], a2[4][2];
+};
+
+// Forward pass for the wave's samples.  ys(u) gives the state of the lane's
+// column sample (8 floats, used by group 0 only).  Writes the rate of sample
+// (16 u + r) rows 4g+i (g < 2) through put_f(u, row, value).
+template <bool EXACT3, class GetY, class PutF>
+__device__ __forceinline__ void forward(const Weights &W, Acts &A, GetY get_y, PutF put_f)
+{
+    const int l = lane_id(), g = l >> 4;
+    Split yb[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        float y[8];
+        get_y(u, y);
+        if (g != 0) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) y[e] = 0.f;
+        }
+        yb[u] = split8(y);
+    }
+    // layer 1
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        f32x4 bias;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bias[i] = W.b1[16 * mt + 4 * g + i];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            f32x4 z = mma_acc<true>(W.w1[mt][l], yb[u], bias);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) A.a1[mt][u][i] = tanhf(z[i]);
+        }
+    }
+    // layer 2
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        Split bk[2];
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            float v[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = A.a1[2 * ks + (e >> 2)][u][e & 3];
+            bk[ks] = split8(v);
+        }
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            f32x4 z;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) z[i] = W.b2[16 * mt + 4 * g + i];
+            z = mma_acc<true>(W.w2[mt][0][l], bk[0], z);
+            z = mma_acc<true>(W.w2[mt][1][l], bk[1], z);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) A.a2[mt][u][i] = tanhf(z[i]);
+        }
+    }
+    // layer 3
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        f32x4 z;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) z[i] = (4 * g + i < NS) ? W.b3[(4 * g + i) & (NS - 1)] : 0.f;
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            float v[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = A.a2[2 * ks + (e >> 2)][u][e & 3];
+            z = mma_acc<true>(W.w3[ks][l], split8(v), z);
+        }
+        if (g < 2) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) put_f(u, 4 * g + i, z[i]);
+        }
+    }
+    (void)EXACT3;
+}
+
+// State Jacobians J = W3 diag(1 - a2^2) W2 diag(1 - a1^2) W1 of the wave's
+// samples, column by column: for column c the B operand of the W2 product
+// is (1 - a1^2) * W1[:, c] in the chained order, the product's accumulators
+// scaled by (1 - a2^2) feed the W3 product.  put_j(u, row, c, value).
+template <bool EXACT3, class PutJ>
+__device__ __forceinline__ void jacobian(const Weights &W, const Acts &A, PutJ put_j)
+{
+    const int l = lane_id(), g = l >> 4;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        float d1[4][4], d2[4][4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                d1[mt][i] = 1.f - A.a1[mt][u][i] * A.a1[mt][u][i];
+                d2[mt][i] = 1.f - A.a2[mt][u][i] * A.a2[mt][u][i];
+            }
+#pragma unroll 1
+        for (int c = 0; c < NS; ++c) {
+            Split bk[2];
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                float v[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) v[e] = d1[2 * ks + (e >> 2)][e & 3] * W.w1p[ks][g][e][c];
+                bk[ks] = split8(v);
+            }
+            f32x4 p2[4];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                f32x4 z = {0.f, 0.f, 0.f, 0.f};
+                z = mma_acc<EXACT3>(W.w2[mt][0][l], bk[0], z);
+                p2[mt] = mma_acc<EXACT3>(W.w2[mt][1][l], bk[1], z);
+            }
+            f32x4 j = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                float v[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) v[e] = d2[2 * ks + (e >> 2)][e & 3] * p2[2 * ks + (e >> 2)][e & 3];
+                j = mma_acc<EXACT3>(W.w3[ks][l], split8(v), j);
+            }
+            if (g < 2) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) put_j(u, 4 * g + i, c, j[i]);
+            }
+        }
+    }
+}
+
+} // namespace mlp
+} // namespace tvi

@@ -18,7 +18,6 @@ and, on top of them,
 from __future__ import annotations
 
 import ctypes
-import math
 import os
 
 import torch
@@ -67,6 +66,8 @@ def load():
         lib.tvi_version.restype = ctypes.c_char_p
         lib.tvi_param_count.argtypes = [MP]
         lib.tvi_param_count.restype = i32
+        lib.tvi_model_eval.argtypes = [MP, i64, P, P, P, P, P, P]
+        lib.tvi_model_eval.restype = i32
         lib.tvi_pcr_solve.argtypes = [i32, i32, i64, i64, P, P, P, i32, P]
         lib.tvi_pcr_solve.restype = i32
         lib.tvi_solve_forward.argtypes = [MP, OP, i64, i64, P, P, P, P, P, P, P, P, P]
@@ -124,6 +125,22 @@ def make_options(chunk=64, tol=(1e-8, 1e-6), max_newton=50, lanes=0, steps_per_l
     o.init = INIT[init] if isinstance(init, str) else int(init)
     o.halving = 1 if halving else 0
     return o
+
+
+def model_eval(kind, states, params, times=None, rate=True, jacobian=True, hidden=64):
+    """(f [M, n], J [M, n, n]) = (h(y), dh/dy) for M states (either may be None)."""
+    dt = states.dtype
+    states = _dev(states, dt, "states")
+    params = _dev(params, dt, "params")
+    if times is not None:
+        times = _dev(times, dt, "times")
+    M, n = states.shape
+    model = Model(KINDS[kind], n, _io_dtype(states), 1 if params.dim() == 1 else 0, hidden)
+    f = torch.empty((M, n), dtype=dt, device=states.device) if rate else None
+    J = torch.empty((M, n, n), dtype=dt, device=states.device) if jacobian else None
+    _check(load().tvi_model_eval(ctypes.byref(model), M, _ptr(states), _ptr(times), _ptr(params), _ptr(f), _ptr(J),
+                                 _stream()), "tvi_model_eval")
+    return f, J
 
 
 def pcr_solve(D, r, transpose=False, out=None):

@@ -54,3 +54,25 @@ def be_step_residual_ragged(kind, y, times, params, offsets):
         r = yb[1:] - yb[:-1] - np.diff(tb)[:, None] * f
         out[b] = np.linalg.norm(r, axis=1).max()
     return out
+
+
+def certify_alternate_root(kind, yg, yo, times, p, agree=1e-8, jump=1e-5, resid=1e-8):
+    """True if two trajectories of one series [N+1, n] part at a step whose
+    backward-Euler equation has (at least) two roots: they agree (to `agree`)
+    up to step k-1, differ by more than `jump` at step k, and both y_k satisfy
+    y_k - y_{k-1} - dt h(y_k) = 0 for that same y_{k-1}.  Exhibiting two
+    distinct roots of one step's equation proves the step is not uniquely
+    solvable, so neither trajectory is wrong."""
+    scale = max(np.abs(yo).max(), 1e-300)
+    d = np.abs(yg - yo).max(axis=1) / scale
+    bad = np.nonzero(d > agree)[0]
+    if bad.size == 0:
+        return False
+    k = int(bad[0])
+    if k == 0 or d[k] <= jump:
+        return False
+    dt = times[k] - times[k - 1]
+    rg = yg[k] - yo[k - 1] - dt * rhs_np(kind, yg[k][None], p[None])[0]
+    ro = yo[k] - yo[k - 1] - dt * rhs_np(kind, yo[k][None], p[None])[0]
+    tol = resid * max(1.0, np.abs(yo[k - 1]).max())
+    return bool(np.abs(rg).max() <= tol and np.abs(ro).max() <= tol)
