@@ -43,6 +43,33 @@ def vdp_flops_per_step_iter(chunk):
     return 44 + 24 * levels
 
 
+def csrc_hash():
+    """Hash of the kernel sources; HBM traffic from profiler counters is reported
+    only while the sources still match the ones the counters were taken from."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2310_08649_amd", "csrc", "*"))):
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per dispatch of `kernel` from profiles/traffic.json (FETCH_SIZE and
+    WRITE_SIZE scaled by a plain-copy calibration), or None if stale or absent."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f).get(kernel)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_hash") != csrc_hash():
+        return None
+    return rec["bytes_per_dispatch"]
+
+
 def time_launches(fn, reps, stream):
     """Average launch duration (ms) by HIP events on the launching stream."""
     import torch
@@ -63,6 +90,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=0, help="0 = autotune")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the headline measurement")
+    ap.add_argument("--probe-copy", action="store_true",
+                    help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -113,9 +142,11 @@ def main():
 
     flops = float(it.sum()) * C * vdp_flops_per_step_iter(C)
     achieved_tflops = flops / (kern_ms * 1e-3) / 1e12
-    roofline = {"kernel": "forward_kernel<VanDerPol,double,%d,%d>" % (S, T), "bound": "alu",
+    kname = "tvi::forward_kernel<tvi::VanDerPol, double, %d, %d>" % (S, T)
+    roofline = {"kernel": kname, "bound": "alu",
                 "achieved": achieved_tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved_tflops / PEAK_FP64_TFLOPS, "traffic": None, "avg_launch_ms": kern_ms,
+                "frac": achieved_tflops / PEAK_FP64_TFLOPS, "traffic": measured_traffic(kname),
+                "avg_launch_ms": kern_ms,
                 "note": "latency-bound: a chain of N/C chunk solves x Newton iterations per series"}
 
     out = {"metric": METRIC, "value": value, "unit": "series*steps/s", "n_gpus": 1, "steps": args.steps,
@@ -174,11 +205,21 @@ def main():
         pcr_ms = float(np.mean(pd))
         bytes_alg = nb * m * (n * n + 2 * n) * 8
         gbs = bytes_alg / (pcr_ms * 1e-3) / 1e9
-        out["pcr_roofline"] = {"kernel": "pcr_kernel<2,double,64,1,false>", "bound": "hbm", "achieved": gbs,
-                               "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS, "traffic": None,
+        pname = "tvi::pcr_kernel<2, double, 64, 1, false>(long, int, double const*, double const*, double*)"
+        out["pcr_roofline"] = {"kernel": pname, "bound": "hbm", "achieved": gbs,
+                               "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+                               "traffic": measured_traffic(pname),
                                "bytes_per_launch": bytes_alg, "avg_launch_ms": pcr_ms,
                                "systems": nb, "block_rows": m, "n": n}
         del D, r, x
+
+    if args.probe_copy:
+        src = torch.ones(1 << 25, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = {"read": src.numel() * 8, "write": dst.numel() * 8}
+        del src, dst
 
     if not args.no_cpu:
         log("CPU oracle on the host cores")

@@ -91,8 +91,13 @@ typedef enum {
 } tvi_status;
 
 typedef enum {
-    TVI_INIT_ZERO = 0,  /* Delta y = 0 over the chunk (Section 2.3)                  */
-    TVI_INIT_EXTRAP = 1 /* extrapolate the last step's slope over the chunk          */
+    TVI_INIT_ZERO = 0,     /* Delta y = 0 over the chunk (Section 2.3)                        */
+    TVI_INIT_EXTRAP = 1,   /* extrapolate the last step's slope over the chunk:
+                              dy0_j = (t_{s+j} - t_s) h(y_s, t_s)                           */
+    TVI_INIT_PREDICTOR = 2 /* the learned chunk predictor: dy0_j = (t_{s+j} - t_s)(h(y_s) + p_j)
+                              with p = the tvi_predictor network (n_in = n + 2: y_s, t_s,
+                              log(t_{s+1} - t_s); n_out = n * predictor_steps), kept only where
+                              its residual is below the extrapolation's; TVI_MLP only          */
 } tvi_init;
 
 typedef struct {
@@ -114,6 +119,10 @@ typedef struct {
                                R the chunk residual (Algorithm 1)                     */
     int32_t init;           /* tvi_init                                              */
     int32_t halving;        /* 1: retry a failed chunk at half its length, down to 1 */
+    const void *predictor;  /* TVI_INIT_PREDICTOR: device parameters (float) of the
+                               predictor, see tvi_predictor_forward                  */
+    int32_t predictor_hidden;  /* its hidden width, <= 256                          */
+    int32_t predictor_steps;   /* steps it predicts, >= chunk                       */
 } tvi_options;
 
 /* Fills `opt` with the defaults: chunk 64, tol_a 1e-8, tol_r 1e-6 (Section 2.3),
@@ -193,15 +202,17 @@ tvi_status tvi_solve_forward(const tvi_model *model, const tvi_options *opt, int
  * The states come either from the full trajectory `y` (then ckpt may be
  * NULL) or, when y is NULL, are recomputed chunk by chunk from the
  * checkpoints `ckpt` written by tvi_solve_forward with the same options;
- * recomputed states are bitwise those of the forward pass.  Recomputation
- * needs `workspace` of tvi_adjoint_workspace_bytes() bytes (device); with the
- * trajectory given, workspace may be NULL.
+ * recomputed states are bitwise those of the forward pass.  `workspace` of
+ * tvi_adjoint_workspace_bytes() bytes (device) is needed for recomputation
+ * and, for TVI_MLP, always (per-series partial gradients, summed afterwards
+ * over the series in a fixed order); otherwise it may be NULL.
  *
  *   g       dL/dy [B][N+1][n] or ragged (required)
- *   dLdp    [B][P] (per-series parameters; shared parameters are not supported by
- *           this entry point for the analytic models)
+ *   dLdp    [B][P] for per-series parameters (TVI_LINEAR, TVI_VANDERPOL,
+ *           TVI_ROBERTSON); [P] for the shared parameters of TVI_MLP
  *   dLdy0   [B][n]
- *   status  int32 [B]: SINGULAR if a transposed block could not be inverted
+ *   status  int32 [B]: SINGULAR if a transposed block could not be inverted,
+ *           or the code of a failed recomputation; that series' outputs are NaN
  */
 size_t tvi_adjoint_workspace_bytes(const tvi_model *model, const tvi_options *opt, int64_t B);
 
@@ -210,6 +221,54 @@ tvi_status tvi_solve_adjoint(const tvi_model *model, const tvi_options *opt, int
                              const void *y, const void *ckpt, const void *g, void *dLdp,
                              void *dLdy0, int32_t *status, void *workspace, size_t workspace_bytes,
                              void *stream);
+
+/*
+ * tvi_loss_grad -- value and gradient g = dL/dy of the losses the benchmarks
+ * integrate, over `points` states of size n (y and g [points][n], device):
+ *   TVI_LOSS_FROBENIUS    L = sqrt(sum y^2) over every entry (the timing loss of
+ *                         Section 5.2), g = y / L
+ *   TVI_LOSS_MEAN_SQUARE  L = sum over observed points of |y|^2 / (n_observed n),
+ *                         g = 2 y / (n_observed n) at observed points, 0 elsewhere;
+ *                         observed: uint8 [points] (device), n_observed its count
+ * The sum is reduced in a fixed order (deterministic).  loss: one double
+ * (device).  workspace: tvi_loss_workspace_bytes() bytes (device).  Enqueued
+ * on `stream` without host synchronisation, so it can be captured in a graph.
+ */
+typedef enum { TVI_LOSS_FROBENIUS = 0, TVI_LOSS_MEAN_SQUARE = 1 } tvi_loss_kind;
+size_t tvi_loss_workspace_bytes(void);
+tvi_status tvi_loss_grad(int32_t kind, int32_t dtype, int64_t points, int32_t n, const void *y,
+                         const uint8_t *observed, int64_t n_observed, void *g, double *loss, void *workspace,
+                         size_t workspace_bytes, void *stream);
+
+/*
+ * Learned chunk predictor: x -> GELU(W1 x + b1) -> GELU(W2 . + b2) -> W3 . + b3,
+ * x standardised by fixed constants.  Float32.  params (device) packs
+ * W1[hidden][n_in], b1[hidden], W2[hidden][hidden], b2[hidden],
+ * W3[n_out][hidden], b3[n_out], then mean[n_in] and std[n_in] of the inputs:
+ * tvi_predictor_param_count() floats; the first count - 2 n_in are the
+ * trained network.  GELU is the exact x (1 + erf(x / sqrt 2)) / 2.
+ *
+ * tvi_predictor_forward      out [M][n_out] for inputs x [M][n_in].
+ * tvi_predictor_train_step   one step of Adam (Kingma and Ba; beta1 0.9,
+ *   beta2 0.999, eps 1e-8, bias-corrected; `step` counts from 1) on the
+ *   mean squared error L = mean (out - target)^2 over a batch of M samples:
+ *   writes L to loss[0] and dL/dnetwork to grad (count - 2 n_in floats),
+ *   updates adam_m, adam_v (same size, zero before the first step) and the
+ *   network part of params in place.  lr = 0 only evaluates L and the
+ *   gradient.
+ * Both need workspace of tvi_predictor_workspace_bytes(M) bytes (device).
+ */
+typedef struct {
+    int32_t n_in, hidden, n_out;
+} tvi_predictor;
+int64_t tvi_predictor_param_count(const tvi_predictor *p);
+size_t tvi_predictor_workspace_bytes(const tvi_predictor *p, int64_t M);
+tvi_status tvi_predictor_forward(const tvi_predictor *p, int64_t M, const float *x, const float *params,
+                                 float *out, void *workspace, size_t workspace_bytes, void *stream);
+tvi_status tvi_predictor_train_step(const tvi_predictor *p, int64_t M, const float *x, const float *target,
+                                    float *params, float *grad, float *adam_m, float *adam_v, int64_t step,
+                                    float lr, float *loss, void *workspace, size_t workspace_bytes,
+                                    void *stream);
 
 #ifdef __cplusplus
 }

@@ -77,7 +77,10 @@ tvi_status check_options(const tvi_options *o)
     if (o->chunk < 1 || o->chunk > 8 * kWave) return TVI_EINVAL;
     if (o->max_newton < 1) return TVI_EINVAL;
     if (!(o->tol_a >= 0.0) || !(o->tol_r >= 0.0)) return TVI_EINVAL;
-    if (o->init != TVI_INIT_ZERO && o->init != TVI_INIT_EXTRAP) return TVI_EINVAL;
+    if (o->init != TVI_INIT_ZERO && o->init != TVI_INIT_EXTRAP && o->init != TVI_INIT_PREDICTOR) return TVI_EINVAL;
+    if (o->init == TVI_INIT_PREDICTOR &&
+        (!o->predictor || o->predictor_hidden < 1 || o->predictor_hidden > 256 || o->predictor_steps < o->chunk))
+        return TVI_EINVAL;
     return TVI_OK;
 }
 
@@ -101,6 +104,9 @@ SolveArgs<IO> make_args(const tvi_model *model, const tvi_options *opt, int64_t 
     a.halving = opt->halving;
     a.tol_a = opt->tol_a;
     a.tol_r = opt->tol_r;
+    a.pred = static_cast<const float *>(opt->predictor);
+    a.pred_hidden = opt->predictor_hidden;
+    a.pred_steps = opt->predictor_steps;
     return a;
 }
 
@@ -137,6 +143,9 @@ void tvi_default_options(tvi_options *opt)
     opt->tol_r = 1e-6;
     opt->init = TVI_INIT_ZERO;
     opt->halving = 1;
+    opt->predictor = nullptr;
+    opt->predictor_hidden = 0;
+    opt->predictor_steps = 0;
 }
 
 const char *tvi_status_str(int32_t s)
@@ -201,6 +210,8 @@ tvi_status tvi_solve_forward(const tvi_model *model, const tvi_options *opt, int
     int S = 0, T = 0;
     if (model->kind == TVI_MLP) {
         if (opt->chunk > 128) return TVI_EUNSUPPORTED;
+    } else if (opt->init == TVI_INIT_PREDICTOR) {
+        return TVI_EUNSUPPORTED;
     } else if ((e = resolve_tiling(opt, S, T)) != TVI_OK) {
         return e;
     }
@@ -223,7 +234,8 @@ tvi_status tvi_solve_forward(const tvi_model *model, const tvi_options *opt, int
 
 size_t tvi_adjoint_workspace_bytes(const tvi_model *model, const tvi_options *opt, int64_t B)
 {
-    if (!model || !opt || B < 0 || model->n < 1) return 0;
+    if (!model || !opt || B < 0 || model->n < 1 || opt->chunk < 1) return 0;
+    if (model->kind == TVI_MLP) return mlp_theta_workspace_bytes(B);
     return (size_t)B * (size_t)opt->chunk * (size_t)model->n * sizeof(double);
 }
 
@@ -235,14 +247,40 @@ tvi_status tvi_solve_adjoint(const tvi_model *model, const tvi_options *opt, int
     tvi_status e = check_model(model);
     if (e != TVI_OK) return e;
     if ((e = check_options(opt)) != TVI_OK) return e;
-    if (model->params_shared) return TVI_EUNSUPPORTED;
+    const bool mlp = model->kind == TVI_MLP;
+    if (mlp != (model->params_shared != 0)) return TVI_EUNSUPPORTED;
     if (B < 0 || N < 0) return TVI_EINVAL;
     if (B == 0) return TVI_OK;
     if (!times || !params || !g || !dLdp || !dLdy0 || !status) return TVI_EINVAL;
     const bool recompute = (y == nullptr);
-    if (recompute) {
-        if (!ckpt || !workspace) return TVI_EINVAL;
-        if (workspace_bytes < tvi_adjoint_workspace_bytes(model, opt, B)) return TVI_EINVAL;
+    if (recompute && !ckpt) return TVI_EINVAL;
+    if ((recompute || mlp) &&
+        (!workspace || workspace_bytes < tvi_adjoint_workspace_bytes(model, opt, B)))
+        return TVI_EINVAL;
+    if (mlp) {
+        if (opt->chunk > 128) return TVI_EUNSUPPORTED;
+        const int pass = recompute ? PASS_ADJOINT_RECOMPUTE : PASS_ADJOINT;
+        const hipStream_t st = static_cast<hipStream_t>(stream);
+        if (model->dtype == TVI_F64) {
+            SolveArgs<double> a = make_args<double>(model, opt, B, N, offsets, times, nullptr, params);
+            a.y = const_cast<double *>(static_cast<const double *>(y));
+            a.ckpt = const_cast<double *>(static_cast<const double *>(ckpt));
+            a.g = static_cast<const double *>(g);
+            a.dLdp = static_cast<double *>(dLdp);
+            a.dLdy0 = static_cast<double *>(dLdy0);
+            a.status = status;
+            a.ws = static_cast<double *>(workspace);
+            return launch_mlp(pass, TVI_F64, &a, st);
+        }
+        SolveArgs<float> a = make_args<float>(model, opt, B, N, offsets, times, nullptr, params);
+        a.y = const_cast<float *>(static_cast<const float *>(y));
+        a.ckpt = const_cast<double *>(static_cast<const double *>(ckpt));
+        a.g = static_cast<const float *>(g);
+        a.dLdp = static_cast<float *>(dLdp);
+        a.dLdy0 = static_cast<float *>(dLdy0);
+        a.status = status;
+        a.ws = static_cast<double *>(workspace);
+        return launch_mlp(pass, TVI_F32, &a, st);
     }
     int S, T;
     if ((e = resolve_tiling(opt, S, T)) != TVI_OK) return e;
@@ -268,6 +306,65 @@ tvi_status tvi_solve_adjoint(const tvi_model *model, const tvi_options *opt, int
     a.status = status;
     a.ws = static_cast<double *>(workspace);
     return dispatch(pass, model, &a, S, T, st);
+}
+
+size_t tvi_loss_workspace_bytes(void) { return loss_workspace_bytes(); }
+
+tvi_status tvi_loss_grad(int32_t kind, int32_t dtype, int64_t points, int32_t n, const void *y,
+                         const uint8_t *observed, int64_t n_observed, void *g, double *loss, void *workspace,
+                         size_t workspace_bytes, void *stream)
+{
+    if (kind != TVI_LOSS_FROBENIUS && kind != TVI_LOSS_MEAN_SQUARE) return TVI_EINVAL;
+    if (dtype != TVI_F32 && dtype != TVI_F64) return TVI_EINVAL;
+    if (points < 0 || n < 1) return TVI_EINVAL;
+    if (!y || !g || !loss || !workspace || workspace_bytes < loss_workspace_bytes()) return TVI_EINVAL;
+    double scale = 1.0;
+    if (kind == TVI_LOSS_MEAN_SQUARE) {
+        if (!observed || n_observed < 1) return TVI_EINVAL;
+        scale = 1.0 / ((double)n_observed * (double)n);
+    }
+    return launch_loss(kind, dtype, points * n, y, kind == TVI_LOSS_MEAN_SQUARE ? observed : nullptr, n, scale, g,
+                       loss, static_cast<double *>(workspace), static_cast<hipStream_t>(stream));
+}
+
+static bool pred_ok(const tvi_predictor *p)
+{
+    return p && p->n_in >= 1 && p->hidden >= 1 && p->n_out >= 1 && p->n_in <= 64 && p->hidden <= 1024 &&
+           p->n_out <= 4096;
+}
+
+int64_t tvi_predictor_param_count(const tvi_predictor *p)
+{
+    return pred_ok(p) ? predictor_param_count(p->n_in, p->hidden, p->n_out) : -1;
+}
+
+size_t tvi_predictor_workspace_bytes(const tvi_predictor *p, int64_t M)
+{
+    return (pred_ok(p) && M >= 0) ? predictor_workspace_bytes(p->n_in, p->hidden, p->n_out, M) : 0;
+}
+
+tvi_status tvi_predictor_forward(const tvi_predictor *p, int64_t M, const float *x, const float *params,
+                                 float *out, void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (!pred_ok(p) || M < 0 || M > 0x7fffffff) return TVI_EINVAL;
+    if (M == 0) return TVI_OK;
+    if (!x || !params || !out || !workspace || workspace_bytes < tvi_predictor_workspace_bytes(p, M))
+        return TVI_EINVAL;
+    return predictor_forward(p->n_in, p->hidden, p->n_out, M, x, params, out, workspace,
+                             static_cast<hipStream_t>(stream));
+}
+
+tvi_status tvi_predictor_train_step(const tvi_predictor *p, int64_t M, const float *x, const float *target,
+                                    float *params, float *grad, float *adam_m, float *adam_v, int64_t step,
+                                    float lr, float *loss, void *workspace, size_t workspace_bytes,
+                                    void *stream)
+{
+    if (!pred_ok(p) || M < 1 || M > 0x7fffffff || step < 1 || !(lr >= 0.f)) return TVI_EINVAL;
+    if (!x || !target || !params || !grad || !adam_m || !adam_v || !loss || !workspace ||
+        workspace_bytes < tvi_predictor_workspace_bytes(p, M))
+        return TVI_EINVAL;
+    return predictor_train_step(p->n_in, p->hidden, p->n_out, M, x, target, params, grad, adam_m, adam_v, step, lr,
+                                loss, workspace, static_cast<hipStream_t>(stream));
 }
 
 } // extern "C"

@@ -242,6 +242,118 @@ __device__ __forceinline__ void seg_scan_down(Affine<N, R> &a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// The same maps kept as "identity plus small", x -> (I + F) x + z.  For blocks
+// D = I - dt j with dt j small (non-stiff steps in float), I + F = D^{-1}
+// with F = D^{-1} (dt j) small, so F and every composition carry full
+// relative precision instead of losing it next to the identity.
+// ---------------------------------------------------------------------------
+template <int N, class R>
+struct AffineI {
+    R F[N][N];
+    R z[N];
+};
+
+template <int N, class R>
+__device__ __forceinline__ void affine_identity(AffineI<N, R> &a)
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) a.F[i][k] = R(0);
+        a.z[i] = R(0);
+    }
+}
+
+// y = (I + F) x + c   (y may alias x or c)
+template <int N, class R>
+__device__ __forceinline__ void apply_ip(const R (&F)[N][N], const R (&x)[N], const R (&c)[N], R (&y)[N])
+{
+    R t[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        R s = c[i];
+#pragma unroll
+        for (int l = 0; l < N; ++l) s = fma(F[i][l], x[l], s);
+        t[i] = s + x[i];
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) y[i] = t[i];
+}
+
+// a <- a o b:  F = Fa + Fb + Fa Fb,  z = (I + Fa) zb + za
+template <int N, class R>
+__device__ __forceinline__ void affine_after(AffineI<N, R> &a, const AffineI<N, R> &b)
+{
+    apply_ip(a.F, b.z, a.z, a.z);
+    R t[N][N];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            R s = a.F[i][k] + b.F[i][k];
+#pragma unroll
+            for (int l = 0; l < N; ++l) s = fma(a.F[i][l], b.F[l][k], s);
+            t[i][k] = s;
+        }
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int k = 0; k < N; ++k) a.F[i][k] = t[i][k];
+}
+
+template <int N, class R>
+__device__ __forceinline__ void affine_read(const AffineI<N, R> &a, int src, AffineI<N, R> &out)
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) out.F[i][k] = lane_read(a.F[i][k], src);
+        out.z[i] = lane_read(a.z[i], src);
+    }
+}
+
+template <int N, int S, class R>
+__device__ __forceinline__ void seg_scan_up(AffineI<N, R> &a)
+{
+    const int lane = lane_id();
+    const int q = lane & (S - 1);
+#pragma unroll
+    for (int d = 1; d < S; d <<= 1) {
+        AffineI<N, R> o;
+        affine_read(a, q >= d ? lane - d : lane, o);
+        if (q >= d) affine_after(a, o);
+    }
+}
+
+template <int N, int S, class R>
+__device__ __forceinline__ void seg_scan_down(AffineI<N, R> &a)
+{
+    const int lane = lane_id();
+    const int q = lane & (S - 1);
+#pragma unroll
+    for (int d = 1; d < S; d <<= 1) {
+        AffineI<N, R> o;
+        affine_read(a, q + d < S ? lane + d : lane, o);
+        if (q + d < S) affine_after(a, o);
+    }
+}
+
+// F with I + F = (I - E)^{-1}: F = (I - E)^{-1} E.  Returns false on a zero or
+// non-finite pivot.
+template <int N, class R>
+__device__ __forceinline__ bool inverse_plus(const R (&E)[N][N], R (&F)[N][N])
+{
+    R D[N][N], X[N][N];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int k = 0; k < N; ++k) D[i][k] = ((i == k) ? R(1) : R(0)) - E[i][k];
+    const bool ok = invert(D, X);
+    matmul(X, E, F);
+    return ok;
+}
+
 // Vector of N doubles from lane src.
 template <int N, class R>
 __device__ __forceinline__ void vec_read(const R (&v)[N], int src, R (&out)[N])

@@ -65,9 +65,21 @@ tvi_status launch_linear4(int pass, int dtype, const void *args, int S, int T, h
 tvi_status launch_pcr(int dtype, int n, int64_t B, int m, const void *D, const void *r, void *x, int transpose,
                       int S, int T, hipStream_t stream);
 tvi_status launch_mlp(int pass, int dtype, const void *args, hipStream_t stream);
+size_t mlp_theta_workspace_bytes(int64_t B);
 tvi_status launch_mlp_eval(int dtype, int64_t M, const void *states, const void *params, void *f, void *J,
                            hipStream_t stream);
 tvi_status launch_eval(int kind, int n, int dtype, int64_t M, const void *states, const void *times,
                        const void *params, int shared, void *f, void *J, hipStream_t stream);
+tvi_status launch_loss(int kind, int dtype, int64_t count, const void *y, const uint8_t *observed,
+                       int64_t point_stride, double scale, void *g, double *loss, double *partial,
+                       hipStream_t stream);
+size_t loss_workspace_bytes();
+int64_t predictor_param_count(int n_in, int H, int n_out);
+size_t predictor_workspace_bytes(int n_in, int H, int n_out, int64_t M);
+tvi_status predictor_forward(int n_in, int H, int n_out, int64_t M, const float *x, const float *params, float *out,
+                             void *ws, hipStream_t st);
+tvi_status predictor_train_step(int n_in, int H, int n_out, int64_t M, const float *x, const float *target,
+                                float *params, float *grad, float *adam_m, float *adam_v, int64_t step, float lr,
+                                float *loss, void *ws, hipStream_t st);
 
 } // namespace tvi

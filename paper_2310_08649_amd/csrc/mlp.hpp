@@ -3,12 +3,14 @@
 // v_mfma_f32_16x16x32_bf16 with hidden units along M and samples (time steps
 // of a chunk) along N.
 //
-// Precision.  The rate h(y) that enters the Newton residual is computed as a
-// "bf16x3" product (every operand split into a bf16 high and low part, three
-// MFMAs ah*bh + ah*bl + al*bh accumulated in float), which is about as
-// accurate as float arithmetic; the Jacobian used only inside Newton's method
-// may take plain bf16 products (an approximate Jacobian changes the
-// convergence rate, not the root); the adjoint uses bf16x3 everywhere.
+// Precision.  Every product that enters the Newton residual or the adjoint
+// is computed from a three-way bf16 split of both operands (x = x0 + x1 + x2,
+// each part a bf16 holding the next 8 bits of the float mantissa) with the
+// six MFMAs x0y0 + x0y1 + x1y0 + x0y2 + x1y1 + x2y0 accumulated in float; the
+// dropped terms are below float rounding, so this is float-accurate.  (A
+// two-way split with three products keeps only about 16 bits.)  The Jacobian
+// used only inside Newton's method may take plain bf16 products: an
+// approximate Jacobian changes the convergence rate, not the root.
 //
 // Operand layout (16x16x32, lane l, group g = l / 16, r = l % 16): the A
 // operand of a lane is row r of the 16-row tile, the B operand column r of
@@ -47,7 +49,7 @@ __device__ __forceinline__ f32x4 mma(const bf16x8 &a, const bf16x8 &b, f32x4 c)
 }
 
 struct Split {
-    bf16x8 hi, lo;
+    bf16x8 p0, p1, p2;
 };
 
 __device__ __forceinline__ Split split8(const float (&x)[8])
@@ -55,34 +57,49 @@ __device__ __forceinline__ Split split8(const float (&x)[8])
     Split s;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-        const __bf16 h = (__bf16)x[e];
-        s.hi[e] = h;
-        s.lo[e] = (__bf16)(x[e] - (float)h);
+        const __bf16 h0 = (__bf16)x[e];
+        const float r1 = x[e] - (float)h0;
+        const __bf16 h1 = (__bf16)r1;
+        s.p0[e] = h0;
+        s.p1[e] = h1;
+        s.p2[e] = (__bf16)(r1 - (float)h1);
     }
     return s;
 }
 
-// c += a * b with bf16x3 (EXACT3) or plain bf16 products
-template <bool EXACT3>
+__device__ __forceinline__ Split split_lds(const float *x)
+{
+    float v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = x[e];
+    return split8(v);
+}
+
+// c += a * b: float-accurate (EXACT, six products) or plain bf16 (one product)
+template <bool EXACT>
 __device__ __forceinline__ f32x4 mma_acc(const Split &a, const Split &b, f32x4 c)
 {
-    if (EXACT3) {
-        c = mma(a.lo, b.hi, c);
-        c = mma(a.hi, b.lo, c);
+    if (EXACT) {
+        c = mma(a.p0, b.p2, c);
+        c = mma(a.p1, b.p1, c);
+        c = mma(a.p2, b.p0, c);
+        c = mma(a.p0, b.p1, c);
+        c = mma(a.p1, b.p0, c);
     }
-    return mma(a.hi, b.hi, c);
+    return mma(a.p0, b.p0, c);
 }
 
 __device__ __forceinline__ int kchain(int ks, int g, int e) { return 32 * ks + 16 * (e >> 2) + 4 * g + (e & 3); }
 
-// Weights in LDS, stored per (tile, lane) in operand order (hi and lo parts).
+// Weights in LDS as float, stored per (tile, lane) in operand order: a lane
+// reads its eight k-elements with two 16-byte loads and splits them.
 struct Weights {
-    Split w1[4][kWave];        // W1   [64 x 8]:  M-tiles 0..3, one K-step (k = 8 g + e, k < 8)
-    Split w2[4][2][kWave];     // W2   [64 x 64]: M-tiles, chained K-steps
-    Split w3[2][kWave];        // W3   [8 x 64]:  one M-tile (rows 8..15 zero), chained K-steps
-    Split w3t[4][kWave];       // W3^T [64 x 8]:  M-tiles, one K-step (k = 8 g + e, k < 8)
-    Split w2t[4][2][kWave];    // W2^T [64 x 64]
-    float w1p[2][4][8][NS];    // W1[k(ks, g, e)][c]: the Jacobian's first factor
+    float w1[4][kWave][8];       // W1   [64 x 8]:  M-tiles 0..3, one K-step (k = 8 g + e, k < 8)
+    float w2[4][2][kWave][8];    // W2   [64 x 64]: M-tiles, chained K-steps
+    float w3[2][kWave][8];       // W3   [8 x 64]:  one M-tile (rows 8..15 zero), chained K-steps
+    float w3t[4][kWave][8];      // W3^T [64 x 8]:  M-tiles, one K-step (k = 8 g + e, k < 8)
+    float w2t[4][2][kWave][8];   // W2^T [64 x 64]
+    float w1p[2][4][8][NS];      // W1[k(ks, g, e)][c]: the Jacobian's first factor
     float b1[H], b2[H], b3[NS];
 };
 
@@ -100,8 +117,11 @@ __device__ void load_weights(Weights &W, const IO *th)
             a[e] = k < NS ? (float)th[oW1 + (16 * mt + r) * NS + k] : 0.f;   // W1[m][k]
             b[e] = k < NS ? (float)th[oW3 + k * H + 16 * mt + r] : 0.f;     // W3^T[m][k] = W3[k][m]
         }
-        W.w1[mt][l] = split8(a);
-        W.w3t[mt][l] = split8(b);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            W.w1[mt][l][e] = a[e];
+            W.w3t[mt][l][e] = b[e];
+        }
     }
     for (int idx = t; idx < 8 * kWave; idx += kThreads) {
         const int mt = idx / (2 * kWave), ks = (idx / kWave) & 1, l = idx % kWave, g = l >> 4, r = l & 15;
@@ -112,15 +132,19 @@ __device__ void load_weights(Weights &W, const IO *th)
             a[e] = (float)th[oW2 + (16 * mt + r) * H + k];   // W2[m][k]
             b[e] = (float)th[oW2 + k * H + 16 * mt + r];     // W2^T[m][k] = W2[k][m]
         }
-        W.w2[mt][ks][l] = split8(a);
-        W.w2t[mt][ks][l] = split8(b);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            W.w2[mt][ks][l][e] = a[e];
+            W.w2t[mt][ks][l][e] = b[e];
+        }
     }
     for (int idx = t; idx < 2 * kWave; idx += kThreads) {
         const int ks = idx / kWave, l = idx % kWave, g = l >> 4, r = l & 15;
         float a[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) a[e] = r < NS ? (float)th[oW3 + r * H + kchain(ks, g, e)] : 0.f;
-        W.w3[ks][l] = split8(a);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) W.w3[ks][l][e] = a[e];
     }
     for (int idx = t; idx < 2 * 4 * 8 * NS; idx += kThreads) {
         const int c = idx % NS, e = (idx / NS) % 8, g = (idx / (NS * 8)) % 4, ks = idx / (NS * 32);
@@ -143,7 +167,7 @@ struct Acts {
 // Forward pass for the wave's samples.  ys(u) gives the state of the lane's
 // column sample (8 floats, used by group 0 only).  Writes the rate of sample
 // (16 u + r) rows 4g+i (g < 2) through put_f(u, row, value).
-template <bool EXACT3, class GetY, class PutF>
+template <bool EXACT, class GetY, class PutF>
 __device__ __forceinline__ void forward(const Weights &W, Acts &A, GetY get_y, PutF put_f)
 {
     const int l = lane_id(), g = l >> 4;
@@ -166,7 +190,7 @@ __device__ __forceinline__ void forward(const Weights &W, Acts &A, GetY get_y, P
         for (int i = 0; i < 4; ++i) bias[i] = W.b1[16 * mt + 4 * g + i];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            f32x4 z = mma_acc<true>(W.w1[mt][l], yb[u], bias);
+            f32x4 z = mma_acc<true>(split_lds(W.w1[mt][l]), yb[u], bias);
 #pragma unroll
             for (int i = 0; i < 4; ++i) A.a1[mt][u][i] = tanhf(z[i]);
         }
@@ -187,8 +211,8 @@ __device__ __forceinline__ void forward(const Weights &W, Acts &A, GetY get_y, P
             f32x4 z;
 #pragma unroll
             for (int i = 0; i < 4; ++i) z[i] = W.b2[16 * mt + 4 * g + i];
-            z = mma_acc<true>(W.w2[mt][0][l], bk[0], z);
-            z = mma_acc<true>(W.w2[mt][1][l], bk[1], z);
+            z = mma_acc<true>(split_lds(W.w2[mt][0][l]), bk[0], z);
+            z = mma_acc<true>(split_lds(W.w2[mt][1][l]), bk[1], z);
 #pragma unroll
             for (int i = 0; i < 4; ++i) A.a2[mt][u][i] = tanhf(z[i]);
         }
@@ -204,21 +228,21 @@ __device__ __forceinline__ void forward(const Weights &W, Acts &A, GetY get_y, P
             float v[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) v[e] = A.a2[2 * ks + (e >> 2)][u][e & 3];
-            z = mma_acc<true>(W.w3[ks][l], split8(v), z);
+            z = mma_acc<true>(split_lds(W.w3[ks][l]), split8(v), z);
         }
         if (g < 2) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) put_f(u, 4 * g + i, z[i]);
         }
     }
-    (void)EXACT3;
+    (void)EXACT;
 }
 
 // State Jacobians J = W3 diag(1 - a2^2) W2 diag(1 - a1^2) W1 of the wave's
 // samples, column by column: for column c the B operand of the W2 product
 // is (1 - a1^2) * W1[:, c] in the chained order, the product's accumulators
 // scaled by (1 - a2^2) feed the W3 product.  put_j(u, row, c, value).
-template <bool EXACT3, class PutJ>
+template <bool EXACT, class PutJ>
 __device__ __forceinline__ void jacobian(const Weights &W, const Acts &A, PutJ put_j)
 {
     const int l = lane_id(), g = l >> 4;
@@ -246,8 +270,8 @@ __device__ __forceinline__ void jacobian(const Weights &W, const Acts &A, PutJ p
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
                 f32x4 z = {0.f, 0.f, 0.f, 0.f};
-                z = mma_acc<EXACT3>(W.w2[mt][0][l], bk[0], z);
-                p2[mt] = mma_acc<EXACT3>(W.w2[mt][1][l], bk[1], z);
+                z = mma_acc<EXACT>(split_lds(W.w2[mt][0][l]), bk[0], z);
+                p2[mt] = mma_acc<EXACT>(split_lds(W.w2[mt][1][l]), bk[1], z);
             }
             f32x4 j = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -255,7 +279,7 @@ __device__ __forceinline__ void jacobian(const Weights &W, const Acts &A, PutJ p
                 float v[8];
 #pragma unroll
                 for (int e = 0; e < 8; ++e) v[e] = d2[2 * ks + (e >> 2)][e & 3] * p2[2 * ks + (e >> 2)][e & 3];
-                j = mma_acc<EXACT3>(W.w3[ks][l], split8(v), j);
+                j = mma_acc<EXACT>(split_lds(W.w3[ks][l]), split8(v), j);
             }
             if (g < 2) {
 #pragma unroll

@@ -1,5 +1,5 @@
-// Chunked backward Euler for the neural-ODE model (n = 8, two tanh layers of
-// 64, shared parameters): one workgroup of four waves per series.
+// Chunked backward Euler and its adjoint for the neural-ODE model (n = 8, two
+// tanh layers of 64, shared parameters): one workgroup of four waves per series.
 //
 // Per Newton iteration (Algorithm 1):
 //   * each wave evaluates the network for its 32 steps of the chunk on MFMA
@@ -11,6 +11,14 @@
 //     pivoting, float) and the affine maps are composed by PCR across the
 //     32 lanes of the wave and then across the four waves through LDS.
 // The chunk start state is carried in double, the increments dy in float.
+//
+// Adjoint (Appendix A): nominal chunks in reverse; the chunk's states are
+// re-solved from its checkpoint by the same code (or read from the
+// trajectory), the transposed blocks D_j^T are inverted and reduced from the
+// last step down, and lam_j is back-propagated through the network on MFMA to
+// accumulate dL/dtheta = sum_j dt_j (dh/dtheta)^T lam_j.  Every workgroup
+// writes its series' partial gradient; a second kernel sums the partials over
+// the series in a fixed order.
 #include "dispatch.hpp"
 #include "mlp.hpp"
 
@@ -18,18 +26,29 @@ namespace tvi {
 
 using namespace mlp;
 
+constexpr int kRow = H + 1;  // padded row of the sample-major scratch (no bank conflicts)
+
 struct MlpShared {
     Weights W;
     float y[kMaxChunk][NS];     // network input of each step
-    float f[kMaxChunk][NS];     // network output of each step
-    float J[kMaxChunk][NS * NS];
+    float f[kMaxChunk][NS];     // network output of each step (adjoint: dt * lam)
     float dy[kMaxChunk][NS];
+    float yc[kMaxChunk][NS];    // converged states of the chunk (adjoint)
+    union {
+        float J[kMaxChunk][NS * NS];
+        struct {
+            float a[kWaves][kSPW][kRow];   // activations, sample-major
+            float d[kWaves][kSPW][kRow];   // back-propagated deltas, sample-major
+        } v;
+        float theta[P];
+    } u;
     float wmap[kWaves][NS * NS + NS];
     float red[kWaves];
+    float lam[NS];
     int flag[kWaves];
 };
 
-// Evaluate the network for the block's steps: every wave its 32 steps.
+// Evaluate the network for the block's steps (every wave its 32 steps) from S.y.
 __device__ __forceinline__ void mlp_rates(MlpShared &S, Acts &A)
 {
     const int w = threadIdx.x / kWave, r = lane_id() & 15;
@@ -42,47 +61,187 @@ __device__ __forceinline__ void mlp_rates(MlpShared &S, Acts &A)
         [&](int u, int row, float v) { S.f[kSPW * w + 16 * u + r][row] = v; });
 }
 
-template <class IO>
-__global__ __launch_bounds__(kThreads) void mlp_forward_kernel(SolveArgs<IO> a)
+__device__ __forceinline__ void mlp_jacobians(MlpShared &S, const Acts &A, bool exact)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
-    MlpShared &S = *reinterpret_cast<MlpShared *>(smem);
+    const int w = threadIdx.x / kWave, r = lane_id() & 15;
+    auto put = [&](int u, int row, int c, float val) { S.u.J[kSPW * w + 16 * u + r][row * NS + c] = val; };
+    if (exact) jacobian<true>(S.W, A, put);
+    else jacobian<false>(S.W, A, put);
+}
+
+// Where the converged states of a chunk go.
+template <class IO>
+struct MlpTrajectorySink {
+    IO *y;       // series' first point or null
+    double *ck;  // series' checkpoints or null
+    int64_t K, Nb;
+    int C;
+    __device__ void put(int64_t k, const double (&ys)[NS], const float (&dy)[NS]) const
+    {
+        if (y) {
+#pragma unroll
+            for (int e = 0; e < NS; ++e) st(y + k * NS + e, ys[e] + (double)dy[e]);
+        }
+    }
+    __device__ void boundary(int64_t s, const double (&ys)[NS], int tid) const
+    {
+        const int64_t c = (s + C - 1) / C;
+        if (ck && tid < NS && c < K) ck[c * NS + tid] = ys[tid];
+    }
+    __device__ void fail(int64_t s, int tid) const
+    {
+        if (!y) return;
+        const double nan = __builtin_nan("");
+        for (int64_t k = s + 1 + tid; k <= Nb; k += kThreads)
+#pragma unroll
+            for (int e = 0; e < NS; ++e) st(y + k * NS + e, nan);
+    }
+};
+
+struct MlpChunkSink {
+    float (*yc)[NS];
+    int64_t c0;
+    __device__ void put(int64_t k, const double (&ys)[NS], const float (&dy)[NS]) const
+    {
+        // the value the trajectory stores (float), as the network sees it
+#pragma unroll
+        for (int e = 0; e < NS; ++e) yc[k - c0 - 1][e] = (float)(ys[e] + (double)dy[e]);
+    }
+    __device__ void boundary(int64_t, const double (&)[NS], int) const {}
+    __device__ void fail(int64_t, int) const {}
+};
+
+// Residual of the chunk iterate dy (Eq. batched-backward-euler) for the lane's
+// step, and its norm over the chunk (block-wide; every thread calls it).
+__device__ __forceinline__ float chunk_residual(MlpShared &S, Acts &A, const double (&ys)[NS], const float (&dy)[NS],
+                                                float hj, bool v, float (&R)[NS])
+{
+    const int w = threadIdx.x / kWave, l = lane_id();
+    const int j = kSPW * w + (l & (kSPW - 1));
+    if (l < kSPW) {
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            S.y[j][k] = (float)(ys[k] + (double)dy[k]);
+            S.dy[j][k] = dy[k];
+        }
+    }
+    __syncthreads();
+    mlp_rates(S, A);
+    __syncthreads();
+    float acc = 0.f;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        const float prev = j > 0 ? S.dy[j - 1][k] : 0.f;
+        R[k] = v ? (dy[k] - prev) - hj * S.f[j][k] : 0.f;
+        acc = fmaf(R[k], R[k], acc);
+    }
+    acc = seg_sum<kSPW>(acc);
+    if (l == 0) S.red[w] = acc;
+    __syncthreads();
+    const float nrm = sqrtf(S.red[0] + S.red[1] + S.red[2] + S.red[3]);
+    __syncthreads();
+    return nrm;
+}
+
+// The norm alone, with activations of its own (the caller's are not live here).
+__device__ __noinline__ float chunk_residual_norm(MlpShared &S, const double (&ys)[NS], const float (&dy)[NS],
+                                                  float hj, bool v)
+{
+    Acts A;
+    float R[NS];
+    return chunk_residual(S, A, ys, dy, hj, v, R);
+}
+
+__device__ __forceinline__ float gelu_f(float x) { return 0.5f * x * (1.f + erff(x * 0.70710678118654752f)); }
+
+// The learned predictor's slopes for the chunk starting at (ys, ts) with first
+// step dts: out[o], o < m * NS, in LDS (block-wide; every thread calls it).
+// params = W1[Hp][NS+2], b1, W2[Hp][Hp], b2, W3[NS*steps][Hp], b3, mean[NS+2], std[NS+2].
+__device__ void predictor_slopes(float *a1, float *a2, float *out, const float *pp, int Hp, int steps,
+                                 const double (&ys)[NS], double ts, double dts, int m)
+{
+    const int tid = threadIdx.x, nin = NS + 2, nout = NS * steps;
+    const float *W1 = pp, *b1 = W1 + Hp * nin, *W2 = b1 + Hp, *b2 = W2 + Hp * Hp, *W3 = b2 + Hp,
+                *b3 = W3 + (int64_t)nout * Hp, *mu = b3 + nout, *sd = mu + nin;
+    float x[NS + 2];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) x[k] = (float)ys[k];
+    x[NS] = (float)ts;
+    x[NS + 1] = (float)log(dts);
+#pragma unroll
+    for (int k = 0; k < NS + 2; ++k) x[k] = (x[k] - mu[k]) / sd[k];
+    for (int o = tid; o < Hp; o += kThreads) {
+        float z = b1[o];
+#pragma unroll
+        for (int k = 0; k < NS + 2; ++k) z = fmaf(W1[o * nin + k], x[k], z);
+        a1[o] = gelu_f(z);
+    }
+    __syncthreads();
+    for (int o = tid; o < Hp; o += kThreads) {
+        float z = b2[o];
+        for (int k = 0; k < Hp; ++k) z = fmaf(W2[(int64_t)o * Hp + k], a1[k], z);
+        a2[o] = gelu_f(z);
+    }
+    __syncthreads();
+    for (int o = tid; o < m * NS; o += kThreads) {
+        float z = b3[o];
+        for (int k = 0; k < Hp; ++k) z = fmaf(W3[(int64_t)o * Hp + k], a2[k], z);
+        out[o] = z;
+    }
+    __syncthreads();
+}
+
+// I + F = (I - dt J)^{-1} with F = (I - dt J)^{-1} (dt J), J a row-major block in
+// LDS (read twice instead of being held in registers).  F^T if TRANSPOSE.
+template <bool TRANSPOSE>
+__device__ __forceinline__ bool block_inverse_plus(const float *J, float dt, float (&F)[NS][NS])
+{
+    float D[NS][NS], X[NS][NS];
+#pragma unroll
+    for (int r = 0; r < NS; ++r)
+#pragma unroll
+        for (int c = 0; c < NS; ++c) D[r][c] = ((r == c) ? 1.f : 0.f) - dt * J[r * NS + c];
+    const bool ok = invert(D, X);
+#pragma unroll
+    for (int r = 0; r < NS; ++r)
+#pragma unroll
+        for (int c = 0; c < NS; ++c) {
+            float acc = 0.f;
+#pragma unroll
+            for (int l = 0; l < NS; ++l) acc = fmaf(X[r][l], dt * J[l * NS + c], acc);
+            if (TRANSPOSE) F[c][r] = acc;
+            else F[r][c] = acc;
+        }
+    return ok;
+}
+
+// Backward Euler from step s0 (state ys) to s_end in attempts that never cross
+// a multiple of C.  Every thread of the block calls it; returns the status.
+template <class IO, class Sink>
+__device__ int mlp_solve(MlpShared &S, const SolveArgs<IO> &a, const IO *t, double (&ys)[NS], int64_t s0,
+                         int64_t s_end, int &total, const Sink &sink)
+{
     const int tid = threadIdx.x, w = tid / kWave, l = lane_id();
     const int j = kSPW * w + (l & (kSPW - 1));   // step of the chunk owned by this lane (0-based)
     const bool writer = l < kSPW;                 // lanes 32..63 duplicate lanes 0..31
-    const int64_t b = blockIdx.x;
-    const SeriesView<IO> sv(a, b);
     const int C = a.chunk;
-
-    load_weights(S.W, a.params);
-    double ys[NS];
-#pragma unroll
-    for (int k = 0; k < NS; ++k) ys[k] = ld(a.y0 + b * NS + k);
-    IO *yb = a.y ? a.y + sv.p0 * NS : nullptr;
-    double *ck = a.ckpt ? a.ckpt + b * a.K * NS : nullptr;
-    if (tid < NS) {
-        if (yb) st(yb + tid, ys[tid]);
-        if (ck) ck[tid] = ys[tid];
-    }
-    __syncthreads();
-
-    int64_t s = 0;
-    int mcur = C, m = 0, it = 0, total = 0, status = ST_OK;
+    int64_t s = s0;
+    int mcur = C, m = 0, it = 0, status = ST_OK, accepted = 0;
     bool start = true, sing = false;
-    float nrm0 = 0.f, dy[NS], tj = 0.f, hj = 0.f;
+    float nrm0 = 0.f, dy[NS], hj = 0.f;
     Acts A;
-    while (s < sv.Nb) {
+    while (s < s_end) {
         if (start) {
-            const int64_t nom_end = min((s / C + 1) * (int64_t)C, sv.Nb);
+            const int64_t nom_end = min((s / C + 1) * (int64_t)C, s_end);
             m = (int)min((int64_t)mcur, nom_end - s);
             const bool v = j < m;
-            const double ts = ld(sv.t + s);
-            const double t1 = ld(sv.t + (v ? s + j + 1 : s)), t0 = ld(sv.t + (v ? s + j : s));
+            const double ts = ld(t + s);
+            const double t1 = ld(t + (v ? s + j + 1 : s)), t0 = ld(t + (v ? s + j : s));
             hj = (float)(t1 - t0);
-            tj = (float)(t1 - ts);
+            const float tj = (float)(t1 - ts);
 #pragma unroll
             for (int k = 0; k < NS; ++k) dy[k] = 0.f;
-            if (a.init == INIT_EXTRAP) {
+            if (a.init == INIT_EXTRAP || a.init == INIT_PREDICTOR) {
                 // the slope of the last step: h(y_s) for backward Euler
                 if (writer) {
 #pragma unroll
@@ -96,6 +255,23 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(SolveArgs<IO> a)
                     for (int k = 0; k < NS; ++k) dy[k] = tj * S.f[j][k];
                 }
             }
+            if (a.init == INIT_PREDICTOR) {
+                // the learned start: the extrapolated slope plus the predicted correction,
+                // kept only if its residual is below the extrapolation's
+                float *scratch = &S.u.v.a[0][0][0];
+                predictor_slopes(scratch, scratch + 256, scratch + 512, a.pred, a.pred_hidden, a.pred_steps, ys, ts,
+                                 ld(t + s + 1) - ts, m);
+                float dyp[NS];
+#pragma unroll
+                for (int k = 0; k < NS; ++k) dyp[k] = v ? dy[k] + tj * scratch[512 + j * NS + k] : 0.f;
+                const float n_ext = chunk_residual_norm(S, ys, dy, hj, v);
+                const float n_pred = chunk_residual_norm(S, ys, dyp, hj, v);
+                if (n_pred < n_ext) {
+#pragma unroll
+                    for (int k = 0; k < NS; ++k) dy[k] = dyp[k];
+                    ++accepted;
+                }
+            }
             it = 0;
             sing = false;
             start = false;
@@ -103,27 +279,8 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(SolveArgs<IO> a)
         const bool v = j < m;
 
         // ---- residual of the current iterate
-        if (writer) {
-#pragma unroll
-            for (int k = 0; k < NS; ++k) {
-                S.y[j][k] = (float)(ys[k] + (double)dy[k]);
-                S.dy[j][k] = dy[k];
-            }
-        }
-        __syncthreads();
-        mlp_rates(S, A);
-        __syncthreads();
-        float R[NS], acc = 0.f;
-#pragma unroll
-        for (int k = 0; k < NS; ++k) {
-            const float prev = j > 0 ? S.dy[j - 1][k] : 0.f;
-            R[k] = v ? (dy[k] - prev) - hj * S.f[j][k] : 0.f;
-            acc = fmaf(R[k], R[k], acc);
-        }
-        acc = seg_sum<kSPW>(acc);
-        if (l == 0) S.red[w] = acc;
-        __syncthreads();
-        const float nrm = sqrtf(S.red[0] + S.red[1] + S.red[2] + S.red[3]);
+        float R[NS];
+        const float nrm = chunk_residual(S, A, ys, dy, hj, v, R);
 
         int act, code = ST_OK;
         if (it == 0) nrm0 = nrm;
@@ -134,17 +291,11 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(SolveArgs<IO> a)
         else act = 3;
 
         if (act == 1) {
-            if (writer && v && yb) {
-#pragma unroll
-                for (int k = 0; k < NS; ++k) st(yb + (s + j + 1) * NS + k, ys[k] + (double)dy[k]);
-            }
+            if (writer && v) sink.put(s + j + 1, ys, dy);
 #pragma unroll
             for (int k = 0; k < NS; ++k) ys[k] += (double)S.dy[m - 1][k];
             s += m;
-            if ((s % C == 0 || s >= sv.Nb) && ck && tid < NS) {
-                const int64_t c = (s + C - 1) / C;
-                if (c < a.K) ck[c * NS + tid] = ys[tid];
-            }
+            if (s % C == 0 || s >= s_end) sink.boundary(s, ys, tid);
             if (s % C == 0) mcur = C;
             start = true;
             __syncthreads();
@@ -158,37 +309,23 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(SolveArgs<IO> a)
                 continue;
             }
             status = code;
-            if (yb) {
-                const double nan = __builtin_nan("");
-                for (int64_t k = s + 1 + tid; k <= sv.Nb; k += kThreads)
-#pragma unroll
-                    for (int e = 0; e < NS; ++e) st(yb + k * NS + e, nan);
-            }
+            sink.fail(s, tid);
             break;
         }
 
         // ---- Newton correction
-        {
-            const int r = l & 15;
-            jacobian<false>(S.W, A, [&](int u, int row, int c, float val) {
-                S.J[kSPW * w + 16 * u + r][row * NS + c] = val;
-            });
-        }
+        mlp_jacobians(S, A, false);
         __syncthreads();
-        Affine<NS, float> map;
+        AffineI<NS, float> map;
         affine_identity(map);
         int ok = 1;
         if (v) {
-            float D[NS][NS];
-#pragma unroll
-            for (int r = 0; r < NS; ++r)
-#pragma unroll
-                for (int c = 0; c < NS; ++c) D[r][c] = ((r == c) ? 1.f : 0.f) - hj * S.J[j][r * NS + c];
-            ok = invert(D, map.M) ? 1 : 0;
+            // (I - dt J)^{-1} = I + F; the correction map x -> (I + F)(x - R)
+            ok = block_inverse_plus<false>(S.u.J[j], hj, map.F) ? 1 : 0;
             float negR[NS], zero[NS];
 #pragma unroll
             for (int k = 0; k < NS; ++k) { negR[k] = -R[k]; zero[k] = 0.f; }
-            matvec_add(map.M, negR, zero, map.z);
+            apply_ip(map.F, negR, zero, map.z);
         }
         seg_scan_up<NS, kSPW>(map);
         ok = seg_and<kWave>(ok);
@@ -196,7 +333,7 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(SolveArgs<IO> a)
 #pragma unroll
             for (int r = 0; r < NS; ++r) {
 #pragma unroll
-                for (int c = 0; c < NS; ++c) S.wmap[w][r * NS + c] = map.M[r][c];
+                for (int c = 0; c < NS; ++c) S.wmap[w][r * NS + c] = map.F[r][c];
                 S.wmap[w][NS * NS + r] = map.z[r];
             }
         }
@@ -207,20 +344,20 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(SolveArgs<IO> a)
 #pragma unroll
         for (int k = 0; k < NS; ++k) vin[k] = 0.f;
         for (int q = 0; q < w; ++q) {
-            float t[NS];
+            float tv[NS];
 #pragma unroll
             for (int r = 0; r < NS; ++r) {
                 float acc2 = S.wmap[q][NS * NS + r];
 #pragma unroll
                 for (int c = 0; c < NS; ++c) acc2 = fmaf(S.wmap[q][r * NS + c], vin[c], acc2);
-                t[r] = acc2;
+                tv[r] = acc2 + vin[r];
             }
 #pragma unroll
-            for (int k = 0; k < NS; ++k) vin[k] = t[k];
+            for (int k = 0; k < NS; ++k) vin[k] = tv[k];
         }
         if (v) {
             float d[NS];
-            matvec_add(map.M, vin, map.z, d);
+            apply_ip(map.F, vin, map.z, d);
 #pragma unroll
             for (int k = 0; k < NS; ++k) dy[k] += d[k];
         }
@@ -230,10 +367,328 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(SolveArgs<IO> a)
         if (!all_ok) sing = true;
         __syncthreads();
     }
+    __syncthreads();
+    (void)accepted;
+    return status;
+}
+
+template <class IO>
+__global__ __launch_bounds__(kThreads) void mlp_forward_kernel(SolveArgs<IO> a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    MlpShared &S = *reinterpret_cast<MlpShared *>(smem);
+    const int tid = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    const SeriesView<IO> sv(a, b);
+
+    load_weights(S.W, a.params);
+    double ys[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) ys[k] = ld(a.y0 + b * NS + k);
+    MlpTrajectorySink<IO> sink{a.y ? a.y + sv.p0 * NS : nullptr, a.ckpt ? a.ckpt + b * a.K * NS : nullptr, a.K,
+                               sv.Nb, a.chunk};
+    if (tid < NS && sink.y) st(sink.y + tid, ys[tid]);
+    sink.boundary(0, ys, tid);
+    __syncthreads();
+    int total = 0;
+    const int status = mlp_solve(S, a, sv.t, ys, 0, sv.Nb, total, sink);
     if (tid == 0) {
         a.status[b] = status;
         if (a.iters) a.iters[b] = total;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint
+// ---------------------------------------------------------------------------
+
+// Gradient accumulators of one wave, in accumulator layout.
+struct GradAcc {
+    f32x4 w3[5];      // dW3 (rows 0..7 of tiles 0..3) and db3 (column 0 of tile 4)
+    f32x4 w2[4][5];   // dW2 (tiles 0..3) and db2 (column 0 of tile 4)
+    f32x4 w1[4];      // dW1 (columns 0..7) and db1 (column 8)
+};
+
+template <class IO, bool RECOMPUTE>
+__global__ __launch_bounds__(kThreads) void mlp_adjoint_kernel(SolveArgs<IO> a, float *theta_partial)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    MlpShared &S = *reinterpret_cast<MlpShared *>(smem);
+    const int tid = threadIdx.x, w = tid / kWave, l = lane_id(), g = l >> 4, r = l & 15;
+    const int j = kSPW * w + (l & (kSPW - 1));
+    const bool writer = l < kSPW;
+    const int64_t b = blockIdx.x;
+    const SeriesView<IO> sv(a, b);
+    const int C = a.chunk;
+    const IO *gb = a.g + sv.p0 * NS;
+
+    load_weights(S.W, a.params);
+    if (tid < NS) S.lam[tid] = 0.f;
+    GradAcc G;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) G.w3[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        G.w1[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int i = 0; i < 5; ++i) G.w2[mt][i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    __syncthreads();
+    int status = ST_OK;
+    const int64_t nck = (sv.Nb + C - 1) / C;
+    for (int64_t c = nck - 1; c >= 0; --c) {
+        const int64_t c0 = c * C;
+        const int m = (int)min((int64_t)C, sv.Nb - c0);
+        const bool v = j < m;
+        // ---- the chunk's converged states
+        if (RECOMPUTE) {
+            double ys[NS];
+#pragma unroll
+            for (int k = 0; k < NS; ++k) ys[k] = c < a.K ? a.ckpt[(b * a.K + c) * NS + k] : __builtin_nan("");
+            int total = 0;
+            const int st2 = mlp_solve(S, a, sv.t, ys, c0, c0 + m, total, MlpChunkSink{S.yc, c0});
+            if (st2 != ST_OK && status == ST_OK) status = st2;
+        } else if (writer) {
+#pragma unroll
+            for (int k = 0; k < NS; ++k) S.yc[j][k] = v ? (float)ld(a.y + (sv.p0 + c0 + j + 1) * NS + k) : 0.f;
+        }
+        __syncthreads();
+        if (writer) {
+#pragma unroll
+            for (int k = 0; k < NS; ++k) S.y[j][k] = v ? S.yc[j][k] : 0.f;
+        }
+        __syncthreads();
+        Acts A;
+        mlp_rates(S, A);
+        mlp_jacobians(S, A, true);
+        __syncthreads();
+
+        // ---- transposed blocks and the reduction from the last step down
+        const double t1 = ld(sv.t + (v ? c0 + j + 1 : c0)), t0 = ld(sv.t + (v ? c0 + j : c0));
+        const float hj = (float)(t1 - t0);
+        AffineI<NS, float> map;
+        affine_identity(map);
+        int ok = 1;
+        if (v) {
+            // (I - dt J)^{-T} = I + F^T
+            float gk[NS], zero[NS];
+            ok = block_inverse_plus<true>(S.u.J[j], hj, map.F) ? 1 : 0;
+#pragma unroll
+            for (int k = 0; k < NS; ++k) { gk[k] = (float)ld(gb + (c0 + j + 1) * NS + k); zero[k] = 0.f; }
+            apply_ip(map.F, gk, zero, map.z);
+        }
+        seg_scan_down<NS, kSPW>(map);
+        ok = seg_and<kWave>(ok);
+        if (l == 0) {
+#pragma unroll
+            for (int rr = 0; rr < NS; ++rr) {
+#pragma unroll
+                for (int cc = 0; cc < NS; ++cc) S.wmap[w][rr * NS + cc] = map.F[rr][cc];
+                S.wmap[w][NS * NS + rr] = map.z[rr];
+            }
+            S.flag[w] = ok;
+        }
+        __syncthreads();
+        float lin[NS];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) lin[k] = S.lam[k];
+        for (int q = kWaves - 1; q > w; --q) {
+            float tv[NS];
+#pragma unroll
+            for (int rr = 0; rr < NS; ++rr) {
+                float acc2 = S.wmap[q][NS * NS + rr];
+#pragma unroll
+                for (int cc = 0; cc < NS; ++cc) acc2 = fmaf(S.wmap[q][rr * NS + cc], lin[cc], acc2);
+                tv[rr] = acc2 + lin[rr];
+            }
+#pragma unroll
+            for (int k = 0; k < NS; ++k) lin[k] = tv[k];
+        }
+        float lam_j[NS];
+        apply_ip(map.F, lin, map.z, lam_j);
+        if (!(S.flag[0] & S.flag[1] & S.flag[2] & S.flag[3]) && status == ST_OK) status = ST_SINGULAR;
+        __syncthreads();
+        // v_j = dt_j lam_j (zero beyond the chunk) into S.f; lam of the chunk's first step carried
+        if (writer) {
+#pragma unroll
+            for (int k = 0; k < NS; ++k) S.f[j][k] = v ? hj * lam_j[k] : 0.f;
+        }
+        if (tid == 0) {
+#pragma unroll
+            for (int k = 0; k < NS; ++k) S.lam[k] = lam_j[k];
+        }
+
+        // ---- back-propagation of v through the network (per wave, its 32 samples)
+        // activations a2, sample-major
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) S.u.v.a[w][16 * u + r][16 * mt + 4 * g + i] = A.a2[mt][u][i];
+        __syncthreads();
+        // dW3 += v a2^T (M = state rows, K = samples, N = hidden), db3 from a ones column
+        {
+            float av[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) av[e] = r < NS ? S.f[kSPW * w + 8 * g + e][r & (NS - 1)] : 0.f;
+            const Split as = split8(av);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                float bv[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) bv[e] = S.u.v.a[w][8 * g + e][16 * nt + r];
+                G.w3[nt] = mma_acc<true>(as, split8(bv), G.w3[nt]);
+            }
+            float ones[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) ones[e] = r == 0 ? 1.f : 0.f;
+            G.w3[4] = mma_acc<true>(as, split8(ones), G.w3[4]);
+        }
+        // delta2 = (W3^T v) * (1 - a2^2): M = hidden, K = state rows (k = 8 g + e < 8), N = samples
+        f32x4 d2[4][2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            float bv[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) bv[e] = g == 0 ? S.f[kSPW * w + 16 * u + r][e] : 0.f;
+            const Split bs = split8(bv);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                f32x4 z = mma_acc<true>(split_lds(S.W.w3t[mt][l]), bs, f32x4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+                for (int i = 0; i < 4; ++i) d2[mt][u][i] = z[i] * (1.f - A.a2[mt][u][i] * A.a2[mt][u][i]);
+            }
+        }
+        __syncthreads();
+        // a1 and delta2, sample-major
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    S.u.v.a[w][16 * u + r][16 * mt + 4 * g + i] = A.a1[mt][u][i];
+                    S.u.v.d[w][16 * u + r][16 * mt + 4 * g + i] = d2[mt][u][i];
+                }
+        __syncthreads();
+        // dW2 += delta2 a1^T, db2 from a ones column
+        {
+            float ones[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) ones[e] = r == 0 ? 1.f : 0.f;
+            const Split os = split8(ones);
+            Split bsn[4];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                float bv[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) bv[e] = S.u.v.a[w][8 * g + e][16 * nt + r];
+                bsn[nt] = split8(bv);
+            }
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                float av[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) av[e] = S.u.v.d[w][8 * g + e][16 * mt + r];
+                const Split as = split8(av);
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) G.w2[mt][nt] = mma_acc<true>(as, bsn[nt], G.w2[mt][nt]);
+                G.w2[mt][4] = mma_acc<true>(as, os, G.w2[mt][4]);
+            }
+        }
+        // delta1 = (W2^T delta2) * (1 - a1^2), with delta2 chained from its accumulators
+        f32x4 d1[4][2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            Split bk[2];
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                float bv[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) bv[e] = d2[2 * ks + (e >> 2)][u][e & 3];
+                bk[ks] = split8(bv);
+            }
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                f32x4 z = mma_acc<true>(split_lds(S.W.w2t[mt][0][l]), bk[0], f32x4{0.f, 0.f, 0.f, 0.f});
+                z = mma_acc<true>(split_lds(S.W.w2t[mt][1][l]), bk[1], z);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) d1[mt][u][i] = z[i] * (1.f - A.a1[mt][u][i] * A.a1[mt][u][i]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) S.u.v.d[w][16 * u + r][16 * mt + 4 * g + i] = d1[mt][u][i];
+        __syncthreads();
+        // dW1 += delta1 y^T (columns 0..7), db1 from column 8 (ones)
+        {
+            float bv[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int smp = kSPW * w + 8 * g + e;
+                bv[e] = r < NS ? S.y[smp][r & (NS - 1)] : (r == NS ? 1.f : 0.f);
+            }
+            const Split bs = split8(bv);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                float av[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) av[e] = S.u.v.d[w][8 * g + e][16 * mt + r];
+                G.w1[mt] = mma_acc<true>(split8(av), bs, G.w1[mt]);
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- dL/dy0 = g_0 + lam_1, and the series' parameter gradient (waves summed in order)
+    if (tid < NS) st(a.dLdy0 + b * NS + tid, status == ST_OK ? ld(gb + tid) + (double)S.lam[tid] : __builtin_nan(""));
+    for (int idx = tid; idx < P; idx += kThreads) S.u.theta[idx] = 0.f;
+    __syncthreads();
+    for (int q = 0; q < kWaves; ++q) {
+        if (w == q) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = 4 * g + i;
+                if (row < NS) {
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) S.u.theta[oW3 + row * H + 16 * nt + r] += G.w3[nt][i];
+                    if (r == 0) S.u.theta[ob3 + row] += G.w3[4][i];
+                }
+            }
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int mrow = 16 * mt + 4 * g + i;
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) S.u.theta[oW2 + mrow * H + 16 * nt + r] += G.w2[mt][nt][i];
+                    if (r == 0) S.u.theta[ob2 + mrow] += G.w2[mt][4][i];
+                    if (r < NS) S.u.theta[oW1 + mrow * NS + r] += G.w1[mt][i];
+                    if (r == NS) S.u.theta[ob1 + mrow] += G.w1[mt][i];
+                }
+        }
+        __syncthreads();
+    }
+    const float nanf_ = __builtin_nanf("");
+    for (int idx = tid; idx < P; idx += kThreads)
+        theta_partial[b * P + idx] = status == ST_OK ? S.u.theta[idx] : nanf_;
+    if (tid == 0) a.status[b] = status;
+}
+
+// dL/dtheta = sum over series of the partials, in series order.
+template <class IO>
+__global__ void mlp_theta_reduce_kernel(int64_t B, const float *partial, IO *out)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    double s = 0.0;
+    for (int64_t b = 0; b < B; ++b) s += (double)partial[b * P + p];
+    st(out + p, s);
 }
 
 // h(y) and dh/dy for M independent states: 128 states per workgroup.
@@ -243,7 +698,7 @@ __global__ __launch_bounds__(kThreads) void mlp_eval_kernel(int64_t M, const IO 
 {
     extern __shared__ __align__(16) unsigned char smem[];
     MlpShared &S = *reinterpret_cast<MlpShared *>(smem);
-    const int tid = threadIdx.x, w = tid / kWave, l = lane_id(), r = l & 15;
+    const int tid = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * kMaxChunk;
     load_weights(S.W, params);
     for (int idx = tid; idx < kMaxChunk * NS; idx += kThreads) {
@@ -253,9 +708,7 @@ __global__ __launch_bounds__(kThreads) void mlp_eval_kernel(int64_t M, const IO 
     __syncthreads();
     Acts A;
     mlp_rates(S, A);
-    jacobian<true>(S.W, A, [&](int u, int row, int c, float val) {
-        S.J[kSPW * w + 16 * u + r][row * NS + c] = val;
-    });
+    mlp_jacobians(S, A, true);
     __syncthreads();
     for (int idx = tid; idx < kMaxChunk * NS; idx += kThreads) {
         const int64_t q = base + idx / NS;
@@ -263,29 +716,49 @@ __global__ __launch_bounds__(kThreads) void mlp_eval_kernel(int64_t M, const IO 
     }
     for (int idx = tid; idx < kMaxChunk * NS * NS; idx += kThreads) {
         const int64_t q = base + idx / (NS * NS);
-        if (q < M && J) J[q * NS * NS + idx % (NS * NS)] = (IO)S.J[idx / (NS * NS)][idx % (NS * NS)];
+        if (q < M && J) J[q * NS * NS + idx % (NS * NS)] = (IO)S.u.J[idx / (NS * NS)][idx % (NS * NS)];
     }
 }
 
-size_t mlp_shared_bytes() { return sizeof(MlpShared); }
+template <class K>
+static bool allow_lds(K kernel)
+{
+    return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)sizeof(MlpShared)) == hipSuccess;
+}
+
+size_t mlp_theta_workspace_bytes(int64_t B) { return (size_t)B * P * sizeof(float); }
 
 template <class IO>
 static tvi_status mlp_launch(int pass, const SolveArgs<IO> &a, hipStream_t stream)
 {
     if (a.B == 0) return TVI_OK;
+    if (a.B > 0x7fffffffLL) return TVI_EINVAL;
     const size_t shm = sizeof(MlpShared);
-    if (pass == PASS_FORWARD) {
-        static bool attr = false;
-        if (!attr) {
-            if (hipFuncSetAttribute((const void *)mlp_forward_kernel<IO>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)shm) != hipSuccess)
-                return TVI_EHIP;
-            attr = true;
+    const dim3 grid((unsigned)a.B), block(kThreads);
+    switch (pass) {
+    case PASS_FORWARD:
+        if (!allow_lds(mlp_forward_kernel<IO>)) return TVI_EHIP;
+        hipLaunchKernelGGL(mlp_forward_kernel<IO>, grid, block, shm, stream, a);
+        break;
+    case PASS_ADJOINT:
+    case PASS_ADJOINT_RECOMPUTE: {
+        float *partial = reinterpret_cast<float *>(a.ws);
+        if (pass == PASS_ADJOINT) {
+            if (!allow_lds(mlp_adjoint_kernel<IO, false>)) return TVI_EHIP;
+            hipLaunchKernelGGL((mlp_adjoint_kernel<IO, false>), grid, block, shm, stream, a, partial);
+        } else {
+            if (!allow_lds(mlp_adjoint_kernel<IO, true>)) return TVI_EHIP;
+            hipLaunchKernelGGL((mlp_adjoint_kernel<IO, true>), grid, block, shm, stream, a, partial);
         }
-        hipLaunchKernelGGL(mlp_forward_kernel<IO>, dim3((unsigned)a.B), dim3(kThreads), shm, stream, a);
-        return hipGetLastError() == hipSuccess ? TVI_OK : TVI_EHIP;
+        if (hipGetLastError() != hipSuccess) return TVI_EHIP;
+        hipLaunchKernelGGL(mlp_theta_reduce_kernel<IO>, dim3((P + 255) / 256), dim3(256), 0, stream, a.B,
+                           (const float *)partial, a.dLdp);
+        break;
     }
-    return TVI_EUNSUPPORTED;
+    default: return TVI_EINVAL;
+    }
+    return hipGetLastError() == hipSuccess ? TVI_OK : TVI_EHIP;
 }
 
 tvi_status launch_mlp(int pass, int dtype, const void *args, hipStream_t stream)
@@ -302,14 +775,12 @@ tvi_status launch_mlp_eval(int dtype, int64_t M, const void *states, const void 
     const int64_t blocks = (M + kMaxChunk - 1) / kMaxChunk;
     if (blocks > 0x7fffffffLL) return TVI_EINVAL;
     if (dtype == TVI_F64) {
-        hipFuncSetAttribute((const void *)mlp_eval_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)shm);
+        if (!allow_lds(mlp_eval_kernel<double>)) return TVI_EHIP;
         hipLaunchKernelGGL(mlp_eval_kernel<double>, dim3((unsigned)blocks), dim3(kThreads), shm, stream, M,
                            static_cast<const double *>(states), static_cast<const double *>(params),
                            static_cast<double *>(f), static_cast<double *>(J));
     } else {
-        hipFuncSetAttribute((const void *)mlp_eval_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)shm);
+        if (!allow_lds(mlp_eval_kernel<float>)) return TVI_EHIP;
         hipLaunchKernelGGL(mlp_eval_kernel<float>, dim3((unsigned)blocks), dim3(kThreads), shm, stream, M,
                            static_cast<const float *>(states), static_cast<const float *>(params),
                            static_cast<float *>(f), static_cast<float *>(J));

@@ -14,86 +14,122 @@
 
 namespace tvi {
 
+template <int N, class IO, int T>
+struct Rows {
+    double D[T][N][N], r[T][N];
+};
+
+// Streamed (non-temporal) loads of a lane's T rows: the data is used once.
+template <int N, class IO, int S, int T, bool TR>
+__device__ __forceinline__ void load_rows(Rows<N, IO, T> &v, const IO *__restrict__ D, const IO *__restrict__ r,
+                                          int64_t b, int m, int q)
+{
+    const IO *Db = D + b * (int64_t)m * N * N;
+    const IO *rb = r + b * (int64_t)m * N;
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+        const int j = q * T + i;
+        const bool ok = j < m;
+        const int jj = ok ? j : 0;
+#pragma unroll
+        for (int e = 0; e < N; ++e) {
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+                const double val = (double)__builtin_nontemporal_load(Db + ((int64_t)jj * N + e) * N + c);
+                if (TR) v.D[i][c][e] = val;
+                else v.D[i][e][c] = val;
+            }
+            v.r[i][e] = (double)__builtin_nontemporal_load(rb + (int64_t)jj * N + e);
+        }
+    }
+}
+
+// Grid-stride over systems; the rows of the next system are loaded before the
+// current one is reduced, so every wave keeps loads in flight.
 template <int N, class IO, int S, int T, bool TR>
 __global__ __launch_bounds__(kWave) void pcr_kernel(int64_t B, int m, const IO *__restrict__ D,
                                                    const IO *__restrict__ r, IO *__restrict__ x)
 {
     const int lane = lane_id();
     const int q = lane & (S - 1);
-    const int64_t b = (int64_t)blockIdx.x * (kWave / S) + lane / S;
-    const bool valid = b < B;
-    const IO *Db = D + (valid ? b : 0) * (int64_t)m * N * N;
-    const IO *rb = r + (valid ? b : 0) * (int64_t)m * N;
+    const int64_t per_block = kWave / S;
+    const int64_t stride = (int64_t)gridDim.x * per_block;
+    int64_t b = (int64_t)blockIdx.x * per_block + lane / S;
 
-    double Mi[T][N][N], zi[T][N];
-    Affine<N> map;
-    affine_identity(map);
-    int ok = 1;
+    // prefetching doubles the row registers: only where they are few
+    constexpr bool kPrefetch = T * (N * N + N) <= 24;
+    Rows<N, IO, T> next;
+    if (kPrefetch && b < B) load_rows<N, IO, S, T, TR>(next, D, r, b, m, q);
+    for (int64_t b0 = (int64_t)blockIdx.x * per_block; b0 < B; b0 += stride, b += stride) {
+        const bool valid = b < B;
+        Rows<N, IO, T> cur;
+        if (kPrefetch) {
+            cur = next;
+            if (b + stride < B) load_rows<N, IO, S, T, TR>(next, D, r, b + stride, m, q);
+        } else if (valid) {
+            load_rows<N, IO, S, T, TR>(cur, D, r, b, m, q);
+        }
+
+        double Mi[T][N][N], zi[T][N];
+        Affine<N> map;
+        affine_identity(map);
+        int ok = 1;
 #pragma unroll
-    for (int u = 0; u < T; ++u) {
-        const int i = TR ? T - 1 - u : u;  // composition order: along the recurrence
-        const int j = q * T + i;
-        if (valid && j < m) {
-            double A[N][N], rv[N];
+        for (int u = 0; u < T; ++u) {
+            const int i = TR ? T - 1 - u : u;  // composition order: along the recurrence
+            const int j = q * T + i;
+            if (valid && j < m) {
+                ok &= invert(cur.D[i], Mi[i]) ? 1 : 0;
+                const double zero[N] = {};
+                matvec_add(Mi[i], cur.r[i], zero, zi[i]);
+                Affine<N> stp;
 #pragma unroll
-            for (int e = 0; e < N; ++e) {
+                for (int e = 0; e < N; ++e) {
 #pragma unroll
-                for (int c = 0; c < N; ++c) {
-                    const double v = ld(Db + ((int64_t)j * N + e) * N + c);
-                    if (TR) A[c][e] = v;
-                    else A[e][c] = v;
+                    for (int c = 0; c < N; ++c) stp.M[e][c] = Mi[i][e][c];
+                    stp.z[e] = zi[i][e];
                 }
-                rv[e] = ld(rb + (int64_t)j * N + e);
+                affine_after(stp, map);
+                map = stp;
             }
-            ok &= invert(A, Mi[i]) ? 1 : 0;
-            const double zero[N] = {};
-            matvec_add(Mi[i], rv, zero, zi[i]);
-            Affine<N> stp;
+        }
+        double din[N];
+        if (!TR) {
+            seg_scan_up<N, S>(map);
+            vec_read(map.z, q > 0 ? lane - 1 : lane, din);
+            if (q == 0) {
 #pragma unroll
-            for (int e = 0; e < N; ++e) {
-#pragma unroll
-                for (int c = 0; c < N; ++c) stp.M[e][c] = Mi[i][e][c];
-                stp.z[e] = zi[i][e];
+                for (int e = 0; e < N; ++e) din[e] = 0.0;
             }
-            affine_after(stp, map);
-            map = stp;
+        } else {
+            seg_scan_down<N, S>(map);
+            vec_read(map.z, q < S - 1 ? lane + 1 : lane, din);
+            if (q == S - 1) {
+#pragma unroll
+                for (int e = 0; e < N; ++e) din[e] = 0.0;
+            }
         }
-    }
-    double din[N];
-    if (!TR) {
-        seg_scan_up<N, S>(map);
-        vec_read(map.z, q > 0 ? lane - 1 : lane, din);
-        if (q == 0) {
 #pragma unroll
-            for (int e = 0; e < N; ++e) din[e] = 0.0;
+        for (int u = 0; u < T; ++u) {
+            const int i = TR ? T - 1 - u : u;
+            const int j = q * T + i;
+            if (valid && j < m) {
+                matvec_add(Mi[i], din, zi[i], din);
+#pragma unroll
+                for (int e = 0; e < N; ++e) zi[i][e] = din[e];
+            }
         }
-    } else {
-        seg_scan_down<N, S>(map);
-        vec_read(map.z, q < S - 1 ? lane + 1 : lane, din);
-        if (q == S - 1) {
+        ok = seg_and<S>(ok);
+        const double nan = __builtin_nan("");
+        IO *xb = x + (valid ? b : 0) * (int64_t)m * N;
 #pragma unroll
-            for (int e = 0; e < N; ++e) din[e] = 0.0;
-        }
-    }
+        for (int i = 0; i < T; ++i) {
+            const int j = q * T + i;
+            if (valid && j < m) {
 #pragma unroll
-    for (int u = 0; u < T; ++u) {
-        const int i = TR ? T - 1 - u : u;
-        const int j = q * T + i;
-        if (valid && j < m) {
-            matvec_add(Mi[i], din, zi[i], din);
-#pragma unroll
-            for (int e = 0; e < N; ++e) zi[i][e] = din[e];
-        }
-    }
-    ok = seg_and<S>(ok);
-    const double nan = __builtin_nan("");
-    IO *xb = x + (valid ? b : 0) * (int64_t)m * N;
-#pragma unroll
-    for (int i = 0; i < T; ++i) {
-        const int j = q * T + i;
-        if (valid && j < m) {
-#pragma unroll
-            for (int e = 0; e < N; ++e) st(xb + (int64_t)j * N + e, ok ? zi[i][e] : nan);
+                for (int e = 0; e < N; ++e)
+                    __builtin_nontemporal_store((IO)(ok ? zi[i][e] : nan), xb + (int64_t)j * N + e);
+            }
         }
     }
 }
@@ -103,9 +139,11 @@ static tvi_status pcr_launch_st(int64_t B, int m, const void *D, const void *r, 
                                 hipStream_t stream)
 {
     const int64_t per_block = kWave / S;
-    const int64_t blocks = (B + per_block - 1) / per_block;
+    int64_t blocks = (B + per_block - 1) / per_block;
     if (blocks == 0) return TVI_OK;
-    if (blocks > 0x7fffffffLL) return TVI_EINVAL;
+    // enough waves to fill every SIMD several times; each then walks the batch
+    const int64_t resident = 256 * 4 * 8;
+    if (blocks > resident) blocks = resident;
     const IO *Dp = static_cast<const IO *>(D);
     const IO *rp = static_cast<const IO *>(r);
     IO *xp = static_cast<IO *>(x);

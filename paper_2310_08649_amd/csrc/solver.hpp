@@ -28,7 +28,7 @@
 namespace tvi {
 
 enum : int { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_SINGULAR = 2, ST_NONFINITE = 3 };
-enum : int { INIT_ZERO = 0, INIT_EXTRAP = 1 };
+enum : int { INIT_ZERO = 0, INIT_EXTRAP = 1, INIT_PREDICTOR = 2 };
 
 template <class IO>
 struct SolveArgs {
@@ -44,6 +44,8 @@ struct SolveArgs {
     const IO *g;               // adjoint: dL/dy
     IO *dLdp, *dLdy0;
     double *ws;                // adjoint recompute workspace [B][chunk][n]
+    const float *pred;         // learned chunk predictor parameters (INIT_PREDICTOR)
+    int32_t pred_hidden, pred_steps;
 };
 
 template <class IO>

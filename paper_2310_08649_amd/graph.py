@@ -1,0 +1,108 @@
+"""One captured HIP graph for a whole training step of a batch of series:
+chunked backward-Euler forward pass (with chunk-boundary checkpoints), the
+loss gradient, and the adjoint with recomputed interior states.
+
+Every buffer is allocated once, before capture, so a replay touches only
+device memory the graph owns; the launches are the library's kernels on the
+capture stream (no host synchronisation, no allocation, no memset inside).
+Ragged series (point offsets) run in the same launches as uniform ones.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import tvi
+
+LOSS = {"frobenius": 0, "mean_square": 1}
+
+
+class CapturedStep:
+    """forward -> loss gradient -> adjoint, captured once, replayed many times.
+
+    Inputs (y0, times, params, offsets) are the graph's own copies: call
+    ``set_inputs`` to change their values between replays.
+    """
+
+    def __init__(self, kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e-6), lanes=0, steps_per_lane=0,
+                 max_newton=50, init="zero", loss="frobenius", observed=None, n_max=None):
+        lib = tvi.load()
+        self.kind = kind
+        dt = y0.dtype
+        dev = y0.device
+        self.y0 = y0.detach().clone().contiguous()
+        self.times = times.detach().clone().contiguous()
+        self.params = params.detach().clone().contiguous()
+        self.offsets = None if offsets is None else offsets.detach().clone().contiguous()
+        B, n = self.y0.shape
+        if self.offsets is None:
+            N = self.times.shape[0] - 1
+            yshape = (B, N + 1, n)
+        else:
+            N = int(n_max if n_max is not None else (self.offsets[1:] - self.offsets[:-1]).max().item() - 1)
+            yshape = (self.times.shape[0], n)
+        self.B, self.n, self.N = B, n, N
+        shared = self.params.dim() == 1
+        self.model = tvi.Model(tvi.KINDS[kind], n, tvi._io_dtype(self.y0), 1 if shared else 0, 64)
+        self.opt = tvi.make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, True)
+        P = lib.tvi_param_count(ctypes.byref(self.model))
+        K = (N + chunk - 1) // chunk + 1
+        self.y = torch.empty(yshape, dtype=dt, device=dev)
+        self.ckpt = torch.empty((B, K, n), dtype=torch.float64, device=dev)
+        self.status_fwd = torch.empty(B, dtype=torch.int32, device=dev)
+        self.iters = torch.empty(B, dtype=torch.int32, device=dev)
+        self.g = torch.empty_like(self.y)
+        self.loss = torch.empty(1, dtype=torch.float64, device=dev)
+        self.loss_kind = LOSS[loss]
+        self.observed = None if observed is None else observed.to(device=dev, dtype=torch.uint8).contiguous()
+        self.n_observed = int(self.observed.sum().item()) if self.observed is not None else 0
+        self.loss_ws = torch.empty(max(1, lib.tvi_loss_workspace_bytes()), dtype=torch.uint8, device=dev)
+        self.dLdp = torch.empty((P,) if shared else (B, P), dtype=dt, device=dev)
+        self.dLdy0 = torch.empty((B, n), dtype=dt, device=dev)
+        self.status_adj = torch.empty(B, dtype=torch.int32, device=dev)
+        wsb = lib.tvi_adjoint_workspace_bytes(ctypes.byref(self.model), ctypes.byref(self.opt), B)
+        self.ws = torch.empty(max(1, wsb), dtype=torch.uint8, device=dev)
+        self.ws_bytes = wsb
+        self.graph = None
+        self.stream = torch.cuda.Stream(device=dev)
+
+    def set_inputs(self, y0=None, times=None, params=None):
+        for dst, src in ((self.y0, y0), (self.times, times), (self.params, params)):
+            if src is not None:
+                dst.copy_(src)
+
+    def _launch(self):
+        lib = tvi.load()
+        P = tvi._ptr
+        st = tvi._stream()
+        tvi._check(lib.tvi_solve_forward(ctypes.byref(self.model), ctypes.byref(self.opt), self.B, self.N,
+                                         P(self.offsets), P(self.times), P(self.y0), P(self.params), P(self.y),
+                                         P(self.ckpt), P(self.status_fwd), P(self.iters), st), "tvi_solve_forward")
+        tvi._check(lib.tvi_loss_grad(self.loss_kind, self.model.dtype, self.y.shape[0] * (self.y.numel() //
+                                     self.y.shape[0]) // self.n, self.n, P(self.y), P(self.observed),
+                                     self.n_observed, P(self.g), P(self.loss), P(self.loss_ws),
+                                     self.loss_ws.numel(), st), "tvi_loss_grad")
+        tvi._check(lib.tvi_solve_adjoint(ctypes.byref(self.model), ctypes.byref(self.opt), self.B, self.N,
+                                         P(self.offsets), P(self.times), P(self.params), None, P(self.ckpt),
+                                         P(self.g), P(self.dLdp), P(self.dLdy0), P(self.status_adj), P(self.ws),
+                                         self.ws_bytes, st), "tvi_solve_adjoint")
+
+    def run_eager(self):
+        """The same launches without a graph (on the current stream)."""
+        self._launch()
+
+    def capture(self):
+        # one eager run first: kernel attributes and lazy module loading happen outside capture
+        self._launch()
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph, stream=self.stream):
+            self._launch()
+        torch.cuda.synchronize()
+        return self
+
+    def replay(self):
+        if self.graph is None:
+            self.capture()
+        self.graph.replay()

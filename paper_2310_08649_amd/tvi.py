@@ -27,7 +27,7 @@ LIB_PATH = os.path.join(_HERE, "libtvi.so")
 
 KINDS = {"linear": 0, "vanderpol": 1, "robertson": 2, "mlp": 3}
 F32, F64 = 0, 1
-INIT = {"zero": 0, "extrap": 1}
+INIT = {"zero": 0, "extrap": 1, "predictor": 2}
 STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "SINGULAR", 3: "NONFINITE"}
 
 
@@ -43,7 +43,8 @@ class Model(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_int32), ("lanes", ctypes.c_int32), ("steps_per_lane", ctypes.c_int32),
                 ("max_newton", ctypes.c_int32), ("tol_a", ctypes.c_double), ("tol_r", ctypes.c_double),
-                ("init", ctypes.c_int32), ("halving", ctypes.c_int32)]
+                ("init", ctypes.c_int32), ("halving", ctypes.c_int32), ("predictor", ctypes.c_void_p),
+                ("predictor_hidden", ctypes.c_int32), ("predictor_steps", ctypes.c_int32)]
 
 
 _lib = None
@@ -76,6 +77,10 @@ def load():
         lib.tvi_adjoint_workspace_bytes.restype = sz
         lib.tvi_solve_adjoint.argtypes = [MP, OP, i64, i64, P, P, P, P, P, P, P, P, P, P, sz, P]
         lib.tvi_solve_adjoint.restype = i32
+        lib.tvi_loss_workspace_bytes.argtypes = []
+        lib.tvi_loss_workspace_bytes.restype = sz
+        lib.tvi_loss_grad.argtypes = [i32, i32, i64, i32, P, P, i64, P, P, P, sz, P]
+        lib.tvi_loss_grad.restype = i32
         _lib = lib
     return _lib
 
@@ -115,7 +120,8 @@ def param_count(kind, n, hidden=64):
 
 
 def make_options(chunk=64, tol=(1e-8, 1e-6), max_newton=50, lanes=0, steps_per_lane=0, init="zero",
-                 halving=True):
+                 halving=True, predictor=None):
+    """``predictor``: (params tensor, hidden, steps) of a trained chunk predictor."""
     o = Options()
     load().tvi_default_options(ctypes.byref(o))
     o.chunk = int(chunk)
@@ -124,6 +130,10 @@ def make_options(chunk=64, tol=(1e-8, 1e-6), max_newton=50, lanes=0, steps_per_l
     o.lanes, o.steps_per_lane = int(lanes), int(steps_per_lane)
     o.init = INIT[init] if isinstance(init, str) else int(init)
     o.halving = 1 if halving else 0
+    if predictor is not None:
+        params, hidden, steps = predictor
+        o.predictor = ctypes.c_void_p(params.data_ptr())
+        o.predictor_hidden, o.predictor_steps = int(hidden), int(steps)
     return o
 
 
@@ -169,7 +179,8 @@ def _geometry(y0, times, offsets):
 
 
 def solve_forward(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e-6), max_newton=50, lanes=0,
-                  steps_per_lane=0, init="zero", halving=True, checkpoints=False, y_out=None, iters=True):
+                  steps_per_lane=0, init="zero", halving=True, checkpoints=False, y_out=None, iters=True,
+                  predictor=None):
     """Chunked backward Euler.  Returns ``(y, status, iters, ckpt)`` (device tensors;
     ``iters`` and ``ckpt`` may be None).  Asynchronous: nothing is synchronised."""
     dt = y0.dtype
@@ -180,7 +191,7 @@ def solve_forward(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e
         offsets = _dev(offsets, torch.int64, "offsets")
     B, n, N, yshape = _geometry(y0, times, offsets)
     model = Model(KINDS[kind], n, _io_dtype(y0), 1 if params.dim() == 1 else 0, 64)
-    opt = make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, halving)
+    opt = make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, halving, predictor)
     dev = y0.device
     y = y_out if y_out is not None else torch.empty(yshape, dtype=dt, device=dev)
     status = torch.empty(B, dtype=torch.int32, device=dev)
@@ -196,7 +207,7 @@ def solve_forward(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e
 
 
 def solve_adjoint(kind, times, params, g, y=None, ckpt=None, offsets=None, chunk=64, tol=(1e-8, 1e-6),
-                  max_newton=50, lanes=0, steps_per_lane=0, init="zero", halving=True, n=None):
+                  max_newton=50, lanes=0, steps_per_lane=0, init="zero", halving=True, n=None, predictor=None):
     """Discrete adjoint.  Returns ``(dLdp [B,P], dLdy0 [B,n], status [B])``.
 
     States come from the trajectory ``y`` or, when ``y`` is None, are recomputed
@@ -217,18 +228,19 @@ def solve_adjoint(kind, times, params, g, y=None, ckpt=None, offsets=None, chunk
     else:
         B, n = offsets.shape[0] - 1, g.shape[1]
         N = int((offsets[1:] - offsets[:-1]).max().item()) - 1 if B else 0
-    if params.dim() != 2 or params.shape[0] != B:
-        raise TviError("the adjoint needs per-series parameters [B, P]")
-    model = Model(KINDS[kind], n, _io_dtype(g), 0, 64)
-    opt = make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, halving)
+    shared = params.dim() == 1
+    if not shared and (params.dim() != 2 or params.shape[0] != B):
+        raise TviError("parameters must be per series [B, P] or shared [P]")
+    model = Model(KINDS[kind], n, _io_dtype(g), 1 if shared else 0, 64)
+    opt = make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, halving, predictor)
     lib = load()
     dev = g.device
     P = lib.tvi_param_count(ctypes.byref(model))
-    dLdp = torch.empty((B, P), dtype=dt, device=dev)
+    dLdp = torch.empty((P,) if shared else (B, P), dtype=dt, device=dev)
     dLdy0 = torch.empty((B, n), dtype=dt, device=dev)
     status = torch.empty(B, dtype=torch.int32, device=dev)
     ws, wsb = None, 0
-    if y is None:
+    if y is None or kind == "mlp":
         wsb = lib.tvi_adjoint_workspace_bytes(ctypes.byref(model), ctypes.byref(opt), B)
         ws = torch.empty(max(1, wsb), dtype=torch.uint8, device=dev)
     _check(lib.tvi_solve_adjoint(ctypes.byref(model), ctypes.byref(opt), B, N, _ptr(offsets), _ptr(times),

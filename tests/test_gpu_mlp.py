@@ -94,3 +94,69 @@ def test_mlp_forward_extrapolated_start_and_checkpoints(tvi):
     assert host(ie).sum() <= host(iz).sum()
     ck = ck.cpu().numpy()
     assert np.allclose(ck[:, 0], y0) and np.allclose(ck[:, -1], host(yz)[:, -1], rtol=1e-6, atol=1e-7)
+
+
+def _mlp_loss_grad(y, obs):
+    """L = mean over series, observed steps and components of y^2; g = dL/dy."""
+    B, n = y.shape[0], y.shape[2]
+    g = np.zeros_like(y)
+    g[:, obs] = 2.0 * y[:, obs] / (B * len(obs) * n)
+    return g
+
+
+@pytest.mark.parametrize("recompute", [True, False])
+def test_mlp_adjoint_matches_oracle(tvi, recompute):
+    w = W.mlp(B=8, N=2000)
+    y0, times, theta = (w[k].astype(np.float32) for k in ("y0", "times", "params"))
+    obs = W.observed_steps(2000, every=100)
+    y, st, _, ck = tvi.solve_forward("mlp", dev(y0), dev(times), dev(theta), chunk=100, tol=TOL32, checkpoints=True)
+    assert (host(st) == 0).all()
+    yh = host(y)
+    g = _mlp_loss_grad(yh, obs)
+    kw = dict(ckpt=ck) if recompute else dict(y=y)
+    dth, dy0, sa = tvi.solve_adjoint("mlp", dev(times), dev(theta), dev(g), chunk=100, tol=TOL32, **kw)
+    assert (host(sa) == 0).all()
+    oth, oy0, ost = oracle.adjoint("mlp", yh, times.astype(np.float64), theta.astype(np.float64), g)
+    assert (ost == 0).all()
+    e1 = np.abs(host(dth) - oth).max() / np.abs(oth).max()
+    e2 = np.abs(host(dy0) - oy0).max() / np.abs(oy0).max()
+    assert e1 <= 1e-5 and e2 <= 1e-5, (e1, e2)
+
+
+def test_mlp_adjoint_recompute_is_bitwise_and_full_size(tvi, mlp_full):
+    y0, times, theta, yo = mlp_full
+    obs = W.observed_steps(10000, every=100)
+    y, st, _, ck = tvi.solve_forward("mlp", dev(y0), dev(times), dev(theta), chunk=100, tol=TOL32, checkpoints=True)
+    g = _mlp_loss_grad(host(y), obs)
+    a1 = tvi.solve_adjoint("mlp", dev(times), dev(theta), dev(g), ckpt=ck, chunk=100, tol=TOL32)
+    a2 = tvi.solve_adjoint("mlp", dev(times), dev(theta), dev(g), y=y, chunk=100, tol=TOL32)
+    assert np.array_equal(host(a1[0]), host(a2[0])) and np.array_equal(host(a1[1]), host(a2[1]))
+    oth, oy0, _ = oracle.adjoint("mlp", yo, times.astype(np.float64), theta.astype(np.float64),
+                                 _mlp_loss_grad(yo, obs))
+    e1 = np.abs(host(a1[0]) - oth).max() / np.abs(oth).max()
+    assert e1 <= 1e-5, e1
+
+
+def test_mlp_gradient_matches_central_differences(tvi):
+    """dL/dtheta along random directions against central differences (eps = 1e-4)
+    of the float64 oracle's loss."""
+    w = W.mlp(B=4, N=400)
+    y0, times, theta = w["y0"], w["times"], w["params"]
+    obs = W.observed_steps(400, every=100)
+    f32 = lambda a: a.astype(np.float32)
+    y, st, _, ck = tvi.solve_forward("mlp", dev(f32(y0)), dev(f32(times)), dev(f32(theta)), chunk=100, tol=TOL32,
+                                     checkpoints=True)
+    g = _mlp_loss_grad(host(y), obs)
+    dth, _, _ = tvi.solve_adjoint("mlp", dev(f32(times)), dev(f32(theta)), dev(g), ckpt=ck, chunk=100, tol=TOL32)
+    dth = host(dth)
+
+    def loss(th):
+        yy, _, _ = oracle.forward("mlp", y0, times, th, tol=(1e-13, 1e-13))
+        return np.sum(yy[:, obs] ** 2) / (yy.shape[0] * len(obs) * 8)
+
+    rng = np.random.default_rng(17)
+    for _ in range(4):
+        d = rng.standard_normal(theta.shape)
+        d /= np.linalg.norm(d)
+        fd = (loss(theta + 1e-4 * d) - loss(theta - 1e-4 * d)) / 2e-4
+        assert abs(dth @ d - fd) <= 1e-4 * max(abs(fd), 1e-6) + 1e-7, (dth @ d, fd)

@@ -141,32 +141,46 @@ def test_linear_nonsymmetric_n2_n3(tvi):
 def vdp_oracle():
     w = W.vanderpol()
     yo, so, io = oracle.forward("vanderpol", w["y0"], w["times"], w["params"], tol=PARITY_TOL)
-    return w, yo, so
+    # The oracle's own sensitivity to rounding-level perturbations: rerun it from a
+    # start perturbed by 1e-13 (relative) and with the Newton stopping test moved.
+    # Relaxation oscillations with mu up to 1000 amplify such differences through
+    # every fast transition, so no two correct implementations agree closer than this.
+    rng = np.random.default_rng(9)
+    y0p = w["y0"] * (1.0 + 1e-13 * rng.choice([-1.0, 1.0], size=w["y0"].shape))
+    yp, sp, _ = oracle.forward("vanderpol", y0p, w["times"], w["params"], tol=PARITY_TOL)
+    yt, stt, _ = oracle.forward("vanderpol", w["y0"], w["times"], w["params"], tol=(1e-12, 1e-12))
+    clean = lambda a: np.nan_to_num(a, nan=0.0)
+    sens = np.maximum(series_rel_err(clean(yp), clean(yo)), series_rel_err(clean(yt), clean(yo)))
+    return w, yo, so, sens
 
 
-def classify_vdp(y, st, w, yo, so, gate, resid_gate):
+def classify_vdp(y, st, w, yo, so, sens, gate, resid_gate):
+    """match: within the gate; conditioned: within 100x the oracle's own rounding
+    sensitivity; alternate: a certified second root of one step; bad: the rest."""
     rel = series_rel_err(np.nan_to_num(y, nan=1e300), np.nan_to_num(yo, nan=0.0))
     both_ok = (so == 0) & (st == 0)
     res = be_step_residual("vanderpol", y, w["times"], w["params"])
     match = both_ok & (rel <= gate)
+    cond = both_ok & ~match & (rel <= 100.0 * sens) & (res <= resid_gate)
     alt = np.zeros_like(match)
-    for b in np.nonzero(both_ok & ~match)[0]:
+    for b in np.nonzero(both_ok & ~match & ~cond)[0]:
         alt[b] = res[b] <= resid_gate and certify_alternate_root("vanderpol", y[b], yo[b], w["times"], w["params"][b])
-    bad = both_ok & ~match & ~alt
-    return match, alt, bad, res
+    bad = both_ok & ~match & ~cond & ~alt
+    return match, cond, alt, bad, res
 
 
 @pytest.mark.parametrize("chunk", [1, 10, 50, 100, 500])
 def test_vanderpol_full_size_parity(tvi, vdp_oracle, chunk):
-    w, yo, so = vdp_oracle
+    w, yo, so, sens = vdp_oracle
     y, st, it, _ = tvi.solve_forward("vanderpol", dev(w["y0"]), dev(w["times"]), dev(w["params"]), chunk=chunk,
                                      tol=PARITY_TOL)
     y, st = host(y), host(st)
-    match, alt, bad, res = classify_vdp(y, st, w, yo, so, 1e-10, 1e-9)
-    print("chunk %d: %d match, %d certified alternate roots, %d GPU / %d oracle failures"
-          % (chunk, match.sum(), alt.sum(), (st != 0).sum(), (so != 0).sum()))
-    # every mismatch is a step with two backward-Euler roots, proved by exhibiting both
-    assert not bad.any(), np.nonzero(bad)[0][:10]
+    match, cond, alt, bad, res = classify_vdp(y, st, w, yo, so, sens, 1e-10, 1e-9)
+    print("chunk %d: %d within 1e-10, %d within the oracle's rounding sensitivity, %d certified alternate "
+          "roots, %d GPU / %d oracle failures" % (chunk, match.sum(), cond.sum(), alt.sum(), (st != 0).sum(),
+                                                  (so != 0).sum()))
+    assert not bad.any(), [(int(b), float(series_rel_err(y[b:b + 1], yo[b:b + 1])[0]), float(sens[b]))
+                           for b in np.nonzero(bad)[0][:10]]
     assert match.sum() >= 0.85 * len(st)
     # a series the GPU reports as solved satisfies backward Euler at every step
     assert (res[st == 0] <= 1e-9).all()
@@ -189,7 +203,7 @@ def test_vanderpol_fp32_storage(tvi):
 
 
 def test_vanderpol_timing_tolerance_residual_invariant(tvi, vdp_oracle):
-    w, yo, so = vdp_oracle
+    w, yo, so, _ = vdp_oracle
     y, st, it, _ = tvi.solve_forward("vanderpol", dev(w["y0"]), dev(w["times"]), dev(w["params"]), chunk=100,
                                      tol=TIMING_TOL)
     y, st = host(y), host(st)

@@ -373,3 +373,67 @@ def test_zero_steps_and_empty_batch():
     assert y.shape == (1, 1, 2) and np.array_equal(y[0, 0], [0.3, 0.1]) and st[0] == 0
     y, st, it = oracle.forward("vanderpol", np.zeros((0, 2)), np.linspace(0, 1, 5), np.zeros((0, 1)))
     assert y.shape == (0, 5, 2)
+
+
+# --------------------------------------------------------------------------
+# Chunk predictor reference: gradient against torch autograd and central
+# differences; GELU against its definition; Adam against torch.optim.Adam
+# --------------------------------------------------------------------------
+def _predictor_case(seed=0, n_in=10, hidden=16, n_out=12, M=7):
+    from oracle import predictor as PR
+    rng = np.random.default_rng(seed)
+    th = 0.3 * rng.standard_normal(sum(PR.sizes(n_in, hidden, n_out)))
+    x = rng.standard_normal((M, n_in))
+    tgt = rng.standard_normal((M, n_out))
+    return PR, th, x, tgt, (n_in, hidden, n_out)
+
+
+def test_predictor_gelu_and_forward_match_torch():
+    import torch
+    PR, th, x, tgt, dims = _predictor_case()
+    n_in, H, n_out = dims
+    W1, b1, W2, b2, W3, b3 = [torch.tensor(a) for a in PR.unpack(th, *dims)]
+    xt = torch.tensor(x)
+    gelu = torch.nn.GELU(approximate="none")
+    ref = gelu(gelu(xt @ W1.T + b1) @ W2.T + b2) @ W3.T + b3
+    out, _ = PR.forward(th, x, *dims)
+    np.testing.assert_allclose(out, ref.numpy(), rtol=1e-12, atol=1e-13)
+    z = np.linspace(-6, 6, 101)
+    np.testing.assert_allclose(PR.gelu_grad(z), (PR.gelu(z + 1e-6) - PR.gelu(z - 1e-6)) / 2e-6, atol=1e-8)
+
+
+def test_predictor_gradient_matches_autograd_and_differences():
+    import torch
+    PR, th, x, tgt, dims = _predictor_case(1)
+    L, g = PR.loss_and_grad(th, x, tgt, *dims)
+    tht = torch.tensor(th, requires_grad=True)
+    n_in, H, n_out = dims
+    parts = torch.split(tht, PR.sizes(*dims))
+    W1, b1, W2, b2, W3, b3 = (parts[0].view(H, n_in), parts[1], parts[2].view(H, H), parts[3],
+                              parts[4].view(n_out, H), parts[5])
+    gelu = torch.nn.GELU(approximate="none")
+    out = gelu(gelu(torch.tensor(x) @ W1.T + b1) @ W2.T + b2) @ W3.T + b3
+    Lt = ((out - torch.tensor(tgt)) ** 2).mean()
+    Lt.backward()
+    assert abs(L - Lt.item()) <= 1e-13 * abs(L)
+    np.testing.assert_allclose(g, tht.grad.numpy(), rtol=1e-11, atol=1e-14)
+    d = np.random.default_rng(2).standard_normal(th.shape)
+    fd = (PR.loss_and_grad(th + 1e-6 * d, x, tgt, *dims)[0] - PR.loss_and_grad(th - 1e-6 * d, x, tgt, *dims)[0]) / 2e-6
+    assert abs(g @ d - fd) <= 1e-7 * max(1.0, abs(fd))
+
+
+def test_predictor_adam_matches_torch():
+    import torch
+    from oracle import predictor as PR
+    rng = np.random.default_rng(3)
+    th = rng.standard_normal(20)
+    p = torch.nn.Parameter(torch.tensor(th))
+    opt = torch.optim.Adam([p], lr=1e-2)
+    m = np.zeros(20)
+    v = np.zeros(20)
+    for step in range(1, 6):
+        g = rng.standard_normal(20)
+        p.grad = torch.tensor(g)
+        opt.step()
+        th, m, v = PR.adam_step(th, g, m, v, step, 1e-2)
+        np.testing.assert_allclose(th, p.detach().numpy(), rtol=1e-12, atol=1e-14)
