@@ -1,24 +1,27 @@
 #!/usr/bin/env python3
 """Benchmark of the chunked backward-Euler solver on one MI355X.
 
-Workload: Van der Pol, n = 2, 512 series x 5000 uniform steps on t in [0, 10],
-mu log-uniform in [1, 1000], y0 ~ U(-2, 2), FP64, the paper's tolerances
-(tol_a 1e-8, tol_r 1e-6), forward integration.  One step of the benchmark is
-one full solve of the workload (every chunk, every Newton iteration, inputs
-resident in HBM).  The chunk length and the lane tiling come from the
-autotuner (run during warm-up, untimed).
+Headline workload: Van der Pol, n = 2, 512 series x 5000 uniform steps on
+t in [0, 10], mu log-uniform in [1, 1000], y0 ~ U(-2, 2), FP64, the paper's
+tolerances (tol_a 1e-8, tol_r 1e-6), forward integration.  One step of the
+benchmark is one full solve of the workload (every chunk, every Newton
+iteration, inputs resident in HBM).  The chunk length, the lane tiling and
+the initial iterate come from the autotuner (run before timing, untimed).
 
-Printed as one JSON line: throughput in series*steps/s, the chunk = 1
-sequential GPU solver (same library, one lane per series) on the same
-inputs, the roofline of the dominant kernel, the standalone block-bidiagonal
-solve against the HBM roofline, forward+adjoint throughput, and the CPU
-oracle timed on the host cores.
+Printed as one JSON line: throughput in series*steps/s, the roofline of the
+dominant kernel, and, beside it, the chunk = 1 sequential GPU solver on the
+same inputs, forward + adjoint in one captured graph, the standalone
+block-bidiagonal solve against the HBM roofline, the neural-ODE path
+(forward + adjoint) against the matrix-core peak, the ragged Robertson batch
+as one captured graph, the learned chunk predictor against its fallbacks, and
+the CPU oracle timed on the host cores.
 """
 import argparse
 import json
 import os
 import sys
 import time
+import traceback
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -26,21 +29,28 @@ sys.path.insert(0, ROOT)
 METRIC = "series·steps/s fwd+adjoint at tol 1e-8 vs chunk=1 sequential; % HBM peak"
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
+PEAK_BF16_TFLOPS = 2500.0
 TIMING_TOL = (1e-8, 1e-6)
+MLP_F_FLOPS = 2 * (64 * 8 + 64 * 64 + 8 * 64)      # h(y): three layers
+MLP_J_FLOPS = 2 * (64 * 64 * 8 + 8 * 64 * 8) + 2 * 64 * 8  # W3 diag W2 diag W1
 
 
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+def levels(chunk):
+    L = 0
+    while (1 << L) < chunk:
+        L += 1
+    return L
+
+
 def vdp_flops_per_step_iter(chunk):
     """Algorithmic flops of one Newton iteration per series-step (Van der Pol):
     residual, Jacobian, block inverse and update (44) plus one composition of
     2x2 affine maps per reduction level (24 per level, ceil(log2 C) levels)."""
-    levels = 0
-    while (1 << levels) < chunk:
-        levels += 1
-    return 44 + 24 * levels
+    return 44 + 24 * levels(chunk)
 
 
 def csrc_hash():
@@ -71,7 +81,7 @@ def measured_traffic(kernel):
 
 
 def time_launches(fn, reps, stream):
-    """Average launch duration (ms) by HIP events on the launching stream."""
+    """Durations (ms) of `reps` calls of fn, by HIP events on the launching stream."""
     import torch
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
     for e0, e1 in evs:
@@ -82,14 +92,268 @@ def time_launches(fn, reps, stream):
     return [e0.elapsed_time(e1) for e0, e1 in evs]
 
 
+def stats(ds):
+    s = sorted(ds)
+    return {"mean_ms": sum(s) / len(s), "median_ms": s[len(s) // 2], "min_ms": s[0]}
+
+
+def extra(out, name, fn):
+    """Run one side measurement; a failure is recorded, not fatal to the line."""
+    log(name)
+    t0 = time.perf_counter()
+    try:
+        out[name] = fn()
+    except Exception as e:  # noqa: BLE001 - the headline must still be printed
+        traceback.print_exc()
+        out[name] = {"error": "%s: %s" % (type(e).__name__, e)}
+    log("%s done in %.1f s" % (name, time.perf_counter() - t0))
+
+
+# ---------------------------------------------------------------------------
+# side measurements
+# ---------------------------------------------------------------------------
+def run_chunk1(ctx, steps):
+    import numpy as np
+    from paper_2310_08649_amd import tvi
+    y0, times, mu, y_out, B, N = ctx["y0"], ctx["times"], ctx["mu"], ctx["y_out"], ctx["B"], ctx["N"]
+    seq = lambda: tvi.solve_forward("vanderpol", y0, times, mu, chunk=1, lanes=1, steps_per_lane=1,
+                                    tol=TIMING_TOL, y_out=y_out, iters=False)
+    seq()
+    d = time_launches(seq, max(3, steps // 3), ctx["stream"])
+    ms = float(np.mean(d))
+    return {"value": B * N / (ms * 1e-3), "unit": "series*steps/s", "ms_per_step": ms,
+            "speedup_of_chunked": ms / ctx["ms_per_step"],
+            "note": "same library, chunk 1: one lane per series, one Newton solve per step"}
+
+
+def run_vdp_fwd_adjoint(ctx, steps):
+    import torch
+    from paper_2310_08649_amd import graph, workloads
+    B, N = ctx["B"], ctx["N"]
+    obs = torch.zeros((B, N + 1), dtype=torch.uint8)
+    obs[:, torch.as_tensor(workloads.observed_steps(N, every=50))] = 1
+    res = {"loss": "mean of |y|^2 at 100 sampled steps per series"}
+    for recompute in (False, True):
+        cs = graph.CapturedStep("vanderpol", ctx["y0"], ctx["times"], ctx["mu"], chunk=ctx["C"], lanes=ctx["S"],
+                                steps_per_lane=ctx["T"], tol=TIMING_TOL, init=ctx["init"], loss="mean_square",
+                                observed=obs.reshape(-1), recompute=recompute).capture()
+        for _ in range(2):
+            cs.replay()
+        d = time_launches(cs.replay, max(5, steps), torch.cuda.current_stream())
+        st = stats(d)
+        res["recompute" if recompute else "stored"] = dict(
+            value=B * N / (st["mean_ms"] * 1e-3), unit="series*steps/s", **st,
+            failed=int(((cs.status_fwd != 0) | (cs.status_adj != 0)).sum().item()),
+            states="recomputed from chunk checkpoints" if recompute else "read from the stored trajectory")
+        del cs
+    return res
+
+
+def run_pcr(ctx, steps):
+    import numpy as np
+    import torch
+    from paper_2310_08649_amd import tvi
+    dev = ctx["dev"]
+    res = []
+    target = 4 << 30
+    for dt, n in ((torch.float64, 2), (torch.float64, 3), (torch.float64, 4), (torch.float32, 2),
+                  (torch.float32, 4)):
+        m = 64
+        es = torch.finfo(dt).bits // 8
+        per_sys = m * (n * n + 2 * n) * es
+        nb = target // per_sys
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(5)
+        D = torch.eye(n, dtype=dt, device=dev).expand(nb, m, n, n).contiguous()
+        D.add_(torch.randn(D.shape, generator=gen, dtype=dt, device=dev), alpha=0.2 / n)
+        r = torch.randn((nb, m, n), generator=gen, dtype=dt, device=dev)
+        x = torch.empty_like(r)
+        fn = lambda: tvi.pcr_solve(D, r, out=x)
+        fn()
+        d = time_launches(fn, 10, ctx["stream"])
+        ms = float(np.mean(d))
+        gbs = nb * per_sys / (ms * 1e-3) / 1e9
+        res.append({"n": n, "dtype": "f64" if dt == torch.float64 else "f32", "systems": int(nb), "block_rows": m,
+                    "bytes_per_launch": int(nb * per_sys), "avg_launch_ms": ms, "achieved": gbs,
+                    "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS})
+        del D, r, x
+        torch.cuda.empty_cache()
+    best = res[0]
+    pname = "tvi::pcr_kernel<2, double, 64, 1, false>(long, int, double const*, double const*, double*)"
+    return {"kernel": pname, "bound": "hbm", "achieved": best["achieved"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": best["frac"], "traffic": measured_traffic(pname), "bytes_per_launch": best["bytes_per_launch"],
+            "avg_launch_ms": best["avg_launch_ms"], "systems": best["systems"], "block_rows": 64, "n": 2,
+            "sweep": res}
+
+
+def run_mlp(ctx, steps):
+    """Neural ODE n = 8, 2 x 64 tanh, 64 series x 1e4 steps, chunk 100, FP32,
+    forward + adjoint of the mean squared state at 100 sampled times."""
+    import numpy as np
+    import torch
+    from paper_2310_08649_amd import graph, tvi, workloads
+    dev = ctx["dev"]
+    w = workloads.mlp()
+    B, N, C = w["y0"].shape[0], w["times"].shape[0] - 1, 100
+    f = lambda a: torch.as_tensor(a, dtype=torch.float32, device=dev)
+    y0, times, theta = f(w["y0"]), f(w["times"]), f(w["params"])
+    obs = torch.zeros((B, N + 1), dtype=torch.uint8)
+    obs[:, torch.as_tensor(workloads.observed_steps(N))] = 1
+    cs = graph.CapturedStep("mlp", y0, times, theta, chunk=C, tol=TIMING_TOL, loss="mean_square",
+                            observed=obs.reshape(-1), recompute=True).capture()
+    cs.replay()
+    d = time_launches(cs.replay, max(3, steps // 2), torch.cuda.current_stream())
+    st = stats(d)
+    corrections = int(cs.iters.sum().item())
+    failed = int(((cs.status_fwd != 0) | (cs.status_adj != 0)).sum().item())
+    # forward kernel alone, and its matrix-core work
+    fwd = lambda: tvi.solve_forward("mlp", y0, times, theta, chunk=C, tol=TIMING_TOL, y_out=cs.y,
+                                    checkpoints=False, iters=False)
+    fwd()
+    fms = float(np.mean(time_launches(fwd, 3, ctx["stream"])))
+    attempts = B * (N // C)
+    # every trip evaluates h on the attempt's steps; every correction also evaluates J
+    flops = (corrections + attempts) * C * MLP_F_FLOPS + corrections * C * MLP_J_FLOPS
+    tf = flops / (fms * 1e-3) / 1e12
+    return {"workload": "mlp n=8 H=64 tanh B=64 N=10000 t=[0,1] chunk=100 f32 (bf16-split MFMA) "
+                        "fwd+adjoint, mean-square loss at 100 sampled times, states recomputed",
+            "value": B * N / (st["mean_ms"] * 1e-3), "unit": "series*steps/s", **st,
+            "forward_ms": fms, "forward_value": B * N / (fms * 1e-3), "newton_corrections": corrections,
+            "failed": failed,
+            "roofline": {"kernel": "tvi::mlp_forward_kernel<float>", "bound": "mfma", "achieved": tf,
+                         "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s", "frac": tf / PEAK_BF16_TFLOPS,
+                         "flops_counted": "h: %d per step per Newton trip, J: %d per step per correction "
+                                          "(useful products, not the bf16 split)" % (MLP_F_FLOPS, MLP_J_FLOPS)}}
+
+
+def run_robertson(ctx, steps):
+    """2000 ragged Robertson series (100..20000 log-spaced steps), FP64,
+    forward + adjoint (Frobenius loss) as one captured graph, autotuned."""
+    import numpy as np
+    import torch
+    from paper_2310_08649_amd import autotune, graph, tvi, workloads
+    dev = ctx["dev"]
+    w = workloads.robertson()
+    d = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev)
+    y0, times, sp = d(w["y0"]), d(w["times"]), d(w["params"])
+    off = torch.as_tensor(w["offsets"], device=dev)
+    total = int(w["steps"].sum())
+    y_out = torch.empty((times.shape[0], 3), dtype=torch.float64, device=dev)
+    tuned = autotune.tune_forward("robertson", y0, times, sp, offsets=off, tol=TIMING_TOL, y_out=y_out,
+                                  use_cache=False, chunks=(16, 32, 64, 128, 256), inits=("zero", "extrap"))
+    b = tuned["best"]
+    cs = graph.CapturedStep("robertson", y0, times, sp, offsets=off, chunk=b["chunk"], lanes=b["lanes"],
+                            steps_per_lane=b["steps_per_lane"], tol=TIMING_TOL, init=b["init"],
+                            loss="frobenius", recompute=True).capture()
+    cs.replay()
+    dd = time_launches(cs.replay, max(3, steps // 2), torch.cuda.current_stream())
+    st = stats(dd)
+    fwd = lambda: tvi.solve_forward("robertson", y0, times, sp, offsets=off, chunk=b["chunk"], lanes=b["lanes"],
+                                    steps_per_lane=b["steps_per_lane"], tol=TIMING_TOL, init=b["init"],
+                                    y_out=y_out, iters=False)
+    seq = lambda: tvi.solve_forward("robertson", y0, times, sp, offsets=off, chunk=1, lanes=1, steps_per_lane=1,
+                                    tol=TIMING_TOL, y_out=y_out, iters=False)
+    fms = float(np.mean(time_launches(fwd, 3, ctx["stream"])))
+    seq()
+    sms = float(np.mean(time_launches(seq, 3, ctx["stream"])))
+    return {"workload": "robertson n=3 B=2000 ragged N_b=exp U(ln 100, ln 2e4) log-spaced t=[1e-5,1e4] f64 "
+                        "fwd+adjoint (Frobenius loss), one captured graph, states recomputed",
+            "series_steps": total, "value": total / (st["mean_ms"] * 1e-3), "unit": "series*steps/s", **st,
+            "failed": int(((cs.status_fwd != 0) | (cs.status_adj != 0)).sum().item()),
+            "forward_value": total / (fms * 1e-3), "chunk1_forward_value": total / (sms * 1e-3),
+            "tuned": b}
+
+
+def run_predictor(ctx, steps):
+    """Learned chunk predictor on the neural ODE: trained on ~1e5 chunks the
+    solver computed (500 series x 1e4 steps, chunk 50), evaluated on 256 new
+    series x 1e4 steps against the extrapolated and the zero start."""
+    import numpy as np
+    import torch
+    from paper_2310_08649_amd import predictor as pred
+    from paper_2310_08649_amd import tvi, workloads
+    dev = ctx["dev"]
+    C = 50
+    f = lambda a: torch.as_tensor(np.asarray(a), dtype=torch.float32, device=dev)
+    theta = f(workloads.mlp(B=1, seed=103)["params"])
+    times = f(np.linspace(0.0, 1.0, 10001))
+    tr_y0 = f(np.random.default_rng(105).standard_normal((500, 8)))
+    ev_y0 = f(np.random.default_rng(107).standard_normal((256, 8)))
+    t0 = time.perf_counter()
+    y, st, _, _ = tvi.solve_forward("mlp", tr_y0, times, theta, chunk=C, tol=TIMING_TOL, init="extrap")
+    x, s = pred.chunk_samples(y, times, C)
+    ok = torch.isfinite(s).all(dim=1) & torch.isfinite(x).all(dim=1)
+    x, s = x[ok].contiguous(), s[ok].contiguous()
+    p = pred.slope_corrections("mlp", x, s, theta, 8, C)
+    d = pred.dims(8, C)
+    net, hist = pred.fit_predictor(d, x, p, epochs=30, seed=0)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    res = {"train_chunks": int(x.shape[0]), "train_seconds": t_train, "train_loss": [hist[0], hist[-1]]}
+    y_ref = None
+    for init in ("zero", "extrap", "predictor"):
+        kw = dict(predictor=(net, d.hidden, C)) if init == "predictor" else {}
+        fn = lambda: tvi.solve_forward("mlp", ev_y0, times, theta, chunk=C, tol=TIMING_TOL, init=init, **kw)
+        yy, stt, it, _ = fn()
+        ms = float(np.mean(time_launches(fn, 3, ctx["stream"])))
+        if y_ref is None:
+            y_ref = yy.clone()
+        res[init] = {"newton_corrections": int(it.sum().item()), "ms": ms,
+                     "failed": int((stt != 0).sum().item()),
+                     "max_rel_diff_vs_zero_start": float(((yy - y_ref).abs().max() / y_ref.abs().max()).item())}
+    # initial-iterate error against the converged chunks of the evaluation set
+    xe, se = pred.chunk_samples(y_ref, times, C)
+    fs, _ = tvi.model_eval("mlp", xe[:, :8].contiguous(), theta, jacobian=False)
+    ext = fs.repeat(1, C)
+    res["initial_slope_mse"] = {"zero": float((se ** 2).mean().item()),
+                                "extrap": float(((ext - se) ** 2).mean().item()),
+                                "predictor": float(((ext + pred.forward(d, net, xe) - se) ** 2).mean().item())}
+    return res
+
+
+def run_cpu_baseline(w, target_s=10.0):
+    import oracle
+    B, N = w["y0"].shape[0], w["times"].shape[0] - 1
+    threads = oracle.default_threads()
+    reps, t = 0, 0.0
+    t0 = time.perf_counter()
+    while t < target_s and reps < 5000:
+        oracle.forward("vanderpol", w["y0"], w["times"], w["params"], tol=TIMING_TOL, threads=threads)
+        reps += 1
+        t = time.perf_counter() - t0
+    # one core on a slice of the series
+    sl = slice(0, 64)
+    reps1, t1 = 0, 0.0
+    t0 = time.perf_counter()
+    while t1 < target_s / 4 and reps1 < 500:
+        oracle.forward("vanderpol", w["y0"][sl], w["times"], w["params"][sl], tol=TIMING_TOL, threads=1)
+        reps1 += 1
+        t1 = time.perf_counter() - t0
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": reps * B * N / t, "unit": "series*steps/s", "cores": threads, "kind": "oracle",
+            "sample": "the full workload (512 x 5000, forward) solved %d times in %.1f s, sequential backward "
+                      "Euler with a dense Newton solve per step" % (reps, t),
+            "one_core_value": reps1 * 64 * N / t1, "cpu_model": cpu, "nproc": os.cpu_count()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--chunk", type=int, default=0, help="0 = autotune")
+    ap.add_argument("--init", default="", help="initial iterate (zero | extrap); empty = autotune")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the headline measurement")
+    ap.add_argument("--only", default="", help="comma-separated side measurements to run")
     ap.add_argument("--probe-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -113,17 +377,18 @@ def main():
     y0, times, mu = d(w["y0"]), d(w["times"]), d(w["params"])
     y_out = torch.empty((B, N + 1, 2), dtype=torch.float64, device=dev)
 
-    # ---- autotune chunk length and tiling (untimed)
-    log("autotuning chunk / tiling")
+    # ---- autotune chunk length, tiling and initial iterate (untimed)
+    log("autotuning chunk / tiling / initial iterate")
     tuned = autotune.tune_forward("vanderpol", y0, times, mu, tol=TIMING_TOL, y_out=y_out, use_cache=False,
-                                  chunks=(10, 50, 100, 200, 500) if args.chunk == 0 else (args.chunk,))
+                                  chunks=(10, 50, 100, 200, 500) if args.chunk == 0 else (args.chunk,),
+                                  inits=("zero", "extrap") if not args.init else (args.init,))
     best = tuned["best"]
-    C, S, T = best["chunk"], best["lanes"], best["steps_per_lane"]
-    log("chosen chunk=%d lanes=%d steps_per_lane=%d (%.3f ms)" % (C, S, T, best["ms"]))
+    C, S, T, init = best["chunk"], best["lanes"], best["steps_per_lane"], best["init"]
+    log("chosen chunk=%d lanes=%d steps_per_lane=%d init=%s (%.3f ms)" % (C, S, T, init, best["ms"]))
 
     def step():
         return tvi.solve_forward("vanderpol", y0, times, mu, chunk=C, lanes=S, steps_per_lane=T, tol=TIMING_TOL,
-                                 y_out=y_out)
+                                 y_out=y_out, init=init)
 
     for _ in range(args.warmup):
         step()
@@ -138,7 +403,8 @@ def main():
     st = status.cpu().numpy()
     it = iters.cpu().numpy()
     durs = time_launches(step, args.steps, stream)
-    kern_ms = float(np.mean(durs))
+    kst = stats(durs)
+    kern_ms = kst["mean_ms"]
 
     flops = float(it.sum()) * C * vdp_flops_per_step_iter(C)
     achieved_tflops = flops / (kern_ms * 1e-3) / 1e12
@@ -146,72 +412,29 @@ def main():
     roofline = {"kernel": kname, "bound": "alu",
                 "achieved": achieved_tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved_tflops / PEAK_FP64_TFLOPS, "traffic": measured_traffic(kname),
-                "avg_launch_ms": kern_ms,
-                "note": "latency-bound: a chain of N/C chunk solves x Newton iterations per series"}
+                "avg_launch_ms": kern_ms, "median_launch_ms": kst["median_ms"], "min_launch_ms": kst["min_ms"],
+                "algorithmic_bytes_per_launch": B * (N + 1) * 2 * 8,
+                "note": "latency-bound: each series is a chain of N/C chunk solves x Newton iterations; "
+                        "the slowest series sets the launch time"}
 
     out = {"metric": METRIC, "value": value, "unit": "series*steps/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "vanderpol n=2 B=512 N=5000 t=[0,10] mu=10^U(0,3) y0=U(-2,2) forward "
                                   "tol_a=1e-8 tol_r=1e-6", "chunk": C, "lanes": S, "steps_per_lane": T,
-                      "series_failed": int((st != 0).sum()), "newton_iters_per_series": float(it.mean())},
+                      "init": init, "series_failed": int((st != 0).sum()),
+                      "newton_iters_per_series": float(it.mean()), "newton_iters_max": int(it.max())},
            "roofline": roofline, "autotune": tuned["table"]}
 
+    ctx = dict(dev=dev, stream=stream, y0=y0, times=times, mu=mu, y_out=y_out, B=B, N=N, C=C, S=S, T=T, init=init,
+               ms_per_step=ms_per_step)
     if not args.no_extras:
-        # chunk = 1 sequential solver: one lane per series, one Newton solve per step
-        log("chunk=1 sequential baseline")
-        seq = lambda: tvi.solve_forward("vanderpol", y0, times, mu, chunk=1, lanes=1, steps_per_lane=1,
-                                        tol=TIMING_TOL, y_out=y_out)
-        seq()
-        sd = time_launches(seq, max(3, args.steps // 4), stream)
-        seq_ms = float(np.mean(sd))
-        out["chunk1"] = {"value": B * N / (seq_ms * 1e-3), "ms_per_step": seq_ms,
-                         "speedup_of_chunked": seq_ms / ms_per_step}
-
-        # forward + adjoint (Frobenius loss, checkpoints + recomputation)
-        log("forward + adjoint")
-        g = torch.empty_like(y_out)
-
-        def fwd_adj():
-            y, st_, _, ck = tvi.solve_forward("vanderpol", y0, times, mu, chunk=C, lanes=S, steps_per_lane=T,
-                                              tol=TIMING_TOL, y_out=y_out, checkpoints=True, iters=False)
-            torch.div(y, torch.linalg.vector_norm(y), out=g)
-            return tvi.solve_adjoint("vanderpol", times, mu, g, ckpt=ck, chunk=C, lanes=S, steps_per_lane=T,
-                                     tol=TIMING_TOL)
-
-        fwd_adj()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        reps = max(3, args.steps // 2)
-        for _ in range(reps):
-            fwd_adj()
-        torch.cuda.synchronize()
-        fa_ms = (time.perf_counter() - t0) * 1e3 / reps
-        out["fwd_adjoint"] = {"value": B * N / (fa_ms * 1e-3), "ms_per_step": fa_ms, "loss": "frobenius",
-                              "states": "recomputed from chunk checkpoints"}
-
-        # standalone block-bidiagonal solve on a working set far beyond the caches
-        log("standalone PCR solve, n=2 fp64, 4 GiB per launch")
-        nb, m, n = 1 << 20, 64, 2
-        gen = torch.Generator(device=dev)
-        gen.manual_seed(5)
-        D = torch.eye(n, dtype=torch.float64, device=dev).expand(nb, m, n, n).contiguous()
-        D.add_(torch.randn(D.shape, generator=gen, dtype=torch.float64, device=dev), alpha=0.2)
-        r = torch.randn((nb, m, n), generator=gen, dtype=torch.float64, device=dev)
-        x = torch.empty_like(r)
-        pcr = lambda: tvi.pcr_solve(D, r, out=x)
-        pcr()
-        pd = time_launches(pcr, 10, stream)
-        pcr_ms = float(np.mean(pd))
-        bytes_alg = nb * m * (n * n + 2 * n) * 8
-        gbs = bytes_alg / (pcr_ms * 1e-3) / 1e9
-        pname = "tvi::pcr_kernel<2, double, 64, 1, false>(long, int, double const*, double const*, double*)"
-        out["pcr_roofline"] = {"kernel": pname, "bound": "hbm", "achieved": gbs,
-                               "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
-                               "traffic": measured_traffic(pname),
-                               "bytes_per_launch": bytes_alg, "avg_launch_ms": pcr_ms,
-                               "systems": nb, "block_rows": m, "n": n}
-        del D, r, x
+        runs = [("chunk1", run_chunk1), ("fwd_adjoint", run_vdp_fwd_adjoint), ("pcr_roofline", run_pcr),
+                ("mlp", run_mlp), ("robertson", run_robertson), ("predictor", run_predictor)]
+        only = set(filter(None, args.only.split(",")))
+        for name, fn in runs:
+            if not only or name in only:
+                extra(out, name, lambda fn=fn: fn(ctx, args.steps))
 
     if args.probe_copy:
         src = torch.ones(1 << 25, dtype=torch.float64, device=dev)
@@ -223,18 +446,7 @@ def main():
 
     if not args.no_cpu:
         log("CPU oracle on the host cores")
-        import oracle
-        threads = oracle.default_threads()
-        reps, t_cpu = 0, 0.0
-        t0 = time.perf_counter()
-        while t_cpu < 2.0 and reps < 50:
-            oracle.forward("vanderpol", w["y0"], w["times"], w["params"], tol=TIMING_TOL, threads=threads)
-            reps += 1
-            t_cpu = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": reps * B * N / t_cpu, "unit": "series*steps/s", "cores": threads,
-                               "kind": "oracle",
-                               "sample": "the full workload (512 x 5000, forward) repeated %d times, "
-                                         "sequential backward Euler with a dense Newton solve per step" % reps}
+        out["cpu_baseline"] = run_cpu_baseline(w)
 
     print(json.dumps(out), flush=True)
 

@@ -74,9 +74,13 @@ def _time(fn, reps):
 
 
 def tune_forward(kind, y0, times, params, offsets=None, tol=(1e-8, 1e-6), chunks=(10, 50, 100, 200, 500),
-                 reps=3, y_out=None, use_cache=True, **kw):
-    """Returns {"best": {chunk, lanes, steps_per_lane, ms}, "table": [...]}."""
-    key = _key(kind, y0, times, offsets, "tol=%g,%g|chunks=%s" % (tol[0], tol[1], ",".join(map(str, chunks))))
+                 reps=3, y_out=None, use_cache=True, inits=("zero",), **kw):
+    """Returns {"best": {chunk, lanes, steps_per_lane, init, failed, ms}, "table": [...]}.
+
+    Candidates are ranked by the number of series that failed to converge,
+    then by time: a faster configuration never wins by giving up on series."""
+    key = _key(kind, y0, times, offsets, "tol=%g,%g|chunks=%s|inits=%s"
+               % (tol[0], tol[1], ",".join(map(str, chunks)), ",".join(inits)))
     if use_cache:
         with _lock:
             hit = _load_cache().get(key)
@@ -85,10 +89,17 @@ def tune_forward(kind, y0, times, params, offsets=None, tol=(1e-8, 1e-6), chunks
     table = []
     for C in chunks:
         for S, T in tilings(C):
-            fn = lambda: tvi.solve_forward(kind, y0, times, params, offsets=offsets, chunk=C, lanes=S,
-                                           steps_per_lane=T, tol=tol, y_out=y_out, **kw)
-            table.append({"chunk": C, "lanes": S, "steps_per_lane": T, "ms": _time(fn, reps)})
-    best = min(table, key=lambda r: r["ms"])
+            for init in inits:
+                res = {}
+
+                def fn():
+                    res["st"] = tvi.solve_forward(kind, y0, times, params, offsets=offsets, chunk=C, lanes=S,
+                                                  steps_per_lane=T, tol=tol, y_out=y_out, init=init, iters=False,
+                                                  **kw)[1]
+                ms = _time(fn, reps)
+                failed = int((res["st"] != 0).sum().item())
+                table.append({"chunk": C, "lanes": S, "steps_per_lane": T, "init": init, "failed": failed, "ms": ms})
+    best = min(table, key=lambda r: (r["failed"], r["ms"]))
     res = {"best": best, "table": table}
     if use_cache:
         with _lock:

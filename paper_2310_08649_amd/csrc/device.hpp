@@ -37,22 +37,92 @@ __device__ __forceinline__ float lane_read(float x, int src)
 // Wave-uniform "does any lane satisfy p".
 __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
 
-// Sum of x over the S-lane segment of this lane (butterfly; every lane of the
-// segment gets the same, order-fixed result).
+// ---------------------------------------------------------------------------
+// Register-to-register lane moves by DPP (data-parallel primitives: a source
+// modifier of an ordinary VALU move, no LDS round trip).  GFX9 controls:
+//   quad_perm [1,0,3,2] / [2,3,0,1]   exchange within quads
+//   row_shr:d / row_shl:d             lane i of a 16-lane row reads i -/+ d
+//   wave_shr:1 / wave_shl:1           lane i reads i -/+ 1 across the wave
+//   row_half_mirror / row_mirror      lane i reads 7-i / 15-i within a row
+//   row_bcast:15 (rows 1,3 read lanes 15,47), row_bcast:31 (rows 2,3 read 31)
+// A lane whose source does not exist, or whose row is masked off, keeps `old`.
+// Every lane of the wave must execute these.
+// ---------------------------------------------------------------------------
+namespace dpp {
+constexpr int QUAD_XOR1 = 0xB1, QUAD_XOR2 = 0x4E;
+constexpr int ROW_SHL = 0x100, ROW_SHR = 0x110;
+constexpr int WAVE_SHL1 = 0x130, WAVE_SHR1 = 0x138;
+constexpr int ROW_MIRROR = 0x140, ROW_HALF_MIRROR = 0x141;
+constexpr int ROW_BCAST15 = 0x142, ROW_BCAST31 = 0x143;
+} // namespace dpp
+
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ int dpp_mov(int old, int x)
+{
+    return __builtin_amdgcn_update_dpp(old, x, CTRL, ROWS, 0xF, false);
+}
+
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ float dpp_mov(float old, float x)
+{
+    return __int_as_float(dpp_mov<CTRL, ROWS>(__float_as_int(old), __float_as_int(x)));
+}
+
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ double dpp_mov(double old, double x)
+{
+    const int lo = dpp_mov<CTRL, ROWS>(__double2loint(old), __double2loint(x));
+    const int hi = dpp_mov<CTRL, ROWS>(__double2hiint(old), __double2hiint(x));
+    return __hiloint2double(hi, lo);
+}
+
+// The value of x in lane `src` (wave-uniform src), for every lane.
+__device__ __forceinline__ int lane_bcast(int x, int src) { return __builtin_amdgcn_readlane(x, src); }
+__device__ __forceinline__ float lane_bcast(float x, int src)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), src));
+}
+__device__ __forceinline__ double lane_bcast(double x, int src)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), src);
+    return __hiloint2double(hi, lo);
+}
+
+// x of lane-1 / lane+1 (a lane without one keeps its own x).
+template <class R>
+__device__ __forceinline__ R lane_prev(R x) { return dpp_mov<dpp::WAVE_SHR1>(x, x); }
+template <class R>
+__device__ __forceinline__ R lane_next(R x) { return dpp_mov<dpp::WAVE_SHL1>(x, x); }
+
+// Sum of x over the S-lane segment of this lane.  Exchanges within quads,
+// half rows and rows, then the row sums by lane broadcast: every lane of a
+// segment computes the same additions on the same operands (in swapped order
+// at most), so all get the bitwise-same, order-fixed result.
 template <int S, class R>
 __device__ __forceinline__ R seg_sum(R x)
 {
-#pragma unroll
-    for (int d = 1; d < S; d <<= 1) x += __shfl_xor(x, d, S);
+    if constexpr (S >= 2) x += dpp_mov<dpp::QUAD_XOR1>(x, x);
+    if constexpr (S >= 4) x += dpp_mov<dpp::QUAD_XOR2>(x, x);
+    if constexpr (S >= 8) x += dpp_mov<dpp::ROW_HALF_MIRROR>(x, x);
+    if constexpr (S >= 16) x += dpp_mov<dpp::ROW_MIRROR>(x, x);
+    if constexpr (S >= 32) {
+        const R r0 = lane_bcast(x, 0), r1 = lane_bcast(x, 16), r2 = lane_bcast(x, 32), r3 = lane_bcast(x, 48);
+        if constexpr (S == 32) x = (lane_id() < 32) ? r0 + r1 : r2 + r3;
+        else x = (r0 + r1) + (r2 + r3);
+    }
     return x;
 }
 
+// Logical and of x != 0 over the S-lane segment (one ballot).
 template <int S>
 __device__ __forceinline__ int seg_and(int x)
 {
-#pragma unroll
-    for (int d = 1; d < S; d <<= 1) x &= __shfl_xor(x, d, S);
-    return x;
+    const unsigned long long m = __ballot(x != 0);
+    if constexpr (S == kWave) return m == ~0ull ? 1 : 0;
+    const int base = lane_id() & ~(S - 1);
+    const unsigned long long seg = (1ull << S) - 1ull;
+    return ((m >> base) & seg) == seg ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -201,46 +271,17 @@ __device__ __forceinline__ void affine_after(Affine<N, R> &a, const Affine<N, R>
         for (int k = 0; k < N; ++k) a.M[i][k] = t[i][k];
 }
 
-template <int N, class R>
-__device__ __forceinline__ void affine_read(const Affine<N, R> &a, int src, Affine<N, R> &out)
-{
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-#pragma unroll
-        for (int k = 0; k < N; ++k) out.M[i][k] = lane_read(a.M[i][k], src);
-        out.z[i] = lane_read(a.z[i], src);
-    }
-}
 
 // Inclusive prefix composition over the segment, lowest lane first:
-// lane q ends with A_q o A_{q-1} o ... o A_0.
-template <int N, int S, class R>
-__device__ __forceinline__ void seg_scan_up(Affine<N, R> &a)
-{
-    const int lane = lane_id();
-    const int q = lane & (S - 1);
-#pragma unroll
-    for (int d = 1; d < S; d <<= 1) {
-        Affine<N, R> o;
-        affine_read(a, q >= d ? lane - d : lane, o);
-        if (q >= d) affine_after(a, o);
-    }
-}
+// lane q ends with A_q o A_{q-1} o ... o A_0.  Kogge-Stone levels by row
+// shifts inside 16-lane rows, then the row totals by row broadcasts.
+template <int N, int S, class Map>
+__device__ __forceinline__ void seg_scan_up(Map &a);
 
 // Inclusive suffix composition, highest lane first:
 // lane q ends with A_q o A_{q+1} o ... o A_{S-1}.
-template <int N, int S, class R>
-__device__ __forceinline__ void seg_scan_down(Affine<N, R> &a)
-{
-    const int lane = lane_id();
-    const int q = lane & (S - 1);
-#pragma unroll
-    for (int d = 1; d < S; d <<= 1) {
-        Affine<N, R> o;
-        affine_read(a, q + d < S ? lane + d : lane, o);
-        if (q + d < S) affine_after(a, o);
-    }
-}
+template <int N, int S, class Map>
+__device__ __forceinline__ void seg_scan_down(Map &a);
 
 // ---------------------------------------------------------------------------
 // The same maps kept as "identity plus small", x -> (I + F) x + z.  For blocks
@@ -302,42 +343,6 @@ __device__ __forceinline__ void affine_after(AffineI<N, R> &a, const AffineI<N, 
         for (int k = 0; k < N; ++k) a.F[i][k] = t[i][k];
 }
 
-template <int N, class R>
-__device__ __forceinline__ void affine_read(const AffineI<N, R> &a, int src, AffineI<N, R> &out)
-{
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-#pragma unroll
-        for (int k = 0; k < N; ++k) out.F[i][k] = lane_read(a.F[i][k], src);
-        out.z[i] = lane_read(a.z[i], src);
-    }
-}
-
-template <int N, int S, class R>
-__device__ __forceinline__ void seg_scan_up(AffineI<N, R> &a)
-{
-    const int lane = lane_id();
-    const int q = lane & (S - 1);
-#pragma unroll
-    for (int d = 1; d < S; d <<= 1) {
-        AffineI<N, R> o;
-        affine_read(a, q >= d ? lane - d : lane, o);
-        if (q >= d) affine_after(a, o);
-    }
-}
-
-template <int N, int S, class R>
-__device__ __forceinline__ void seg_scan_down(AffineI<N, R> &a)
-{
-    const int lane = lane_id();
-    const int q = lane & (S - 1);
-#pragma unroll
-    for (int d = 1; d < S; d <<= 1) {
-        AffineI<N, R> o;
-        affine_read(a, q + d < S ? lane + d : lane, o);
-        if (q + d < S) affine_after(a, o);
-    }
-}
 
 // F with I + F = (I - E)^{-1}: F = (I - E)^{-1} E.  Returns false on a zero or
 // non-finite pivot.
@@ -354,12 +359,128 @@ __device__ __forceinline__ bool inverse_plus(const R (&E)[N][N], R (&F)[N][N])
     return ok;
 }
 
-// Vector of N doubles from lane src.
+// Lane moves of a whole map (Affine or AffineI), element by element.
+template <int CTRL, int ROWS, int N, class R>
+__device__ __forceinline__ void dpp_map(const Affine<N, R> &a, Affine<N, R> &o)
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) o.M[i][k] = dpp_mov<CTRL, ROWS>(a.M[i][k], a.M[i][k]);
+        o.z[i] = dpp_mov<CTRL, ROWS>(a.z[i], a.z[i]);
+    }
+}
+
+template <int CTRL, int ROWS, int N, class R>
+__device__ __forceinline__ void dpp_map(const AffineI<N, R> &a, AffineI<N, R> &o)
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) o.F[i][k] = dpp_mov<CTRL, ROWS>(a.F[i][k], a.F[i][k]);
+        o.z[i] = dpp_mov<CTRL, ROWS>(a.z[i], a.z[i]);
+    }
+}
+
+template <int N, class R>
+__device__ __forceinline__ void bcast_map(const Affine<N, R> &a, int src, Affine<N, R> &o)
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) o.M[i][k] = lane_bcast(a.M[i][k], src);
+        o.z[i] = lane_bcast(a.z[i], src);
+    }
+}
+
+template <int N, class R>
+__device__ __forceinline__ void bcast_map(const AffineI<N, R> &a, int src, AffineI<N, R> &o)
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) o.F[i][k] = lane_bcast(a.F[i][k], src);
+        o.z[i] = lane_bcast(a.z[i], src);
+    }
+}
+
+template <int CTRL, int D, int W, bool UP, class Map>
+__device__ __forceinline__ void scan_level(Map &a, int r)
+{
+    if constexpr (D < W) {
+        Map o;
+        dpp_map<CTRL + D, 0xF>(a, o);
+        if (UP ? (r >= D) : (r + D < W)) affine_after(a, o);
+    }
+}
+
+template <int N, int S, class Map>
+__device__ __forceinline__ void seg_scan_up(Map &a)
+{
+    constexpr int W = S < 16 ? S : 16;
+    const int lane = lane_id();
+    const int r = lane & (W - 1);
+    scan_level<dpp::ROW_SHR, 1, W, true>(a, r);
+    scan_level<dpp::ROW_SHR, 2, W, true>(a, r);
+    scan_level<dpp::ROW_SHR, 4, W, true>(a, r);
+    scan_level<dpp::ROW_SHR, 8, W, true>(a, r);
+    if constexpr (S >= 32) {
+        Map o;
+        dpp_map<dpp::ROW_BCAST15, 0xA>(a, o);
+        if (lane & 16) affine_after(a, o);
+    }
+    if constexpr (S >= 64) {
+        Map o;
+        dpp_map<dpp::ROW_BCAST31, 0xC>(a, o);
+        if (lane & 32) affine_after(a, o);
+    }
+}
+
+template <int N, int S, class Map>
+__device__ __forceinline__ void seg_scan_down(Map &a)
+{
+    constexpr int W = S < 16 ? S : 16;
+    const int lane = lane_id();
+    const int r = lane & (W - 1);
+    scan_level<dpp::ROW_SHL, 1, W, false>(a, r);
+    scan_level<dpp::ROW_SHL, 2, W, false>(a, r);
+    scan_level<dpp::ROW_SHL, 4, W, false>(a, r);
+    scan_level<dpp::ROW_SHL, 8, W, false>(a, r);
+    if constexpr (S >= 32) {
+        // rows 0 and 2 take the suffix totals of rows 1 and 3 (their first lanes)
+        Map h1, h3;
+        bcast_map(a, 16, h1);
+        bcast_map(a, 48, h3);
+        if (!(lane & 16)) affine_after(a, (lane & 32) ? h3 : h1);
+    }
+    if constexpr (S >= 64) {
+        Map h;
+        bcast_map(a, 32, h);
+        if (!(lane & 32)) affine_after(a, h);
+    }
+}
+
+// Vector from lane src (any lane of the wave; an LDS permute).
 template <int N, class R>
 __device__ __forceinline__ void vec_read(const R (&v)[N], int src, R (&out)[N])
 {
 #pragma unroll
     for (int i = 0; i < N; ++i) out[i] = lane_read(v[i], src);
+}
+
+// Vector of lane-1 / lane+1.
+template <int N, class R>
+__device__ __forceinline__ void vec_prev(const R (&v)[N], R (&out)[N])
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) out[i] = lane_prev(v[i]);
+}
+
+template <int N, class R>
+__device__ __forceinline__ void vec_next(const R (&v)[N], R (&out)[N])
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) out[i] = lane_next(v[i]);
 }
 
 // IO conversions

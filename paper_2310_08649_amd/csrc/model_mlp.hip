@@ -83,9 +83,9 @@ struct MlpTrajectorySink {
             for (int e = 0; e < NS; ++e) st(y + k * NS + e, ys[e] + (double)dy[e]);
         }
     }
-    __device__ void boundary(int64_t s, const double (&ys)[NS], int tid) const
+    // c: index of the checkpoint (the chunk boundary just reached, or the end)
+    __device__ void boundary(int64_t c, const double (&ys)[NS], int tid) const
     {
-        const int64_t c = (s + C - 1) / C;
         if (ck && tid < NS && c < K) ck[c * NS + tid] = ys[tid];
     }
     __device__ void fail(int64_t s, int tid) const
@@ -228,11 +228,12 @@ __device__ int mlp_solve(MlpShared &S, const SolveArgs<IO> &a, const IO *t, doub
     int64_t s = s0;
     int mcur = C, m = 0, it = 0, status = ST_OK, accepted = 0;
     bool start = true, sing = false;
+    int64_t ck_next = s / C + 1, ck_at = ck_next * C;  // next nominal boundary: no division in the loop
     float nrm0 = 0.f, dy[NS], hj = 0.f;
     Acts A;
     while (s < s_end) {
         if (start) {
-            const int64_t nom_end = min((s / C + 1) * (int64_t)C, s_end);
+            const int64_t nom_end = min(ck_at, s_end);
             m = (int)min((int64_t)mcur, nom_end - s);
             const bool v = j < m;
             const double ts = ld(t + s);
@@ -295,8 +296,13 @@ __device__ int mlp_solve(MlpShared &S, const SolveArgs<IO> &a, const IO *t, doub
 #pragma unroll
             for (int k = 0; k < NS; ++k) ys[k] += (double)S.dy[m - 1][k];
             s += m;
-            if (s % C == 0 || s >= s_end) sink.boundary(s, ys, tid);
-            if (s % C == 0) mcur = C;
+            const bool at_ck = s == ck_at;
+            if (at_ck || s >= s_end) sink.boundary(ck_next, ys, tid);
+            if (at_ck) {
+                mcur = C;
+                ++ck_next;
+                ck_at += C;
+            }
             start = true;
             __syncthreads();
             continue;

@@ -96,14 +96,14 @@ __global__ __launch_bounds__(kWave) void pcr_kernel(int64_t B, int m, const IO *
         double din[N];
         if (!TR) {
             seg_scan_up<N, S>(map);
-            vec_read(map.z, q > 0 ? lane - 1 : lane, din);
+            vec_prev(map.z, din);
             if (q == 0) {
 #pragma unroll
                 for (int e = 0; e < N; ++e) din[e] = 0.0;
             }
         } else {
             seg_scan_down<N, S>(map);
-            vec_read(map.z, q < S - 1 ? lane + 1 : lane, din);
+            vec_next(map.z, din);
             if (q == S - 1) {
 #pragma unroll
                 for (int e = 0; e < N; ++e) din[e] = 0.0;

@@ -85,9 +85,9 @@ struct TrajectorySink {
             for (int i = 0; i < N; ++i) st(y + k * N + i, v[i]);
         }
     }
-    __device__ __forceinline__ void boundary(int64_t s, const double (&v)[N], int q) const
+    // c: index of the checkpoint (the chunk boundary just reached, or the end)
+    __device__ __forceinline__ void boundary(int64_t c, const double (&v)[N], int q) const
     {
-        const int64_t c = (s + C - 1) / C;
         if (ck && q == 0 && c < K) {
 #pragma unroll
             for (int i = 0; i < N; ++i) ck[c * N + i] = v[i];
@@ -126,6 +126,8 @@ struct ChunkNewton {
     double ys[n];      // state at the chunk start
     int64_t s;         // chunk start step
     int64_t s_end;     // the solve ends when s reaches s_end
+    int64_t ck_next;   // index of the next nominal chunk boundary ...
+    int64_t ck_at;     // ... and its step (ck_next * C): no division inside the loop
     int m, mcur;       // attempt length and the current limit (halved on failure)
     int it, total;     // corrections in this attempt / in total
     double nrm0;
@@ -152,12 +154,14 @@ struct ChunkNewton {
         nrm0 = 0.0;
         m = 0;
         mcur = C;
+        ck_next = s / C + 1;
+        ck_at = ck_next * C;
         double Mi[T][n][n], zi[T][n], R[T][n];
 
         while (wave_any(active)) {
             // ---- attempt set-up: owned times and the initial iterate (lane-local)
             if (active && start) {
-                const int64_t nom_end = min((s / C + 1) * (int64_t)C, s_end);
+                const int64_t nom_end = min(ck_at, s_end);
                 m = (int)min((int64_t)mcur, nom_end - s);
                 const double ts = ld(t + s);
                 double slope[n];
@@ -185,7 +189,7 @@ struct ChunkNewton {
 
             // ---- residual of the owned steps and its segment norm
             double prev[n];
-            vec_read(dy[T - 1], q > 0 ? lane - 1 : lane, prev);
+            vec_prev(dy[T - 1], prev);
             double acc = 0.0;
 #pragma unroll
             for (int i = 0; i < T; ++i) {
@@ -242,8 +246,13 @@ struct ChunkNewton {
 #pragma unroll
                     for (int k = 0; k < n; ++k) ys[k] += last[k];
                     s += m;
-                    if (s % C == 0 || s >= s_end) sink.boundary(s, ys, q);
-                    if (s % C == 0) mcur = C;
+                    const bool at_ck = s == ck_at;
+                    if (at_ck || s >= s_end) sink.boundary(ck_next, ys, q);
+                    if (at_ck) {
+                        mcur = C;
+                        ++ck_next;
+                        ck_at += C;
+                    }
                     if (s >= s_end) active = false;
                     start = true;
                 }
@@ -304,7 +313,7 @@ struct ChunkNewton {
                 }
                 seg_scan_up<n, S>(map);
                 double din[n];
-                vec_read(map.z, q > 0 ? lane - 1 : lane, din);
+                vec_prev(map.z, din);
                 if (q == 0) {
 #pragma unroll
                     for (int k = 0; k < n; ++k) din[k] = 0.0;
@@ -471,7 +480,7 @@ __global__ __launch_bounds__(kWave) void adjoint_kernel(SolveArgs<IO> a)
         // lam at the first owned step of every lane, then the value entering from the right
         double vq[n], lin[n];
         matvec_add(map.M, lam, map.z, vq);
-        vec_read(vq, q < S - 1 ? lane + 1 : lane, lin);
+        vec_next(vq, lin);
         if (q == S - 1) {
 #pragma unroll
             for (int k = 0; k < n; ++k) lin[k] = lam[k];

@@ -1,6 +1,7 @@
 """One captured HIP graph for a whole training step of a batch of series:
 chunked backward-Euler forward pass (with chunk-boundary checkpoints), the
-loss gradient, and the adjoint with recomputed interior states.
+loss gradient, and the adjoint, either with interior states recomputed from
+the checkpoints or read from the stored trajectory.
 
 Every buffer is allocated once, before capture, so a replay touches only
 device memory the graph owns; the launches are the library's kernels on the
@@ -26,9 +27,10 @@ class CapturedStep:
     """
 
     def __init__(self, kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e-6), lanes=0, steps_per_lane=0,
-                 max_newton=50, init="zero", loss="frobenius", observed=None, n_max=None):
+                 max_newton=50, init="zero", loss="frobenius", observed=None, n_max=None, recompute=True):
         lib = tvi.load()
         self.kind = kind
+        self.recompute = recompute
         dt = y0.dtype
         dev = y0.device
         self.y0 = y0.detach().clone().contiguous()
@@ -84,7 +86,8 @@ class CapturedStep:
                                      self.n_observed, P(self.g), P(self.loss), P(self.loss_ws),
                                      self.loss_ws.numel(), st), "tvi_loss_grad")
         tvi._check(lib.tvi_solve_adjoint(ctypes.byref(self.model), ctypes.byref(self.opt), self.B, self.N,
-                                         P(self.offsets), P(self.times), P(self.params), None, P(self.ckpt),
+                                         P(self.offsets), P(self.times), P(self.params),
+                                         None if self.recompute else P(self.y), P(self.ckpt),
                                          P(self.g), P(self.dLdp), P(self.dLdy0), P(self.status_adj), P(self.ws),
                                          self.ws_bytes, st), "tvi_solve_adjoint")
 
