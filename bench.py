@@ -281,10 +281,10 @@ def run_predictor(ctx, steps):
     ev_y0 = f(np.random.default_rng(107).standard_normal((256, 8)))
     t0 = time.perf_counter()
     y, st, _, _ = tvi.solve_forward("mlp", tr_y0, times, theta, chunk=C, tol=TIMING_TOL, init="extrap")
-    x, s = pred.chunk_samples(y, times, C)
-    ok = torch.isfinite(s).all(dim=1) & torch.isfinite(x).all(dim=1)
-    x, s = x[ok].contiguous(), s[ok].contiguous()
-    p = pred.slope_corrections("mlp", x, s, theta, 8, C)
+    x, inc, dts = pred.chunk_samples(y, times, C)
+    ok = torch.isfinite(inc).all(dim=1) & torch.isfinite(x).all(dim=1)
+    x, inc, dts = x[ok].contiguous(), inc[ok].contiguous(), dts[ok].contiguous()
+    p = pred.corrections("mlp", x, inc, dts, theta, 8)
     d = pred.dims(8, C)
     net, hist = pred.fit_predictor(d, x, p, epochs=30, seed=0)
     torch.cuda.synchronize()
@@ -302,12 +302,11 @@ def run_predictor(ctx, steps):
                      "failed": int((stt != 0).sum().item()),
                      "max_rel_diff_vs_zero_start": float(((yy - y_ref).abs().max() / y_ref.abs().max()).item())}
     # initial-iterate error against the converged chunks of the evaluation set
-    xe, se = pred.chunk_samples(y_ref, times, C)
-    fs, _ = tvi.model_eval("mlp", xe[:, :8].contiguous(), theta, jacobian=False)
-    ext = fs.repeat(1, C)
-    res["initial_slope_mse"] = {"zero": float((se ** 2).mean().item()),
-                                "extrap": float(((ext - se) ** 2).mean().item()),
-                                "predictor": float(((ext + pred.forward(d, net, xe) - se) ** 2).mean().item())}
+    xe, ie, de = pred.chunk_samples(y_ref, times, C)
+    ext = pred.extrapolated("mlp", xe, de, theta, 8)
+    res["initial_iterate_mse"] = {"zero": float((ie ** 2).mean().item()),
+                                  "extrap": float(((ext - ie) ** 2).mean().item()),
+                                  "predictor": float(((ext + pred.forward(d, net, xe) - ie) ** 2).mean().item())}
     return res
 
 

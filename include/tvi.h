@@ -94,7 +94,7 @@ typedef enum {
     TVI_INIT_ZERO = 0,     /* Delta y = 0 over the chunk (Section 2.3)                        */
     TVI_INIT_EXTRAP = 1,   /* extrapolate the last step's slope over the chunk:
                               dy0_j = (t_{s+j} - t_s) h(y_s, t_s)                           */
-    TVI_INIT_PREDICTOR = 2 /* the learned chunk predictor: dy0_j = (t_{s+j} - t_s)(h(y_s) + p_j)
+    TVI_INIT_PREDICTOR = 2 /* the learned chunk predictor: dy0_j = (t_{s+j} - t_s) h(y_s) + p_j
                               with p = the tvi_predictor network (n_in = n + 2: y_s, t_s,
                               log(t_{s+1} - t_s); n_out = n * predictor_steps), kept only where
                               its residual is below the extrapolation's; TVI_MLP only          */

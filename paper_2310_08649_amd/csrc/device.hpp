@@ -76,6 +76,28 @@ __device__ __forceinline__ double dpp_mov(double old, double x)
     return __hiloint2double(hi, lo);
 }
 
+// The same moves with zero fill: a lane whose source does not exist, or whose
+// row is masked off, gets 0.
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ int dpp_zero(int x)
+{
+    return __builtin_amdgcn_update_dpp(0, x, CTRL, ROWS, 0xF, true);
+}
+
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ float dpp_zero(float x)
+{
+    return __int_as_float(dpp_zero<CTRL, ROWS>(__float_as_int(x)));
+}
+
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ double dpp_zero(double x)
+{
+    const int lo = dpp_zero<CTRL, ROWS>(__double2loint(x));
+    const int hi = dpp_zero<CTRL, ROWS>(__double2hiint(x));
+    return __hiloint2double(hi, lo);
+}
+
 // The value of x in lane `src` (wave-uniform src), for every lane.
 __device__ __forceinline__ int lane_bcast(int x, int src) { return __builtin_amdgcn_readlane(x, src); }
 __device__ __forceinline__ float lane_bcast(float x, int src)
@@ -89,11 +111,11 @@ __device__ __forceinline__ double lane_bcast(double x, int src)
     return __hiloint2double(hi, lo);
 }
 
-// x of lane-1 / lane+1 (a lane without one keeps its own x).
+// x of lane-1 / lane+1 (0 for lane 0 / lane 63).
 template <class R>
-__device__ __forceinline__ R lane_prev(R x) { return dpp_mov<dpp::WAVE_SHR1>(x, x); }
+__device__ __forceinline__ R lane_prev(R x) { return dpp_zero<dpp::WAVE_SHR1>(x); }
 template <class R>
-__device__ __forceinline__ R lane_next(R x) { return dpp_mov<dpp::WAVE_SHL1>(x, x); }
+__device__ __forceinline__ R lane_next(R x) { return dpp_zero<dpp::WAVE_SHL1>(x); }
 
 // Sum of x over the S-lane segment of this lane.  Exchanges within quads,
 // half rows and rows, then the row sums by lane broadcast: every lane of a
@@ -234,59 +256,21 @@ __device__ __forceinline__ bool invert(R (&A)[N][N], R (&X)[N][N])
 }
 
 // ---------------------------------------------------------------------------
-// Affine maps v -> M v + z over a segment of S lanes.
+// Affine maps over a segment of S lanes, kept as "identity plus F":
+// x -> (I + F) x + z.
 //
 // A block lower-bidiagonal system with sub-diagonal blocks -I,
 //   D_j x_j - x_{j-1} = r_j,
-// is the affine recurrence x_j = M_j x_{j-1} + z_j with M_j = D_j^{-1},
+// is the affine recurrence x_j = M_j x_{j-1} + z_j with M_j = D_j^{-1} = I + F_j,
 // z_j = D_j^{-1} r_j and x_0 = 0.  One level of parallel cyclic reduction at
 // stride d replaces row j's dependence on x_{j-1..} by one on x_{j-d..}:
 // z_j <- z_j + M_j z_{j-d},  M_j <- M_j M_{j-d}  (the split of Section 3.2
 // with B = -I), i.e. a Kogge-Stone scan with map composition.
-// ---------------------------------------------------------------------------
-template <int N, class R = double>
-struct Affine {
-    R M[N][N];
-    R z[N];
-};
-
-template <int N, class R>
-__device__ __forceinline__ void affine_identity(Affine<N, R> &a)
-{
-    set_identity(a.M);
-#pragma unroll
-    for (int i = 0; i < N; ++i) a.z[i] = R(0);
-}
-
-// a <- a o b  (apply b first, then a):  M = Ma Mb,  z = Ma zb + za
-template <int N, class R>
-__device__ __forceinline__ void affine_after(Affine<N, R> &a, const Affine<N, R> &b)
-{
-    matvec_add(a.M, b.z, a.z, a.z);
-    R t[N][N];
-    matmul(a.M, b.M, t);
-#pragma unroll
-    for (int i = 0; i < N; ++i)
-#pragma unroll
-        for (int k = 0; k < N; ++k) a.M[i][k] = t[i][k];
-}
-
-
-// Inclusive prefix composition over the segment, lowest lane first:
-// lane q ends with A_q o A_{q-1} o ... o A_0.  Kogge-Stone levels by row
-// shifts inside 16-lane rows, then the row totals by row broadcasts.
-template <int N, int S, class Map>
-__device__ __forceinline__ void seg_scan_up(Map &a);
-
-// Inclusive suffix composition, highest lane first:
-// lane q ends with A_q o A_{q+1} o ... o A_{S-1}.
-template <int N, int S, class Map>
-__device__ __forceinline__ void seg_scan_down(Map &a);
-
-// ---------------------------------------------------------------------------
-// The same maps kept as "identity plus small", x -> (I + F) x + z.  For blocks
-// D = I - dt j with dt j small (non-stiff steps in float), I + F = D^{-1}
-// with F = D^{-1} (dt j) small, so F and every composition carry full
+//
+// Keeping F rather than M makes the identity map all zeros, so a lane move
+// that fills missing sources with zero hands the lanes without a partner the
+// identity, and every lane composes unconditionally.  For D = I - dt j with
+// dt j small (non-stiff steps in float) F = D^{-1} (dt j) also keeps full
 // relative precision instead of losing it next to the identity.
 // ---------------------------------------------------------------------------
 template <int N, class R>
@@ -359,37 +343,15 @@ __device__ __forceinline__ bool inverse_plus(const R (&E)[N][N], R (&F)[N][N])
     return ok;
 }
 
-// Lane moves of a whole map (Affine or AffineI), element by element.
-template <int CTRL, int ROWS, int N, class R>
-__device__ __forceinline__ void dpp_map(const Affine<N, R> &a, Affine<N, R> &o)
-{
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-#pragma unroll
-        for (int k = 0; k < N; ++k) o.M[i][k] = dpp_mov<CTRL, ROWS>(a.M[i][k], a.M[i][k]);
-        o.z[i] = dpp_mov<CTRL, ROWS>(a.z[i], a.z[i]);
-    }
-}
-
+// Lane moves of a whole map, element by element (zero fill: identity).
 template <int CTRL, int ROWS, int N, class R>
 __device__ __forceinline__ void dpp_map(const AffineI<N, R> &a, AffineI<N, R> &o)
 {
 #pragma unroll
     for (int i = 0; i < N; ++i) {
 #pragma unroll
-        for (int k = 0; k < N; ++k) o.F[i][k] = dpp_mov<CTRL, ROWS>(a.F[i][k], a.F[i][k]);
-        o.z[i] = dpp_mov<CTRL, ROWS>(a.z[i], a.z[i]);
-    }
-}
-
-template <int N, class R>
-__device__ __forceinline__ void bcast_map(const Affine<N, R> &a, int src, Affine<N, R> &o)
-{
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-#pragma unroll
-        for (int k = 0; k < N; ++k) o.M[i][k] = lane_bcast(a.M[i][k], src);
-        o.z[i] = lane_bcast(a.z[i], src);
+        for (int k = 0; k < N; ++k) o.F[i][k] = dpp_zero<CTRL, ROWS>(a.F[i][k]);
+        o.z[i] = dpp_zero<CTRL, ROWS>(a.z[i]);
     }
 }
 
@@ -404,60 +366,110 @@ __device__ __forceinline__ void bcast_map(const AffineI<N, R> &a, int src, Affin
     }
 }
 
-template <int CTRL, int D, int W, bool UP, class Map>
-__device__ __forceinline__ void scan_level(Map &a, int r)
+// o <- keep ? o : identity
+template <int N, class R>
+__device__ __forceinline__ void keep_or_identity(AffineI<N, R> &o, bool keep)
 {
-    if constexpr (D < W) {
-        Map o;
-        dpp_map<CTRL + D, 0xF>(a, o);
-        if (UP ? (r >= D) : (r + D < W)) affine_after(a, o);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) o.F[i][k] = keep ? o.F[i][k] : R(0);
+        o.z[i] = keep ? o.z[i] : R(0);
     }
 }
 
-template <int N, int S, class Map>
-__device__ __forceinline__ void seg_scan_up(Map &a)
+// One Kogge-Stone level at stride D inside 16-lane rows (W = min(S, 16)).
+// Row shifts zero-fill at row edges; narrower segments also mask their own edges.
+template <int CTRL, int D, int S, bool UP, int N, class R>
+__device__ __forceinline__ void scan_level(AffineI<N, R> &a, int q)
 {
     constexpr int W = S < 16 ? S : 16;
-    const int lane = lane_id();
-    const int r = lane & (W - 1);
-    scan_level<dpp::ROW_SHR, 1, W, true>(a, r);
-    scan_level<dpp::ROW_SHR, 2, W, true>(a, r);
-    scan_level<dpp::ROW_SHR, 4, W, true>(a, r);
-    scan_level<dpp::ROW_SHR, 8, W, true>(a, r);
+    if constexpr (D < W) {
+        AffineI<N, R> o;
+        dpp_map<CTRL + D, 0xF>(a, o);
+        if constexpr (S < 16) keep_or_identity(o, UP ? (q >= D) : (q + D < S));
+        affine_after(a, o);
+    }
+}
+
+// Inclusive prefix composition over the segment, lowest lane first:
+// lane q ends with A_q o A_{q-1} o ... o A_0.  Row shifts inside 16-lane rows,
+// then the row totals by row broadcasts (rows 1, 3 take lanes 15, 47; rows 2,
+// 3 take lane 31); masked rows receive the identity.
+template <int N, int S, class R>
+__device__ __forceinline__ void seg_scan_up(AffineI<N, R> &a)
+{
+    const int q = lane_id() & (S - 1);
+    scan_level<dpp::ROW_SHR, 1, S, true>(a, q);
+    scan_level<dpp::ROW_SHR, 2, S, true>(a, q);
+    scan_level<dpp::ROW_SHR, 4, S, true>(a, q);
+    scan_level<dpp::ROW_SHR, 8, S, true>(a, q);
     if constexpr (S >= 32) {
-        Map o;
+        AffineI<N, R> o;
         dpp_map<dpp::ROW_BCAST15, 0xA>(a, o);
-        if (lane & 16) affine_after(a, o);
+        affine_after(a, o);
     }
     if constexpr (S >= 64) {
-        Map o;
+        AffineI<N, R> o;
         dpp_map<dpp::ROW_BCAST31, 0xC>(a, o);
-        if (lane & 32) affine_after(a, o);
+        affine_after(a, o);
     }
 }
 
-template <int N, int S, class Map>
-__device__ __forceinline__ void seg_scan_down(Map &a)
+// Inclusive suffix composition, highest lane first:
+// lane q ends with A_q o A_{q+1} o ... o A_{S-1}.  Row shifts, then rows 0
+// and 2 take the totals of rows 1 and 3 (their first lanes), then rows 0 and
+// 1 take the total of rows 2-3 (lane 32), by lane broadcasts.
+template <int N, int S, class R>
+__device__ __forceinline__ void seg_scan_down(AffineI<N, R> &a)
 {
-    constexpr int W = S < 16 ? S : 16;
     const int lane = lane_id();
-    const int r = lane & (W - 1);
-    scan_level<dpp::ROW_SHL, 1, W, false>(a, r);
-    scan_level<dpp::ROW_SHL, 2, W, false>(a, r);
-    scan_level<dpp::ROW_SHL, 4, W, false>(a, r);
-    scan_level<dpp::ROW_SHL, 8, W, false>(a, r);
+    const int q = lane & (S - 1);
+    scan_level<dpp::ROW_SHL, 1, S, false>(a, q);
+    scan_level<dpp::ROW_SHL, 2, S, false>(a, q);
+    scan_level<dpp::ROW_SHL, 4, S, false>(a, q);
+    scan_level<dpp::ROW_SHL, 8, S, false>(a, q);
     if constexpr (S >= 32) {
-        // rows 0 and 2 take the suffix totals of rows 1 and 3 (their first lanes)
-        Map h1, h3;
+        AffineI<N, R> h1, h3;
         bcast_map(a, 16, h1);
         bcast_map(a, 48, h3);
-        if (!(lane & 16)) affine_after(a, (lane & 32) ? h3 : h1);
+        AffineI<N, R> o = (lane & 32) ? h3 : h1;
+        keep_or_identity(o, !(lane & 16));
+        affine_after(a, o);
     }
     if constexpr (S >= 64) {
-        Map h;
-        bcast_map(a, 32, h);
-        if (!(lane & 32)) affine_after(a, h);
+        AffineI<N, R> o;
+        bcast_map(a, 32, o);
+        keep_or_identity(o, !(lane & 32));
+        affine_after(a, o);
     }
+}
+
+// F of the inverse of the block D: I + F = D^{-1}, via Gauss-Jordan on D
+// (partial pivoting).  Returns false on a zero or non-finite pivot.
+template <int N, class R>
+__device__ __forceinline__ bool invert_plus(R (&D)[N][N], R (&F)[N][N])
+{
+    const bool ok = invert(D, F);
+#pragma unroll
+    for (int i = 0; i < N; ++i) F[i][i] -= R(1);
+    return ok;
+}
+
+// y = (I + F)^T x + c   (y may alias x or c)
+template <int N, class R>
+__device__ __forceinline__ void apply_ip_t(const R (&F)[N][N], const R (&x)[N], const R (&c)[N], R (&y)[N])
+{
+    R t[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        R s = c[i];
+#pragma unroll
+        for (int l = 0; l < N; ++l) s = fma(F[l][i], x[l], s);
+        t[i] = s + x[i];
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) y[i] = t[i];
 }
 
 // Vector from lane src (any lane of the wave; an LDS permute).

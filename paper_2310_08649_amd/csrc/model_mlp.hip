@@ -157,7 +157,7 @@ __device__ __forceinline__ float gelu_f(float x) { return 0.5f * x * (1.f + erff
 // The learned predictor's slopes for the chunk starting at (ys, ts) with first
 // step dts: out[o], o < m * NS, in LDS (block-wide; every thread calls it).
 // params = W1[Hp][NS+2], b1, W2[Hp][Hp], b2, W3[NS*steps][Hp], b3, mean[NS+2], std[NS+2].
-__device__ void predictor_slopes(float *a1, float *a2, float *out, const float *pp, int Hp, int steps,
+__device__ void predictor_corrections(float *a1, float *a2, float *out, const float *pp, int Hp, int steps,
                                  const double (&ys)[NS], double ts, double dts, int m)
 {
     const int tid = threadIdx.x, nin = NS + 2, nout = NS * steps;
@@ -257,14 +257,14 @@ __device__ int mlp_solve(MlpShared &S, const SolveArgs<IO> &a, const IO *t, doub
                 }
             }
             if (a.init == INIT_PREDICTOR) {
-                // the learned start: the extrapolated slope plus the predicted correction,
-                // kept only if its residual is below the extrapolation's
+                // the learned start: the extrapolated increments plus the predicted
+                // corrections, kept only if its residual is below the extrapolation's
                 float *scratch = &S.u.v.a[0][0][0];
-                predictor_slopes(scratch, scratch + 256, scratch + 512, a.pred, a.pred_hidden, a.pred_steps, ys, ts,
+                predictor_corrections(scratch, scratch + 256, scratch + 512, a.pred, a.pred_hidden, a.pred_steps, ys, ts,
                                  ld(t + s + 1) - ts, m);
                 float dyp[NS];
 #pragma unroll
-                for (int k = 0; k < NS; ++k) dyp[k] = v ? dy[k] + tj * scratch[512 + j * NS + k] : 0.f;
+                for (int k = 0; k < NS; ++k) dyp[k] = v ? dy[k] + scratch[512 + j * NS + k] : 0.f;
                 const float n_ext = chunk_residual_norm(S, ys, dy, hj, v);
                 const float n_pred = chunk_residual_norm(S, ys, dyp, hj, v);
                 if (n_pred < n_ext) {

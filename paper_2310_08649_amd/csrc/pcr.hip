@@ -70,8 +70,8 @@ __global__ __launch_bounds__(kWave) void pcr_kernel(int64_t B, int m, const IO *
             load_rows<N, IO, S, T, TR>(cur, D, r, b, m, q);
         }
 
-        double Mi[T][N][N], zi[T][N];
-        Affine<N> map;
+        double Fi[T][N][N], zi[T][N];  // I + Fi = D^{-1} (of the transposed block when TR)
+        AffineI<N, double> map;
         affine_identity(map);
         int ok = 1;
 #pragma unroll
@@ -79,44 +79,43 @@ __global__ __launch_bounds__(kWave) void pcr_kernel(int64_t B, int m, const IO *
             const int i = TR ? T - 1 - u : u;  // composition order: along the recurrence
             const int j = q * T + i;
             if (valid && j < m) {
-                ok &= invert(cur.D[i], Mi[i]) ? 1 : 0;
+                ok &= invert_plus(cur.D[i], Fi[i]) ? 1 : 0;
                 const double zero[N] = {};
-                matvec_add(Mi[i], cur.r[i], zero, zi[i]);
-                Affine<N> stp;
+                apply_ip(Fi[i], cur.r[i], zero, zi[i]);
+                AffineI<N, double> stp;
 #pragma unroll
                 for (int e = 0; e < N; ++e) {
 #pragma unroll
-                    for (int c = 0; c < N; ++c) stp.M[e][c] = Mi[i][e][c];
+                    for (int c = 0; c < N; ++c) stp.F[e][c] = Fi[i][e][c];
                     stp.z[e] = zi[i][e];
                 }
                 affine_after(stp, map);
                 map = stp;
             }
         }
-        double din[N];
-        if (!TR) {
-            seg_scan_up<N, S>(map);
-            vec_prev(map.z, din);
-            if (q == 0) {
+        if (!TR) seg_scan_up<N, S>(map);
+        else seg_scan_down<N, S>(map);
+        if constexpr (T == 1) {
+            // the composed map's offset is the solution at the lane's row
 #pragma unroll
-                for (int e = 0; e < N; ++e) din[e] = 0.0;
-            }
+            for (int e = 0; e < N; ++e) zi[0][e] = map.z[e];
         } else {
-            seg_scan_down<N, S>(map);
-            vec_next(map.z, din);
-            if (q == S - 1) {
+            double din[N];
+            if (!TR) vec_prev(map.z, din);
+            else vec_next(map.z, din);
+            if (q == (TR ? S - 1 : 0)) {
 #pragma unroll
                 for (int e = 0; e < N; ++e) din[e] = 0.0;
             }
-        }
 #pragma unroll
-        for (int u = 0; u < T; ++u) {
-            const int i = TR ? T - 1 - u : u;
-            const int j = q * T + i;
-            if (valid && j < m) {
-                matvec_add(Mi[i], din, zi[i], din);
+            for (int u = 0; u < T; ++u) {
+                const int i = TR ? T - 1 - u : u;
+                const int j = q * T + i;
+                if (valid && j < m) {
+                    apply_ip(Fi[i], din, zi[i], din);
 #pragma unroll
-                for (int e = 0; e < N; ++e) zi[i][e] = din[e];
+                    for (int e = 0; e < N; ++e) zi[i][e] = din[e];
+                }
             }
         }
         ok = seg_and<S>(ok);

@@ -156,7 +156,7 @@ struct ChunkNewton {
         mcur = C;
         ck_next = s / C + 1;
         ck_at = ck_next * C;
-        double Mi[T][n][n], zi[T][n], R[T][n];
+        double Fi[T][n][n], zi[T][n], R[T][n];
 
         while (wave_any(active)) {
             // ---- attempt set-up: owned times and the initial iterate (lane-local)
@@ -271,7 +271,7 @@ struct ChunkNewton {
             // ---- Newton correction: blocks, in-lane composition, PCR, replay
             if (wave_any(act == 3)) {
                 const bool corr = act == 3;
-                Affine<n> map;
+                AffineI<n, double> map;
                 affine_identity(map);
                 int ok = 1;
 #pragma unroll
@@ -285,45 +285,44 @@ struct ChunkNewton {
                         for (int r = 0; r < n; ++r)
 #pragma unroll
                             for (int c = 0; c < n; ++c) D[r][c] = ((r == c) ? 1.0 : 0.0) - hh[i] * J[r][c];
-                        ok &= invert(D, Mi[i]) ? 1 : 0;
+                        ok &= invert_plus(D, Fi[i]) ? 1 : 0;
                         const double zero[n] = {};
                         double negR[n];
 #pragma unroll
                         for (int k = 0; k < n; ++k) negR[k] = -R[i][k];
-                        matvec_add(Mi[i], negR, zero, zi[i]);
-                        if (i == 0) {
+                        apply_ip(Fi[i], negR, zero, zi[i]);
+                        AffineI<n, double> step;
 #pragma unroll
-                            for (int r = 0; r < n; ++r) {
+                        for (int r = 0; r < n; ++r) {
 #pragma unroll
-                                for (int c = 0; c < n; ++c) map.M[r][c] = Mi[0][r][c];
-                                map.z[r] = zi[0][r];
-                            }
-                        } else {
-                            Affine<n> step;
-#pragma unroll
-                            for (int r = 0; r < n; ++r) {
-#pragma unroll
-                                for (int c = 0; c < n; ++c) step.M[r][c] = Mi[i][r][c];
-                                step.z[r] = zi[i][r];
-                            }
-                            affine_after(step, map);
-                            map = step;
+                            for (int c = 0; c < n; ++c) step.F[r][c] = Fi[i][r][c];
+                            step.z[r] = zi[i][r];
                         }
+                        if (i > 0) affine_after(step, map);
+                        map = step;
                     }
                 }
                 seg_scan_up<n, S>(map);
-                double din[n];
-                vec_prev(map.z, din);
-                if (q == 0) {
+                if constexpr (T == 1) {
+                    // the composed map's offset is the solution at the lane's step
+                    if (corr && owned(q, 0)) {
 #pragma unroll
-                    for (int k = 0; k < n; ++k) din[k] = 0.0;
-                }
+                        for (int k = 0; k < n; ++k) dy[0][k] += map.z[k];
+                    }
+                } else {
+                    double din[n];
+                    vec_prev(map.z, din);
+                    if (q == 0) {
 #pragma unroll
-                for (int i = 0; i < T; ++i) {
-                    if (corr && owned(q, i)) {
-                        matvec_add(Mi[i], din, zi[i], din);
+                        for (int k = 0; k < n; ++k) din[k] = 0.0;
+                    }
 #pragma unroll
-                        for (int k = 0; k < n; ++k) dy[i][k] += din[k];
+                    for (int i = 0; i < T; ++i) {
+                        if (corr && owned(q, i)) {
+                            apply_ip(Fi[i], din, zi[i], din);
+#pragma unroll
+                            for (int k = 0; k < n; ++k) dy[i][k] += din[k];
+                        }
                     }
                 }
                 ok = seg_and<S>(ok);
@@ -433,8 +432,8 @@ __global__ __launch_bounds__(kWave) void adjoint_kernel(SolveArgs<IO> a)
         }
 
         // ---- transposed blocks and the in-lane reverse composition
-        double Ni[T][n][n], wi[T][n], yl[T][n], hl[T], tl[T];
-        Affine<n> map;
+        double Fi[T][n][n], wi[T][n], yl[T][n], hl[T], tl[T];  // I + Fi = D^{-1} (not transposed)
+        AffineI<n, double> map;
         affine_identity(map);
         int ok = 1;
 #pragma unroll
@@ -452,34 +451,30 @@ __global__ __launch_bounds__(kWave) void adjoint_kernel(SolveArgs<IO> a)
             tl[i] = v ? ld(sv.t + k) : 0.0;
             hl[i] = v ? tl[i] - ld(sv.t + k - 1) : 0.0;
             if (v) {
-                double J[n][n], D[n][n], Mi[n][n];
+                double J[n][n], D[n][n];
                 model.jac(yl[i], tl[i], J);
 #pragma unroll
                 for (int r = 0; r < n; ++r)
 #pragma unroll
                     for (int cc = 0; cc < n; ++cc) D[r][cc] = ((r == cc) ? 1.0 : 0.0) - hl[i] * J[r][cc];
-                ok &= invert(D, Mi) ? 1 : 0;
-#pragma unroll
-                for (int r = 0; r < n; ++r)
-#pragma unroll
-                    for (int cc = 0; cc < n; ++cc) Ni[i][r][cc] = Mi[cc][r];
+                ok &= invert_plus(D, Fi[i]) ? 1 : 0;
                 const double zero[n] = {};
-                matvec_add(Ni[i], gk, zero, wi[i]);
-                Affine<n> stp;
+                apply_ip_t(Fi[i], gk, zero, wi[i]);
+                AffineI<n, double> stp;
 #pragma unroll
                 for (int r = 0; r < n; ++r) {
 #pragma unroll
-                    for (int cc = 0; cc < n; ++cc) stp.M[r][cc] = Ni[i][r][cc];
+                    for (int cc = 0; cc < n; ++cc) stp.F[r][cc] = Fi[i][cc][r];
                     stp.z[r] = wi[i][r];
                 }
-                affine_after(stp, map);
+                if (i < T - 1) affine_after(stp, map);
                 map = stp;
             }
         }
         seg_scan_down<n, S>(map);
         // lam at the first owned step of every lane, then the value entering from the right
         double vq[n], lin[n];
-        matvec_add(map.M, lam, map.z, vq);
+        apply_ip(map.F, lam, map.z, vq);
         vec_next(vq, lin);
         if (q == S - 1) {
 #pragma unroll
@@ -489,7 +484,7 @@ __global__ __launch_bounds__(kWave) void adjoint_kernel(SolveArgs<IO> a)
         for (int i = T - 1; i >= 0; --i) {
             const int j = q * T + i + 1;
             if (active && j <= m) {
-                matvec_add(Ni[i], lin, wi[i], lin);
+                apply_ip_t(Fi[i], lin, wi[i], lin);
                 double w[n];
 #pragma unroll
                 for (int k = 0; k < n; ++k) w[k] = hl[i] * lin[k];

@@ -2,13 +2,14 @@
 on the GPU by the library's kernels, and use as the Newton start.
 
 The network maps the chunk-start features x = [y_s, t_s, log dt] to the
-corrections p_j = s_j - h(y_s) of the average slopes
-s_j = (y_{s+j} - y_s) / (t_{s+j} - t_s), j = 1..C, of the converged chunk
-over the last step's slope h(y_s); the solver starts Newton from
-dy0_j = (t_{s+j} - t_s)(h(y_s) + p_j).  The untrained network (zero last
-layer) is exactly the extrapolation start, and what it learns is the
-curvature of the trajectory over the chunk.  Targets are scaled to unit
-variance for training and the scale is folded back into the last layer.
+corrections p_j = dy_j - (t_{s+j} - t_s) h(y_s), j = 1..C, of the converged
+chunk's increments dy_j = y_{s+j} - y_s over the extrapolated increments
+(the last step's slope h(y_s) carried over the chunk); the solver starts
+Newton from dy0_j = (t_{s+j} - t_s) h(y_s) + p_j.  The untrained network
+(zero last layer) is exactly the extrapolation start, and the loss is the
+mean squared error of the initial iterate itself, the quantity Newton's
+work depends on.  Targets are scaled to unit variance for training and the
+scale is folded back into the last layer.
 
 Training data are windows of trajectories that the chunked solver itself
 computed; nothing else is needed.  The parameter vector is the network's
@@ -73,8 +74,8 @@ def init_params(d, seed=0, device="cuda"):
 
 
 def chunk_samples(y, times, chunk, stride=None):
-    """Training pairs from trajectories y [B, N+1, n] on a shared grid:
-    features [y_s, t_s, log dt_s] and slopes [(y_{s+j} - y_s) / (t_{s+j} - t_s)]_j."""
+    """Training pairs from trajectories y [B, N+1, n] on a shared grid: features
+    [y_s, t_s, log dt_s], increments [y_{s+j} - y_s]_j and offsets [t_{s+j} - t_s]_j."""
     y = torch.as_tensor(y)
     t = torch.as_tensor(times, dtype=y.dtype, device=y.device)
     B, Np1, n = y.shape
@@ -82,17 +83,24 @@ def chunk_samples(y, times, chunk, stride=None):
     ys = y[:, starts]                                              # [B, S, n]
     idx = starts[:, None] + torch.arange(1, chunk + 1, device=y.device)[None]
     dt = (t[idx] - t[starts][:, None])                             # [S, chunk]
-    slopes = (y[:, idx] - ys[:, :, None]) / dt[None, :, :, None]   # [B, S, chunk, n]
+    inc = y[:, idx] - ys[:, :, None]                               # [B, S, chunk, n]
     h = t[starts + 1] - t[starts]
     feat = torch.cat([ys, t[starts][None, :, None].expand(B, -1, 1),
                       torch.log(h)[None, :, None].expand(B, -1, 1)], dim=2)
-    return feat.reshape(-1, n + 2).float().contiguous(), slopes.reshape(-1, chunk * n).float().contiguous()
+    dts = dt[None].expand(B, -1, -1).reshape(-1, chunk)
+    return (feat.reshape(-1, n + 2).float().contiguous(), inc.reshape(-1, chunk * n).float().contiguous(),
+            dts.float().contiguous())
 
 
-def slope_corrections(kind, x, s, model_params, n, chunk):
-    """Targets p_j = s_j - h(y_s) from features x (whose first n columns are y_s)."""
+def extrapolated(kind, x, dts, model_params, n):
+    """Increments of the extrapolation start, (t_{s+j} - t_s) h(y_s), for features x."""
     f, _ = tvi.model_eval(kind, x[:, :n].contiguous(), model_params, jacobian=False)
-    return (s - f.repeat(1, chunk)).contiguous()
+    return (dts[:, :, None] * f[:, None, :]).reshape(x.shape[0], -1).contiguous()
+
+
+def corrections(kind, x, inc, dts, model_params, n):
+    """Targets p_j = dy_j - (t_{s+j} - t_s) h(y_s)."""
+    return (inc - extrapolated(kind, x, dts, model_params, n)).contiguous()
 
 
 def fit_predictor(d, x, target, epochs, batch=256, lr=2e-3, seed=0):

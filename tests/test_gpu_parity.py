@@ -346,3 +346,34 @@ def test_edge_sizes(tvi):
         assert series_rel_err(host(y), yo).max() <= 1e-10
         ck, y = host(ck), host(y)
         assert np.array_equal(ck[:, 0], w["y0"]) and np.array_equal(ck[:, -1], y[:, -1])
+
+
+# --------------------------------------------------------------------------
+# Every lane tiling: the cross-lane scans for narrow segments (edges masked
+# inside a row), 32- and 64-lane segments (row broadcasts) and in-lane Thomas
+# all give the oracle's trajectory and gradient.
+# --------------------------------------------------------------------------
+def test_every_tiling_forward_and_adjoint(tvi):
+    from paper_2310_08649_amd import autotune
+    rng = np.random.default_rng(41)
+    n, B, N = 3, 37, 130
+    A = -2.0 * np.eye(n)[None] + rng.standard_normal((B, n, n))
+    p = A.reshape(B, -1)
+    y0 = rng.standard_normal((B, n))
+    times = np.cumsum(np.r_[0.0, 0.005 + 0.01 * rng.random(N)])
+    yo, so, _ = oracle.forward("linear", y0, times, p, tol=PARITY_TOL)
+    assert (so == 0).all()
+    g = yo / np.sqrt(np.sum(yo ** 2))
+    op, oy0, _ = oracle.adjoint("linear", yo, times, p, g)
+    cases = [(1, 1, 1)] + [(C, S, T) for C in (3, 4, 7, 16, 24, 40, 64, 100, 130, 256) for S, T in autotune.tilings(C)]
+    for C, S, T in cases:
+        kw = dict(chunk=C, lanes=S, steps_per_lane=T, tol=PARITY_TOL)
+        y, st, _, ck = tvi.solve_forward("linear", dev(y0), dev(times), dev(p), checkpoints=True, **kw)
+        assert (host(st) == 0).all(), (C, S, T)
+        assert series_rel_err(host(y), yo).max() <= 1e-10, (C, S, T)
+        for src in (dict(y=y), dict(ckpt=ck)):
+            dp, dy0, sa = tvi.solve_adjoint("linear", dev(times), dev(p), dev(g), **src, **kw)
+            assert (host(sa) == 0).all(), (C, S, T)
+            for a, b in ((host(dp), op), (host(dy0), oy0)):
+                err = np.abs(a - b).max(axis=1) / np.abs(b).max(axis=1)
+                assert err.max() <= 1e-10, (C, S, T, list(src), err.max())

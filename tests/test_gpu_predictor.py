@@ -93,9 +93,9 @@ def test_trained_predictor_gains_over_extrapolation(mods):
     tr = W.mlp(B=96, N=2000, seed=105)
     y, st, _, _ = tvi.solve_forward("mlp", f32(tr["y0"]), f32(tr["times"]), f32(tr["params"]), chunk=C, tol=tol)
     assert (st.cpu().numpy() == 0).all()
-    x, s = pred.chunk_samples(y, f32(tr["times"]), C)
+    x, inc, dts = pred.chunk_samples(y, f32(tr["times"]), C)
     d = pred.dims(8, C)
-    p = pred.slope_corrections("mlp", x, s, f32(tr["params"]), 8, C)
+    p = pred.corrections("mlp", x, inc, dts, f32(tr["params"]), 8)
     theta, hist = pred.fit_predictor(d, x, p, epochs=40, seed=3)
     assert hist[-1] < 0.2 * hist[0], hist
 
@@ -112,13 +112,12 @@ def test_trained_predictor_gains_over_extrapolation(mods):
         rel = np.abs(yy.cpu().numpy() - yo).max() / np.abs(yo).max()
         assert rel <= 1e-5, (init, rel)
         its[init] = int(it.sum().item())
-    # initial-iterate error on the held-out chunks: learned vs extrapolated slopes
-    xe, se = pred.chunk_samples(f32(yo), f32(ev["times"]), C)
-    fs, _ = tvi.model_eval("mlp", xe[:, :8].contiguous(), args[2], jacobian=False)
-    ext = fs.repeat(1, C)
-    err_ext = float(((ext - se) ** 2).mean().item())
-    err_pred = float(((ext + pred.forward(d, theta, xe) - se) ** 2).mean().item())
-    print("Newton corrections: zero %d, extrapolation %d, predictor %d; initial slope MSE: extrapolation %.3e, "
-          "predictor %.3e" % (its["zero"], its["extrap"], its["predictor"], err_ext, err_pred))
+    # initial-iterate error on the held-out chunks: learned vs extrapolated increments
+    xe, ie, de = pred.chunk_samples(f32(yo), f32(ev["times"]), C)
+    ext = pred.extrapolated("mlp", xe, de, args[2], 8)
+    err_ext = float(((ext - ie) ** 2).mean().item())
+    err_pred = float(((ext + pred.forward(d, theta, xe) - ie) ** 2).mean().item())
+    print("Newton corrections: zero %d, extrapolation %d, predictor %d; initial iterate MSE: extrapolation "
+          "%.3e, predictor %.3e" % (its["zero"], its["extrap"], its["predictor"], err_ext, err_pred))
     assert err_pred < 0.5 * err_ext
     assert its["predictor"] <= its["extrap"] < its["zero"]
