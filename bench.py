@@ -256,6 +256,7 @@ def run_robertson(ctx, steps):
     fms = float(np.mean(time_launches(fwd, 3, ctx["stream"])))
     seq()
     sms = float(np.mean(time_launches(seq, 3, ctx["stream"])))
+    ctx["rob_tuned"] = b
     return {"workload": "robertson n=3 B=2000 ragged N_b=exp U(ln 100, ln 2e4) log-spaced t=[1e-5,1e4] f64 "
                         "fwd+adjoint (Frobenius loss), one captured graph, states recomputed",
             "series_steps": total, "value": total / (st["mean_ms"] * 1e-3), "unit": "series*steps/s", **st,
@@ -292,7 +293,7 @@ def run_predictor(ctx, steps):
     res = {"train_chunks": int(x.shape[0]), "train_seconds": t_train, "train_loss": [hist[0], hist[-1]]}
     y_ref = None
     for init in ("zero", "extrap", "predictor"):
-        kw = dict(predictor=(net, d.hidden, C)) if init == "predictor" else {}
+        kw = dict(predictor=pred.solver_args(d, net, 8, base=1)) if init == "predictor" else {}
         fn = lambda: tvi.solve_forward("mlp", ev_y0, times, theta, chunk=C, tol=TIMING_TOL, init=init, **kw)
         yy, stt, it, _ = fn()
         ms = float(np.mean(time_launches(fn, 3, ctx["stream"])))
@@ -307,6 +308,59 @@ def run_predictor(ctx, steps):
     res["initial_iterate_mse"] = {"zero": float((ie ** 2).mean().item()),
                                   "extrap": float(((ext - ie) ** 2).mean().item()),
                                   "predictor": float(((ext + pred.forward(d, net, xe) - ie) ** 2).mean().item())}
+    out = {"mlp": res}
+    try:
+        out["robertson"] = _predictor_robertson(ctx)
+    except Exception as e:  # noqa: BLE001
+        traceback.print_exc()
+        out["robertson"] = {"error": "%s: %s" % (type(e).__name__, e)}
+    return out
+
+
+def _predictor_robertson(ctx):
+    """The same on the stiff kinetics: trained on ~1e5 chunks of 2000 other
+    ragged series, evaluated on the benchmark's ragged batch at its tuned
+    chunk and tiling."""
+    import numpy as np
+    import torch
+    from paper_2310_08649_amd import predictor as pred
+    from paper_2310_08649_amd import tvi, workloads
+    dev = ctx["dev"]
+    b = ctx.get("rob_tuned") or {"chunk": 64, "lanes": 64, "steps_per_lane": 1}
+    C, S, T = b["chunk"], b["lanes"], b["steps_per_lane"]
+    d64 = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev)
+    t0 = time.perf_counter()
+    tr = workloads.robertson(seed=106)
+    off = torch.as_tensor(tr["offsets"], device=dev)
+    y, st, _, _ = tvi.solve_forward("robertson", d64(tr["y0"]), d64(tr["times"]), d64(tr["params"]), offsets=off,
+                                    chunk=C, lanes=S, steps_per_lane=T, tol=TIMING_TOL)
+    x, ys, inc, dts, series = pred.chunk_samples_ragged(y, d64(tr["times"]), off, C)
+    ok = torch.isfinite(inc).all(dim=1)
+    d = pred.dims(3, C)
+    # corrections to the zero start: on log-spaced grids the extrapolation overshoots
+    net, hist = pred.fit_predictor(d, x[ok].contiguous(), inc[ok].float().contiguous(), epochs=20, seed=0)
+    torch.cuda.synchronize()
+    res = {"chunk": C, "lanes": S, "steps_per_lane": T, "base": "zero", "train_chunks": int(ok.sum().item()),
+           "train_seconds": time.perf_counter() - t0, "train_loss": [hist[0], hist[-1]]}
+    ev = workloads.robertson()
+    eoff = torch.as_tensor(ev["offsets"], device=dev)
+    args = (d64(ev["y0"]), d64(ev["times"]), d64(ev["params"]))
+    y_ref = None
+    for init in ("zero", "extrap", "predictor"):
+        kw = dict(predictor=pred.solver_args(d, net, 3, base=0)) if init == "predictor" else {}
+        fn = lambda: tvi.solve_forward("robertson", *args, offsets=eoff, chunk=C, lanes=S, steps_per_lane=T,
+                                       tol=TIMING_TOL, init=init, **kw)
+        yy, stt, it, _ = fn()
+        ms = float(np.mean(time_launches(fn, 3, ctx["stream"])))
+        if y_ref is None:
+            y_ref = yy.clone()
+        res[init] = {"newton_corrections": int(it.sum().item()), "newton_corrections_max": int(it.max().item()),
+                     "ms": ms, "failed": int((stt != 0).sum().item())}
+    xe, yse, ie, de, se = pred.chunk_samples_ragged(y_ref, args[1], eoff, C)
+    pe = pred.corrections_at("robertson", yse, ie, de, args[2][se].contiguous())
+    res["initial_iterate_mse"] = {"zero": float((ie ** 2).mean().item()),
+                                  "extrap": float((pe.double() ** 2).mean().item()),
+                                  "predictor": float(((ie - pred.forward(d, net, xe).double()) ** 2).mean().item())}
     return res
 
 

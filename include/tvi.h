@@ -94,10 +94,12 @@ typedef enum {
     TVI_INIT_ZERO = 0,     /* Delta y = 0 over the chunk (Section 2.3)                        */
     TVI_INIT_EXTRAP = 1,   /* extrapolate the last step's slope over the chunk:
                               dy0_j = (t_{s+j} - t_s) h(y_s, t_s)                           */
-    TVI_INIT_PREDICTOR = 2 /* the learned chunk predictor: dy0_j = (t_{s+j} - t_s) h(y_s) + p_j
-                              with p = the tvi_predictor network (n_in = n + 2: y_s, t_s,
-                              log(t_{s+1} - t_s); n_out = n * predictor_steps), kept only where
-                              its residual is below the extrapolation's; TVI_MLP only          */
+    TVI_INIT_PREDICTOR = 2 /* the learned chunk predictor: dy0_j = base_j + p_j, base = the zero
+                              start (predictor_base 0) or the extrapolated one (1), p = the
+                              tvi_predictor network (n_in = n + 2: y_s, t_s, log(t_{s+1} - t_s);
+                              n_out = n * predictor_steps), kept only where its chunk residual
+                              is below the base's.  Analytic models: needs >= 4 lanes per series
+                              and steps_per_lane * n <= 12 (TVI_EUNSUPPORTED otherwise)        */
 } tvi_init;
 
 typedef struct {
@@ -119,10 +121,12 @@ typedef struct {
                                R the chunk residual (Algorithm 1)                     */
     int32_t init;           /* tvi_init                                              */
     int32_t halving;        /* 1: retry a failed chunk at half its length, down to 1 */
-    const void *predictor;  /* TVI_INIT_PREDICTOR: device parameters (float) of the
-                               predictor, see tvi_predictor_forward                  */
+    const void *predictor;  /* TVI_INIT_PREDICTOR: the predictor's parameters in the
+                               inference layout written by tvi_predictor_pack (device) */
     int32_t predictor_hidden;  /* its hidden width, <= 256                          */
     int32_t predictor_steps;   /* steps it predicts, >= chunk                       */
+    int32_t predictor_base;    /* 0: corrections to the zero start, 1: to the
+                                  extrapolated start (TVI_INIT_EXTRAP)              */
 } tvi_options;
 
 /* Fills `opt` with the defaults: chunk 64, tol_a 1e-8, tol_r 1e-6 (Section 2.3),
@@ -257,6 +261,11 @@ tvi_status tvi_loss_grad(int32_t kind, int32_t dtype, int64_t points, int32_t n,
  *   network part of params in place.  lr = 0 only evaluates L and the
  *   gradient.
  * Both need workspace of tvi_predictor_workspace_bytes(M) bytes (device).
+ * tvi_predictor_pack         the inference layout the solvers read
+ *   (tvi_options.predictor): the same count of floats with W1, W2, W3 stored
+ *   transposed (W1^T[n_in][hidden], b1, W2^T[hidden][hidden], b2,
+ *   W3^T[hidden][n_out], b3, mean, std), so that lanes computing neighbouring
+ *   outputs read neighbouring weights.  packed must not alias params.
  */
 typedef struct {
     int32_t n_in, hidden, n_out;
@@ -269,6 +278,7 @@ tvi_status tvi_predictor_train_step(const tvi_predictor *p, int64_t M, const flo
                                     float *params, float *grad, float *adam_m, float *adam_v, int64_t step,
                                     float lr, float *loss, void *workspace, size_t workspace_bytes,
                                     void *stream);
+tvi_status tvi_predictor_pack(const tvi_predictor *p, const float *params, float *packed, void *stream);
 
 #ifdef __cplusplus
 }

@@ -79,7 +79,8 @@ tvi_status check_options(const tvi_options *o)
     if (!(o->tol_a >= 0.0) || !(o->tol_r >= 0.0)) return TVI_EINVAL;
     if (o->init != TVI_INIT_ZERO && o->init != TVI_INIT_EXTRAP && o->init != TVI_INIT_PREDICTOR) return TVI_EINVAL;
     if (o->init == TVI_INIT_PREDICTOR &&
-        (!o->predictor || o->predictor_hidden < 1 || o->predictor_hidden > 256 || o->predictor_steps < o->chunk))
+        (!o->predictor || o->predictor_hidden < 1 || o->predictor_hidden > 256 || o->predictor_steps < o->chunk ||
+         (o->predictor_base != 0 && o->predictor_base != 1)))
         return TVI_EINVAL;
     return TVI_OK;
 }
@@ -107,6 +108,7 @@ SolveArgs<IO> make_args(const tvi_model *model, const tvi_options *opt, int64_t 
     a.pred = static_cast<const float *>(opt->predictor);
     a.pred_hidden = opt->predictor_hidden;
     a.pred_steps = opt->predictor_steps;
+    a.pred_base = opt->predictor_base;
     return a;
 }
 
@@ -146,6 +148,7 @@ void tvi_default_options(tvi_options *opt)
     opt->predictor = nullptr;
     opt->predictor_hidden = 0;
     opt->predictor_steps = 0;
+    opt->predictor_base = 1;
 }
 
 const char *tvi_status_str(int32_t s)
@@ -210,10 +213,10 @@ tvi_status tvi_solve_forward(const tvi_model *model, const tvi_options *opt, int
     int S = 0, T = 0;
     if (model->kind == TVI_MLP) {
         if (opt->chunk > 128) return TVI_EUNSUPPORTED;
-    } else if (opt->init == TVI_INIT_PREDICTOR) {
-        return TVI_EUNSUPPORTED;
     } else if ((e = resolve_tiling(opt, S, T)) != TVI_OK) {
         return e;
+    } else if (opt->init == TVI_INIT_PREDICTOR && (S < 4 || T * model->n > kPredictorMaxTN)) {
+        return TVI_EUNSUPPORTED;  // the network is shared by a segment's lanes; register budget
     }
     const hipStream_t st = static_cast<hipStream_t>(stream);
     if (model->dtype == TVI_F64) {
@@ -284,6 +287,8 @@ tvi_status tvi_solve_adjoint(const tvi_model *model, const tvi_options *opt, int
     }
     int S, T;
     if ((e = resolve_tiling(opt, S, T)) != TVI_OK) return e;
+    if (recompute && opt->init == TVI_INIT_PREDICTOR && (S < 4 || T * model->n > kPredictorMaxTN))
+        return TVI_EUNSUPPORTED;
     const int pass = recompute ? PASS_ADJOINT_RECOMPUTE : PASS_ADJOINT;
     const hipStream_t st = static_cast<hipStream_t>(stream);
     if (model->dtype == TVI_F64) {
@@ -352,6 +357,12 @@ tvi_status tvi_predictor_forward(const tvi_predictor *p, int64_t M, const float 
         return TVI_EINVAL;
     return predictor_forward(p->n_in, p->hidden, p->n_out, M, x, params, out, workspace,
                              static_cast<hipStream_t>(stream));
+}
+
+tvi_status tvi_predictor_pack(const tvi_predictor *p, const float *params, float *packed, void *stream)
+{
+    if (!pred_ok(p) || !params || !packed || params == packed) return TVI_EINVAL;
+    return predictor_pack(p->n_in, p->hidden, p->n_out, params, packed, static_cast<hipStream_t>(stream));
 }
 
 tvi_status tvi_predictor_train_step(const tvi_predictor *p, int64_t M, const float *x, const float *target,

@@ -19,11 +19,14 @@ static tvi_status launch_st(int pass, const SolveArgs<IO> &a, hipStream_t stream
     if (blocks == 0) return TVI_OK;
     if (blocks > 0x7fffffffLL) return TVI_EINVAL;
     dim3 grid((unsigned)blocks), block(kWave);
+    // the learned predictor's hidden layers and outputs: [segments][2H + n S T] floats of LDS
+    const size_t lds =
+        a.init == INIT_PREDICTOR ? (size_t)per_block * (2 * a.pred_hidden + Model::N * S * T) * sizeof(float) : 0;
     switch (pass) {
-    case PASS_FORWARD: hipLaunchKernelGGL((forward_kernel<Model, IO, S, T>), grid, block, 0, stream, a); break;
+    case PASS_FORWARD: hipLaunchKernelGGL((forward_kernel<Model, IO, S, T>), grid, block, lds, stream, a); break;
     case PASS_ADJOINT: hipLaunchKernelGGL((adjoint_kernel<Model, IO, S, T, false>), grid, block, 0, stream, a); break;
     case PASS_ADJOINT_RECOMPUTE:
-        hipLaunchKernelGGL((adjoint_kernel<Model, IO, S, T, true>), grid, block, 0, stream, a);
+        hipLaunchKernelGGL((adjoint_kernel<Model, IO, S, T, true>), grid, block, lds, stream, a);
         break;
     default: return TVI_EINVAL;
     }
@@ -78,6 +81,7 @@ int64_t predictor_param_count(int n_in, int H, int n_out);
 size_t predictor_workspace_bytes(int n_in, int H, int n_out, int64_t M);
 tvi_status predictor_forward(int n_in, int H, int n_out, int64_t M, const float *x, const float *params, float *out,
                              void *ws, hipStream_t st);
+tvi_status predictor_pack(int n_in, int H, int n_out, const float *params, float *packed, hipStream_t st);
 tvi_status predictor_train_step(int n_in, int H, int n_out, int64_t M, const float *x, const float *target,
                                 float *params, float *grad, float *adam_m, float *adam_v, int64_t step, float lr,
                                 float *loss, void *ws, hipStream_t st);

@@ -152,17 +152,17 @@ __device__ __noinline__ float chunk_residual_norm(MlpShared &S, const double (&y
     return chunk_residual(S, A, ys, dy, hj, v, R);
 }
 
-__device__ __forceinline__ float gelu_f(float x) { return 0.5f * x * (1.f + erff(x * 0.70710678118654752f)); }
-
-// The learned predictor's slopes for the chunk starting at (ys, ts) with first
-// step dts: out[o], o < m * NS, in LDS (block-wide; every thread calls it).
-// params = W1[Hp][NS+2], b1, W2[Hp][Hp], b2, W3[NS*steps][Hp], b3, mean[NS+2], std[NS+2].
+// The learned predictor's corrections for the chunk starting at (ys, ts) with
+// first step dts: out[o], o < m * NS, in LDS (block-wide; every thread calls it).
+// params in the inference layout: W1^T[NS+2][Hp], b1, W2^T[Hp][Hp], b2,
+// W3^T[Hp][NS*steps], b3, mean[NS+2], std[NS+2]; neighbouring threads compute
+// neighbouring units and read neighbouring weights.
 __device__ void predictor_corrections(float *a1, float *a2, float *out, const float *pp, int Hp, int steps,
-                                 const double (&ys)[NS], double ts, double dts, int m)
+                                      const double (&ys)[NS], double ts, double dts, int m)
 {
     const int tid = threadIdx.x, nin = NS + 2, nout = NS * steps;
-    const float *W1 = pp, *b1 = W1 + Hp * nin, *W2 = b1 + Hp, *b2 = W2 + Hp * Hp, *W3 = b2 + Hp,
-                *b3 = W3 + (int64_t)nout * Hp, *mu = b3 + nout, *sd = mu + nin;
+    const float *W1 = pp, *b1 = W1 + nin * Hp, *W2 = b1 + Hp, *b2 = W2 + (int64_t)Hp * Hp, *W3 = b2 + Hp,
+                *b3 = W3 + (int64_t)Hp * nout, *mu = b3 + nout, *sd = mu + nin;
     float x[NS + 2];
 #pragma unroll
     for (int k = 0; k < NS; ++k) x[k] = (float)ys[k];
@@ -173,21 +173,13 @@ __device__ void predictor_corrections(float *a1, float *a2, float *out, const fl
     for (int o = tid; o < Hp; o += kThreads) {
         float z = b1[o];
 #pragma unroll
-        for (int k = 0; k < NS + 2; ++k) z = fmaf(W1[o * nin + k], x[k], z);
+        for (int k = 0; k < NS + 2; ++k) z = fmaf(W1[k * Hp + o], x[k], z);
         a1[o] = gelu_f(z);
     }
     __syncthreads();
-    for (int o = tid; o < Hp; o += kThreads) {
-        float z = b2[o];
-        for (int k = 0; k < Hp; ++k) z = fmaf(W2[(int64_t)o * Hp + k], a1[k], z);
-        a2[o] = gelu_f(z);
-    }
+    dense_t<2>(W2, Hp, b2, a1, Hp, tid, kThreads, Hp, a2, true);
     __syncthreads();
-    for (int o = tid; o < m * NS; o += kThreads) {
-        float z = b3[o];
-        for (int k = 0; k < Hp; ++k) z = fmaf(W3[(int64_t)o * Hp + k], a2[k], z);
-        out[o] = z;
-    }
+    dense_t<2>(W3, nout, b3, a2, Hp, tid, kThreads, m * NS, out, false);
     __syncthreads();
 }
 
@@ -242,7 +234,7 @@ __device__ int mlp_solve(MlpShared &S, const SolveArgs<IO> &a, const IO *t, doub
             const float tj = (float)(t1 - ts);
 #pragma unroll
             for (int k = 0; k < NS; ++k) dy[k] = 0.f;
-            if (a.init == INIT_EXTRAP || a.init == INIT_PREDICTOR) {
+            if (a.init == INIT_EXTRAP || (a.init == INIT_PREDICTOR && a.pred_base == 1)) {
                 // the slope of the last step: h(y_s) for backward Euler
                 if (writer) {
 #pragma unroll
@@ -257,17 +249,17 @@ __device__ int mlp_solve(MlpShared &S, const SolveArgs<IO> &a, const IO *t, doub
                 }
             }
             if (a.init == INIT_PREDICTOR) {
-                // the learned start: the extrapolated increments plus the predicted
-                // corrections, kept only if its residual is below the extrapolation's
+                // the learned start: its base (zero or extrapolated increments) plus the
+                // predicted corrections, kept only if its residual is below the base's
                 float *scratch = &S.u.v.a[0][0][0];
                 predictor_corrections(scratch, scratch + 256, scratch + 512, a.pred, a.pred_hidden, a.pred_steps, ys, ts,
                                  ld(t + s + 1) - ts, m);
                 float dyp[NS];
 #pragma unroll
                 for (int k = 0; k < NS; ++k) dyp[k] = v ? dy[k] + scratch[512 + j * NS + k] : 0.f;
-                const float n_ext = chunk_residual_norm(S, ys, dy, hj, v);
+                const float n_base = chunk_residual_norm(S, ys, dy, hj, v);
                 const float n_pred = chunk_residual_norm(S, ys, dyp, hj, v);
-                if (n_pred < n_ext) {
+                if (n_pred < n_base) {
 #pragma unroll
                     for (int k = 0; k < NS; ++k) dy[k] = dyp[k];
                     ++accepted;

@@ -5,6 +5,8 @@
 // a chunk's initial Newton iterate.  Float32 on the vector ALUs: tiled
 // products with every output element accumulated by one thread in a fixed
 // order, so results are deterministic.
+#include <algorithm>
+
 #include "dispatch.hpp"
 
 namespace tvi {
@@ -240,6 +242,41 @@ static void forward(hipStream_t st, const Layout &L, int M, const float *x, cons
 } // namespace pred
 
 int64_t predictor_param_count(int n_in, int H, int n_out) { return pred::Layout(n_in, H, n_out).P + 2 * n_in; }
+
+namespace pred {
+// Inference layout: the three weight matrices transposed (rows of length R
+// become columns), everything else copied, offsets unchanged.
+__global__ void pack_kernel(int n_in, int H, int n_out, int64_t count, const float *__restrict__ src,
+                            float *__restrict__ dst)
+{
+    const int64_t w1 = 0, b1 = w1 + (int64_t)H * n_in, w2 = b1 + H, b2 = w2 + (int64_t)H * H, w3 = b2 + H,
+                  b3 = w3 + (int64_t)n_out * H;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t from = i;
+        if (i < b1) {                        // W1^T[k][u] = W1[u][k]
+            const int64_t k = (i - w1) / H, u = (i - w1) % H;
+            from = w1 + u * n_in + k;
+        } else if (i >= w2 && i < b2) {      // W2^T[k][u] = W2[u][k]
+            const int64_t k = (i - w2) / H, u = (i - w2) % H;
+            from = w2 + u * H + k;
+        } else if (i >= w3 && i < b3) {      // W3^T[k][o] = W3[o][k]
+            const int64_t k = (i - w3) / n_out, o = (i - w3) % n_out;
+            from = w3 + o * H + k;
+        }
+        dst[i] = src[from];
+    }
+}
+} // namespace pred
+
+tvi_status predictor_pack(int n_in, int H, int n_out, const float *params, float *packed, hipStream_t st)
+{
+    const int64_t count = predictor_param_count(n_in, H, n_out);
+    const int64_t blocks = std::min<int64_t>((count + 255) / 256, 4096);
+    hipLaunchKernelGGL(pred::pack_kernel, dim3((unsigned)blocks), dim3(256), 0, st, n_in, H, n_out, count, params,
+                       packed);
+    return hipGetLastError() == hipSuccess ? TVI_OK : TVI_EHIP;
+}
 
 size_t predictor_workspace_bytes(int n_in, int H, int n_out, int64_t M)
 {

@@ -44,8 +44,8 @@ struct SolveArgs {
     const IO *g;               // adjoint: dL/dy
     IO *dLdp, *dLdy0;
     double *ws;                // adjoint recompute workspace [B][chunk][n]
-    const float *pred;         // learned chunk predictor parameters (INIT_PREDICTOR)
-    int32_t pred_hidden, pred_steps;
+    const float *pred;         // learned chunk predictor, inference layout (INIT_PREDICTOR)
+    int32_t pred_hidden, pred_steps, pred_base;
 };
 
 template <class IO>
@@ -118,10 +118,56 @@ struct WorkspaceSink {
     __device__ __forceinline__ void fail(int64_t, int) const {}
 };
 
+// The learned chunk predictor as the solver sees it: network parameters in
+// the inference layout (W1^T[n+2][H], b1[H], W2^T[H][H], b2[H],
+// W3^T[H][n*steps], b3[n*steps], mean[n+2], std[n+2], float32), the start it
+// corrects (0 zero, 1 extrapolation) and the wave's LDS scratch,
+// [64/S][2H + n S T] floats.
+constexpr int kPredictorMaxTN = 12;  // owned values per lane for which the learned start is compiled
+
+struct PredictorRef {
+    const float *p;
+    int H, steps, base;
+    float *lds;
+};
+
+__device__ __forceinline__ float gelu_f(float x) { return 0.5f * x * (1.f + erff(x * 0.70710678118654752f)); }
+
+// out[o] = act(b[o] + sum_k Wt[k ld + o] in[k]) for o = o0, o0 + stride, ... < no:
+// a layer of the predictor from transposed weights (Wt[K][ld]) and an input
+// vector in LDS.  G outputs per pass share every read of `in` and keep G
+// independent accumulators (and G loads in flight per k); lanes of a pass
+// read neighbouring weights.
+template <int G>
+__device__ __forceinline__ void dense_t(const float *__restrict__ Wt, int ld, const float *__restrict__ b,
+                                        const float *in, int K, int o0, int stride, int no, float *out, bool gelu)
+{
+    for (int ob = o0; ob < no; ob += G * stride) {
+        float acc[G];
+        int oi[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            oi[g] = min(ob + g * stride, no - 1);  // clamped: a surplus accumulator is discarded
+            acc[g] = b[oi[g]];
+        }
+#pragma unroll 4
+        for (int k = 0; k < K; ++k) {
+            const float a = in[k];
+            const float *w = Wt + (int64_t)k * ld;
+#pragma unroll
+            for (int g = 0; g < G; ++g) acc[g] = fmaf(w[oi[g]], a, acc[g]);
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+            if (ob + g * stride < no) out[ob + g * stride] = gelu ? gelu_f(acc[g]) : acc[g];
+    }
+}
+
 // Per-lane state of the chunked Newton solve of one series.
 template <class Model, int S, int T>
 struct ChunkNewton {
     static constexpr int n = Model::N;
+    static constexpr bool kPredictorT = T * n <= kPredictorMaxTN;  // register budget of the learned start
 
     double ys[n];      // state at the chunk start
     int64_t s;         // chunk start step
@@ -135,15 +181,101 @@ struct ChunkNewton {
     int status;
     double dy[T][n];   // Newton iterate Delta y of the owned steps
     double tt[T], hh[T];
+    double t_s, h_s;   // time and first step of the current attempt (predictor features)
 
     __device__ __forceinline__ bool owned(int q, int i) const { return active && (q * T + i + 1 <= m); }
+
+    // Backward-Euler residual of the chunk at iterate d (owned steps; zero
+    // elsewhere), stored in R if KEEP, and its Euclidean norm over the segment.
+    // Wave-uniform.
+    template <bool KEEP>
+    __device__ __forceinline__ double residual(const Model &model, const double (&d)[T][n], int q,
+                                               double (&R)[T][n]) const
+    {
+        double prev[n];
+        vec_prev(d[T - 1], prev);
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < T; ++i) {
+            double yv[n], f[n];
+#pragma unroll
+            for (int k = 0; k < n; ++k) yv[k] = ys[k] + d[i][k];
+            model.rhs(yv, tt[i], f);
+            const bool v = owned(q, i);
+#pragma unroll
+            for (int k = 0; k < n; ++k) {
+                const double dp = (i == 0) ? (q > 0 ? prev[k] : 0.0) : d[i - 1][k];
+                const double r = v ? (d[i][k] - dp) - hh[i] * f[k] : 0.0;
+                if (KEEP) R[i][k] = r;
+                acc = fma(r, r, acc);
+            }
+        }
+        return sqrt(seg_sum<S>(acc));
+    }
+
+    // The extrapolated start: dy_j = (t_{s+j} - t_s) h(y_s) on the owned steps.
+    __device__ __forceinline__ void extrapolate(const Model &model, int q, bool zero)
+    {
+        double slope[n];
+        if (zero) {
+#pragma unroll
+            for (int k = 0; k < n; ++k) slope[k] = 0.0;
+        } else {
+            model.rhs(ys, t_s, slope);
+        }
+#pragma unroll
+        for (int i = 0; i < T; ++i) {
+            const bool v = q * T + i + 1 <= m;
+#pragma unroll
+            for (int k = 0; k < n; ++k) dy[i][k] = v ? (tt[i] - t_s) * slope[k] : 0.0;
+        }
+    }
+
+    // The predictor's corrections for the lane's owned steps of the current
+    // attempt (chunk start ys, t_s, first step h_s) where `want` (segment-uniform).
+    // The S lanes of a segment
+    // share the hidden layers and the outputs through LDS; neighbouring lanes
+    // compute neighbouring units and read neighbouring (transposed) weights.
+    // Every lane of the wave calls it.
+    __device__ void predict(const PredictorRef &pr, int q, int seg, bool want, double (&pc)[T][n]) const
+    {
+        const int H = pr.H, nin = n + 2, nout = n * pr.steps;
+        const float *W1 = pr.p, *b1 = W1 + nin * H, *W2 = b1 + H, *b2 = W2 + (int64_t)H * H, *W3 = b2 + H,
+                    *b3 = W3 + (int64_t)H * nout, *mu = b3 + nout, *sd = mu + nin;
+        float x[n + 2];
+#pragma unroll
+        for (int k = 0; k < n; ++k) x[k] = (float)ys[k];
+        x[n] = (float)t_s;
+        x[n + 1] = (float)log(h_s);
+#pragma unroll
+        for (int k = 0; k < n + 2; ++k) x[k] = (x[k] - mu[k]) / sd[k];
+        float *a1 = pr.lds + seg * (2 * H + n * S * T), *a2 = a1 + H, *out = a2 + H;
+        for (int u = q; u < H; u += S) {
+            float z = b1[u];
+#pragma unroll
+            for (int k = 0; k < n + 2; ++k) z = fmaf(W1[k * H + u], x[k], z);
+            a1[u] = gelu_f(z);
+        }
+        __syncthreads();
+        dense_t<4>(W2, H, b2, a1, H, q, S, H, a2, true);
+        __syncthreads();
+        dense_t<4>(W3, nout, b3, a2, H, q, S, want ? m * n : 0, out, false);  // this attempt's outputs (m <= S T)
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < T; ++i) {
+            const int j = q * T + i;  // 0-based step of the chunk
+#pragma unroll
+            for (int k = 0; k < n; ++k) pc[i][k] = (want && j < m) ? (double)out[j * n + k] : 0.0;
+        }
+        __syncthreads();
+    }
 
     // Solve steps s..s_end from ys (already set).  C is the nominal chunk
     // length: attempts never cross a multiple of C, so a checkpoint at every
     // multiple of C restarts the identical sequence of attempts.
     template <class IO, class Sink>
     __device__ void run(const Model &model, const IO *t, int C, int max_newton, double tol_a, double tol_r,
-                        int init, bool halving, const Sink &sink)
+                        int init, bool halving, const Sink &sink, const PredictorRef &pr)
     {
         const int lane = lane_id();
         const int q = lane & (S - 1);
@@ -157,20 +289,15 @@ struct ChunkNewton {
         ck_next = s / C + 1;
         ck_at = ck_next * C;
         double Fi[T][n][n], zi[T][n], R[T][n];
+        bool fresh = false;  // an attempt whose initial iterate the predictor may still replace
 
         while (wave_any(active)) {
             // ---- attempt set-up: owned times and the initial iterate (lane-local)
             if (active && start) {
                 const int64_t nom_end = min(ck_at, s_end);
                 m = (int)min((int64_t)mcur, nom_end - s);
-                const double ts = ld(t + s);
-                double slope[n];
-                if (init == INIT_EXTRAP) {
-                    model.rhs(ys, ts, slope);
-                } else {
-#pragma unroll
-                    for (int k = 0; k < n; ++k) slope[k] = 0.0;
-                }
+                t_s = ld(t + s);
+                h_s = ld(t + s + 1) - t_s;
 #pragma unroll
                 for (int i = 0; i < T; ++i) {
                     const int j = q * T + i + 1;
@@ -179,34 +306,32 @@ struct ChunkNewton {
                     tt[i] = ld(t + kk);
                     const double tp = (i == 0) ? ld(t + (v ? kk - 1 : s)) : tt[i - 1];
                     hh[i] = v ? tt[i] - tp : 0.0;
-#pragma unroll
-                    for (int k = 0; k < n; ++k) dy[i][k] = v ? (tt[i] - ts) * slope[k] : 0.0;
                 }
+                extrapolate(model, q, init == INIT_ZERO || (init == INIT_PREDICTOR && pr.base == 0));
                 it = 0;
                 sing = false;
                 start = false;
+                fresh = true;
             }
 
-            // ---- residual of the owned steps and its segment norm
-            double prev[n];
-            vec_prev(dy[T - 1], prev);
-            double acc = 0.0;
+            // ---- learned start: its base (zero or extrapolation) plus the predicted
+            // corrections, kept where its residual is below the base's
+            // (instances with T n > kPredictorMaxTN leave it out: the host rejects the predictor there)
+            if (kPredictorT && init == INIT_PREDICTOR && wave_any(fresh)) {
+                double pc[T][n];
+                predict(pr, q, lane / S, fresh, pc);
+                const double n_base = residual<false>(model, dy, q, R);
 #pragma unroll
-            for (int i = 0; i < T; ++i) {
-                double yv[n], f[n];
+                for (int i = 0; i < T; ++i)
 #pragma unroll
-                for (int k = 0; k < n; ++k) yv[k] = ys[k] + dy[i][k];
-                model.rhs(yv, tt[i], f);
-                const bool v = owned(q, i);
-#pragma unroll
-                for (int k = 0; k < n; ++k) {
-                    const double dp = (i == 0) ? (q > 0 ? prev[k] : 0.0) : dy[i - 1][k];
-                    const double r = (dy[i][k] - dp) - hh[i] * f[k];
-                    R[i][k] = v ? r : 0.0;
-                    acc = fma(R[i][k], R[i][k], acc);
-                }
+                    for (int k = 0; k < n; ++k) dy[i][k] += (fresh && owned(q, i)) ? pc[i][k] : 0.0;
+                const double n_pred = residual<false>(model, dy, q, R);
+                if (fresh && !(n_pred < n_base)) extrapolate(model, q, pr.base == 0);
             }
-            const double nrm = sqrt(seg_sum<S>(acc));
+            fresh = false;
+
+            // ---- residual of the owned steps and its segment norm
+            const double nrm = residual<true>(model, dy, q, R);
 
             // ---- per-series decision (uniform within the segment)
             int act = 0; // 1 converged, 2 failed, 3 correct
@@ -369,7 +494,9 @@ __global__ __launch_bounds__(kWave) void forward_kernel(SolveArgs<IO> a)
     cn.total = 0;
     cn.status = ST_OK;
     cn.active = sv.valid && sv.Nb > 0;
-    cn.run(model, sv.t, a.chunk, a.max_newton, a.tol_a, a.tol_r, a.init, a.halving != 0, sink);
+    extern __shared__ float pred_lds[];
+    cn.run(model, sv.t, a.chunk, a.max_newton, a.tol_a, a.tol_r, a.init, a.halving != 0, sink,
+           PredictorRef{a.pred, a.pred_hidden, a.pred_steps, a.pred_base, pred_lds});
     if (sv.valid && q == 0) {
         a.status[sv.b] = cn.status;
         if (a.iters) a.iters[sv.b] = cn.total;
@@ -426,7 +553,9 @@ __global__ __launch_bounds__(kWave) void adjoint_kernel(SolveArgs<IO> a)
 #pragma unroll
             for (int k = 0; k < n; ++k) cn.ys[k] = have_ckpt ? a.ckpt[(sv.b * a.K + c) * n + k] : 0.0;
             WorkspaceSink<n> wsink{wsb, s};
-            cn.run(model, sv.t, C, a.max_newton, a.tol_a, a.tol_r, a.init, a.halving != 0, wsink);
+            extern __shared__ float pred_lds[];
+            cn.run(model, sv.t, C, a.max_newton, a.tol_a, a.tol_r, a.init, a.halving != 0, wsink,
+                   PredictorRef{a.pred, a.pred_hidden, a.pred_steps, a.pred_base, pred_lds});
             if (active && cn.status != ST_OK) status = cn.status;
             __syncthreads(); // one wave per block: makes the workspace writes visible to the wave
         }

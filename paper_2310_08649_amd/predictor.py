@@ -2,13 +2,14 @@
 on the GPU by the library's kernels, and use as the Newton start.
 
 The network maps the chunk-start features x = [y_s, t_s, log dt] to the
-corrections p_j = dy_j - (t_{s+j} - t_s) h(y_s), j = 1..C, of the converged
-chunk's increments dy_j = y_{s+j} - y_s over the extrapolated increments
-(the last step's slope h(y_s) carried over the chunk); the solver starts
-Newton from dy0_j = (t_{s+j} - t_s) h(y_s) + p_j.  The untrained network
-(zero last layer) is exactly the extrapolation start, and the loss is the
-mean squared error of the initial iterate itself, the quantity Newton's
-work depends on.  Targets are scaled to unit variance for training and the
+corrections p_j = dy_j - base_j, j = 1..C, of the converged chunk's
+increments dy_j = y_{s+j} - y_s over a base start: the extrapolated
+increments (t_{s+j} - t_s) h(y_s) (base 1; the last step's slope carried over
+the chunk), or zero (base 0; the paper's start, better where extrapolation
+over a chunk overshoots, as on log-spaced grids).  The solver starts Newton
+from dy0_j = base_j + p_j.  The untrained network (zero last layer) is exactly
+the base start, and the loss is the mean squared error of the initial iterate
+itself, the quantity Newton's work depends on.  Targets are scaled to unit variance for training and the
 scale is folded back into the last layer.
 
 Training data are windows of trajectories that the chunked solver itself
@@ -44,6 +45,8 @@ def _lib():
         lib.tvi_predictor_forward.restype = i32
         lib.tvi_predictor_train_step.argtypes = [PP, i64, P, P, P, P, P, P, i64, f32, P, P, sz, P]
         lib.tvi_predictor_train_step.restype = i32
+        lib.tvi_predictor_pack.argtypes = [PP, P, P, P]
+        lib.tvi_predictor_pack.restype = i32
         lib._pred_bound = True
     return lib
 
@@ -92,6 +95,39 @@ def chunk_samples(y, times, chunk, stride=None):
             dts.float().contiguous())
 
 
+def chunk_samples_ragged(y, times, offsets, chunk):
+    """Pairs from ragged series (y [points, n], times [points], point offsets
+    [B+1]) at the nominal chunk starts s = 0, C, 2C, ... of every series that
+    has C more steps: float features, and in y's precision the chunk-start
+    states, increments [y_{s+j} - y_s]_j, offsets [t_{s+j} - t_s]_j, and the
+    series index of each pair."""
+    y = torch.as_tensor(y)
+    t = torch.as_tensor(times, dtype=y.dtype, device=y.device)
+    off = torch.as_tensor(offsets, device=y.device).long()
+    p0 = off[:-1]
+    steps = off[1:] - off[:-1] - 1
+    nck = torch.div(steps, chunk, rounding_mode="floor")            # full chunks per series
+    series = torch.repeat_interleave(torch.arange(nck.shape[0], device=y.device), nck)
+    first = torch.cumsum(nck, 0) - nck
+    c = torch.arange(series.shape[0], device=y.device) - first[series]
+    start = p0[series] + c * chunk                                   # point index of y_s
+    idx = start[:, None] + torch.arange(1, chunk + 1, device=y.device)[None]
+    ys = y[start]
+    inc = y[idx] - ys[:, None, :]
+    dts = t[idx] - t[start][:, None]
+    feat = torch.cat([ys, t[start][:, None], torch.log(t[start + 1] - t[start])[:, None]], dim=1)
+    return feat.float().contiguous(), ys.contiguous(), inc.reshape(inc.shape[0], -1).contiguous(), \
+        dts.contiguous(), series
+
+
+def corrections_at(kind, ys, inc, dts, model_params):
+    """Targets p_j = dy_j - (t_{s+j} - t_s) h(y_s) from the chunk-start states ys
+    (in their own precision; model_params per pair or shared), as float."""
+    f, _ = tvi.model_eval(kind, ys, model_params, jacobian=False)
+    ext = (dts[:, :, None] * f[:, None, :]).reshape(ys.shape[0], -1)
+    return (inc - ext).float().contiguous()
+
+
 def extrapolated(kind, x, dts, model_params, n):
     """Increments of the extrapolation start, (t_{s+j} - t_s) h(y_s), for features x."""
     f, _ = tvi.model_eval(kind, x[:, :n].contiguous(), model_params, jacobian=False)
@@ -123,6 +159,21 @@ def set_standardisation(theta, d, x):
     theta[P:P + d.n_in] = mu
     theta[P + d.n_in:P + 2 * d.n_in] = sd
     return theta
+
+
+def pack(d, theta):
+    """The inference layout the solvers read (weights transposed), a new tensor."""
+    out = torch.empty_like(theta)
+    tvi._check(_lib().tvi_predictor_pack(ctypes.byref(d), tvi._ptr(theta), tvi._ptr(out), tvi._stream()),
+               "tvi_predictor_pack")
+    return out
+
+
+def solver_args(d, theta, n, base=1):
+    """The ``predictor=`` argument of ``tvi.solve_forward`` / ``solve_adjoint``
+    for a network trained on corrections to the zero start (base 0) or to the
+    extrapolated start (base 1)."""
+    return (pack(d, theta), d.hidden, d.n_out // n, base)
 
 
 def forward(d, theta, x):

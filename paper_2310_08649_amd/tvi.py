@@ -44,7 +44,8 @@ class Options(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_int32), ("lanes", ctypes.c_int32), ("steps_per_lane", ctypes.c_int32),
                 ("max_newton", ctypes.c_int32), ("tol_a", ctypes.c_double), ("tol_r", ctypes.c_double),
                 ("init", ctypes.c_int32), ("halving", ctypes.c_int32), ("predictor", ctypes.c_void_p),
-                ("predictor_hidden", ctypes.c_int32), ("predictor_steps", ctypes.c_int32)]
+                ("predictor_hidden", ctypes.c_int32), ("predictor_steps", ctypes.c_int32),
+                ("predictor_base", ctypes.c_int32)]
 
 
 _lib = None
@@ -121,7 +122,9 @@ def param_count(kind, n, hidden=64):
 
 def make_options(chunk=64, tol=(1e-8, 1e-6), max_newton=50, lanes=0, steps_per_lane=0, init="zero",
                  halving=True, predictor=None):
-    """``predictor``: (params tensor, hidden, steps) of a trained chunk predictor."""
+    """``predictor``: (packed params, hidden, steps[, base]) of a trained chunk
+    predictor, as made by ``predictor.solver_args`` (base 0: corrections to the
+    zero start, 1: to the extrapolated start)."""
     o = Options()
     load().tvi_default_options(ctypes.byref(o))
     o.chunk = int(chunk)
@@ -131,9 +134,10 @@ def make_options(chunk=64, tol=(1e-8, 1e-6), max_newton=50, lanes=0, steps_per_l
     o.init = INIT[init] if isinstance(init, str) else int(init)
     o.halving = 1 if halving else 0
     if predictor is not None:
-        params, hidden, steps = predictor
+        params, hidden, steps = predictor[:3]
         o.predictor = ctypes.c_void_p(params.data_ptr())
         o.predictor_hidden, o.predictor_steps = int(hidden), int(steps)
+        o.predictor_base = int(predictor[3]) if len(predictor) > 3 else 1
     return o
 
 

@@ -106,7 +106,7 @@ def test_trained_predictor_gains_over_extrapolation(mods):
                               ev["params"].astype(np.float32), tol=(1e-12, 1e-12))
     its = {}
     for init in ("zero", "extrap", "predictor"):
-        kw = dict(predictor=(theta, d.hidden, C)) if init == "predictor" else {}
+        kw = dict(predictor=pred.solver_args(d, theta, 8, base=1)) if init == "predictor" else {}
         yy, st, it, _ = tvi.solve_forward("mlp", *args, chunk=C, tol=tol, init=init, **kw)
         assert (st.cpu().numpy() == 0).all()
         rel = np.abs(yy.cpu().numpy() - yo).max() / np.abs(yo).max()
@@ -121,3 +121,79 @@ def test_trained_predictor_gains_over_extrapolation(mods):
           "%.3e, predictor %.3e" % (its["zero"], its["extrap"], its["predictor"], err_ext, err_pred))
     assert err_pred < 0.5 * err_ext
     assert its["predictor"] <= its["extrap"] < its["zero"]
+
+
+def _dev64(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def test_untrained_predictor_start_is_its_base(mods):
+    """A network with a zero last layer proposes exactly its base start (the
+    extrapolation, or zero), which is then kept: trajectories and iteration
+    counts are bitwise equal to those of that start."""
+    pred, tvi = mods
+    for kind, w, C in (
+            ("vanderpol", W.vanderpol(B=64, N=1000, mu_range=(1.0, 100.0)), 50),
+            ("robertson", W.robertson(B=40, n_range=(100, 1500)), 64),
+            ("linear", W.linear(B=8, N=200), 20)):
+        n = w["y0"].shape[1]
+        off = None if w["offsets"] is None else torch.as_tensor(w["offsets"], device="cuda")
+        d = pred.dims(n, C)
+        theta = pred.init_params(d, seed=2)
+        args = (_dev64(w["y0"]), _dev64(w["times"]), _dev64(w["params"]))
+        for base, init in ((1, "extrap"), (0, "zero")):
+            ye, se, ie, _ = tvi.solve_forward(kind, *args, offsets=off, chunk=C, init=init)
+            yp, sp, ip, _ = tvi.solve_forward(kind, *args, offsets=off, chunk=C, init="predictor",
+                                              predictor=pred.solver_args(d, theta, n, base=base))
+            assert torch.equal(se, sp) and torch.equal(ie, ip), (kind, init)
+            assert torch.equal(torch.nan_to_num(ye), torch.nan_to_num(yp)), (kind, init)
+
+
+def test_predictor_on_robertson(mods):
+    """Train on ragged Robertson chunks the solver computed (corrections to the
+    zero start: on log-spaced grids the extrapolation overshoots), then solve
+    held-out series from the learned start: the oracle's trajectory, a smaller
+    initial iterate error than the zero start, and the recomputing adjoint
+    (which re-runs the predictor from every checkpoint) bitwise equal to the
+    adjoint on the stored trajectory."""
+    pred, tvi = mods
+    from tests.helpers import PARITY_TOL, TIMING_TOL, series_rel_err
+    C = 64
+    tr = W.robertson(B=300, seed=106, n_range=(200, 4000))
+    off = torch.as_tensor(tr["offsets"], device="cuda")
+    y, st, _, _ = tvi.solve_forward("robertson", _dev64(tr["y0"]), _dev64(tr["times"]), _dev64(tr["params"]),
+                                    offsets=off, chunk=C, tol=TIMING_TOL)
+    assert (st.cpu().numpy() == 0).all()
+    x, ys, inc, dts, series = pred.chunk_samples_ragged(y, _dev64(tr["times"]), off, C)
+    d = pred.dims(3, C)
+    theta, hist = pred.fit_predictor(d, x, inc.float().contiguous(), epochs=60, seed=1)
+    assert hist[-1] < 0.5 * hist[0], hist
+    args_p = pred.solver_args(d, theta, 3, base=0)
+
+    ev = W.robertson(B=48, seed=108, n_range=(200, 4000))
+    eoff = torch.as_tensor(ev["offsets"], device="cuda")
+    args = (_dev64(ev["y0"]), _dev64(ev["times"]), _dev64(ev["params"]))
+    yo, so, _ = oracle.forward("robertson", ev["y0"], ev["times"], ev["params"], offsets=ev["offsets"],
+                               tol=PARITY_TOL)
+    its = {}
+    for init in ("zero", "predictor"):
+        kw = dict(predictor=args_p) if init == "predictor" else {}
+        yy, st, it, ck = tvi.solve_forward("robertson", *args, offsets=eoff, chunk=C, tol=PARITY_TOL, init=init,
+                                           checkpoints=True, **kw)
+        assert (st.cpu().numpy() == 0).all(), init
+        assert series_rel_err(yy.cpu().numpy(), yo, ev["offsets"]).max() <= 1e-10, init
+        its[init] = int(it.sum().item())
+        if init == "predictor":
+            g = yy / torch.sqrt((yy ** 2).sum())
+            a1 = tvi.solve_adjoint("robertson", args[1], args[2], g, y=yy, offsets=eoff, chunk=C, tol=PARITY_TOL,
+                                   init=init, **kw)
+            a2 = tvi.solve_adjoint("robertson", args[1], args[2], g, ckpt=ck, offsets=eoff, chunk=C, tol=PARITY_TOL,
+                                   init=init, **kw)
+            assert torch.equal(a1[0], a2[0]) and torch.equal(a1[1], a2[1])
+            y_ref = yy
+    xe, yse, ie, de, se = pred.chunk_samples_ragged(y_ref, args[1], eoff, C)
+    err_zero = float((ie ** 2).mean().item())
+    err_pred = float(((ie - pred.forward(d, theta, xe).double()) ** 2).mean().item())
+    print("Robertson Newton corrections: zero %d, predictor %d; initial iterate MSE: zero %.3e, predictor %.3e"
+          % (its["zero"], its["predictor"], err_zero, err_pred))
+    assert err_pred < err_zero
