@@ -19,14 +19,33 @@ static tvi_status launch_st(int pass, const SolveArgs<IO> &a, hipStream_t stream
     if (blocks == 0) return TVI_OK;
     if (blocks > 0x7fffffffLL) return TVI_EINVAL;
     dim3 grid((unsigned)blocks), block(kWave);
-    // the learned predictor's hidden layers and outputs: [segments][2H + n S T] floats of LDS
-    const size_t lds =
-        a.init == INIT_PREDICTOR ? (size_t)per_block * (2 * a.pred_hidden + Model::N * S * T) * sizeof(float) : 0;
+    const bool pred = a.init == INIT_PREDICTOR;
+    // the learned start has its own instances (segments of >= 4 lanes, T n <= kPredictorMaxTN)
+    constexpr bool kPred = S >= 4 && T * Model::N <= kPredictorMaxTN;
+    if (pred && !kPred && pass != PASS_ADJOINT) return TVI_EUNSUPPORTED;
+    // its hidden layers and outputs: [segments][2H + n S T] floats of LDS
+    const size_t lds = pred ? (size_t)per_block * (2 * a.pred_hidden + Model::N * S * T) * sizeof(float) : 0;
     switch (pass) {
-    case PASS_FORWARD: hipLaunchKernelGGL((forward_kernel<Model, IO, S, T>), grid, block, lds, stream, a); break;
-    case PASS_ADJOINT: hipLaunchKernelGGL((adjoint_kernel<Model, IO, S, T, false>), grid, block, 0, stream, a); break;
+    case PASS_FORWARD:
+        if constexpr (kPred) {
+            if (pred) {
+                hipLaunchKernelGGL((forward_kernel<Model, IO, S, T, true>), grid, block, lds, stream, a);
+                break;
+            }
+        }
+        hipLaunchKernelGGL((forward_kernel<Model, IO, S, T, false>), grid, block, 0, stream, a);
+        break;
+    case PASS_ADJOINT:
+        hipLaunchKernelGGL((adjoint_kernel<Model, IO, S, T, false, false>), grid, block, 0, stream, a);
+        break;
     case PASS_ADJOINT_RECOMPUTE:
-        hipLaunchKernelGGL((adjoint_kernel<Model, IO, S, T, true>), grid, block, lds, stream, a);
+        if constexpr (kPred) {
+            if (pred) {
+                hipLaunchKernelGGL((adjoint_kernel<Model, IO, S, T, true, true>), grid, block, lds, stream, a);
+                break;
+            }
+        }
+        hipLaunchKernelGGL((adjoint_kernel<Model, IO, S, T, true, false>), grid, block, 0, stream, a);
         break;
     default: return TVI_EINVAL;
     }

@@ -273,7 +273,9 @@ struct ChunkNewton {
     // Solve steps s..s_end from ys (already set).  C is the nominal chunk
     // length: attempts never cross a multiple of C, so a checkpoint at every
     // multiple of C restarts the identical sequence of attempts.
-    template <class IO, class Sink>
+    // PRED: this instance carries the learned start (kept out of the others:
+    // its registers and code would slow every solve).
+    template <bool PRED, class IO, class Sink>
     __device__ void run(const Model &model, const IO *t, int C, int max_newton, double tol_a, double tol_r,
                         int init, bool halving, const Sink &sink, const PredictorRef &pr)
     {
@@ -316,8 +318,9 @@ struct ChunkNewton {
 
             // ---- learned start: its base (zero or extrapolation) plus the predicted
             // corrections, kept where its residual is below the base's
-            // (instances with T n > kPredictorMaxTN leave it out: the host rejects the predictor there)
-            if (kPredictorT && init == INIT_PREDICTOR && wave_any(fresh)) {
+            // (compiled only into PRED instances with T n <= kPredictorMaxTN)
+            if constexpr (PRED && kPredictorT) {
+              if (init == INIT_PREDICTOR && wave_any(fresh)) {
                 double pc[T][n];
                 predict(pr, q, lane / S, fresh, pc);
                 const double n_base = residual<false>(model, dy, q, R);
@@ -327,6 +330,7 @@ struct ChunkNewton {
                     for (int k = 0; k < n; ++k) dy[i][k] += (fresh && owned(q, i)) ? pc[i][k] : 0.0;
                 const double n_pred = residual<false>(model, dy, q, R);
                 if (fresh && !(n_pred < n_base)) extrapolate(model, q, pr.base == 0);
+              }
             }
             fresh = false;
 
@@ -464,7 +468,7 @@ struct ChunkNewton {
 // ---------------------------------------------------------------------------
 // Forward kernel: one segment of S lanes per series, 64 / S series per wave.
 // ---------------------------------------------------------------------------
-template <class Model, class IO, int S, int T>
+template <class Model, class IO, int S, int T, bool PRED>
 __global__ __launch_bounds__(kWave) void forward_kernel(SolveArgs<IO> a)
 {
     constexpr int n = Model::N;
@@ -495,7 +499,7 @@ __global__ __launch_bounds__(kWave) void forward_kernel(SolveArgs<IO> a)
     cn.status = ST_OK;
     cn.active = sv.valid && sv.Nb > 0;
     extern __shared__ float pred_lds[];
-    cn.run(model, sv.t, a.chunk, a.max_newton, a.tol_a, a.tol_r, a.init, a.halving != 0, sink,
+    cn.template run<PRED>(model, sv.t, a.chunk, a.max_newton, a.tol_a, a.tol_r, a.init, a.halving != 0, sink,
            PredictorRef{a.pred, a.pred_hidden, a.pred_steps, a.pred_base, pred_lds});
     if (sv.valid && q == 0) {
         a.status[sv.b] = cn.status;
@@ -510,7 +514,7 @@ __global__ __launch_bounds__(kWave) void forward_kernel(SolveArgs<IO> a)
 // the same segment scan run from the highest lane down.  With RECOMPUTE the
 // chunk's states are re-solved from its checkpoint by the forward code.
 // ---------------------------------------------------------------------------
-template <class Model, class IO, int S, int T, bool RECOMPUTE>
+template <class Model, class IO, int S, int T, bool RECOMPUTE, bool PRED>
 __global__ __launch_bounds__(kWave) void adjoint_kernel(SolveArgs<IO> a)
 {
     constexpr int n = Model::N;
@@ -554,7 +558,7 @@ __global__ __launch_bounds__(kWave) void adjoint_kernel(SolveArgs<IO> a)
             for (int k = 0; k < n; ++k) cn.ys[k] = have_ckpt ? a.ckpt[(sv.b * a.K + c) * n + k] : 0.0;
             WorkspaceSink<n> wsink{wsb, s};
             extern __shared__ float pred_lds[];
-            cn.run(model, sv.t, C, a.max_newton, a.tol_a, a.tol_r, a.init, a.halving != 0, wsink,
+            cn.template run<PRED>(model, sv.t, C, a.max_newton, a.tol_a, a.tol_r, a.init, a.halving != 0, wsink,
                    PredictorRef{a.pred, a.pred_hidden, a.pred_steps, a.pred_base, pred_lds});
             if (active && cn.status != ST_OK) status = cn.status;
             __syncthreads(); // one wave per block: makes the workspace writes visible to the wave
