@@ -215,9 +215,15 @@ def run_mlp(ctx, steps):
     # every trip evaluates h on the attempt's steps; every correction also evaluates J
     flops = (corrections + attempts) * C * MLP_F_FLOPS + corrections * C * MLP_J_FLOPS
     tf = flops / (fms * 1e-3) / 1e12
+    # the same step with the adjoint reading the stored trajectory
+    cs2 = graph.CapturedStep("mlp", y0, times, theta, chunk=C, tol=TIMING_TOL, loss="mean_square",
+                             observed=obs.reshape(-1), recompute=False).capture()
+    cs2.replay()
+    st2 = stats(time_launches(cs2.replay, max(3, steps // 2), torch.cuda.current_stream()))
     return {"workload": "mlp n=8 H=64 tanh B=64 N=10000 t=[0,1] chunk=100 f32 (bf16-split MFMA) "
                         "fwd+adjoint, mean-square loss at 100 sampled times, states recomputed",
             "value": B * N / (st["mean_ms"] * 1e-3), "unit": "series*steps/s", **st,
+            "stored_trajectory_value": B * N / (st2["mean_ms"] * 1e-3),
             "forward_ms": fms, "forward_value": B * N / (fms * 1e-3), "newton_corrections": corrections,
             "failed": failed,
             "roofline": {"kernel": "tvi::mlp_forward_kernel<float>", "bound": "mfma", "achieved": tf,
@@ -248,6 +254,12 @@ def run_robertson(ctx, steps):
     cs.replay()
     dd = time_launches(cs.replay, max(3, steps // 2), torch.cuda.current_stream())
     st = stats(dd)
+    cs2 = graph.CapturedStep("robertson", y0, times, sp, offsets=off, chunk=b["chunk"], lanes=b["lanes"],
+                             steps_per_lane=b["steps_per_lane"], tol=TIMING_TOL, init=b["init"],
+                             loss="frobenius", recompute=False).capture()
+    cs2.replay()
+    st2 = stats(time_launches(cs2.replay, max(3, steps // 2), torch.cuda.current_stream()))
+    del cs2
     fwd = lambda: tvi.solve_forward("robertson", y0, times, sp, offsets=off, chunk=b["chunk"], lanes=b["lanes"],
                                     steps_per_lane=b["steps_per_lane"], tol=TIMING_TOL, init=b["init"],
                                     y_out=y_out, iters=False)
@@ -261,6 +273,7 @@ def run_robertson(ctx, steps):
                         "fwd+adjoint (Frobenius loss), one captured graph, states recomputed",
             "series_steps": total, "value": total / (st["mean_ms"] * 1e-3), "unit": "series*steps/s", **st,
             "failed": int(((cs.status_fwd != 0) | (cs.status_adj != 0)).sum().item()),
+            "stored_trajectory_value": total / (st2["mean_ms"] * 1e-3),
             "forward_value": total / (fms * 1e-3), "chunk1_forward_value": total / (sms * 1e-3),
             "tuned": b}
 
@@ -433,7 +446,8 @@ def main():
     # ---- autotune chunk length, tiling and initial iterate (untimed)
     log("autotuning chunk / tiling / initial iterate")
     tuned = autotune.tune_forward("vanderpol", y0, times, mu, tol=TIMING_TOL, y_out=y_out, use_cache=False,
-                                  chunks=(10, 50, 100, 200, 500) if args.chunk == 0 else (args.chunk,),
+                                  chunks=(10, 16, 32, 50, 64, 100, 128, 200, 256, 500) if args.chunk == 0
+                                  else (args.chunk,),
                                   inits=("zero", "extrap") if not args.init else (args.init,))
     best = tuned["best"]
     C, S, T, init = best["chunk"], best["lanes"], best["steps_per_lane"], best["init"]

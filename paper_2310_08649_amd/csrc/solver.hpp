@@ -176,7 +176,7 @@ struct ChunkNewton {
     int64_t ck_at;     // ... and its step (ck_next * C): no division inside the loop
     int m, mcur;       // attempt length and the current limit (halved on failure)
     int it, total;     // corrections in this attempt / in total
-    double nrm0;
+    double nrm0;       // squared residual norm at the attempt's first iterate
     bool active, start, sing;
     int status;
     double dy[T][n];   // Newton iterate Delta y of the owned steps
@@ -186,7 +186,8 @@ struct ChunkNewton {
     __device__ __forceinline__ bool owned(int q, int i) const { return active && (q * T + i + 1 <= m); }
 
     // Backward-Euler residual of the chunk at iterate d (owned steps; zero
-    // elsewhere), stored in R if KEEP, and its Euclidean norm over the segment.
+    // elsewhere), stored in R if KEEP, and its squared Euclidean norm over the
+    // segment (the tests compare squares: no square root in the loop).
     // Wave-uniform.
     template <bool KEEP>
     __device__ __forceinline__ double residual(const Model &model, const double (&d)[T][n], int q,
@@ -210,7 +211,7 @@ struct ChunkNewton {
                 acc = fma(r, r, acc);
             }
         }
-        return sqrt(seg_sum<S>(acc));
+        return seg_sum<S>(acc);
     }
 
     // The extrapolated start: dy_j = (t_{s+j} - t_s) h(y_s) on the owned steps.
@@ -290,6 +291,7 @@ struct ChunkNewton {
         mcur = C;
         ck_next = s / C + 1;
         ck_at = ck_next * C;
+        const double tol_a2 = tol_a * tol_a, tol_r2 = tol_r * tol_r;
         double Fi[T][n][n], zi[T][n], R[T][n];
         bool fresh = false;  // an attempt whose initial iterate the predictor may still replace
 
@@ -335,16 +337,16 @@ struct ChunkNewton {
             fresh = false;
 
             // ---- residual of the owned steps and its segment norm
-            const double nrm = residual<true>(model, dy, q, R);
+            const double nrm2 = residual<true>(model, dy, q, R);
 
             // ---- per-series decision (uniform within the segment)
             int act = 0; // 1 converged, 2 failed, 3 correct
             int code = ST_OK;
             if (active) {
-                if (it == 0) nrm0 = nrm;
+                if (it == 0) nrm0 = nrm2;
                 if (sing) { act = 2; code = ST_SINGULAR; }
-                else if (!finite(nrm)) { act = 2; code = ST_NONFINITE; }
-                else if (nrm <= tol_a || nrm <= tol_r * nrm0) act = 1;
+                else if (!finite(nrm2)) { act = 2; code = ST_NONFINITE; }
+                else if (nrm2 <= tol_a2 || nrm2 <= tol_r2 * nrm0) act = 1;
                 else if (it >= max_newton) { act = 2; code = ST_NOT_CONVERGED; }
                 else act = 3;
             }

@@ -114,3 +114,37 @@ def test_adjoint_and_pcr_reject_bad_arguments(lib):
     assert lib.tvi_pcr_solve(tvi.F64, 9, 4, 8, f, f, f, 0, None) == -4
     assert lib.tvi_pcr_solve(7, 2, 4, 8, f, f, f, 0, None) == -1
     assert lib.tvi_pcr_solve(tvi.F64, 2, 4, 8, None, f, f, 0, None) == -1
+
+
+def test_predictor_options_and_pack_reject_bad_arguments(lib):
+    """The learned start: bad base, missing parameters, too few predicted steps,
+    too narrow a segment or too many values per lane are refused before any
+    launch; pack refuses aliasing and a bad shape."""
+    from paper_2310_08649_amd import predictor as pred
+    from paper_2310_08649_amd import tvi
+    f = _fake()
+    m = tvi.Model(tvi.KINDS["vanderpol"], 2, tvi.F64, 0, 64)
+
+    def fwd(o):
+        return lib.tvi_solve_forward(ctypes.byref(m), ctypes.byref(o), 4, 10, None, f, f, f, f, None, f, None, None)
+
+    class P:  # a stand-in for a device tensor: only its address is marshalled
+        def data_ptr(self):
+            return 0x1000
+
+    o = tvi.make_options(chunk=16, init="predictor", predictor=(P(), 128, 16, 2))
+    assert fwd(o) == -1                       # base must be 0 or 1
+    o = tvi.make_options(chunk=16, init="predictor", predictor=(P(), 128, 8, 0))
+    assert fwd(o) == -1                       # predicts fewer steps than the chunk
+    o = tvi.make_options(chunk=16, init="predictor", predictor=(P(), 512, 16, 0))
+    assert fwd(o) == -1                       # hidden width beyond 256
+    o = tvi.make_options(chunk=16, init="predictor")
+    assert fwd(o) == -1                       # no parameters
+    o = tvi.make_options(chunk=4, lanes=1, steps_per_lane=4, init="predictor", predictor=(P(), 128, 4, 0))
+    assert fwd(o) == -4                       # one lane per series cannot share the network
+    o = tvi.make_options(chunk=64, lanes=8, steps_per_lane=8, init="predictor", predictor=(P(), 128, 64, 0))
+    assert fwd(o) == -4                       # 8 steps x n = 2 per lane: not compiled
+    d = pred.Predictor(4, 128, 32)
+    assert lib.tvi_predictor_pack(ctypes.byref(d), f, f, None) == -1   # aliasing
+    bad = pred.Predictor(0, 128, 32)
+    assert lib.tvi_predictor_pack(ctypes.byref(bad), f, ctypes.c_void_p(0x2000), None) == -1
