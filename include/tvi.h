@@ -130,7 +130,8 @@ typedef struct {
 } tvi_options;
 
 /* Fills `opt` with the defaults: chunk 64, tol_a 1e-8, tol_r 1e-6 (Section 2.3),
- * max_newton 50, lanes/steps chosen from chunk, TVI_INIT_ZERO, halving on. */
+ * max_newton 50, lanes/steps chosen from chunk, TVI_INIT_ZERO, halving on, no
+ * predictor (predictor_base 1 once one is given). */
 void tvi_default_options(tvi_options *opt);
 
 const char *tvi_status_str(int32_t status);

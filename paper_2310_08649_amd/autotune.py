@@ -74,13 +74,17 @@ def _time(fn, reps):
 
 
 def tune_forward(kind, y0, times, params, offsets=None, tol=(1e-8, 1e-6), chunks=(10, 50, 100, 200, 500),
-                 reps=3, y_out=None, use_cache=True, inits=("zero",), **kw):
+                 reps=3, y_out=None, use_cache=True, inits=("zero",), adjoint=None, **kw):
     """Returns {"best": {chunk, lanes, steps_per_lane, init, failed, ms}, "table": [...]}.
 
     Candidates are ranked by the number of series that failed to converge,
-    then by time: a faster configuration never wins by giving up on series."""
-    key = _key(kind, y0, times, offsets, "tol=%g,%g|chunks=%s|inits=%s"
-               % (tol[0], tol[1], ",".join(map(str, chunks)), ",".join(inits)))
+    then by time: a faster configuration never wins by giving up on series.
+    With ``adjoint="stored"`` or ``"recompute"`` each candidate is timed as a
+    forward solve followed by the adjoint (Frobenius-loss gradient, states
+    read from the trajectory or recomputed from checkpoints): the tiling that
+    suits the forward pass alone need not suit the pair."""
+    key = _key(kind, y0, times, offsets, "tol=%g,%g|chunks=%s|inits=%s|adjoint=%s"
+               % (tol[0], tol[1], ",".join(map(str, chunks)), ",".join(inits), adjoint))
     if use_cache:
         with _lock:
             hit = _load_cache().get(key)
@@ -93,9 +97,16 @@ def tune_forward(kind, y0, times, params, offsets=None, tol=(1e-8, 1e-6), chunks
                 res = {}
 
                 def fn():
-                    res["st"] = tvi.solve_forward(kind, y0, times, params, offsets=offsets, chunk=C, lanes=S,
-                                                  steps_per_lane=T, tol=tol, y_out=y_out, init=init, iters=False,
-                                                  **kw)[1]
+                    y, st, _, ck = tvi.solve_forward(kind, y0, times, params, offsets=offsets, chunk=C, lanes=S,
+                                                     steps_per_lane=T, tol=tol, y_out=y_out, init=init,
+                                                     iters=False, checkpoints=adjoint == "recompute", **kw)
+                    res["st"] = st
+                    if adjoint:
+                        g = y if "g" not in res else res["g"]
+                        res["g"] = g
+                        src = dict(ckpt=ck) if adjoint == "recompute" else dict(y=y)
+                        tvi.solve_adjoint(kind, times, params, g, offsets=offsets, chunk=C, lanes=S,
+                                          steps_per_lane=T, tol=tol, init=init, **src, **kw)
                 ms = _time(fn, reps)
                 failed = int((res["st"] != 0).sum().item())
                 table.append({"chunk": C, "lanes": S, "steps_per_lane": T, "init": init, "failed": failed, "ms": ms})

@@ -258,9 +258,11 @@ struct ChunkNewton {
             a1[u] = gelu_f(z);
         }
         __syncthreads();
-        dense_t<4>(W2, H, b2, a1, H, q, S, H, a2, true);
+        // fewer accumulators where the solver's own state already fills the registers
+        constexpr int G = T == 1 ? 4 : 1;
+        dense_t<G>(W2, H, b2, a1, H, q, S, H, a2, true);
         __syncthreads();
-        dense_t<4>(W3, nout, b3, a2, H, q, S, want ? m * n : 0, out, false);  // this attempt's outputs (m <= S T)
+        dense_t<G>(W3, nout, b3, a2, H, q, S, want ? m * n : 0, out, false);  // this attempt's outputs (m <= S T)
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < T; ++i) {
@@ -292,7 +294,6 @@ struct ChunkNewton {
         ck_next = s / C + 1;
         ck_at = ck_next * C;
         const double tol_a2 = tol_a * tol_a, tol_r2 = tol_r * tol_r;
-        double Fi[T][n][n], zi[T][n], R[T][n];
         bool fresh = false;  // an attempt whose initial iterate the predictor may still replace
 
         while (wave_any(active)) {
@@ -325,18 +326,20 @@ struct ChunkNewton {
               if (init == INIT_PREDICTOR && wave_any(fresh)) {
                 double pc[T][n];
                 predict(pr, q, lane / S, fresh, pc);
-                const double n_base = residual<false>(model, dy, q, R);
+                double Rt[T][n];  // not kept (KEEP = false)
+                const double n_base = residual<false>(model, dy, q, Rt);
 #pragma unroll
                 for (int i = 0; i < T; ++i)
 #pragma unroll
                     for (int k = 0; k < n; ++k) dy[i][k] += (fresh && owned(q, i)) ? pc[i][k] : 0.0;
-                const double n_pred = residual<false>(model, dy, q, R);
+                const double n_pred = residual<false>(model, dy, q, Rt);
                 if (fresh && !(n_pred < n_base)) extrapolate(model, q, pr.base == 0);
               }
             }
             fresh = false;
 
             // ---- residual of the owned steps and its segment norm
+            double R[T][n];  // live within this trip only
             const double nrm2 = residual<true>(model, dy, q, R);
 
             // ---- per-series decision (uniform within the segment)
@@ -402,6 +405,7 @@ struct ChunkNewton {
             // ---- Newton correction: blocks, in-lane composition, PCR, replay
             if (wave_any(act == 3)) {
                 const bool corr = act == 3;
+                double Fi[T][n][n], zi[T][n];
                 AffineI<n, double> map;
                 affine_identity(map);
                 int ok = 1;

@@ -437,3 +437,11 @@ def test_predictor_adam_matches_torch():
         opt.step()
         th, m, v = PR.adam_step(th, g, m, v, step, 1e-2)
         np.testing.assert_allclose(th, p.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_smoke_case_converges_in_the_oracle():
+    """The smoke check's reference: every series of its workload converges at
+    the parity tolerance in the oracle."""
+    w = W.vanderpol(B=32, N=1000, mu_range=(1.0, 20.0))
+    _, so, _ = oracle.forward("vanderpol", w["y0"], w["times"], w["params"], tol=(1e-13, 1e-13))
+    assert (so == 0).all()
