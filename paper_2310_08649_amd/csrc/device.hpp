@@ -207,32 +207,35 @@ __device__ __forceinline__ void matTvec_add(const R (&A)[N][N], const R (&x)[N],
     for (int i = 0; i < N; ++i) y[i] = t[i];
 }
 
-// X = A^{-1} by Gauss-Jordan elimination with partial pivoting: for each
+// X <- A^{-1} X by Gauss-Jordan elimination with partial pivoting: for each
 // column the row of largest magnitude among the remaining ones is moved to the
 // pivot position by conditional (select) row exchanges, so every register
 // index stays static.  A is destroyed.  Returns false if a pivot is zero or
 // not finite.
 template <int N, class R>
-__device__ __forceinline__ bool invert(R (&A)[N][N], R (&X)[N][N])
+__device__ __forceinline__ bool gj_solve(R (&A)[N][N], R (&X)[N][N])
 {
-    set_identity(X);
     bool ok = true;
 #pragma unroll
     for (int c = 0; c < N; ++c) {
 #pragma unroll
         for (int r = c + 1; r < N; ++r) {
             const bool sw = fabs(A[r][c]) > fabs(A[c][c]);
+            // larger blocks: the exchange's selects run only where some lane of
+            // the wave exchanges (blocks I - dt j rarely need one)
+            if (N < 4 || wave_any(sw)) {
 #pragma unroll
-            for (int k = c; k < N; ++k) {
-                const R a = A[r][k], b = A[c][k];
-                A[r][k] = sw ? b : a;
-                A[c][k] = sw ? a : b;
-            }
+                for (int k = c; k < N; ++k) {
+                    const R a = A[r][k], b = A[c][k];
+                    A[r][k] = sw ? b : a;
+                    A[c][k] = sw ? a : b;
+                }
 #pragma unroll
-            for (int k = 0; k < N; ++k) {
-                const R a = X[r][k], b = X[c][k];
-                X[r][k] = sw ? b : a;
-                X[c][k] = sw ? a : b;
+                for (int k = 0; k < N; ++k) {
+                    const R a = X[r][k], b = X[c][k];
+                    X[r][k] = sw ? b : a;
+                    X[c][k] = sw ? a : b;
+                }
             }
         }
         const R piv = A[c][c];
@@ -253,6 +256,14 @@ __device__ __forceinline__ bool invert(R (&A)[N][N], R (&X)[N][N])
         }
     }
     return ok;
+}
+
+// X = A^{-1} (A destroyed).
+template <int N, class R>
+__device__ __forceinline__ bool invert(R (&A)[N][N], R (&X)[N][N])
+{
+    set_identity(X);
+    return gj_solve(A, X);
 }
 
 // ---------------------------------------------------------------------------
@@ -333,14 +344,15 @@ __device__ __forceinline__ void affine_after(AffineI<N, R> &a, const AffineI<N, 
 template <int N, class R>
 __device__ __forceinline__ bool inverse_plus(const R (&E)[N][N], R (&F)[N][N])
 {
-    R D[N][N], X[N][N];
+    R D[N][N];
 #pragma unroll
     for (int i = 0; i < N; ++i)
 #pragma unroll
-        for (int k = 0; k < N; ++k) D[i][k] = ((i == k) ? R(1) : R(0)) - E[i][k];
-    const bool ok = invert(D, X);
-    matmul(X, E, F);
-    return ok;
+        for (int k = 0; k < N; ++k) {
+            D[i][k] = ((i == k) ? R(1) : R(0)) - E[i][k];
+            F[i][k] = E[i][k];
+        }
+    return gj_solve(D, F);  // one solve with right-hand side E
 }
 
 // Lane moves of a whole map, element by element (zero fill: identity).

@@ -184,25 +184,27 @@ __device__ void predictor_corrections(float *a1, float *a2, float *out, const fl
 }
 
 // I + F = (I - dt J)^{-1} with F = (I - dt J)^{-1} (dt J), J a row-major block in
-// LDS (read twice instead of being held in registers).  F^T if TRANSPOSE.
+// LDS.  F^T if TRANSPOSE.
 template <bool TRANSPOSE>
 __device__ __forceinline__ bool block_inverse_plus(const float *J, float dt, float (&F)[NS][NS])
 {
+    // F = (I - dt J)^{-1} (dt J): one Gauss-Jordan solve with right-hand side dt J
     float D[NS][NS], X[NS][NS];
 #pragma unroll
     for (int r = 0; r < NS; ++r)
 #pragma unroll
-        for (int c = 0; c < NS; ++c) D[r][c] = ((r == c) ? 1.f : 0.f) - dt * J[r * NS + c];
-    const bool ok = invert(D, X);
+        for (int c = 0; c < NS; ++c) {
+            const float e = dt * J[r * NS + c];
+            D[r][c] = ((r == c) ? 1.f : 0.f) - e;
+            X[r][c] = e;
+        }
+    const bool ok = gj_solve(D, X);
 #pragma unroll
     for (int r = 0; r < NS; ++r)
 #pragma unroll
         for (int c = 0; c < NS; ++c) {
-            float acc = 0.f;
-#pragma unroll
-            for (int l = 0; l < NS; ++l) acc = fmaf(X[r][l], dt * J[l * NS + c], acc);
-            if (TRANSPOSE) F[c][r] = acc;
-            else F[r][c] = acc;
+            if (TRANSPOSE) F[c][r] = X[r][c];
+            else F[r][c] = X[r][c];
         }
     return ok;
 }

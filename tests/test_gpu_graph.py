@@ -75,3 +75,30 @@ def test_captured_robertson_step_replays_exactly(mods):
     op, oy0, _ = oracle.adjoint("robertson", ref[0].cpu().numpy(), w["times"], w["params"], g, offsets=w["offsets"])
     dp = ref[2].cpu().numpy()
     assert (np.abs(dp - op).max(axis=1) / np.abs(op).max(axis=1)).max() <= 1e-10
+
+
+def test_loss_gradients_float_storage(mods):
+    """The float path of the loss kernels: value accumulated in double, gradient
+    to float rounding, against the definitions in float64."""
+    graph, tvi = mods
+    lib = tvi.load()
+    rng = np.random.default_rng(3)
+    y = rng.standard_normal((5000, 8)).astype(np.float32)
+    obs = (rng.random(5000) < 0.02).astype(np.uint8)
+    ws = torch.empty(lib.tvi_loss_workspace_bytes(), dtype=torch.uint8, device="cuda")
+    yd = dev(y, torch.float32)
+    for kind in (0, 1):
+        g = torch.empty(5000, 8, dtype=torch.float32, device="cuda")
+        L = torch.empty(1, dtype=torch.float64, device="cuda")
+        rc = lib.tvi_loss_grad(kind, tvi.F32, 5000, 8, tvi._ptr(yd), tvi._ptr(dev(obs, torch.uint8)),
+                               int(obs.sum()), tvi._ptr(g), tvi._ptr(L), tvi._ptr(ws), ws.numel(), tvi._stream())
+        assert rc == 0
+        y64 = y.astype(np.float64)
+        if kind == 0:
+            Lr = np.sqrt(np.sum(y64 ** 2))
+            gr = y64 / Lr
+        else:
+            Lr = np.sum(y64[obs == 1] ** 2) / (obs.sum() * 8)
+            gr = np.where(obs[:, None] == 1, 2 * y64 / (obs.sum() * 8), 0.0)
+        assert abs(L.item() - Lr) <= 1e-12 * Lr
+        np.testing.assert_allclose(g.cpu().numpy(), gr, rtol=1e-6, atol=1e-7 * np.abs(gr).max())

@@ -160,3 +160,25 @@ def test_mlp_gradient_matches_central_differences(tvi):
         d /= np.linalg.norm(d)
         fd = (loss(theta + 1e-4 * d) - loss(theta - 1e-4 * d)) / 2e-4
         assert abs(dth @ d - fd) <= 1e-4 * max(abs(fd), 1e-6) + 1e-7, (dth @ d, fd)
+
+
+def test_mlp_double_storage_forward_and_adjoint(tvi):
+    """Double inputs and outputs (the network still computes in float): the
+    trajectory and gradient at the float gate against the oracle on the same
+    float-rounded inputs, and recomputation bitwise equal to the stored path."""
+    w = W.mlp(B=6, N=1500)
+    y0, times, theta = (w[k].astype(np.float32).astype(np.float64) for k in ("y0", "times", "params"))
+    yo, so, _ = oracle.forward("mlp", y0, times, theta, tol=(1e-12, 1e-12))
+    assert (so == 0).all()
+    d = lambda a: dev(a, torch.float64)
+    y, st, _, ck = tvi.solve_forward("mlp", d(y0), d(times), d(theta), chunk=64, tol=TOL32, checkpoints=True)
+    assert y.dtype == torch.float64 and (host(st) == 0).all()
+    assert series_rel_err(host(y), yo).max() <= 1e-5
+    obs = W.observed_steps(1500, every=100)
+    g = _mlp_loss_grad(host(y), obs)
+    a1 = tvi.solve_adjoint("mlp", d(times), d(theta), d(g), ckpt=ck, chunk=64, tol=TOL32)
+    a2 = tvi.solve_adjoint("mlp", d(times), d(theta), d(g), y=y, chunk=64, tol=TOL32)
+    assert torch.equal(a1[0], a2[0]) and torch.equal(a1[1], a2[1])
+    oth, oy0, _ = oracle.adjoint("mlp", host(y), times, theta, g)
+    assert np.abs(host(a1[0]) - oth).max() <= 1e-5 * np.abs(oth).max()
+    assert np.abs(host(a1[1]) - oy0).max() <= 1e-5 * np.abs(oy0).max()
