@@ -247,11 +247,13 @@ def run_robertson(ctx, steps):
     off = torch.as_tensor(w["offsets"], device=dev)
     total = int(w["steps"].sum())
     y_out = torch.empty((times.shape[0], 3), dtype=torch.float64, device=dev)
+    order = tvi.order_longest_first(off)  # ragged series launch longest first
     tune = lambda adjoint: autotune.tune_forward("robertson", y0, times, sp, offsets=off, tol=TIMING_TOL,
                                                  y_out=y_out, use_cache=False, chunks=(16, 32, 64, 128, 256),
-                                                 inits=("zero", "extrap"), adjoint=adjoint)["best"]
+                                                 inits=("zero", "extrap"), adjoint=adjoint, order=order)["best"]
     res = {"workload": "robertson n=3 B=2000 ragged N_b=exp U(ln 100, ln 2e4) log-spaced t=[1e-5,1e4] f64 "
-                       "fwd+adjoint (Frobenius loss), one captured graph", "series_steps": total}
+                       "fwd+adjoint (Frobenius loss), one captured graph, series launched longest first",
+           "series_steps": total}
     for mode in ("recompute", "stored"):
         b = tune(mode)
         cs = graph.CapturedStep("robertson", y0, times, sp, offsets=off, chunk=b["chunk"], lanes=b["lanes"],
@@ -267,9 +269,9 @@ def run_robertson(ctx, steps):
     b = tune(None)
     fwd = lambda: tvi.solve_forward("robertson", y0, times, sp, offsets=off, chunk=b["chunk"], lanes=b["lanes"],
                                     steps_per_lane=b["steps_per_lane"], tol=TIMING_TOL, init=b["init"],
-                                    y_out=y_out, iters=False)
+                                    y_out=y_out, iters=False, order=order)
     seq = lambda: tvi.solve_forward("robertson", y0, times, sp, offsets=off, chunk=1, lanes=1, steps_per_lane=1,
-                                    tol=TIMING_TOL, y_out=y_out, iters=False)
+                                    tol=TIMING_TOL, y_out=y_out, iters=False, order=order)
     fms = float(np.mean(time_launches(fwd, 3, ctx["stream"])))
     seq()
     sms = float(np.mean(time_launches(seq, 3, ctx["stream"])))

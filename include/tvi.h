@@ -127,12 +127,26 @@ typedef struct {
     int32_t predictor_steps;   /* steps it predicts, >= chunk                       */
     int32_t predictor_base;    /* 0: corrections to the zero start, 1: to the
                                   extrapolated start (TVI_INIT_EXTRAP)              */
+    const int32_t *order;      /* NULL, or the launch order [B] (device): series
+                                  order[i] is solved in launch slot i.  Must be a
+                                  permutation of 0..B-1 (entries outside [0, B)
+                                  leave their slot idle; repeated entries give
+                                  undefined results).  See tvi_order_longest_first */
 } tvi_options;
 
 /* Fills `opt` with the defaults: chunk 64, tol_a 1e-8, tol_r 1e-6 (Section 2.3),
  * max_newton 50, lanes/steps chosen from chunk, TVI_INIT_ZERO, halving on, no
- * predictor (predictor_base 1 once one is given). */
+ * predictor (predictor_base 1 once one is given), series in index order. */
 void tvi_default_options(tvi_options *opt);
+
+/* tvi_order_longest_first -- the launch order that solves ragged series
+ * longest first (ties by index): order[B] (device, written) from the point
+ * offsets [B+1] (device).  Each series is one workgroup or lane segment and
+ * the dispatcher hands out workgroups in launch order as slots free up, so
+ * this is the longest-processing-time-first schedule of the batch (series are
+ * independent, Section 2.1).  Results do not depend on the order.  Enqueued on
+ * `stream`; O(B^2 / 1024) LDS-tiled comparisons, computed once per batch. */
+tvi_status tvi_order_longest_first(const int64_t *offsets, int64_t B, int32_t *order, void *stream);
 
 const char *tvi_status_str(int32_t status);
 const char *tvi_version(void);

@@ -109,6 +109,7 @@ SolveArgs<IO> make_args(const tvi_model *model, const tvi_options *opt, int64_t 
     a.pred_hidden = opt->predictor_hidden;
     a.pred_steps = opt->predictor_steps;
     a.pred_base = opt->predictor_base;
+    a.order = opt->order;
     return a;
 }
 
@@ -149,6 +150,7 @@ void tvi_default_options(tvi_options *opt)
     opt->predictor_hidden = 0;
     opt->predictor_steps = 0;
     opt->predictor_base = 1;
+    opt->order = nullptr;
 }
 
 const char *tvi_status_str(int32_t s)
@@ -357,6 +359,14 @@ tvi_status tvi_predictor_forward(const tvi_predictor *p, int64_t M, const float 
         return TVI_EINVAL;
     return predictor_forward(p->n_in, p->hidden, p->n_out, M, x, params, out, workspace,
                              static_cast<hipStream_t>(stream));
+}
+
+tvi_status tvi_order_longest_first(const int64_t *offsets, int64_t B, int32_t *order, void *stream)
+{
+    if (B < 0 || B > 0x7fffffffLL) return TVI_EINVAL;
+    if (B == 0) return TVI_OK;
+    if (!offsets || !order) return TVI_EINVAL;
+    return launch_order(offsets, B, order, static_cast<hipStream_t>(stream));
 }
 
 tvi_status tvi_predictor_pack(const tvi_predictor *p, const float *params, float *packed, void *stream)

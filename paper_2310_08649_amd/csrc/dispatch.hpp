@@ -92,6 +92,7 @@ tvi_status launch_mlp_eval(int dtype, int64_t M, const void *states, const void 
                            hipStream_t stream);
 tvi_status launch_eval(int kind, int n, int dtype, int64_t M, const void *states, const void *times,
                        const void *params, int shared, void *f, void *J, hipStream_t stream);
+tvi_status launch_order(const int64_t *offsets, int64_t B, int32_t *order, hipStream_t stream);
 tvi_status launch_loss(int kind, int dtype, int64_t count, const void *y, const uint8_t *observed,
                        int64_t point_stride, double scale, void *g, double *loss, double *partial,
                        hipStream_t stream);

@@ -378,8 +378,9 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(SolveArgs<IO> a)
     extern __shared__ __align__(16) unsigned char smem[];
     MlpShared &S = *reinterpret_cast<MlpShared *>(smem);
     const int tid = threadIdx.x;
-    const int64_t b = blockIdx.x;
-    const SeriesView<IO> sv(a, b);
+    const SeriesView<IO> sv(a, blockIdx.x);
+    if (!sv.valid) return;  // a launch order entry outside [0, B): the whole block idles
+    const int64_t b = sv.b;
 
     load_weights(S.W, a.params);
     double ys[NS];
@@ -417,8 +418,9 @@ __global__ __launch_bounds__(kThreads) void mlp_adjoint_kernel(SolveArgs<IO> a, 
     const int tid = threadIdx.x, w = tid / kWave, l = lane_id(), g = l >> 4, r = l & 15;
     const int j = kSPW * w + (l & (kSPW - 1));
     const bool writer = l < kSPW;
-    const int64_t b = blockIdx.x;
-    const SeriesView<IO> sv(a, b);
+    const SeriesView<IO> sv(a, blockIdx.x);
+    if (!sv.valid) return;  // a launch order entry outside [0, B): the whole block idles
+    const int64_t b = sv.b;
     const int C = a.chunk;
     const IO *gb = a.g + sv.p0 * NS;
 

@@ -46,6 +46,7 @@ struct SolveArgs {
     double *ws;                // adjoint recompute workspace [B][chunk][n]
     const float *pred;         // learned chunk predictor, inference layout (INIT_PREDICTOR)
     int32_t pred_hidden, pred_steps, pred_base;
+    const int32_t *order;      // launch slot -> series (longest first), or null
 };
 
 template <class IO>
@@ -53,10 +54,13 @@ struct SeriesView {
     int64_t b, p0, Nb;
     const IO *t;
     bool valid;
-    __device__ __forceinline__ SeriesView(const SolveArgs<IO> &a, int64_t b_) : b(b_)
+    // slot: the launch position; with an order the series is order[slot]
+    // (entries outside [0, B) leave the slot idle)
+    __device__ __forceinline__ SeriesView(const SolveArgs<IO> &a, int64_t slot) : b(slot)
     {
-        valid = b < a.B;
-        if (!valid) { p0 = 0; Nb = 0; t = a.times; return; }
+        if (a.order && slot < a.B) b = a.order[slot];
+        valid = b >= 0 && b < a.B && slot < a.B;
+        if (!valid) { b = 0; p0 = 0; Nb = 0; t = a.times; return; }
         if (a.offsets) {
             p0 = a.offsets[b];
             Nb = a.offsets[b + 1] - p0 - 1;

@@ -6,7 +6,8 @@ the checkpoints or read from the stored trajectory.
 Every buffer is allocated once, before capture, so a replay touches only
 device memory the graph owns; the launches are the library's kernels on the
 capture stream (no host synchronisation, no allocation, no memset inside).
-Ragged series (point offsets) run in the same launches as uniform ones.
+Ragged series (point offsets) run in the same launches as uniform ones,
+longest first.
 """
 from __future__ import annotations
 
@@ -27,7 +28,8 @@ class CapturedStep:
     """
 
     def __init__(self, kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e-6), lanes=0, steps_per_lane=0,
-                 max_newton=50, init="zero", loss="frobenius", observed=None, n_max=None, recompute=True):
+                 max_newton=50, init="zero", loss="frobenius", observed=None, n_max=None, recompute=True,
+                 longest_first=True):
         lib = tvi.load()
         self.kind = kind
         self.recompute = recompute
@@ -47,7 +49,9 @@ class CapturedStep:
         self.B, self.n, self.N = B, n, N
         shared = self.params.dim() == 1
         self.model = tvi.Model(tvi.KINDS[kind], n, tvi._io_dtype(self.y0), 1 if shared else 0, 64)
-        self.opt = tvi.make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, True)
+        # ragged series launch longest first (computed once: the lengths are inputs)
+        self.order = tvi.order_longest_first(self.offsets) if self.offsets is not None and longest_first else None
+        self.opt = tvi.make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, True, order=self.order)
         P = lib.tvi_param_count(ctypes.byref(self.model))
         K = (N + chunk - 1) // chunk + 1
         self.y = torch.empty(yshape, dtype=dt, device=dev)

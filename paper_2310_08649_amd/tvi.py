@@ -45,7 +45,7 @@ class Options(ctypes.Structure):
                 ("max_newton", ctypes.c_int32), ("tol_a", ctypes.c_double), ("tol_r", ctypes.c_double),
                 ("init", ctypes.c_int32), ("halving", ctypes.c_int32), ("predictor", ctypes.c_void_p),
                 ("predictor_hidden", ctypes.c_int32), ("predictor_steps", ctypes.c_int32),
-                ("predictor_base", ctypes.c_int32)]
+                ("predictor_base", ctypes.c_int32), ("order", ctypes.c_void_p)]
 
 
 _lib = None
@@ -121,7 +121,7 @@ def param_count(kind, n, hidden=64):
 
 
 def make_options(chunk=64, tol=(1e-8, 1e-6), max_newton=50, lanes=0, steps_per_lane=0, init="zero",
-                 halving=True, predictor=None):
+                 halving=True, predictor=None, order=None):
     """``predictor``: (packed params, hidden, steps[, base]) of a trained chunk
     predictor, as made by ``predictor.solver_args`` (base 0: corrections to the
     zero start, 1: to the extrapolated start)."""
@@ -138,7 +138,23 @@ def make_options(chunk=64, tol=(1e-8, 1e-6), max_newton=50, lanes=0, steps_per_l
         o.predictor = ctypes.c_void_p(params.data_ptr())
         o.predictor_hidden, o.predictor_steps = int(hidden), int(steps)
         o.predictor_base = int(predictor[3]) if len(predictor) > 3 else 1
+    if order is not None:
+        o.order = ctypes.c_void_p(order.data_ptr())
     return o
+
+
+def order_longest_first(offsets):
+    """Launch order [B] (int32, device) that solves ragged series longest first."""
+    offsets = _dev(offsets, torch.int64, "offsets")
+    B = offsets.shape[0] - 1
+    order = torch.empty(max(B, 0), dtype=torch.int32, device=offsets.device)
+    lib = load()
+    if not hasattr(lib, "_order_bound"):
+        lib.tvi_order_longest_first.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
+        lib.tvi_order_longest_first.restype = ctypes.c_int32
+        lib._order_bound = True
+    _check(lib.tvi_order_longest_first(_ptr(offsets), B, _ptr(order), _stream()), "tvi_order_longest_first")
+    return order
 
 
 def model_eval(kind, states, params, times=None, rate=True, jacobian=True, hidden=64):
@@ -184,7 +200,7 @@ def _geometry(y0, times, offsets):
 
 def solve_forward(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e-6), max_newton=50, lanes=0,
                   steps_per_lane=0, init="zero", halving=True, checkpoints=False, y_out=None, iters=True,
-                  predictor=None):
+                  predictor=None, order=None):
     """Chunked backward Euler.  Returns ``(y, status, iters, ckpt)`` (device tensors;
     ``iters`` and ``ckpt`` may be None).  Asynchronous: nothing is synchronised."""
     dt = y0.dtype
@@ -195,7 +211,7 @@ def solve_forward(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e
         offsets = _dev(offsets, torch.int64, "offsets")
     B, n, N, yshape = _geometry(y0, times, offsets)
     model = Model(KINDS[kind], n, _io_dtype(y0), 1 if params.dim() == 1 else 0, 64)
-    opt = make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, halving, predictor)
+    opt = make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, halving, predictor, order)
     dev = y0.device
     y = y_out if y_out is not None else torch.empty(yshape, dtype=dt, device=dev)
     status = torch.empty(B, dtype=torch.int32, device=dev)
@@ -211,7 +227,8 @@ def solve_forward(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e
 
 
 def solve_adjoint(kind, times, params, g, y=None, ckpt=None, offsets=None, chunk=64, tol=(1e-8, 1e-6),
-                  max_newton=50, lanes=0, steps_per_lane=0, init="zero", halving=True, n=None, predictor=None):
+                  max_newton=50, lanes=0, steps_per_lane=0, init="zero", halving=True, n=None, predictor=None,
+                  order=None):
     """Discrete adjoint.  Returns ``(dLdp [B,P], dLdy0 [B,n], status [B])``.
 
     States come from the trajectory ``y`` or, when ``y`` is None, are recomputed
@@ -236,7 +253,7 @@ def solve_adjoint(kind, times, params, g, y=None, ckpt=None, offsets=None, chunk
     if not shared and (params.dim() != 2 or params.shape[0] != B):
         raise TviError("parameters must be per series [B, P] or shared [P]")
     model = Model(KINDS[kind], n, _io_dtype(g), 1 if shared else 0, 64)
-    opt = make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, halving, predictor)
+    opt = make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, halving, predictor, order)
     lib = load()
     dev = g.device
     P = lib.tvi_param_count(ctypes.byref(model))

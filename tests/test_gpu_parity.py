@@ -377,3 +377,43 @@ def test_every_tiling_forward_and_adjoint(tvi):
             for a, b in ((host(dp), op), (host(dy0), oy0)):
                 err = np.abs(a - b).max(axis=1) / np.abs(b).max(axis=1)
                 assert err.max() <= 1e-10, (C, S, T, list(src), err.max())
+
+
+# --------------------------------------------------------------------------
+# Launch order: longest first is the stable descending sort of the lengths,
+# and results do not depend on the order (bitwise)
+# --------------------------------------------------------------------------
+def test_launch_order_longest_first_and_order_independence(tvi):
+    w = W.robertson(B=70, n_range=(50, 2500))
+    off = dev(w["offsets"], torch.int64)
+    order = host(tvi.order_longest_first(off))
+    assert np.array_equal(order, np.argsort(-w["steps"], kind="stable"))
+    args = (dev(w["y0"]), dev(w["times"]), dev(w["params"]))
+    for C, S, T in ((64, 64, 1), (40, 16, 4), (7, 8, 1)):
+        kw = dict(offsets=off, chunk=C, lanes=S, steps_per_lane=T, tol=PARITY_TOL)
+        ya, sa, ia, ca = tvi.solve_forward("robertson", *args, checkpoints=True, **kw)
+        yb, sb, ib, cb = tvi.solve_forward("robertson", *args, checkpoints=True, order=dev(order, torch.int32), **kw)
+        assert torch.equal(ya, yb) and torch.equal(sa, sb) and torch.equal(ia, ib)
+        # checkpoints that exist (c * C <= N_b, and the final state); the rest is never written
+        nck = -(-w["steps"] // C) + 1
+        for b in range(len(nck)):
+            assert torch.equal(ca[b, :nck[b]], cb[b, :nck[b]]), (C, b)
+        g = ya / torch.sqrt((ya ** 2).sum())
+        for src in (dict(y=ya), dict(ckpt=ca)):
+            pa = tvi.solve_adjoint("robertson", args[1], args[2], g, **src, **kw)
+            pb = tvi.solve_adjoint("robertson", args[1], args[2], g, order=dev(order, torch.int32), **src, **kw)
+            assert all(torch.equal(a, b) for a, b in zip(pa, pb)), (C, S, T, list(src))
+
+
+def test_launch_order_neural_ode(tvi):
+    w = W.mlp(B=6, N=600)
+    f = lambda a: dev(a, torch.float32)
+    args = (f(w["y0"]), f(w["times"]), f(w["params"]))
+    rev = dev(np.arange(5, -1, -1), torch.int32)
+    ya, sa, _, ca = tvi.solve_forward("mlp", *args, chunk=50, tol=TIMING_TOL, checkpoints=True)
+    yb, sb, _, cb = tvi.solve_forward("mlp", *args, chunk=50, tol=TIMING_TOL, checkpoints=True, order=rev)
+    assert torch.equal(ya, yb) and torch.equal(sa, sb) and torch.equal(ca, cb)
+    g = (ya / torch.sqrt((ya.double() ** 2).sum()).float()).contiguous()
+    pa = tvi.solve_adjoint("mlp", args[1], args[2], g, ckpt=ca, chunk=50, tol=TIMING_TOL)
+    pb = tvi.solve_adjoint("mlp", args[1], args[2], g, ckpt=ca, chunk=50, tol=TIMING_TOL, order=rev)
+    assert all(torch.equal(a, b) for a, b in zip(pa, pb))
