@@ -462,10 +462,22 @@ __device__ __forceinline__ void seg_scan_down(AffineI<N, R> &a)
 template <int N, class R>
 __device__ __forceinline__ bool invert_plus(R (&D)[N][N], R (&F)[N][N])
 {
-    const bool ok = invert(D, F);
+    if constexpr (N == 2) {
+        // 2 x 2: the adjugate over the determinant (one division).  Elimination
+        // with the pivot D00 forms the same determinant, D00 D11 - D01 D10.
+        const R det = fma(D[0][0], D[1][1], -(D[0][1] * D[1][0]));
+        const R id = R(1) / det;
+        F[0][0] = fma(D[1][1], id, R(-1));
+        F[0][1] = -D[0][1] * id;
+        F[1][0] = -D[1][0] * id;
+        F[1][1] = fma(D[0][0], id, R(-1));
+        return det != R(0) && finite(det) && finite(id);
+    } else {
+        const bool ok = invert(D, F);
 #pragma unroll
-    for (int i = 0; i < N; ++i) F[i][i] -= R(1);
-    return ok;
+        for (int i = 0; i < N; ++i) F[i][i] -= R(1);
+        return ok;
+    }
 }
 
 // y = (I + F)^T x + c   (y may alias x or c)
