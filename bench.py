@@ -10,11 +10,12 @@ the initial iterate come from the autotuner (run before timing, untimed).
 
 Printed as one JSON line: throughput in series*steps/s, the roofline of the
 dominant kernel, and, beside it, the chunk = 1 sequential GPU solver on the
-same inputs, forward + adjoint in one captured graph, the standalone
-block-bidiagonal solve against the HBM roofline, the neural-ODE path
-(forward + adjoint) against the matrix-core peak, the ragged Robertson batch
-as one captured graph, the learned chunk predictor against its fallbacks, and
-the CPU oracle timed on the host cores.
+same inputs, the same workload with float storage, forward + adjoint in one
+captured graph, the small linear system, the standalone block-bidiagonal
+solve against the HBM roofline, the neural-ODE path (forward + adjoint)
+against the matrix-core peak, the ragged Robertson batch as one captured
+graph, the learned chunk predictor against its fallbacks, and the CPU oracle
+timed on the host cores.
 """
 import argparse
 import json
@@ -54,15 +55,21 @@ def vdp_flops_per_step_iter(chunk):
 
 
 def csrc_hash():
-    """Hash of the kernel sources; HBM traffic from profiler counters is reported
-    only while the sources still match the ones the counters were taken from."""
+    """Hash of the kernel sources with comments and blank space removed; HBM
+    traffic from profiler counters is reported only while the code still
+    matches the code the counters were taken from."""
     import glob
     import hashlib
+    import re
     h = hashlib.sha256()
     for p in sorted(glob.glob(os.path.join(ROOT, "paper_2310_08649_amd", "csrc", "*"))):
+        with open(p) as f:
+            src = f.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        src = " ".join(src.split())
         h.update(os.path.basename(p).encode())
-        with open(p, "rb") as f:
-            h.update(f.read())
+        h.update(src.encode())
     return h.hexdigest()[:16]
 
 
@@ -124,6 +131,46 @@ def run_chunk1(ctx, steps):
     return {"value": B * N / (ms * 1e-3), "unit": "series*steps/s", "ms_per_step": ms,
             "speedup_of_chunked": ms / ctx["ms_per_step"],
             "note": "same library, chunk 1: one lane per series, one Newton solve per step"}
+
+
+def run_vdp_fp32(ctx, steps):
+    """The headline workload with float storage (residual, blocks and scans in double)."""
+    import numpy as np
+    import torch
+    from paper_2310_08649_amd import tvi
+    f = lambda a: a.to(torch.float32)
+    y0, times, mu = f(ctx["y0"]), f(ctx["times"]), f(ctx["mu"])
+    y = torch.empty(ctx["y_out"].shape, dtype=torch.float32, device=ctx["dev"])
+    res = {}
+    for C, S, T in ((ctx["C"], ctx["S"], ctx["T"]), (1, 1, 1)):
+        fn = lambda: tvi.solve_forward("vanderpol", y0, times, mu, chunk=C, lanes=S, steps_per_lane=T,
+                                       tol=TIMING_TOL, y_out=y, iters=False)
+        st = fn()[1]
+        ms = float(np.mean(time_launches(fn, max(3, steps // 2), ctx["stream"])))
+        res["chunk%d" % C] = {"value": ctx["B"] * ctx["N"] / (ms * 1e-3), "ms": ms,
+                              "failed": int((st != 0).sum().item())}
+    res["unit"] = "series*steps/s"
+    return res
+
+
+def run_linear(ctx, steps):
+    """The linear stiff system, n = 4, 8 series x 200 steps, chunk 20, FP64 (a
+    launch-latency-sized problem: one chunk per lane segment, 10 chunks)."""
+    import numpy as np
+    import torch
+    from paper_2310_08649_amd import tvi, workloads
+    w = workloads.linear()
+    d = lambda a: torch.as_tensor(a, dtype=torch.float64, device=ctx["dev"])
+    y0, times, A = d(w["y0"]), d(w["times"]), d(w["params"])
+    B, N = w["y0"].shape[0], w["times"].shape[0] - 1
+    y = torch.empty((B, N + 1, 4), dtype=torch.float64, device=ctx["dev"])
+    res = {"unit": "series*steps/s"}
+    for C in (20, 1):
+        fn = lambda: tvi.solve_forward("linear", y0, times, A, chunk=C, tol=TIMING_TOL, y_out=y, iters=False)
+        fn()
+        ms = float(np.mean(time_launches(fn, 20, ctx["stream"])))
+        res["chunk%d" % C] = {"value": B * N / (ms * 1e-3), "ms": ms}
+    return res
 
 
 def run_vdp_fwd_adjoint(ctx, steps):
@@ -499,7 +546,8 @@ def main():
     ctx = dict(dev=dev, stream=stream, y0=y0, times=times, mu=mu, y_out=y_out, B=B, N=N, C=C, S=S, T=T, init=init,
                ms_per_step=ms_per_step)
     if not args.no_extras:
-        runs = [("chunk1", run_chunk1), ("fwd_adjoint", run_vdp_fwd_adjoint), ("pcr_roofline", run_pcr),
+        runs = [("chunk1", run_chunk1), ("fp32", run_vdp_fp32), ("fwd_adjoint", run_vdp_fwd_adjoint),
+                ("linear", run_linear), ("pcr_roofline", run_pcr),
                 ("mlp", run_mlp), ("robertson", run_robertson), ("predictor", run_predictor)]
         only = set(filter(None, args.only.split(",")))
         for name, fn in runs:

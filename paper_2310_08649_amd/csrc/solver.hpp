@@ -6,14 +6,14 @@
 // iteration (Algorithm 1, Eq. batched-update):
 //   1. each lane evaluates the residual of its steps (Eq. batched-backward-
 //      euler), R_j = dy_j - dy_{j-1} - dt_j h(y_s + dy_j, t_{s+j});
-//      ||R|| is a butterfly sum over the segment;
+//      ||R||^2 is summed over the segment by DPP exchanges;
 //   2. each lane forms its diagonal blocks D_j = I - dt_j j_j, inverts them
-//      (partial pivoting) and composes its T rows serially into one affine map
+//      (kept as I + F) and composes its T rows serially into one affine map
 //      (the in-lane part is Thomas's algorithm, Alg. thomas);
 //   3. log2(S) parallel-cyclic-reduction levels (Section 3.2) compose the
-//      lane maps across the segment through cross-lane reads;
-//   4. each lane replays its T rows from the reduced value entering it and
-//      adds the Newton correction to dy.
+//      lane maps across the segment by DPP lane moves;
+//   4. each lane takes the correction of its rows (T = 1: the composed map's
+//      offset; T > 1: a replay from the value entering the lane).
 // S = 1 is the one-series-per-lane sequential solver (chunk = 1) or
 // per-lane Thomas; T = 1 is pure PCR.
 //

@@ -417,3 +417,37 @@ def test_launch_order_neural_ode(tvi):
     pa = tvi.solve_adjoint("mlp", args[1], args[2], g, ckpt=ca, chunk=50, tol=TIMING_TOL)
     pb = tvi.solve_adjoint("mlp", args[1], args[2], g, ckpt=ca, chunk=50, tol=TIMING_TOL, order=rev)
     assert all(torch.equal(a, b) for a, b in zip(pa, pb))
+
+
+def test_ragged_with_empty_and_single_step_series(tvi):
+    """Series of 0, 1 and a few steps next to long ones, launched in index and in
+    longest-first order: each matches the oracle; a series without steps keeps
+    y0, and its gradient is dL/dy0 = g_0."""
+    rng = np.random.default_rng(12)
+    steps = np.array([0, 1, 5, 0, 300, 2, 64, 65])
+    B = len(steps)
+    off = np.zeros(B + 1, dtype=np.int64)
+    off[1:] = np.cumsum(steps + 1)
+    times = np.concatenate([np.r_[0.0, np.cumsum(0.01 + 0.02 * rng.random(k))] for k in steps])
+    y0 = np.tile(np.array([1.0, 0.0, 0.0]), (B, 1))
+    p = 10.0 ** rng.uniform(-0.3, 0.3, size=(B, 3))
+    yo, so, _ = oracle.forward("robertson", y0, times, p, offsets=off, tol=PARITY_TOL)
+    assert (so == 0).all()
+    g = rng.standard_normal(yo.shape)
+    op, oy0, _ = oracle.adjoint("robertson", yo, times, p, g, offsets=off)
+    offd = dev(off, torch.int64)
+    for order in (None, tvi.order_longest_first(offd)):
+        kw = dict(offsets=offd, chunk=16, tol=PARITY_TOL, order=order)
+        y, st, _, ck = tvi.solve_forward("robertson", dev(y0), dev(times), dev(p), checkpoints=True, **kw)
+        assert (host(st) == 0).all()
+        assert series_rel_err(host(y), yo, off).max() <= 1e-10
+        for src in (dict(y=y), dict(ckpt=ck)):
+            dp, dy0, sa = tvi.solve_adjoint("robertson", dev(times), dev(p), dev(g), **src, **kw)
+            assert (host(sa) == 0).all()
+            dp, dy0 = host(dp), host(dy0)
+            for b in range(B):
+                assert np.abs(dy0[b] - oy0[b]).max() <= 1e-10 * max(np.abs(oy0[b]).max(), 1e-300), b
+                if steps[b] == 0:
+                    assert np.array_equal(dy0[b], g[off[b]]) and np.all(dp[b] == 0.0)
+                else:
+                    assert np.abs(dp[b] - op[b]).max() <= 1e-10 * np.abs(op[b]).max(), b
