@@ -451,3 +451,31 @@ def test_ragged_with_empty_and_single_step_series(tvi):
                     assert np.array_equal(dy0[b], g[off[b]]) and np.all(dp[b] == 0.0)
                 else:
                     assert np.abs(dp[b] - op[b]).max() <= 1e-10 * np.abs(op[b]).max(), b
+
+
+def test_robertson_full_size_in_the_benchmark_configuration(tvi):
+    """The 2000 ragged series (7.7 M steps) in the launch configuration the
+    benchmark times (chunk 256, 64 lanes x 4 steps, longest first): every
+    element against the oracle, mass conservation, and the adjoint from the
+    stored trajectory against the oracle's on every series."""
+    w = W.robertson()
+    yo, so, _ = oracle.forward("robertson", w["y0"], w["times"], w["params"], offsets=w["offsets"], tol=PARITY_TOL)
+    assert (so == 0).all()
+    off = dev(w["offsets"], torch.int64)
+    kw = dict(offsets=off, chunk=256, lanes=64, steps_per_lane=4, tol=PARITY_TOL,
+              order=tvi.order_longest_first(off))
+    y, st, _, ck = tvi.solve_forward("robertson", dev(w["y0"]), dev(w["times"]), dev(w["params"]), checkpoints=True,
+                                     **kw)
+    yh = host(y)
+    assert (host(st) == 0).all()
+    assert series_rel_err(yh, yo, w["offsets"]).max() <= 1e-10
+    assert np.abs(yh.sum(axis=1) - 1.0).max() <= 1e-12
+    g = yh / np.sqrt(np.sum(yh ** 2))
+    dp, dy0, sa = tvi.solve_adjoint("robertson", dev(w["times"]), dev(w["params"]), dev(g), y=y, **kw)
+    dp2, dy02, _ = tvi.solve_adjoint("robertson", dev(w["times"]), dev(w["params"]), dev(g), ckpt=ck, **kw)
+    assert (host(sa) == 0).all()
+    assert torch.equal(dp, dp2) and torch.equal(dy0, dy02)
+    op, oy0, _ = oracle.adjoint("robertson", yh, w["times"], w["params"], g, offsets=w["offsets"])
+    for a, b in ((host(dp), op), (host(dy0), oy0)):
+        err = np.abs(a - b).max(axis=1) / np.abs(b).max(axis=1)
+        assert err.max() <= 1e-10, err.max()
