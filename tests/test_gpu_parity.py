@@ -479,3 +479,81 @@ def test_robertson_full_size_in_the_benchmark_configuration(tvi):
     for a, b in ((host(dp), op), (host(dy0), oy0)):
         err = np.abs(a - b).max(axis=1) / np.abs(b).max(axis=1)
         assert err.max() <= 1e-10, err.max()
+
+
+# --------------------------------------------------------------------------
+# Blocks that need row exchanges (partial pivoting), in some lanes of a wave
+# and not in others, and the per-lane Thomas tilings (one lane per series)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [3, 4])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_pcr_solve_blocks_that_need_pivoting(tvi, n, transpose):
+    rng = np.random.default_rng(200 + n)
+    B, m = 9, 64
+    D = np.empty((B, m, n, n))
+    for b in range(B):
+        for j in range(m):
+            blk = 2.0 * np.eye(n) + 0.3 * rng.standard_normal((n, n))
+            if (b * m + j) % 3 == 0:   # a row permutation: small diagonal, large off-diagonal pivots
+                blk = blk[rng.permutation(n)]
+            if (b * m + j) % 7 == 0:   # a zero leading pivot: elimination without row exchanges divides by 0
+                blk[0, 0] = 0.0
+            D[b, j] = blk
+    r = rng.standard_normal((B, m, n))
+    ref = bb.dense_solve(D, r, transpose=transpose)
+    x = host(tvi.pcr_solve(dev(D), dev(r), transpose=transpose))
+    # backward error: the blocks are well conditioned but the chain may grow
+    res = np.zeros_like(x)
+    for j in range(m):
+        if transpose:
+            res[:, j] = np.einsum("bki,bk->bi", D[:, j], x[:, j]) - (x[:, j + 1] if j + 1 < m else 0.0) - r[:, j]
+        else:
+            res[:, j] = np.einsum("bik,bk->bi", D[:, j], x[:, j]) - (x[:, j - 1] if j > 0 else 0.0) - r[:, j]
+    assert np.abs(res).max() <= 1e-12 * max(np.abs(x).max(), 1.0)
+    assert np.abs(x - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
+def test_linear_solver_pivoting_and_per_lane_thomas(tvi):
+    """Rotation-dominated linear systems, I - dt A needing row exchanges, solved
+    with PCR tilings and with one lane per series (Thomas within the lane)."""
+    rng = np.random.default_rng(55)
+    n, B, N = 4, 24, 60
+    A = np.zeros((B, n, n))
+    for b in range(B):
+        k = rng.uniform(20.0, 60.0, size=2)
+        A[b, 0, 1], A[b, 1, 0] = -k[0], k[0]
+        A[b, 2, 3], A[b, 3, 2] = -k[1], k[1]
+        A[b] += -1.0 * np.eye(n) + 0.1 * rng.standard_normal((n, n))
+    p = A.reshape(B, -1)
+    y0 = rng.standard_normal((B, n))
+    times = np.linspace(0.0, 1.5, N + 1)   # dt k > 1: the off-diagonal dominates
+    yo, so, _ = oracle.forward("linear", y0, times, p, tol=PARITY_TOL)
+    assert (so == 0).all()
+    g = yo / np.sqrt(np.sum(yo ** 2))
+    op, oy0, _ = oracle.adjoint("linear", yo, times, p, g)
+    for C, S, T in ((1, 1, 1), (4, 1, 4), (8, 1, 8), (20, 4, 8), (60, 64, 1), (16, 8, 2)):
+        kw = dict(chunk=C, lanes=S, steps_per_lane=T, tol=PARITY_TOL)
+        y, st, _, ck = tvi.solve_forward("linear", dev(y0), dev(times), dev(p), checkpoints=True, **kw)
+        assert (host(st) == 0).all(), (C, S, T)
+        assert series_rel_err(host(y), yo).max() <= 1e-10, (C, S, T)
+        dp, dy0, sa = tvi.solve_adjoint("linear", dev(times), dev(p), dev(g), ckpt=ck, **kw)
+        assert (host(sa) == 0).all()
+        for a, b in ((host(dp), op), (host(dy0), oy0)):
+            assert (np.abs(a - b).max(axis=1) / np.abs(b).max(axis=1)).max() <= 1e-10, (C, S, T)
+
+
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_pcr_forward_and_transposed_solves_are_adjoint(tvi, n):
+    """<A^-1 r, s> = <r, A^-T s> for the block-bidiagonal A, per series, at the
+    longest chunk and with the solves run as separate launches."""
+    rng = np.random.default_rng(400 + n)
+    B, m = 256, 512
+    D = 1.6 * np.eye(n)[None, None] + (0.3 / np.sqrt(n)) * rng.standard_normal((B, m, n, n))
+    r = rng.standard_normal((B, m, n))
+    s = rng.standard_normal((B, m, n))
+    x = host(tvi.pcr_solve(dev(D), dev(r)))
+    z = host(tvi.pcr_solve(dev(D), dev(s), transpose=True))
+    lhs = np.einsum("bjk,bjk->b", x, s)
+    rhs = np.einsum("bjk,bjk->b", r, z)
+    scale = np.sqrt(np.einsum("bjk,bjk->b", x, x) * np.einsum("bjk,bjk->b", s, s))
+    assert (np.abs(lhs - rhs) <= 1e-13 * np.sqrt(m) * scale).all()
