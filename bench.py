@@ -173,6 +173,39 @@ def run_linear(ctx, steps):
     return res
 
 
+def run_tiling_study(ctx, steps):
+    """PCR against Thomas over the block size n: the linear stiff system (one Newton
+    correction per chunk, so the launch is the block work itself), FP64, n = 2, 3, 4,
+    for every tiling of chunks of 8 and 64 steps.  S lanes per series run
+    ceil(log2 S) PCR levels and each lane runs T steps by the serial (Thomas)
+    recurrence; S = 1 is Thomas alone, T = 1 is PCR alone.  Two sizes: 512 series x
+    5000 steps (B*S lanes: a narrow tiling leaves most of the chip idle) and 65536
+    series x 1000 steps (every tiling fills the chip, so the work per step decides)."""
+    import numpy as np
+    import torch
+    from paper_2310_08649_amd import tvi, workloads
+    tilings = ((1, 1, 1), (8, 8, 1), (8, 4, 2), (8, 1, 8), (64, 64, 1), (64, 32, 2), (64, 16, 4), (64, 8, 8))
+    res = {"unit": "ms per launch", "workload": "linear, A = -Q diag(10^U(-1,3)) Q^T per series, t=[0,1], FP64"}
+    for B, N, reps in ((512, 5000, 10), (65536, 1000, 3)):
+        size = {}
+        for n in (2, 3, 4):
+            w = workloads.linear(B=B, N=N, n=n, seed=110 + n)
+            d = lambda a: torch.as_tensor(a, dtype=torch.float64, device=ctx["dev"])
+            y0, times, A = d(w["y0"]), d(w["times"]), d(w["params"])
+            y = torch.empty((B, N + 1, n), dtype=torch.float64, device=ctx["dev"])
+            row = {}
+            for C, S, T in tilings:
+                fn = lambda: tvi.solve_forward("linear", y0, times, A, chunk=C, lanes=S, steps_per_lane=T,
+                                               tol=TIMING_TOL, y_out=y, iters=False)
+                st = fn()[1]
+                ms = float(np.median(time_launches(fn, reps, ctx["stream"])))
+                row["C%d_S%d_T%d" % (C, S, T)] = {"ms": ms, "failed": int((st != 0).sum().item())}
+            size["n%d" % n] = row
+            del y, y0, times, A
+        res["B%d_N%d" % (B, N)] = size
+    return res
+
+
 def run_vdp_fwd_adjoint(ctx, steps):
     import torch
     from paper_2310_08649_amd import graph, workloads
@@ -547,7 +580,7 @@ def main():
                ms_per_step=ms_per_step)
     if not args.no_extras:
         runs = [("chunk1", run_chunk1), ("fp32", run_vdp_fp32), ("fwd_adjoint", run_vdp_fwd_adjoint),
-                ("linear", run_linear), ("pcr_roofline", run_pcr),
+                ("linear", run_linear), ("tiling_study", run_tiling_study), ("pcr_roofline", run_pcr),
                 ("mlp", run_mlp), ("robertson", run_robertson), ("predictor", run_predictor)]
         only = set(filter(None, args.only.split(",")))
         for name, fn in runs:
