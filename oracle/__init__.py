@@ -1,4 +1,4 @@
-"""CPU oracle for time-vectorized backward-Euler integration.
+"""CPU oracle for time-vectorized backward- and forward-Euler integration.
 
 TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
 the ``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares
@@ -8,7 +8,9 @@ Contents
 --------
 * ``forward`` / ``adjoint``: ctypes front end of ``oracle.c``, the plain
   sequential backward-Euler integrator with a dense Newton solve per step
-  (Section 2.2, Eq. backward-euler) and its discrete adjoint (Appendix A).
+  (Section 2.2, Eq. backward-euler) and its discrete adjoint (Appendix A);
+  with ``scheme="forward_euler"`` the explicit recurrence of Eq. forward-euler
+  and the discrete adjoint of that map.
 * ``rhs`` / ``vjp_p``: the model right-hand sides, their state Jacobians and
   parameter vector-Jacobian products, as the C oracle evaluates them.
 * ``blockbidiag``: the plain definitions of the batched block-bidiagonal
@@ -64,6 +66,10 @@ def _bind(lib):
     lib.oracle_forward.restype = i32
     lib.oracle_adjoint.argtypes = [i32, i32, i32, i64, i64, P, P, P, P, i32, P, i32, P, P, P]
     lib.oracle_adjoint.restype = i32
+    lib.oracle_forward_euler.argtypes = [i32, i32, i32, i64, i64, P, P, P, P, i32, i32, P, P]
+    lib.oracle_forward_euler.restype = i32
+    lib.oracle_forward_euler_adjoint.argtypes = [i32, i32, i32, i64, i64, P, P, P, P, i32, P, i32, P, P, P]
+    lib.oracle_forward_euler_adjoint.restype = i32
     return lib
 
 
@@ -149,14 +155,21 @@ def _layout(y0, times, offsets):
     return B, n, N, offsets, (int(offsets[-1]), n)
 
 
+SCHEMES = ("backward_euler", "forward_euler")
+
+
 def forward(kind, y0, times, params, offsets=None, tol=(1e-8, 1e-6), max_newton=50,
-            threads=None, hidden=64, params_shared=None):
-    """Sequential backward Euler (dense Newton per step).
+            threads=None, hidden=64, params_shared=None, scheme="backward_euler"):
+    """Sequential backward Euler (dense Newton per step), or forward Euler
+    (``scheme="forward_euler"``: no iteration, ``tol`` and ``max_newton`` unused,
+    ``iters`` all zero).
 
     Returns ``(y, status, iters)`` with ``y`` in the layout of ``times``:
     ``[B, N+1, n]`` for a shared uniform grid, ``[points, n]`` for ragged
     series given by point ``offsets``.
     """
+    if scheme not in SCHEMES:
+        raise ValueError("scheme must be one of %s" % (SCHEMES,))
     y0, times, params = _f64(y0), _f64(times), _f64(params)
     B, n, N, offsets, shape = _layout(y0, times, offsets)
     if params_shared is None:
@@ -164,17 +177,25 @@ def forward(kind, y0, times, params, offsets=None, tol=(1e-8, 1e-6), max_newton=
     y = np.empty(shape)
     status = np.zeros(B, dtype=np.int32)
     iters = np.zeros(B, dtype=np.int32)
-    rc = _load().oracle_forward(
-        _kind(kind), n, hidden, B, N, _p(offsets), _p(times), _p(y0), _p(params), int(params_shared),
-        float(tol[0]), float(tol[1]), int(max_newton), int(threads or default_threads()),
-        _p(y), _p(status), _p(iters))
+    if scheme == "forward_euler":
+        rc = _load().oracle_forward_euler(
+            _kind(kind), n, hidden, B, N, _p(offsets), _p(times), _p(y0), _p(params), int(params_shared),
+            int(threads or default_threads()), _p(y), _p(status))
+    else:
+        rc = _load().oracle_forward(
+            _kind(kind), n, hidden, B, N, _p(offsets), _p(times), _p(y0), _p(params), int(params_shared),
+            float(tol[0]), float(tol[1]), int(max_newton), int(threads or default_threads()),
+            _p(y), _p(status), _p(iters))
     if rc:
         raise ValueError("oracle_forward rejected its arguments (%d)" % rc)
     return y, status, iters
 
 
-def adjoint(kind, y, times, params, g, offsets=None, threads=None, hidden=64, params_shared=None):
-    """Discrete adjoint of ``forward``: returns ``(dLdp, dLdy0, status)``."""
+def adjoint(kind, y, times, params, g, offsets=None, threads=None, hidden=64, params_shared=None,
+            scheme="backward_euler"):
+    """Discrete adjoint of ``forward`` (same ``scheme``): returns ``(dLdp, dLdy0, status)``."""
+    if scheme not in SCHEMES:
+        raise ValueError("scheme must be one of %s" % (SCHEMES,))
     y, times, params, g = _f64(y), _f64(times), _f64(params), _f64(g)
     if offsets is None:
         B, n = y.shape[0], y.shape[2]
@@ -192,9 +213,9 @@ def adjoint(kind, y, times, params, g, offsets=None, threads=None, hidden=64, pa
     dLdp = np.zeros(P if params_shared else (B, P))
     dLdy0 = np.zeros((B, n))
     status = np.zeros(B, dtype=np.int32)
-    rc = _load().oracle_adjoint(
-        _kind(kind), n, hidden, B, N, _p(offsets), _p(times), _p(y), _p(params), int(params_shared),
-        _p(g), int(threads or default_threads()), _p(dLdp), _p(dLdy0), _p(status))
+    fn = _load().oracle_forward_euler_adjoint if scheme == "forward_euler" else _load().oracle_adjoint
+    rc = fn(_kind(kind), n, hidden, B, N, _p(offsets), _p(times), _p(y), _p(params), int(params_shared),
+            _p(g), int(threads or default_threads()), _p(dLdp), _p(dLdy0), _p(status))
     if rc:
         raise ValueError("oracle_adjoint rejected its arguments (%d)" % rc)
     del y0

@@ -18,6 +18,10 @@
  * iteration.  The gradient is the discrete adjoint of that computed map
  * (Appendix A: the same scheme for the forward and the backward problem).
  *
+ * The explicit scheme of Section 2.2 (Eq. forward-euler) is here too, as its
+ * plain definition: y_k = y_{k-1} + (t_k - t_{k-1}) h(y_{k-1}, t_{k-1}; p),
+ * one step after another, with the discrete adjoint of that map.
+ *
  * Everything is IEEE double, no fast-math.  Series are independent
  * (Section 2.1) and are distributed over a pthread pool, longest first.
  */
@@ -247,6 +251,7 @@ int oracle_vjp_p(int kind, int n, int hidden, const double *y, double t, const d
 /* ------------------------------------------------------------------------ */
 typedef struct {
     int kind, n, H, P, params_shared;
+    int explicit_scheme; /* 0: backward Euler, 1: forward Euler */
     int64_t B, N;
     const int64_t *offsets; /* point offsets [B+1] or NULL (uniform: N+1 points each) */
     const double *times, *y0, *params;
@@ -358,6 +363,75 @@ static void adjoint_series(problem_t *pb, int64_t b, double *gp)
     pb->status[b] = status;
 }
 
+/* Sequential forward Euler for one series (Section 2.2, Eq. forward-euler):
+ *   y_k = y_{k-1} + dt_k h(y_{k-1}, t_{k-1}; p).
+ * A non-finite state stops the series (NONFINITE; NaN from that step on). */
+static void forward_euler_series(problem_t *pb, int64_t b)
+{
+    const int n = pb->n, H = pb->H, kind = pb->kind;
+    const int64_t Nb = n_steps(pb, b);
+    const double *t = series_times(pb, b), *p = series_params(pb, b);
+    double *Y = pb->y + first_point(pb, b) * n;
+    double f[NMAX];
+    int32_t status = ORACLE_OK;
+
+    for (int i = 0; i < n; ++i) Y[i] = pb->y0[b * n + i];
+    for (int64_t k = 1; k <= Nb; ++k) {
+        const double dt = t[k] - t[k - 1];
+        const double *yp = Y + (k - 1) * n;
+        rhs(kind, n, H, yp, t[k - 1], p, f, NULL);
+        int finite = 1;
+        for (int i = 0; i < n; ++i) {
+            Y[k * n + i] = yp[i] + dt * f[i];
+            finite &= isfinite(Y[k * n + i]) ? 1 : 0;
+        }
+        if (!finite) {
+            status = ORACLE_NONFINITE;
+            for (int64_t q = k * n; q <= Nb * n + n - 1; ++q) Y[q] = NAN;
+            break;
+        }
+    }
+    pb->status[b] = status;
+    if (pb->iters) pb->iters[b] = 0;
+}
+
+/* Discrete adjoint of the forward-Euler map for one series.  With the
+ * constraints c_k = y_k - y_{k-1} - dt_k h(y_{k-1}) = 0, stationarity of
+ * L - sum_k lam_k^T c_k in y_k gives
+ *   lam_k = g_k + (I + dt_{k+1} j(y_k))^T lam_{k+1},   k = N..1,  lam_{N+1} = 0,
+ *   dL/dp = sum_k dt_k (dh/dp (y_{k-1}))^T lam_k,
+ *   dL/dy0 = g_0 + (I + dt_1 j(y_0))^T lam_1. */
+static void adjoint_forward_euler_series(problem_t *pb, int64_t b, double *gp)
+{
+    const int n = pb->n, H = pb->H, kind = pb->kind;
+    const int64_t Nb = n_steps(pb, b), p0 = first_point(pb, b);
+    const double *t = series_times(pb, b), *p = series_params(pb, b);
+    const double *Y = pb->y + p0 * n, *G = pb->g + p0 * n;
+    double lam[NMAX], nxt[NMAX], f[NMAX], J[NMAX * NMAX], w[NMAX];
+
+    memset(lam, 0, sizeof(lam)); /* lam_{N+1} */
+    for (int64_t k = Nb; k >= 0; --k) {
+        /* nxt = (I + dt_{k+1} j(y_k))^T lam_{k+1}; zero at k = N */
+        for (int i = 0; i < n; ++i) nxt[i] = 0.0;
+        if (k < Nb) {
+            const double dt1 = t[k + 1] - t[k];
+            rhs(kind, n, H, Y + k * n, t[k], p, f, J);
+            for (int i = 0; i < n; ++i) {
+                double s = lam[i];
+                for (int r = 0; r < n; ++r) s += dt1 * J[r * n + i] * lam[r];
+                nxt[i] = s;
+            }
+        }
+        for (int i = 0; i < n; ++i) lam[i] = G[k * n + i] + nxt[i];
+        if (k == 0) break; /* lam now holds dL/dy0 */
+        const double dt = t[k] - t[k - 1];
+        for (int i = 0; i < n; ++i) w[i] = dt * lam[i];
+        vjp_p(kind, n, H, Y + (k - 1) * n, t[k - 1], p, w, gp);
+    }
+    for (int i = 0; i < n; ++i) pb->dLdy0[b * n + i] = lam[i];
+    pb->status[b] = ORACLE_OK;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Thread pool over series, longest series first.                           */
 /* ------------------------------------------------------------------------ */
@@ -373,8 +447,13 @@ static void *worker(void *arg)
         pthread_mutex_unlock(&pb->lock);
         if (i >= pb->B) break;
         int64_t b = pb->order[i];
-        if (job->adjoint) adjoint_series(pb, b, job->gp_series + b * pb->P);
-        else forward_series(pb, b);
+        if (job->adjoint) {
+            if (pb->explicit_scheme) adjoint_forward_euler_series(pb, b, job->gp_series + b * pb->P);
+            else adjoint_series(pb, b, job->gp_series + b * pb->P);
+        } else {
+            if (pb->explicit_scheme) forward_euler_series(pb, b);
+            else forward_series(pb, b);
+        }
     }
     return NULL;
 }
@@ -429,14 +508,15 @@ static int validate(int kind, int n, int hidden, int64_t B, int64_t N, const int
     return 0;
 }
 
-int oracle_forward(int kind, int n, int hidden, int64_t B, int64_t N, const int64_t *offsets,
-                   const double *times, const double *y0, const double *params, int params_shared,
-                   double tol_a, double tol_r, int max_newton, int threads,
-                   double *y_out, int32_t *status, int32_t *iters)
+static int forward_driver(int explicit_scheme, int kind, int n, int hidden, int64_t B, int64_t N,
+                          const int64_t *offsets, const double *times, const double *y0, const double *params,
+                          int params_shared, double tol_a, double tol_r, int max_newton, int threads,
+                          double *y_out, int32_t *status, int32_t *iters)
 {
     if (validate(kind, n, hidden, B, N, offsets)) return -1;
     problem_t pb;
     memset(&pb, 0, sizeof(pb));
+    pb.explicit_scheme = explicit_scheme;
     pb.kind = kind; pb.n = n; pb.H = hidden; pb.P = oracle_param_count(kind, n, hidden);
     pb.params_shared = params_shared; pb.B = B; pb.N = N; pb.offsets = offsets;
     pb.times = times; pb.y0 = y0; pb.params = params;
@@ -445,13 +525,15 @@ int oracle_forward(int kind, int n, int hidden, int64_t B, int64_t N, const int6
     return run_pool(&pb, threads, 0, NULL);
 }
 
-int oracle_adjoint(int kind, int n, int hidden, int64_t B, int64_t N, const int64_t *offsets,
-                   const double *times, const double *y, const double *params, int params_shared,
-                   const double *g, int threads, double *dLdp, double *dLdy0, int32_t *status)
+static int adjoint_driver(int explicit_scheme, int kind, int n, int hidden, int64_t B, int64_t N,
+                          const int64_t *offsets, const double *times, const double *y, const double *params,
+                          int params_shared, const double *g, int threads, double *dLdp, double *dLdy0,
+                          int32_t *status)
 {
     if (validate(kind, n, hidden, B, N, offsets)) return -1;
     problem_t pb;
     memset(&pb, 0, sizeof(pb));
+    pb.explicit_scheme = explicit_scheme;
     pb.kind = kind; pb.n = n; pb.H = hidden; pb.P = oracle_param_count(kind, n, hidden);
     pb.params_shared = params_shared; pb.B = B; pb.N = N; pb.offsets = offsets;
     pb.times = times; pb.params = params;
@@ -474,4 +556,37 @@ int oracle_adjoint(int kind, int n, int hidden, int64_t B, int64_t N, const int6
         free(gp_series);
     }
     return rc;
+}
+
+int oracle_forward(int kind, int n, int hidden, int64_t B, int64_t N, const int64_t *offsets,
+                   const double *times, const double *y0, const double *params, int params_shared,
+                   double tol_a, double tol_r, int max_newton, int threads,
+                   double *y_out, int32_t *status, int32_t *iters)
+{
+    return forward_driver(0, kind, n, hidden, B, N, offsets, times, y0, params, params_shared, tol_a, tol_r,
+                          max_newton, threads, y_out, status, iters);
+}
+
+int oracle_adjoint(int kind, int n, int hidden, int64_t B, int64_t N, const int64_t *offsets,
+                   const double *times, const double *y, const double *params, int params_shared,
+                   const double *g, int threads, double *dLdp, double *dLdy0, int32_t *status)
+{
+    return adjoint_driver(0, kind, n, hidden, B, N, offsets, times, y, params, params_shared, g, threads, dLdp,
+                          dLdy0, status);
+}
+
+int oracle_forward_euler(int kind, int n, int hidden, int64_t B, int64_t N, const int64_t *offsets,
+                         const double *times, const double *y0, const double *params, int params_shared,
+                         int threads, double *y_out, int32_t *status)
+{
+    return forward_driver(1, kind, n, hidden, B, N, offsets, times, y0, params, params_shared, 0.0, 0.0, 0,
+                          threads, y_out, status, NULL);
+}
+
+int oracle_forward_euler_adjoint(int kind, int n, int hidden, int64_t B, int64_t N, const int64_t *offsets,
+                                 const double *times, const double *y, const double *params, int params_shared,
+                                 const double *g, int threads, double *dLdp, double *dLdy0, int32_t *status)
+{
+    return adjoint_driver(1, kind, n, hidden, B, N, offsets, times, y, params, params_shared, g, threads, dLdp,
+                          dLdy0, status);
 }

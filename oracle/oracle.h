@@ -1,5 +1,5 @@
 /*
- * CPU oracle for time-vectorized backward-Euler integration.
+ * CPU oracle for time-vectorized backward- and forward-Euler integration.
  *
  * TEST INFRASTRUCTURE ONLY: used by the test suite, the smoke check and the
  * CPU-baseline leg of the benchmark, never by the library.  Shares no code
@@ -66,6 +66,17 @@ int oracle_forward(int kind, int n, int hidden, int64_t B, int64_t N, const int6
 int oracle_adjoint(int kind, int n, int hidden, int64_t B, int64_t N, const int64_t *offsets,
                    const double *times, const double *y, const double *params, int params_shared,
                    const double *g, int threads, double *dLdp, double *dLdy0, int32_t *status);
+
+/* Sequential forward Euler: y_k = y_{k-1} + (t_k - t_{k-1}) h(y_{k-1}, t_{k-1}; p).
+ * A non-finite state stops its series (NONFINITE; NaN from that step on). */
+int oracle_forward_euler(int kind, int n, int hidden, int64_t B, int64_t N, const int64_t *offsets,
+                         const double *times, const double *y0, const double *params, int params_shared,
+                         int threads, double *y_out, int32_t *status);
+
+/* Discrete adjoint of the map computed by oracle_forward_euler, given its trajectory y. */
+int oracle_forward_euler_adjoint(int kind, int n, int hidden, int64_t B, int64_t N, const int64_t *offsets,
+                                 const double *times, const double *y, const double *params, int params_shared,
+                                 const double *g, int threads, double *dLdp, double *dLdy0, int32_t *status);
 
 #ifdef __cplusplus
 }

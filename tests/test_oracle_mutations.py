@@ -6,6 +6,7 @@ import subprocess
 import pytest
 
 import oracle
+from tests import test_oracle_forward_euler as fe
 from tests import test_oracle_pins as pins
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
@@ -35,6 +36,16 @@ MUTATIONS = [
     ("vdp_param_vjp_wrong_component", "gp[0] += w[1] * (1.0 - y[0] * y[0]) * y[1];",
      "gp[0] += w[0] * (1.0 - y[0] * y[0]) * y[1];",
      [lambda: pins.test_model_param_vjp_matches_central_differences(pins._model_cases()[1])]),
+    ("fe_update_sign", "Y[k * n + i] = yp[i] + dt * f[i];", "Y[k * n + i] = yp[i] - dt * f[i];",
+     [fe.test_fe_linear_closed_form, fe.test_fe_vdp_mu_zero_is_a_growing_rotation]),
+    ("fe_rate_at_wrong_time_point", "rhs(kind, n, H, yp, t[k - 1], p, f, NULL);",
+     "rhs(kind, n, H, yp + (k > 1 ? -n : 0), t[k - 1], p, f, NULL);",
+     [fe.test_fe_linear_closed_form]),
+    ("fe_adjoint_untransposed", "s += dt1 * J[r * n + i] * lam[r];", "s += dt1 * J[i * n + r] * lam[r];",
+     [fe.test_fe_adjoint_linear_closed_form, fe.test_fe_adjoint_fd_vanderpol]),
+    ("fe_adjoint_param_term_at_new_state", "vjp_p(kind, n, H, Y + (k - 1) * n, t[k - 1], p, w, gp);",
+     "vjp_p(kind, n, H, Y + k * n, t[k - 1], p, w, gp);",
+     [fe.test_fe_adjoint_linear_closed_form, fe.test_fe_adjoint_fd_vanderpol]),
 ]
 
 
