@@ -102,6 +102,16 @@ typedef enum {
                               and steps_per_lane * n <= 12 (TVI_EUNSUPPORTED otherwise)        */
 } tvi_init;
 
+typedef enum {
+    TVI_BACKWARD_EULER = 0, /* y_k - y_{k-1} - dt_k h(y_k, t_k) = 0 (Section 2.2, Eq. backward-euler)  */
+    TVI_FORWARD_EULER = 1   /* y_k - y_{k-1} - dt_k h(y_{k-1}, t_{k-1}) = 0 (Eq. forward-euler):
+                               the same chunked Newton solve with identity diagonal blocks and
+                               sub-diagonal blocks -(I + dt_j j(y_{j-1})), no block inverse; one
+                               correction per chunk for a linear h.  Linear, Van der Pol and
+                               Robertson only (TVI_EUNSUPPORTED for TVI_MLP and with
+                               TVI_INIT_PREDICTOR); the adjoint is that of the explicit map     */
+} tvi_scheme;
+
 typedef struct {
     int32_t kind;          /* tvi_model_kind                                   */
     int32_t n;             /* state size                                       */
@@ -132,11 +142,13 @@ typedef struct {
                                   permutation of 0..B-1 (entries outside [0, B)
                                   leave their slot idle; repeated entries give
                                   undefined results).  See tvi_order_longest_first */
+    int32_t scheme;            /* tvi_scheme                                        */
 } tvi_options;
 
 /* Fills `opt` with the defaults: chunk 64, tol_a 1e-8, tol_r 1e-6 (Section 2.3),
  * max_newton 50, lanes/steps chosen from chunk, TVI_INIT_ZERO, halving on, no
- * predictor (predictor_base 1 once one is given), series in index order. */
+ * predictor (predictor_base 1 once one is given), series in index order,
+ * backward Euler. */
 void tvi_default_options(tvi_options *opt);
 
 /* tvi_order_longest_first -- the launch order that solves ragged series

@@ -82,6 +82,8 @@ tvi_status check_options(const tvi_options *o)
         (!o->predictor || o->predictor_hidden < 1 || o->predictor_hidden > 256 || o->predictor_steps < o->chunk ||
          (o->predictor_base != 0 && o->predictor_base != 1)))
         return TVI_EINVAL;
+    if (o->scheme != TVI_BACKWARD_EULER && o->scheme != TVI_FORWARD_EULER) return TVI_EINVAL;
+    if (o->scheme == TVI_FORWARD_EULER && o->init == TVI_INIT_PREDICTOR) return TVI_EUNSUPPORTED;
     return TVI_OK;
 }
 
@@ -110,6 +112,7 @@ SolveArgs<IO> make_args(const tvi_model *model, const tvi_options *opt, int64_t 
     a.pred_steps = opt->predictor_steps;
     a.pred_base = opt->predictor_base;
     a.order = opt->order;
+    a.scheme = opt->scheme;
     return a;
 }
 
@@ -151,6 +154,7 @@ void tvi_default_options(tvi_options *opt)
     opt->predictor_steps = 0;
     opt->predictor_base = 1;
     opt->order = nullptr;
+    opt->scheme = TVI_BACKWARD_EULER;
 }
 
 const char *tvi_status_str(int32_t s)
@@ -214,7 +218,7 @@ tvi_status tvi_solve_forward(const tvi_model *model, const tvi_options *opt, int
     if (!times || !y0 || !params || !status || (!y_out && !ckpt)) return TVI_EINVAL;
     int S = 0, T = 0;
     if (model->kind == TVI_MLP) {
-        if (opt->chunk > 128) return TVI_EUNSUPPORTED;
+        if (opt->chunk > 128 || opt->scheme != TVI_BACKWARD_EULER) return TVI_EUNSUPPORTED;
     } else if ((e = resolve_tiling(opt, S, T)) != TVI_OK) {
         return e;
     } else if (opt->init == TVI_INIT_PREDICTOR && (S < 4 || T * model->n > kPredictorMaxTN)) {
@@ -263,7 +267,7 @@ tvi_status tvi_solve_adjoint(const tvi_model *model, const tvi_options *opt, int
         (!workspace || workspace_bytes < tvi_adjoint_workspace_bytes(model, opt, B)))
         return TVI_EINVAL;
     if (mlp) {
-        if (opt->chunk > 128) return TVI_EUNSUPPORTED;
+        if (opt->chunk > 128 || opt->scheme != TVI_BACKWARD_EULER) return TVI_EUNSUPPORTED;
         const int pass = recompute ? PASS_ADJOINT_RECOMPUTE : PASS_ADJOINT;
         const hipStream_t st = static_cast<hipStream_t>(stream);
         if (model->dtype == TVI_F64) {

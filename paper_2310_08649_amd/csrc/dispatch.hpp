@@ -25,6 +25,22 @@ static tvi_status launch_st(int pass, const SolveArgs<IO> &a, hipStream_t stream
     if (pred && !kPred && pass != PASS_ADJOINT) return TVI_EUNSUPPORTED;
     // its hidden layers and outputs: [segments][2H + n S T] floats of LDS
     const size_t lds = pred ? (size_t)per_block * (2 * a.pred_hidden + Model::N * S * T) * sizeof(float) : 0;
+    if (a.scheme == 1) {  // forward Euler: its own instances, no learned start
+        if (pred) return TVI_EUNSUPPORTED;
+        switch (pass) {
+        case PASS_FORWARD:
+            hipLaunchKernelGGL((forward_kernel<Model, IO, S, T, false, true>), grid, block, 0, stream, a);
+            break;
+        case PASS_ADJOINT:
+            hipLaunchKernelGGL((adjoint_kernel<Model, IO, S, T, false, false, true>), grid, block, 0, stream, a);
+            break;
+        case PASS_ADJOINT_RECOMPUTE:
+            hipLaunchKernelGGL((adjoint_kernel<Model, IO, S, T, true, false, true>), grid, block, 0, stream, a);
+            break;
+        default: return TVI_EINVAL;
+        }
+        return hipGetLastError() == hipSuccess ? TVI_OK : TVI_EHIP;
+    }
     switch (pass) {
     case PASS_FORWARD:
         if constexpr (kPred) {

@@ -17,6 +17,14 @@
 // S = 1 is the one-series-per-lane sequential solver (chunk = 1) or
 // per-lane Thomas; T = 1 is pure PCR.
 //
+// FE instances integrate the explicit scheme (Eq. forward-euler) the same
+// way: the chunk residual is R_j = dy_j - dy_{j-1} - dt_j h(y_s + dy_{j-1},
+// t_{s+j-1}), the chunk Jacobian has identity diagonal blocks and
+// sub-diagonal blocks -(I + dt_j j(y_{j-1})), so the correction is the affine
+// recurrence delta_j = (I + dt_j j_{j-1}) delta_{j-1} - R_j: the same maps and
+// scans, with no block inverse.  Newton on this lower-triangular system makes
+// the chunk exact after at most m corrections (one for a linear h).
+//
 // Control flow is flattened into one wave-uniform loop so that series of a
 // wave that converge, fail, halve their chunk or finish at different times
 // never leave a cross-lane read divergent.
@@ -47,6 +55,7 @@ struct SolveArgs {
     const float *pred;         // learned chunk predictor, inference layout (INIT_PREDICTOR)
     int32_t pred_hidden, pred_steps, pred_base;
     const int32_t *order;      // launch slot -> series (longest first), or null
+    int32_t scheme;            // 0 backward Euler, 1 forward Euler (selects the instance)
 };
 
 template <class IO>
@@ -167,8 +176,9 @@ __device__ __forceinline__ void dense_t(const float *__restrict__ Wt, int ld, co
     }
 }
 
-// Per-lane state of the chunked Newton solve of one series.
-template <class Model, int S, int T>
+// Per-lane state of the chunked Newton solve of one series (FE: the
+// forward-Euler chunk system instead of the backward-Euler one).
+template <class Model, int S, int T, bool FE = false>
 struct ChunkNewton {
     static constexpr int n = Model::N;
     static constexpr bool kPredictorT = T * n <= kPredictorMaxTN;  // register budget of the learned start
@@ -192,6 +202,7 @@ struct ChunkNewton {
     // Backward-Euler residual of the chunk at iterate d (owned steps; zero
     // elsewhere), stored in R if KEEP, and its squared Euclidean norm over the
     // segment (the tests compare squares: no square root in the loop).
+    // FE: the forward-Euler residual, the rate taken at the previous step.
     // Wave-uniform.
     template <bool KEEP>
     __device__ __forceinline__ double residual(const Model &model, const double (&d)[T][n], int q,
@@ -203,9 +214,15 @@ struct ChunkNewton {
 #pragma unroll
         for (int i = 0; i < T; ++i) {
             double yv[n], f[n];
+            if constexpr (FE) {
 #pragma unroll
-            for (int k = 0; k < n; ++k) yv[k] = ys[k] + d[i][k];
-            model.rhs(yv, tt[i], f);
+                for (int k = 0; k < n; ++k) yv[k] = ys[k] + ((i == 0) ? (q > 0 ? prev[k] : 0.0) : d[i - 1][k]);
+                model.rhs(yv, tt[i] - hh[i], f);
+            } else {
+#pragma unroll
+                for (int k = 0; k < n; ++k) yv[k] = ys[k] + d[i][k];
+                model.rhs(yv, tt[i], f);
+            }
             const bool v = owned(q, i);
 #pragma unroll
             for (int k = 0; k < n; ++k) {
@@ -413,23 +430,40 @@ struct ChunkNewton {
                 AffineI<n, double> map;
                 affine_identity(map);
                 int ok = 1;
+                double prev[n];  // FE: the increment at the step before the lane's first
+                if constexpr (FE) vec_prev(dy[T - 1], prev);
 #pragma unroll
                 for (int i = 0; i < T; ++i) {
                     if (corr && owned(q, i)) {
-                        double yv[n], J[n][n], D[n][n];
+                        if constexpr (FE) {
+                            // delta_j = (I + dt_j j(y_{j-1})) delta_{j-1} - R_j
+                            double yv[n], J[n][n];
 #pragma unroll
-                        for (int k = 0; k < n; ++k) yv[k] = ys[k] + dy[i][k];
-                        model.jac(yv, tt[i], J);
+                            for (int k = 0; k < n; ++k)
+                                yv[k] = ys[k] + ((i == 0) ? (q > 0 ? prev[k] : 0.0) : dy[i - 1][k]);
+                            model.jac(yv, tt[i] - hh[i], J);
 #pragma unroll
-                        for (int r = 0; r < n; ++r)
+                            for (int r = 0; r < n; ++r) {
 #pragma unroll
-                            for (int c = 0; c < n; ++c) D[r][c] = ((r == c) ? 1.0 : 0.0) - hh[i] * J[r][c];
-                        ok &= invert_plus(D, Fi[i]) ? 1 : 0;
-                        const double zero[n] = {};
-                        double negR[n];
+                                for (int c = 0; c < n; ++c) Fi[i][r][c] = hh[i] * J[r][c];
+                                zi[i][r] = -R[i][r];
+                            }
+                        } else {
+                            double yv[n], J[n][n], D[n][n];
 #pragma unroll
-                        for (int k = 0; k < n; ++k) negR[k] = -R[i][k];
-                        apply_ip(Fi[i], negR, zero, zi[i]);
+                            for (int k = 0; k < n; ++k) yv[k] = ys[k] + dy[i][k];
+                            model.jac(yv, tt[i], J);
+#pragma unroll
+                            for (int r = 0; r < n; ++r)
+#pragma unroll
+                                for (int c = 0; c < n; ++c) D[r][c] = ((r == c) ? 1.0 : 0.0) - hh[i] * J[r][c];
+                            ok &= invert_plus(D, Fi[i]) ? 1 : 0;
+                            const double zero[n] = {};
+                            double negR[n];
+#pragma unroll
+                            for (int k = 0; k < n; ++k) negR[k] = -R[i][k];
+                            apply_ip(Fi[i], negR, zero, zi[i]);
+                        }
                         AffineI<n, double> step;
 #pragma unroll
                         for (int r = 0; r < n; ++r) {
@@ -478,7 +512,7 @@ struct ChunkNewton {
 // ---------------------------------------------------------------------------
 // Forward kernel: one segment of S lanes per series, 64 / S series per wave.
 // ---------------------------------------------------------------------------
-template <class Model, class IO, int S, int T, bool PRED>
+template <class Model, class IO, int S, int T, bool PRED, bool FE = false>
 __global__ __launch_bounds__(kWave) void forward_kernel(SolveArgs<IO> a)
 {
     constexpr int n = Model::N;
@@ -489,7 +523,7 @@ __global__ __launch_bounds__(kWave) void forward_kernel(SolveArgs<IO> a)
     Model model;
     if (sv.valid) model.load(a.params_shared ? a.params : a.params + sv.b * Model::P);
 
-    ChunkNewton<Model, S, T> cn;
+    ChunkNewton<Model, S, T, FE> cn;
     if (sv.valid) {
 #pragma unroll
         for (int k = 0; k < n; ++k) cn.ys[k] = ld(a.y0 + sv.b * n + k);
@@ -523,8 +557,11 @@ __global__ __launch_bounds__(kWave) void forward_kernel(SolveArgs<IO> a)
 // the affine recurrence lam_j = D_j^{-T} lam_{j+1} + D_j^{-T} g_j, reduced by
 // the same segment scan run from the highest lane down.  With RECOMPUTE the
 // chunk's states are re-solved from its checkpoint by the forward code.
+// FE: the discrete adjoint of the forward-Euler map,
+//   lam_k = (I + dt_{k+1} j(y_k))^T lam_{k+1} + g_k,  lam_{N+1} = 0,
+//   dL/dp = sum_k dt_k (dh/dp(y_{k-1}))^T lam_k,  dL/dy0 = g_0 + (I + dt_1 j(y_0))^T lam_1.
 // ---------------------------------------------------------------------------
-template <class Model, class IO, int S, int T, bool RECOMPUTE, bool PRED>
+template <class Model, class IO, int S, int T, bool RECOMPUTE, bool PRED, bool FE = false>
 __global__ __launch_bounds__(kWave) void adjoint_kernel(SolveArgs<IO> a)
 {
     constexpr int n = Model::N;
@@ -556,7 +593,7 @@ __global__ __launch_bounds__(kWave) void adjoint_kernel(SolveArgs<IO> a)
         const int m = active ? (int)min((int64_t)C, sv.Nb - s) : 0;
 
         if (RECOMPUTE) {
-            ChunkNewton<Model, S, T> cn;
+            ChunkNewton<Model, S, T, FE> cn;
             const bool have_ckpt = active && c < a.K;
             if (active && !have_ckpt) status = ST_NONFINITE;
             cn.active = have_ckpt;
@@ -594,15 +631,28 @@ __global__ __launch_bounds__(kWave) void adjoint_kernel(SolveArgs<IO> a)
             tl[i] = v ? ld(sv.t + k) : 0.0;
             hl[i] = v ? tl[i] - ld(sv.t + k - 1) : 0.0;
             if (v) {
-                double J[n][n], D[n][n];
-                model.jac(yl[i], tl[i], J);
+                if constexpr (FE) {
+                    // I + Fi = I + dt_{k+1} j(y_k); nothing follows the series' last step
+                    double J[n][n];
+                    const double h1 = (k < sv.Nb) ? ld(sv.t + k + 1) - tl[i] : 0.0;
+                    model.jac(yl[i], tl[i], J);
 #pragma unroll
-                for (int r = 0; r < n; ++r)
+                    for (int r = 0; r < n; ++r) {
 #pragma unroll
-                    for (int cc = 0; cc < n; ++cc) D[r][cc] = ((r == cc) ? 1.0 : 0.0) - hl[i] * J[r][cc];
-                ok &= invert_plus(D, Fi[i]) ? 1 : 0;
-                const double zero[n] = {};
-                apply_ip_t(Fi[i], gk, zero, wi[i]);
+                        for (int cc = 0; cc < n; ++cc) Fi[i][r][cc] = h1 * J[r][cc];
+                        wi[i][r] = gk[r];
+                    }
+                } else {
+                    double J[n][n], D[n][n];
+                    model.jac(yl[i], tl[i], J);
+#pragma unroll
+                    for (int r = 0; r < n; ++r)
+#pragma unroll
+                        for (int cc = 0; cc < n; ++cc) D[r][cc] = ((r == cc) ? 1.0 : 0.0) - hl[i] * J[r][cc];
+                    ok &= invert_plus(D, Fi[i]) ? 1 : 0;
+                    const double zero[n] = {};
+                    apply_ip_t(Fi[i], gk, zero, wi[i]);
+                }
                 AffineI<n, double> stp;
 #pragma unroll
                 for (int r = 0; r < n; ++r) {
@@ -623,6 +673,17 @@ __global__ __launch_bounds__(kWave) void adjoint_kernel(SolveArgs<IO> a)
 #pragma unroll
             for (int k = 0; k < n; ++k) lin[k] = lam[k];
         }
+        // FE: the state before each owned step (the parameter term is taken there)
+        double ybefore[n];
+        if constexpr (FE) {
+            vec_prev(yl[T - 1], ybefore);
+            if (q == 0 && active) {
+                const bool have = !RECOMPUTE || c < a.K;  // a missing checkpoint already failed the series
+#pragma unroll
+                for (int e = 0; e < n; ++e)
+                    ybefore[e] = !have ? 0.0 : RECOMPUTE ? a.ckpt[(sv.b * a.K + c) * n + e] : (double)ld(yb + s * n + e);
+            }
+        }
 #pragma unroll
         for (int i = T - 1; i >= 0; --i) {
             const int j = q * T + i + 1;
@@ -631,7 +692,14 @@ __global__ __launch_bounds__(kWave) void adjoint_kernel(SolveArgs<IO> a)
                 double w[n];
 #pragma unroll
                 for (int k = 0; k < n; ++k) w[k] = hl[i] * lin[k];
-                model.vjp_p(yl[i], tl[i], w, gp);
+                if constexpr (FE) {
+                    double yp[n];
+#pragma unroll
+                    for (int k = 0; k < n; ++k) yp[k] = (i == 0) ? ybefore[k] : yl[i - 1][k];
+                    model.vjp_p(yp, tl[i] - hl[i], w, gp);
+                } else {
+                    model.vjp_p(yl[i], tl[i], w, gp);
+                }
             }
         }
         double first[n];
@@ -651,6 +719,25 @@ __global__ __launch_bounds__(kWave) void adjoint_kernel(SolveArgs<IO> a)
     for (int k = 0; k < P; ++k) gp[k] = seg_sum<S>(gp[k]);
     if (sv.valid && q == 0) {
         const double nan = __builtin_nan("");
+        if constexpr (FE) {
+            // lam <- (I + dt_1 j(y_0))^T lam_1 (lam_1 = 0 when the series has no step)
+            if (sv.Nb > 0) {
+                double y0v[n], J[n][n], out[n];
+#pragma unroll
+                for (int e = 0; e < n; ++e) y0v[e] = RECOMPUTE ? a.ckpt[sv.b * a.K * n + e] : (double)ld(yb + e);
+                const double t0 = ld(sv.t), h1 = ld(sv.t + 1) - t0;
+                model.jac(y0v, t0, J);
+#pragma unroll
+                for (int e = 0; e < n; ++e) {
+                    double acc = lam[e];
+#pragma unroll
+                    for (int r = 0; r < n; ++r) acc = fma(h1 * J[r][e], lam[r], acc);
+                    out[e] = acc;
+                }
+#pragma unroll
+                for (int e = 0; e < n; ++e) lam[e] = out[e];
+            }
+        }
 #pragma unroll
         for (int k = 0; k < n; ++k) st(a.dLdy0 + sv.b * n + k, status == ST_OK ? ld(gb + k) + lam[k] : nan);
 #pragma unroll

@@ -7,7 +7,7 @@ fallback: when the library or a GPU is missing these functions raise.
 
 Entry points with the C names:
   ``pcr_solve``      batched block-bidiagonal solve (Section 3)
-  ``solve_forward``  chunked backward Euler (Algorithm 1)
+  ``solve_forward``  chunked backward Euler (Algorithm 1), or forward Euler
   ``solve_adjoint``  its discrete adjoint (Appendix A)
 and, on top of them,
   ``odeint``         forward integration returning the trajectory
@@ -28,6 +28,7 @@ LIB_PATH = os.path.join(_HERE, "libtvi.so")
 KINDS = {"linear": 0, "vanderpol": 1, "robertson": 2, "mlp": 3}
 F32, F64 = 0, 1
 INIT = {"zero": 0, "extrap": 1, "predictor": 2}
+SCHEMES = {"backward_euler": 0, "forward_euler": 1}
 STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "SINGULAR", 3: "NONFINITE"}
 
 
@@ -45,7 +46,7 @@ class Options(ctypes.Structure):
                 ("max_newton", ctypes.c_int32), ("tol_a", ctypes.c_double), ("tol_r", ctypes.c_double),
                 ("init", ctypes.c_int32), ("halving", ctypes.c_int32), ("predictor", ctypes.c_void_p),
                 ("predictor_hidden", ctypes.c_int32), ("predictor_steps", ctypes.c_int32),
-                ("predictor_base", ctypes.c_int32), ("order", ctypes.c_void_p)]
+                ("predictor_base", ctypes.c_int32), ("order", ctypes.c_void_p), ("scheme", ctypes.c_int32)]
 
 
 _lib = None
@@ -121,10 +122,11 @@ def param_count(kind, n, hidden=64):
 
 
 def make_options(chunk=64, tol=(1e-8, 1e-6), max_newton=50, lanes=0, steps_per_lane=0, init="zero",
-                 halving=True, predictor=None, order=None):
+                 halving=True, predictor=None, order=None, scheme="backward_euler"):
     """``predictor``: (packed params, hidden, steps[, base]) of a trained chunk
     predictor, as made by ``predictor.solver_args`` (base 0: corrections to the
-    zero start, 1: to the extrapolated start)."""
+    zero start, 1: to the extrapolated start).  ``scheme``: "backward_euler" or
+    "forward_euler"."""
     o = Options()
     load().tvi_default_options(ctypes.byref(o))
     o.chunk = int(chunk)
@@ -140,6 +142,7 @@ def make_options(chunk=64, tol=(1e-8, 1e-6), max_newton=50, lanes=0, steps_per_l
         o.predictor_base = int(predictor[3]) if len(predictor) > 3 else 1
     if order is not None:
         o.order = ctypes.c_void_p(order.data_ptr())
+    o.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
     return o
 
 
@@ -200,8 +203,8 @@ def _geometry(y0, times, offsets):
 
 def solve_forward(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e-6), max_newton=50, lanes=0,
                   steps_per_lane=0, init="zero", halving=True, checkpoints=False, y_out=None, iters=True,
-                  predictor=None, order=None):
-    """Chunked backward Euler.  Returns ``(y, status, iters, ckpt)`` (device tensors;
+                  predictor=None, order=None, scheme="backward_euler"):
+    """Chunked backward Euler (or forward Euler, ``scheme="forward_euler"``).  Returns ``(y, status, iters, ckpt)`` (device tensors;
     ``iters`` and ``ckpt`` may be None).  Asynchronous: nothing is synchronised."""
     dt = y0.dtype
     y0 = _dev(y0, dt, "y0")
@@ -211,7 +214,7 @@ def solve_forward(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e
         offsets = _dev(offsets, torch.int64, "offsets")
     B, n, N, yshape = _geometry(y0, times, offsets)
     model = Model(KINDS[kind], n, _io_dtype(y0), 1 if params.dim() == 1 else 0, 64)
-    opt = make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, halving, predictor, order)
+    opt = make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, halving, predictor, order, scheme)
     dev = y0.device
     y = y_out if y_out is not None else torch.empty(yshape, dtype=dt, device=dev)
     status = torch.empty(B, dtype=torch.int32, device=dev)
@@ -228,7 +231,7 @@ def solve_forward(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e
 
 def solve_adjoint(kind, times, params, g, y=None, ckpt=None, offsets=None, chunk=64, tol=(1e-8, 1e-6),
                   max_newton=50, lanes=0, steps_per_lane=0, init="zero", halving=True, n=None, predictor=None,
-                  order=None):
+                  order=None, scheme="backward_euler"):
     """Discrete adjoint.  Returns ``(dLdp [B,P], dLdy0 [B,n], status [B])``.
 
     States come from the trajectory ``y`` or, when ``y`` is None, are recomputed
@@ -253,7 +256,7 @@ def solve_adjoint(kind, times, params, g, y=None, ckpt=None, offsets=None, chunk
     if not shared and (params.dim() != 2 or params.shape[0] != B):
         raise TviError("parameters must be per series [B, P] or shared [P]")
     model = Model(KINDS[kind], n, _io_dtype(g), 1 if shared else 0, 64)
-    opt = make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, halving, predictor, order)
+    opt = make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, halving, predictor, order, scheme)
     lib = load()
     dev = g.device
     P = lib.tvi_param_count(ctypes.byref(model))
@@ -281,7 +284,8 @@ def check_status(status, what="integration"):
 
 
 def odeint(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e-6), check=True, **kw):
-    """Backward-Euler trajectory y [B, N+1, n] (or ragged [points, n])."""
+    """Trajectory y [B, N+1, n] (or ragged [points, n]); backward Euler unless
+    ``scheme="forward_euler"`` is passed."""
     y, status, _, _ = solve_forward(kind, y0, times, params, offsets=offsets, chunk=chunk, tol=tol, iters=False,
                                     **kw)
     if check:

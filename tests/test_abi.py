@@ -148,3 +148,28 @@ def test_predictor_options_and_pack_reject_bad_arguments(lib):
     assert lib.tvi_predictor_pack(ctypes.byref(d), f, f, None) == -1   # aliasing
     bad = pred.Predictor(0, 128, 32)
     assert lib.tvi_predictor_pack(ctypes.byref(bad), f, ctypes.c_void_p(0x2000), None) == -1
+
+
+def test_scheme_option_is_checked(lib):
+    """Forward Euler: an unknown scheme is invalid; the neural ODE and the learned
+    start are refused with it; the default is backward Euler."""
+    from paper_2310_08649_amd import tvi
+    f = _fake()
+    assert tvi.make_options().scheme == 0
+    m = tvi.Model(tvi.KINDS["vanderpol"], 2, tvi.F64, 0, 64)
+    o = tvi.make_options(chunk=16, scheme=2)
+    assert lib.tvi_solve_forward(ctypes.byref(m), ctypes.byref(o), 4, 10, None, f, f, f, f, None, f, None, None) == -1
+    assert lib.tvi_solve_adjoint(ctypes.byref(m), ctypes.byref(o), 4, 10, None, f, f, f, None, f, f, f, f, None, 0,
+                                 None) == -1
+
+    class P:
+        def data_ptr(self):
+            return 0x1000
+
+    o = tvi.make_options(chunk=16, init="predictor", predictor=(P(), 128, 16, 0), scheme="forward_euler")
+    assert lib.tvi_solve_forward(ctypes.byref(m), ctypes.byref(o), 4, 10, None, f, f, f, f, None, f, None, None) == -4
+    mm = tvi.Model(tvi.KINDS["mlp"], 8, tvi.F32, 1, 64)
+    o = tvi.make_options(chunk=16, scheme="forward_euler")
+    assert lib.tvi_solve_forward(ctypes.byref(mm), ctypes.byref(o), 4, 10, None, f, f, f, f, None, f, None, None) == -4
+    assert lib.tvi_solve_adjoint(ctypes.byref(mm), ctypes.byref(o), 4, 10, None, f, f, f, None, f, f, f, f, f, 10**9,
+                                 None) == -4
