@@ -306,10 +306,56 @@ def run_mlp(ctx, steps):
             "stored_trajectory_value": B * N / (st2["mean_ms"] * 1e-3),
             "forward_ms": fms, "forward_value": B * N / (fms * 1e-3), "newton_corrections": corrections,
             "failed": failed,
-            "roofline": {"kernel": "tvi::mlp_forward_kernel<float>", "bound": "mfma", "achieved": tf,
+            "roofline": {"kernel": "tvi::mlp_forward_kernel<float, false>", "bound": "mfma", "achieved": tf,
                          "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s", "frac": tf / PEAK_BF16_TFLOPS,
                          "flops_counted": "h: %d per step per Newton trip, J: %d per step per correction "
                                           "(useful products, not the bf16 split)" % (MLP_F_FLOPS, MLP_J_FLOPS)}}
+
+
+def run_forward_euler(ctx, steps):
+    """The explicit scheme (Eq. forward-euler) solved in chunks by the same Newton
+    and scan kernels: Van der Pol 512 x 5000 FP64 on [0, 10] with mu = 10^U(0,1)
+    (steps stable for forward Euler), forward, chunk swept against chunk 1; and
+    the neural ODE 64 x 1e4 FP32, chunk 100, forward + adjoint of the mean
+    squared state at 100 sampled times as one captured graph."""
+    import numpy as np
+    import torch
+    from paper_2310_08649_amd import graph, tvi, workloads
+    dev = ctx["dev"]
+    res = {"unit": "series*steps/s"}
+    w = workloads.vanderpol(mu_range=(1.0, 10.0), seed=120)
+    d = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev)
+    y0, times, mu = d(w["y0"]), d(w["times"]), d(w["params"])
+    B, N = w["y0"].shape[0], w["times"].shape[0] - 1
+    y = torch.empty((B, N + 1, 2), dtype=torch.float64, device=dev)
+    vdp = {}
+    for C in (1, 16, 32, 64, 128, 256):
+        fn = lambda: tvi.solve_forward("vanderpol", y0, times, mu, chunk=C, tol=TIMING_TOL, y_out=y, iters=False,
+                                       scheme="forward_euler", **({"lanes": 1, "steps_per_lane": 1} if C == 1 else {}))
+        st = fn()[1]
+        ms = float(np.median(time_launches(fn, max(3, steps // 2), ctx["stream"])))
+        vdp["chunk%d" % C] = {"value": B * N / (ms * 1e-3), "ms": ms, "failed": int((st != 0).sum().item())}
+    best = min((v["ms"], k) for k, v in vdp.items() if k != "chunk1" and v["failed"] == 0)
+    vdp["speedup_of_best_over_chunk1"] = vdp["chunk1"]["ms"] / best[0]
+    res["vanderpol_forward"] = vdp
+    del y
+    wm = workloads.mlp()
+    f = lambda a: torch.as_tensor(a, dtype=torch.float32, device=dev)
+    Bm, Nm = wm["y0"].shape[0], wm["times"].shape[0] - 1
+    obs = torch.zeros((Bm, Nm + 1), dtype=torch.uint8)
+    obs[:, torch.as_tensor(workloads.observed_steps(Nm))] = 1
+    mlp = {}
+    for C in (100, 1):
+        cs = graph.CapturedStep("mlp", f(wm["y0"]), f(wm["times"]), f(wm["params"]), chunk=C, tol=TIMING_TOL,
+                                loss="mean_square", observed=obs.reshape(-1), recompute=True,
+                                scheme="forward_euler").capture()
+        cs.replay()
+        st = stats(time_launches(cs.replay, 3, torch.cuda.current_stream()))
+        mlp["chunk%d" % C] = dict(value=Bm * Nm / (st["mean_ms"] * 1e-3), **st,
+                                  failed=int(((cs.status_fwd != 0) | (cs.status_adj != 0)).sum().item()))
+        del cs
+    res["mlp_forward_adjoint"] = mlp
+    return res
 
 
 def run_robertson(ctx, steps):
@@ -582,7 +628,8 @@ def main():
     if not args.no_extras:
         runs = [("chunk1", run_chunk1), ("fp32", run_vdp_fp32), ("fwd_adjoint", run_vdp_fwd_adjoint),
                 ("linear", run_linear), ("tiling_study", run_tiling_study), ("pcr_roofline", run_pcr),
-                ("mlp", run_mlp), ("robertson", run_robertson), ("predictor", run_predictor)]
+                ("mlp", run_mlp), ("robertson", run_robertson), ("predictor", run_predictor),
+                ("forward_euler", run_forward_euler)]
         only = set(filter(None, args.only.split(",")))
         for name, fn in runs:
             if not only or name in only:

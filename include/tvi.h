@@ -107,9 +107,9 @@ typedef enum {
     TVI_FORWARD_EULER = 1   /* y_k - y_{k-1} - dt_k h(y_{k-1}, t_{k-1}) = 0 (Eq. forward-euler):
                                the same chunked Newton solve with identity diagonal blocks and
                                sub-diagonal blocks -(I + dt_j j(y_{j-1})), no block inverse; one
-                               correction per chunk for a linear h.  Linear, Van der Pol and
-                               Robertson only (TVI_EUNSUPPORTED for TVI_MLP and with
-                               TVI_INIT_PREDICTOR); the adjoint is that of the explicit map     */
+                               correction per chunk for a linear h.  Every model; not with
+                               TVI_INIT_PREDICTOR (TVI_EUNSUPPORTED).  The adjoint is that of
+                               the explicit map                                                */
 } tvi_scheme;
 
 typedef struct {

@@ -218,7 +218,7 @@ tvi_status tvi_solve_forward(const tvi_model *model, const tvi_options *opt, int
     if (!times || !y0 || !params || !status || (!y_out && !ckpt)) return TVI_EINVAL;
     int S = 0, T = 0;
     if (model->kind == TVI_MLP) {
-        if (opt->chunk > 128 || opt->scheme != TVI_BACKWARD_EULER) return TVI_EUNSUPPORTED;
+        if (opt->chunk > 128) return TVI_EUNSUPPORTED;
     } else if ((e = resolve_tiling(opt, S, T)) != TVI_OK) {
         return e;
     } else if (opt->init == TVI_INIT_PREDICTOR && (S < 4 || T * model->n > kPredictorMaxTN)) {
@@ -267,7 +267,7 @@ tvi_status tvi_solve_adjoint(const tvi_model *model, const tvi_options *opt, int
         (!workspace || workspace_bytes < tvi_adjoint_workspace_bytes(model, opt, B)))
         return TVI_EINVAL;
     if (mlp) {
-        if (opt->chunk > 128 || opt->scheme != TVI_BACKWARD_EULER) return TVI_EUNSUPPORTED;
+        if (opt->chunk > 128) return TVI_EUNSUPPORTED;
         const int pass = recompute ? PASS_ADJOINT_RECOMPUTE : PASS_ADJOINT;
         const hipStream_t st = static_cast<hipStream_t>(stream);
         if (model->dtype == TVI_F64) {

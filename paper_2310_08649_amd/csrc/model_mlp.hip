@@ -19,6 +19,12 @@
 // accumulate dL/dtheta = sum_j dt_j (dh/dtheta)^T lam_j.  Every workgroup
 // writes its series' partial gradient; a second kernel sums the partials over
 // the series in a fixed order.
+//
+// FE instances integrate the explicit scheme (Eq. forward-euler): the network
+// is evaluated at the previous step's state (step j reads position j, which
+// holds y_{j-1}), the blocks are I + dt_j J(y_{j-1}) with no inverse, and the
+// adjoint evaluates position j at y_{s+j}: the map (I + dt_{s+j+1} J(y_{s+j}))^T
+// and the parameter term of step s+j+1 share that position's activations.
 #include "dispatch.hpp"
 #include "mlp.hpp"
 
@@ -111,8 +117,10 @@ struct MlpChunkSink {
     __device__ void fail(int64_t, int) const {}
 };
 
-// Residual of the chunk iterate dy (Eq. batched-backward-euler) for the lane's
-// step, and its norm over the chunk (block-wide; every thread calls it).
+// Residual of the chunk iterate dy (Eq. batched-backward-euler; FE: Eq.
+// forward-euler) for the lane's step, and its norm over the chunk (block-wide;
+// every thread calls it).
+template <bool FE = false>
 __device__ __forceinline__ float chunk_residual(MlpShared &S, Acts &A, const double (&ys)[NS], const float (&dy)[NS],
                                                 float hj, bool v, float (&R)[NS])
 {
@@ -121,7 +129,13 @@ __device__ __forceinline__ float chunk_residual(MlpShared &S, Acts &A, const dou
     if (l < kSPW) {
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
-            S.y[j][k] = (float)(ys[k] + (double)dy[k]);
+            if constexpr (FE) {
+                // the network input of step j + 1 is this step's state; step 0 reads the chunk start
+                if (j + 1 < kMaxChunk) S.y[j + 1][k] = (float)(ys[k] + (double)dy[k]);
+                if (j == 0) S.y[0][k] = (float)ys[k];
+            } else {
+                S.y[j][k] = (float)(ys[k] + (double)dy[k]);
+            }
             S.dy[j][k] = dy[k];
         }
     }
@@ -211,7 +225,7 @@ __device__ __forceinline__ bool block_inverse_plus(const float *J, float dt, flo
 
 // Backward Euler from step s0 (state ys) to s_end in attempts that never cross
 // a multiple of C.  Every thread of the block calls it; returns the status.
-template <class IO, class Sink>
+template <bool FE, class IO, class Sink>
 __device__ int mlp_solve(MlpShared &S, const SolveArgs<IO> &a, const IO *t, double (&ys)[NS], int64_t s0,
                          int64_t s_end, int &total, const Sink &sink)
 {
@@ -250,7 +264,7 @@ __device__ int mlp_solve(MlpShared &S, const SolveArgs<IO> &a, const IO *t, doub
                     for (int k = 0; k < NS; ++k) dy[k] = tj * S.f[j][k];
                 }
             }
-            if (a.init == INIT_PREDICTOR) {
+            if (!FE && a.init == INIT_PREDICTOR) {  // not offered with the explicit scheme
                 // the learned start: its base (zero or extrapolated increments) plus the
                 // predicted corrections, kept only if its residual is below the base's
                 float *scratch = &S.u.v.a[0][0][0];
@@ -275,7 +289,7 @@ __device__ int mlp_solve(MlpShared &S, const SolveArgs<IO> &a, const IO *t, doub
 
         // ---- residual of the current iterate
         float R[NS];
-        const float nrm = chunk_residual(S, A, ys, dy, hj, v, R);
+        const float nrm = chunk_residual<FE>(S, A, ys, dy, hj, v, R);
 
         int act, code = ST_OK;
         if (it == 0) nrm0 = nrm;
@@ -320,12 +334,22 @@ __device__ int mlp_solve(MlpShared &S, const SolveArgs<IO> &a, const IO *t, doub
         affine_identity(map);
         int ok = 1;
         if (v) {
-            // (I - dt J)^{-1} = I + F; the correction map x -> (I + F)(x - R)
-            ok = block_inverse_plus<false>(S.u.J[j], hj, map.F) ? 1 : 0;
-            float negR[NS], zero[NS];
+            if constexpr (FE) {
+                // the correction map x -> (I + dt J(y_{j-1})) x - R
 #pragma unroll
-            for (int k = 0; k < NS; ++k) { negR[k] = -R[k]; zero[k] = 0.f; }
-            apply_ip(map.F, negR, zero, map.z);
+                for (int rr = 0; rr < NS; ++rr) {
+#pragma unroll
+                    for (int cc = 0; cc < NS; ++cc) map.F[rr][cc] = hj * S.u.J[j][rr * NS + cc];
+                    map.z[rr] = -R[rr];
+                }
+            } else {
+                // (I - dt J)^{-1} = I + F; the correction map x -> (I + F)(x - R)
+                ok = block_inverse_plus<false>(S.u.J[j], hj, map.F) ? 1 : 0;
+                float negR[NS], zero[NS];
+#pragma unroll
+                for (int k = 0; k < NS; ++k) { negR[k] = -R[k]; zero[k] = 0.f; }
+                apply_ip(map.F, negR, zero, map.z);
+            }
         }
         seg_scan_up<NS, kSPW>(map);
         ok = seg_and<kWave>(ok);
@@ -372,7 +396,7 @@ __device__ int mlp_solve(MlpShared &S, const SolveArgs<IO> &a, const IO *t, doub
     return status;
 }
 
-template <class IO>
+template <class IO, bool FE>
 __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(SolveArgs<IO> a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -392,7 +416,7 @@ __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(SolveArgs<IO> a)
     sink.boundary(0, ys, tid);
     __syncthreads();
     int total = 0;
-    const int status = mlp_solve(S, a, sv.t, ys, 0, sv.Nb, total, sink);
+    const int status = mlp_solve<FE>(S, a, sv.t, ys, 0, sv.Nb, total, sink);
     if (tid == 0) {
         a.status[b] = status;
         if (a.iters) a.iters[b] = total;
@@ -410,7 +434,7 @@ struct GradAcc {
     f32x4 w1[4];      // dW1 (columns 0..7) and db1 (column 8)
 };
 
-template <class IO, bool RECOMPUTE>
+template <class IO, bool RECOMPUTE, bool FE>
 __global__ __launch_bounds__(kThreads) void mlp_adjoint_kernel(SolveArgs<IO> a, float *theta_partial)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -448,7 +472,7 @@ __global__ __launch_bounds__(kThreads) void mlp_adjoint_kernel(SolveArgs<IO> a, 
 #pragma unroll
             for (int k = 0; k < NS; ++k) ys[k] = c < a.K ? a.ckpt[(b * a.K + c) * NS + k] : __builtin_nan("");
             int total = 0;
-            const int st2 = mlp_solve(S, a, sv.t, ys, c0, c0 + m, total, MlpChunkSink{S.yc, c0});
+            const int st2 = mlp_solve<FE>(S, a, sv.t, ys, c0, c0 + m, total, MlpChunkSink{S.yc, c0});
             if (st2 != ST_OK && status == ST_OK) status = st2;
         } else if (writer) {
 #pragma unroll
@@ -456,8 +480,21 @@ __global__ __launch_bounds__(kThreads) void mlp_adjoint_kernel(SolveArgs<IO> a, 
         }
         __syncthreads();
         if (writer) {
+            if constexpr (FE) {
+                // position j holds y_{c0+j}: the chunk start, then the converged states
+                float y0c[NS];
+                if (j == 0) {
 #pragma unroll
-            for (int k = 0; k < NS; ++k) S.y[j][k] = v ? S.yc[j][k] : 0.f;
+                    for (int k = 0; k < NS; ++k)
+                        y0c[k] = RECOMPUTE ? (c < a.K ? (float)a.ckpt[(b * a.K + c) * NS + k] : 0.f)
+                                           : (float)ld(a.y + (sv.p0 + c0) * NS + k);
+                }
+#pragma unroll
+                for (int k = 0; k < NS; ++k) S.y[j][k] = !v ? 0.f : (j == 0 ? y0c[k] : S.yc[j - 1][k]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < NS; ++k) S.y[j][k] = v ? S.yc[j][k] : 0.f;
+            }
         }
         __syncthreads();
         Acts A;
@@ -472,12 +509,23 @@ __global__ __launch_bounds__(kThreads) void mlp_adjoint_kernel(SolveArgs<IO> a, 
         affine_identity(map);
         int ok = 1;
         if (v) {
-            // (I - dt J)^{-T} = I + F^T
-            float gk[NS], zero[NS];
-            ok = block_inverse_plus<true>(S.u.J[j], hj, map.F) ? 1 : 0;
+            if constexpr (FE) {
+                // u_j = (I + dt_{c0+j+1} J(y_{c0+j}))^T u_{j+1} + g_{c0+j}: u_j = lam_{c0+j} for
+                // j >= 1; u_0 (no g: it belongs to the earlier chunk) is carried
 #pragma unroll
-            for (int k = 0; k < NS; ++k) { gk[k] = (float)ld(gb + (c0 + j + 1) * NS + k); zero[k] = 0.f; }
-            apply_ip(map.F, gk, zero, map.z);
+                for (int rr = 0; rr < NS; ++rr) {
+#pragma unroll
+                    for (int cc = 0; cc < NS; ++cc) map.F[rr][cc] = hj * S.u.J[j][cc * NS + rr];
+                    map.z[rr] = j == 0 ? 0.f : (float)ld(gb + (c0 + j) * NS + rr);
+                }
+            } else {
+                // (I - dt J)^{-T} = I + F^T
+                float gk[NS], zero[NS];
+                ok = block_inverse_plus<true>(S.u.J[j], hj, map.F) ? 1 : 0;
+#pragma unroll
+                for (int k = 0; k < NS; ++k) { gk[k] = (float)ld(gb + (c0 + j + 1) * NS + k); zero[k] = 0.f; }
+                apply_ip(map.F, gk, zero, map.z);
+            }
         }
         seg_scan_down<NS, kSPW>(map);
         ok = seg_and<kWave>(ok);
@@ -493,7 +541,11 @@ __global__ __launch_bounds__(kThreads) void mlp_adjoint_kernel(SolveArgs<IO> a, 
         __syncthreads();
         float lin[NS];
 #pragma unroll
-        for (int k = 0; k < NS; ++k) lin[k] = S.lam[k];
+        for (int k = 0; k < NS; ++k) {
+            // FE: the chunk's last step, lam_{c0+m} = g_{c0+m} + the carried value
+            lin[k] = S.lam[k];
+            if constexpr (FE) lin[k] += (float)ld(gb + (c0 + m) * NS + k);
+        }
         for (int q = kWaves - 1; q > w; --q) {
             float tv[NS];
 #pragma unroll
@@ -508,12 +560,24 @@ __global__ __launch_bounds__(kThreads) void mlp_adjoint_kernel(SolveArgs<IO> a, 
         }
         float lam_j[NS];
         apply_ip(map.F, lin, map.z, lam_j);
+        // FE: the parameter term of step c0+j+1 takes lam_{c0+j+1}, the next position's value
+        float lam_w[NS];
+        if constexpr (FE) {
+            vec_next(lam_j, lam_w);
+            if ((l & (kSPW - 1)) == kSPW - 1) {
+#pragma unroll
+                for (int k = 0; k < NS; ++k) lam_w[k] = lin[k];
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < NS; ++k) lam_w[k] = lam_j[k];
+        }
         if (!(S.flag[0] & S.flag[1] & S.flag[2] & S.flag[3]) && status == ST_OK) status = ST_SINGULAR;
         __syncthreads();
         // v_j = dt_j lam_j (zero beyond the chunk) into S.f; lam of the chunk's first step carried
         if (writer) {
 #pragma unroll
-            for (int k = 0; k < NS; ++k) S.f[j][k] = v ? hj * lam_j[k] : 0.f;
+            for (int k = 0; k < NS; ++k) S.f[j][k] = v ? hj * lam_w[k] : 0.f;
         }
         if (tid == 0) {
 #pragma unroll
@@ -647,7 +711,8 @@ __global__ __launch_bounds__(kThreads) void mlp_adjoint_kernel(SolveArgs<IO> a, 
         __syncthreads();
     }
 
-    // ---- dL/dy0 = g_0 + lam_1, and the series' parameter gradient (waves summed in order)
+    // ---- dL/dy0 = g_0 + lam_1 (FE: g_0 + the carried (I + dt_1 J(y_0))^T lam_1), and the
+    // series' parameter gradient (waves summed in order)
     if (tid < NS) st(a.dLdy0 + b * NS + tid, status == ST_OK ? ld(gb + tid) + (double)S.lam[tid] : __builtin_nan(""));
     for (int idx = tid; idx < P; idx += kThreads) S.u.theta[idx] = 0.f;
     __syncthreads();
@@ -731,7 +796,7 @@ static bool allow_lds(K kernel)
 
 size_t mlp_theta_workspace_bytes(int64_t B) { return (size_t)B * P * sizeof(float); }
 
-template <class IO>
+template <class IO, bool FE>
 static tvi_status mlp_launch(int pass, const SolveArgs<IO> &a, hipStream_t stream)
 {
     if (a.B == 0) return TVI_OK;
@@ -740,18 +805,18 @@ static tvi_status mlp_launch(int pass, const SolveArgs<IO> &a, hipStream_t strea
     const dim3 grid((unsigned)a.B), block(kThreads);
     switch (pass) {
     case PASS_FORWARD:
-        if (!allow_lds(mlp_forward_kernel<IO>)) return TVI_EHIP;
-        hipLaunchKernelGGL(mlp_forward_kernel<IO>, grid, block, shm, stream, a);
+        if (!allow_lds(mlp_forward_kernel<IO, FE>)) return TVI_EHIP;
+        hipLaunchKernelGGL((mlp_forward_kernel<IO, FE>), grid, block, shm, stream, a);
         break;
     case PASS_ADJOINT:
     case PASS_ADJOINT_RECOMPUTE: {
         float *partial = reinterpret_cast<float *>(a.ws);
         if (pass == PASS_ADJOINT) {
-            if (!allow_lds(mlp_adjoint_kernel<IO, false>)) return TVI_EHIP;
-            hipLaunchKernelGGL((mlp_adjoint_kernel<IO, false>), grid, block, shm, stream, a, partial);
+            if (!allow_lds(mlp_adjoint_kernel<IO, false, FE>)) return TVI_EHIP;
+            hipLaunchKernelGGL((mlp_adjoint_kernel<IO, false, FE>), grid, block, shm, stream, a, partial);
         } else {
-            if (!allow_lds(mlp_adjoint_kernel<IO, true>)) return TVI_EHIP;
-            hipLaunchKernelGGL((mlp_adjoint_kernel<IO, true>), grid, block, shm, stream, a, partial);
+            if (!allow_lds(mlp_adjoint_kernel<IO, true, FE>)) return TVI_EHIP;
+            hipLaunchKernelGGL((mlp_adjoint_kernel<IO, true, FE>), grid, block, shm, stream, a, partial);
         }
         if (hipGetLastError() != hipSuccess) return TVI_EHIP;
         hipLaunchKernelGGL(mlp_theta_reduce_kernel<IO>, dim3((P + 255) / 256), dim3(256), 0, stream, a.B,
@@ -763,10 +828,16 @@ static tvi_status mlp_launch(int pass, const SolveArgs<IO> &a, hipStream_t strea
     return hipGetLastError() == hipSuccess ? TVI_OK : TVI_EHIP;
 }
 
+template <class IO>
+static tvi_status mlp_launch_scheme(int pass, const SolveArgs<IO> &a, hipStream_t stream)
+{
+    return a.scheme == 1 ? mlp_launch<IO, true>(pass, a, stream) : mlp_launch<IO, false>(pass, a, stream);
+}
+
 tvi_status launch_mlp(int pass, int dtype, const void *args, hipStream_t stream)
 {
-    if (dtype == TVI_F64) return mlp_launch<double>(pass, *static_cast<const SolveArgs<double> *>(args), stream);
-    return mlp_launch<float>(pass, *static_cast<const SolveArgs<float> *>(args), stream);
+    if (dtype == TVI_F64) return mlp_launch_scheme<double>(pass, *static_cast<const SolveArgs<double> *>(args), stream);
+    return mlp_launch_scheme<float>(pass, *static_cast<const SolveArgs<float> *>(args), stream);
 }
 
 tvi_status launch_mlp_eval(int dtype, int64_t M, const void *states, const void *params, void *f, void *J,

@@ -165,3 +165,54 @@ def test_fe_odeint_adjoint_autograd(tvi):
     yo, _, _ = oracle.forward("vanderpol", w["y0"], times, w["params"], scheme=FE)
     op, oy0, _ = oracle.adjoint("vanderpol", yo, times, w["params"], yo / np.sqrt(np.sum(yo ** 2)), scheme=FE)
     assert grad_err(host(p.grad), op) <= 1e-10 and grad_err(host(y0.grad), oy0) <= 1e-10
+
+
+# --------------------------------------------------------------------------
+# The neural ODE (MFMA path, float): gate 1e-5 against the float64 oracle on
+# the same float-rounded inputs
+# --------------------------------------------------------------------------
+TOL32 = (1e-8, 1e-6)
+
+
+def _f32(w):
+    return (w[k].astype(np.float32) for k in ("y0", "times", "params"))
+
+
+@pytest.fixture(scope="module")
+def mlp_fe():
+    w = W.mlp()  # 64 series x 10000 steps
+    y0, times, theta = _f32(w)
+    yo, so, _ = oracle.forward("mlp", y0, times, theta, scheme=FE)
+    assert (so == 0).all()
+    return y0, times, theta, yo
+
+
+@pytest.mark.parametrize("chunk", [100, 1, 37, 128])
+def test_fe_mlp_forward_full_size(tvi, mlp_fe, chunk):
+    y0, times, theta, yo = mlp_fe
+    f = lambda a: dev(a, torch.float32)
+    y, st, it, _ = tvi.solve_forward("mlp", f(y0), f(times), f(theta), chunk=chunk, tol=TOL32, scheme=FE)
+    assert (host(st) == 0).all()
+    err = series_rel_err(host(y).astype(np.float64), yo)
+    assert err.max() <= 1e-5, err.max()
+
+
+def test_fe_mlp_adjoint_stored_and_recomputed(tvi):
+    w = W.mlp(B=8, N=2000)
+    y0, times, theta = _f32(w)
+    f = lambda a: dev(a, torch.float32)
+    y, st, _, ck = tvi.solve_forward("mlp", f(y0), f(times), f(theta), chunk=100, tol=TOL32, checkpoints=True,
+                                     scheme=FE)
+    assert (host(st) == 0).all()
+    yh = host(y).astype(np.float64)
+    obs = W.observed_steps(2000, every=100)
+    g = np.zeros_like(yh)
+    g[:, obs] = 2.0 * yh[:, obs] / (8 * len(obs) * 8)
+    a1 = tvi.solve_adjoint("mlp", f(times), f(theta), f(g), ckpt=ck, chunk=100, tol=TOL32, scheme=FE)
+    a2 = tvi.solve_adjoint("mlp", f(times), f(theta), f(g), y=y, chunk=100, tol=TOL32, scheme=FE)
+    assert (host(a1[2]) == 0).all() and (host(a2[2]) == 0).all()
+    assert torch.equal(a1[0], a2[0]) and torch.equal(a1[1], a2[1])
+    oth, oy0, _ = oracle.adjoint("mlp", yh, times.astype(np.float64), theta.astype(np.float64), g, scheme=FE)
+    e1 = np.abs(host(a1[0]) - oth).max() / np.abs(oth).max()
+    e2 = np.abs(host(a1[1]) - oy0).max() / np.abs(oy0).max()
+    assert e1 <= 1e-5 and e2 <= 1e-5, (e1, e2)
