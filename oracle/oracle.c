@@ -25,6 +25,7 @@
  * Everything is IEEE double, no fast-math.  Series are independent
  * (Section 2.1) and are distributed over a pthread pool, longest first.
  */
+#define _DEFAULT_SOURCE
 #include "oracle.h"
 
 #include <math.h>
@@ -86,6 +87,8 @@ int oracle_param_count(int kind, int n, int hidden)
     case ORACLE_VANDERPOL: return 1;
     case ORACLE_ROBERTSON: return 3;
     case ORACLE_MLP:       return hidden * n + hidden + hidden * hidden + hidden + n * hidden + n;
+    case ORACLE_CHABOCHE:  return n >= 3 ? 8 + 2 * (n - 2) : -1;
+    case ORACLE_NEURON:    return (n >= 4 && n % 4 == 0) ? 15 * (n / 4) + 1 : -1;
     default:               return -1;
     }
 }
@@ -113,11 +116,45 @@ static void mlp_forward(int n, int H, const double *th, const double *y,
     }
 }
 
+/* Chaboche viscoplasticity (Section 5.1.1), n_unit = n - 2 backstresses.
+ * State (sigma, K, X_1..X_nu); parameters
+ *   p = (E, n, eta, sigma0, K_inf, tau, C_1..C_nu, gamma_1..gamma_nu, edot_a, T).
+ * With s = sigma - sum X and a = (|s| - K - sigma0) / eta, the plastic rate is
+ * ep = <a>^n sign(s) (<> the Macaulay bracket), |ep| = <a>^n, and
+ *   dsigma/dt = E (edot(t) - ep),  dK/dt = tau (K_inf - K) |ep|,
+ *   dX_i/dt = 2/3 C_i ep - gamma_i X_i |ep|,  edot(t) = edot_a sin(2 pi t / T).
+ * The isotropic hardening grows with the plastic rate (the standard form; the
+ * printed dK/dt lacks the |ep| factor, under which the paper's parameter table
+ * never leaves the elastic range). */
+typedef struct {
+    double s, sg, a, pa, dpa, ep, edot;
+} chaboche_flow;
+
+static chaboche_flow chaboche_eval(int nu, const double *y, double t, const double *p)
+{
+    chaboche_flow c;
+    double sx = 0.0;
+    for (int i = 0; i < nu; ++i) sx += y[2 + i];
+    c.s = y[0] - sx;
+    c.sg = c.s > 0.0 ? 1.0 : (c.s < 0.0 ? -1.0 : 0.0);
+    c.a = (fabs(c.s) - y[1] - p[3]) / p[2];
+    c.pa = c.a > 0.0 ? pow(c.a, p[1]) : 0.0;                      /* <a>^n              */
+    c.dpa = c.a > 0.0 ? p[1] * pow(c.a, p[1] - 1.0) / p[2] : 0.0; /* d<a>^n / d|s|      */
+    c.ep = c.pa * c.sg;
+    c.edot = p[6 + 2 * nu] * sin(2.0 * M_PI * t / p[7 + 2 * nu]);
+    return c;
+}
+
+/* Coupled neurons (Section 5.1.1), n_unit = n / 4, state (V_i, m_i, h_i, n_i) per
+ * neuron; parameters per neuron (C, g_Na, E_Na, g_K, E_K, g_L, E_L, m_inf, tau_m,
+ * h_inf, tau_h, n_inf, tau_n, g_C, T), then the current amplitude I_a. */
+enum { NR_C, NR_GNA, NR_ENA, NR_GK, NR_EK, NR_GL, NR_EL, NR_MINF, NR_TM, NR_HINF, NR_TH, NR_NINF, NR_TN,
+       NR_GC, NR_T, NR_PER_UNIT };
+
 /* f = h(y,t;p); if J != NULL also J = dh/dy (row-major n x n). */
 static void rhs(int kind, int n, int H, const double *y, double t, const double *p,
                 double *f, double *J)
 {
-    (void)t;
     switch (kind) {
     case ORACLE_LINEAR:
         for (int i = 0; i < n; ++i) {
@@ -173,6 +210,61 @@ static void rhs(int kind, int n, int H, const double *y, double t, const double 
         }
         break;
     }
+    case ORACLE_CHABOCHE: {
+        const int nu = n - 2;
+        const double E = p[0], tau = p[5], Kinf = p[4];
+        const double *C = p + 6, *gam = p + 6 + nu;
+        const chaboche_flow c = chaboche_eval(nu, y, t, p);
+        f[0] = E * (c.edot - c.ep);
+        f[1] = tau * (Kinf - y[1]) * c.pa;
+        for (int i = 0; i < nu; ++i) f[2 + i] = 2.0 / 3.0 * C[i] * c.ep - gam[i] * y[2 + i] * c.pa;
+        if (J) {
+            /* d ep and d|ep| with respect to sigma, K and each X_j */
+            double dep[NMAX], dab[NMAX];
+            dep[0] = c.dpa * c.sg * c.sg; dab[0] = c.dpa * c.sg;
+            dep[1] = -c.dpa * c.sg;       dab[1] = -c.dpa;
+            for (int j = 0; j < nu; ++j) { dep[2 + j] = -c.dpa * c.sg * c.sg; dab[2 + j] = -c.dpa * c.sg; }
+            for (int k = 0; k < n; ++k) {
+                J[0 * n + k] = -E * dep[k];
+                J[1 * n + k] = tau * (Kinf - y[1]) * dab[k] - ((k == 1) ? tau * c.pa : 0.0);
+                for (int i = 0; i < nu; ++i)
+                    J[(2 + i) * n + k] = 2.0 / 3.0 * C[i] * dep[k] - gam[i] * y[2 + i] * dab[k]
+                                         - ((k == 2 + i) ? gam[i] * c.pa : 0.0);
+            }
+        }
+        break;
+    }
+    case ORACLE_NEURON: {
+        const int nu = n / 4;
+        const double Ia = p[NR_PER_UNIT * nu];
+        if (J) memset(J, 0, sizeof(double) * n * n);
+        for (int i = 0; i < nu; ++i) {
+            const double *q = p + NR_PER_UNIT * i;
+            const double V = y[4 * i], m = y[4 * i + 1], hh = y[4 * i + 2], nn = y[4 * i + 3];
+            double cpl = 0.0;
+            for (int j = 0; j < nu; ++j) cpl += V - y[4 * j];
+            const double I = Ia * sin(2.0 * M_PI * t / q[NR_T]);
+            const double m3 = m * m * m, n4 = nn * nn * nn * nn;
+            const double F = -q[NR_GNA] * m3 * hh * (V - q[NR_ENA]) - q[NR_GK] * n4 * (V - q[NR_EK])
+                             - q[NR_GL] * (V - q[NR_EL]) + I + q[NR_GC] * cpl;
+            f[4 * i] = F / q[NR_C];
+            f[4 * i + 1] = (q[NR_MINF] - m) / q[NR_TM];
+            f[4 * i + 2] = (q[NR_HINF] - hh) / q[NR_TH];
+            f[4 * i + 3] = (q[NR_NINF] - nn) / q[NR_TN];
+            if (J) {
+                double *r = J + 4 * i * n;
+                for (int j = 0; j < nu; ++j) r[4 * j] = (j == i) ? 0.0 : -q[NR_GC] / q[NR_C];
+                r[4 * i] = (-q[NR_GNA] * m3 * hh - q[NR_GK] * n4 - q[NR_GL] + q[NR_GC] * (nu - 1)) / q[NR_C];
+                r[4 * i + 1] = -3.0 * q[NR_GNA] * m * m * hh * (V - q[NR_ENA]) / q[NR_C];
+                r[4 * i + 2] = -q[NR_GNA] * m3 * (V - q[NR_ENA]) / q[NR_C];
+                r[4 * i + 3] = -4.0 * q[NR_GK] * nn * nn * nn * (V - q[NR_EK]) / q[NR_C];
+                J[(4 * i + 1) * n + 4 * i + 1] = -1.0 / q[NR_TM];
+                J[(4 * i + 2) * n + 4 * i + 2] = -1.0 / q[NR_TH];
+                J[(4 * i + 3) * n + 4 * i + 3] = -1.0 / q[NR_TN];
+            }
+        }
+        break;
+    }
     }
 }
 
@@ -180,6 +272,72 @@ static void rhs(int kind, int n, int H, const double *y, double t, const double 
 static void vjp_p(int kind, int n, int H, const double *y, double t, const double *p,
                   const double *w, double *gp)
 {
+    switch (kind) {
+    case ORACLE_CHABOCHE: {
+        const int nu = n - 2;
+        const double E = p[0], Kinf = p[4], tau = p[5], eda = p[6 + 2 * nu], T = p[7 + 2 * nu];
+        const double *C = p + 6, *gam = p + 6 + nu;
+        const chaboche_flow c = chaboche_eval(nu, y, t, p);
+        /* the weights carried by ep and by |ep| = <a>^n */
+        double g_ep = -E * w[0], g_pa = w[1] * tau * (Kinf - y[1]);
+        for (int i = 0; i < nu; ++i) {
+            g_ep += 2.0 / 3.0 * C[i] * w[2 + i];
+            g_pa -= gam[i] * y[2 + i] * w[2 + i];
+        }
+        const double g_a = g_ep * c.sg + g_pa; /* weight of <a>^n itself */
+        if (c.a > 0.0) {
+            gp[1] += g_a * c.pa * log(c.a);         /* d<a>^n / dn      */
+            gp[2] += g_a * (-p[1] * c.pa / p[2]);  /* d<a>^n / deta    */
+            gp[3] += g_a * (-c.dpa);               /* d<a>^n / dsigma0 */
+        }
+        gp[0] += w[0] * (c.edot - c.ep);
+        gp[4] += w[1] * tau * c.pa;
+        gp[5] += w[1] * (Kinf - y[1]) * c.pa;
+        for (int i = 0; i < nu; ++i) {
+            gp[6 + i] += w[2 + i] * 2.0 / 3.0 * c.ep;
+            gp[6 + nu + i] -= w[2 + i] * y[2 + i] * c.pa;
+        }
+        const double ph = 2.0 * M_PI * t / T;
+        gp[6 + 2 * nu] += w[0] * E * sin(ph);
+        gp[7 + 2 * nu] += w[0] * E * eda * cos(ph) * (-ph / T);
+        return;
+    }
+    case ORACLE_NEURON: {
+        const int nu = n / 4;
+        const double Ia = p[NR_PER_UNIT * nu];
+        for (int i = 0; i < nu; ++i) {
+            const double *q = p + NR_PER_UNIT * i;
+            double *g = gp + NR_PER_UNIT * i;
+            const double V = y[4 * i], m = y[4 * i + 1], hh = y[4 * i + 2], nn = y[4 * i + 3];
+            double cpl = 0.0;
+            for (int j = 0; j < nu; ++j) cpl += V - y[4 * j];
+            const double ph = 2.0 * M_PI * t / q[NR_T];
+            const double I = Ia * sin(ph);
+            const double m3 = m * m * m, n4 = nn * nn * nn * nn;
+            const double F = -q[NR_GNA] * m3 * hh * (V - q[NR_ENA]) - q[NR_GK] * n4 * (V - q[NR_EK])
+                             - q[NR_GL] * (V - q[NR_EL]) + I + q[NR_GC] * cpl;
+            const double wv = w[4 * i] / q[NR_C];
+            g[NR_C] -= wv * F / q[NR_C];
+            g[NR_GNA] -= wv * m3 * hh * (V - q[NR_ENA]);
+            g[NR_ENA] += wv * q[NR_GNA] * m3 * hh;
+            g[NR_GK] -= wv * n4 * (V - q[NR_EK]);
+            g[NR_EK] += wv * q[NR_GK] * n4;
+            g[NR_GL] -= wv * (V - q[NR_EL]);
+            g[NR_EL] += wv * q[NR_GL];
+            g[NR_GC] += wv * cpl;
+            g[NR_T] += wv * Ia * cos(ph) * (-ph / q[NR_T]);
+            gp[NR_PER_UNIT * nu] += wv * sin(ph);
+            g[NR_MINF] += w[4 * i + 1] / q[NR_TM];
+            g[NR_TM] -= w[4 * i + 1] * (q[NR_MINF] - m) / (q[NR_TM] * q[NR_TM]);
+            g[NR_HINF] += w[4 * i + 2] / q[NR_TH];
+            g[NR_TH] -= w[4 * i + 2] * (q[NR_HINF] - hh) / (q[NR_TH] * q[NR_TH]);
+            g[NR_NINF] += w[4 * i + 3] / q[NR_TN];
+            g[NR_TN] -= w[4 * i + 3] * (q[NR_NINF] - nn) / (q[NR_TN] * q[NR_TN]);
+        }
+        return;
+    }
+    default: break;
+    }
     (void)t;
     switch (kind) {
     case ORACLE_LINEAR: /* h_i = sum_k A_ik y_k  ->  dL/dA_ik = w_i y_k */
@@ -500,6 +658,8 @@ static int validate(int kind, int n, int hidden, int64_t B, int64_t N, const int
     if (oracle_param_count(kind, n, hidden) < 0) return -1;
     if (kind == ORACLE_VANDERPOL && n != 2) return -1;
     if (kind == ORACLE_ROBERTSON && n != 3) return -1;
+    if (kind == ORACLE_CHABOCHE && n < 3) return -1;
+    if (kind == ORACLE_NEURON && (n < 4 || n % 4)) return -1;
     if (kind == ORACLE_MLP && (hidden < 1 || hidden > HMAX)) return -1;
     if (!offsets && N < 0) return -1;
     if (offsets)

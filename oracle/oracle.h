@@ -24,6 +24,12 @@
  *   ORACLE_ROBERTSON  n = 3, rate constants 0.04 s1, 3e7 s2, 1e4 s3, p = (s1, s2, s3)
  *   ORACLE_MLP        h = W3 tanh(W2 tanh(W1 y + b1) + b2) + b3 with hidden width H,
  *                     p = W1[H][n], b1[H], W2[H][H], b2[H], W3[n][H], b3[n]
+ *   ORACLE_CHABOCHE   Chaboche viscoplasticity with nu = n - 2 backstresses, state
+ *                     (sigma, K, X_1..X_nu), p = (E, n, eta, sigma0, K_inf, tau,
+ *                     C_1..C_nu, gamma_1..gamma_nu, edot_a, T) (Section 5.1.1)
+ *   ORACLE_NEURON     nu = n / 4 coupled neurons, state (V, m, h, n) per neuron,
+ *                     p = 15 per neuron (C, g_Na, E_Na, g_K, E_K, g_L, E_L, m_inf,
+ *                     tau_m, h_inf, tau_h, n_inf, tau_n, g_C, T), then I_a (Section 5.1.1)
  */
 #ifndef TVI_ORACLE_H
 #define TVI_ORACLE_H
@@ -34,7 +40,8 @@
 extern "C" {
 #endif
 
-enum { ORACLE_LINEAR = 0, ORACLE_VANDERPOL = 1, ORACLE_ROBERTSON = 2, ORACLE_MLP = 3 };
+enum { ORACLE_LINEAR = 0, ORACLE_VANDERPOL = 1, ORACLE_ROBERTSON = 2, ORACLE_MLP = 3, ORACLE_CHABOCHE = 4,
+       ORACLE_NEURON = 5 };
 enum { ORACLE_OK = 0, ORACLE_NOT_CONVERGED = 1, ORACLE_SINGULAR = 2, ORACLE_NONFINITE = 3 };
 
 int oracle_param_count(int kind, int n, int hidden);

@@ -18,6 +18,12 @@ is benchmarked and tested on:
                  [0.5, 2], series lengths log-uniform in [100, 20000] on
                  log-spaced grids over [1e-5, 1e4], y0 = (1, 0, 0)
 
+and two of the paper's own example problems with its parameter tables
+(Section 5.1.1; deterministic, no draws):
+
+* ``chaboche``   Chaboche viscoplasticity, n = 2 + n_unit backstresses
+* ``neuron``     coupled neurons, n = 4 n_unit
+
 Every generator returns a dict of contiguous numpy arrays in the library's
 series-major layouts (see ``include/tvi.h``).
 """
@@ -98,3 +104,36 @@ def robertson(B=2000, seed=104, n_range=(100, 20000), t_range=(1e-5, 1e4), s_ran
 def observed_steps(N, every=100):
     """Observed step indices of the sampled mean-squared loss: k = every, 2 every, ..., N."""
     return np.arange(every, N + 1, every, dtype=np.int64)
+
+
+def chaboche(n_unit=1, n_batch=3, n_time=2000, t_max=10.0):
+    """The Chaboche timing case: E = 10, n = 5, eta = 2, sigma0 = 1, K_inf = 10,
+    tau = 1, C_i = linspace(0.1, 1, n_unit), gamma_i = linspace(0.1, 0.5, n_unit),
+    edot_a = linspace(0.1, 1, n_batch) (one value per series), T = 1, t in
+    [0, t_max] in n_time equal steps, zero initial state.  Parameter vector per
+    series: (E, n, eta, sigma0, K_inf, tau, C_1..C_nu, gamma_1..gamma_nu, edot_a, T)."""
+    nu = n_unit
+    base = np.concatenate([[10.0, 5.0, 2.0, 1.0, 10.0, 1.0], np.linspace(0.1, 1.0, nu), np.linspace(0.1, 0.5, nu)])
+    params = np.array([np.concatenate([base, [ea, 1.0]]) for ea in np.linspace(0.1, 1.0, n_batch)])
+    n = 2 + nu
+    return dict(kind="chaboche", n=n, y0=np.zeros((n_batch, n)), times=np.linspace(0.0, t_max, n_time + 1),
+                params=params, offsets=None)
+
+
+NEURON_TABLE = (  # per neuron: (lo, hi) of linspace over the neurons, in the parameter order
+    ("C", 0.1, 1.0), ("g_Na", 0.1, 1.0), ("E_Na", 0.1, 1.0), ("g_K", 0.1, 1.0), ("E_K", 0.1, 1.0),
+    ("g_L", 0.1, 1.0), ("E_L", 0.1, 1.0), ("m_inf", 0.1, 1.0), ("tau_m", 0.5, 5.0), ("h_inf", 0.1, 1.0),
+    ("tau_h", 1.5, 15.0), ("n_inf", 0.1, 1.0), ("tau_n", 1.0, 10.0), ("g_C", 1e-3, 1e-2), ("T", 0.5, 2.0))
+
+
+def neuron(n_unit=1, n_batch=3, n_time=2000, t_max=10.0):
+    """The coupled-neuron timing case: each per-neuron parameter is
+    linspace(lo, hi, n_unit) over the neurons (NEURON_TABLE), the current
+    amplitude I_a = linspace(0.1, 1, n_batch) (one value per series), t in
+    [0, t_max] in n_time equal steps, zero initial state.  Parameter vector per
+    series: the 15 per-neuron values of neuron 1, ..., of neuron n_unit, then I_a."""
+    per = np.stack([np.linspace(lo, hi, n_unit) for _, lo, hi in NEURON_TABLE], axis=1)  # [n_unit][15]
+    params = np.array([np.concatenate([per.reshape(-1), [ia]]) for ia in np.linspace(0.1, 1.0, n_batch)])
+    n = 4 * n_unit
+    return dict(kind="neuron", n=n, y0=np.zeros((n_batch, n)), times=np.linspace(0.0, t_max, n_time + 1),
+                params=params, offsets=None)

@@ -7,6 +7,7 @@ import pytest
 
 import oracle
 from tests import test_oracle_forward_euler as fe
+from tests import test_oracle_paper_models as pm
 from tests import test_oracle_pins as pins
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
@@ -46,6 +47,17 @@ MUTATIONS = [
     ("fe_adjoint_param_term_at_new_state", "vjp_p(kind, n, H, Y + (k - 1) * n, t[k - 1], p, w, gp);",
      "vjp_p(kind, n, H, Y + k * n, t[k - 1], p, w, gp);",
      [fe.test_fe_adjoint_linear_closed_form, fe.test_fe_adjoint_fd_vanderpol]),
+    ("chaboche_hardening_without_plastic_rate", "f[1] = tau * (Kinf - y[1]) * c.pa;",
+     "f[1] = tau * (Kinf - y[1]);",
+     [lambda: pm.test_rate_jacobian_and_parameter_gradient_match_autograd(pm._cases()[3])]),
+    ("chaboche_jacobian_sign", "dep[1] = -c.dpa * c.sg;", "dep[1] = c.dpa * c.sg;",
+     [lambda: pm.test_rate_jacobian_and_parameter_gradient_match_autograd(pm._cases()[0])]),
+    ("neuron_vjp_sign", "g[NR_TM] -= w[4 * i + 1] * (q[NR_MINF] - m) / (q[NR_TM] * q[NR_TM]);",
+     "g[NR_TM] += w[4 * i + 1] * (q[NR_MINF] - m) / (q[NR_TM] * q[NR_TM]);",
+     [lambda: pm.test_rate_jacobian_and_parameter_gradient_match_autograd(pm._cases()[9])]),
+    ("neuron_coupling_jacobian", "r[4 * j] = (j == i) ? 0.0 : -q[NR_GC] / q[NR_C];",
+     "r[4 * j] = (j == i) ? 0.0 : q[NR_GC] / q[NR_C];",
+     [lambda: pm.test_rate_jacobian_and_parameter_gradient_match_autograd(pm._cases()[10])]),
 ]
 
 
