@@ -57,6 +57,20 @@
  *                  h = W3 tanh(W2 tanh(W1 y + b1) + b2) + b3, one shared
  *                  p = (W1[64][8], b1[64], W2[64][64], b2[64], W3[8][64], b3[8]) (P = 5256);
  *                  computed in float on MFMA (bf16x3 products for h)
+ *   TVI_CHABOCHE   Chaboche viscoplasticity (Section 5.1.1), n = 2 + nu with nu = 1 or 2
+ *                  backstresses: state (sigma, K, X_1..X_nu), s = sigma - sum X,
+ *                  a = (|s| - K - sigma0)/eta, ep = <a>^n sign(s),
+ *                  h = (E (edot(t) - ep), tau (K_inf - K) |ep|, 2/3 C_i ep - gamma_i X_i |ep|),
+ *                  edot(t) = edot_a sin(2 pi t / T),
+ *                  p = (E, n, eta, sigma0, K_inf, tau, C_1..C_nu, gamma_1..gamma_nu, edot_a, T)
+ *                  (P = 8 + 2 nu); the hardening rate carries |ep| (the model's standard form);
+ *                  TVI_F64 only
+ *   TVI_NEURON     one neuron of the coupled-neuron model (Section 5.1.1), n = 4, state
+ *                  (V, m, h, n): dV/dt = (-g_Na m^3 h (V - E_Na) - g_K n^4 (V - E_K)
+ *                  - g_L (V - E_L) + I_a sin(2 pi t / T)) / C, dx/dt = (x_inf - x)/tau_x,
+ *                  p = (C, g_Na, E_Na, g_K, E_K, g_L, E_L, m_inf, tau_m, h_inf, tau_h, n_inf,
+ *                  tau_n, g_C, T, I_a) (P = 16; g_C couples neurons and has no effect on one);
+ *                  TVI_F64 only
  */
 #ifndef TVI_H
 #define TVI_H
@@ -72,7 +86,9 @@ typedef enum {
     TVI_LINEAR = 0,
     TVI_VANDERPOL = 1,
     TVI_ROBERTSON = 2,
-    TVI_MLP = 3
+    TVI_MLP = 3,
+    TVI_CHABOCHE = 4,
+    TVI_NEURON = 5
 } tvi_model_kind;
 
 typedef enum { TVI_F32 = 0, TVI_F64 = 1 } tvi_dtype;

@@ -35,6 +35,8 @@ int model_params(const tvi_model *m)
     case TVI_LINEAR: return m->n * m->n;
     case TVI_VANDERPOL: return 1;
     case TVI_ROBERTSON: return 3;
+    case TVI_CHABOCHE: return 8 + 2 * (m->n - 2);
+    case TVI_NEURON: return 15 * (m->n / 4) + 1;
     case TVI_MLP: {
         const int n = m->n, H = m->hidden;
         return H * n + H + H * H + H + n * H + n;
@@ -51,6 +53,12 @@ tvi_status check_model(const tvi_model *m)
     case TVI_LINEAR: return (m->n >= 2 && m->n <= 4) ? TVI_OK : TVI_EUNSUPPORTED;
     case TVI_VANDERPOL: return m->n == 2 ? TVI_OK : TVI_EINVAL;
     case TVI_ROBERTSON: return m->n == 3 ? TVI_OK : TVI_EINVAL;
+    case TVI_CHABOCHE:  // 1 or 2 backstresses in the register-resident solver
+        if (m->n < 3) return TVI_EINVAL;
+        return m->n <= 4 ? TVI_OK : TVI_EUNSUPPORTED;
+    case TVI_NEURON:    // one neuron
+        if (m->n < 4 || m->n % 4) return TVI_EINVAL;
+        return m->n == 4 ? TVI_OK : TVI_EUNSUPPORTED;
     case TVI_MLP:
         if (m->n != 8) return TVI_EINVAL;
         return m->hidden == 64 ? TVI_OK : TVI_EUNSUPPORTED;
@@ -121,6 +129,10 @@ tvi_status dispatch(int pass, const tvi_model *model, const void *args, int S, i
     switch (model->kind) {
     case TVI_VANDERPOL: return launch_vanderpol(pass, model->dtype, args, S, T, stream);
     case TVI_ROBERTSON: return launch_robertson(pass, model->dtype, args, S, T, stream);
+    case TVI_CHABOCHE:
+        return model->n == 3 ? launch_chaboche3(pass, model->dtype, args, S, T, stream)
+                             : launch_chaboche4(pass, model->dtype, args, S, T, stream);
+    case TVI_NEURON: return launch_neuron4(pass, model->dtype, args, S, T, stream);
     case TVI_MLP: return launch_mlp(pass, model->dtype, args, stream);
     case TVI_LINEAR:
         switch (model->n) {

@@ -100,6 +100,9 @@ tvi_status launch_robertson(int pass, int dtype, const void *args, int S, int T,
 tvi_status launch_linear2(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
 tvi_status launch_linear3(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
 tvi_status launch_linear4(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
+tvi_status launch_chaboche3(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
+tvi_status launch_chaboche4(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
+tvi_status launch_neuron4(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
 tvi_status launch_pcr(int dtype, int n, int64_t B, int m, const void *D, const void *r, void *x, int transpose,
                       int S, int T, hipStream_t stream);
 tvi_status launch_mlp(int pass, int dtype, const void *args, hipStream_t stream);

@@ -59,6 +59,13 @@ tvi_status launch_eval(int kind, int n, int dtype, int64_t M, const void *states
     switch (kind) {
     case TVI_VANDERPOL: return eval_dtype<VanDerPol>(dtype, M, states, times, params, shared, f, J, stream);
     case TVI_ROBERTSON: return eval_dtype<Robertson>(dtype, M, states, times, params, shared, f, J, stream);
+    case TVI_CHABOCHE:
+        switch (n) {
+        case 3: return eval_dtype<Chaboche<1>>(dtype, M, states, times, params, shared, f, J, stream);
+        case 4: return eval_dtype<Chaboche<2>>(dtype, M, states, times, params, shared, f, J, stream);
+        default: return TVI_EUNSUPPORTED;
+        }
+    case TVI_NEURON: return eval_dtype<Neuron1>(dtype, M, states, times, params, shared, f, J, stream);
     case TVI_LINEAR:
         switch (n) {
         case 2: return eval_dtype<Linear<2>>(dtype, M, states, times, params, shared, f, J, stream);

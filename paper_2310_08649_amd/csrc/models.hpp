@@ -119,4 +119,187 @@ struct Robertson {
     }
 };
 
+// Chaboche viscoplasticity (Section 5.1.1) with NU backstresses: state
+// (sigma, K, X_1..X_NU), p = (E, n, eta, sigma0, K_inf, tau, C_1..C_NU,
+// gamma_1..gamma_NU, edot_a, T).  With s = sigma - sum X and
+// a = (|s| - K - sigma0) / eta the plastic rate is ep = <a>^n sign(s):
+//   dsigma/dt = E (edot(t) - ep),  dK/dt = tau (K_inf - K) |ep|,
+//   dX_i/dt = 2/3 C_i ep - gamma_i X_i |ep|,  edot(t) = edot_a sin(2 pi t / T)
+// (isotropic hardening driven by the plastic rate, the model's standard form).
+template <int NU>
+struct Chaboche {
+    static constexpr int N = 2 + NU;
+    static constexpr int P = 8 + 2 * NU;
+    double E, ex, eta, s0, Kinf, tau, C[NU], gam[NU], eda, T;
+
+    template <class IO>
+    __device__ __forceinline__ void load(const IO *p)
+    {
+        E = ld(p);
+        ex = ld(p + 1);
+        eta = ld(p + 2);
+        s0 = ld(p + 3);
+        Kinf = ld(p + 4);
+        tau = ld(p + 5);
+#pragma unroll
+        for (int i = 0; i < NU; ++i) {
+            C[i] = ld(p + 6 + i);
+            gam[i] = ld(p + 6 + NU + i);
+        }
+        eda = ld(p + 6 + 2 * NU);
+        T = ld(p + 7 + 2 * NU);
+    }
+    // sign of s, the overstress a, <a>^n, d<a>^n/d|s| and the imposed strain rate
+    struct Flow {
+        double sg, a, pa, dpa, edot;
+    };
+    __device__ __forceinline__ Flow flow(const double (&y)[N], double t) const
+    {
+        Flow c;
+        double sx = 0.0;
+#pragma unroll
+        for (int i = 0; i < NU; ++i) sx += y[2 + i];
+        const double s = y[0] - sx;
+        c.sg = s > 0.0 ? 1.0 : (s < 0.0 ? -1.0 : 0.0);
+        c.a = (fabs(s) - y[1] - s0) / eta;
+        const double pm1 = c.a > 0.0 ? pow(c.a, ex - 1.0) : 0.0;
+        c.pa = pm1 * c.a;
+        c.dpa = ex * pm1 / eta;
+        c.edot = eda * sin(2.0 * M_PI * t / T);
+        return c;
+    }
+    __device__ __forceinline__ void rhs(const double (&y)[N], double t, double (&f)[N]) const
+    {
+        const Flow c = flow(y, t);
+        const double ep = c.pa * c.sg;
+        f[0] = E * (c.edot - ep);
+        f[1] = tau * (Kinf - y[1]) * c.pa;
+#pragma unroll
+        for (int i = 0; i < NU; ++i) f[2 + i] = 2.0 / 3.0 * C[i] * ep - gam[i] * y[2 + i] * c.pa;
+    }
+    __device__ __forceinline__ void jac(const double (&y)[N], double t, double (&J)[N][N]) const
+    {
+        const Flow c = flow(y, t);
+        // derivatives of ep and of |ep| with respect to sigma, K and X_j
+        double dep[N], dab[N];
+        dep[0] = c.dpa * c.sg * c.sg;
+        dab[0] = c.dpa * c.sg;
+        dep[1] = -c.dpa * c.sg;
+        dab[1] = -c.dpa;
+#pragma unroll
+        for (int j = 0; j < NU; ++j) {
+            dep[2 + j] = -c.dpa * c.sg * c.sg;
+            dab[2 + j] = -c.dpa * c.sg;
+        }
+        const double hk = tau * (Kinf - y[1]);
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            J[0][k] = -E * dep[k];
+            J[1][k] = hk * dab[k] - ((k == 1) ? tau * c.pa : 0.0);
+#pragma unroll
+            for (int i = 0; i < NU; ++i)
+                J[2 + i][k] = 2.0 / 3.0 * C[i] * dep[k] - gam[i] * y[2 + i] * dab[k] - ((k == 2 + i) ? gam[i] * c.pa : 0.0);
+        }
+    }
+    __device__ __forceinline__ void vjp_p(const double (&y)[N], double t, const double (&w)[N], double (&gp)[P]) const
+    {
+        const Flow c = flow(y, t);
+        const double ep = c.pa * c.sg;
+        // the weights carried by ep and by |ep| = <a>^n
+        double g_ep = -E * w[0], g_pa = w[1] * tau * (Kinf - y[1]);
+#pragma unroll
+        for (int i = 0; i < NU; ++i) {
+            g_ep += 2.0 / 3.0 * C[i] * w[2 + i];
+            g_pa -= gam[i] * y[2 + i] * w[2 + i];
+        }
+        const double g_a = g_ep * c.sg + g_pa;
+        if (c.a > 0.0) {
+            gp[1] += g_a * c.pa * log(c.a);
+            gp[2] += g_a * (-ex * c.pa / eta);
+            gp[3] += g_a * (-c.dpa);
+        }
+        gp[0] += w[0] * (c.edot - ep);
+        gp[4] += w[1] * tau * c.pa;
+        gp[5] += w[1] * (Kinf - y[1]) * c.pa;
+#pragma unroll
+        for (int i = 0; i < NU; ++i) {
+            gp[6 + i] += w[2 + i] * (2.0 / 3.0) * ep;
+            gp[6 + NU + i] -= w[2 + i] * y[2 + i] * c.pa;
+        }
+        const double ph = 2.0 * M_PI * t / T;
+        gp[6 + 2 * NU] += w[0] * E * sin(ph);
+        gp[7 + 2 * NU] += w[0] * E * eda * cos(ph) * (-ph / T);
+    }
+};
+
+// One neuron of the coupled-neuron model (Section 5.1.1): state (V, m, h, n),
+// p = (C, g_Na, E_Na, g_K, E_K, g_L, E_L, m_inf, tau_m, h_inf, tau_h, n_inf,
+// tau_n, g_C, T, I_a):
+//   dV/dt = (-g_Na m^3 h (V - E_Na) - g_K n^4 (V - E_K) - g_L (V - E_L) + I(t)) / C,
+//   dx/dt = (x_inf - x) / tau_x for x = m, h, n,  I(t) = I_a sin(2 pi t / T)
+// (the coupling sum over the other neurons is empty for one neuron).
+struct Neuron1 {
+    static constexpr int N = 4;
+    static constexpr int P = 16;
+    double q[P];
+
+    template <class IO>
+    __device__ __forceinline__ void load(const IO *p)
+    {
+#pragma unroll
+        for (int k = 0; k < P; ++k) q[k] = ld(p + k);
+    }
+    enum { C, GNA, ENA, GK, EK, GL, EL, MINF, TM, HINF, TH, NINF, TN, GC, TP, IA };
+    __device__ __forceinline__ double current(const double (&y)[4], double t) const
+    {
+        const double m3 = y[1] * y[1] * y[1], n4 = y[3] * y[3] * y[3] * y[3];
+        return -q[GNA] * m3 * y[2] * (y[0] - q[ENA]) - q[GK] * n4 * (y[0] - q[EK]) - q[GL] * (y[0] - q[EL]) +
+               q[IA] * sin(2.0 * M_PI * t / q[TP]);
+    }
+    __device__ __forceinline__ void rhs(const double (&y)[4], double t, double (&f)[4]) const
+    {
+        f[0] = current(y, t) / q[C];
+        f[1] = (q[MINF] - y[1]) / q[TM];
+        f[2] = (q[HINF] - y[2]) / q[TH];
+        f[3] = (q[NINF] - y[3]) / q[TN];
+    }
+    __device__ __forceinline__ void jac(const double (&y)[4], double, double (&J)[4][4]) const
+    {
+        const double m = y[1], h = y[2], n = y[3], V = y[0];
+        J[0][0] = (-q[GNA] * m * m * m * h - q[GK] * n * n * n * n - q[GL]) / q[C];
+        J[0][1] = -3.0 * q[GNA] * m * m * h * (V - q[ENA]) / q[C];
+        J[0][2] = -q[GNA] * m * m * m * (V - q[ENA]) / q[C];
+        J[0][3] = -4.0 * q[GK] * n * n * n * (V - q[EK]) / q[C];
+#pragma unroll
+        for (int r = 1; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) J[r][c] = 0.0;
+        J[1][1] = -1.0 / q[TM];
+        J[2][2] = -1.0 / q[TH];
+        J[3][3] = -1.0 / q[TN];
+    }
+    __device__ __forceinline__ void vjp_p(const double (&y)[4], double t, const double (&w)[4], double (&gp)[P]) const
+    {
+        const double m = y[1], h = y[2], n = y[3], V = y[0];
+        const double m3 = m * m * m, n4 = n * n * n * n;
+        const double ph = 2.0 * M_PI * t / q[TP];
+        const double wv = w[0] / q[C];
+        gp[C] -= wv * current(y, t) / q[C];
+        gp[GNA] -= wv * m3 * h * (V - q[ENA]);
+        gp[ENA] += wv * q[GNA] * m3 * h;
+        gp[GK] -= wv * n4 * (V - q[EK]);
+        gp[EK] += wv * q[GK] * n4;
+        gp[GL] -= wv * (V - q[EL]);
+        gp[EL] += wv * q[GL];
+        gp[TP] += wv * q[IA] * cos(ph) * (-ph / q[TP]);
+        gp[IA] += wv * sin(ph);
+        gp[MINF] += w[1] / q[TM];
+        gp[TM] -= w[1] * (q[MINF] - m) / (q[TM] * q[TM]);
+        gp[HINF] += w[2] / q[TH];
+        gp[TH] -= w[2] * (q[HINF] - h) / (q[TH] * q[TH]);
+        gp[NINF] += w[3] / q[TN];
+        gp[TN] -= w[3] * (q[NINF] - n) / (q[TN] * q[TN]);
+    }
+};
+
 } // namespace tvi

@@ -25,7 +25,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtvi.so")
 
-KINDS = {"linear": 0, "vanderpol": 1, "robertson": 2, "mlp": 3}
+KINDS = {"linear": 0, "vanderpol": 1, "robertson": 2, "mlp": 3, "chaboche": 4, "neuron": 5}
 F32, F64 = 0, 1
 INIT = {"zero": 0, "extrap": 1, "predictor": 2}
 SCHEMES = {"backward_euler": 0, "forward_euler": 1}

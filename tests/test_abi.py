@@ -171,3 +171,22 @@ def test_scheme_option_is_checked(lib):
     mm = tvi.Model(tvi.KINDS["mlp"], 8, tvi.F32, 1, 64)
     o = tvi.make_options(chunk=16, init="predictor", predictor=(P(), 128, 16, 0), scheme="forward_euler")
     assert lib.tvi_solve_forward(ctypes.byref(mm), ctypes.byref(o), 4, 10, None, f, f, f, f, None, f, None, None) == -4
+
+
+def test_paper_example_models_sizes(lib):
+    """Chaboche with 1 or 2 backstresses and one neuron run in the register-resident
+    solver; other sizes are refused before any launch, as is float storage."""
+    from paper_2310_08649_amd import tvi
+    assert tvi.param_count("chaboche", 3) == 10 and tvi.param_count("chaboche", 4) == 12
+    assert tvi.param_count("neuron", 4) == 16
+    o = tvi.make_options(chunk=16)
+    f = _fake()
+
+    def fwd(kind, n, dtype=tvi.F64):
+        m = tvi.Model(tvi.KINDS[kind], n, dtype, 0, 64)
+        return lib.tvi_solve_forward(ctypes.byref(m), ctypes.byref(o), 4, 10, None, f, f, f, f, None, f, None, None)
+
+    assert fwd("chaboche", 2) == -1
+    assert fwd("chaboche", 5) == -4
+    assert fwd("neuron", 6) == -1
+    assert fwd("neuron", 8) == -4

@@ -1,0 +1,92 @@
+"""The paper's Chaboche and coupled-neuron example problems (Section 5.1.1,
+its parameter tables) on the GPU against the oracle: model rates and
+Jacobians, forward trajectories and adjoint gradients for backward and
+forward Euler over the paper's chunk sizes, through the C ABI.  FP64 gate:
+1e-10 relative per series."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2310_08649_amd import workloads as W
+from tests.helpers import PARITY_TOL, series_rel_err
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def tvi():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2310_08649_amd import tvi as t
+    t.load()
+    return t
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def grad_err(a, b):
+    return (np.abs(a - b).max(axis=1) / np.maximum(np.abs(b).max(axis=1), 1e-300)).max()
+
+
+CASES = [("chaboche", 1), ("chaboche", 2), ("neuron", 1)]
+
+
+@pytest.mark.parametrize("kind,nu", CASES)
+def test_rate_and_jacobian_match_oracle(tvi, kind, nu):
+    rng = np.random.default_rng(8)
+    w = getattr(W, kind)(nu, 50)
+    M = 300
+    p = w["params"][rng.integers(0, 50, size=M)]
+    n = w["n"]
+    if kind == "chaboche":  # elastic and plastic states, both signs of the overstress
+        y = np.concatenate([rng.uniform(-4, 4, (M, 1)), rng.uniform(0, 1.5, (M, 1)),
+                            0.2 * rng.standard_normal((M, nu))], axis=1)
+    else:
+        y = rng.uniform(0.0, 1.0, (M, n))
+    t = rng.uniform(0.0, 10.0, M)
+    f, J = tvi.model_eval(kind, dev(y), dev(p), times=dev(t))
+    f, J = host(f), host(J)
+    for q in range(M):
+        fo, Jo = oracle.rhs(kind, y[q], t[q], p[q])
+        np.testing.assert_allclose(f[q], fo, rtol=1e-12, atol=1e-13 * max(1.0, np.abs(fo).max()))
+        np.testing.assert_allclose(J[q], Jo, rtol=1e-12, atol=1e-13 * max(1.0, np.abs(Jo).max()))
+
+
+@pytest.mark.parametrize("kind,nu", CASES)
+@pytest.mark.parametrize("scheme", ["backward_euler", "forward_euler"])
+def test_paper_grid_forward_and_adjoint(tvi, kind, nu, scheme):
+    """n_time = 2000 and n_batch = 10 as in the paper's study, its chunk sizes
+    (1000 exceeds the longest chunk here: 512), trajectories and gradients of
+    its Frobenius loss, stored and recomputed states."""
+    w = getattr(W, kind)(nu, 10)
+    yo, so, _ = oracle.forward(kind, w["y0"], w["times"], w["params"], tol=PARITY_TOL, scheme=scheme)
+    assert (so == 0).all()
+    g = yo / np.sqrt(np.sum(yo ** 2))
+    op, oy0, _ = oracle.adjoint(kind, yo, w["times"], w["params"], g, scheme=scheme)
+    for C in (1, 3, 10, 30, 100, 300, 512):
+        kw = dict(chunk=C, tol=PARITY_TOL, scheme=scheme)
+        y, st, _, ck = tvi.solve_forward(kind, dev(w["y0"]), dev(w["times"]), dev(w["params"]), checkpoints=True,
+                                         **kw)
+        assert (host(st) == 0).all(), C
+        assert series_rel_err(host(y), yo).max() <= 1e-10, C
+        a1 = tvi.solve_adjoint(kind, dev(w["times"]), dev(w["params"]), dev(g), y=y, **kw)
+        a2 = tvi.solve_adjoint(kind, dev(w["times"]), dev(w["params"]), dev(g), ckpt=ck, **kw)
+        assert (host(a1[2]) == 0).all() and (host(a2[2]) == 0).all()
+        assert torch.equal(a1[0], a2[0]) and torch.equal(a1[1], a2[1]), C
+        assert grad_err(host(a1[0]), op) <= 1e-10, (C, grad_err(host(a1[0]), op))
+        # dL/dy0 is the zero initial state's sensitivity; compare normwise over the batch
+        assert np.abs(host(a1[1]) - oy0).max() <= 1e-10 * np.abs(oy0).max(), C
+
+
+def test_float_storage_is_refused(tvi):
+    w = W.chaboche(1, 3)
+    f = lambda a: dev(a, torch.float32)
+    with pytest.raises(tvi.TviError):
+        tvi.solve_forward("chaboche", f(w["y0"]), f(w["times"]), f(w["params"]), chunk=10)
