@@ -358,6 +358,50 @@ def run_forward_euler(ctx, steps):
     return res
 
 
+def run_paper_grid(ctx, steps):
+    """The paper's chunk-efficiency study (Section 5.3, its parameter table) on
+    its Chaboche (1 and 2 backstresses) and coupled-neuron (one neuron) example
+    problems, FP64: n_time = 2000, n_batch in {3, 10, 30, 50}, chunks
+    {1, 3, 10, 30, 100, 300, 512} (512 is the longest chunk here; the paper's
+    grid ends at 1000), forward + adjoint of the Frobenius loss of the whole
+    trajectory as one captured graph (states read from the stored trajectory).
+    Each chunk runs with PCR across lanes (T = 1 up to 64 steps) and with the
+    PCR->Thomas hybrid at T = 8; the speed-up is chunk 1 against the best."""
+    import torch
+    from paper_2310_08649_amd import graph, workloads
+    dev = ctx["dev"]
+    out = {"unit": "ms per forward+adjoint", "paper_best_speedup": {"chaboche": 190, "neuron": 94}}
+    best_by_model = {}
+    for kind, nu in (("chaboche", 1), ("chaboche", 2), ("neuron", 1)):
+        for nb in (3, 10, 30, 50):
+            w = getattr(workloads, kind)(nu, nb)
+            d = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev)
+            row = {}
+            for C in (1, 3, 10, 30, 100, 300, 512):
+                tilings = [(1, 1)] if C == 1 else [(0, 0)] + ([(-(-C // 8), 8)] if C >= 32 else [])
+                for S, T in tilings:
+                    if S > 64:
+                        continue
+                    S2 = S if S in (0, 1) else max(4, 1 << (S - 1).bit_length())
+                    cs = graph.CapturedStep(kind, d(w["y0"]), d(w["times"]), d(w["params"]), chunk=C, lanes=S2,
+                                            steps_per_lane=T, tol=TIMING_TOL, loss="frobenius",
+                                            recompute=False).capture()
+                    cs.replay()
+                    st = stats(time_launches(cs.replay, 3, torch.cuda.current_stream()))
+                    failed = int(((cs.status_fwd != 0) | (cs.status_adj != 0)).sum().item())
+                    key = "C%d" % C + ("" if T in (0, 1) else "_T%d" % T)
+                    row[key] = {"ms": st["median_ms"], "failed": failed}
+                    del cs
+            ok = {k: v["ms"] for k, v in row.items() if v["failed"] == 0}
+            bk = min(ok, key=ok.get)
+            sp = row["C1"]["ms"] / ok[bk]
+            row["best"] = {"config": bk, "ms": ok[bk], "speedup_over_chunk1": sp}
+            out["%s_nu%d_B%d" % (kind, nu, nb)] = row
+            best_by_model[kind] = max(best_by_model.get(kind, 0.0), sp)
+    out["best_speedup"] = best_by_model
+    return out
+
+
 def run_robertson(ctx, steps):
     """2000 ragged Robertson series (100..20000 log-spaced steps), FP64,
     forward + adjoint (Frobenius loss) as one captured graph, with the
@@ -629,7 +673,7 @@ def main():
         runs = [("chunk1", run_chunk1), ("fp32", run_vdp_fp32), ("fwd_adjoint", run_vdp_fwd_adjoint),
                 ("linear", run_linear), ("tiling_study", run_tiling_study), ("pcr_roofline", run_pcr),
                 ("mlp", run_mlp), ("robertson", run_robertson), ("predictor", run_predictor),
-                ("forward_euler", run_forward_euler)]
+                ("forward_euler", run_forward_euler), ("paper_grid", run_paper_grid)]
         only = set(filter(None, args.only.split(",")))
         for name, fn in runs:
             if not only or name in only:
