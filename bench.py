@@ -133,6 +133,27 @@ def run_chunk1(ctx, steps):
             "note": "same library, chunk 1: one lane per series, one Newton solve per step"}
 
 
+def run_jacobian_reuse(ctx, steps):
+    """The headline workload with chord steps allowed (jacobian_reuse: a correction
+    reuses the previous factorization while the residual keeps falling by that
+    factor), tuned over chunk, start and factor, against the full-Newton headline."""
+    from paper_2310_08649_amd import autotune
+    tuned = autotune.tune_forward("vanderpol", ctx["y0"], ctx["times"], ctx["mu"], tol=TIMING_TOL,
+                                  chunks=(32, 50, 64, 100), inits=("zero", "extrap"), reuses=(0.1, 0.2, 0.3),
+                                  reps=5, y_out=ctx["y_out"], use_cache=False)
+    b = tuned["best"]
+    fast = min((r for r in tuned["table"] if r["failed"] <= ctx["failed"]), key=lambda r: r["ms"], default=None)
+    out = {"fewest_failed": b, "fewest_failed_value": ctx["B"] * ctx["N"] / (b["ms"] * 1e-3),
+           "unit": "series*steps/s", "full_newton_ms": ctx["ms_per_step"], "full_newton_failed": ctx["failed"],
+           "note": "not the headline: chord steps do less arithmetic per correction than the paper's Newton "
+                   "iteration that the roofline counts"}
+    if fast is not None:
+        out["fastest_no_more_failures"] = fast
+        out["fastest_value"] = ctx["B"] * ctx["N"] / (fast["ms"] * 1e-3)
+        out["speedup_over_full_newton"] = ctx["ms_per_step"] / fast["ms"]
+    return out
+
+
 def run_vdp_fp32(ctx, steps):
     """The headline workload with float storage (residual, blocks and scans in double)."""
     import numpy as np
@@ -668,9 +689,9 @@ def main():
            "roofline": roofline, "autotune": tuned["table"]}
 
     ctx = dict(dev=dev, stream=stream, y0=y0, times=times, mu=mu, y_out=y_out, B=B, N=N, C=C, S=S, T=T, init=init,
-               ms_per_step=ms_per_step)
+               ms_per_step=ms_per_step, failed=int((st != 0).sum()))
     if not args.no_extras:
-        runs = [("chunk1", run_chunk1), ("fp32", run_vdp_fp32), ("fwd_adjoint", run_vdp_fwd_adjoint),
+        runs = [("chunk1", run_chunk1), ("jacobian_reuse", run_jacobian_reuse), ("fp32", run_vdp_fp32), ("fwd_adjoint", run_vdp_fwd_adjoint),
                 ("linear", run_linear), ("tiling_study", run_tiling_study), ("pcr_roofline", run_pcr),
                 ("mlp", run_mlp), ("robertson", run_robertson), ("predictor", run_predictor),
                 ("forward_euler", run_forward_euler), ("paper_grid", run_paper_grid)]

@@ -159,12 +159,22 @@ typedef struct {
                                   leave their slot idle; repeated entries give
                                   undefined results).  See tvi_order_longest_first */
     int32_t scheme;            /* tvi_scheme                                        */
+    double jacobian_reuse;     /* 0: a full Newton correction every iteration (the
+                                  paper's).  In (0, 1): a correction reuses the
+                                  previous one's inverted blocks and PCR matrices (a
+                                  chord step) while the residual norm has fallen by at
+                                  least this factor since then; otherwise the blocks
+                                  are formed at the current iterate.  The converged
+                                  result meets the same residual test.  Backward Euler,
+                                  analytic models, zero or extrapolated start, and
+                                  tilings with (steps_per_lane + log2 lanes) n^2 <= 72
+                                  (TVI_EUNSUPPORTED otherwise)                      */
 } tvi_options;
 
 /* Fills `opt` with the defaults: chunk 64, tol_a 1e-8, tol_r 1e-6 (Section 2.3),
  * max_newton 50, lanes/steps chosen from chunk, TVI_INIT_ZERO, halving on, no
  * predictor (predictor_base 1 once one is given), series in index order,
- * backward Euler. */
+ * backward Euler, a full Newton correction every iteration. */
 void tvi_default_options(tvi_options *opt);
 
 /* tvi_order_longest_first -- the launch order that solves ragged series

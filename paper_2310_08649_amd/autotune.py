@@ -74,8 +74,11 @@ def _time(fn, reps):
 
 
 def tune_forward(kind, y0, times, params, offsets=None, tol=(1e-8, 1e-6), chunks=(10, 50, 100, 200, 500),
-                 reps=3, y_out=None, use_cache=True, inits=("zero",), adjoint=None, **kw):
-    """Returns {"best": {chunk, lanes, steps_per_lane, init, failed, ms}, "table": [...]}.
+                 reps=3, y_out=None, use_cache=True, inits=("zero",), adjoint=None, reuses=(0.0,), **kw):
+    """Returns {"best": {chunk, lanes, steps_per_lane, init, jacobian_reuse, failed, ms}, "table": [...]}.
+
+    ``reuses``: Jacobian-reuse factors to try (0: full Newton); a factor that
+    the tiling does not support is skipped.
 
     Candidates are ranked by the number of series that failed to converge,
     then by time: a faster configuration never wins by giving up on series.
@@ -83,8 +86,8 @@ def tune_forward(kind, y0, times, params, offsets=None, tol=(1e-8, 1e-6), chunks
     forward solve followed by the adjoint (Frobenius-loss gradient, states
     read from the trajectory or recomputed from checkpoints): the tiling that
     suits the forward pass alone need not suit the pair."""
-    key = _key(kind, y0, times, offsets, "tol=%g,%g|chunks=%s|inits=%s|adjoint=%s"
-               % (tol[0], tol[1], ",".join(map(str, chunks)), ",".join(inits), adjoint))
+    key = _key(kind, y0, times, offsets, "tol=%g,%g|chunks=%s|inits=%s|adjoint=%s|reuses=%s"
+               % (tol[0], tol[1], ",".join(map(str, chunks)), ",".join(inits), adjoint, ",".join(map(str, reuses))))
     if use_cache:
         with _lock:
             hit = _load_cache().get(key)
@@ -93,23 +96,30 @@ def tune_forward(kind, y0, times, params, offsets=None, tol=(1e-8, 1e-6), chunks
     table = []
     for C in chunks:
         for S, T in tilings(C):
-            for init in inits:
+            for init, reuse in [(i, r) for i in inits for r in reuses]:
                 res = {}
 
                 def fn():
                     y, st, _, ck = tvi.solve_forward(kind, y0, times, params, offsets=offsets, chunk=C, lanes=S,
                                                      steps_per_lane=T, tol=tol, y_out=y_out, init=init,
-                                                     iters=False, checkpoints=adjoint == "recompute", **kw)
+                                                     iters=False, checkpoints=adjoint == "recompute",
+                                                     jacobian_reuse=reuse, **kw)
                     res["st"] = st
                     if adjoint:
                         g = y if "g" not in res else res["g"]
                         res["g"] = g
                         src = dict(ckpt=ck) if adjoint == "recompute" else dict(y=y)
                         tvi.solve_adjoint(kind, times, params, g, offsets=offsets, chunk=C, lanes=S,
-                                          steps_per_lane=T, tol=tol, init=init, **src, **kw)
-                ms = _time(fn, reps)
+                                          steps_per_lane=T, tol=tol, init=init, jacobian_reuse=reuse, **src, **kw)
+                try:
+                    ms = _time(fn, reps)
+                except tvi.TviError:
+                    if reuse > 0.0:
+                        continue  # this tiling keeps too many matrices per lane for reuse
+                    raise
                 failed = int((res["st"] != 0).sum().item())
-                table.append({"chunk": C, "lanes": S, "steps_per_lane": T, "init": init, "failed": failed, "ms": ms})
+                table.append({"chunk": C, "lanes": S, "steps_per_lane": T, "init": init, "jacobian_reuse": reuse,
+                              "failed": failed, "ms": ms})
     best = min(table, key=lambda r: (r["failed"], r["ms"]))
     res = {"best": best, "table": table}
     if use_cache:

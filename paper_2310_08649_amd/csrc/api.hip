@@ -92,6 +92,9 @@ tvi_status check_options(const tvi_options *o)
         return TVI_EINVAL;
     if (o->scheme != TVI_BACKWARD_EULER && o->scheme != TVI_FORWARD_EULER) return TVI_EINVAL;
     if (o->scheme == TVI_FORWARD_EULER && o->init == TVI_INIT_PREDICTOR) return TVI_EUNSUPPORTED;
+    if (!(o->jacobian_reuse >= 0.0 && o->jacobian_reuse < 1.0)) return TVI_EINVAL;
+    if (o->jacobian_reuse > 0.0 && (o->scheme != TVI_BACKWARD_EULER || o->init == TVI_INIT_PREDICTOR))
+        return TVI_EUNSUPPORTED;
     return TVI_OK;
 }
 
@@ -121,6 +124,7 @@ SolveArgs<IO> make_args(const tvi_model *model, const tvi_options *opt, int64_t 
     a.pred_base = opt->predictor_base;
     a.order = opt->order;
     a.scheme = opt->scheme;
+    a.reuse = opt->jacobian_reuse;
     return a;
 }
 
@@ -167,6 +171,7 @@ void tvi_default_options(tvi_options *opt)
     opt->predictor_base = 1;
     opt->order = nullptr;
     opt->scheme = TVI_BACKWARD_EULER;
+    opt->jacobian_reuse = 0.0;
 }
 
 const char *tvi_status_str(int32_t s)
@@ -230,7 +235,7 @@ tvi_status tvi_solve_forward(const tvi_model *model, const tvi_options *opt, int
     if (!times || !y0 || !params || !status || (!y_out && !ckpt)) return TVI_EINVAL;
     int S = 0, T = 0;
     if (model->kind == TVI_MLP) {
-        if (opt->chunk > 128) return TVI_EUNSUPPORTED;
+        if (opt->chunk > 128 || opt->jacobian_reuse > 0.0) return TVI_EUNSUPPORTED;
     } else if ((e = resolve_tiling(opt, S, T)) != TVI_OK) {
         return e;
     } else if (opt->init == TVI_INIT_PREDICTOR && (S < 4 || T * model->n > kPredictorMaxTN)) {
@@ -279,7 +284,7 @@ tvi_status tvi_solve_adjoint(const tvi_model *model, const tvi_options *opt, int
         (!workspace || workspace_bytes < tvi_adjoint_workspace_bytes(model, opt, B)))
         return TVI_EINVAL;
     if (mlp) {
-        if (opt->chunk > 128) return TVI_EUNSUPPORTED;
+        if (opt->chunk > 128 || opt->jacobian_reuse > 0.0) return TVI_EUNSUPPORTED;
         const int pass = recompute ? PASS_ADJOINT_RECOMPUTE : PASS_ADJOINT;
         const hipStream_t st = static_cast<hipStream_t>(stream);
         if (model->dtype == TVI_F64) {

@@ -25,6 +25,27 @@ static tvi_status launch_st(int pass, const SolveArgs<IO> &a, hipStream_t stream
     if (pred && !kPred && pass != PASS_ADJOINT) return TVI_EUNSUPPORTED;
     // its hidden layers and outputs: [segments][2H + n S T] floats of LDS
     const size_t lds = pred ? (size_t)per_block * (2 * a.pred_hidden + Model::N * S * T) * sizeof(float) : 0;
+    // the reuse of factorized blocks (chord steps) keeps T + log2(S) n x n matrices per lane
+    constexpr bool kReuse = (T + scan_levels<S>()) * Model::N * Model::N <= 72;
+    if (a.reuse > 0.0) {
+        if (!kReuse || pred || a.scheme != 0) return TVI_EUNSUPPORTED;
+        if constexpr (kReuse) {
+            switch (pass) {
+            case PASS_FORWARD:
+                hipLaunchKernelGGL((forward_kernel<Model, IO, S, T, false, false, true>), grid, block, 0, stream, a);
+                break;
+            case PASS_ADJOINT:  // states read from the trajectory: no Newton iteration to reproduce
+                hipLaunchKernelGGL((adjoint_kernel<Model, IO, S, T, false, false>), grid, block, 0, stream, a);
+                break;
+            case PASS_ADJOINT_RECOMPUTE:
+                hipLaunchKernelGGL((adjoint_kernel<Model, IO, S, T, true, false, false, true>), grid, block, 0, stream,
+                                   a);
+                break;
+            default: return TVI_EINVAL;
+            }
+            return hipGetLastError() == hipSuccess ? TVI_OK : TVI_EHIP;
+        }
+    }
     if (a.scheme == 1) {  // forward Euler: its own instances, no learned start
         if (pred) return TVI_EUNSUPPORTED;
         switch (pass) {

@@ -46,7 +46,8 @@ class Options(ctypes.Structure):
                 ("max_newton", ctypes.c_int32), ("tol_a", ctypes.c_double), ("tol_r", ctypes.c_double),
                 ("init", ctypes.c_int32), ("halving", ctypes.c_int32), ("predictor", ctypes.c_void_p),
                 ("predictor_hidden", ctypes.c_int32), ("predictor_steps", ctypes.c_int32),
-                ("predictor_base", ctypes.c_int32), ("order", ctypes.c_void_p), ("scheme", ctypes.c_int32)]
+                ("predictor_base", ctypes.c_int32), ("order", ctypes.c_void_p), ("scheme", ctypes.c_int32),
+                ("jacobian_reuse", ctypes.c_double)]
 
 
 _lib = None
@@ -122,11 +123,13 @@ def param_count(kind, n, hidden=64):
 
 
 def make_options(chunk=64, tol=(1e-8, 1e-6), max_newton=50, lanes=0, steps_per_lane=0, init="zero",
-                 halving=True, predictor=None, order=None, scheme="backward_euler"):
+                 halving=True, predictor=None, order=None, scheme="backward_euler", jacobian_reuse=0.0):
     """``predictor``: (packed params, hidden, steps[, base]) of a trained chunk
     predictor, as made by ``predictor.solver_args`` (base 0: corrections to the
     zero start, 1: to the extrapolated start).  ``scheme``: "backward_euler" or
-    "forward_euler"."""
+    "forward_euler".  ``jacobian_reuse``: 0 for a full Newton correction every
+    iteration, or the residual reduction factor below which a correction reuses
+    the previous factorization."""
     o = Options()
     load().tvi_default_options(ctypes.byref(o))
     o.chunk = int(chunk)
@@ -143,6 +146,7 @@ def make_options(chunk=64, tol=(1e-8, 1e-6), max_newton=50, lanes=0, steps_per_l
     if order is not None:
         o.order = ctypes.c_void_p(order.data_ptr())
     o.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
+    o.jacobian_reuse = float(jacobian_reuse)
     return o
 
 
@@ -203,7 +207,7 @@ def _geometry(y0, times, offsets):
 
 def solve_forward(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e-6), max_newton=50, lanes=0,
                   steps_per_lane=0, init="zero", halving=True, checkpoints=False, y_out=None, iters=True,
-                  predictor=None, order=None, scheme="backward_euler"):
+                  predictor=None, order=None, scheme="backward_euler", jacobian_reuse=0.0):
     """Chunked backward Euler (or forward Euler, ``scheme="forward_euler"``).  Returns ``(y, status, iters, ckpt)`` (device tensors;
     ``iters`` and ``ckpt`` may be None).  Asynchronous: nothing is synchronised."""
     dt = y0.dtype
@@ -214,7 +218,8 @@ def solve_forward(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e
         offsets = _dev(offsets, torch.int64, "offsets")
     B, n, N, yshape = _geometry(y0, times, offsets)
     model = Model(KINDS[kind], n, _io_dtype(y0), 1 if params.dim() == 1 else 0, 64)
-    opt = make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, halving, predictor, order, scheme)
+    opt = make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, halving, predictor, order, scheme,
+                       jacobian_reuse)
     dev = y0.device
     y = y_out if y_out is not None else torch.empty(yshape, dtype=dt, device=dev)
     status = torch.empty(B, dtype=torch.int32, device=dev)
@@ -231,7 +236,7 @@ def solve_forward(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e
 
 def solve_adjoint(kind, times, params, g, y=None, ckpt=None, offsets=None, chunk=64, tol=(1e-8, 1e-6),
                   max_newton=50, lanes=0, steps_per_lane=0, init="zero", halving=True, n=None, predictor=None,
-                  order=None, scheme="backward_euler"):
+                  order=None, scheme="backward_euler", jacobian_reuse=0.0):
     """Discrete adjoint.  Returns ``(dLdp [B,P], dLdy0 [B,n], status [B])``.
 
     States come from the trajectory ``y`` or, when ``y`` is None, are recomputed
@@ -256,7 +261,8 @@ def solve_adjoint(kind, times, params, g, y=None, ckpt=None, offsets=None, chunk
     if not shared and (params.dim() != 2 or params.shape[0] != B):
         raise TviError("parameters must be per series [B, P] or shared [P]")
     model = Model(KINDS[kind], n, _io_dtype(g), 1 if shared else 0, 64)
-    opt = make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, halving, predictor, order, scheme)
+    opt = make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, halving, predictor, order, scheme,
+                       jacobian_reuse)
     lib = load()
     dev = g.device
     P = lib.tvi_param_count(ctypes.byref(model))
