@@ -669,7 +669,7 @@ def main():
 
     flops = float(it.sum()) * C * vdp_flops_per_step_iter(C)
     achieved_tflops = flops / (kern_ms * 1e-3) / 1e12
-    kname = "tvi::forward_kernel<tvi::VanDerPol, double, %d, %d, %s, false>" % (
+    kname = "tvi::forward_kernel<tvi::VanDerPol, double, %d, %d, %s, false, false>" % (
         S, T, "true" if init == "predictor" else "false")
     roofline = {"kernel": kname, "bound": "alu",
                 "achieved": achieved_tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
