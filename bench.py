@@ -423,6 +423,60 @@ def run_paper_grid(ctx, steps):
     return out
 
 
+def run_forward_ad(ctx, steps):
+    """The state Jacobian by forward-mode AD (one evaluation of the rate on dual
+    numbers) against the hand-written one, FP64, same chunk and tiling: the
+    headline Van der Pol forward; the linear system n = 4 (512 x 5000, C = 64);
+    Robertson (2000 ragged series, C = 256, longest first, forward); the paper's
+    Chaboche (2 backstresses) and neuron problems at n_batch = 50, C = 100,
+    forward + adjoint.  The paper reports AD at 2-8x the analytic cost (Section 5.4)."""
+    import numpy as np
+    import torch
+    from paper_2310_08649_amd import graph, tvi, workloads
+    dev = ctx["dev"]
+    d = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev)
+    res = {"unit": "ms per launch (forward) or per forward+adjoint graph"}
+
+    def pair(fn_of_jac, reps):
+        out = {}
+        for jac in ("analytic", "forward_ad"):
+            fn = fn_of_jac(jac)
+            fn()
+            out[jac] = float(np.median(time_launches(fn, reps, ctx["stream"])))
+        out["ad_over_analytic"] = out["forward_ad"] / out["analytic"]
+        return out
+
+    res["vanderpol"] = pair(lambda jac: lambda: tvi.solve_forward(
+        "vanderpol", ctx["y0"], ctx["times"], ctx["mu"], chunk=ctx["C"], lanes=ctx["S"], steps_per_lane=ctx["T"],
+        tol=TIMING_TOL, init=ctx["init"], y_out=ctx["y_out"], iters=False, jacobian=jac), max(3, steps // 2))
+    w = workloads.linear(B=512, N=5000, n=4, seed=114)
+    yl = torch.empty((512, 5001, 4), dtype=torch.float64, device=dev)
+    res["linear_n4"] = pair(lambda jac: lambda: tvi.solve_forward(
+        "linear", d(w["y0"]), d(w["times"]), d(w["params"]), chunk=64, tol=TIMING_TOL, y_out=yl, iters=False,
+        jacobian=jac), 5)
+    del yl
+    w = workloads.robertson()
+    off = torch.as_tensor(w["offsets"], device=dev)
+    order = tvi.order_longest_first(off)
+    yr = torch.empty((w["times"].shape[0], 3), dtype=torch.float64, device=dev)
+    res["robertson"] = pair(lambda jac: lambda: tvi.solve_forward(
+        "robertson", d(w["y0"]), d(w["times"]), d(w["params"]), offsets=off, chunk=256, lanes=64, steps_per_lane=4,
+        tol=TIMING_TOL, y_out=yr, iters=False, order=order, jacobian=jac), 3)
+    del yr
+    for kind, nu in (("chaboche", 2), ("neuron", 1)):
+        w = getattr(workloads, kind)(nu, 50)
+        row = {}
+        for jac in ("analytic", "forward_ad"):
+            cs = graph.CapturedStep(kind, d(w["y0"]), d(w["times"]), d(w["params"]), chunk=100, tol=TIMING_TOL,
+                                    loss="frobenius", recompute=False, jacobian=jac).capture()
+            cs.replay()
+            row[jac] = stats(time_launches(cs.replay, 5, torch.cuda.current_stream()))["median_ms"]
+            del cs
+        row["ad_over_analytic"] = row["forward_ad"] / row["analytic"]
+        res["%s_nu%d" % (kind, nu)] = row
+    return res
+
+
 def run_robertson(ctx, steps):
     """2000 ragged Robertson series (100..20000 log-spaced steps), FP64,
     forward + adjoint (Frobenius loss) as one captured graph, with the
@@ -694,7 +748,8 @@ def main():
         runs = [("chunk1", run_chunk1), ("jacobian_reuse", run_jacobian_reuse), ("fp32", run_vdp_fp32), ("fwd_adjoint", run_vdp_fwd_adjoint),
                 ("linear", run_linear), ("tiling_study", run_tiling_study), ("pcr_roofline", run_pcr),
                 ("mlp", run_mlp), ("robertson", run_robertson), ("predictor", run_predictor),
-                ("forward_euler", run_forward_euler), ("paper_grid", run_paper_grid)]
+                ("forward_euler", run_forward_euler), ("paper_grid", run_paper_grid),
+                ("forward_ad", run_forward_ad)]
         only = set(filter(None, args.only.split(",")))
         for name, fn in runs:
             if not only or name in only:

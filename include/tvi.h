@@ -128,6 +128,15 @@ typedef enum {
                                the explicit map                                                */
 } tvi_scheme;
 
+typedef enum {
+    TVI_JACOBIAN_ANALYTIC = 0,  /* the hand-written j = dh/dy (Section 2.2, the analytic option)          */
+    TVI_JACOBIAN_FORWARD_AD = 1 /* forward-mode automatic differentiation of h (Section 2.2, the forward
+                                   AD option): one evaluation of h on dual numbers seeded with the unit
+                                   vectors gives j in registers.  Analytic models with TVI_F64 storage,
+                                   backward Euler, zero or extrapolated start, no Jacobian reuse
+                                   (TVI_EUNSUPPORTED otherwise)                                        */
+} tvi_jacobian;
+
 typedef struct {
     int32_t kind;          /* tvi_model_kind                                   */
     int32_t n;             /* state size                                       */
@@ -169,12 +178,14 @@ typedef struct {
                                   analytic models, zero or extrapolated start, and
                                   tilings with (steps_per_lane + log2 lanes) n^2 <= 72
                                   (TVI_EUNSUPPORTED otherwise)                      */
+    int32_t jacobian;          /* tvi_jacobian: how the state Jacobian j is formed   */
 } tvi_options;
 
 /* Fills `opt` with the defaults: chunk 64, tol_a 1e-8, tol_r 1e-6 (Section 2.3),
  * max_newton 50, lanes/steps chosen from chunk, TVI_INIT_ZERO, halving on, no
  * predictor (predictor_base 1 once one is given), series in index order,
- * backward Euler, a full Newton correction every iteration. */
+ * backward Euler, a full Newton correction every iteration, the analytic
+ * Jacobian. */
 void tvi_default_options(tvi_options *opt);
 
 /* tvi_order_longest_first -- the launch order that solves ragged series

@@ -95,6 +95,10 @@ tvi_status check_options(const tvi_options *o)
     if (!(o->jacobian_reuse >= 0.0 && o->jacobian_reuse < 1.0)) return TVI_EINVAL;
     if (o->jacobian_reuse > 0.0 && (o->scheme != TVI_BACKWARD_EULER || o->init == TVI_INIT_PREDICTOR))
         return TVI_EUNSUPPORTED;
+    if (o->jacobian != TVI_JACOBIAN_ANALYTIC && o->jacobian != TVI_JACOBIAN_FORWARD_AD) return TVI_EINVAL;
+    if (o->jacobian == TVI_JACOBIAN_FORWARD_AD &&
+        (o->scheme != TVI_BACKWARD_EULER || o->init == TVI_INIT_PREDICTOR || o->jacobian_reuse > 0.0))
+        return TVI_EUNSUPPORTED;
     return TVI_OK;
 }
 
@@ -128,8 +132,10 @@ SolveArgs<IO> make_args(const tvi_model *model, const tvi_options *opt, int64_t 
     return a;
 }
 
-tvi_status dispatch(int pass, const tvi_model *model, const void *args, int S, int T, hipStream_t stream)
+tvi_status dispatch(int pass, const tvi_model *model, const void *args, int S, int T, hipStream_t stream,
+                    int jacobian = TVI_JACOBIAN_ANALYTIC)
 {
+    if (jacobian == TVI_JACOBIAN_FORWARD_AD) return launch_ad(model->kind, model->n, pass, model->dtype, args, S, T, stream);
     switch (model->kind) {
     case TVI_VANDERPOL: return launch_vanderpol(pass, model->dtype, args, S, T, stream);
     case TVI_ROBERTSON: return launch_robertson(pass, model->dtype, args, S, T, stream);
@@ -172,6 +178,7 @@ void tvi_default_options(tvi_options *opt)
     opt->order = nullptr;
     opt->scheme = TVI_BACKWARD_EULER;
     opt->jacobian_reuse = 0.0;
+    opt->jacobian = TVI_JACOBIAN_ANALYTIC;
 }
 
 const char *tvi_status_str(int32_t s)
@@ -235,7 +242,8 @@ tvi_status tvi_solve_forward(const tvi_model *model, const tvi_options *opt, int
     if (!times || !y0 || !params || !status || (!y_out && !ckpt)) return TVI_EINVAL;
     int S = 0, T = 0;
     if (model->kind == TVI_MLP) {
-        if (opt->chunk > 128 || opt->jacobian_reuse > 0.0) return TVI_EUNSUPPORTED;
+        if (opt->chunk > 128 || opt->jacobian_reuse > 0.0 || opt->jacobian != TVI_JACOBIAN_ANALYTIC)
+            return TVI_EUNSUPPORTED;
     } else if ((e = resolve_tiling(opt, S, T)) != TVI_OK) {
         return e;
     } else if (opt->init == TVI_INIT_PREDICTOR && (S < 4 || T * model->n > kPredictorMaxTN)) {
@@ -248,14 +256,14 @@ tvi_status tvi_solve_forward(const tvi_model *model, const tvi_options *opt, int
         a.ckpt = static_cast<double *>(ckpt);
         a.status = status;
         a.iters = iters;
-        return dispatch(PASS_FORWARD, model, &a, S, T, st);
+        return dispatch(PASS_FORWARD, model, &a, S, T, st, opt->jacobian);
     }
     SolveArgs<float> a = make_args<float>(model, opt, B, N, offsets, times, y0, params);
     a.y = static_cast<float *>(y_out);
     a.ckpt = static_cast<double *>(ckpt);
     a.status = status;
     a.iters = iters;
-    return dispatch(PASS_FORWARD, model, &a, S, T, st);
+    return dispatch(PASS_FORWARD, model, &a, S, T, st, opt->jacobian);
 }
 
 size_t tvi_adjoint_workspace_bytes(const tvi_model *model, const tvi_options *opt, int64_t B)
@@ -284,7 +292,8 @@ tvi_status tvi_solve_adjoint(const tvi_model *model, const tvi_options *opt, int
         (!workspace || workspace_bytes < tvi_adjoint_workspace_bytes(model, opt, B)))
         return TVI_EINVAL;
     if (mlp) {
-        if (opt->chunk > 128 || opt->jacobian_reuse > 0.0) return TVI_EUNSUPPORTED;
+        if (opt->chunk > 128 || opt->jacobian_reuse > 0.0 || opt->jacobian != TVI_JACOBIAN_ANALYTIC)
+            return TVI_EUNSUPPORTED;
         const int pass = recompute ? PASS_ADJOINT_RECOMPUTE : PASS_ADJOINT;
         const hipStream_t st = static_cast<hipStream_t>(stream);
         if (model->dtype == TVI_F64) {
@@ -323,7 +332,7 @@ tvi_status tvi_solve_adjoint(const tvi_model *model, const tvi_options *opt, int
         a.dLdy0 = static_cast<double *>(dLdy0);
         a.status = status;
         a.ws = static_cast<double *>(workspace);
-        return dispatch(pass, model, &a, S, T, st);
+        return dispatch(pass, model, &a, S, T, st, opt->jacobian);
     }
     SolveArgs<float> a = make_args<float>(model, opt, B, N, offsets, times, nullptr, params);
     a.y = const_cast<float *>(static_cast<const float *>(y));
@@ -333,7 +342,7 @@ tvi_status tvi_solve_adjoint(const tvi_model *model, const tvi_options *opt, int
     a.dLdy0 = static_cast<float *>(dLdy0);
     a.status = status;
     a.ws = static_cast<double *>(workspace);
-    return dispatch(pass, model, &a, S, T, st);
+    return dispatch(pass, model, &a, S, T, st, opt->jacobian);
 }
 
 size_t tvi_loss_workspace_bytes(void) { return loss_workspace_bytes(); }

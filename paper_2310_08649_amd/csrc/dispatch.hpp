@@ -11,6 +11,17 @@ namespace tvi {
 
 enum Pass : int { PASS_FORWARD = 0, PASS_ADJOINT = 1, PASS_ADJOINT_RECOMPUTE = 2 };
 
+// Models with the learned-start, Jacobian-reuse and forward-Euler instances
+// (the forward-AD Jacobian variants have the plain backward-Euler ones only).
+template <class M>
+struct Variants {
+    static constexpr bool value = true;
+};
+template <class M>
+struct Variants<ForwardAD<M>> {
+    static constexpr bool value = false;
+};
+
 template <class Model, class IO, int S, int T>
 static tvi_status launch_st(int pass, const SolveArgs<IO> &a, hipStream_t stream)
 {
@@ -21,15 +32,16 @@ static tvi_status launch_st(int pass, const SolveArgs<IO> &a, hipStream_t stream
     dim3 grid((unsigned)blocks), block(kWave);
     const bool pred = a.init == INIT_PREDICTOR;
     // the learned start has its own instances (segments of >= 4 lanes, T n <= kPredictorMaxTN)
-    constexpr bool kPred = S >= 4 && T * Model::N <= kPredictorMaxTN;
+    constexpr bool kVar = Variants<Model>::value;
+    constexpr bool kPred = kVar && S >= 4 && T * Model::N <= kPredictorMaxTN;
     if (pred && !kPred && pass != PASS_ADJOINT) return TVI_EUNSUPPORTED;
     // its hidden layers and outputs: [segments][2H + n S T] floats of LDS
     const size_t lds = pred ? (size_t)per_block * (2 * a.pred_hidden + Model::N * S * T) * sizeof(float) : 0;
     // the reuse of factorized blocks (chord steps) keeps T + log2(S) n x n matrices per lane
     constexpr bool kReuse = (T + scan_levels<S>()) * Model::N * Model::N <= 72;
     if (a.reuse > 0.0) {
-        if (!kReuse || pred || a.scheme != 0) return TVI_EUNSUPPORTED;
-        if constexpr (kReuse) {
+        if (!kReuse || !kVar || pred || a.scheme != 0) return TVI_EUNSUPPORTED;
+        if constexpr (kReuse && kVar) {
             switch (pass) {
             case PASS_FORWARD:
                 hipLaunchKernelGGL((forward_kernel<Model, IO, S, T, false, false, true>), grid, block, 0, stream, a);
@@ -47,8 +59,8 @@ static tvi_status launch_st(int pass, const SolveArgs<IO> &a, hipStream_t stream
         }
     }
     if (a.scheme == 1) {  // forward Euler: its own instances, no learned start
-        if (pred) return TVI_EUNSUPPORTED;
-        switch (pass) {
+        if (pred || !kVar) return TVI_EUNSUPPORTED;
+        if constexpr (kVar) switch (pass) {
         case PASS_FORWARD:
             hipLaunchKernelGGL((forward_kernel<Model, IO, S, T, false, true>), grid, block, 0, stream, a);
             break;
@@ -124,6 +136,10 @@ tvi_status launch_linear4(int pass, int dtype, const void *args, int S, int T, h
 tvi_status launch_chaboche3(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
 tvi_status launch_chaboche4(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
 tvi_status launch_neuron4(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
+// the same models with forward-AD state Jacobians (double storage only)
+tvi_status launch_ad(int kind, int n, int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
+tvi_status launch_ad_vdp_rob(int kind, int pass, const void *args, int S, int T, hipStream_t stream);
+tvi_status launch_ad_linear(int n, int pass, const void *args, int S, int T, hipStream_t stream);
 tvi_status launch_pcr(int dtype, int n, int64_t B, int m, const void *D, const void *r, void *x, int transpose,
                       int S, int T, hipStream_t stream);
 tvi_status launch_mlp(int pass, int dtype, const void *args, hipStream_t stream);

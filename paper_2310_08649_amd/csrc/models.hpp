@@ -5,6 +5,7 @@
 #pragma once
 
 #include "device.hpp"
+#include "dual.hpp"
 
 namespace tvi {
 
@@ -23,16 +24,18 @@ struct Linear {
 #pragma unroll
             for (int k = 0; k < NN; ++k) A[i][k] = ld(p + i * NN + k);
     }
-    __device__ __forceinline__ void rhs(const double (&y)[NN], double, double (&f)[NN]) const
+    template <class V>
+    __device__ __forceinline__ void rhs_t(const V (&y)[NN], double, V (&f)[NN]) const
     {
 #pragma unroll
         for (int i = 0; i < NN; ++i) {
-            double s = 0.0;
+            V s = V(0.0);
 #pragma unroll
-            for (int k = 0; k < NN; ++k) s = fma(A[i][k], y[k], s);
+            for (int k = 0; k < NN; ++k) s = fma_t(A[i][k], y[k], s);
             f[i] = s;
         }
     }
+    __device__ __forceinline__ void rhs(const double (&y)[NN], double t, double (&f)[NN]) const { rhs_t(y, t, f); }
     __device__ __forceinline__ void jac(const double (&)[NN], double, double (&J)[NN][NN]) const
     {
 #pragma unroll
@@ -59,11 +62,13 @@ struct VanDerPol {
 
     template <class IO>
     __device__ __forceinline__ void load(const IO *p) { mu = ld(p); }
-    __device__ __forceinline__ void rhs(const double (&y)[2], double, double (&f)[2]) const
+    template <class V>
+    __device__ __forceinline__ void rhs_t(const V (&y)[2], double, V (&f)[2]) const
     {
         f[0] = y[1];
         f[1] = mu * (1.0 - y[0] * y[0]) * y[1] - y[0];
     }
+    __device__ __forceinline__ void rhs(const double (&y)[2], double t, double (&f)[2]) const { rhs_t(y, t, f); }
     __device__ __forceinline__ void jac(const double (&y)[2], double, double (&J)[2][2]) const
     {
         J[0][0] = 0.0;
@@ -91,13 +96,15 @@ struct Robertson {
         k2 = 3.0e7 * ld(p + 1);
         k3 = 1.0e4 * ld(p + 2);
     }
-    __device__ __forceinline__ void rhs(const double (&y)[3], double, double (&f)[3]) const
+    template <class V>
+    __device__ __forceinline__ void rhs_t(const V (&y)[3], double, V (&f)[3]) const
     {
-        const double a = k1 * y[0], b = k3 * y[1] * y[2], c = k2 * y[1] * y[1];
+        const V a = k1 * y[0], b = k3 * y[1] * y[2], c = k2 * y[1] * y[1];
         f[0] = -a + b;
         f[1] = a - b - c;
         f[2] = c;
     }
+    __device__ __forceinline__ void rhs(const double (&y)[3], double t, double (&f)[3]) const { rhs_t(y, t, f); }
     __device__ __forceinline__ void jac(const double (&y)[3], double, double (&J)[3][3]) const
     {
         J[0][0] = -k1;
@@ -168,15 +175,24 @@ struct Chaboche {
         c.edot = eda * sin(2.0 * M_PI * t / T);
         return c;
     }
-    __device__ __forceinline__ void rhs(const double (&y)[N], double t, double (&f)[N]) const
+    template <class V>
+    __device__ __forceinline__ void rhs_t(const V (&y)[N], double t, V (&f)[N]) const
     {
-        const Flow c = flow(y, t);
-        const double ep = c.pa * c.sg;
-        f[0] = E * (c.edot - ep);
-        f[1] = tau * (Kinf - y[1]) * c.pa;
+        V sx = V(0.0);
 #pragma unroll
-        for (int i = 0; i < NU; ++i) f[2 + i] = 2.0 / 3.0 * C[i] * ep - gam[i] * y[2 + i] * c.pa;
+        for (int i = 0; i < NU; ++i) sx = sx + y[2 + i];
+        const V s = y[0] - sx;
+        const double sg = val(s) > 0.0 ? 1.0 : (val(s) < 0.0 ? -1.0 : 0.0);
+        const V a = (abs_t(s) - y[1] - s0) / eta;
+        const V pa = val(a) > 0.0 ? pow_pos(a, ex) : V(0.0);  // <a>^n as a^(n-1) a, as in flow()
+        const V ep = pa * sg;
+        const double edot = eda * sin(2.0 * M_PI * t / T);
+        f[0] = E * (edot - ep);
+        f[1] = tau * (Kinf - y[1]) * pa;
+#pragma unroll
+        for (int i = 0; i < NU; ++i) f[2 + i] = 2.0 / 3.0 * C[i] * ep - gam[i] * y[2 + i] * pa;
     }
+    __device__ __forceinline__ void rhs(const double (&y)[N], double t, double (&f)[N]) const { rhs_t(y, t, f); }
     __device__ __forceinline__ void jac(const double (&y)[N], double t, double (&J)[N][N]) const
     {
         const Flow c = flow(y, t);
@@ -250,19 +266,22 @@ struct Neuron1 {
         for (int k = 0; k < P; ++k) q[k] = ld(p + k);
     }
     enum { C, GNA, ENA, GK, EK, GL, EL, MINF, TM, HINF, TH, NINF, TN, GC, TP, IA };
-    __device__ __forceinline__ double current(const double (&y)[4], double t) const
+    template <class V>
+    __device__ __forceinline__ V current(const V (&y)[4], double t) const
     {
-        const double m3 = y[1] * y[1] * y[1], n4 = y[3] * y[3] * y[3] * y[3];
+        const V m3 = y[1] * y[1] * y[1], n4 = y[3] * y[3] * y[3] * y[3];
         return -q[GNA] * m3 * y[2] * (y[0] - q[ENA]) - q[GK] * n4 * (y[0] - q[EK]) - q[GL] * (y[0] - q[EL]) +
                q[IA] * sin(2.0 * M_PI * t / q[TP]);
     }
-    __device__ __forceinline__ void rhs(const double (&y)[4], double t, double (&f)[4]) const
+    template <class V>
+    __device__ __forceinline__ void rhs_t(const V (&y)[4], double t, V (&f)[4]) const
     {
         f[0] = current(y, t) / q[C];
         f[1] = (q[MINF] - y[1]) / q[TM];
         f[2] = (q[HINF] - y[2]) / q[TH];
         f[3] = (q[NINF] - y[3]) / q[TN];
     }
+    __device__ __forceinline__ void rhs(const double (&y)[4], double t, double (&f)[4]) const { rhs_t(y, t, f); }
     __device__ __forceinline__ void jac(const double (&y)[4], double, double (&J)[4][4]) const
     {
         const double m = y[1], h = y[2], n = y[3], V = y[0];
@@ -299,6 +318,30 @@ struct Neuron1 {
         gp[TH] -= w[2] * (q[HINF] - h) / (q[TH] * q[TH]);
         gp[NINF] += w[3] / q[TN];
         gp[TN] -= w[3] * (q[NINF] - n) / (q[TN] * q[TN]);
+    }
+};
+
+// A model whose state Jacobian comes from forward-mode automatic
+// differentiation of its right-hand side (one evaluation on duals seeded with
+// the unit vectors) instead of the hand-written one; the rate and the
+// parameter products are the model's own.
+template <class M>
+struct ForwardAD : M {
+    static constexpr int N = M::N;
+    __device__ __forceinline__ void jac(const double (&y)[N], double t, double (&J)[N][N]) const
+    {
+        Dual<N> yd[N], fd[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            yd[k].v = y[k];
+#pragma unroll
+            for (int c = 0; c < N; ++c) yd[k].d[c] = (c == k) ? 1.0 : 0.0;
+        }
+        this->rhs_t(yd, t, fd);
+#pragma unroll
+        for (int r = 0; r < N; ++r)
+#pragma unroll
+            for (int c = 0; c < N; ++c) J[r][c] = fd[r].d[c];
     }
 };
 

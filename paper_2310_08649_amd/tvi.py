@@ -29,6 +29,7 @@ KINDS = {"linear": 0, "vanderpol": 1, "robertson": 2, "mlp": 3, "chaboche": 4, "
 F32, F64 = 0, 1
 INIT = {"zero": 0, "extrap": 1, "predictor": 2}
 SCHEMES = {"backward_euler": 0, "forward_euler": 1}
+JACOBIANS = {"analytic": 0, "forward_ad": 1}
 STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "SINGULAR", 3: "NONFINITE"}
 
 
@@ -47,7 +48,7 @@ class Options(ctypes.Structure):
                 ("init", ctypes.c_int32), ("halving", ctypes.c_int32), ("predictor", ctypes.c_void_p),
                 ("predictor_hidden", ctypes.c_int32), ("predictor_steps", ctypes.c_int32),
                 ("predictor_base", ctypes.c_int32), ("order", ctypes.c_void_p), ("scheme", ctypes.c_int32),
-                ("jacobian_reuse", ctypes.c_double)]
+                ("jacobian_reuse", ctypes.c_double), ("jacobian", ctypes.c_int32)]
 
 
 _lib = None
@@ -123,13 +124,14 @@ def param_count(kind, n, hidden=64):
 
 
 def make_options(chunk=64, tol=(1e-8, 1e-6), max_newton=50, lanes=0, steps_per_lane=0, init="zero",
-                 halving=True, predictor=None, order=None, scheme="backward_euler", jacobian_reuse=0.0):
+                 halving=True, predictor=None, order=None, scheme="backward_euler", jacobian_reuse=0.0,
+                 jacobian="analytic"):
     """``predictor``: (packed params, hidden, steps[, base]) of a trained chunk
     predictor, as made by ``predictor.solver_args`` (base 0: corrections to the
     zero start, 1: to the extrapolated start).  ``scheme``: "backward_euler" or
     "forward_euler".  ``jacobian_reuse``: 0 for a full Newton correction every
     iteration, or the residual reduction factor below which a correction reuses
-    the previous factorization."""
+    the previous factorization.  ``jacobian``: "analytic" or "forward_ad"."""
     o = Options()
     load().tvi_default_options(ctypes.byref(o))
     o.chunk = int(chunk)
@@ -147,6 +149,7 @@ def make_options(chunk=64, tol=(1e-8, 1e-6), max_newton=50, lanes=0, steps_per_l
         o.order = ctypes.c_void_p(order.data_ptr())
     o.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
     o.jacobian_reuse = float(jacobian_reuse)
+    o.jacobian = JACOBIANS[jacobian] if isinstance(jacobian, str) else int(jacobian)
     return o
 
 
@@ -207,7 +210,7 @@ def _geometry(y0, times, offsets):
 
 def solve_forward(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e-6), max_newton=50, lanes=0,
                   steps_per_lane=0, init="zero", halving=True, checkpoints=False, y_out=None, iters=True,
-                  predictor=None, order=None, scheme="backward_euler", jacobian_reuse=0.0):
+                  predictor=None, order=None, scheme="backward_euler", jacobian_reuse=0.0, jacobian="analytic"):
     """Chunked backward Euler (or forward Euler, ``scheme="forward_euler"``).  Returns ``(y, status, iters, ckpt)`` (device tensors;
     ``iters`` and ``ckpt`` may be None).  Asynchronous: nothing is synchronised."""
     dt = y0.dtype
@@ -219,7 +222,7 @@ def solve_forward(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e
     B, n, N, yshape = _geometry(y0, times, offsets)
     model = Model(KINDS[kind], n, _io_dtype(y0), 1 if params.dim() == 1 else 0, 64)
     opt = make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, halving, predictor, order, scheme,
-                       jacobian_reuse)
+                       jacobian_reuse, jacobian)
     dev = y0.device
     y = y_out if y_out is not None else torch.empty(yshape, dtype=dt, device=dev)
     status = torch.empty(B, dtype=torch.int32, device=dev)
@@ -236,7 +239,7 @@ def solve_forward(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e
 
 def solve_adjoint(kind, times, params, g, y=None, ckpt=None, offsets=None, chunk=64, tol=(1e-8, 1e-6),
                   max_newton=50, lanes=0, steps_per_lane=0, init="zero", halving=True, n=None, predictor=None,
-                  order=None, scheme="backward_euler", jacobian_reuse=0.0):
+                  order=None, scheme="backward_euler", jacobian_reuse=0.0, jacobian="analytic"):
     """Discrete adjoint.  Returns ``(dLdp [B,P], dLdy0 [B,n], status [B])``.
 
     States come from the trajectory ``y`` or, when ``y`` is None, are recomputed
@@ -262,7 +265,7 @@ def solve_adjoint(kind, times, params, g, y=None, ckpt=None, offsets=None, chunk
         raise TviError("parameters must be per series [B, P] or shared [P]")
     model = Model(KINDS[kind], n, _io_dtype(g), 1 if shared else 0, 64)
     opt = make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, halving, predictor, order, scheme,
-                       jacobian_reuse)
+                       jacobian_reuse, jacobian)
     lib = load()
     dev = g.device
     P = lib.tvi_param_count(ctypes.byref(model))

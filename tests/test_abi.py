@@ -210,3 +210,19 @@ def test_jacobian_reuse_option_is_checked(lib):
     assert fwd(tvi.make_options(chunk=512, lanes=64, steps_per_lane=8, jacobian_reuse=0.2), mr) == -4
     mm = tvi.Model(tvi.KINDS["mlp"], 8, tvi.F32, 1, 64)
     assert fwd(tvi.make_options(chunk=16, jacobian_reuse=0.2), mm) == -4
+
+
+def test_jacobian_option_is_checked(lib):
+    from paper_2310_08649_amd import tvi
+    f = _fake()
+
+    def fwd(o, kind="vanderpol", n=2, dtype=tvi.F64, shared=0):
+        m = tvi.Model(tvi.KINDS[kind], n, dtype, shared, 64)
+        return lib.tvi_solve_forward(ctypes.byref(m), ctypes.byref(o), 4, 10, None, f, f, f, f, None, f, None, None)
+
+    assert tvi.make_options().jacobian == 0
+    assert fwd(tvi.make_options(chunk=16, jacobian=2)) == -1
+    assert fwd(tvi.make_options(chunk=16, jacobian="forward_ad", scheme="forward_euler")) == -4
+    assert fwd(tvi.make_options(chunk=16, jacobian="forward_ad", jacobian_reuse=0.2)) == -4
+    assert fwd(tvi.make_options(chunk=16, jacobian="forward_ad"), dtype=tvi.F32) == -4
+    assert fwd(tvi.make_options(chunk=16, jacobian="forward_ad"), kind="mlp", n=8, dtype=tvi.F32, shared=1) == -4
