@@ -381,10 +381,10 @@ def run_forward_euler(ctx, steps):
 
 def run_paper_grid(ctx, steps):
     """The paper's chunk-efficiency study (Section 5.3, its parameter table) on
-    its Chaboche (1 and 2 backstresses) and coupled-neuron (one neuron) example
+    its Chaboche (1 to 5 backstresses) and coupled-neuron (one neuron) example
     problems, FP64: n_time = 2000, n_batch in {3, 10, 30, 50}, chunks
     {1, 3, 10, 30, 100, 300, 512} (512 is the longest chunk here; the paper's
-    grid ends at 1000), forward + adjoint of the Frobenius loss of the whole
+    grid ends at 1000; 3-5 backstresses run one step per lane, chunks up to 64), forward + adjoint of the Frobenius loss of the whole
     trajectory as one captured graph (states read from the stored trajectory).
     Each chunk runs with PCR across lanes (T = 1 up to 64 steps) and with the
     PCR->Thomas hybrid at T = 8; the speed-up is chunk 1 against the best."""
@@ -393,13 +393,15 @@ def run_paper_grid(ctx, steps):
     dev = ctx["dev"]
     out = {"unit": "ms per forward+adjoint", "paper_best_speedup": {"chaboche": 190, "neuron": 94}}
     best_by_model = {}
-    for kind, nu in (("chaboche", 1), ("chaboche", 2), ("neuron", 1)):
+    for kind, nu in (("chaboche", 1), ("chaboche", 2), ("chaboche", 3), ("chaboche", 4), ("chaboche", 5),
+                     ("neuron", 1)):
+        big = kind == "chaboche" and nu >= 3  # one step per lane: chunks up to 64
         for nb in (3, 10, 30, 50):
             w = getattr(workloads, kind)(nu, nb)
             d = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev)
             row = {}
-            for C in (1, 3, 10, 30, 100, 300, 512):
-                tilings = [(1, 1)] if C == 1 else [(0, 0)] + ([(-(-C // 8), 8)] if C >= 32 else [])
+            for C in ((1, 3, 10, 30, 64) if big else (1, 3, 10, 30, 100, 300, 512)):
+                tilings = [(1, 1)] if C == 1 else [(0, 0)] + ([(-(-C // 8), 8)] if C >= 32 and not big else [])
                 for S, T in tilings:
                     if S > 64:
                         continue

@@ -57,8 +57,9 @@
  *                  h = W3 tanh(W2 tanh(W1 y + b1) + b2) + b3, one shared
  *                  p = (W1[64][8], b1[64], W2[64][64], b2[64], W3[8][64], b3[8]) (P = 5256);
  *                  computed in float on MFMA (bf16x3 products for h)
- *   TVI_CHABOCHE   Chaboche viscoplasticity (Section 5.1.1), n = 2 + nu with nu = 1 or 2
- *                  backstresses: state (sigma, K, X_1..X_nu), s = sigma - sum X,
+ *   TVI_CHABOCHE   Chaboche viscoplasticity (Section 5.1.1), n = 2 + nu with nu = 1..5
+ *                  backstresses (nu >= 3: one step per lane, backward Euler, analytic
+ *                  Jacobian, no learned start or Jacobian reuse; TVI_EUNSUPPORTED otherwise): state (sigma, K, X_1..X_nu), s = sigma - sum X,
  *                  a = (|s| - K - sigma0)/eta, ep = <a>^n sign(s),
  *                  h = (E (edot(t) - ep), tau (K_inf - K) |ep|, 2/3 C_i ep - gamma_i X_i |ep|),
  *                  edot(t) = edot_a sin(2 pi t / T),

@@ -53,9 +53,9 @@ tvi_status check_model(const tvi_model *m)
     case TVI_LINEAR: return (m->n >= 2 && m->n <= 4) ? TVI_OK : TVI_EUNSUPPORTED;
     case TVI_VANDERPOL: return m->n == 2 ? TVI_OK : TVI_EINVAL;
     case TVI_ROBERTSON: return m->n == 3 ? TVI_OK : TVI_EINVAL;
-    case TVI_CHABOCHE:  // 1 or 2 backstresses in the register-resident solver
+    case TVI_CHABOCHE:  // 1 to 5 backstresses in the register-resident solver
         if (m->n < 3) return TVI_EINVAL;
-        return m->n <= 4 ? TVI_OK : TVI_EUNSUPPORTED;
+        return m->n <= 7 ? TVI_OK : TVI_EUNSUPPORTED;
     case TVI_NEURON:    // one neuron
         if (m->n < 4 || m->n % 4) return TVI_EINVAL;
         return m->n == 4 ? TVI_OK : TVI_EUNSUPPORTED;
@@ -140,8 +140,14 @@ tvi_status dispatch(int pass, const tvi_model *model, const void *args, int S, i
     case TVI_VANDERPOL: return launch_vanderpol(pass, model->dtype, args, S, T, stream);
     case TVI_ROBERTSON: return launch_robertson(pass, model->dtype, args, S, T, stream);
     case TVI_CHABOCHE:
-        return model->n == 3 ? launch_chaboche3(pass, model->dtype, args, S, T, stream)
-                             : launch_chaboche4(pass, model->dtype, args, S, T, stream);
+        switch (model->n) {
+        case 3: return launch_chaboche3(pass, model->dtype, args, S, T, stream);
+        case 4: return launch_chaboche4(pass, model->dtype, args, S, T, stream);
+        case 5: return launch_chaboche5(pass, model->dtype, args, S, T, stream);
+        case 6: return launch_chaboche6(pass, model->dtype, args, S, T, stream);
+        case 7: return launch_chaboche7(pass, model->dtype, args, S, T, stream);
+        default: return TVI_EUNSUPPORTED;
+        }
     case TVI_NEURON: return launch_neuron4(pass, model->dtype, args, S, T, stream);
     case TVI_MLP: return launch_mlp(pass, model->dtype, args, stream);
     case TVI_LINEAR:

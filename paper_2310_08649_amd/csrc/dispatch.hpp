@@ -21,6 +21,20 @@ template <class M>
 struct Variants<ForwardAD<M>> {
     static constexpr bool value = false;
 };
+// Chaboche with 3-5 backstresses (n = 5..7): one step per lane and the plain
+// backward-Euler instances only (the registers of larger blocks)
+template <int NU>
+struct Variants<Chaboche<NU>> {
+    static constexpr bool value = NU <= 2;
+};
+template <class M>
+struct MaxStepsPerLane {
+    static constexpr int value = 8;
+};
+template <int NU>
+struct MaxStepsPerLane<Chaboche<NU>> {
+    static constexpr int value = NU <= 2 ? 8 : 1;
+};
 
 template <class Model, class IO, int S, int T>
 static tvi_status launch_st(int pass, const SolveArgs<IO> &a, hipStream_t stream)
@@ -104,13 +118,22 @@ static tvi_status launch_st(int pass, const SolveArgs<IO> &a, hipStream_t stream
 template <class Model, class IO, int S>
 static tvi_status launch_s(int pass, const SolveArgs<IO> &a, int T, hipStream_t stream)
 {
+    constexpr int kMaxT = MaxStepsPerLane<Model>::value;
+    if (T > kMaxT) return TVI_EUNSUPPORTED;
     switch (T) {
     case 1: return launch_st<Model, IO, S, 1>(pass, a, stream);
-    case 2: return launch_st<Model, IO, S, 2>(pass, a, stream);
-    case 4: return launch_st<Model, IO, S, 4>(pass, a, stream);
-    case 8: return launch_st<Model, IO, S, 8>(pass, a, stream);
-    default: return TVI_EUNSUPPORTED;
+    case 2:
+        if constexpr (kMaxT >= 2) return launch_st<Model, IO, S, 2>(pass, a, stream);
+        break;
+    case 4:
+        if constexpr (kMaxT >= 4) return launch_st<Model, IO, S, 4>(pass, a, stream);
+        break;
+    case 8:
+        if constexpr (kMaxT >= 8) return launch_st<Model, IO, S, 8>(pass, a, stream);
+        break;
+    default: break;
     }
+    return TVI_EUNSUPPORTED;
 }
 
 template <class Model, class IO>
@@ -135,6 +158,9 @@ tvi_status launch_linear3(int pass, int dtype, const void *args, int S, int T, h
 tvi_status launch_linear4(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
 tvi_status launch_chaboche3(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
 tvi_status launch_chaboche4(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
+tvi_status launch_chaboche5(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
+tvi_status launch_chaboche6(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
+tvi_status launch_chaboche7(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
 tvi_status launch_neuron4(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
 // the same models with forward-AD state Jacobians (double storage only)
 tvi_status launch_ad(int kind, int n, int pass, int dtype, const void *args, int S, int T, hipStream_t stream);

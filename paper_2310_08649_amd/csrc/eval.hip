@@ -63,6 +63,9 @@ tvi_status launch_eval(int kind, int n, int dtype, int64_t M, const void *states
         switch (n) {
         case 3: return eval_dtype<Chaboche<1>>(dtype, M, states, times, params, shared, f, J, stream);
         case 4: return eval_dtype<Chaboche<2>>(dtype, M, states, times, params, shared, f, J, stream);
+        case 5: return eval_dtype<Chaboche<3>>(dtype, M, states, times, params, shared, f, J, stream);
+        case 6: return eval_dtype<Chaboche<4>>(dtype, M, states, times, params, shared, f, J, stream);
+        case 7: return eval_dtype<Chaboche<5>>(dtype, M, states, times, params, shared, f, J, stream);
         default: return TVI_EUNSUPPORTED;
         }
     case TVI_NEURON: return eval_dtype<Neuron1>(dtype, M, states, times, params, shared, f, J, stream);

@@ -13,8 +13,9 @@ tvi_status launch_ad(int kind, int n, int pass, int dtype, const void *args, int
     case TVI_ROBERTSON: return launch_ad_vdp_rob(kind, pass, args, S, T, stream);
     case TVI_LINEAR: return launch_ad_linear(n, pass, args, S, T, stream);
     case TVI_CHABOCHE:
-        return n == 3 ? launch_solver<ForwardAD<Chaboche<1>>, double>(pass, a, S, T, stream)
-                      : launch_solver<ForwardAD<Chaboche<2>>, double>(pass, a, S, T, stream);
+        if (n == 3) return launch_solver<ForwardAD<Chaboche<1>>, double>(pass, a, S, T, stream);
+        if (n == 4) return launch_solver<ForwardAD<Chaboche<2>>, double>(pass, a, S, T, stream);
+        return TVI_EUNSUPPORTED;
     case TVI_NEURON: return launch_solver<ForwardAD<Neuron1>, double>(pass, a, S, T, stream);
     default: return TVI_EUNSUPPORTED;
     }

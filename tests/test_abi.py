@@ -174,8 +174,8 @@ def test_scheme_option_is_checked(lib):
 
 
 def test_paper_example_models_sizes(lib):
-    """Chaboche with 1 or 2 backstresses and one neuron run in the register-resident
-    solver; other sizes are refused before any launch, as is float storage."""
+    """Chaboche with 1 to 5 backstresses and one neuron run in the register-resident
+    solver; other sizes are refused before any launch."""
     from paper_2310_08649_amd import tvi
     assert tvi.param_count("chaboche", 3) == 10 and tvi.param_count("chaboche", 4) == 12
     assert tvi.param_count("neuron", 4) == 16
@@ -187,7 +187,7 @@ def test_paper_example_models_sizes(lib):
         return lib.tvi_solve_forward(ctypes.byref(m), ctypes.byref(o), 4, 10, None, f, f, f, f, None, f, None, None)
 
     assert fwd("chaboche", 2) == -1
-    assert fwd("chaboche", 5) == -4
+    assert fwd("chaboche", 8) == -4
     assert fwd("neuron", 6) == -1
     assert fwd("neuron", 8) == -4
 
@@ -226,3 +226,20 @@ def test_jacobian_option_is_checked(lib):
     assert fwd(tvi.make_options(chunk=16, jacobian="forward_ad", jacobian_reuse=0.2)) == -4
     assert fwd(tvi.make_options(chunk=16, jacobian="forward_ad"), dtype=tvi.F32) == -4
     assert fwd(tvi.make_options(chunk=16, jacobian="forward_ad"), kind="mlp", n=8, dtype=tvi.F32, shared=1) == -4
+
+
+def test_larger_chaboche_one_step_per_lane(lib):
+    from paper_2310_08649_amd import tvi
+    f = _fake()
+    m = tvi.Model(tvi.KINDS["chaboche"], 7, tvi.F64, 0, 64)
+
+    def fwd(o):
+        return lib.tvi_solve_forward(ctypes.byref(m), ctypes.byref(o), 4, 10, None, f, f, f, f, None, f, None, None)
+
+    assert tvi.param_count("chaboche", 7) == 18
+    assert fwd(tvi.make_options(chunk=128, lanes=64, steps_per_lane=2)) == -4   # one step per lane only
+    assert fwd(tvi.make_options(chunk=16, scheme="forward_euler")) == -4
+    assert fwd(tvi.make_options(chunk=16, jacobian="forward_ad")) == -4
+    mb = tvi.Model(tvi.KINDS["chaboche"], 8, tvi.F64, 0, 64)
+    assert lib.tvi_solve_forward(ctypes.byref(mb), ctypes.byref(tvi.make_options(chunk=16)), 4, 10, None, f, f, f, f,
+                                 None, f, None, None) == -4

@@ -90,3 +90,37 @@ def test_float_storage_is_refused(tvi):
     f = lambda a: dev(a, torch.float32)
     with pytest.raises(tvi.TviError):
         tvi.solve_forward("chaboche", f(w["y0"]), f(w["times"]), f(w["params"]), chunk=10)
+
+
+@pytest.mark.parametrize("nu", [3, 4, 5])
+def test_chaboche_more_backstresses(tvi, nu):
+    """3-5 backstresses (n = 5..7) at one step per lane: rates and Jacobians, and
+    the paper-grid chunks up to 64, forward and adjoint."""
+    w = W.chaboche(nu, 10)
+    rng = np.random.default_rng(9 + nu)
+    M = 200
+    p = w["params"][rng.integers(0, 10, size=M)]
+    y = np.concatenate([rng.uniform(-4, 4, (M, 1)), rng.uniform(0, 1.5, (M, 1)), 0.2 * rng.standard_normal((M, nu))],
+                       axis=1)
+    t = rng.uniform(0.0, 10.0, M)
+    f, J = tvi.model_eval("chaboche", dev(y), dev(p), times=dev(t))
+    f, J = host(f), host(J)
+    for q in range(M):
+        fo, Jo = oracle.rhs("chaboche", y[q], t[q], p[q])
+        np.testing.assert_allclose(f[q], fo, rtol=1e-12, atol=1e-13 * max(1.0, np.abs(fo).max()))
+        np.testing.assert_allclose(J[q], Jo, rtol=1e-12, atol=1e-13 * max(1.0, np.abs(Jo).max()))
+    yo, so, _ = oracle.forward("chaboche", w["y0"], w["times"], w["params"], tol=PARITY_TOL)
+    assert (so == 0).all()
+    g = yo / np.sqrt(np.sum(yo ** 2))
+    op, oy0, _ = oracle.adjoint("chaboche", yo, w["times"], w["params"], g)
+    for C in (1, 3, 10, 30, 64):
+        kw = dict(chunk=C, lanes=max(4, 1 << (C - 1).bit_length()) if C > 1 else 1, steps_per_lane=1, tol=PARITY_TOL)
+        y, st, _, ck = tvi.solve_forward("chaboche", dev(w["y0"]), dev(w["times"]), dev(w["params"]),
+                                         checkpoints=True, **kw)
+        assert (host(st) == 0).all(), C
+        assert series_rel_err(host(y), yo).max() <= 1e-10, C
+        a1 = tvi.solve_adjoint("chaboche", dev(w["times"]), dev(w["params"]), dev(g), y=y, **kw)
+        a2 = tvi.solve_adjoint("chaboche", dev(w["times"]), dev(w["params"]), dev(g), ckpt=ck, **kw)
+        assert torch.equal(a1[0], a2[0]) and torch.equal(a1[1], a2[1]), C
+        assert grad_err(host(a1[0]), op) <= 1e-10, (C, grad_err(host(a1[0]), op))
+        assert np.abs(host(a1[1]) - oy0).max() <= 1e-10 * np.abs(oy0).max(), C
