@@ -102,3 +102,35 @@ def test_loss_gradients_float_storage(mods):
             gr = np.where(obs[:, None] == 1, 2 * y64 / (obs.sum() * 8), 0.0)
         assert abs(L.item() - Lr) <= 1e-12 * Lr
         np.testing.assert_allclose(g.cpu().numpy(), gr, rtol=1e-6, atol=1e-7 * np.abs(gr).max())
+
+
+@pytest.mark.parametrize("opts", [dict(scheme="forward_euler"), dict(jacobian="forward_ad"),
+                                  dict(jacobian_reuse=0.2), dict(jacobian_reuse=0.2, recompute=False)],
+                         ids=["forward_euler", "forward_ad", "reuse_recompute", "reuse_stored"])
+def test_captured_step_with_solver_options_replays_exactly(mods, opts):
+    """Forward Euler, AD Jacobians and Jacobian reuse inside one captured graph:
+    every replay, with eager work in between, equals the eager run bitwise."""
+    graph, tvi = mods
+    w = W.vanderpol(B=96, N=800, mu_range=(1.0, 10.0))
+    step = graph.CapturedStep("vanderpol", dev(w["y0"]), dev(w["times"]), dev(w["params"]), chunk=40,
+                              tol=PARITY_TOL, loss="frobenius", **opts)
+    step.run_eager()
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in (step.y, step.g, step.dLdp, step.dLdy0, step.status_fwd, step.status_adj)]
+    assert (ref[4].cpu().numpy() == 0).all() and (ref[5].cpu().numpy() == 0).all()
+    step.capture()
+    for rep in range(3):
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        step.replay()
+        torch.cuda.synchronize()
+        got = (step.y, step.g, step.dLdp, step.dLdy0, step.status_fwd, step.status_adj)
+        for a, b in zip(got, ref):
+            assert torch.equal(a, b), rep
+        del junk
+    scheme = opts.get("scheme", "backward_euler")
+    yo, so, _ = oracle.forward("vanderpol", w["y0"], w["times"], w["params"], tol=PARITY_TOL, scheme=scheme)
+    assert series_rel_err(ref[0].cpu().numpy(), yo).max() <= 1e-10
+    op, _, _ = oracle.adjoint("vanderpol", ref[0].cpu().numpy(), w["times"], w["params"], ref[1].cpu().numpy(),
+                              scheme=scheme)
+    dp = ref[2].cpu().numpy()
+    assert (np.abs(dp - op).max(axis=1) / np.abs(op).max(axis=1)).max() <= 1e-10
