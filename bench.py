@@ -381,10 +381,11 @@ def run_forward_euler(ctx, steps):
 
 def run_paper_grid(ctx, steps):
     """The paper's chunk-efficiency study (Section 5.3, its parameter table) on
-    its Chaboche (1 to 5 backstresses) and coupled-neuron (one neuron) example
+    its Chaboche (1 to 5 backstresses) and coupled-neuron (1 and 2 neurons) example
     problems, FP64: n_time = 2000, n_batch in {3, 10, 30, 50}, chunks
     {1, 3, 10, 30, 100, 300, 512} (512 is the longest chunk here; the paper's
-    grid ends at 1000; 3-5 backstresses run one step per lane, chunks up to 64), forward + adjoint of the Frobenius loss of the whole
+    grid ends at 1000; 3-5 backstresses and 2 neurons run one step per lane,
+    chunks up to 64), forward + adjoint of the Frobenius loss of the whole
     trajectory as one captured graph (states read from the stored trajectory).
     Each chunk runs with PCR across lanes (T = 1 up to 64 steps) and with the
     PCR->Thomas hybrid at T = 8; the speed-up is chunk 1 against the best."""
@@ -394,8 +395,8 @@ def run_paper_grid(ctx, steps):
     out = {"unit": "ms per forward+adjoint", "paper_best_speedup": {"chaboche": 190, "neuron": 94}}
     best_by_model = {}
     for kind, nu in (("chaboche", 1), ("chaboche", 2), ("chaboche", 3), ("chaboche", 4), ("chaboche", 5),
-                     ("neuron", 1)):
-        big = kind == "chaboche" and nu >= 3  # one step per lane: chunks up to 64
+                     ("neuron", 1), ("neuron", 2)):
+        big = (kind == "chaboche" and nu >= 3) or (kind == "neuron" and nu >= 2)  # one step per lane: C <= 64
         for nb in (3, 10, 30, 50):
             w = getattr(workloads, kind)(nu, nb)
             d = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev)

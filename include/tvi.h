@@ -66,12 +66,13 @@
  *                  p = (E, n, eta, sigma0, K_inf, tau, C_1..C_nu, gamma_1..gamma_nu, edot_a, T)
  *                  (P = 8 + 2 nu); the hardening rate carries |ep| (the model's standard form);
  *                  TVI_F64 only
- *   TVI_NEURON     one neuron of the coupled-neuron model (Section 5.1.1), n = 4, state
- *                  (V, m, h, n): dV/dt = (-g_Na m^3 h (V - E_Na) - g_K n^4 (V - E_K)
- *                  - g_L (V - E_L) + I_a sin(2 pi t / T)) / C, dx/dt = (x_inf - x)/tau_x,
+ *   TVI_NEURON     the coupled-neuron model (Section 5.1.1) with nu = n / 4 = 1 or 2 neurons,
+ *                  state (V_i, m_i, h_i, n_i) per neuron: dV_i/dt = (-g_Na m^3 h (V_i - E_Na)
+ *                  - g_K n^4 (V_i - E_K) - g_L (V_i - E_L) + I_a sin(2 pi t / T_i)
+ *                  + g_C sum_j (V_i - V_j)) / C_i, dx/dt = (x_inf - x)/tau_x,
  *                  p = (C, g_Na, E_Na, g_K, E_K, g_L, E_L, m_inf, tau_m, h_inf, tau_h, n_inf,
- *                  tau_n, g_C, T, I_a) (P = 16; g_C couples neurons and has no effect on one);
- *                  TVI_F64 only
+ *                  tau_n, g_C, T) per neuron, then I_a (P = 15 nu + 1); TVI_F64 only; two
+ *                  neurons: one step per lane, backward Euler, analytic Jacobian
  */
 #ifndef TVI_H
 #define TVI_H

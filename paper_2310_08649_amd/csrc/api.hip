@@ -56,9 +56,9 @@ tvi_status check_model(const tvi_model *m)
     case TVI_CHABOCHE:  // 1 to 5 backstresses in the register-resident solver
         if (m->n < 3) return TVI_EINVAL;
         return m->n <= 7 ? TVI_OK : TVI_EUNSUPPORTED;
-    case TVI_NEURON:    // one neuron
+    case TVI_NEURON:    // one or two neurons
         if (m->n < 4 || m->n % 4) return TVI_EINVAL;
-        return m->n == 4 ? TVI_OK : TVI_EUNSUPPORTED;
+        return m->n <= 8 ? TVI_OK : TVI_EUNSUPPORTED;
     case TVI_MLP:
         if (m->n != 8) return TVI_EINVAL;
         return m->hidden == 64 ? TVI_OK : TVI_EUNSUPPORTED;
@@ -148,7 +148,9 @@ tvi_status dispatch(int pass, const tvi_model *model, const void *args, int S, i
         case 7: return launch_chaboche7(pass, model->dtype, args, S, T, stream);
         default: return TVI_EUNSUPPORTED;
         }
-    case TVI_NEURON: return launch_neuron4(pass, model->dtype, args, S, T, stream);
+    case TVI_NEURON:
+        return model->n == 4 ? launch_neuron4(pass, model->dtype, args, S, T, stream)
+                             : launch_neuron8(pass, model->dtype, args, S, T, stream);
     case TVI_MLP: return launch_mlp(pass, model->dtype, args, stream);
     case TVI_LINEAR:
         switch (model->n) {

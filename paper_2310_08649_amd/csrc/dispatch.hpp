@@ -27,9 +27,18 @@ template <int NU>
 struct Variants<Chaboche<NU>> {
     static constexpr bool value = NU <= 2;
 };
+// Two coupled neurons (n = 8): likewise
+template <int NU>
+struct Variants<Neurons<NU>> {
+    static constexpr bool value = false;
+};
 template <class M>
 struct MaxStepsPerLane {
     static constexpr int value = 8;
+};
+template <int NU>
+struct MaxStepsPerLane<Neurons<NU>> {
+    static constexpr int value = 1;
 };
 template <int NU>
 struct MaxStepsPerLane<Chaboche<NU>> {
@@ -162,6 +171,7 @@ tvi_status launch_chaboche5(int pass, int dtype, const void *args, int S, int T,
 tvi_status launch_chaboche6(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
 tvi_status launch_chaboche7(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
 tvi_status launch_neuron4(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
+tvi_status launch_neuron8(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
 // the same models with forward-AD state Jacobians (double storage only)
 tvi_status launch_ad(int kind, int n, int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
 tvi_status launch_ad_vdp_rob(int kind, int pass, const void *args, int S, int T, hipStream_t stream);

@@ -68,7 +68,10 @@ tvi_status launch_eval(int kind, int n, int dtype, int64_t M, const void *states
         case 7: return eval_dtype<Chaboche<5>>(dtype, M, states, times, params, shared, f, J, stream);
         default: return TVI_EUNSUPPORTED;
         }
-    case TVI_NEURON: return eval_dtype<Neuron1>(dtype, M, states, times, params, shared, f, J, stream);
+    case TVI_NEURON:
+        if (n == 4) return eval_dtype<Neuron1>(dtype, M, states, times, params, shared, f, J, stream);
+        if (n == 8) return eval_dtype<Neurons<2>>(dtype, M, states, times, params, shared, f, J, stream);
+        return TVI_EUNSUPPORTED;
     case TVI_LINEAR:
         switch (n) {
         case 2: return eval_dtype<Linear<2>>(dtype, M, states, times, params, shared, f, J, stream);

@@ -16,7 +16,9 @@ tvi_status launch_ad(int kind, int n, int pass, int dtype, const void *args, int
         if (n == 3) return launch_solver<ForwardAD<Chaboche<1>>, double>(pass, a, S, T, stream);
         if (n == 4) return launch_solver<ForwardAD<Chaboche<2>>, double>(pass, a, S, T, stream);
         return TVI_EUNSUPPORTED;
-    case TVI_NEURON: return launch_solver<ForwardAD<Neuron1>, double>(pass, a, S, T, stream);
+    case TVI_NEURON:
+        if (n == 4) return launch_solver<ForwardAD<Neuron1>, double>(pass, a, S, T, stream);
+        return TVI_EUNSUPPORTED;
     default: return TVI_EUNSUPPORTED;
     }
 }

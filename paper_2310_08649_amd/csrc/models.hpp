@@ -321,6 +321,102 @@ struct Neuron1 {
     }
 };
 
+// NU coupled neurons (Section 5.1.1): state (V_i, m_i, h_i, n_i) per neuron,
+// p = the 15 per-neuron values (C, g_Na, E_Na, g_K, E_K, g_L, E_L, m_inf, tau_m,
+// h_inf, tau_h, n_inf, tau_n, g_C, T) of each neuron, then I_a:
+//   dV_i/dt = (-g_Na m^3 h (V_i - E_Na) - g_K n^4 (V_i - E_K) - g_L (V_i - E_L)
+//              + I_a sin(2 pi t / T_i) + g_C sum_j (V_i - V_j)) / C_i,
+//   dx_i/dt = (x_inf - x_i) / tau_x for x = m, h, n.
+template <int NU>
+struct Neurons {
+    static constexpr int N = 4 * NU;
+    static constexpr int P = 15 * NU + 1;
+    double q[P];
+    enum { C, GNA, ENA, GK, EK, GL, EL, MINF, TM, HINF, TH, NINF, TN, GC, TP };
+
+    template <class IO>
+    __device__ __forceinline__ void load(const IO *p)
+    {
+#pragma unroll
+        for (int k = 0; k < P; ++k) q[k] = ld(p + k);
+    }
+    template <class V>
+    __device__ __forceinline__ void rhs_t(const V (&y)[N], double t, V (&f)[N]) const
+    {
+        V vs = V(0.0);
+#pragma unroll
+        for (int j = 0; j < NU; ++j) vs = vs + y[4 * j];
+#pragma unroll
+        for (int i = 0; i < NU; ++i) {
+            const double *u = q + 15 * i;
+            const V &Vi = y[4 * i], &m = y[4 * i + 1], &h = y[4 * i + 2], &n = y[4 * i + 3];
+            const V m3 = m * m * m, n4 = n * n * n * n;
+            const V cpl = NU * Vi - vs;  // sum over j of (V_i - V_j)
+            const V F = -u[GNA] * m3 * h * (Vi - u[ENA]) - u[GK] * n4 * (Vi - u[EK]) - u[GL] * (Vi - u[EL]) +
+                        q[15 * NU] * sin(2.0 * M_PI * t / u[TP]) + u[GC] * cpl;
+            f[4 * i] = F / u[C];
+            f[4 * i + 1] = (u[MINF] - m) / u[TM];
+            f[4 * i + 2] = (u[HINF] - h) / u[TH];
+            f[4 * i + 3] = (u[NINF] - n) / u[TN];
+        }
+    }
+    __device__ __forceinline__ void rhs(const double (&y)[N], double t, double (&f)[N]) const { rhs_t(y, t, f); }
+    __device__ __forceinline__ void jac(const double (&y)[N], double, double (&J)[N][N]) const
+    {
+#pragma unroll
+        for (int r = 0; r < N; ++r)
+#pragma unroll
+            for (int c = 0; c < N; ++c) J[r][c] = 0.0;
+#pragma unroll
+        for (int i = 0; i < NU; ++i) {
+            const double *u = q + 15 * i;
+            const double V = y[4 * i], m = y[4 * i + 1], h = y[4 * i + 2], n = y[4 * i + 3];
+#pragma unroll
+            for (int j = 0; j < NU; ++j) J[4 * i][4 * j] = (j == i) ? 0.0 : -u[GC] / u[C];
+            J[4 * i][4 * i] = (-u[GNA] * m * m * m * h - u[GK] * n * n * n * n - u[GL] + u[GC] * (NU - 1)) / u[C];
+            J[4 * i][4 * i + 1] = -3.0 * u[GNA] * m * m * h * (V - u[ENA]) / u[C];
+            J[4 * i][4 * i + 2] = -u[GNA] * m * m * m * (V - u[ENA]) / u[C];
+            J[4 * i][4 * i + 3] = -4.0 * u[GK] * n * n * n * (V - u[EK]) / u[C];
+            J[4 * i + 1][4 * i + 1] = -1.0 / u[TM];
+            J[4 * i + 2][4 * i + 2] = -1.0 / u[TH];
+            J[4 * i + 3][4 * i + 3] = -1.0 / u[TN];
+        }
+    }
+    __device__ __forceinline__ void vjp_p(const double (&y)[N], double t, const double (&w)[N], double (&gp)[P]) const
+    {
+        double vs = 0.0;
+#pragma unroll
+        for (int j = 0; j < NU; ++j) vs += y[4 * j];
+#pragma unroll
+        for (int i = 0; i < NU; ++i) {
+            const double *u = q + 15 * i;
+            double *g = gp + 15 * i;
+            const double V = y[4 * i], m = y[4 * i + 1], h = y[4 * i + 2], n = y[4 * i + 3];
+            const double m3 = m * m * m, n4 = n * n * n * n, cpl = NU * V - vs;
+            const double ph = 2.0 * M_PI * t / u[TP], Ia = q[15 * NU];
+            const double F = -u[GNA] * m3 * h * (V - u[ENA]) - u[GK] * n4 * (V - u[EK]) - u[GL] * (V - u[EL]) +
+                             Ia * sin(ph) + u[GC] * cpl;
+            const double wv = w[4 * i] / u[C];
+            g[C] -= wv * F / u[C];
+            g[GNA] -= wv * m3 * h * (V - u[ENA]);
+            g[ENA] += wv * u[GNA] * m3 * h;
+            g[GK] -= wv * n4 * (V - u[EK]);
+            g[EK] += wv * u[GK] * n4;
+            g[GL] -= wv * (V - u[EL]);
+            g[EL] += wv * u[GL];
+            g[GC] += wv * cpl;
+            g[TP] += wv * Ia * cos(ph) * (-ph / u[TP]);
+            gp[15 * NU] += wv * sin(ph);
+            g[MINF] += w[4 * i + 1] / u[TM];
+            g[TM] -= w[4 * i + 1] * (u[MINF] - m) / (u[TM] * u[TM]);
+            g[HINF] += w[4 * i + 2] / u[TH];
+            g[TH] -= w[4 * i + 2] * (u[HINF] - h) / (u[TH] * u[TH]);
+            g[NINF] += w[4 * i + 3] / u[TN];
+            g[TN] -= w[4 * i + 3] * (u[NINF] - n) / (u[TN] * u[TN]);
+        }
+    }
+};
+
 // A model whose state Jacobian comes from forward-mode automatic
 // differentiation of its right-hand side (one evaluation on duals seeded with
 // the unit vectors) instead of the hand-written one; the rate and the

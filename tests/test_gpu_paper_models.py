@@ -124,3 +124,36 @@ def test_chaboche_more_backstresses(tvi, nu):
         assert torch.equal(a1[0], a2[0]) and torch.equal(a1[1], a2[1]), C
         assert grad_err(host(a1[0]), op) <= 1e-10, (C, grad_err(host(a1[0]), op))
         assert np.abs(host(a1[1]) - oy0).max() <= 1e-10 * np.abs(oy0).max(), C
+
+
+def test_two_coupled_neurons(tvi):
+    """Two neurons (n = 8, coupled through g_C) at one step per lane: rates and
+    Jacobians, and the paper-grid chunks up to 64, forward and adjoint."""
+    w = W.neuron(2, 10)
+    rng = np.random.default_rng(19)
+    M = 200
+    p = w["params"][rng.integers(0, 10, size=M)].copy()
+    p[:, :30] *= np.exp(0.2 * rng.standard_normal((M, 30)))  # distinct neurons, noticeable coupling
+    y = rng.uniform(0.0, 1.0, (M, 8))
+    t = rng.uniform(0.0, 10.0, M)
+    f, J = tvi.model_eval("neuron", dev(y), dev(p), times=dev(t))
+    f, J = host(f), host(J)
+    for q in range(M):
+        fo, Jo = oracle.rhs("neuron", y[q], t[q], p[q])
+        np.testing.assert_allclose(f[q], fo, rtol=1e-12, atol=1e-13 * max(1.0, np.abs(fo).max()))
+        np.testing.assert_allclose(J[q], Jo, rtol=1e-12, atol=1e-13 * max(1.0, np.abs(Jo).max()))
+    yo, so, _ = oracle.forward("neuron", w["y0"], w["times"], w["params"], tol=PARITY_TOL)
+    assert (so == 0).all()
+    g = yo / np.sqrt(np.sum(yo ** 2))
+    op, oy0, _ = oracle.adjoint("neuron", yo, w["times"], w["params"], g)
+    for C in (1, 3, 10, 30, 64):
+        kw = dict(chunk=C, lanes=max(4, 1 << (C - 1).bit_length()) if C > 1 else 1, steps_per_lane=1, tol=PARITY_TOL)
+        y, st, _, ck = tvi.solve_forward("neuron", dev(w["y0"]), dev(w["times"]), dev(w["params"]),
+                                         checkpoints=True, **kw)
+        assert (host(st) == 0).all(), C
+        assert series_rel_err(host(y), yo).max() <= 1e-10, C
+        a1 = tvi.solve_adjoint("neuron", dev(w["times"]), dev(w["params"]), dev(g), y=y, **kw)
+        a2 = tvi.solve_adjoint("neuron", dev(w["times"]), dev(w["params"]), dev(g), ckpt=ck, **kw)
+        assert torch.equal(a1[0], a2[0]) and torch.equal(a1[1], a2[1]), C
+        assert grad_err(host(a1[0]), op) <= 1e-10, (C, grad_err(host(a1[0]), op))
+        assert np.abs(host(a1[1]) - oy0).max() <= 1e-10 * np.abs(oy0).max(), C
