@@ -712,11 +712,13 @@ def main():
         step()
     torch.cuda.synchronize()
     log("timing %d steps" % args.steps)
+    torch.cuda.reset_peak_memory_stats()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         _, status, iters, _ = step()
     torch.cuda.synchronize()
     ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    peak_mem = torch.cuda.max_memory_allocated()  # every device buffer is the caller's (torch)
     value = B * N / (ms_per_step * 1e-3)
     st = status.cpu().numpy()
     it = iters.cpu().numpy()
@@ -743,6 +745,7 @@ def main():
                                   "tol_a=1e-8 tol_r=1e-6", "chunk": C, "lanes": S, "steps_per_lane": T,
                       "init": init, "series_failed": int((st != 0).sum()),
                       "newton_iters_per_series": float(it.mean()), "newton_iters_max": int(it.max())},
+           "peak_device_memory_bytes": int(peak_mem),
            "roofline": roofline, "autotune": tuned["table"]}
 
     ctx = dict(dev=dev, stream=stream, y0=y0, times=times, mu=mu, y_out=y_out, B=B, N=N, C=C, S=S, T=T, init=init,
