@@ -452,20 +452,22 @@ def run_forward_ad(ctx, steps):
     res["vanderpol"] = pair(lambda jac: lambda: tvi.solve_forward(
         "vanderpol", ctx["y0"], ctx["times"], ctx["mu"], chunk=ctx["C"], lanes=ctx["S"], steps_per_lane=ctx["T"],
         tol=TIMING_TOL, init=ctx["init"], y_out=ctx["y_out"], iters=False, jacobian=jac), max(3, steps // 2))
+    # inputs resident on the device before the timed launches
     w = workloads.linear(B=512, N=5000, n=4, seed=114)
     yl = torch.empty((512, 5001, 4), dtype=torch.float64, device=dev)
+    la = (d(w["y0"]), d(w["times"]), d(w["params"]))
     res["linear_n4"] = pair(lambda jac: lambda: tvi.solve_forward(
-        "linear", d(w["y0"]), d(w["times"]), d(w["params"]), chunk=64, tol=TIMING_TOL, y_out=yl, iters=False,
-        jacobian=jac), 5)
-    del yl
+        "linear", *la, chunk=64, tol=TIMING_TOL, y_out=yl, iters=False, jacobian=jac), 5)
+    del yl, la
     w = workloads.robertson()
     off = torch.as_tensor(w["offsets"], device=dev)
     order = tvi.order_longest_first(off)
     yr = torch.empty((w["times"].shape[0], 3), dtype=torch.float64, device=dev)
+    ra = (d(w["y0"]), d(w["times"]), d(w["params"]))
     res["robertson"] = pair(lambda jac: lambda: tvi.solve_forward(
-        "robertson", d(w["y0"]), d(w["times"]), d(w["params"]), offsets=off, chunk=256, lanes=64, steps_per_lane=4,
-        tol=TIMING_TOL, y_out=yr, iters=False, order=order, jacobian=jac), 3)
-    del yr
+        "robertson", *ra, offsets=off, chunk=256, lanes=64, steps_per_lane=4, tol=TIMING_TOL, y_out=yr,
+        iters=False, order=order, jacobian=jac), 3)
+    del yr, ra
     for kind, nu in (("chaboche", 2), ("neuron", 1)):
         w = getattr(workloads, kind)(nu, 50)
         row = {}
