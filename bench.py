@@ -466,7 +466,7 @@ def run_forward_ad(ctx, steps):
     ra = (d(w["y0"]), d(w["times"]), d(w["params"]))
     res["robertson"] = pair(lambda jac: lambda: tvi.solve_forward(
         "robertson", *ra, offsets=off, chunk=256, lanes=64, steps_per_lane=4, tol=TIMING_TOL, y_out=yr,
-        iters=False, order=order, jacobian=jac), 3)
+        iters=False, order=order, jacobian=jac, n_max=int(w["steps"].max())), 3)
     del yr, ra
     for kind, nu in (("chaboche", 2), ("neuron", 1)):
         w = getattr(workloads, kind)(nu, 50)
@@ -500,7 +500,8 @@ def run_robertson(ctx, steps):
     order = tvi.order_longest_first(off)  # ragged series launch longest first
     tune = lambda adjoint: autotune.tune_forward("robertson", y0, times, sp, offsets=off, tol=TIMING_TOL,
                                                  y_out=y_out, use_cache=False, chunks=(16, 32, 64, 128, 256),
-                                                 inits=("zero", "extrap"), adjoint=adjoint, order=order)["best"]
+                                                 inits=("zero", "extrap"), adjoint=adjoint, order=order,
+                                                 n_max=int(w["steps"].max()))["best"]
     res = {"workload": "robertson n=3 B=2000 ragged N_b=exp U(ln 100, ln 2e4) log-spaced t=[1e-5,1e4] f64 "
                        "fwd+adjoint (Frobenius loss), one captured graph, series launched longest first",
            "series_steps": total}
@@ -517,11 +518,12 @@ def run_robertson(ctx, steps):
     res["value"] = res["recompute"]["value"]
     res["unit"] = "series*steps/s"
     b = tune(None)
+    nmax = int(w["steps"].max())
     fwd = lambda: tvi.solve_forward("robertson", y0, times, sp, offsets=off, chunk=b["chunk"], lanes=b["lanes"],
                                     steps_per_lane=b["steps_per_lane"], tol=TIMING_TOL, init=b["init"],
-                                    y_out=y_out, iters=False, order=order)
+                                    y_out=y_out, iters=False, order=order, n_max=nmax)
     seq = lambda: tvi.solve_forward("robertson", y0, times, sp, offsets=off, chunk=1, lanes=1, steps_per_lane=1,
-                                    tol=TIMING_TOL, y_out=y_out, iters=False, order=order)
+                                    tol=TIMING_TOL, y_out=y_out, iters=False, order=order, n_max=nmax)
     fms = float(np.mean(time_launches(fwd, 3, ctx["stream"])))
     seq()
     sms = float(np.mean(time_launches(seq, 3, ctx["stream"])))
@@ -615,7 +617,7 @@ def _predictor_robertson(ctx):
     for init in ("zero", "extrap", "predictor"):
         kw = dict(predictor=pred.solver_args(d, net, 3, base=0)) if init == "predictor" else {}
         fn = lambda: tvi.solve_forward("robertson", *args, offsets=eoff, chunk=C, lanes=S, steps_per_lane=T,
-                                       tol=TIMING_TOL, init=init, **kw)
+                                       tol=TIMING_TOL, init=init, n_max=int(ev["steps"].max()), **kw)
         yy, stt, it, _ = fn()
         ms = float(np.mean(time_launches(fn, 3, ctx["stream"])))
         if y_ref is None:

@@ -197,29 +197,33 @@ def pcr_solve(D, r, transpose=False, out=None):
     return x
 
 
-def _geometry(y0, times, offsets):
+def _geometry(y0, times, offsets, n_max=None):
     B, n = y0.shape
     if offsets is None:
         N = times.shape[0] - 1
         return B, n, N, (B, N + 1, n)
     if offsets.shape != (B + 1,):
         raise TviError("offsets must be [B+1] point offsets")
+    if n_max is not None:  # the caller knows the longest series: no device reduction and sync
+        return B, n, int(n_max), (times.shape[0], n)
     N = int((offsets[1:] - offsets[:-1]).max().item()) - 1 if B else 0
     return B, n, N, (times.shape[0], n)
 
 
 def solve_forward(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e-6), max_newton=50, lanes=0,
                   steps_per_lane=0, init="zero", halving=True, checkpoints=False, y_out=None, iters=True,
-                  predictor=None, order=None, scheme="backward_euler", jacobian_reuse=0.0, jacobian="analytic"):
+                  predictor=None, order=None, scheme="backward_euler", jacobian_reuse=0.0, jacobian="analytic",
+                  n_max=None):
     """Chunked backward Euler (or forward Euler, ``scheme="forward_euler"``).  Returns ``(y, status, iters, ckpt)`` (device tensors;
-    ``iters`` and ``ckpt`` may be None).  Asynchronous: nothing is synchronised."""
+    ``iters`` and ``ckpt`` may be None).  Asynchronous: nothing is synchronised, except that ragged series
+    without ``n_max`` (the longest series' step count) read it from ``offsets``."""
     dt = y0.dtype
     y0 = _dev(y0, dt, "y0")
     times = _dev(times, dt, "times")
     params = _dev(params, dt, "params")
     if offsets is not None:
         offsets = _dev(offsets, torch.int64, "offsets")
-    B, n, N, yshape = _geometry(y0, times, offsets)
+    B, n, N, yshape = _geometry(y0, times, offsets, n_max)
     model = Model(KINDS[kind], n, _io_dtype(y0), 1 if params.dim() == 1 else 0, 64)
     opt = make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, halving, predictor, order, scheme,
                        jacobian_reuse, jacobian)
@@ -239,7 +243,7 @@ def solve_forward(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e
 
 def solve_adjoint(kind, times, params, g, y=None, ckpt=None, offsets=None, chunk=64, tol=(1e-8, 1e-6),
                   max_newton=50, lanes=0, steps_per_lane=0, init="zero", halving=True, n=None, predictor=None,
-                  order=None, scheme="backward_euler", jacobian_reuse=0.0, jacobian="analytic"):
+                  order=None, scheme="backward_euler", jacobian_reuse=0.0, jacobian="analytic", n_max=None):
     """Discrete adjoint.  Returns ``(dLdp [B,P], dLdy0 [B,n], status [B])``.
 
     States come from the trajectory ``y`` or, when ``y`` is None, are recomputed
@@ -259,7 +263,7 @@ def solve_adjoint(kind, times, params, g, y=None, ckpt=None, offsets=None, chunk
         N = times.shape[0] - 1
     else:
         B, n = offsets.shape[0] - 1, g.shape[1]
-        N = int((offsets[1:] - offsets[:-1]).max().item()) - 1 if B else 0
+        N = int(n_max) if n_max is not None else (int((offsets[1:] - offsets[:-1]).max().item()) - 1 if B else 0)
     shared = params.dim() == 1
     if not shared and (params.dim() != 2 or params.shape[0] != B):
         raise TviError("parameters must be per series [B, P] or shared [P]")

@@ -609,3 +609,20 @@ def test_jacobian_reuse_linear_every_supported_tiling(tvi):
             ya = tvi.solve_forward("linear", *args, **kw)[0]
             yb = tvi.solve_forward("linear", *args, jacobian_reuse=0.3, **kw)[0]
             assert torch.equal(ya, yb), (C, S, T)
+
+
+def test_ragged_n_max_given_equals_computed(tvi):
+    """Ragged solves with the longest series' step count given (no device
+    reduction) equal those that read it from the offsets, bitwise."""
+    w = W.robertson(B=40, n_range=(50, 900))
+    off = dev(w["offsets"], torch.int64)
+    args = (dev(w["y0"]), dev(w["times"]), dev(w["params"]))
+    kw = dict(offsets=off, chunk=64, tol=PARITY_TOL, checkpoints=True)
+    ya, sa, ia, ca = tvi.solve_forward("robertson", *args, **kw)
+    yb, sb, ib, cb = tvi.solve_forward("robertson", *args, n_max=int(w["steps"].max()), **kw)
+    assert torch.equal(ya, yb) and torch.equal(sa, sb) and torch.equal(ia, ib)
+    g = ya / torch.sqrt((ya ** 2).sum())
+    pa = tvi.solve_adjoint("robertson", args[1], args[2], g, ckpt=ca, offsets=off, chunk=64, tol=PARITY_TOL)
+    pb = tvi.solve_adjoint("robertson", args[1], args[2], g, ckpt=cb, offsets=off, chunk=64, tol=PARITY_TOL,
+                           n_max=int(w["steps"].max()))
+    assert all(torch.equal(a, b) for a, b in zip(pa, pb))
