@@ -679,8 +679,8 @@ def main():
                     help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(series would shard across GPUs; see the design notes)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (series are independent and "
+              "would shard across GPUs, each running the same kernels on its share)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
