@@ -614,16 +614,19 @@ def _predictor_robertson(ctx):
     eoff = torch.as_tensor(ev["offsets"], device=dev)
     args = (d64(ev["y0"]), d64(ev["times"]), d64(ev["params"]))
     y_ref = None
-    for init in ("zero", "extrap", "predictor"):
+    for key in ("zero", "extrap", "predictor", "extrap_zero_reference", "predictor_zero_reference"):
+        init = key.split("_")[0]
         kw = dict(predictor=pred.solver_args(d, net, 3, base=0)) if init == "predictor" else {}
+        if key.endswith("zero_reference"):
+            kw["reference"] = "zero"  # Algorithm 1's n0: a better start may stop sooner
         fn = lambda: tvi.solve_forward("robertson", *args, offsets=eoff, chunk=C, lanes=S, steps_per_lane=T,
                                        tol=TIMING_TOL, init=init, n_max=int(ev["steps"].max()), **kw)
         yy, stt, it, _ = fn()
         ms = float(np.mean(time_launches(fn, 3, ctx["stream"])))
         if y_ref is None:
             y_ref = yy.clone()
-        res[init] = {"newton_corrections": int(it.sum().item()), "newton_corrections_max": int(it.max().item()),
-                     "ms": ms, "failed": int((stt != 0).sum().item())}
+        res[key] = {"newton_corrections": int(it.sum().item()), "newton_corrections_max": int(it.max().item()),
+                    "ms": ms, "failed": int((stt != 0).sum().item())}
     xe, yse, ie, de, se = pred.chunk_samples_ragged(y_ref, args[1], eoff, C)
     pe = pred.corrections_at("robertson", yse, ie, de, args[2][se].contiguous())
     res["initial_iterate_mse"] = {"zero": float((ie ** 2).mean().item()),

@@ -181,13 +181,19 @@ typedef struct {
                                   tilings with (steps_per_lane + log2 lanes) n^2 <= 72
                                   (TVI_EUNSUPPORTED otherwise)                      */
     int32_t jacobian;          /* tvi_jacobian: how the state Jacobian j is formed   */
+    int32_t reference_residual;/* the R0 of the relative test ||R|| <= tol_r ||R0||:
+                                  0: the residual of the attempt's first iterate
+                                  (for the zero start, Algorithm 1's n0); 1: the
+                                  residual at dy = 0 whatever the start (Algorithm
+                                  1's n0 in every case: a better start may stop
+                                  sooner; one more residual evaluation per attempt) */
 } tvi_options;
 
 /* Fills `opt` with the defaults: chunk 64, tol_a 1e-8, tol_r 1e-6 (Section 2.3),
  * max_newton 50, lanes/steps chosen from chunk, TVI_INIT_ZERO, halving on, no
  * predictor (predictor_base 1 once one is given), series in index order,
  * backward Euler, a full Newton correction every iteration, the analytic
- * Jacobian. */
+ * Jacobian, the first iterate's residual as the reference of the relative test. */
 void tvi_default_options(tvi_options *opt);
 
 /* tvi_order_longest_first -- the launch order that solves ragged series

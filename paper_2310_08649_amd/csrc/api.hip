@@ -96,6 +96,7 @@ tvi_status check_options(const tvi_options *o)
     if (o->jacobian_reuse > 0.0 && (o->scheme != TVI_BACKWARD_EULER || o->init == TVI_INIT_PREDICTOR))
         return TVI_EUNSUPPORTED;
     if (o->jacobian != TVI_JACOBIAN_ANALYTIC && o->jacobian != TVI_JACOBIAN_FORWARD_AD) return TVI_EINVAL;
+    if (o->reference_residual != 0 && o->reference_residual != 1) return TVI_EINVAL;
     if (o->jacobian == TVI_JACOBIAN_FORWARD_AD &&
         (o->scheme != TVI_BACKWARD_EULER || o->init == TVI_INIT_PREDICTOR || o->jacobian_reuse > 0.0))
         return TVI_EUNSUPPORTED;
@@ -129,6 +130,7 @@ SolveArgs<IO> make_args(const tvi_model *model, const tvi_options *opt, int64_t 
     a.order = opt->order;
     a.scheme = opt->scheme;
     a.reuse = opt->jacobian_reuse;
+    a.zero_ref = opt->reference_residual;
     return a;
 }
 
@@ -187,6 +189,7 @@ void tvi_default_options(tvi_options *opt)
     opt->scheme = TVI_BACKWARD_EULER;
     opt->jacobian_reuse = 0.0;
     opt->jacobian = TVI_JACOBIAN_ANALYTIC;
+    opt->reference_residual = 0;
 }
 
 const char *tvi_status_str(int32_t s)

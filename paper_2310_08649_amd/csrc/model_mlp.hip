@@ -158,12 +158,13 @@ __device__ __forceinline__ float chunk_residual(MlpShared &S, Acts &A, const dou
 }
 
 // The norm alone, with activations of its own (the caller's are not live here).
+template <bool FE = false>
 __device__ __noinline__ float chunk_residual_norm(MlpShared &S, const double (&ys)[NS], const float (&dy)[NS],
                                                   float hj, bool v)
 {
     Acts A;
     float R[NS];
-    return chunk_residual(S, A, ys, dy, hj, v, R);
+    return chunk_residual<FE>(S, A, ys, dy, hj, v, R);
 }
 
 // The learned predictor's corrections for the chunk starting at (ys, ts) with
@@ -237,7 +238,9 @@ __device__ int mlp_solve(MlpShared &S, const SolveArgs<IO> &a, const IO *t, doub
     int mcur = C, m = 0, it = 0, status = ST_OK, accepted = 0;
     bool start = true, sing = false;
     int64_t ck_next = s / C + 1, ck_at = ck_next * C;  // next nominal boundary: no division in the loop
-    float nrm0 = 0.f, dy[NS], hj = 0.f;
+    float nrm0 = 0.f, nrm_zero = 0.f, dy[NS], hj = 0.f;
+    // the reference of the relative test: the first iterate's residual, or Alg. 1's n0 = ||R(dy = 0)||
+    const bool ref_zero = a.zero_ref != 0 && a.init != INIT_ZERO;
     Acts A;
     while (s < s_end) {
         if (start) {
@@ -281,6 +284,12 @@ __device__ int mlp_solve(MlpShared &S, const SolveArgs<IO> &a, const IO *t, doub
                     ++accepted;
                 }
             }
+            if (ref_zero) {  // block-uniform
+                float z0[NS];
+#pragma unroll
+                for (int k = 0; k < NS; ++k) z0[k] = 0.f;
+                nrm_zero = chunk_residual_norm<FE>(S, ys, z0, hj, v);
+            }
             it = 0;
             sing = false;
             start = false;
@@ -292,7 +301,7 @@ __device__ int mlp_solve(MlpShared &S, const SolveArgs<IO> &a, const IO *t, doub
         const float nrm = chunk_residual<FE>(S, A, ys, dy, hj, v, R);
 
         int act, code = ST_OK;
-        if (it == 0) nrm0 = nrm;
+        if (it == 0) nrm0 = ref_zero ? nrm_zero : nrm;
         if (sing) { act = 2; code = ST_SINGULAR; }
         else if (!finite(nrm)) { act = 2; code = ST_NONFINITE; }
         else if ((double)nrm <= a.tol_a || (double)nrm <= a.tol_r * (double)nrm0) act = 1;

@@ -57,6 +57,7 @@ struct SolveArgs {
     const int32_t *order;      // launch slot -> series (longest first), or null
     int32_t scheme;            // 0 backward Euler, 1 forward Euler (selects the instance)
     double reuse;              // > 0: keep the factorized blocks while ||R|| falls by this factor
+    int32_t zero_ref;          // 1: the relative test measures against ||R(dy = 0)|| (Alg. 1's n0)
 };
 
 template <class IO>
@@ -194,7 +195,8 @@ struct ChunkNewton {
     int64_t ck_at;     // ... and its step (ck_next * C): no division inside the loop
     int m, mcur;       // attempt length and the current limit (halved on failure)
     int it, total;     // corrections in this attempt / in total
-    double nrm0;       // squared residual norm at the attempt's first iterate
+    double nrm0;       // squared residual norm at the attempt's first iterate (or at dy = 0)
+    double nrm_zero;   // squared residual norm of the attempt at dy = 0
     bool active, start, sing;
     int status;
     double dy[T][n];   // Newton iterate Delta y of the owned steps
@@ -310,8 +312,12 @@ struct ChunkNewton {
     // its registers and code would slow every solve).
     template <bool PRED, class IO, class Sink>
     __device__ void run(const Model &model, const IO *t, int C, int max_newton, double tol_a, double tol_r,
-                        int init, bool halving, const Sink &sink, const PredictorRef &pr, double reuse = 0.0)
+                        int init, bool halving, const Sink &sink, const PredictorRef &pr, double reuse = 0.0,
+                        bool zero_ref = false)
     {
+        // the reference of the relative test differs from the first iterate's only for a nonzero start
+        const bool ref_zero = zero_ref && init != INIT_ZERO;
+        nrm_zero = 0.0;
         const double reuse2 = reuse * reuse;
         have_jac = false;
         nrm_prev = 0.0;
@@ -384,7 +390,19 @@ struct ChunkNewton {
                 if (fresh && !(n_pred < n_base)) extrapolate(model, q, pr.base == 0);
               }
             }
+            const bool new_attempt = fresh;
             fresh = false;
+
+            // ---- reference residual of a new attempt at dy = 0 (wave-uniform call)
+            if (ref_zero && wave_any(new_attempt)) {
+                double z0[T][n], Rt[T][n];
+#pragma unroll
+                for (int i = 0; i < T; ++i)
+#pragma unroll
+                    for (int k = 0; k < n; ++k) z0[i][k] = 0.0;
+                const double nz = residual<false>(model, z0, q, Rt);
+                if (new_attempt) nrm_zero = nz;
+            }
 
             // ---- residual of the owned steps and its segment norm
             double R[T][n];  // live within this trip only
@@ -394,7 +412,7 @@ struct ChunkNewton {
             int act = 0; // 1 converged, 2 failed, 3 correct
             int code = ST_OK;
             if (active) {
-                if (it == 0) nrm0 = nrm2;
+                if (it == 0) nrm0 = ref_zero ? nrm_zero : nrm2;
                 if (sing) { act = 2; code = ST_SINGULAR; }
                 else if (!finite(nrm2)) { act = 2; code = ST_NONFINITE; }
                 else if (nrm2 <= tol_a2 || nrm2 <= tol_r2 * nrm0) act = 1;
@@ -631,7 +649,7 @@ __global__ __launch_bounds__(kWave) void forward_kernel(SolveArgs<IO> a)
     cn.active = sv.valid && sv.Nb > 0;
     extern __shared__ float pred_lds[];
     cn.template run<PRED>(model, sv.t, a.chunk, a.max_newton, a.tol_a, a.tol_r, a.init, a.halving != 0, sink,
-           PredictorRef{a.pred, a.pred_hidden, a.pred_steps, a.pred_base, pred_lds}, a.reuse);
+           PredictorRef{a.pred, a.pred_hidden, a.pred_steps, a.pred_base, pred_lds}, a.reuse, a.zero_ref != 0);
     if (sv.valid && q == 0) {
         a.status[sv.b] = cn.status;
         if (a.iters) a.iters[sv.b] = cn.total;
@@ -693,7 +711,8 @@ __global__ __launch_bounds__(kWave) void adjoint_kernel(SolveArgs<IO> a)
             WorkspaceSink<n> wsink{wsb, s};
             extern __shared__ float pred_lds[];
             cn.template run<PRED>(model, sv.t, C, a.max_newton, a.tol_a, a.tol_r, a.init, a.halving != 0, wsink,
-                   PredictorRef{a.pred, a.pred_hidden, a.pred_steps, a.pred_base, pred_lds}, a.reuse);
+                   PredictorRef{a.pred, a.pred_hidden, a.pred_steps, a.pred_base, pred_lds}, a.reuse,
+                   a.zero_ref != 0);
             if (active && cn.status != ST_OK) status = cn.status;
             __syncthreads(); // one wave per block: makes the workspace writes visible to the wave
         }

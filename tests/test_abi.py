@@ -243,3 +243,12 @@ def test_larger_chaboche_one_step_per_lane(lib):
     mb = tvi.Model(tvi.KINDS["chaboche"], 8, tvi.F64, 0, 64)
     assert lib.tvi_solve_forward(ctypes.byref(mb), ctypes.byref(tvi.make_options(chunk=16)), 4, 10, None, f, f, f, f,
                                  None, f, None, None) == -4
+
+
+def test_reference_residual_option_is_checked(lib):
+    from paper_2310_08649_amd import tvi
+    f = _fake()
+    m = tvi.Model(tvi.KINDS["vanderpol"], 2, tvi.F64, 0, 64)
+    assert tvi.make_options().reference_residual == 0
+    o = tvi.make_options(chunk=16, reference=2)
+    assert lib.tvi_solve_forward(ctypes.byref(m), ctypes.byref(o), 4, 10, None, f, f, f, f, None, f, None, None) == -1

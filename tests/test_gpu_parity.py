@@ -626,3 +626,28 @@ def test_ragged_n_max_given_equals_computed(tvi):
     pb = tvi.solve_adjoint("robertson", args[1], args[2], g, ckpt=cb, offsets=off, chunk=64, tol=PARITY_TOL,
                            n_max=int(w["steps"].max()))
     assert all(torch.equal(a, b) for a, b in zip(pa, pb))
+
+
+def test_zero_increment_reference_residual(tvi):
+    """The relative stopping test against ||R(dy = 0)|| (Algorithm 1's n0): the
+    same trajectory at the parity tolerance, no change at all for the zero start,
+    and recomputation in the adjoint stays bitwise.  (Whether a nonzero start
+    then needs fewer corrections depends on whether it is better than zero.)"""
+    w = W.vanderpol(B=64, N=1000, mu_range=(1.0, 30.0))
+    yo, so, _ = oracle.forward("vanderpol", w["y0"], w["times"], w["params"], tol=PARITY_TOL)
+    assert (so == 0).all()
+    args = (dev(w["y0"]), dev(w["times"]), dev(w["params"]))
+    for C, S, T in ((50, 64, 1), (32, 8, 4)):
+        kw = dict(chunk=C, lanes=S, steps_per_lane=T, tol=PARITY_TOL)
+        yz1, _, iz1, _ = tvi.solve_forward("vanderpol", *args, init="zero", **kw)
+        yz0, _, iz0, _ = tvi.solve_forward("vanderpol", *args, init="zero", reference="zero", **kw)
+        assert torch.equal(yz1, yz0) and torch.equal(iz1, iz0)
+        y1, s1, i1, _ = tvi.solve_forward("vanderpol", *args, init="extrap", **kw)
+        y0r, s0r, i0r, ck = tvi.solve_forward("vanderpol", *args, init="extrap", reference="zero", checkpoints=True,
+                                              **kw)
+        assert (host(s0r) == 0).all()
+        assert series_rel_err(host(y0r), yo).max() <= 1e-10, (C, S, T)
+        g = y0r / torch.sqrt((y0r ** 2).sum())
+        a1 = tvi.solve_adjoint("vanderpol", args[1], args[2], g, y=y0r, init="extrap", reference="zero", **kw)
+        a2 = tvi.solve_adjoint("vanderpol", args[1], args[2], g, ckpt=ck, init="extrap", reference="zero", **kw)
+        assert torch.equal(a1[0], a2[0]) and torch.equal(a1[1], a2[1]), (C, S, T)

@@ -121,6 +121,17 @@ def test_trained_predictor_gains_over_extrapolation(mods):
           "%.3e, predictor %.3e" % (its["zero"], its["extrap"], its["predictor"], err_ext, err_pred))
     assert err_pred < 0.5 * err_ext
     assert its["predictor"] <= its["extrap"] < its["zero"]
+    # with Algorithm 1's reference residual (that of dy = 0) a better start may stop sooner
+    its0 = {}
+    for init in ("extrap", "predictor"):
+        kw = dict(predictor=pred.solver_args(d, theta, 8, base=1)) if init == "predictor" else {}
+        yy, st, it, _ = tvi.solve_forward("mlp", *args, chunk=C, tol=tol, init=init, reference="zero", **kw)
+        assert (st.cpu().numpy() == 0).all()
+        rel = np.abs(yy.cpu().numpy() - yo).max() / np.abs(yo).max()
+        assert rel <= 1e-5, (init, rel)
+        its0[init] = int(it.sum().item())
+    print("with the zero-increment reference: extrapolation %d, predictor %d" % (its0["extrap"], its0["predictor"]))
+    assert its0["predictor"] <= its0["extrap"] <= its["extrap"]
 
 
 def _dev64(a):
