@@ -614,7 +614,7 @@ def _predictor_robertson(ctx):
     eoff = torch.as_tensor(ev["offsets"], device=dev)
     args = (d64(ev["y0"]), d64(ev["times"]), d64(ev["params"]))
     y_ref = None
-    for key in ("zero", "extrap", "predictor", "extrap_zero_reference", "predictor_zero_reference"):
+    for key in ("zero", "extrap", "predictor", "extrap_zero_reference"):
         init = key.split("_")[0]
         kw = dict(predictor=pred.solver_args(d, net, 3, base=0)) if init == "predictor" else {}
         if key.endswith("zero_reference"):
@@ -735,7 +735,7 @@ def main():
 
     flops = float(it.sum()) * C * vdp_flops_per_step_iter(C)
     achieved_tflops = flops / (kern_ms * 1e-3) / 1e12
-    kname = "tvi::forward_kernel<tvi::VanDerPol, double, %d, %d, %s, false, false>" % (
+    kname = "tvi::forward_kernel<tvi::VanDerPol, double, %d, %d, %s, false, false, false>" % (
         S, T, "true" if init == "predictor" else "false")
     roofline = {"kernel": kname, "bound": "alu",
                 "achieved": achieved_tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",

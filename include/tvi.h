@@ -186,7 +186,11 @@ typedef struct {
                                   (for the zero start, Algorithm 1's n0); 1: the
                                   residual at dy = 0 whatever the start (Algorithm
                                   1's n0 in every case: a better start may stop
-                                  sooner; one more residual evaluation per attempt) */
+                                  sooner; one more residual evaluation per attempt.
+                                  Analytic models: backward Euler, extrapolated start,
+                                  no Jacobian reuse or AD Jacobian, not the
+                                  one-step-per-lane models (TVI_EUNSUPPORTED
+                                  otherwise); the neural ODE: any start          */
 } tvi_options;
 
 /* Fills `opt` with the defaults: chunk 64, tol_a 1e-8, tol_r 1e-6 (Section 2.3),

@@ -62,6 +62,10 @@ static tvi_status launch_st(int pass, const SolveArgs<IO> &a, hipStream_t stream
     const size_t lds = pred ? (size_t)per_block * (2 * a.pred_hidden + Model::N * S * T) * sizeof(float) : 0;
     // the reuse of factorized blocks (chord steps) keeps T + log2(S) n x n matrices per lane
     constexpr bool kReuse = (T + scan_levels<S>()) * Model::N * Model::N <= 72;
+    // the zero-increment reference of the relative test (matters only for a nonzero start)
+    const bool zref = a.zero_ref != 0 && a.init != INIT_ZERO;
+    // (instances for the plain backward-Euler solver only)
+    if (zref && (!kVar || a.reuse > 0.0 || pred || a.scheme != 0)) return TVI_EUNSUPPORTED;
     if (a.reuse > 0.0) {
         if (!kReuse || !kVar || pred || a.scheme != 0) return TVI_EUNSUPPORTED;
         if constexpr (kReuse && kVar) {
@@ -105,6 +109,13 @@ static tvi_status launch_st(int pass, const SolveArgs<IO> &a, hipStream_t stream
                 break;
             }
         }
+        if constexpr (kVar) {
+            if (zref) {
+                hipLaunchKernelGGL((forward_kernel<Model, IO, S, T, false, false, false, true>), grid, block, 0, stream,
+                                   a);
+                break;
+            }
+        }
         hipLaunchKernelGGL((forward_kernel<Model, IO, S, T, false>), grid, block, 0, stream, a);
         break;
     case PASS_ADJOINT:
@@ -114,6 +125,13 @@ static tvi_status launch_st(int pass, const SolveArgs<IO> &a, hipStream_t stream
         if constexpr (kPred) {
             if (pred) {
                 hipLaunchKernelGGL((adjoint_kernel<Model, IO, S, T, true, true>), grid, block, lds, stream, a);
+                break;
+            }
+        }
+        if constexpr (kVar) {
+            if (zref) {
+                hipLaunchKernelGGL((adjoint_kernel<Model, IO, S, T, true, false, false, false, true>), grid, block, 0,
+                                   stream, a);
                 break;
             }
         }

@@ -310,13 +310,14 @@ struct ChunkNewton {
     // multiple of C restarts the identical sequence of attempts.
     // PRED: this instance carries the learned start (kept out of the others:
     // its registers and code would slow every solve).
-    template <bool PRED, class IO, class Sink>
+    // ZREF: the relative test measures against ||R(dy = 0)|| (instances of their own: the extra
+    // residual evaluation would otherwise sit in every solver's loop)
+    template <bool PRED, bool ZREF, class IO, class Sink>
     __device__ void run(const Model &model, const IO *t, int C, int max_newton, double tol_a, double tol_r,
-                        int init, bool halving, const Sink &sink, const PredictorRef &pr, double reuse = 0.0,
-                        bool zero_ref = false)
+                        int init, bool halving, const Sink &sink, const PredictorRef &pr, double reuse = 0.0)
     {
         // the reference of the relative test differs from the first iterate's only for a nonzero start
-        const bool ref_zero = zero_ref && init != INIT_ZERO;
+        const bool ref_zero = ZREF && init != INIT_ZERO;
         nrm_zero = 0.0;
         const double reuse2 = reuse * reuse;
         have_jac = false;
@@ -394,7 +395,8 @@ struct ChunkNewton {
             fresh = false;
 
             // ---- reference residual of a new attempt at dy = 0 (wave-uniform call)
-            if (ref_zero && wave_any(new_attempt)) {
+            if constexpr (ZREF) {
+              if (ref_zero && wave_any(new_attempt)) {
                 double z0[T][n], Rt[T][n];
 #pragma unroll
                 for (int i = 0; i < T; ++i)
@@ -402,6 +404,7 @@ struct ChunkNewton {
                     for (int k = 0; k < n; ++k) z0[i][k] = 0.0;
                 const double nz = residual<false>(model, z0, q, Rt);
                 if (new_attempt) nrm_zero = nz;
+              }
             }
 
             // ---- residual of the owned steps and its segment norm
@@ -617,7 +620,7 @@ struct ChunkNewton {
 // ---------------------------------------------------------------------------
 // Forward kernel: one segment of S lanes per series, 64 / S series per wave.
 // ---------------------------------------------------------------------------
-template <class Model, class IO, int S, int T, bool PRED, bool FE = false, bool REUSE = false>
+template <class Model, class IO, int S, int T, bool PRED, bool FE = false, bool REUSE = false, bool ZREF = false>
 __global__ __launch_bounds__(kWave) void forward_kernel(SolveArgs<IO> a)
 {
     constexpr int n = Model::N;
@@ -648,8 +651,8 @@ __global__ __launch_bounds__(kWave) void forward_kernel(SolveArgs<IO> a)
     cn.status = ST_OK;
     cn.active = sv.valid && sv.Nb > 0;
     extern __shared__ float pred_lds[];
-    cn.template run<PRED>(model, sv.t, a.chunk, a.max_newton, a.tol_a, a.tol_r, a.init, a.halving != 0, sink,
-           PredictorRef{a.pred, a.pred_hidden, a.pred_steps, a.pred_base, pred_lds}, a.reuse, a.zero_ref != 0);
+    cn.template run<PRED, ZREF>(model, sv.t, a.chunk, a.max_newton, a.tol_a, a.tol_r, a.init, a.halving != 0, sink,
+           PredictorRef{a.pred, a.pred_hidden, a.pred_steps, a.pred_base, pred_lds}, a.reuse);
     if (sv.valid && q == 0) {
         a.status[sv.b] = cn.status;
         if (a.iters) a.iters[sv.b] = cn.total;
@@ -666,7 +669,8 @@ __global__ __launch_bounds__(kWave) void forward_kernel(SolveArgs<IO> a)
 //   lam_k = (I + dt_{k+1} j(y_k))^T lam_{k+1} + g_k,  lam_{N+1} = 0,
 //   dL/dp = sum_k dt_k (dh/dp(y_{k-1}))^T lam_k,  dL/dy0 = g_0 + (I + dt_1 j(y_0))^T lam_1.
 // ---------------------------------------------------------------------------
-template <class Model, class IO, int S, int T, bool RECOMPUTE, bool PRED, bool FE = false, bool REUSE = false>
+template <class Model, class IO, int S, int T, bool RECOMPUTE, bool PRED, bool FE = false, bool REUSE = false,
+          bool ZREF = false>
 __global__ __launch_bounds__(kWave) void adjoint_kernel(SolveArgs<IO> a)
 {
     constexpr int n = Model::N;
@@ -710,9 +714,8 @@ __global__ __launch_bounds__(kWave) void adjoint_kernel(SolveArgs<IO> a)
             for (int k = 0; k < n; ++k) cn.ys[k] = have_ckpt ? a.ckpt[(sv.b * a.K + c) * n + k] : 0.0;
             WorkspaceSink<n> wsink{wsb, s};
             extern __shared__ float pred_lds[];
-            cn.template run<PRED>(model, sv.t, C, a.max_newton, a.tol_a, a.tol_r, a.init, a.halving != 0, wsink,
-                   PredictorRef{a.pred, a.pred_hidden, a.pred_steps, a.pred_base, pred_lds}, a.reuse,
-                   a.zero_ref != 0);
+            cn.template run<PRED, ZREF>(model, sv.t, C, a.max_newton, a.tol_a, a.tol_r, a.init, a.halving != 0,
+                   wsink, PredictorRef{a.pred, a.pred_hidden, a.pred_steps, a.pred_base, pred_lds}, a.reuse);
             if (active && cn.status != ST_OK) status = cn.status;
             __syncthreads(); // one wave per block: makes the workspace writes visible to the wave
         }
