@@ -658,3 +658,25 @@ def test_zero_increment_reference_residual(tvi):
         a1 = tvi.solve_adjoint("vanderpol", args[1], args[2], g, y=y0r, init="extrap", reference="zero", **kw)
         a2 = tvi.solve_adjoint("vanderpol", args[1], args[2], g, ckpt=ck, init="extrap", reference="zero", **kw)
         assert torch.equal(a1[0], a2[0]) and torch.equal(a1[1], a2[1]), (C, S, T)
+
+
+# --------------------------------------------------------------------------
+# PCR with 3x3 and 4x4 blocks: batches larger than one pass of the grid (each
+# wave then walks several systems), partially filled last waves
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [3, 4])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("m,B", [(64, 8192 * 2 + 5), (8, 8192 * 8 + 13), (100, 9000), (3, 9000)])
+def test_pcr_grid_stride(tvi, n, dtype, m, B):
+    rng = np.random.default_rng(300 + 7 * n + m)
+    D = 1.6 * np.eye(n)[None, None] + (0.3 / np.sqrt(n)) * rng.standard_normal((B, m, n, n))
+    r = rng.standard_normal((B, m, n))
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    D, r = D.astype(npdt), r.astype(npdt)
+    for transpose in (False, True):
+        # the oracle's block forward (back) substitution, pinned to the dense solve
+        ref = bb.thomas(D.astype(np.float64), r.astype(np.float64), transpose=transpose)
+        x = host(tvi.pcr_solve(dev(D, dtype), dev(r, dtype), transpose=transpose)).astype(np.float64)
+        err = np.abs(x - ref).max(axis=(1, 2)) / np.abs(ref).max(axis=(1, 2))
+        gate = 1e-12 if dtype == torch.float64 else 1e-5
+        assert err.max() <= gate, (transpose, int(err.argmax()), float(err.max()))
