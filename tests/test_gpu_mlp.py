@@ -80,6 +80,19 @@ def test_mlp_forward_full_size_parity(tvi, mlp_full, chunk):
     assert (host(it) >= -(-10000 // chunk)).all()
 
 
+def test_mlp_forward_chip_filling_batch(tvi):
+    """1024 series x 1000 steps of 1e-4 (the benchmark's chip-filling neural-ODE batch):
+    one workgroup per series, four per CU."""
+    w = W.mlp(B=1024, N=1000, seed=131, t_end=0.1)
+    y0, times, theta = (w[k].astype(np.float32) for k in ("y0", "times", "params"))
+    yo, so, _ = oracle.forward("mlp", y0, times, theta, tol=(1e-12, 1e-12))
+    assert (so == 0).all()
+    y, st, it, _ = tvi.solve_forward("mlp", dev(y0), dev(times), dev(theta), chunk=100, tol=TOL32)
+    assert (host(st) == 0).all()
+    err = series_rel_err(host(y), yo)
+    assert err.max() <= 1e-5, err.max()
+
+
 def test_mlp_forward_extrapolated_start_and_checkpoints(tvi):
     w = W.mlp(B=8, N=1000)
     y0, times, theta = (w[k].astype(np.float32) for k in ("y0", "times", "params"))
