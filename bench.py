@@ -12,8 +12,9 @@ Printed as one JSON line: throughput in series*steps/s, the roofline of the
 dominant kernel, and, beside it, the chunk = 1 sequential GPU solver on the
 same inputs, the same workload with float storage, forward + adjoint in one
 captured graph, the small linear system, the standalone block-bidiagonal
-solve against the HBM roofline, the neural-ODE path (forward + adjoint)
-against the matrix-core peak, the ragged Robertson batch as one captured
+solve against the HBM roofline, the headline kernel on a chip-filling
+batch, the neural-ODE path (forward + adjoint, and a chip-filling forward
+batch) against the matrix-core peak, the ragged Robertson batch as one captured
 graph, the learned chunk predictor against its fallbacks, and the CPU oracle
 timed on the host cores.
 """
