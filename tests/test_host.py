@@ -109,3 +109,68 @@ def test_neuron_workload_is_the_paper_table(nu, nb):
                 lo, hi = g["per_neuron_linspace_over_n_unit"][name]
                 assert row[15 * i + k] == np.linspace(lo, hi, nu)[i], (name, i)
         assert row[15 * nu] == np.linspace(*g["I_a"]["linspace"], nb)[b]
+
+
+# --------------------------------------------------------------------------
+# Benchmark host logic (no GPU): the one-GPU contract, the algorithmic flop
+# count, and the staleness gate on profiler traffic
+# --------------------------------------------------------------------------
+def _bench():
+    import importlib.util
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "bench.py")
+    spec = importlib.util.spec_from_file_location("bench_under_test", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod, path
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    _, path = _bench()
+    r = subprocess.run([sys.executable, path, "--gpus", "2"], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_bench_reduction_levels_and_flop_count():
+    import math
+    b, _ = _bench()
+    for c in range(1, 600):
+        assert b.levels(c) == math.ceil(math.log2(c))
+    # residual, Jacobian, inverse and update, plus one 2x2 affine composition per level
+    assert b.vdp_flops_per_step_iter(50) == 44 + 24 * 6
+    assert b.vdp_flops_per_step_iter(1) == 44
+
+
+def test_bench_traffic_is_reported_only_for_matching_kernel_code(monkeypatch):
+    import json
+    import os
+    b, _ = _bench()
+    with open(os.path.join(b.ROOT, "profiles", "traffic.json")) as f:
+        table = json.load(f)
+    kernel, rec = next(iter(table.items()))
+    monkeypatch.setattr(b, "csrc_hash", lambda: rec["source_hash"])
+    assert b.measured_traffic(kernel) == rec["bytes_per_dispatch"]
+    assert b.measured_traffic("no such kernel") is None
+    monkeypatch.setattr(b, "csrc_hash", lambda: "0" * 16)
+    assert b.measured_traffic(kernel) is None
+
+
+def test_bench_code_hash_ignores_comments_only(tmp_path, monkeypatch):
+    import os
+    import shutil
+    b, _ = _bench()
+    src = os.path.join(b.ROOT, "paper_2310_08649_amd", "csrc")
+    dst = tmp_path / "paper_2310_08649_amd" / "csrc"
+    shutil.copytree(src, dst)
+    h0 = b.csrc_hash()
+    monkeypatch.setattr(b, "ROOT", str(tmp_path))
+    assert b.csrc_hash() == h0
+    f = dst / "pcr.hip"
+    text = f.read_text()
+    f.write_text("// a new comment\n/* and a block\n   comment */\n\n" + text + "\n\n")
+    assert b.csrc_hash() == h0
+    f.write_text(text.replace("kWave", "kWave + 0", 1))
+    assert b.csrc_hash() != h0
