@@ -1,22 +1,26 @@
 #!/usr/bin/env python3
-"""Benchmark of the chunked backward-Euler solver on one MI355X.
+"""Benchmark of the chunked backward-Euler solver and its adjoint on one MI355X.
 
-Headline workload: Van der Pol, n = 2, 512 series x 5000 uniform steps on
-t in [0, 10], mu log-uniform in [1, 1000], y0 ~ U(-2, 2), FP64, the paper's
-tolerances (tol_a 1e-8, tol_r 1e-6), forward integration.  One step of the
-benchmark is one full solve of the workload (every chunk, every Newton
-iteration, inputs resident in HBM).  The chunk length, the lane tiling and
-the initial iterate come from the autotuner (run before timing, untimed).
+Headline workload: the ragged stiff-kinetics batch.  2000 Robertson series
+(n = 3; rate constants 0.04 s1, 3e7 s2, 1e4 s3 with s_i = 10^U(log 0.5, log 2)),
+N_b = round(exp U(ln 100, ln 20000)) log-spaced steps on t in [1e-5, 1e4],
+y0 = (1, 0, 0), FP64, the paper's tolerances (tol_a 1e-8, tol_r 1e-6).  One
+step of the benchmark is one replay of a captured HIP graph holding the whole
+training step: the chunked forward solve, the gradient of the Frobenius loss
+L = sqrt(sum y^2) over every output (the timing loss of Section 5.2), and the
+discrete adjoint (Appendix A) with dL/dp and dL/dy0, series launched longest
+first.  Chunk length, lane tiling, initial iterate and the adjoint's state
+source (stored trajectory or recomputation from checkpoints) come from the
+autotuner, run before timing.  Inputs are resident in HBM.
 
-Printed as one JSON line: throughput in series*steps/s, the roofline of the
-dominant kernel, and, beside it, the chunk = 1 sequential GPU solver on the
-same inputs, the same workload with float storage, forward + adjoint in one
-captured graph, the small linear system, the standalone block-bidiagonal
-solve against the HBM roofline, the headline kernel on a chip-filling
-batch, the neural-ODE path (forward + adjoint, and a chip-filling forward
-batch) against the matrix-core peak, the ragged Robertson batch as one captured
-graph, the learned chunk predictor against its fallbacks, and the CPU oracle
-timed on the host cores.
+The last stdout line is one compact JSON object: throughput in series*steps/s
+(only steps of series whose forward and adjoint both succeeded), the same
+graph at chunk = 1 (the sequential GPU baseline: one lane per series, one
+Newton solve per step), the roofline of the dominant kernel (timed with HIP
+events on its launch stream), and the CPU oracle timed on the host cores.
+Further measurements (Van der Pol, the neural ODE, the standalone
+block-bidiagonal solve, the tiling study, the paper's example problems, the
+learned predictor) run only with --extras FILE and are written to FILE.
 """
 import argparse
 import json
@@ -55,15 +59,43 @@ def vdp_flops_per_step_iter(chunk):
     return 44 + 24 * levels(chunk)
 
 
-def csrc_hash():
-    """Hash of the kernel sources with comments and blank space removed; HBM
-    traffic from profiler counters is reported only while the code still
-    matches the code the counters were taken from."""
+# Robertson (n = 3) per-step flop counts: an affine-map composition
+# (F = Fa + Fb + Fa Fb, z = (I + Fa) zb + za) and the block factorization
+# (inverse and z = -M r) are 2 n^3 + 2 n^2 = 72 each; the residual (rates 8,
+# state 3, residual 9, squared norm 6) 26; the Jacobian and D = I - dt j 24;
+# a replay (I + F) x + z 24; the parameter product (dh/dp)^T w and dt lam 12.
+ROB_LEVEL, ROB_FACT, ROB_RES, ROB_JAC, ROB_REPLAY, ROB_VJP = 72, 72, 26, 24, 24, 12
+
+
+def rob_forward_flops_per_step(S, T):
+    """Algorithmic flops per series-step of one Newton correction of the hybrid
+    PCR/Thomas solve (Section 3.3): residual, Jacobian, factorization, the
+    lane's serial compositions (T - 1 per T steps) and log2(S) reduction levels
+    per lane (shared by its T steps), and the replay when T > 1."""
+    return (ROB_RES + ROB_JAC + ROB_FACT + ROB_LEVEL * ((T - 1) + levels(S)) / T
+            + (ROB_REPLAY if T > 1 else 0))
+
+
+def rob_adjoint_flops_per_step(S, T):
+    """Per series-step of the adjoint (one transposed solve, no Newton loop):
+    Jacobian, factorization, compositions and levels as above, the replay and
+    the parameter product."""
+    return ROB_JAC + ROB_FACT + ROB_LEVEL * ((T - 1) + levels(S)) / T + ROB_REPLAY + ROB_VJP
+
+
+def csrc_hash(files=None):
+    """Hash of kernel sources (comments and blank space removed): all of csrc,
+    or the listed basenames.  HBM traffic from profiler counters is reported
+    only while the sources the kernel is built from still match."""
     import glob
     import hashlib
     import re
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2310_08649_amd", "csrc", "*"))):
+    paths = sorted(glob.glob(os.path.join(ROOT, "paper_2310_08649_amd", "csrc", "*")))
+    if files is not None:
+        want = set(files)
+        paths = [p for p in paths if os.path.basename(p) in want]
+    for p in paths:
         with open(p) as f:
             src = f.read()
         src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
@@ -83,7 +115,7 @@ def measured_traffic(kernel):
             rec = json.load(f).get(kernel)
     except (OSError, ValueError):
         return None
-    if not rec or rec.get("source_hash") != csrc_hash():
+    if not rec or rec.get("source_hash") != csrc_hash(rec.get("sources")):
         return None
     return rec["bytes_per_dispatch"]
 
@@ -106,7 +138,7 @@ def stats(ds):
 
 
 def extra(out, name, fn):
-    """Run one side measurement; a failure is recorded, not fatal to the line."""
+    """Run one side measurement; a failure is recorded, not fatal."""
     log(name)
     t0 = time.perf_counter()
     try:
@@ -118,41 +150,276 @@ def extra(out, name, fn):
 
 
 # ---------------------------------------------------------------------------
-# side measurements
+# headline: ragged Robertson, forward + loss gradient + adjoint, one graph
 # ---------------------------------------------------------------------------
-def run_chunk1(ctx, steps):
+def rob_inputs(dev):
+    import torch
+    from paper_2310_08649_amd import workloads
+    w = workloads.robertson()
+    d = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev)
+    return w, d(w["y0"]), d(w["times"]), d(w["params"]), torch.as_tensor(w["offsets"], device=dev)
+
+
+def kernel_names(S, T, init, recompute):
+    """Demangled names of the solver kernels a Robertson step launches."""
+    pred = "true" if init == "predictor" else "false"
+    fwd = "tvi::forward_kernel<tvi::Robertson, double, %d, %d, %s, false, false>(tvi::SolveArgs<double>)" % (
+        S, T, pred)
+    adj = "tvi::adjoint_kernel<tvi::Robertson, double, %d, %d, %s, %s, false, false>(tvi::SolveArgs<double>)" % (
+        S, T, "true" if recompute else "false", pred if recompute else "false")
+    return fwd, adj
+
+
+def time_stages(cs, reps, stream):
+    """HIP-event durations (ms) of the forward, loss and adjoint launches of a
+    captured step, run eagerly on `stream` (the stream they are launched on)."""
+    import torch
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(reps)]
+    for e in evs:
+        e[0].record(stream)
+        cs.launch_forward()
+        e[1].record(stream)
+        cs.launch_loss()
+        e[2].record(stream)
+        cs.launch_adjoint()
+        e[3].record(stream)
+    torch.cuda.synchronize()
+    return {name: stats([e[i].elapsed_time(e[i + 1]) for e in evs])
+            for i, name in enumerate(("forward", "loss", "adjoint"))}
+
+
+def run_headline(args, dev, stream):
+    import numpy as np
+    import torch
+    from paper_2310_08649_amd import autotune, graph, tvi
+    w, y0, times, sp, off = rob_inputs(dev)
+    B = w["y0"].shape[0]
+    lens = np.asarray(w["steps"], dtype=np.int64)
+    total = int(lens.sum())
+    nmax = int(lens.max())
+    order = tvi.order_longest_first(off)
+
+    # ---- autotune (untimed): chunk, tiling, start, and where the adjoint takes its states
+    if args.config:
+        C, S, T, init, mode = args.config.split(",")
+        best = {"chunk": int(C), "lanes": int(S), "steps_per_lane": int(T), "init": init, "adjoint": mode}
+        table = None
+        log("configuration given: %s" % args.config)
+    else:
+        log("autotuning chunk / tiling / start / adjoint state source")
+        y_out = torch.empty((times.shape[0], 3), dtype=torch.float64, device=dev)
+        cands = []
+        for mode in ("stored", "recompute"):
+            r = autotune.tune_forward("robertson", y0, times, sp, offsets=off, tol=TIMING_TOL, y_out=y_out,
+                                      use_cache=False, chunks=(32, 64, 128, 256, 512), inits=("zero", "extrap"),
+                                      adjoint=mode, order=order, n_max=nmax)
+            for row in r["table"]:
+                cands.append(dict(row, adjoint=mode))
+        del y_out
+        best = min(cands, key=lambda r: (r["failed"], r["ms"]))
+        table = cands
+        log("chosen chunk=%d lanes=%d steps_per_lane=%d init=%s adjoint=%s (%.3f ms)" % (
+            best["chunk"], best["lanes"], best["steps_per_lane"], best["init"], best["adjoint"], best["ms"]))
+    C, S, T, init, mode = best["chunk"], best["lanes"], best["steps_per_lane"], best["init"], best["adjoint"]
+
+    def capture(chunk, lanes, spl, start, recompute):
+        return graph.CapturedStep("robertson", y0, times, sp, offsets=off, chunk=chunk, lanes=lanes,
+                                  steps_per_lane=spl, tol=TIMING_TOL, init=start, loss="frobenius", n_max=nmax,
+                                  recompute=recompute).capture()
+
+    cs = capture(C, S, T, init, mode == "recompute")
+    for _ in range(args.warmup):
+        cs.replay()
+    torch.cuda.synchronize()
+    log("timing %d graph replays" % args.steps)
+    torch.cuda.reset_peak_memory_stats()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        cs.replay()
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    peak_mem = int(torch.cuda.max_memory_allocated())
+    replay = stats(time_launches(cs.replay, args.steps, stream))
+
+    st_f, st_a = cs.status_fwd.cpu().numpy(), cs.status_adj.cpu().numpy()
+    it = cs.iters.cpu().numpy().astype(np.float64)
+    ok = (st_f == 0) & (st_a == 0)
+    good_steps = int(lens[ok].sum())
+    value = good_steps / (ms_per_step * 1e-3)
+
+    # ---- per-kernel durations with HIP events on the launch stream (eager launches of the same step)
+    stages = time_stages(cs, args.steps, stream)
+    fwd_name, adj_name = kernel_names(S, T, init, mode == "recompute")
+    chunks_b = np.maximum(1, (lens + C - 1) // C)
+    fwd_flops = float(np.sum(it * lens / chunks_b)) * rob_forward_flops_per_step(S, T)
+    adj_flops = float(total) * rob_adjoint_flops_per_step(S, T)
+    points = int(times.shape[0])
+    fwd_bytes = points * (3 * 8 + 8)                      # write y, read t
+    adj_bytes = points * (3 * 8 + 3 * 8 + 8) + B * 6 * 8   # read y, g, t; write dL/dp, dL/dy0
+    if mode == "recompute":
+        fwd_bytes += 3 * 8 * int(np.sum(chunks_b + 1))     # checkpoints
+        adj_flops += fwd_flops                             # the adjoint re-solves every chunk
+    loss_bytes = points * 2 * 3 * 8                       # read y, write g
+    kern = {
+        "forward": {"kernel": fwd_name, "flops": fwd_flops, "bytes": fwd_bytes, **stages["forward"]},
+        "adjoint": {"kernel": adj_name, "flops": adj_flops, "bytes": adj_bytes, **stages["adjoint"]},
+    }
+    dom_key = max(kern, key=lambda k: kern[k]["mean_ms"])
+    dom = kern[dom_key]
+    tf = dom["flops"] / (dom["mean_ms"] * 1e-3) / 1e12
+    gbs = dom["bytes"] / (dom["mean_ms"] * 1e-3) / 1e9
+    other = kern["adjoint" if dom_key == "forward" else "forward"]
+    roofline = {"bound": "alu", "achieved": round(tf, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(tf / PEAK_FP64_TFLOPS, 4), "traffic": measured_traffic(dom["kernel"]),
+                "kernel": dom["kernel"], "avg_launch_ms": round(dom["mean_ms"], 4),
+                "algorithmic_flops": dom["flops"], "algorithmic_bytes": dom["bytes"],
+                "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4),
+                "other_kernel": {"kernel": other["kernel"], "avg_launch_ms": round(other["mean_ms"], 4),
+                                 "tflops": round(other["flops"] / (other["mean_ms"] * 1e-3) / 1e12, 3),
+                                 "hbm_gbs": round(other["bytes"] / (other["mean_ms"] * 1e-3) / 1e9, 1)},
+                "loss_ms": round(stages["loss"]["mean_ms"], 4),
+                "loss_hbm_gbs": round(loss_bytes / (stages["loss"]["mean_ms"] * 1e-3) / 1e9, 1)}
+    head = {"value": value, "ms_per_step": ms_per_step, "replay": replay, "config": {
+        "workload": "robertson n=3 B=2000 ragged N_b=round(exp U(ln 100, ln 2e4)) log-spaced t=[1e-5,1e4] "
+                    "y0=(1,0,0) s_i=10^U(log 0.5, log 2) f64 tol=(1e-8,1e-6) fwd + Frobenius-loss gradient + "
+                    "adjoint (dL/dp, dL/dy0) in one captured graph, longest first",
+        "chunk": C, "lanes": S, "steps_per_lane": T, "init": init, "adjoint_states": mode, "series": B,
+        "series_steps": total, "series_failed": int((~ok).sum()), "series_steps_counted": good_steps,
+        "newton_corrections": int(it.sum())}, "roofline": roofline, "peak_device_memory_bytes": peak_mem}
+    del cs
+
+    # ---- the other adjoint state source at the same settings, and the chunk = 1 baseline
+    alt = capture(C, S, T, init, mode != "recompute")
+    alt.replay()
+    a_st = stats(time_launches(alt.replay, max(3, args.steps // 2), stream))
+    a_ok = ((alt.status_fwd == 0) & (alt.status_adj == 0)).cpu().numpy()
+    head["other_adjoint_states"] = {"adjoint_states": "recompute" if mode != "recompute" else "stored",
+                                    "value": int(lens[a_ok].sum()) / (a_st["mean_ms"] * 1e-3),
+                                    "ms_per_step": a_st["mean_ms"]}
+    del alt
+    log("chunk = 1 baseline")
+    seq = capture(1, 1, 1, "zero", False)
+    seq.replay()
+    torch.cuda.synchronize()
+    reps1 = max(3, args.steps // 4)
+    t0 = time.perf_counter()
+    for _ in range(reps1):
+        seq.replay()
+    torch.cuda.synchronize()
+    ms1 = (time.perf_counter() - t0) * 1e3 / reps1
+    s_ok = ((seq.status_fwd == 0) & (seq.status_adj == 0)).cpu().numpy()
+    head["chunk1"] = {"value": int(lens[s_ok].sum()) / (ms1 * 1e-3), "ms_per_step": ms1,
+                      "series_failed": int((~s_ok).sum()), "speedup_of_chunked": ms1 / ms_per_step}
+    del seq
+    if table is not None:
+        head["autotune_best"] = {k: best[k] for k in ("chunk", "lanes", "steps_per_lane", "init", "adjoint",
+                                                       "failed", "ms")}
+        head["autotune_candidates"] = len(table)
+    head["_table"] = table
+    return head, w
+
+
+def subset_ragged(w, idx):
+    """The ragged series idx of workload w as a workload of their own."""
+    import numpy as np
+    off = w["offsets"]
+    pts = [np.arange(off[b], off[b + 1]) for b in idx]
+    lens = np.array([len(p) for p in pts], dtype=np.int64)
+    return {"y0": w["y0"][idx], "params": w["params"][idx], "times": w["times"][np.concatenate(pts)],
+            "offsets": np.concatenate([[0], np.cumsum(lens)]).astype(np.int64), "steps": lens - 1}
+
+
+def run_cpu_baseline(w, target_s=10.0):
+    """The oracle (sequential backward Euler with a dense Newton solve per step,
+    then its discrete adjoint) on the headline workload: the whole batch solved
+    repeatedly for about target_s seconds on every host thread, and one thread
+    on every tenth series."""
+    import numpy as np
+    import oracle
+
+    def once(ww, threads):
+        y, st, _ = oracle.forward("robertson", ww["y0"], ww["times"], ww["params"], offsets=ww["offsets"],
+                                  tol=TIMING_TOL, threads=threads)
+        yy = np.where(np.isfinite(y), y, 0.0)
+        g = yy / np.sqrt(np.sum(yy ** 2))
+        _, _, sa = oracle.adjoint("robertson", yy, ww["times"], ww["params"], g, offsets=ww["offsets"],
+                                  threads=threads)
+        ok = (st == 0) & (sa == 0)
+        return int(np.asarray(ww["steps"])[ok].sum())
+
+    threads = oracle.default_threads()
+    reps, steps, t = 0, 0, 0.0
+    t0 = time.perf_counter()
+    while t < target_s and reps < 1000:
+        steps += once(w, threads)
+        reps += 1
+        t = time.perf_counter() - t0
+    sub = subset_ragged(w, np.arange(0, w["y0"].shape[0], 10))
+    reps1, steps1, t1 = 0, 0, 0.0
+    t0 = time.perf_counter()
+    while t1 < target_s / 2 and reps1 < 100:
+        steps1 += once(sub, 1)
+        reps1 += 1
+        t1 = time.perf_counter() - t0
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": steps / t, "unit": "series*steps/s", "cores": threads, "kind": "oracle",
+            "sample": "the whole headline batch (2000 ragged Robertson series, forward + Frobenius-loss "
+                      "adjoint) solved %d times in %.1f s on %d threads" % (reps, t, threads),
+            "one_core_value": steps1 / t1, "one_core_sample": "every tenth series, %d times in %.1f s" % (reps1, t1),
+            "cpu_model": cpu, "nproc": os.cpu_count()}
+
+
+# ---------------------------------------------------------------------------
+# side measurements (--extras FILE)
+# ---------------------------------------------------------------------------
+def vdp_context(dev, stream, steps):
+    """Van der Pol n = 2, 512 series x 5000 uniform steps on [0, 10],
+    mu = 10^U(0, 3), y0 = U(-2, 2), FP64, forward, autotuned: the context the
+    Van der Pol side measurements share."""
+    import torch
+    from paper_2310_08649_amd import autotune, tvi, workloads
+    w = workloads.vanderpol()
+    B, N = w["y0"].shape[0], w["times"].shape[0] - 1
+    d = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev)
+    y0, times, mu = d(w["y0"]), d(w["times"]), d(w["params"])
+    y_out = torch.empty((B, N + 1, 2), dtype=torch.float64, device=dev)
+    tuned = autotune.tune_forward("vanderpol", y0, times, mu, tol=TIMING_TOL, y_out=y_out, use_cache=False,
+                                  chunks=(10, 16, 32, 50, 64, 100, 128, 200, 256, 500), inits=("zero", "extrap"))
+    b = tuned["best"]
+    C, S, T, init = b["chunk"], b["lanes"], b["steps_per_lane"], b["init"]
+    fn = lambda: tvi.solve_forward("vanderpol", y0, times, mu, chunk=C, lanes=S, steps_per_lane=T, tol=TIMING_TOL,
+                                   y_out=y_out, init=init)
+    _, st, it, _ = fn()
+    kst = stats(time_launches(fn, steps, stream))
+    return dict(dev=dev, stream=stream, y0=y0, times=times, mu=mu, y_out=y_out, B=B, N=N, C=C, S=S, T=T, init=init,
+                ms_per_step=kst["mean_ms"], failed=int((st != 0).sum().item()), iters=it, kst=kst)
+
+
+def run_vanderpol(ctx, steps):
+    """Van der Pol forward (the workload is forward only), its chunk = 1
+    baseline and the FP64 roofline of its kernel."""
     import numpy as np
     from paper_2310_08649_amd import tvi
-    y0, times, mu, y_out, B, N = ctx["y0"], ctx["times"], ctx["mu"], ctx["y_out"], ctx["B"], ctx["N"]
-    seq = lambda: tvi.solve_forward("vanderpol", y0, times, mu, chunk=1, lanes=1, steps_per_lane=1,
-                                    tol=TIMING_TOL, y_out=y_out, iters=False)
+    B, N, C, S, T = ctx["B"], ctx["N"], ctx["C"], ctx["S"], ctx["T"]
+    kms = ctx["kst"]["mean_ms"]
+    flops = float(ctx["iters"].sum().item()) * C * vdp_flops_per_step_iter(C)
+    seq = lambda: tvi.solve_forward("vanderpol", ctx["y0"], ctx["times"], ctx["mu"], chunk=1, lanes=1,
+                                    steps_per_lane=1, tol=TIMING_TOL, y_out=ctx["y_out"], iters=False)
     seq()
-    d = time_launches(seq, max(3, steps // 3), ctx["stream"])
-    ms = float(np.mean(d))
-    return {"value": B * N / (ms * 1e-3), "unit": "series*steps/s", "ms_per_step": ms,
-            "speedup_of_chunked": ms / ctx["ms_per_step"],
-            "note": "same library, chunk 1: one lane per series, one Newton solve per step"}
-
-
-def run_jacobian_reuse(ctx, steps):
-    """The headline workload with chord steps allowed (jacobian_reuse: a correction
-    reuses the previous factorization while the residual keeps falling by that
-    factor), tuned over chunk, start and factor, against the full-Newton headline."""
-    from paper_2310_08649_amd import autotune
-    tuned = autotune.tune_forward("vanderpol", ctx["y0"], ctx["times"], ctx["mu"], tol=TIMING_TOL,
-                                  chunks=(32, 50, 64, 100), inits=("zero", "extrap"), reuses=(0.1, 0.2, 0.3),
-                                  reps=5, y_out=ctx["y_out"], use_cache=False)
-    b = tuned["best"]
-    fast = min((r for r in tuned["table"] if r["failed"] <= ctx["failed"]), key=lambda r: r["ms"], default=None)
-    out = {"fewest_failed": b, "fewest_failed_value": ctx["B"] * ctx["N"] / (b["ms"] * 1e-3),
-           "unit": "series*steps/s", "full_newton_ms": ctx["ms_per_step"], "full_newton_failed": ctx["failed"],
-           "note": "not the headline: chord steps do less arithmetic per correction than the paper's Newton "
-                   "iteration that the roofline counts"}
-    if fast is not None:
-        out["fastest_no_more_failures"] = fast
-        out["fastest_value"] = ctx["B"] * ctx["N"] / (fast["ms"] * 1e-3)
-        out["speedup_over_full_newton"] = ctx["ms_per_step"] / fast["ms"]
-    return out
+    ms1 = float(np.mean(time_launches(seq, max(3, steps // 3), ctx["stream"])))
+    return {"value": B * N / (kms * 1e-3), "unit": "series*steps/s", "ms": kms, "chunk": C, "lanes": S,
+            "steps_per_lane": T, "init": ctx["init"], "failed": ctx["failed"],
+            "achieved_tflops": flops / (kms * 1e-3) / 1e12,
+            "frac_fp64_peak": flops / (kms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+            "chunk1": {"value": B * N / (ms1 * 1e-3), "ms": ms1, "speedup_of_chunked": ms1 / kms}}
 
 
 def run_vdp_fp32(ctx, steps):
@@ -527,57 +794,6 @@ def run_forward_ad(ctx, steps):
     return res
 
 
-def run_robertson(ctx, steps):
-    """2000 ragged Robertson series (100..20000 log-spaced steps), FP64,
-    forward + adjoint (Frobenius loss) as one captured graph, with the
-    adjoint's states recomputed from checkpoints or read from the stored
-    trajectory; chunk, tiling and start autotuned for each pair."""
-    import numpy as np
-    import torch
-    from paper_2310_08649_amd import autotune, graph, tvi, workloads
-    dev = ctx["dev"]
-    w = workloads.robertson()
-    d = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev)
-    y0, times, sp = d(w["y0"]), d(w["times"]), d(w["params"])
-    off = torch.as_tensor(w["offsets"], device=dev)
-    total = int(w["steps"].sum())
-    y_out = torch.empty((times.shape[0], 3), dtype=torch.float64, device=dev)
-    order = tvi.order_longest_first(off)  # ragged series launch longest first
-    tune = lambda adjoint: autotune.tune_forward("robertson", y0, times, sp, offsets=off, tol=TIMING_TOL,
-                                                 y_out=y_out, use_cache=False, chunks=(16, 32, 64, 128, 256),
-                                                 inits=("zero", "extrap"), adjoint=adjoint, order=order,
-                                                 n_max=int(w["steps"].max()))["best"]
-    res = {"workload": "robertson n=3 B=2000 ragged N_b=exp U(ln 100, ln 2e4) log-spaced t=[1e-5,1e4] f64 "
-                       "fwd+adjoint (Frobenius loss), one captured graph, series launched longest first",
-           "series_steps": total}
-    for mode in ("recompute", "stored"):
-        b = tune(mode)
-        cs = graph.CapturedStep("robertson", y0, times, sp, offsets=off, chunk=b["chunk"], lanes=b["lanes"],
-                                steps_per_lane=b["steps_per_lane"], tol=TIMING_TOL, init=b["init"],
-                                loss="frobenius", recompute=mode == "recompute").capture()
-        cs.replay()
-        st = stats(time_launches(cs.replay, max(3, steps // 2), torch.cuda.current_stream()))
-        res[mode] = dict(value=total / (st["mean_ms"] * 1e-3), unit="series*steps/s", **st, tuned=b,
-                         failed=int(((cs.status_fwd != 0) | (cs.status_adj != 0)).sum().item()))
-        del cs
-    res["value"] = res["recompute"]["value"]
-    res["unit"] = "series*steps/s"
-    b = tune(None)
-    nmax = int(w["steps"].max())
-    fwd = lambda: tvi.solve_forward("robertson", y0, times, sp, offsets=off, chunk=b["chunk"], lanes=b["lanes"],
-                                    steps_per_lane=b["steps_per_lane"], tol=TIMING_TOL, init=b["init"],
-                                    y_out=y_out, iters=False, order=order, n_max=nmax)
-    seq = lambda: tvi.solve_forward("robertson", y0, times, sp, offsets=off, chunk=1, lanes=1, steps_per_lane=1,
-                                    tol=TIMING_TOL, y_out=y_out, iters=False, order=order, n_max=nmax)
-    fms = float(np.mean(time_launches(fwd, 3, ctx["stream"])))
-    seq()
-    sms = float(np.mean(time_launches(seq, 3, ctx["stream"])))
-    ctx["rob_tuned"] = b
-    res.update(forward_value=total / (fms * 1e-3), forward_tuned=b, chunk1_forward_value=total / (sms * 1e-3),
-               forward_speedup_over_chunk1=sms / fms)
-    return res
-
-
 def run_predictor(ctx, steps):
     """Learned chunk predictor on the neural ODE: trained on ~1e5 chunks the
     solver computed (500 series x 1e4 steps, chunk 50), evaluated on 256 new
@@ -680,49 +896,18 @@ def _predictor_robertson(ctx):
     return res
 
 
-def run_cpu_baseline(w, target_s=10.0):
-    import oracle
-    B, N = w["y0"].shape[0], w["times"].shape[0] - 1
-    threads = oracle.default_threads()
-    reps, t = 0, 0.0
-    t0 = time.perf_counter()
-    while t < target_s and reps < 5000:
-        oracle.forward("vanderpol", w["y0"], w["times"], w["params"], tol=TIMING_TOL, threads=threads)
-        reps += 1
-        t = time.perf_counter() - t0
-    # one core on a slice of the series
-    sl = slice(0, 64)
-    reps1, t1 = 0, 0.0
-    t0 = time.perf_counter()
-    while t1 < target_s / 4 and reps1 < 500:
-        oracle.forward("vanderpol", w["y0"][sl], w["times"], w["params"][sl], tol=TIMING_TOL, threads=1)
-        reps1 += 1
-        t1 = time.perf_counter() - t0
-    cpu = "unknown"
-    try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    cpu = line.split(":", 1)[1].strip()
-                    break
-    except OSError:
-        pass
-    return {"value": reps * B * N / t, "unit": "series*steps/s", "cores": threads, "kind": "oracle",
-            "sample": "the full workload (512 x 5000, forward) solved %d times in %.1f s, sequential backward "
-                      "Euler with a dense Newton solve per step" % (reps, t),
-            "one_core_value": reps1 * 64 * N / t1, "cpu_model": cpu, "nproc": os.cpu_count()}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--chunk", type=int, default=0, help="0 = autotune")
-    ap.add_argument("--init", default="", help="initial iterate (zero | extrap); empty = autotune")
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="only the headline measurement")
-    ap.add_argument("--only", default="", help="comma-separated side measurements to run")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="",
+                    help="chunk,lanes,steps_per_lane,init,adjoint (stored | recompute): skip the autotuner")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--extras", default="", help="also run the side measurements and write them to this JSON file")
+    ap.add_argument("--only", default="", help="comma-separated side measurements to run (with --extras)")
     ap.add_argument("--probe-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -731,88 +916,40 @@ def main():
               "would shard across GPUs, each running the same kernels on its share)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
-    from paper_2310_08649_amd import autotune, tvi, workloads
+    from paper_2310_08649_amd import tvi
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     tvi.load()
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
-    w = workloads.vanderpol()  # 512 x 5000
-    B, N = w["y0"].shape[0], w["times"].shape[0] - 1
-    d = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev)
-    y0, times, mu = d(w["y0"]), d(w["times"]), d(w["params"])
-    y_out = torch.empty((B, N + 1, 2), dtype=torch.float64, device=dev)
 
-    # ---- autotune chunk length, tiling and initial iterate (untimed)
-    log("autotuning chunk / tiling / initial iterate")
-    tuned = autotune.tune_forward("vanderpol", y0, times, mu, tol=TIMING_TOL, y_out=y_out, use_cache=False,
-                                  chunks=(10, 16, 32, 50, 64, 100, 128, 200, 256, 500) if args.chunk == 0
-                                  else (args.chunk,),
-                                  inits=("zero", "extrap") if not args.init else (args.init,))
-    best = tuned["best"]
-    C, S, T, init = best["chunk"], best["lanes"], best["steps_per_lane"], best["init"]
-    log("chosen chunk=%d lanes=%d steps_per_lane=%d init=%s (%.3f ms)" % (C, S, T, init, best["ms"]))
+    head, w = run_headline(args, dev, stream)
+    table = head.pop("_table")
+    out = compose_line(args, head)
 
-    def step():
-        return tvi.solve_forward("vanderpol", y0, times, mu, chunk=C, lanes=S, steps_per_lane=T, tol=TIMING_TOL,
-                                 y_out=y_out, init=init)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log("timing %d steps" % args.steps)
-    torch.cuda.reset_peak_memory_stats()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        _, status, iters, _ = step()
-    torch.cuda.synchronize()
-    ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
-    peak_mem = torch.cuda.max_memory_allocated()  # every device buffer is the caller's (torch)
-    value = B * N / (ms_per_step * 1e-3)
-    st = status.cpu().numpy()
-    it = iters.cpu().numpy()
-    durs = time_launches(step, args.steps, stream)
-    kst = stats(durs)
-    kern_ms = kst["mean_ms"]
-
-    flops = float(it.sum()) * C * vdp_flops_per_step_iter(C)
-    achieved_tflops = flops / (kern_ms * 1e-3) / 1e12
-    kname = "tvi::forward_kernel<tvi::VanDerPol, double, %d, %d, %s, false, false, false>" % (
-        S, T, "true" if init == "predictor" else "false")
-    roofline = {"kernel": kname, "bound": "alu",
-                "achieved": achieved_tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved_tflops / PEAK_FP64_TFLOPS, "traffic": measured_traffic(kname),
-                "avg_launch_ms": kern_ms, "median_launch_ms": kst["median_ms"], "min_launch_ms": kst["min_ms"],
-                "algorithmic_bytes_per_launch": B * (N + 1) * 2 * 8,
-                "note": "latency-bound: each series is a chain of N/C chunk solves x Newton iterations; "
-                        "the slowest series sets the launch time"}
-
-    out = {"metric": METRIC, "value": value, "unit": "series*steps/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "vanderpol n=2 B=512 N=5000 t=[0,10] mu=10^U(0,3) y0=U(-2,2) forward "
-                                  "tol_a=1e-8 tol_r=1e-6", "chunk": C, "lanes": S, "steps_per_lane": T,
-                      "init": init, "series_failed": int((st != 0).sum()),
-                      "newton_iters_per_series": float(it.mean()), "newton_iters_max": int(it.max())},
-           "peak_device_memory_bytes": int(peak_mem),
-           "roofline": roofline, "autotune": tuned["table"]}
-
-    ctx = dict(dev=dev, stream=stream, y0=y0, times=times, mu=mu, y_out=y_out, B=B, N=N, C=C, S=S, T=T, init=init,
-               ms_per_step=ms_per_step, failed=int((st != 0).sum()))
-    if not args.no_extras:
-        runs = [("chunk1", run_chunk1), ("jacobian_reuse", run_jacobian_reuse), ("fp32", run_vdp_fp32), ("fwd_adjoint", run_vdp_fwd_adjoint),
-                ("linear", run_linear), ("tiling_study", run_tiling_study), ("saturated", run_saturated),
-                ("pcr_roofline", run_pcr),
-                ("mlp", run_mlp), ("robertson", run_robertson), ("predictor", run_predictor),
-                ("forward_euler", run_forward_euler), ("paper_grid", run_paper_grid),
-                ("forward_ad", run_forward_ad)]
+    if args.extras:
+        ext = {"headline_autotune_table": table}
         only = set(filter(None, args.only.split(",")))
+        want = lambda name: not only or name in only
+        ctx = {"dev": dev, "stream": stream}
+        vdp_runs = [("vanderpol", run_vanderpol), ("fp32", run_vdp_fp32), ("fwd_adjoint", run_vdp_fwd_adjoint)]
+        if any(want(n) for n in [r[0] for r in vdp_runs] + ["forward_ad"]):
+            log("Van der Pol context (autotune)")
+            ctx = vdp_context(dev, stream, args.steps)
+        c = head["config"]
+        ctx["rob_tuned"] = {"chunk": c["chunk"], "lanes": c["lanes"], "steps_per_lane": c["steps_per_lane"]}
+        runs = vdp_runs + [("linear", run_linear), ("tiling_study", run_tiling_study),
+                           ("saturated", run_saturated), ("pcr_roofline", run_pcr), ("mlp", run_mlp),
+                           ("predictor", run_predictor), ("forward_euler", run_forward_euler),
+                           ("paper_grid", run_paper_grid), ("forward_ad", run_forward_ad)]
         for name, fn in runs:
-            if not only or name in only:
-                extra(out, name, lambda fn=fn: fn(ctx, args.steps))
+            if want(name):
+                extra(ext, name, lambda fn=fn: fn(ctx, args.steps))
+        with open(args.extras, "w") as f:
+            json.dump(ext, f, indent=1)
+        log("side measurements written to %s" % args.extras)
 
     if args.probe_copy:
         src = torch.ones(1 << 25, dtype=torch.float64, device=dev)
@@ -826,7 +963,21 @@ def main():
         log("CPU oracle on the host cores")
         out["cpu_baseline"] = run_cpu_baseline(w)
 
-    print(json.dumps(out), flush=True)
+    print(json.dumps(out, separators=(",", ":")), flush=True)
+
+
+def compose_line(args, head):
+    """The benchmark's JSON line (printed last, compact) from the headline results."""
+    out = {"metric": METRIC, "value": head["value"], "unit": "series*steps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": head["config"],
+           "speedup_vs_chunk1": head["chunk1"]["speedup_of_chunked"], "chunk1": head["chunk1"],
+           "other_adjoint_states": head["other_adjoint_states"], "replay_event_ms": head["replay"],
+           "roofline": head["roofline"], "peak_device_memory_bytes": head["peak_device_memory_bytes"]}
+    if "autotune_best" in head:
+        out["autotune_best"] = head["autotune_best"]
+        out["autotune_candidates"] = head["autotune_candidates"]
+    return out
 
 
 if __name__ == "__main__":

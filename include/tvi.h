@@ -59,7 +59,7 @@
  *                  computed in float on MFMA (bf16x3 products for h)
  *   TVI_CHABOCHE   Chaboche viscoplasticity (Section 5.1.1), n = 2 + nu with nu = 1..5
  *                  backstresses (nu >= 3: one step per lane, backward Euler, analytic
- *                  Jacobian, no learned start or Jacobian reuse; TVI_EUNSUPPORTED otherwise): state (sigma, K, X_1..X_nu), s = sigma - sum X,
+ *                  Jacobian, no learned start; TVI_EUNSUPPORTED otherwise): state (sigma, K, X_1..X_nu), s = sigma - sum X,
  *                  a = (|s| - K - sigma0)/eta, ep = <a>^n sign(s),
  *                  h = (E (edot(t) - ep), tau (K_inf - K) |ep|, 2/3 C_i ep - gamma_i X_i |ep|),
  *                  edot(t) = edot_a sin(2 pi t / T),
@@ -135,7 +135,7 @@ typedef enum {
     TVI_JACOBIAN_FORWARD_AD = 1 /* forward-mode automatic differentiation of h (Section 2.2, the forward
                                    AD option): one evaluation of h on dual numbers seeded with the unit
                                    vectors gives j in registers.  Analytic models with TVI_F64 storage,
-                                   backward Euler, zero or extrapolated start, no Jacobian reuse
+                                   backward Euler, zero or extrapolated start
                                    (TVI_EUNSUPPORTED otherwise)                                        */
 } tvi_jacobian;
 
@@ -170,16 +170,6 @@ typedef struct {
                                   leave their slot idle; repeated entries give
                                   undefined results).  See tvi_order_longest_first */
     int32_t scheme;            /* tvi_scheme                                        */
-    double jacobian_reuse;     /* 0: a full Newton correction every iteration (the
-                                  paper's).  In (0, 1): a correction reuses the
-                                  previous one's inverted blocks and PCR matrices (a
-                                  chord step) while the residual norm has fallen by at
-                                  least this factor since then; otherwise the blocks
-                                  are formed at the current iterate.  The converged
-                                  result meets the same residual test.  Backward Euler,
-                                  analytic models, zero or extrapolated start, and
-                                  tilings with (steps_per_lane + log2 lanes) n^2 <= 72
-                                  (TVI_EUNSUPPORTED otherwise)                      */
     int32_t jacobian;          /* tvi_jacobian: how the state Jacobian j is formed   */
     int32_t reference_residual;/* the R0 of the relative test ||R|| <= tol_r ||R0||:
                                   0: the residual of the attempt's first iterate
@@ -188,7 +178,7 @@ typedef struct {
                                   1's n0 in every case: a better start may stop
                                   sooner; one more residual evaluation per attempt.
                                   Analytic models: backward Euler, extrapolated start,
-                                  no Jacobian reuse or AD Jacobian, not the
+                                  no AD Jacobian, not the
                                   one-step-per-lane models (TVI_EUNSUPPORTED
                                   otherwise); the neural ODE: any start          */
 } tvi_options;
@@ -196,8 +186,7 @@ typedef struct {
 /* Fills `opt` with the defaults: chunk 64, tol_a 1e-8, tol_r 1e-6 (Section 2.3),
  * max_newton 50, lanes/steps chosen from chunk, TVI_INIT_ZERO, halving on, no
  * predictor (predictor_base 1 once one is given), series in index order,
- * backward Euler, a full Newton correction every iteration, the analytic
- * Jacobian, the first iterate's residual as the reference of the relative test. */
+ * backward Euler, the analytic Jacobian, the first iterate's residual as the reference of the relative test. */
 void tvi_default_options(tvi_options *opt);
 
 /* tvi_order_longest_first -- the launch order that solves ragged series

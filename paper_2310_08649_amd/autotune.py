@@ -35,10 +35,35 @@ def tilings(chunk):
     return out
 
 
+def source_hash():
+    """Hash of the library's kernel sources (comments and blank space removed):
+    a tuning made for other kernel code is not reused."""
+    import glob
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    here = os.path.dirname(os.path.abspath(__file__))
+    for p in sorted(glob.glob(os.path.join(here, "csrc", "*"))):
+        with open(p) as f:
+            src = f.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(os.path.basename(p).encode())
+        h.update(" ".join(src.split()).encode())
+    return h.hexdigest()[:16]
+
+
 def _key(kind, y0, times, offsets, extra=""):
+    """Problem signature: model, size, dtype, batch, steps, device, the ragged
+    lengths (a hash of the offsets), the kernel sources and the caller's options."""
+    import hashlib
     dev = torch.cuda.get_device_name(y0.device)
     N = times.shape[0] - 1 if offsets is None else int(times.shape[0] - y0.shape[0])
-    return "%s|n=%d|%s|B=%d|N=%d|%s|%s" % (kind, y0.shape[1], str(y0.dtype), y0.shape[0], N, dev, extra)
+    lens = "uniform"
+    if offsets is not None:
+        lens = hashlib.sha256(offsets.detach().cpu().numpy().tobytes()).hexdigest()[:16]
+    return "%s|n=%d|%s|B=%d|N=%d|%s|lens=%s|src=%s|%s" % (kind, y0.shape[1], str(y0.dtype), y0.shape[0], N, dev,
+                                                        lens, source_hash(), extra)
 
 
 def _load_cache():
@@ -74,20 +99,21 @@ def _time(fn, reps):
 
 
 def tune_forward(kind, y0, times, params, offsets=None, tol=(1e-8, 1e-6), chunks=(10, 50, 100, 200, 500),
-                 reps=3, y_out=None, use_cache=True, inits=("zero",), adjoint=None, reuses=(0.0,), **kw):
-    """Returns {"best": {chunk, lanes, steps_per_lane, init, jacobian_reuse, failed, ms}, "table": [...]}.
+                 reps=3, y_out=None, use_cache=True, inits=("zero",), adjoint=None, **kw):
+    """Returns {"best": {chunk, lanes, steps_per_lane, init, failed, ms}, "table": [...]}.
 
-    ``reuses``: Jacobian-reuse factors to try (0: full Newton); a factor that
-    the tiling does not support is skipped.
-
-    Candidates are ranked by the number of series that failed to converge,
-    then by time: a faster configuration never wins by giving up on series.
-    With ``adjoint="stored"`` or ``"recompute"`` each candidate is timed as a
+    Candidates are ranked by the number of series that failed to converge
+    (forward, or forward or adjoint when the adjoint is timed), then by time:
+    a faster configuration never wins by giving up on series.  With
+    ``adjoint="stored"`` or ``"recompute"`` each candidate is timed as a
     forward solve followed by the adjoint (Frobenius-loss gradient, states
     read from the trajectory or recomputed from checkpoints): the tiling that
-    suits the forward pass alone need not suit the pair."""
-    key = _key(kind, y0, times, offsets, "tol=%g,%g|chunks=%s|inits=%s|adjoint=%s|reuses=%s"
-               % (tol[0], tol[1], ",".join(map(str, chunks)), ",".join(inits), adjoint, ",".join(map(str, reuses))))
+    suits the forward pass alone need not suit the pair.  Further keyword
+    options (scheme, jacobian, order, max_newton, n_max, ...) are passed to
+    both solves and are part of the cache key."""
+    opts = ",".join("%s=%s" % (k, "tensor" if isinstance(v, torch.Tensor) else v) for k, v in sorted(kw.items()))
+    key = _key(kind, y0, times, offsets, "tol=%g,%g|chunks=%s|inits=%s|adjoint=%s|%s"
+               % (tol[0], tol[1], ",".join(map(str, chunks)), ",".join(inits), adjoint, opts))
     if use_cache:
         with _lock:
             hit = _load_cache().get(key)
@@ -96,30 +122,27 @@ def tune_forward(kind, y0, times, params, offsets=None, tol=(1e-8, 1e-6), chunks
     table = []
     for C in chunks:
         for S, T in tilings(C):
-            for init, reuse in [(i, r) for i in inits for r in reuses]:
+            for init in inits:
                 res = {}
 
                 def fn():
                     y, st, _, ck = tvi.solve_forward(kind, y0, times, params, offsets=offsets, chunk=C, lanes=S,
                                                      steps_per_lane=T, tol=tol, y_out=y_out, init=init,
-                                                     iters=False, checkpoints=adjoint == "recompute",
-                                                     jacobian_reuse=reuse, **kw)
+                                                     iters=False, checkpoints=adjoint == "recompute", **kw)
                     res["st"] = st
                     if adjoint:
                         g = y if "g" not in res else res["g"]
                         res["g"] = g
                         src = dict(ckpt=ck) if adjoint == "recompute" else dict(y=y)
-                        tvi.solve_adjoint(kind, times, params, g, offsets=offsets, chunk=C, lanes=S,
-                                          steps_per_lane=T, tol=tol, init=init, jacobian_reuse=reuse, **src, **kw)
-                try:
-                    ms = _time(fn, reps)
-                except tvi.TviError:
-                    if reuse > 0.0:
-                        continue  # this tiling keeps too many matrices per lane for reuse
-                    raise
-                failed = int((res["st"] != 0).sum().item())
-                table.append({"chunk": C, "lanes": S, "steps_per_lane": T, "init": init, "jacobian_reuse": reuse,
-                              "failed": failed, "ms": ms})
+                        _, _, sa = tvi.solve_adjoint(kind, times, params, g, offsets=offsets, chunk=C, lanes=S,
+                                                     steps_per_lane=T, tol=tol, init=init, **src, **kw)
+                        res["sa"] = sa
+                ms = _time(fn, reps)
+                bad = res["st"] != 0
+                if adjoint:
+                    bad = bad | (res["sa"] != 0)
+                table.append({"chunk": C, "lanes": S, "steps_per_lane": T, "init": init,
+                              "failed": int(bad.sum().item()), "ms": ms})
     best = min(table, key=lambda r: (r["failed"], r["ms"]))
     res = {"best": best, "table": table}
     if use_cache:

@@ -92,13 +92,10 @@ tvi_status check_options(const tvi_options *o)
         return TVI_EINVAL;
     if (o->scheme != TVI_BACKWARD_EULER && o->scheme != TVI_FORWARD_EULER) return TVI_EINVAL;
     if (o->scheme == TVI_FORWARD_EULER && o->init == TVI_INIT_PREDICTOR) return TVI_EUNSUPPORTED;
-    if (!(o->jacobian_reuse >= 0.0 && o->jacobian_reuse < 1.0)) return TVI_EINVAL;
-    if (o->jacobian_reuse > 0.0 && (o->scheme != TVI_BACKWARD_EULER || o->init == TVI_INIT_PREDICTOR))
-        return TVI_EUNSUPPORTED;
     if (o->jacobian != TVI_JACOBIAN_ANALYTIC && o->jacobian != TVI_JACOBIAN_FORWARD_AD) return TVI_EINVAL;
     if (o->reference_residual != 0 && o->reference_residual != 1) return TVI_EINVAL;
     if (o->jacobian == TVI_JACOBIAN_FORWARD_AD &&
-        (o->scheme != TVI_BACKWARD_EULER || o->init == TVI_INIT_PREDICTOR || o->jacobian_reuse > 0.0))
+        (o->scheme != TVI_BACKWARD_EULER || o->init == TVI_INIT_PREDICTOR))
         return TVI_EUNSUPPORTED;
     return TVI_OK;
 }
@@ -129,7 +126,6 @@ SolveArgs<IO> make_args(const tvi_model *model, const tvi_options *opt, int64_t 
     a.pred_base = opt->predictor_base;
     a.order = opt->order;
     a.scheme = opt->scheme;
-    a.reuse = opt->jacobian_reuse;
     a.zero_ref = opt->reference_residual;
     return a;
 }
@@ -187,7 +183,6 @@ void tvi_default_options(tvi_options *opt)
     opt->predictor_base = 1;
     opt->order = nullptr;
     opt->scheme = TVI_BACKWARD_EULER;
-    opt->jacobian_reuse = 0.0;
     opt->jacobian = TVI_JACOBIAN_ANALYTIC;
     opt->reference_residual = 0;
 }
@@ -253,7 +248,7 @@ tvi_status tvi_solve_forward(const tvi_model *model, const tvi_options *opt, int
     if (!times || !y0 || !params || !status || (!y_out && !ckpt)) return TVI_EINVAL;
     int S = 0, T = 0;
     if (model->kind == TVI_MLP) {
-        if (opt->chunk > 128 || opt->jacobian_reuse > 0.0 || opt->jacobian != TVI_JACOBIAN_ANALYTIC)
+        if (opt->chunk > 128 || opt->jacobian != TVI_JACOBIAN_ANALYTIC)
             return TVI_EUNSUPPORTED;
     } else if ((e = resolve_tiling(opt, S, T)) != TVI_OK) {
         return e;
@@ -303,7 +298,7 @@ tvi_status tvi_solve_adjoint(const tvi_model *model, const tvi_options *opt, int
         (!workspace || workspace_bytes < tvi_adjoint_workspace_bytes(model, opt, B)))
         return TVI_EINVAL;
     if (mlp) {
-        if (opt->chunk > 128 || opt->jacobian_reuse > 0.0 || opt->jacobian != TVI_JACOBIAN_ANALYTIC)
+        if (opt->chunk > 128 || opt->jacobian != TVI_JACOBIAN_ANALYTIC)
             return TVI_EUNSUPPORTED;
         const int pass = recompute ? PASS_ADJOINT_RECOMPUTE : PASS_ADJOINT;
         const hipStream_t st = static_cast<hipStream_t>(stream);

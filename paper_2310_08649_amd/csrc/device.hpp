@@ -408,34 +408,6 @@ __device__ __forceinline__ void scan_level(AffineI<N, R> &a, int q)
 template <int S>
 constexpr int scan_levels() { return S >= 64 ? 6 : S >= 32 ? 5 : S >= 16 ? 4 : S >= 8 ? 3 : S >= 4 ? 2 : S >= 2 ? 1 : 0; }
 
-// The lane's own F before each level of a segment scan, kept so that a later
-// scan with the same matrices composes only the offsets.
-template <int N, int S, class R>
-struct ScanRecord {
-    R F[scan_levels<S>() > 0 ? scan_levels<S>() : 1][N][N];
-};
-
-template <int N, class R>
-__device__ __forceinline__ void copy_mat(const R (&a)[N][N], R (&b)[N][N])
-{
-#pragma unroll
-    for (int i = 0; i < N; ++i)
-#pragma unroll
-        for (int k = 0; k < N; ++k) b[i][k] = a[i][k];
-}
-
-// Offsets only: z <- (I + F_q) z_partner + z with the recorded F_q of the level.
-template <int CTRL, int ROWS, int N, class R>
-__device__ __forceinline__ void z_level(R (&z)[N], const R (&F)[N][N], bool keep)
-{
-    R o[N];
-#pragma unroll
-    for (int i = 0; i < N; ++i) o[i] = dpp_zero<CTRL, ROWS>(z[i]);
-#pragma unroll
-    for (int i = 0; i < N; ++i) o[i] = keep ? o[i] : R(0);
-    apply_ip(F, o, z, z);
-}
-
 // Inclusive prefix composition over the segment, lowest lane first:
 // lane q ends with A_q o A_{q-1} o ... o A_0.  Row shifts inside 16-lane rows,
 // then the row totals by row broadcasts (rows 1, 3 take lanes 15, 47; rows 2,
@@ -458,73 +430,6 @@ __device__ __forceinline__ void seg_scan_up(AffineI<N, R> &a)
         dpp_map<dpp::ROW_BCAST31, 0xC>(a, o);
         affine_after(a, o);
     }
-}
-
-// seg_scan_up that also records the lane's F before each level.
-template <int N, class R>
-__device__ __forceinline__ void copy_mat_if(const R (&a)[N][N], R (&b)[N][N], bool on)
-{
-#pragma unroll
-    for (int i = 0; i < N; ++i)
-#pragma unroll
-        for (int k = 0; k < N; ++k) b[i][k] = on ? a[i][k] : b[i][k];
-}
-
-template <int CTRL, int D, int IDX, int S, int N, class R>
-__device__ __forceinline__ void scan_level_rec(AffineI<N, R> &a, int q, ScanRecord<N, S, R> &r, bool on)
-{
-    constexpr int W = S < 16 ? S : 16;
-    if constexpr (D < W) {
-        copy_mat_if(a.F, r.F[IDX], on);
-        AffineI<N, R> o;
-        dpp_map<CTRL + D, 0xF>(a, o);
-        if constexpr (S < 16) keep_or_identity(o, q >= D);
-        affine_after(a, o);
-    }
-}
-
-// (The record is written only where `on`.)
-template <int N, int S, class R>
-__device__ __forceinline__ void seg_scan_up_rec(AffineI<N, R> &a, ScanRecord<N, S, R> &r, bool on)
-{
-    const int q = lane_id() & (S - 1);
-    scan_level_rec<dpp::ROW_SHR, 1, 0, S>(a, q, r, on);
-    scan_level_rec<dpp::ROW_SHR, 2, 1, S>(a, q, r, on);
-    scan_level_rec<dpp::ROW_SHR, 4, 2, S>(a, q, r, on);
-    scan_level_rec<dpp::ROW_SHR, 8, 3, S>(a, q, r, on);
-    if constexpr (S >= 32) {
-        copy_mat_if(a.F, r.F[4], on);
-        AffineI<N, R> o;
-        dpp_map<dpp::ROW_BCAST15, 0xA>(a, o);
-        affine_after(a, o);
-    }
-    if constexpr (S >= 64) {
-        copy_mat_if(a.F, r.F[5], on);
-        AffineI<N, R> o;
-        dpp_map<dpp::ROW_BCAST31, 0xC>(a, o);
-        affine_after(a, o);
-    }
-}
-
-template <int CTRL, int D, int IDX, int S, int N, class R>
-__device__ __forceinline__ void z_level_row(R (&z)[N], int q, const ScanRecord<N, S, R> &r)
-{
-    constexpr int W = S < 16 ? S : 16;
-    if constexpr (D < W) z_level<CTRL + D, 0xF>(z, r.F[IDX], S < 16 ? (q >= D) : true);
-}
-
-// The offsets of seg_scan_up for maps whose F parts are those recorded: lane q
-// ends with the offset of A_q o ... o A_0.
-template <int N, int S, class R>
-__device__ __forceinline__ void seg_scan_up_z(R (&z)[N], const ScanRecord<N, S, R> &r)
-{
-    const int q = lane_id() & (S - 1);
-    z_level_row<dpp::ROW_SHR, 1, 0, S>(z, q, r);
-    z_level_row<dpp::ROW_SHR, 2, 1, S>(z, q, r);
-    z_level_row<dpp::ROW_SHR, 4, 2, S>(z, q, r);
-    z_level_row<dpp::ROW_SHR, 8, 3, S>(z, q, r);
-    if constexpr (S >= 32) z_level<dpp::ROW_BCAST15, 0xA>(z, r.F[4], true);
-    if constexpr (S >= 64) z_level<dpp::ROW_BCAST31, 0xC>(z, r.F[5], true);
 }
 
 // Inclusive suffix composition, highest lane first:

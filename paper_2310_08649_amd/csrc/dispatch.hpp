@@ -11,7 +11,7 @@ namespace tvi {
 
 enum Pass : int { PASS_FORWARD = 0, PASS_ADJOINT = 1, PASS_ADJOINT_RECOMPUTE = 2 };
 
-// Models with the learned-start, Jacobian-reuse and forward-Euler instances
+// Models with the learned-start and forward-Euler instances
 // (the forward-AD Jacobian variants have the plain backward-Euler ones only).
 template <class M>
 struct Variants {
@@ -60,31 +60,10 @@ static tvi_status launch_st(int pass, const SolveArgs<IO> &a, hipStream_t stream
     if (pred && !kPred && pass != PASS_ADJOINT) return TVI_EUNSUPPORTED;
     // its hidden layers and outputs: [segments][2H + n S T] floats of LDS
     const size_t lds = pred ? (size_t)per_block * (2 * a.pred_hidden + Model::N * S * T) * sizeof(float) : 0;
-    // the reuse of factorized blocks (chord steps) keeps T + log2(S) n x n matrices per lane
-    constexpr bool kReuse = (T + scan_levels<S>()) * Model::N * Model::N <= 72;
     // the zero-increment reference of the relative test (matters only for a nonzero start)
     const bool zref = a.zero_ref != 0 && a.init != INIT_ZERO;
     // (instances for the plain backward-Euler solver only)
-    if (zref && (!kVar || a.reuse > 0.0 || pred || a.scheme != 0)) return TVI_EUNSUPPORTED;
-    if (a.reuse > 0.0) {
-        if (!kReuse || !kVar || pred || a.scheme != 0) return TVI_EUNSUPPORTED;
-        if constexpr (kReuse && kVar) {
-            switch (pass) {
-            case PASS_FORWARD:
-                hipLaunchKernelGGL((forward_kernel<Model, IO, S, T, false, false, true>), grid, block, 0, stream, a);
-                break;
-            case PASS_ADJOINT:  // states read from the trajectory: no Newton iteration to reproduce
-                hipLaunchKernelGGL((adjoint_kernel<Model, IO, S, T, false, false>), grid, block, 0, stream, a);
-                break;
-            case PASS_ADJOINT_RECOMPUTE:
-                hipLaunchKernelGGL((adjoint_kernel<Model, IO, S, T, true, false, false, true>), grid, block, 0, stream,
-                                   a);
-                break;
-            default: return TVI_EINVAL;
-            }
-            return hipGetLastError() == hipSuccess ? TVI_OK : TVI_EHIP;
-        }
-    }
+    if (zref && (!kVar || pred || a.scheme != 0)) return TVI_EUNSUPPORTED;
     if (a.scheme == 1) {  // forward Euler: its own instances, no learned start
         if (pred || !kVar) return TVI_EUNSUPPORTED;
         if constexpr (kVar) switch (pass) {
@@ -111,8 +90,7 @@ static tvi_status launch_st(int pass, const SolveArgs<IO> &a, hipStream_t stream
         }
         if constexpr (kVar) {
             if (zref) {
-                hipLaunchKernelGGL((forward_kernel<Model, IO, S, T, false, false, false, true>), grid, block, 0, stream,
-                                   a);
+                hipLaunchKernelGGL((forward_kernel<Model, IO, S, T, false, false, true>), grid, block, 0, stream, a);
                 break;
             }
         }
@@ -130,8 +108,8 @@ static tvi_status launch_st(int pass, const SolveArgs<IO> &a, hipStream_t stream
         }
         if constexpr (kVar) {
             if (zref) {
-                hipLaunchKernelGGL((adjoint_kernel<Model, IO, S, T, true, false, false, false, true>), grid, block, 0,
-                                   stream, a);
+                hipLaunchKernelGGL((adjoint_kernel<Model, IO, S, T, true, false, false, true>), grid, block, 0, stream,
+                                   a);
                 break;
             }
         }

@@ -56,7 +56,6 @@ struct SolveArgs {
     int32_t pred_hidden, pred_steps, pred_base;
     const int32_t *order;      // launch slot -> series (longest first), or null
     int32_t scheme;            // 0 backward Euler, 1 forward Euler (selects the instance)
-    double reuse;              // > 0: keep the factorized blocks while ||R|| falls by this factor
     int32_t zero_ref;          // 1: the relative test measures against ||R(dy = 0)|| (Alg. 1's n0)
 };
 
@@ -179,11 +178,8 @@ __device__ __forceinline__ void dense_t(const float *__restrict__ Wt, int ld, co
 }
 
 // Per-lane state of the chunked Newton solve of one series (FE: the
-// forward-Euler chunk system instead of the backward-Euler one).  REUSE: a
-// correction may reuse the previous one's inverted blocks and scan matrices
-// (a chord step) while the residual norm keeps falling by the given factor;
-// otherwise the blocks are formed again at the current iterate.
-template <class Model, int S, int T, bool FE = false, bool REUSE = false>
+// forward-Euler chunk system instead of the backward-Euler one).
+template <class Model, int S, int T, bool FE = false>
 struct ChunkNewton {
     static constexpr int n = Model::N;
     static constexpr bool kPredictorT = T * n <= kPredictorMaxTN;  // register budget of the learned start
@@ -202,11 +198,6 @@ struct ChunkNewton {
     double dy[T][n];   // Newton iterate Delta y of the owned steps
     double tt[T], hh[T];
     double t_s, h_s;   // time and first step of the current attempt (predictor features)
-    // REUSE: the last factorization of this attempt (inverted blocks, scan matrices)
-    double Fc[REUSE ? T : 1][n][n];
-    ScanRecord<n, (REUSE ? S : 1), double> rec;
-    bool have_jac;
-    double nrm_prev;   // squared residual norm before the last correction
 
     __device__ __forceinline__ bool owned(int q, int i) const { return active && (q * T + i + 1 <= m); }
 
@@ -314,28 +305,11 @@ struct ChunkNewton {
     // residual evaluation would otherwise sit in every solver's loop)
     template <bool PRED, bool ZREF, class IO, class Sink>
     __device__ void run(const Model &model, const IO *t, int C, int max_newton, double tol_a, double tol_r,
-                        int init, bool halving, const Sink &sink, const PredictorRef &pr, double reuse = 0.0)
+                        int init, bool halving, const Sink &sink, const PredictorRef &pr)
     {
         // the reference of the relative test differs from the first iterate's only for a nonzero start
         const bool ref_zero = ZREF && init != INIT_ZERO;
         nrm_zero = 0.0;
-        const double reuse2 = reuse * reuse;
-        have_jac = false;
-        nrm_prev = 0.0;
-        if constexpr (REUSE) {  // defined values for the lanes a chord scan passes through
-#pragma unroll
-            for (int i = 0; i < T; ++i)
-#pragma unroll
-                for (int r = 0; r < n; ++r)
-#pragma unroll
-                    for (int c = 0; c < n; ++c) Fc[i][r][c] = 0.0;
-#pragma unroll
-            for (int l = 0; l < (int)(sizeof(rec.F) / sizeof(rec.F[0])); ++l)
-#pragma unroll
-                for (int r = 0; r < n; ++r)
-#pragma unroll
-                    for (int c = 0; c < n; ++c) rec.F[l][r][c] = 0.0;
-        }
         const int lane = lane_id();
         const int q = lane & (S - 1);
         const int base = lane - q;
@@ -369,7 +343,6 @@ struct ChunkNewton {
                 extrapolate(model, q, init == INIT_ZERO || (init == INIT_PREDICTOR && pr.base == 0));
                 it = 0;
                 sing = false;
-                have_jac = false;
                 start = false;
                 fresh = true;
             }
@@ -472,58 +445,8 @@ struct ChunkNewton {
             }
 
             // ---- Newton correction: blocks, in-lane composition, PCR, replay
-            // REUSE: each series decides for itself (segment-uniform), so that its
-            // iterates never depend on the other series of its wave; a wave whose
-            // series disagree runs both paths, each updating only its own series
-            bool want = false;
-            if constexpr (REUSE) {
-                want = act == 3 && have_jac && nrm2 <= reuse2 * nrm_prev;
-                if (wave_any(want)) {
-                    const bool corr = want;
-                    double zl[T][n], zacc[n];
-#pragma unroll
-                    for (int k = 0; k < n; ++k) zacc[k] = 0.0;
-#pragma unroll
-                    for (int i = 0; i < T; ++i) {
-                        const bool v = corr && owned(q, i);
-                        double negR[n];
-                        const double zero[n] = {};
-#pragma unroll
-                        for (int k = 0; k < n; ++k) negR[k] = v ? -R[i][k] : 0.0;
-                        apply_ip(Fc[i], negR, zero, zl[i]);
-                        if (v) apply_ip(Fc[i], zacc, zl[i], zacc);
-                    }
-                    seg_scan_up_z<n, S>(zacc, rec);
-                    if constexpr (T == 1) {
-                        if (corr && owned(q, 0)) {
-#pragma unroll
-                            for (int k = 0; k < n; ++k) dy[0][k] += zacc[k];
-                        }
-                    } else {
-                        double din[n];
-                        vec_prev(zacc, din);
-                        if (q == 0) {
-#pragma unroll
-                            for (int k = 0; k < n; ++k) din[k] = 0.0;
-                        }
-#pragma unroll
-                        for (int i = 0; i < T; ++i) {
-                            if (corr && owned(q, i)) {
-                                apply_ip(Fc[i], din, zl[i], din);
-#pragma unroll
-                                for (int k = 0; k < n; ++k) dy[i][k] += din[k];
-                            }
-                        }
-                    }
-                    if (corr) {
-                        nrm_prev = nrm2;
-                        ++it;
-                        ++total;
-                    }
-                }
-            }
-            if (wave_any(act == 3 && !want)) {
-                const bool corr = act == 3 && !want;
+            if (wave_any(act == 3)) {
+                const bool corr = act == 3;
                 double Fi[T][n][n], zi[T][n];
                 AffineI<n, double> map;
                 affine_identity(map);
@@ -573,17 +496,7 @@ struct ChunkNewton {
                         map = step;
                     }
                 }
-                if constexpr (REUSE) {
-#pragma unroll
-                    for (int i = 0; i < T; ++i) copy_mat_if(Fi[i], Fc[i], corr);
-                    seg_scan_up_rec<n, S>(map, rec, corr);
-                    if (corr) {
-                        have_jac = true;
-                        nrm_prev = nrm2;
-                    }
-                } else {
-                    seg_scan_up<n, S>(map);
-                }
+                seg_scan_up<n, S>(map);
                 if constexpr (T == 1) {
                     // the composed map's offset is the solution at the lane's step
                     if (corr && owned(q, 0)) {
@@ -620,7 +533,7 @@ struct ChunkNewton {
 // ---------------------------------------------------------------------------
 // Forward kernel: one segment of S lanes per series, 64 / S series per wave.
 // ---------------------------------------------------------------------------
-template <class Model, class IO, int S, int T, bool PRED, bool FE = false, bool REUSE = false, bool ZREF = false>
+template <class Model, class IO, int S, int T, bool PRED, bool FE = false, bool ZREF = false>
 __global__ __launch_bounds__(kWave) void forward_kernel(SolveArgs<IO> a)
 {
     constexpr int n = Model::N;
@@ -631,7 +544,7 @@ __global__ __launch_bounds__(kWave) void forward_kernel(SolveArgs<IO> a)
     Model model;
     if (sv.valid) model.load(a.params_shared ? a.params : a.params + sv.b * Model::P);
 
-    ChunkNewton<Model, S, T, FE, REUSE> cn;
+    ChunkNewton<Model, S, T, FE> cn;
     if (sv.valid) {
 #pragma unroll
         for (int k = 0; k < n; ++k) cn.ys[k] = ld(a.y0 + sv.b * n + k);
@@ -652,7 +565,7 @@ __global__ __launch_bounds__(kWave) void forward_kernel(SolveArgs<IO> a)
     cn.active = sv.valid && sv.Nb > 0;
     extern __shared__ float pred_lds[];
     cn.template run<PRED, ZREF>(model, sv.t, a.chunk, a.max_newton, a.tol_a, a.tol_r, a.init, a.halving != 0, sink,
-           PredictorRef{a.pred, a.pred_hidden, a.pred_steps, a.pred_base, pred_lds}, a.reuse);
+           PredictorRef{a.pred, a.pred_hidden, a.pred_steps, a.pred_base, pred_lds});
     if (sv.valid && q == 0) {
         a.status[sv.b] = cn.status;
         if (a.iters) a.iters[sv.b] = cn.total;
@@ -669,8 +582,7 @@ __global__ __launch_bounds__(kWave) void forward_kernel(SolveArgs<IO> a)
 //   lam_k = (I + dt_{k+1} j(y_k))^T lam_{k+1} + g_k,  lam_{N+1} = 0,
 //   dL/dp = sum_k dt_k (dh/dp(y_{k-1}))^T lam_k,  dL/dy0 = g_0 + (I + dt_1 j(y_0))^T lam_1.
 // ---------------------------------------------------------------------------
-template <class Model, class IO, int S, int T, bool RECOMPUTE, bool PRED, bool FE = false, bool REUSE = false,
-          bool ZREF = false>
+template <class Model, class IO, int S, int T, bool RECOMPUTE, bool PRED, bool FE = false, bool ZREF = false>
 __global__ __launch_bounds__(kWave) void adjoint_kernel(SolveArgs<IO> a)
 {
     constexpr int n = Model::N;
@@ -702,7 +614,7 @@ __global__ __launch_bounds__(kWave) void adjoint_kernel(SolveArgs<IO> a)
         const int m = active ? (int)min((int64_t)C, sv.Nb - s) : 0;
 
         if (RECOMPUTE) {
-            ChunkNewton<Model, S, T, FE, REUSE> cn;
+            ChunkNewton<Model, S, T, FE> cn;
             const bool have_ckpt = active && c < a.K;
             if (active && !have_ckpt) status = ST_NONFINITE;
             cn.active = have_ckpt;
@@ -715,7 +627,7 @@ __global__ __launch_bounds__(kWave) void adjoint_kernel(SolveArgs<IO> a)
             WorkspaceSink<n> wsink{wsb, s};
             extern __shared__ float pred_lds[];
             cn.template run<PRED, ZREF>(model, sv.t, C, a.max_newton, a.tol_a, a.tol_r, a.init, a.halving != 0,
-                   wsink, PredictorRef{a.pred, a.pred_hidden, a.pred_steps, a.pred_base, pred_lds}, a.reuse);
+                   wsink, PredictorRef{a.pred, a.pred_hidden, a.pred_steps, a.pred_base, pred_lds});
             if (active && cn.status != ST_OK) status = cn.status;
             __syncthreads(); // one wave per block: makes the workspace writes visible to the wave
         }

@@ -29,7 +29,7 @@ class CapturedStep:
 
     def __init__(self, kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e-6), lanes=0, steps_per_lane=0,
                  max_newton=50, init="zero", loss="frobenius", observed=None, n_max=None, recompute=True,
-                 longest_first=True, scheme="backward_euler", jacobian_reuse=0.0, jacobian="analytic"):
+                 longest_first=True, scheme="backward_euler", jacobian="analytic"):
         lib = tvi.load()
         self.kind = kind
         self.recompute = recompute
@@ -52,11 +52,12 @@ class CapturedStep:
         # ragged series launch longest first (computed once: the lengths are inputs)
         self.order = tvi.order_longest_first(self.offsets) if self.offsets is not None and longest_first else None
         self.opt = tvi.make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, True, order=self.order,
-                                    scheme=scheme, jacobian_reuse=jacobian_reuse, jacobian=jacobian)
+                                    scheme=scheme, jacobian=jacobian)
         P = lib.tvi_param_count(ctypes.byref(self.model))
         K = (N + chunk - 1) // chunk + 1
         self.y = torch.empty(yshape, dtype=dt, device=dev)
-        self.ckpt = torch.empty((B, K, n), dtype=torch.float64, device=dev)
+        # checkpoints only where the adjoint recomputes from them
+        self.ckpt = torch.empty((B, K, n), dtype=torch.float64, device=dev) if recompute else None
         self.status_fwd = torch.empty(B, dtype=torch.int32, device=dev)
         self.iters = torch.empty(B, dtype=torch.int32, device=dev)
         self.g = torch.empty_like(self.y)
@@ -79,22 +80,38 @@ class CapturedStep:
             if src is not None:
                 dst.copy_(src)
 
-    def _launch(self):
+    def launch_forward(self):
+        """The forward solve alone (current stream)."""
         lib = tvi.load()
         P = tvi._ptr
-        st = tvi._stream()
         tvi._check(lib.tvi_solve_forward(ctypes.byref(self.model), ctypes.byref(self.opt), self.B, self.N,
                                          P(self.offsets), P(self.times), P(self.y0), P(self.params), P(self.y),
-                                         P(self.ckpt), P(self.status_fwd), P(self.iters), st), "tvi_solve_forward")
-        tvi._check(lib.tvi_loss_grad(self.loss_kind, self.model.dtype, self.y.shape[0] * (self.y.numel() //
-                                     self.y.shape[0]) // self.n, self.n, P(self.y), P(self.observed),
+                                         P(self.ckpt), P(self.status_fwd), P(self.iters), tvi._stream()),
+                   "tvi_solve_forward")
+
+    def launch_loss(self):
+        """The loss value and its gradient g = dL/dy alone (current stream)."""
+        lib = tvi.load()
+        P = tvi._ptr
+        points = self.y.numel() // self.n
+        tvi._check(lib.tvi_loss_grad(self.loss_kind, self.model.dtype, points, self.n, P(self.y), P(self.observed),
                                      self.n_observed, P(self.g), P(self.loss), P(self.loss_ws),
-                                     self.loss_ws.numel(), st), "tvi_loss_grad")
+                                     self.loss_ws.numel(), tvi._stream()), "tvi_loss_grad")
+
+    def launch_adjoint(self):
+        """The adjoint alone (current stream)."""
+        lib = tvi.load()
+        P = tvi._ptr
         tvi._check(lib.tvi_solve_adjoint(ctypes.byref(self.model), ctypes.byref(self.opt), self.B, self.N,
                                          P(self.offsets), P(self.times), P(self.params),
                                          None if self.recompute else P(self.y), P(self.ckpt),
                                          P(self.g), P(self.dLdp), P(self.dLdy0), P(self.status_adj), P(self.ws),
-                                         self.ws_bytes, st), "tvi_solve_adjoint")
+                                         self.ws_bytes, tvi._stream()), "tvi_solve_adjoint")
+
+    def _launch(self):
+        self.launch_forward()
+        self.launch_loss()
+        self.launch_adjoint()
 
     def run_eager(self):
         """The same launches without a graph (on the current stream)."""

@@ -48,7 +48,7 @@ class Options(ctypes.Structure):
                 ("init", ctypes.c_int32), ("halving", ctypes.c_int32), ("predictor", ctypes.c_void_p),
                 ("predictor_hidden", ctypes.c_int32), ("predictor_steps", ctypes.c_int32),
                 ("predictor_base", ctypes.c_int32), ("order", ctypes.c_void_p), ("scheme", ctypes.c_int32),
-                ("jacobian_reuse", ctypes.c_double), ("jacobian", ctypes.c_int32),
+                ("jacobian", ctypes.c_int32),
                 ("reference_residual", ctypes.c_int32)]
 
 
@@ -125,14 +125,12 @@ def param_count(kind, n, hidden=64):
 
 
 def make_options(chunk=64, tol=(1e-8, 1e-6), max_newton=50, lanes=0, steps_per_lane=0, init="zero",
-                 halving=True, predictor=None, order=None, scheme="backward_euler", jacobian_reuse=0.0,
+                 halving=True, predictor=None, order=None, scheme="backward_euler",
                  jacobian="analytic", reference="first"):
     """``predictor``: (packed params, hidden, steps[, base]) of a trained chunk
     predictor, as made by ``predictor.solver_args`` (base 0: corrections to the
     zero start, 1: to the extrapolated start).  ``scheme``: "backward_euler" or
-    "forward_euler".  ``jacobian_reuse``: 0 for a full Newton correction every
-    iteration, or the residual reduction factor below which a correction reuses
-    the previous factorization.  ``jacobian``: "analytic" or "forward_ad".
+    "forward_euler".  ``jacobian``: "analytic" or "forward_ad".
     ``reference``: the R0 of the relative stopping test, "first" (the attempt's
     first iterate) or "zero" (the residual at dy = 0, Algorithm 1's n0)."""
     o = Options()
@@ -151,7 +149,6 @@ def make_options(chunk=64, tol=(1e-8, 1e-6), max_newton=50, lanes=0, steps_per_l
     if order is not None:
         o.order = ctypes.c_void_p(order.data_ptr())
     o.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
-    o.jacobian_reuse = float(jacobian_reuse)
     o.jacobian = JACOBIANS[jacobian] if isinstance(jacobian, str) else int(jacobian)
     o.reference_residual = {"first": 0, "zero": 1}[reference] if isinstance(reference, str) else int(reference)
     return o
@@ -216,7 +213,7 @@ def _geometry(y0, times, offsets, n_max=None):
 
 def solve_forward(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e-6), max_newton=50, lanes=0,
                   steps_per_lane=0, init="zero", halving=True, checkpoints=False, y_out=None, iters=True,
-                  predictor=None, order=None, scheme="backward_euler", jacobian_reuse=0.0, jacobian="analytic",
+                  predictor=None, order=None, scheme="backward_euler", jacobian="analytic",
                   n_max=None, reference="first"):
     """Chunked backward Euler (or forward Euler, ``scheme="forward_euler"``).  Returns ``(y, status, iters, ckpt)`` (device tensors;
     ``iters`` and ``ckpt`` may be None).  Asynchronous: nothing is synchronised, except that ragged series
@@ -230,7 +227,7 @@ def solve_forward(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e
     B, n, N, yshape = _geometry(y0, times, offsets, n_max)
     model = Model(KINDS[kind], n, _io_dtype(y0), 1 if params.dim() == 1 else 0, 64)
     opt = make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, halving, predictor, order, scheme,
-                       jacobian_reuse, jacobian, reference)
+                       jacobian, reference)
     dev = y0.device
     y = y_out if y_out is not None else torch.empty(yshape, dtype=dt, device=dev)
     status = torch.empty(B, dtype=torch.int32, device=dev)
@@ -247,7 +244,7 @@ def solve_forward(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e
 
 def solve_adjoint(kind, times, params, g, y=None, ckpt=None, offsets=None, chunk=64, tol=(1e-8, 1e-6),
                   max_newton=50, lanes=0, steps_per_lane=0, init="zero", halving=True, n=None, predictor=None,
-                  order=None, scheme="backward_euler", jacobian_reuse=0.0, jacobian="analytic", n_max=None,
+                  order=None, scheme="backward_euler", jacobian="analytic", n_max=None,
                   reference="first"):
     """Discrete adjoint.  Returns ``(dLdp [B,P], dLdy0 [B,n], status [B])``.
 
@@ -274,7 +271,7 @@ def solve_adjoint(kind, times, params, g, y=None, ckpt=None, offsets=None, chunk
         raise TviError("parameters must be per series [B, P] or shared [P]")
     model = Model(KINDS[kind], n, _io_dtype(g), 1 if shared else 0, 64)
     opt = make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, halving, predictor, order, scheme,
-                       jacobian_reuse, jacobian, reference)
+                       jacobian, reference)
     lib = load()
     dev = g.device
     P = lib.tvi_param_count(ctypes.byref(model))

@@ -192,26 +192,6 @@ def test_paper_example_models_sizes(lib):
     assert fwd("neuron", 12) == -4
 
 
-def test_jacobian_reuse_option_is_checked(lib):
-    from paper_2310_08649_amd import tvi
-    f = _fake()
-    m = tvi.Model(tvi.KINDS["vanderpol"], 2, tvi.F64, 0, 64)
-
-    def fwd(o, model=m):
-        return lib.tvi_solve_forward(ctypes.byref(model), ctypes.byref(o), 4, 10, None, f, f, f, f, None, f, None,
-                                     None)
-
-    assert tvi.make_options().jacobian_reuse == 0.0
-    assert fwd(tvi.make_options(chunk=16, jacobian_reuse=1.0)) == -1
-    assert fwd(tvi.make_options(chunk=16, jacobian_reuse=-0.1)) == -1
-    assert fwd(tvi.make_options(chunk=16, jacobian_reuse=0.2, scheme="forward_euler")) == -4
-    # Robertson at 8 steps per lane over 64 lanes keeps too many matrices per lane
-    mr = tvi.Model(tvi.KINDS["robertson"], 3, tvi.F64, 0, 64)
-    assert fwd(tvi.make_options(chunk=512, lanes=64, steps_per_lane=8, jacobian_reuse=0.2), mr) == -4
-    mm = tvi.Model(tvi.KINDS["mlp"], 8, tvi.F32, 1, 64)
-    assert fwd(tvi.make_options(chunk=16, jacobian_reuse=0.2), mm) == -4
-
-
 def test_jacobian_option_is_checked(lib):
     from paper_2310_08649_amd import tvi
     f = _fake()
@@ -223,7 +203,6 @@ def test_jacobian_option_is_checked(lib):
     assert tvi.make_options().jacobian == 0
     assert fwd(tvi.make_options(chunk=16, jacobian=2)) == -1
     assert fwd(tvi.make_options(chunk=16, jacobian="forward_ad", scheme="forward_euler")) == -4
-    assert fwd(tvi.make_options(chunk=16, jacobian="forward_ad", jacobian_reuse=0.2)) == -4
     assert fwd(tvi.make_options(chunk=16, jacobian="forward_ad"), dtype=tvi.F32) == -4
     assert fwd(tvi.make_options(chunk=16, jacobian="forward_ad"), kind="mlp", n=8, dtype=tvi.F32, shared=1) == -4
 

@@ -105,10 +105,10 @@ def test_loss_gradients_float_storage(mods):
 
 
 @pytest.mark.parametrize("opts", [dict(scheme="forward_euler"), dict(jacobian="forward_ad"),
-                                  dict(jacobian_reuse=0.2), dict(jacobian_reuse=0.2, recompute=False)],
-                         ids=["forward_euler", "forward_ad", "reuse_recompute", "reuse_stored"])
+                                  dict(scheme="forward_euler", recompute=False)],
+                         ids=["forward_euler", "forward_ad", "forward_euler_stored"])
 def test_captured_step_with_solver_options_replays_exactly(mods, opts):
-    """Forward Euler, AD Jacobians and Jacobian reuse inside one captured graph:
+    """Forward Euler and AD Jacobians inside one captured graph:
     every replay, with eager work in between, equals the eager run bitwise."""
     graph, tvi = mods
     w = W.vanderpol(B=96, N=800, mu_range=(1.0, 10.0))

@@ -566,58 +566,6 @@ def test_pcr_forward_and_transposed_solves_are_adjoint(tvi, n):
     assert (np.abs(lhs - rhs) <= 1e-13 * np.sqrt(m) * scale).all()
 
 
-# --------------------------------------------------------------------------
-# Jacobian reuse (chord steps): the same residual test, so the same root at
-# the parity tolerance; recomputation stays bitwise equal to the forward pass
-# --------------------------------------------------------------------------
-@pytest.mark.parametrize("reuse", [0.1, 0.5])
-def test_jacobian_reuse_parity(tvi, reuse):
-    # mu up to 30: the stiffest series of the full-Newton adjoint test sit at the
-    # edge of the 1e-10 gate through the adjoint's own conditioning, which the
-    # way the states were reached does not change
-    w = W.vanderpol(B=64, N=1000, mu_range=(1.0, 30.0))
-    yo, so, _ = oracle.forward("vanderpol", w["y0"], w["times"], w["params"], tol=PARITY_TOL)
-    ok = so == 0
-    g = np.where(ok[:, None, None], yo, 0.0)
-    g = g / np.sqrt(np.sum(g ** 2))
-    for C, S, T, init in ((50, 64, 1, "zero"), (32, 16, 2, "extrap"), (8, 4, 2, "zero"), (4, 1, 4, "zero")):
-        kw = dict(chunk=C, lanes=S, steps_per_lane=T, tol=PARITY_TOL, init=init, jacobian_reuse=reuse)
-        y, st, it, ck = tvi.solve_forward("vanderpol", dev(w["y0"]), dev(w["times"]), dev(w["params"]),
-                                          checkpoints=True, **kw)
-        st = host(st)
-        both = ok & (st == 0)
-        assert both.mean() >= 0.95, (C, S, T)
-        assert series_rel_err(host(y)[both], yo[both]).max() <= 1e-10, (C, S, T)
-        gz = torch.where(dev(both)[:, None, None] > 0, dev(g), torch.zeros_like(dev(g)))
-        yz = torch.where(dev(both)[:, None, None] > 0, y, torch.zeros_like(y))
-        a1 = tvi.solve_adjoint("vanderpol", dev(w["times"]), dev(w["params"]), gz, y=yz, **kw)
-        a2 = tvi.solve_adjoint("vanderpol", dev(w["times"]), dev(w["params"]), gz, ckpt=ck, **kw)
-        b = np.flatnonzero(both)
-        assert np.array_equal(host(a1[0])[b], host(a2[0])[b]) and np.array_equal(host(a1[1])[b], host(a2[1])[b])
-        # the oracle's adjoint at the states this solve converged to (the two stopping
-        # points differ within the tolerance, and stiff series amplify that in the gradient)
-        opb, oy0b, _ = oracle.adjoint("vanderpol", host(yz), w["times"], w["params"], host(gz))
-        for a, r in ((host(a1[0])[b], opb[b]), (host(a1[1])[b], oy0b[b])):
-            err = np.abs(a - r).max(axis=1) / np.maximum(np.abs(r).max(axis=1), 1e-300)
-            assert err.max() <= 1e-10, (C, S, T, err.max())
-
-
-def test_jacobian_reuse_linear_every_supported_tiling(tvi):
-    """On a linear system the first correction is exact: reuse never triggers and
-    the result equals the full-Newton one bitwise."""
-    from paper_2310_08649_amd import autotune
-    rng = np.random.default_rng(61)
-    n, B, N = 2, 20, 90
-    A = -2.0 * np.eye(n)[None] + rng.standard_normal((B, n, n))
-    args = (dev(rng.standard_normal((B, n))), dev(np.linspace(0, 1, N + 1)), dev(A.reshape(B, -1)))
-    for C in (3, 16, 40, 90):
-        for S, T in autotune.tilings(C):
-            kw = dict(chunk=C, lanes=S, steps_per_lane=T, tol=PARITY_TOL)
-            ya = tvi.solve_forward("linear", *args, **kw)[0]
-            yb = tvi.solve_forward("linear", *args, jacobian_reuse=0.3, **kw)[0]
-            assert torch.equal(ya, yb), (C, S, T)
-
-
 def test_ragged_n_max_given_equals_computed(tvi):
     """Ragged solves with the longest series' step count given (no device
     reduction) equal those that read it from the offsets, bitwise."""

@@ -68,11 +68,11 @@ def test_option_marshalling():
     if not os.path.exists(tvi.LIB_PATH):
         pytest.skip("libtvi.so not built")
     o = tvi.make_options(chunk=37, tol=(1e-9, 1e-7), max_newton=12, lanes=16, steps_per_lane=4, init="extrap",
-                         halving=False, scheme="forward_euler", jacobian_reuse=0.25, jacobian="forward_ad",
+                         halving=False, scheme="forward_euler", jacobian="forward_ad",
                          reference="zero")
     assert (o.chunk, o.max_newton, o.lanes, o.steps_per_lane, o.init, o.halving) == (37, 12, 16, 4, 1, 0)
     assert (o.tol_a, o.tol_r) == (1e-9, 1e-7)
-    assert (o.scheme, o.jacobian, o.reference_residual) == (1, 1, 1) and o.jacobian_reuse == 0.25
+    assert (o.scheme, o.jacobian, o.reference_residual) == (1, 1, 1)
     assert tvi.make_options(init="predictor").init == 2 and tvi.make_options(init="zero").init == 0
 
 
@@ -144,18 +144,73 @@ def test_bench_reduction_levels_and_flop_count():
     assert b.vdp_flops_per_step_iter(1) == 44
 
 
-def test_bench_traffic_is_reported_only_for_matching_kernel_code(monkeypatch):
+def test_bench_robertson_flop_counts():
+    b, _ = _bench()
+    # pure PCR over 64 lanes: six reduction levels per step
+    assert b.rob_forward_flops_per_step(64, 1) == 26 + 24 + 72 + 6 * 72
+    # hybrid: three serial compositions and six levels shared by four steps, plus the replay
+    assert b.rob_forward_flops_per_step(64, 4) == 26 + 24 + 72 + 72 * (3 + 6) / 4 + 24
+    # one lane per series (chunk 1): no composition at all
+    assert b.rob_forward_flops_per_step(1, 1) == 26 + 24 + 72
+    assert b.rob_adjoint_flops_per_step(1, 1) == 24 + 72 + 24 + 12
+
+
+def test_bench_traffic_is_reported_only_for_matching_kernel_code(monkeypatch, tmp_path):
     import json
     import os
+    import shutil
     b, _ = _bench()
-    with open(os.path.join(b.ROOT, "profiles", "traffic.json")) as f:
-        table = json.load(f)
-    kernel, rec = next(iter(table.items()))
-    monkeypatch.setattr(b, "csrc_hash", lambda: rec["source_hash"])
-    assert b.measured_traffic(kernel) == rec["bytes_per_dispatch"]
+    srcs = ["solver.hpp", "device.hpp"]
+    kernel = "tvi::forward_kernel<tvi::Robertson, double, 64, 4, false, false, false>(tvi::SolveArgs<double>)"
+    table = {kernel: {"bytes_per_dispatch": 1.5e8, "sources": srcs, "source_hash": b.csrc_hash(srcs)}}
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(table))
+    csrc = tmp_path / "paper_2310_08649_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    for name in srcs:
+        shutil.copy(os.path.join(b.ROOT, "paper_2310_08649_amd", "csrc", name), csrc / name)
+    monkeypatch.setattr(b, "ROOT", str(tmp_path))
+    assert b.measured_traffic(kernel) == 1.5e8
     assert b.measured_traffic("no such kernel") is None
-    monkeypatch.setattr(b, "csrc_hash", lambda: "0" * 16)
+    # a change to a file the kernel is not built from leaves the counters valid
+    (csrc / "unrelated.hip").write_text("int x;")
+    assert b.measured_traffic(kernel) == 1.5e8
+    # a change to one it is built from makes them stale
+    (csrc / "device.hpp").write_text((csrc / "device.hpp").read_text() + "\nint changed;\n")
     assert b.measured_traffic(kernel) is None
+
+
+def test_bench_line_is_compact_json():
+    import argparse
+    import json
+    b, _ = _bench()
+    args = argparse.Namespace(steps=20, warmup=5)
+    cfg = {"workload": "x" * 300, "chunk": 256, "lanes": 64, "steps_per_lane": 4, "init": "zero",
+           "adjoint_states": "stored", "series": 2000, "series_steps": 7710000, "series_failed": 0,
+           "series_steps_counted": 7710000, "newton_corrections": 86000}
+    roof = {"bound": "alu", "achieved": 11.2, "peak": 78.6, "unit": "TFLOP/s", "frac": 0.142, "traffic": 2.5e8,
+            "kernel": "k" * 120, "avg_launch_ms": 0.63, "algorithmic_flops": 7.1e9, "algorithmic_bytes": 2.4e8,
+            "hbm_gbs": 390.0, "hbm_frac": 0.05, "other_kernel": {"kernel": "k" * 120, "avg_launch_ms": 0.5,
+                                                                   "tflops": 5.0, "hbm_gbs": 800.0},
+            "loss_ms": 0.05, "loss_hbm_gbs": 3000.0}
+    head = {"value": 6.4e9, "ms_per_step": 1.2, "replay": {"mean_ms": 1.2, "median_ms": 1.2, "min_ms": 1.19},
+            "config": cfg, "roofline": roof, "peak_device_memory_bytes": 10 ** 9,
+            "chunk1": {"value": 1e8, "ms_per_step": 80.0, "series_failed": 0, "speedup_of_chunked": 66.0},
+            "other_adjoint_states": {"adjoint_states": "recompute", "value": 4e9, "ms_per_step": 1.8},
+            "autotune_best": {"chunk": 256}, "autotune_candidates": 40}
+    out = b.compose_line(args, head)
+    out["cpu_baseline"] = {"value": 1e8, "unit": "series*steps/s", "cores": 16, "kind": "oracle",
+                           "sample": "s" * 200, "one_core_value": 1e7, "one_core_sample": "s" * 60,
+                           "cpu_model": "c" * 40, "nproc": 16}
+    line = json.dumps(out, separators=(",", ":"))
+    assert len(line) < 4096
+    back = json.loads(line)
+    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+              "scaling", "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"):
+        assert k in back
+    for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
+        assert k in back["roofline"]
+    assert "workload" in back["config"]
 
 
 def test_bench_code_hash_ignores_comments_only(tmp_path, monkeypatch):
