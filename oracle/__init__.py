@@ -32,7 +32,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-KINDS = {"linear": 0, "vanderpol": 1, "robertson": 2, "mlp": 3, "chaboche": 4, "neuron": 5}
+KINDS = {"linear": 0, "vanderpol": 1, "robertson": 2, "mlp": 3, "chaboche": 4, "neuron": 5, "mds": 6, "fnode": 7}
 STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "SINGULAR", 3: "NONFINITE"}
 
 _lib = None

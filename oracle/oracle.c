@@ -33,7 +33,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define NMAX 16
+#define NMAX 64
 #define HMAX 512
 
 /* ------------------------------------------------------------------------ */
@@ -89,6 +89,8 @@ int oracle_param_count(int kind, int n, int hidden)
     case ORACLE_MLP:       return hidden * n + hidden + hidden * hidden + hidden + n * hidden + n;
     case ORACLE_CHABOCHE:  return n >= 3 ? 8 + 2 * (n - 2) : -1;
     case ORACLE_NEURON:    return (n >= 4 && n % 4 == 0) ? 15 * (n / 4) + 1 : -1;
+    case ORACLE_MDS:       return (n >= 2 && n % 2 == 0) ? 3 * (n / 2) + 2 : -1;
+    case ORACLE_FNODE:     return 2 * (n + 1) * (n + 1) + 2 * (n + 1) + n * (n + 1) + n + 2;
     default:               return -1;
     }
 }
@@ -150,6 +152,69 @@ static chaboche_flow chaboche_eval(int nu, const double *y, double t, const doub
  * h_inf, tau_h, n_inf, tau_n, g_C, T), then the current amplitude I_a. */
 enum { NR_C, NR_GNA, NR_ENA, NR_GK, NR_EK, NR_GL, NR_EL, NR_MINF, NR_TM, NR_HINF, NR_TH, NR_NINF, NR_TN,
        NR_GC, NR_T, NR_PER_UNIT };
+
+/* Mass-damper-spring chain (Section 5.1.1) of nu = n / 2 units, state
+ * (d_1, v_1, ..., d_nu, v_nu); p = (K_1..K_nu, C_1..C_nu, M_1..M_nu, f_a, T).
+ * Unit i is mass M_i joined to its neighbour on the fixed side, i + 1, by the
+ * spring K_i and the damper C_i; position nu + 1 is the wall (d = v = 0) and
+ * the periodic force acts on the first mass:
+ *   dd_i/dt = v_i,
+ *   dv_i/dt = [K_i (d_{i+1} - d_i) + C_i (v_{i+1} - v_i)
+ *             - K_{i-1} (d_i - d_{i-1}) - C_{i-1} (v_i - v_{i-1})] / M_i + f_i(t),
+ * with no i - 1 terms for the first unit, f_1 = f_a sin(2 pi t / T), f_i = 0
+ * otherwise.  The spring and damper forces restore (the printed signs would
+ * drive the chain away from rest), every force on a mass is divided by that
+ * mass, and the printed forcing lacks its time argument. */
+static void mds_accel_row(int nu, int i, const double *y, const double *p, double *acc)
+{
+    const double *K = p, *C = p + nu, *M = p + 2 * nu;
+    const double d = y[2 * i], v = y[2 * i + 1];
+    const double dn = (i + 1 < nu) ? y[2 * i + 2] : 0.0, vn = (i + 1 < nu) ? y[2 * i + 3] : 0.0;
+    double a = K[i] * (dn - d) + C[i] * (vn - v);
+    if (i > 0) a -= K[i - 1] * (d - y[2 * i - 2]) + C[i - 1] * (v - y[2 * i - 1]);
+    *acc = a / M[i];
+}
+
+/* Forced neural ODE (Section 5.1.1) of size n: x = (y, f(t)),
+ * a1 = tanh(W1 x + b1), a2 = tanh(W2 a1 + b2), h = tanh(W3 a2 + b3), with
+ * W1, W2 (n+1) x (n+1), W3 n x (n+1), f(t) = f_a sin(2 pi t / T);
+ * p = (W1, b1, W2, b2, W3, b3, f_a, T), matrices row-major. */
+typedef struct {
+    const double *W1, *b1, *W2, *b2, *W3, *b3;
+    double fa, T;
+} fnode_params;
+
+static fnode_params fnode_unpack(int n, const double *p)
+{
+    const int m = n + 1;
+    fnode_params q;
+    q.W1 = p; q.b1 = q.W1 + m * m; q.W2 = q.b1 + m; q.b2 = q.W2 + m * m; q.W3 = q.b2 + m; q.b3 = q.W3 + n * m;
+    q.fa = q.b3[n]; q.T = q.b3[n + 1];
+    return q;
+}
+
+static void fnode_forward(int n, const fnode_params *q, const double *y, double t, double *x, double *a1,
+                          double *a2, double *a3)
+{
+    const int m = n + 1;
+    for (int k = 0; k < n; ++k) x[k] = y[k];
+    x[n] = q->fa * sin(2.0 * M_PI * t / q->T);
+    for (int i = 0; i < m; ++i) {
+        double s = q->b1[i];
+        for (int k = 0; k < m; ++k) s += q->W1[i * m + k] * x[k];
+        a1[i] = tanh(s);
+    }
+    for (int i = 0; i < m; ++i) {
+        double s = q->b2[i];
+        for (int k = 0; k < m; ++k) s += q->W2[i * m + k] * a1[k];
+        a2[i] = tanh(s);
+    }
+    for (int i = 0; i < n; ++i) {
+        double s = q->b3[i];
+        for (int k = 0; k < m; ++k) s += q->W3[i * m + k] * a2[k];
+        a3[i] = tanh(s);
+    }
+}
 
 /* f = h(y,t;p); if J != NULL also J = dh/dy (row-major n x n). */
 static void rhs(int kind, int n, int H, const double *y, double t, const double *p,
@@ -234,6 +299,58 @@ static void rhs(int kind, int n, int H, const double *y, double t, const double 
         }
         break;
     }
+    case ORACLE_MDS: {
+        const int nu = n / 2;
+        const double *K = p, *C = p + nu, *M = p + 2 * nu;
+        for (int i = 0; i < nu; ++i) {
+            double a;
+            mds_accel_row(nu, i, y, p, &a);
+            f[2 * i] = y[2 * i + 1];
+            f[2 * i + 1] = a + (i == 0 ? p[3 * nu] * sin(2.0 * M_PI * t / p[3 * nu + 1]) : 0.0);
+        }
+        if (J) {
+            memset(J, 0, sizeof(double) * n * n);
+            for (int i = 0; i < nu; ++i) {
+                double *r = J + (2 * i + 1) * n;
+                J[(2 * i) * n + 2 * i + 1] = 1.0;
+                r[2 * i] = -K[i] / M[i];
+                r[2 * i + 1] = -C[i] / M[i];
+                if (i + 1 < nu) { r[2 * i + 2] = K[i] / M[i]; r[2 * i + 3] = C[i] / M[i]; }
+                if (i > 0) {
+                    r[2 * i] -= K[i - 1] / M[i];
+                    r[2 * i + 1] -= C[i - 1] / M[i];
+                    r[2 * i - 2] = K[i - 1] / M[i];
+                    r[2 * i - 1] = C[i - 1] / M[i];
+                }
+            }
+        }
+        break;
+    }
+    case ORACLE_FNODE: {
+        const int m = n + 1;
+        const fnode_params q = fnode_unpack(n, p);
+        double x[NMAX + 1], a1[NMAX + 1], a2[NMAX + 1];
+        fnode_forward(n, &q, y, t, x, a1, a2, f);
+        if (J) {
+            /* J = diag(1 - h^2) W3 diag(1 - a2^2) W2 diag(1 - a1^2) W1[:, 0:n],
+               column by column as Jacobian-vector products with unit vectors */
+            double u1[NMAX + 1], u2[NMAX + 1];
+            for (int c = 0; c < n; ++c) {
+                for (int i = 0; i < m; ++i) u1[i] = (1.0 - a1[i] * a1[i]) * q.W1[i * m + c];
+                for (int i = 0; i < m; ++i) {
+                    double s = 0.0;
+                    for (int k = 0; k < m; ++k) s += q.W2[i * m + k] * u1[k];
+                    u2[i] = (1.0 - a2[i] * a2[i]) * s;
+                }
+                for (int i = 0; i < n; ++i) {
+                    double s = 0.0;
+                    for (int k = 0; k < m; ++k) s += q.W3[i * m + k] * u2[k];
+                    J[i * n + c] = (1.0 - f[i] * f[i]) * s;
+                }
+            }
+        }
+        break;
+    }
     case ORACLE_NEURON: {
         const int nu = n / 4;
         const double Ia = p[NR_PER_UNIT * nu];
@@ -300,6 +417,70 @@ static void vjp_p(int kind, int n, int H, const double *y, double t, const doubl
         const double ph = 2.0 * M_PI * t / T;
         gp[6 + 2 * nu] += w[0] * E * sin(ph);
         gp[7 + 2 * nu] += w[0] * E * eda * cos(ph) * (-ph / T);
+        return;
+    }
+    case ORACLE_MDS: {
+        /* h is linear in K, C, 1/M and f_a: dv_i/dt = a_i + f_i with a_i the
+           spring and damper acceleration of mass i */
+        const int nu = n / 2;
+        const double *M = p + 2 * nu;
+        double *gK = gp, *gC = gp + nu, *gM = gp + 2 * nu;
+        for (int i = 0; i < nu; ++i) {
+            const double wi = w[2 * i + 1] / M[i];
+            const double d = y[2 * i], v = y[2 * i + 1];
+            const double dn = (i + 1 < nu) ? y[2 * i + 2] : 0.0, vn = (i + 1 < nu) ? y[2 * i + 3] : 0.0;
+            gK[i] += wi * (dn - d);
+            gC[i] += wi * (vn - v);
+            if (i > 0) {
+                gK[i - 1] -= wi * (d - y[2 * i - 2]);
+                gC[i - 1] -= wi * (v - y[2 * i - 1]);
+            }
+            double a;
+            mds_accel_row(nu, i, y, p, &a);
+            gM[i] -= w[2 * i + 1] * a / M[i];
+        }
+        const double ph = 2.0 * M_PI * t / p[3 * nu + 1];
+        gp[3 * nu] += w[1] * sin(ph);
+        gp[3 * nu + 1] += w[1] * p[3 * nu] * cos(ph) * (-ph / p[3 * nu + 1]);
+        return;
+    }
+    case ORACLE_FNODE: {
+        /* back-propagation of w through the three layers, then into f_a and T
+           through the forcing input */
+        const int m = n + 1;
+        const fnode_params q = fnode_unpack(n, p);
+        double x[NMAX + 1], a1[NMAX + 1], a2[NMAX + 1], a3[NMAX], d3[NMAX], d2[NMAX + 1], d1[NMAX + 1];
+        fnode_forward(n, &q, y, t, x, a1, a2, a3);
+        double *gW1 = gp, *gb1 = gW1 + m * m, *gW2 = gb1 + m, *gb2 = gW2 + m * m, *gW3 = gb2 + m,
+               *gb3 = gW3 + n * m;
+        for (int i = 0; i < n; ++i) d3[i] = w[i] * (1.0 - a3[i] * a3[i]);
+        for (int i = 0; i < n; ++i) {
+            for (int k = 0; k < m; ++k) gW3[i * m + k] += d3[i] * a2[k];
+            gb3[i] += d3[i];
+        }
+        for (int k = 0; k < m; ++k) {
+            double s = 0.0;
+            for (int i = 0; i < n; ++i) s += q.W3[i * m + k] * d3[i];
+            d2[k] = s * (1.0 - a2[k] * a2[k]);
+        }
+        for (int i = 0; i < m; ++i) {
+            for (int k = 0; k < m; ++k) gW2[i * m + k] += d2[i] * a1[k];
+            gb2[i] += d2[i];
+        }
+        for (int k = 0; k < m; ++k) {
+            double s = 0.0;
+            for (int i = 0; i < m; ++i) s += q.W2[i * m + k] * d2[i];
+            d1[k] = s * (1.0 - a1[k] * a1[k]);
+        }
+        double gx = 0.0; /* dL/d(forcing input) */
+        for (int i = 0; i < m; ++i) {
+            for (int k = 0; k < m; ++k) gW1[i * m + k] += d1[i] * x[k];
+            gb1[i] += d1[i];
+            gx += q.W1[i * m + n] * d1[i];
+        }
+        const double ph = 2.0 * M_PI * t / q.T;
+        gb3[n] += gx * sin(ph);
+        gb3[n + 1] += gx * q.fa * cos(ph) * (-ph / q.T);
         return;
     }
     case ORACLE_NEURON: {

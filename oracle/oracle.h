@@ -30,6 +30,12 @@
  *   ORACLE_NEURON     nu = n / 4 coupled neurons, state (V, m, h, n) per neuron,
  *                     p = 15 per neuron (C, g_Na, E_Na, g_K, E_K, g_L, E_L, m_inf,
  *                     tau_m, h_inf, tau_h, n_inf, tau_n, g_C, T), then I_a (Section 5.1.1)
+ *   ORACLE_MDS        mass-damper-spring chain of nu = n / 2 units, state (d_1, v_1, ..,
+ *                     d_nu, v_nu), p = (K_1..K_nu, C_1..C_nu, M_1..M_nu, f_a, T) (Section 5.1.1)
+ *   ORACLE_FNODE      forced neural ODE h = tanh(W3 tanh(W2 tanh(W1 (y, f(t)) + b1) + b2) + b3),
+ *                     p = (W1[n+1][n+1], b1[n+1], W2[n+1][n+1], b2[n+1], W3[n][n+1], b3[n],
+ *                     f_a, T), f(t) = f_a sin(2 pi t / T) (Section 5.1.1)
+ * State size n <= 64.
  */
 #ifndef TVI_ORACLE_H
 #define TVI_ORACLE_H
@@ -41,7 +47,7 @@ extern "C" {
 #endif
 
 enum { ORACLE_LINEAR = 0, ORACLE_VANDERPOL = 1, ORACLE_ROBERTSON = 2, ORACLE_MLP = 3, ORACLE_CHABOCHE = 4,
-       ORACLE_NEURON = 5 };
+       ORACLE_NEURON = 5, ORACLE_MDS = 6, ORACLE_FNODE = 7 };
 enum { ORACLE_OK = 0, ORACLE_NOT_CONVERGED = 1, ORACLE_SINGULAR = 2, ORACLE_NONFINITE = 3 };
 
 int oracle_param_count(int kind, int n, int hidden);

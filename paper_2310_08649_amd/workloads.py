@@ -23,6 +23,8 @@ and two of the paper's own example problems with its parameter tables
 
 * ``chaboche``   Chaboche viscoplasticity, n = 2 + n_unit backstresses
 * ``neuron``     coupled neurons, n = 4 n_unit
+* ``mds``        mass-damper-spring chain, n = 2 n_unit
+* ``fnode``      forced neural ODE, n = n_unit (weights drawn once, seeded)
 
 Every generator returns a dict of contiguous numpy arrays in the library's
 series-major layouts (see ``include/tvi.h``).
@@ -137,3 +139,41 @@ def neuron(n_unit=1, n_batch=3, n_time=2000, t_max=10.0):
     n = 4 * n_unit
     return dict(kind="neuron", n=n, y0=np.zeros((n_batch, n)), times=np.linspace(0.0, t_max, n_time + 1),
                 params=params, offsets=None)
+
+
+def mds(n_unit=1, n_batch=3, n_time=2000, t_max=1.0):
+    """The mass-damper-spring timing case: K_i = linspace(1e-2, 1, n_unit),
+    C_i = linspace(1e-6, 1e-4, n_unit), M_i = linspace(1e-7, 1e-5, n_unit),
+    f_a = 1, T = linspace(1e-2, 1, n_batch) (one value per series), t in
+    [0, t_max] in n_time equal steps, zero initial state.  State (d_1, v_1, ...,
+    d_nu, v_nu); parameter vector per series (K_1..K_nu, C_1..C_nu, M_1..M_nu,
+    f_a, T)."""
+    nu = n_unit
+    base = np.concatenate([np.linspace(1e-2, 1.0, nu), np.linspace(1e-6, 1e-4, nu), np.linspace(1e-7, 1e-5, nu)])
+    params = np.array([np.concatenate([base, [1.0, T]]) for T in np.linspace(1e-2, 1.0, n_batch)])
+    n = 2 * nu
+    return dict(kind="mds", n=n, y0=np.zeros((n_batch, n)), times=np.linspace(0.0, t_max, n_time + 1),
+                params=params, offsets=None)
+
+
+def fnode_weights(n_unit, seed=140):
+    """The forced neural ODE's layers: W1, b1 (n+1 -> n+1), W2, b2 (n+1 -> n+1),
+    W3, b3 (n+1 -> n), every entry U(-sqrt(1/(n+1)), sqrt(1/(n+1))), drawn once
+    in that order."""
+    rng = np.random.default_rng(seed)
+    m = n_unit + 1
+    a = np.sqrt(1.0 / m)
+    shapes = ((m, m), (m,), (m, m), (m,), (n_unit, m), (n_unit,))
+    return np.concatenate([rng.uniform(-a, a, size=sh).reshape(-1) for sh in shapes])
+
+
+def fnode(n_unit=1, n_batch=3, n_time=2000, t_max=1.0, seed=140):
+    """The neural-ODE timing case: dy/dt = tanh(L3(tanh(L2(tanh(L1(y, f(t))))))),
+    the layers from fnode_weights (fixed for every series), f(t) = f_a sin(2 pi t / T)
+    with f_a = 1 and T = linspace(1e-2, 1, n_batch) (one value per series), t in
+    [0, t_max] in n_time equal steps, zero initial state.  Parameter vector per
+    series (W1, b1, W2, b2, W3, b3, f_a, T)."""
+    w = fnode_weights(n_unit, seed)
+    params = np.array([np.concatenate([w, [1.0, T]]) for T in np.linspace(1e-2, 1.0, n_batch)])
+    return dict(kind="fnode", n=n_unit, y0=np.zeros((n_batch, n_unit)),
+                times=np.linspace(0.0, t_max, n_time + 1), params=params, offsets=None)

@@ -7,6 +7,7 @@ import pytest
 
 import oracle
 from tests import test_oracle_forward_euler as fe
+from tests import test_oracle_mds_fnode as mf
 from tests import test_oracle_paper_models as pm
 from tests import test_oracle_pins as pins
 
@@ -27,7 +28,9 @@ MUTATIONS = [
      [pins.test_lin_adjoint_closed_form, pins.test_adjoint_fd_vanderpol]),
     ("adjoint_dropped_g0", "pb->dLdy0[b * n + i] = G[i] + lam[i];", "pb->dLdy0[b * n + i] = lam[i];",
      [pins.test_lin_adjoint_closed_form]),
-    ("mlp_vjp_dropped_tanh_derivative", "d1[k] = s * (1.0 - a1[k] * a1[k]);", "d1[k] = s;",
+    ("mlp_vjp_dropped_tanh_derivative",
+     "for (int i = 0; i < H; ++i) s += W2[i * H + k] * d2[i];\n            d1[k] = s * (1.0 - a1[k] * a1[k]);",
+     "for (int i = 0; i < H; ++i) s += W2[i * H + k] * d2[i];\n            d1[k] = s;",
      [lambda: pins.test_model_param_vjp_matches_central_differences(pins._model_cases()[3])]),
     ("mlp_w2_transposed", "for (int k = 0; k < H; ++k) s += W2[i * H + k] * a1[k];",
      "for (int k = 0; k < H; ++k) s += W2[k * H + i] * a1[k];",
@@ -58,6 +61,24 @@ MUTATIONS = [
     ("neuron_coupling_jacobian", "r[4 * j] = (j == i) ? 0.0 : -q[NR_GC] / q[NR_C];",
      "r[4 * j] = (j == i) ? 0.0 : q[NR_GC] / q[NR_C];",
      [lambda: pm.test_rate_jacobian_and_parameter_gradient_match_autograd(pm._cases()[10])]),
+    # mass-damper-spring: a damper acting one unit off, a spring dividing by the
+    # neighbour's mass, the wall not holding, the force on the wrong mass
+    ("mds_damper_index", "if (i > 0) a -= K[i - 1] * (d - y[2 * i - 2]) + C[i - 1] * (v - y[2 * i - 1]);",
+     "if (i > 0) a -= K[i - 1] * (d - y[2 * i - 2]) + C[i] * (v - y[2 * i - 1]);",
+     [lambda: mf.test_mds_momentum_balance_every_step(2), lambda: mf.test_mds_backward_euler_energy_identity(2, True),
+      lambda: mf.test_mds_rate_and_jacobian_match_element_assembly(2)]),
+    ("mds_spring_over_neighbour_mass", "*acc = a / M[i];", "*acc = a / M[i + 1 < nu ? i + 1 : i];",
+     [lambda: mf.test_mds_momentum_balance_every_step(2), lambda: mf.test_mds_backward_euler_energy_identity(2, False)]),
+    ("mds_wall_released", "const double dn = (i + 1 < nu) ? y[2 * i + 2] : 0.0, vn = (i + 1 < nu) ? y[2 * i + 3] : 0.0;\n    double a",
+     "const double dn = (i + 1 < nu) ? y[2 * i + 2] : y[2 * i], vn = (i + 1 < nu) ? y[2 * i + 3] : y[2 * i + 1];\n    double a",
+     [lambda: mf.test_mds_momentum_balance_every_step(1), mf.test_mds_single_unit_converges_to_forced_oscillator]),
+    ("mds_force_sign", "f[2 * i + 1] = a + (i == 0 ? p[3 * nu] * sin(", "f[2 * i + 1] = a - (i == 0 ? p[3 * nu] * sin(",
+     [lambda: mf.test_mds_momentum_balance_every_step(2), mf.test_mds_single_unit_converges_to_forced_oscillator]),
+    # forced neural ODE: the output tanh dropped, the forcing fed at the wrong input
+    ("fnode_output_tanh_dropped", "J[i * n + c] = (1.0 - f[i] * f[i]) * s;", "J[i * n + c] = s;",
+     [lambda: mf.test_fnode_rate_jacobian_and_parameter_gradient_match_autograd(5)]),
+    ("fnode_forcing_input_column", "gx += q.W1[i * m + n] * d1[i];", "gx += q.W1[i * m] * d1[i];",
+     [lambda: mf.test_fnode_rate_jacobian_and_parameter_gradient_match_autograd(5)]),
 ]
 
 
