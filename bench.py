@@ -37,6 +37,7 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 PEAK_BF16_TFLOPS = 2500.0
 TIMING_TOL = (1e-8, 1e-6)
+COPY_PROBE_BYTES = 1 << 28  # the plain device copy that calibrates the HBM byte counters
 MLP_F_FLOPS = 2 * (64 * 8 + 64 * 64 + 8 * 64)      # h(y): three layers
 MLP_J_FLOPS = 2 * (64 * 64 * 8 + 8 * 64 * 8) + 2 * 64 * 8  # W3 diag W2 diag W1
 
@@ -118,6 +119,69 @@ def measured_traffic(kernel):
     if not rec or rec.get("source_hash") != csrc_hash(rec.get("sources")):
         return None
     return rec["bytes_per_dispatch"]
+
+
+# Files each solver kernel is built from: its traffic record goes stale when one changes.
+KERNEL_SOURCES = {"Robertson": ["model_robertson.hip", "solver.hpp", "device.hpp", "models.hpp", "dual.hpp",
+                                "dispatch.hpp"],
+                  "VanDerPol": ["model_vanderpol.hip", "solver.hpp", "device.hpp", "models.hpp", "dual.hpp",
+                                "dispatch.hpp"],
+                  "pcr_kernel": ["pcr.hip", "device.hpp", "solver.hpp", "models.hpp", "dual.hpp", "dispatch.hpp"]}
+
+
+def _counter_rows(path):
+    """(kernel name, dispatch id, counter value) from a rocprofv3 counter_collection.csv
+    (the file itself, or the directory it was written under)."""
+    import csv
+    import glob
+    if os.path.isdir(path):
+        found = glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True)
+        if not found:
+            raise FileNotFoundError("no counter_collection.csv under " + path)
+        path = found[0]
+    out = []
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            name = r["Kernel_Name"]
+            if name.startswith("void "):
+                name = name[5:]
+            out.append((name, r.get("Dispatch_Id", r.get("Correlation_Id")), float(r["Counter_Value"])))
+    return out
+
+
+def record_traffic(fetch_path, write_path, copy_bytes):
+    """Write profiles/traffic.json from two rocprofv3 --pmc runs of the same command
+    (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch).  Each counter is scaled by what
+    it reads for the plain device copy of copy_bytes bytes in the same run (the
+    largest __amd_rocclr_copyBuffer dispatch): bytes = KiB * 1024 * scale."""
+    def per_kernel(rows):
+        acc = {}
+        for name, disp, v in rows:
+            acc.setdefault(name, {}).setdefault(disp, 0.0)
+            acc[name][disp] += v  # counters summed over the dispatch's instances
+        return {k: list(d.values()) for k, d in acc.items()}
+    fetch, write = per_kernel(_counter_rows(fetch_path)), per_kernel(_counter_rows(write_path))
+    copy = "__amd_rocclr_copyBuffer"
+    f_scale = copy_bytes / (max(fetch[copy]) * 1024.0)
+    w_scale = copy_bytes / (max(write[copy]) * 1024.0)
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            table = json.load(f)
+    except (OSError, ValueError):
+        table = {}
+    for name in fetch:
+        if name not in write or not name.startswith("tvi::"):
+            continue
+        srcs = next((v for k, v in KERNEL_SOURCES.items() if k in name), None)
+        fv, wv = fetch[name], write[name]
+        table[name] = {"bytes_per_dispatch": (sum(fv) / len(fv) * f_scale + sum(wv) / len(wv) * w_scale) * 1024.0,
+                       "fetch_kib": sum(fv) / len(fv), "write_kib": sum(wv) / len(wv), "dispatches": len(fv),
+                       "fetch_scale": f_scale, "write_scale": w_scale, "sources": srcs,
+                       "source_hash": csrc_hash(srcs)}
+    with open(path, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    return table
 
 
 def time_launches(fn, reps, stream):
@@ -910,7 +974,15 @@ def main():
     ap.add_argument("--only", default="", help="comma-separated side measurements to run (with --extras)")
     ap.add_argument("--probe-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH", "WRITE"),
+                    help="no GPU work: write profiles/traffic.json from the counter_collection.csv of a "
+                         "rocprofv3 --pmc FETCH_SIZE run and of a --pmc WRITE_SIZE run of this script "
+                         "with --probe-copy")
     args = ap.parse_args()
+    if args.record_traffic:
+        table = record_traffic(args.record_traffic[0], args.record_traffic[1], COPY_PROBE_BYTES)
+        print(json.dumps({k: round(v["bytes_per_dispatch"]) for k, v in table.items()}, indent=1))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (series are independent and "
               "would shard across GPUs, each running the same kernels on its share)", file=sys.stderr)
@@ -952,7 +1024,7 @@ def main():
         log("side measurements written to %s" % args.extras)
 
     if args.probe_copy:
-        src = torch.ones(1 << 25, dtype=torch.float64, device=dev)
+        src = torch.ones(COPY_PROBE_BYTES // 8, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()

@@ -229,3 +229,36 @@ def test_bench_code_hash_ignores_comments_only(tmp_path, monkeypatch):
     assert b.csrc_hash() == h0
     f.write_text(text.replace("kWave", "kWave + 0", 1))
     assert b.csrc_hash() != h0
+
+
+def test_bench_records_traffic_from_counter_csvs(monkeypatch, tmp_path):
+    """The traffic record: per-kernel FETCH_SIZE and WRITE_SIZE (KiB per dispatch)
+    scaled by what each counter reads for the plain copy of known size."""
+    import json
+    import os
+    import shutil
+    b, _ = _bench()
+    kern = "tvi::forward_kernel<tvi::Robertson, double, 64, 8, false, false, false>(tvi::SolveArgs<double>)"
+    hdr = "Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n"
+
+    def csv(path, counter, copy_kib, k1, k2):
+        path.mkdir()
+        (path / "run_counter_collection.csv").write_text(
+            hdr + '1,"__amd_rocclr_copyBuffer",%s,%r\n' % (counter, copy_kib)
+            + '2,"void %s",%s,%r\n' % (kern, counter, k1) + '3,"void %s",%s,%r\n' % (kern, counter, k2))
+
+    csv(tmp_path / "f", "FETCH_SIZE", 131072.0, 100.0, 300.0)   # fetch reads half the copy's bytes
+    csv(tmp_path / "w", "WRITE_SIZE", 262144.0, 1000.0, 1000.0)
+    (tmp_path / "profiles").mkdir()
+    csrc = tmp_path / "paper_2310_08649_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    for name in b.KERNEL_SOURCES["Robertson"]:
+        shutil.copy(os.path.join(b.ROOT, "paper_2310_08649_amd", "csrc", name), csrc / name)
+    monkeypatch.setattr(b, "ROOT", str(tmp_path))
+    table = b.record_traffic(str(tmp_path / "f"), str(tmp_path / "w"), 1 << 28)
+    rec = table[kern]
+    assert abs(rec["fetch_scale"] - 2.0) < 1e-12 and abs(rec["write_scale"] - 1.0) < 1e-12
+    assert rec["bytes_per_dispatch"] == (200.0 * 2.0 + 1000.0) * 1024.0
+    assert json.loads((tmp_path / "profiles" / "traffic.json").read_text())[kern]["dispatches"] == 2
+    assert b.measured_traffic(kern) == rec["bytes_per_dispatch"]
+    assert "__amd_rocclr_copyBuffer" not in table
