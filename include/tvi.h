@@ -105,7 +105,9 @@ typedef enum {
     TVI_EINVAL = -1,
     TVI_EHIP = -2,
     TVI_ENOMEM = -3,
-    TVI_EUNSUPPORTED = -4
+    TVI_EUNSUPPORTED = -4,
+    TVI_ESCRATCH = -5      /* the workspace a call needs exceeds the static scratch of
+                              tvi_solve_adjoint_noalloc (TVI_NOALLOC_SCRATCH_BYTES)  */
 } tvi_status;
 
 typedef enum {
@@ -290,6 +292,33 @@ tvi_status tvi_solve_adjoint(const tvi_model *model, const tvi_options *opt, int
                              const void *y, const void *ckpt, const void *g, void *dLdp,
                              void *dLdy0, int32_t *status, void *workspace, size_t workspace_bytes,
                              void *stream);
+
+/*
+ * tvi_solve_adjoint_noalloc -- tvi_solve_adjoint for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  The same computation and kernels, with the
+ * workspace taken from a static device array of TVI_NOALLOC_SCRATCH_BYTES
+ * bytes instead of a caller buffer; each GPU the library runs on holds its own
+ * copy of that array until the process ends.  Nothing is allocated or freed.
+ *
+ * Arguments as tvi_solve_adjoint without the workspace.  The current device
+ * (hipSetDevice) must be the one `stream` belongs to: its copy of the array is
+ * used, its address looked up on the first call on that device.
+ * Returns TVI_ESCRATCH, with nothing enqueued, when
+ * tvi_adjoint_workspace_bytes(model, opt, B) exceeds TVI_NOALLOC_SCRATCH_BYTES
+ * (recomputed states need B * chunk * n doubles, the neural ODE B * P floats),
+ * TVI_EHIP when the array's address cannot be obtained, otherwise what
+ * tvi_solve_adjoint returns.  The array keeps the last call's contents; every
+ * byte a call reads from it was written earlier in the same call, so nothing
+ * needs clearing.  Calls on one GPU share the array: calls that overlap in
+ * time there (two streams, or two host threads) race and give undefined
+ * results; calls in sequence on one stream are safe.
+ */
+#define TVI_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+tvi_status tvi_solve_adjoint_noalloc(const tvi_model *model, const tvi_options *opt, int64_t B, int64_t N,
+                                     const int64_t *offsets, const void *times, const void *params,
+                                     const void *y, const void *ckpt, const void *g, void *dLdp, void *dLdy0,
+                                     int32_t *status, void *stream);
 
 /*
  * tvi_loss_grad -- value and gradient g = dL/dy of the losses the benchmarks

@@ -1,5 +1,6 @@
 // C ABI entry points (declared in tvi.h): argument checks on the host, choice
 // of the lane tiling, and the launch on the caller's stream.
+#include <mutex>
 #include <string.h>
 
 #include "dispatch.hpp"
@@ -161,6 +162,31 @@ tvi_status dispatch(int pass, const tvi_model *model, const void *args, int S, i
     }
 }
 
+// Static device scratch of tvi_solve_adjoint_noalloc.  Host code must not
+// pass `scratch` itself to a kernel (in host code it names a host-side
+// stand-in): the device address of each GPU's copy comes from
+// hipGetSymbolAddress, looked up once per device and kept.
+static __device__ __align__(256) unsigned char scratch[TVI_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mutex;
+void *scratch_ptr[kMaxDevices] = {};
+
+tvi_status device_scratch(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return TVI_EHIP;
+    if (dev >= kMaxDevices) return TVI_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    if (!scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return TVI_EHIP;
+        scratch_ptr[dev] = p;
+    }
+    *out = scratch_ptr[dev];
+    return TVI_OK;
+}
+
 } // namespace
 
 extern "C" {
@@ -198,6 +224,7 @@ const char *tvi_status_str(int32_t s)
     case TVI_EHIP: return "HIP launch or runtime error";
     case TVI_ENOMEM: return "out of memory";
     case TVI_EUNSUPPORTED: return "unsupported model, size or tiling";
+    case TVI_ESCRATCH: return "workspace needed exceeds the static scratch of the allocation-free entry point";
     default: return "unknown status";
     }
 }
@@ -349,6 +376,22 @@ tvi_status tvi_solve_adjoint(const tvi_model *model, const tvi_options *opt, int
     a.status = status;
     a.ws = static_cast<double *>(workspace);
     return dispatch(pass, model, &a, S, T, st, opt->jacobian);
+}
+
+tvi_status tvi_solve_adjoint_noalloc(const tvi_model *model, const tvi_options *opt, int64_t B, int64_t N,
+                                     const int64_t *offsets, const void *times, const void *params, const void *y,
+                                     const void *ckpt, const void *g, void *dLdp, void *dLdy0, int32_t *status,
+                                     void *stream)
+{
+    tvi_status e = check_model(model);
+    if (e != TVI_OK) return e;
+    if ((e = check_options(opt)) != TVI_OK) return e;
+    if (B < 0) return TVI_EINVAL;
+    if (tvi_adjoint_workspace_bytes(model, opt, B) > TVI_NOALLOC_SCRATCH_BYTES) return TVI_ESCRATCH;
+    void *ws = nullptr;
+    if ((e = device_scratch(&ws)) != TVI_OK) return e;
+    return tvi_solve_adjoint(model, opt, B, N, offsets, times, params, y, ckpt, g, dLdp, dLdy0, status, ws,
+                             TVI_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 size_t tvi_loss_workspace_bytes(void) { return loss_workspace_bytes(); }

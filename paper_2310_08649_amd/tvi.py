@@ -82,6 +82,8 @@ def load():
         lib.tvi_adjoint_workspace_bytes.restype = sz
         lib.tvi_solve_adjoint.argtypes = [MP, OP, i64, i64, P, P, P, P, P, P, P, P, P, P, sz, P]
         lib.tvi_solve_adjoint.restype = i32
+        lib.tvi_solve_adjoint_noalloc.argtypes = [MP, OP, i64, i64, P, P, P, P, P, P, P, P, P, P]
+        lib.tvi_solve_adjoint_noalloc.restype = i32
         lib.tvi_loss_workspace_bytes.argtypes = []
         lib.tvi_loss_workspace_bytes.restype = sz
         lib.tvi_loss_grad.argtypes = [i32, i32, i64, i32, P, P, i64, P, P, P, sz, P]
@@ -245,11 +247,13 @@ def solve_forward(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e
 def solve_adjoint(kind, times, params, g, y=None, ckpt=None, offsets=None, chunk=64, tol=(1e-8, 1e-6),
                   max_newton=50, lanes=0, steps_per_lane=0, init="zero", halving=True, n=None, predictor=None,
                   order=None, scheme="backward_euler", jacobian="analytic", n_max=None,
-                  reference="first"):
+                  reference="first", noalloc=False):
     """Discrete adjoint.  Returns ``(dLdp [B,P], dLdy0 [B,n], status [B])``.
 
     States come from the trajectory ``y`` or, when ``y`` is None, are recomputed
-    from ``ckpt`` (then the options must equal those of the forward pass)."""
+    from ``ckpt`` (then the options must equal those of the forward pass).
+    ``noalloc=True`` calls ``tvi_solve_adjoint_noalloc``: the workspace is the
+    library's static device scratch instead of a tensor allocated here."""
     dt = g.dtype
     times = _dev(times, dt, "times")
     params = _dev(params, dt, "params")
@@ -278,6 +282,11 @@ def solve_adjoint(kind, times, params, g, y=None, ckpt=None, offsets=None, chunk
     dLdp = torch.empty((P,) if shared else (B, P), dtype=dt, device=dev)
     dLdy0 = torch.empty((B, n), dtype=dt, device=dev)
     status = torch.empty(B, dtype=torch.int32, device=dev)
+    if noalloc:
+        _check(lib.tvi_solve_adjoint_noalloc(ctypes.byref(model), ctypes.byref(opt), B, N, _ptr(offsets),
+                                             _ptr(times), _ptr(params), _ptr(y), _ptr(ckpt), _ptr(g), _ptr(dLdp),
+                                             _ptr(dLdy0), _ptr(status), _stream()), "tvi_solve_adjoint_noalloc")
+        return dLdp, dLdy0, status
     ws, wsb = None, 0
     if y is None or kind == "mlp":
         wsb = lib.tvi_adjoint_workspace_bytes(ctypes.byref(model), ctypes.byref(opt), B)

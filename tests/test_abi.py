@@ -231,3 +231,20 @@ def test_reference_residual_option_is_checked(lib):
     assert tvi.make_options().reference_residual == 0
     o = tvi.make_options(chunk=16, reference=2)
     assert lib.tvi_solve_forward(ctypes.byref(m), ctypes.byref(o), 4, 10, None, f, f, f, f, None, f, None, None) == -1
+
+
+def test_noalloc_adjoint_rejects_more_than_its_scratch_on_the_host(lib):
+    """tvi_solve_adjoint_noalloc refuses a workspace above its static scratch
+    (TVI_ESCRATCH) on the host, before any HIP call."""
+    from paper_2310_08649_amd import tvi
+    o = tvi.make_options(chunk=512)
+    m = tvi.Model(2, 3, tvi.F64, 0, 64)
+    assert lib.tvi_adjoint_workspace_bytes(ctypes.byref(m), ctypes.byref(o), 4096) > (32 << 20)
+    f = _fake()
+    assert lib.tvi_solve_adjoint_noalloc(ctypes.byref(m), ctypes.byref(o), 4096, 100, None, f, f, None, f, f, f, f, f,
+                                         None) == -5
+    assert lib.tvi_status_str(-5).startswith(b"workspace needed exceeds")
+    # bad options are still refused first
+    o.chunk = 0
+    assert lib.tvi_solve_adjoint_noalloc(ctypes.byref(m), ctypes.byref(o), 4, 100, None, f, f, None, f, f, f, f, f,
+                                         None) == -1
