@@ -619,7 +619,7 @@ def run_pcr(ctx, steps):
     res = []
     target = 4 << 30
     for dt, n in ((torch.float64, 2), (torch.float64, 3), (torch.float64, 4), (torch.float32, 2),
-                  (torch.float32, 4)):
+                  (torch.float32, 4), (torch.float32, 8)):
         m = 64
         es = torch.finfo(dt).bits // 8
         per_sys = m * (n * n + 2 * n) * es
@@ -799,6 +799,82 @@ def run_paper_grid(ctx, steps):
             out["%s_nu%d_B%d" % (kind, nu, nb)] = row
             best_by_model[kind] = max(best_by_model.get(kind, 0.0), sp)
     out["best_speedup"] = best_by_model
+    return out
+
+
+def run_block_grid(ctx, steps):
+    """The paper's chunk-efficiency study (Section 5.3, its parameter table) on
+    the problems the block solver takes: the mass-damper-spring chain
+    (n_unit 1, 2, 3, 5, 10; n = 2 n_unit), the coupled neurons with 3 to 10
+    units (n = 12..40) and the forced neural ODE (n_unit 1, 5, ..., 25), FP64,
+    n_time = 2000, chunks {1, 3, 10, 30, 100, 300, 1000}, each with Thomas's
+    algorithm (T = chunk) and with PCR (T = 1), forward + Frobenius-loss
+    gradient + adjoint as one captured graph (states read from the stored
+    trajectory), at the batch sizes the table lists (largest and smallest)."""
+    import torch
+    from paper_2310_08649_amd import graph, workloads
+    dev = ctx["dev"]
+    d = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev)
+    out = {"unit": "ms per forward+adjoint", "paper_best_speedup": {"mass_damper_spring": 106, "neuron": 94,
+                                                                    "neural_ode": 97}}
+    grid = [("mds", nu, (3, 100)) for nu in (1, 2, 3, 5, 10)] + \
+           [("neuron", nu, (3, 50)) for nu in (3, 5, 10)] + \
+           [("fnode", nu, (3, 100)) for nu in (1, 5, 10, 15, 20, 25)]
+    best_by_model = {}
+    for kind, nu, batches in grid:
+        for nb in batches:
+            w = getattr(workloads, kind)(nu, nb)
+            row = {}
+            for C in (1, 3, 10, 30, 100, 300, 1000):
+                for name, T in (("thomas", C), ("pcr", 1)):
+                    if C == 1 and name == "pcr":
+                        continue
+                    cs = graph.CapturedStep(kind, d(w["y0"]), d(w["times"]), d(w["params"]), chunk=C,
+                                            steps_per_lane=T, tol=TIMING_TOL, loss="frobenius",
+                                            recompute=False).capture()
+                    cs.replay()
+                    st = stats(time_launches(cs.replay, 3, torch.cuda.current_stream()))
+                    failed = int(((cs.status_fwd != 0) | (cs.status_adj != 0)).sum().item())
+                    row["C%d_%s" % (C, name)] = {"ms": st["median_ms"], "failed": failed}
+                    del cs
+            ok = {k: v["ms"] for k, v in row.items() if v["failed"] == 0}
+            bk = min(ok, key=ok.get)
+            sp = row["C1_thomas"]["ms"] / ok[bk]
+            row["best"] = {"config": bk, "ms": ok[bk], "speedup_over_chunk1": sp}
+            out["%s_nu%d_B%d" % (kind, nu, nb)] = row
+            log("block grid %s nu=%d B=%d best %s %.3f ms (%.1fx over chunk 1)" % (kind, nu, nb, bk, ok[bk], sp))
+            best_by_model[kind] = max(best_by_model.get(kind, 0.0), sp)
+    out["best_speedup"] = best_by_model
+    return out
+
+
+def run_crossover(ctx, steps):
+    """Thomas against PCR and the hybrids over the state size (Section 3: PCR
+    pays log2 levels of n^3 block products, Thomas a serial chain of n^2
+    products): the mass-damper-spring chain at n = 2, 4, 8, 12, 20, 40, 100
+    series, 2000 steps, chunk 100 and 1000, forward + adjoint graph, every
+    segment length T (T = chunk: Thomas; T = 1: PCR)."""
+    import torch
+    from paper_2310_08649_amd import graph, workloads
+    dev = ctx["dev"]
+    d = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev)
+    out = {"unit": "ms per forward+adjoint", "series": 100, "n_time": 2000}
+    for nu in (1, 2, 4, 6, 10, 20):
+        w = workloads.mds(nu, 100)
+        for C in (100, 1000):
+            row = {}
+            for T in sorted({C, 1, 4, 16, 64} - {t for t in (4, 16, 64) if t >= C}):
+                cs = graph.CapturedStep("mds", d(w["y0"]), d(w["times"]), d(w["params"]), chunk=C, steps_per_lane=T,
+                                        tol=TIMING_TOL, loss="frobenius", recompute=False).capture()
+                cs.replay()
+                st = stats(time_launches(cs.replay, 3, torch.cuda.current_stream()))
+                failed = int(((cs.status_fwd != 0) | (cs.status_adj != 0)).sum().item())
+                row["T%d" % T] = {"ms": st["median_ms"], "failed": failed}
+                del cs
+            best = min((k for k in row if row[k]["failed"] == 0), key=lambda k: row[k]["ms"])
+            row["best"] = best
+            out["n%d_C%d" % (2 * nu, C)] = row
+            log("crossover n=%d C=%d best %s" % (2 * nu, C, best))
     return out
 
 
@@ -1015,7 +1091,8 @@ def main():
         runs = vdp_runs + [("linear", run_linear), ("tiling_study", run_tiling_study),
                            ("saturated", run_saturated), ("pcr_roofline", run_pcr), ("mlp", run_mlp),
                            ("predictor", run_predictor), ("forward_euler", run_forward_euler),
-                           ("paper_grid", run_paper_grid), ("forward_ad", run_forward_ad)]
+                           ("paper_grid", run_paper_grid), ("forward_ad", run_forward_ad),
+                           ("block_grid", run_block_grid), ("crossover", run_crossover)]
         for name, fn in runs:
             if want(name):
                 extra(ext, name, lambda fn=fn: fn(ctx, args.steps))

@@ -72,7 +72,30 @@
  *                  + g_C sum_j (V_i - V_j)) / C_i, dx/dt = (x_inf - x)/tau_x,
  *                  p = (C, g_Na, E_Na, g_K, E_K, g_L, E_L, m_inf, tau_m, h_inf, tau_h, n_inf,
  *                  tau_n, g_C, T) per neuron, then I_a (P = 15 nu + 1); TVI_F64 only; two
- *                  neurons: one step per lane, backward Euler, analytic Jacobian
+ *                  neurons: one step per lane, backward Euler, analytic Jacobian; 3 to 10
+ *                  neurons (n = 12..40): the block solver
+ *   TVI_MDS        the mass-damper-spring chain (Section 5.1.1) of nu = n / 2 units, n even,
+ *                  2 <= n <= 40, state (d_1, v_1, ..., d_nu, v_nu):
+ *                  dd_i/dt = v_i, dv_i/dt = [K_i (d_{i+1} - d_i) + C_i (v_{i+1} - v_i)
+ *                  - K_{i-1} (d_i - d_{i-1}) - C_{i-1} (v_i - v_{i-1})] / M_i + f_i(t),
+ *                  position nu + 1 the wall (d = v = 0), no i - 1 terms for the first unit,
+ *                  f_1 = f_a sin(2 pi t / T), f_i = 0 otherwise;
+ *                  p = (K_1..K_nu, C_1..C_nu, M_1..M_nu, f_a, T) (P = 3 nu + 2); block solver
+ *   TVI_FNODE      the forced neural ODE (Section 5.1.1), 1 <= n <= 40: x = (y, f_a sin(2 pi t / T)),
+ *                  h = tanh(W3 tanh(W2 tanh(W1 x + b1) + b2) + b3), W1, W2 (n+1) x (n+1),
+ *                  W3 n x (n+1); p = (W1, b1, W2, b2, W3, b3, f_a, T) row-major, per series
+ *                  (P = 2 (n+1)^2 + 2 (n+1) + n (n+1) + n + 2); block solver
+ *
+ * The block solver (models above marked so) keeps one n x n block per wavefront,
+ * one row per lane, one workgroup of 8 wavefronts per series (Section 3 for
+ * blocks too large for one lane): TVI_F64, per-series parameters, backward
+ * Euler, zero or extrapolated start, chunk <= 1024.  tvi_options.steps_per_lane
+ * is its segment length T: each segment composes T steps serially (Thomas's
+ * algorithm) and ceil(log2(chunk / T)) PCR levels join the segments; T = chunk
+ * (or 0) is Thomas's algorithm, T = 1 pure PCR (lanes is ignored).  Its
+ * forward pass needs tvi_options.workspace of tvi_forward_workspace_bytes()
+ * bytes; its adjoint reads the stored trajectory (no recomputation) and needs
+ * the workspace of tvi_adjoint_workspace_bytes().
  */
 #ifndef TVI_H
 #define TVI_H
@@ -90,7 +113,9 @@ typedef enum {
     TVI_ROBERTSON = 2,
     TVI_MLP = 3,
     TVI_CHABOCHE = 4,
-    TVI_NEURON = 5
+    TVI_NEURON = 5,
+    TVI_MDS = 6,
+    TVI_FNODE = 7
 } tvi_model_kind;
 
 typedef enum { TVI_F32 = 0, TVI_F64 = 1 } tvi_dtype;
@@ -183,6 +208,10 @@ typedef struct {
                                   no AD Jacobian, not the
                                   one-step-per-lane models (TVI_EUNSUPPORTED
                                   otherwise); the neural ODE: any start          */
+    void *workspace;           /* block-solver forward pass: device buffer of
+                                  tvi_forward_workspace_bytes() bytes (caller-owned,
+                                  contents need no initialisation); NULL otherwise */
+    size_t workspace_bytes;    /* its size                                           */
 } tvi_options;
 
 /* Fills `opt` with the defaults: chunk 64, tol_a 1e-8, tol_r 1e-6 (Section 2.3),
@@ -230,7 +259,9 @@ tvi_status tvi_model_eval(const tvi_model *model, int64_t M, const void *states,
  * ceil(log2(lanes)) reduction levels run across the lanes of the system.
  *
  *   D  [B][m][n][n]   r, x  [B][m][n]     (dtype float or double, device)
- *   n in {2, 3, 4}, 1 <= m <= 512.
+ *   n in {2, 3, 4}, 1 <= m <= 512; n = 8 (the neural ODE's blocks) with
+ *   TVI_F32 and 1 <= m <= 128.  Double storage computes in double, float
+ *   storage in float.
  * A system with a singular block gets NaN in x.  Returns TVI_OK once enqueued,
  * TVI_EINVAL on bad sizes or null pointers, TVI_EHIP on a launch failure.
  */
@@ -286,6 +317,13 @@ tvi_status tvi_solve_forward(const tvi_model *model, const tvi_options *opt, int
  *           or the code of a failed recomputation; that series' outputs are NaN
  */
 size_t tvi_adjoint_workspace_bytes(const tvi_model *model, const tvi_options *opt, int64_t B);
+
+/* Bytes of tvi_options.workspace the forward pass of B series needs: nonzero
+ * only for models solved by the block solver (per series: the chunk's inverse
+ * blocks, segment maps, offsets and Newton iterate, 8 (chunk (NP^2 + 2 NP) +
+ * 2 S NP^2 + ...) bytes with NP the state size padded to 8, 16, 24, 32 or 40
+ * and S = ceil(chunk / steps_per_lane)).  0 for unsupported arguments. */
+size_t tvi_forward_workspace_bytes(const tvi_model *model, const tvi_options *opt, int64_t B);
 
 tvi_status tvi_solve_adjoint(const tvi_model *model, const tvi_options *opt, int64_t B, int64_t N,
                              const int64_t *offsets, const void *times, const void *params,

@@ -3,32 +3,13 @@
 #include <mutex>
 #include <string.h>
 
+#include "api_common.hpp"
 #include "dispatch.hpp"
 
 using namespace tvi;
+using namespace tvi::api;
 
 namespace {
-
-bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
-
-int next_pow2(int v)
-{
-    int p = 1;
-    while (p < v) p <<= 1;
-    return p;
-}
-
-// Lanes per series S and steps per lane T for a chunk of C steps: the fewest
-// steps per lane that fit the chunk in one wavefront, then the fewest lanes.
-void choose_tiling(int C, int &S, int &T)
-{
-    if (C <= 1) { S = 1; T = 1; return; }
-    T = 1;
-    while (T < 8 && T * kWave < C) T <<= 1;
-    S = next_pow2((C + T - 1) / T);
-    if (S < 4) S = 4;
-    if (S > kWave) S = kWave;
-}
 
 int model_params(const tvi_model *m)
 {
@@ -38,6 +19,8 @@ int model_params(const tvi_model *m)
     case TVI_ROBERTSON: return 3;
     case TVI_CHABOCHE: return 8 + 2 * (m->n - 2);
     case TVI_NEURON: return 15 * (m->n / 4) + 1;
+    case TVI_MDS: return 3 * (m->n / 2) + 2;
+    case TVI_FNODE: return 2 * (m->n + 1) * (m->n + 1) + 2 * (m->n + 1) + m->n * (m->n + 1) + m->n + 2;
     case TVI_MLP: {
         const int n = m->n, H = m->hidden;
         return H * n + H + H * H + H + n * H + n;
@@ -57,9 +40,15 @@ tvi_status check_model(const tvi_model *m)
     case TVI_CHABOCHE:  // 1 to 5 backstresses in the register-resident solver
         if (m->n < 3) return TVI_EINVAL;
         return m->n <= 7 ? TVI_OK : TVI_EUNSUPPORTED;
-    case TVI_NEURON:    // one or two neurons
+    case TVI_NEURON:    // one or two neurons in registers, 3 to 10 by the block solver
         if (m->n < 4 || m->n % 4) return TVI_EINVAL;
-        return m->n <= 8 ? TVI_OK : TVI_EUNSUPPORTED;
+        return m->n <= blk::kMaxN ? TVI_OK : TVI_EUNSUPPORTED;
+    case TVI_MDS:
+        if (m->n < 2 || m->n % 2) return TVI_EINVAL;
+        return m->n <= blk::kMaxN ? TVI_OK : TVI_EUNSUPPORTED;
+    case TVI_FNODE:
+        if (m->n < 1) return TVI_EINVAL;
+        return m->n <= blk::kMaxN ? TVI_OK : TVI_EUNSUPPORTED;
     case TVI_MLP:
         if (m->n != 8) return TVI_EINVAL;
         return m->hidden == 64 ? TVI_OK : TVI_EUNSUPPORTED;
@@ -67,68 +56,68 @@ tvi_status check_model(const tvi_model *m)
     }
 }
 
-tvi_status resolve_tiling(const tvi_options *o, int &S, int &T)
+// Models solved by the block solver: the paper's mass-damper-spring chain and
+// forced neural ODE at every size, and more than two coupled neurons.
+bool is_block(const tvi_model *m)
 {
-    if (o->lanes == 0 && o->steps_per_lane == 0) {
-        choose_tiling(o->chunk, S, T);
-    } else {
-        S = o->lanes;
-        T = o->steps_per_lane;
-        if (!(S == 1 || pow2_in(S, 4, kWave)) || !pow2_in(T, 1, 8)) return TVI_EINVAL;
-    }
-    if ((int64_t)S * T < o->chunk) return TVI_EINVAL;
-    return TVI_OK;
+    return m->kind == TVI_MDS || m->kind == TVI_FNODE || (m->kind == TVI_NEURON && m->n > 8);
 }
 
-tvi_status check_options(const tvi_options *o)
+int block_nf(const tvi_model *m)
 {
-    if (!o) return TVI_EINVAL;
-    if (o->chunk < 1 || o->chunk > 8 * kWave) return TVI_EINVAL;
-    if (o->max_newton < 1) return TVI_EINVAL;
-    if (!(o->tol_a >= 0.0) || !(o->tol_r >= 0.0)) return TVI_EINVAL;
-    if (o->init != TVI_INIT_ZERO && o->init != TVI_INIT_EXTRAP && o->init != TVI_INIT_PREDICTOR) return TVI_EINVAL;
-    if (o->init == TVI_INIT_PREDICTOR &&
-        (!o->predictor || o->predictor_hidden < 1 || o->predictor_hidden > 256 || o->predictor_steps < o->chunk ||
-         (o->predictor_base != 0 && o->predictor_base != 1)))
-        return TVI_EINVAL;
-    if (o->scheme != TVI_BACKWARD_EULER && o->scheme != TVI_FORWARD_EULER) return TVI_EINVAL;
-    if (o->scheme == TVI_FORWARD_EULER && o->init == TVI_INIT_PREDICTOR) return TVI_EUNSUPPORTED;
-    if (o->jacobian != TVI_JACOBIAN_ANALYTIC && o->jacobian != TVI_JACOBIAN_FORWARD_AD) return TVI_EINVAL;
-    if (o->reference_residual != 0 && o->reference_residual != 1) return TVI_EINVAL;
-    if (o->jacobian == TVI_JACOBIAN_FORWARD_AD &&
-        (o->scheme != TVI_BACKWARD_EULER || o->init == TVI_INIT_PREDICTOR))
+    switch (m->kind) {
+    case TVI_MDS: return block_nf_mds(m->n);
+    case TVI_FNODE: return block_nf_fnode(m->n);
+    default: return block_nf_neuron(m->n);
+    }
+}
+
+// Steps per segment of the block solver: 0 = the whole chunk (Thomas's algorithm).
+int block_T(const tvi_options *o) { return o->steps_per_lane <= 0 || o->steps_per_lane > o->chunk ? o->chunk : o->steps_per_lane; }
+
+tvi_status check_block(const tvi_model *m, const tvi_options *o)
+{
+    if (m->dtype != TVI_F64 || m->params_shared) return TVI_EUNSUPPORTED;
+    if (o->chunk > blk::kMaxChunk || o->steps_per_lane < 0) return TVI_EINVAL;
+    if (o->scheme != TVI_BACKWARD_EULER || o->jacobian != TVI_JACOBIAN_ANALYTIC || o->reference_residual != 0 ||
+        o->init == TVI_INIT_PREDICTOR)
         return TVI_EUNSUPPORTED;
     return TVI_OK;
 }
 
-template <class IO>
-SolveArgs<IO> make_args(const tvi_model *model, const tvi_options *opt, int64_t B, int64_t N, const int64_t *offsets,
-                        const void *times, const void *y0, const void *params)
+size_t block_ws_bytes(const tvi_model *m, const tvi_options *o, int64_t B, bool adjoint)
 {
-    SolveArgs<IO> a;
-    memset(&a, 0, sizeof(a));
-    a.B = B;
-    a.N = N;
-    a.K = (N + opt->chunk - 1) / opt->chunk + 1;
-    a.offsets = offsets;
-    a.times = static_cast<const IO *>(times);
-    a.y0 = static_cast<const IO *>(y0);
-    a.params = static_cast<const IO *>(params);
-    a.params_shared = model->params_shared;
-    a.chunk = opt->chunk;
-    a.max_newton = opt->max_newton;
-    a.init = opt->init;
-    a.halving = opt->halving;
-    a.tol_a = opt->tol_a;
-    a.tol_r = opt->tol_r;
-    a.pred = static_cast<const float *>(opt->predictor);
-    a.pred_hidden = opt->predictor_hidden;
-    a.pred_steps = opt->predictor_steps;
-    a.pred_base = opt->predictor_base;
-    a.order = opt->order;
-    a.scheme = opt->scheme;
-    a.zero_ref = opt->reference_residual;
-    return a;
+    const blk::WsLayout l = blk::ws_layout(blk::padded(m->n), o->chunk, block_T(o), adjoint ? block_nf(m) : 0);
+    return (size_t)B * (size_t)l.total * sizeof(double);
+}
+
+tvi_status launch_block(int pass, const tvi_model *m, const blk::BlockArgs *ba, const blk::EvalArgs *ev,
+                        hipStream_t st)
+{
+    switch (m->kind) {
+    case TVI_MDS: return launch_block_mds(pass, m->n, ba, ev, st);
+    case TVI_FNODE: return launch_block_fnode(pass, m->n, ba, ev, st);
+    default: return launch_block_neuron(pass, m->n, ba, ev, st);
+    }
+}
+
+tvi_status solve_block(int pass, const tvi_model *m, const tvi_options *o, const SolveArgs<double> &a, void *ws,
+                       size_t ws_bytes, hipStream_t st)
+{
+    tvi_status e = check_block(m, o);
+    if (e != TVI_OK) return e;
+    const bool adj = pass != 0;
+    if (!ws || ws_bytes < block_ws_bytes(m, o, a.B, adj)) return TVI_EINVAL;
+    if (a.B > 0x7fffffffLL) return TVI_EINVAL;
+    blk::BlockArgs ba;
+    ba.a = a;
+    ba.n = m->n;
+    ba.P = model_params(m);
+    ba.T = block_T(o);
+    ba.NF = adj ? block_nf(m) : 0;
+    ba.ws_stride = blk::ws_layout(blk::padded(m->n), o->chunk, ba.T, ba.NF).total;
+    ba.ws = static_cast<double *>(ws);
+    return launch_block(pass, m, &ba, nullptr, st);
 }
 
 tvi_status dispatch(int pass, const tvi_model *model, const void *args, int S, int T, hipStream_t stream,
@@ -211,6 +200,8 @@ void tvi_default_options(tvi_options *opt)
     opt->scheme = TVI_BACKWARD_EULER;
     opt->jacobian = TVI_JACOBIAN_ANALYTIC;
     opt->reference_residual = 0;
+    opt->workspace = nullptr;
+    opt->workspace_bytes = 0;
 }
 
 const char *tvi_status_str(int32_t s)
@@ -246,6 +237,13 @@ tvi_status tvi_model_eval(const tvi_model *model, int64_t M, const void *states,
         if (!model->params_shared) return TVI_EUNSUPPORTED;
         return launch_mlp_eval(model->dtype, M, states, params, f, J, st);
     }
+    if (is_block(model)) {
+        if (model->dtype != TVI_F64) return TVI_EUNSUPPORTED;
+        blk::EvalArgs ev{model->n, model_params(model), model->params_shared, M, static_cast<const double *>(states),
+                         static_cast<const double *>(times), static_cast<const double *>(params),
+                         static_cast<double *>(f), static_cast<double *>(J)};
+        return launch_block(2, model, nullptr, &ev, st);
+    }
     return launch_eval(model->kind, model->n, model->dtype, M, states, times, params, model->params_shared, f, J, st);
 }
 
@@ -253,7 +251,8 @@ tvi_status tvi_pcr_solve(int32_t dtype, int32_t n, int64_t B, int64_t m, const v
                          int32_t transpose, void *stream)
 {
     if (dtype != TVI_F32 && dtype != TVI_F64) return TVI_EINVAL;
-    if (n < 2 || n > 4) return TVI_EUNSUPPORTED;
+    if ((n < 2 || n > 4) && !(n == 8 && dtype == TVI_F32)) return TVI_EUNSUPPORTED;
+    if (n == 8 && m > 2 * kWave) return TVI_EUNSUPPORTED;  // two block rows per lane at most
     if (B < 0 || m < 1 || m > 8 * kWave) return TVI_EINVAL;
     if (B == 0) return TVI_OK;
     if (!D || !r || !x) return TVI_EINVAL;
@@ -274,6 +273,15 @@ tvi_status tvi_solve_forward(const tvi_model *model, const tvi_options *opt, int
     if (B == 0) return TVI_OK;
     if (!times || !y0 || !params || !status || (!y_out && !ckpt)) return TVI_EINVAL;
     int S = 0, T = 0;
+    if (is_block(model)) {
+        if ((e = check_block(model, opt)) != TVI_OK) return e;
+        SolveArgs<double> a = make_args<double>(opt, B, N, offsets, times, y0, params, model->params_shared);
+        a.y = static_cast<double *>(y_out);
+        a.ckpt = static_cast<double *>(ckpt);
+        a.status = status;
+        a.iters = iters;
+        return solve_block(0, model, opt, a, opt->workspace, opt->workspace_bytes, static_cast<hipStream_t>(stream));
+    }
     if (model->kind == TVI_MLP) {
         if (opt->chunk > 128 || opt->jacobian != TVI_JACOBIAN_ANALYTIC)
             return TVI_EUNSUPPORTED;
@@ -284,14 +292,14 @@ tvi_status tvi_solve_forward(const tvi_model *model, const tvi_options *opt, int
     }
     const hipStream_t st = static_cast<hipStream_t>(stream);
     if (model->dtype == TVI_F64) {
-        SolveArgs<double> a = make_args<double>(model, opt, B, N, offsets, times, y0, params);
+        SolveArgs<double> a = make_args<double>(opt, B, N, offsets, times, y0, params, model->params_shared);
         a.y = static_cast<double *>(y_out);
         a.ckpt = static_cast<double *>(ckpt);
         a.status = status;
         a.iters = iters;
         return dispatch(PASS_FORWARD, model, &a, S, T, st, opt->jacobian);
     }
-    SolveArgs<float> a = make_args<float>(model, opt, B, N, offsets, times, y0, params);
+    SolveArgs<float> a = make_args<float>(opt, B, N, offsets, times, y0, params, model->params_shared);
     a.y = static_cast<float *>(y_out);
     a.ckpt = static_cast<double *>(ckpt);
     a.status = status;
@@ -299,10 +307,21 @@ tvi_status tvi_solve_forward(const tvi_model *model, const tvi_options *opt, int
     return dispatch(PASS_FORWARD, model, &a, S, T, st, opt->jacobian);
 }
 
+size_t tvi_forward_workspace_bytes(const tvi_model *model, const tvi_options *opt, int64_t B)
+{
+    if (!model || !opt || B < 0 || opt->chunk < 1 || opt->chunk > blk::kMaxChunk || check_model(model) != TVI_OK)
+        return 0;
+    return is_block(model) ? block_ws_bytes(model, opt, B, false) : 0;
+}
+
 size_t tvi_adjoint_workspace_bytes(const tvi_model *model, const tvi_options *opt, int64_t B)
 {
     if (!model || !opt || B < 0 || model->n < 1 || opt->chunk < 1) return 0;
     if (model->kind == TVI_MLP) return mlp_theta_workspace_bytes(B);
+    if (is_block(model)) {
+        if (opt->chunk > blk::kMaxChunk || check_model(model) != TVI_OK) return 0;
+        return block_ws_bytes(model, opt, B, true);
+    }
     return (size_t)B * (size_t)opt->chunk * (size_t)model->n * sizeof(double);
 }
 
@@ -320,6 +339,17 @@ tvi_status tvi_solve_adjoint(const tvi_model *model, const tvi_options *opt, int
     if (B == 0) return TVI_OK;
     if (!times || !params || !g || !dLdp || !dLdy0 || !status) return TVI_EINVAL;
     const bool recompute = (y == nullptr);
+    if (is_block(model)) {
+        if (recompute) return TVI_EUNSUPPORTED;  // the block solver reads the stored trajectory
+        if ((e = check_block(model, opt)) != TVI_OK) return e;
+        SolveArgs<double> a = make_args<double>(opt, B, N, offsets, times, nullptr, params, model->params_shared);
+        a.y = const_cast<double *>(static_cast<const double *>(y));
+        a.g = static_cast<const double *>(g);
+        a.dLdp = static_cast<double *>(dLdp);
+        a.dLdy0 = static_cast<double *>(dLdy0);
+        a.status = status;
+        return solve_block(1, model, opt, a, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
+    }
     if (recompute && !ckpt) return TVI_EINVAL;
     if ((recompute || mlp) &&
         (!workspace || workspace_bytes < tvi_adjoint_workspace_bytes(model, opt, B)))
@@ -330,7 +360,7 @@ tvi_status tvi_solve_adjoint(const tvi_model *model, const tvi_options *opt, int
         const int pass = recompute ? PASS_ADJOINT_RECOMPUTE : PASS_ADJOINT;
         const hipStream_t st = static_cast<hipStream_t>(stream);
         if (model->dtype == TVI_F64) {
-            SolveArgs<double> a = make_args<double>(model, opt, B, N, offsets, times, nullptr, params);
+            SolveArgs<double> a = make_args<double>(opt, B, N, offsets, times, nullptr, params, model->params_shared);
             a.y = const_cast<double *>(static_cast<const double *>(y));
             a.ckpt = const_cast<double *>(static_cast<const double *>(ckpt));
             a.g = static_cast<const double *>(g);
@@ -340,7 +370,7 @@ tvi_status tvi_solve_adjoint(const tvi_model *model, const tvi_options *opt, int
             a.ws = static_cast<double *>(workspace);
             return launch_mlp(pass, TVI_F64, &a, st);
         }
-        SolveArgs<float> a = make_args<float>(model, opt, B, N, offsets, times, nullptr, params);
+        SolveArgs<float> a = make_args<float>(opt, B, N, offsets, times, nullptr, params, model->params_shared);
         a.y = const_cast<float *>(static_cast<const float *>(y));
         a.ckpt = const_cast<double *>(static_cast<const double *>(ckpt));
         a.g = static_cast<const float *>(g);
@@ -357,7 +387,7 @@ tvi_status tvi_solve_adjoint(const tvi_model *model, const tvi_options *opt, int
     const int pass = recompute ? PASS_ADJOINT_RECOMPUTE : PASS_ADJOINT;
     const hipStream_t st = static_cast<hipStream_t>(stream);
     if (model->dtype == TVI_F64) {
-        SolveArgs<double> a = make_args<double>(model, opt, B, N, offsets, times, nullptr, params);
+        SolveArgs<double> a = make_args<double>(opt, B, N, offsets, times, nullptr, params, model->params_shared);
         a.y = const_cast<double *>(static_cast<const double *>(y));
         a.ckpt = const_cast<double *>(static_cast<const double *>(ckpt));
         a.g = static_cast<const double *>(g);
@@ -367,7 +397,7 @@ tvi_status tvi_solve_adjoint(const tvi_model *model, const tvi_options *opt, int
         a.ws = static_cast<double *>(workspace);
         return dispatch(pass, model, &a, S, T, st, opt->jacobian);
     }
-    SolveArgs<float> a = make_args<float>(model, opt, B, N, offsets, times, nullptr, params);
+    SolveArgs<float> a = make_args<float>(opt, B, N, offsets, times, nullptr, params, model->params_shared);
     a.y = const_cast<float *>(static_cast<const float *>(y));
     a.ckpt = const_cast<double *>(static_cast<const double *>(ckpt));
     a.g = static_cast<const float *>(g);

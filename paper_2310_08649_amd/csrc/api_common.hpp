@@ -1,0 +1,112 @@
+// Host-side argument checks and the kernel-argument record shared by the
+// library's entry points and by user models compiled against the library
+// (tvi_user_model.hpp).
+#pragma once
+
+#include <string.h>
+
+#include "block.hpp"
+#include "solver.hpp"
+#include "tvi.h"
+
+namespace tvi {
+namespace api {
+
+inline bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
+
+inline int next_pow2(int v)
+{
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+// Lanes per series S and steps per lane T for a chunk of C steps: the fewest
+// steps per lane that fit the chunk in one wavefront, then the fewest lanes.
+inline void choose_tiling(int C, int &S, int &T)
+{
+    if (C <= 1) { S = 1; T = 1; return; }
+    T = 1;
+    while (T < 8 && T * kWave < C) T <<= 1;
+    S = next_pow2((C + T - 1) / T);
+    if (S < 4) S = 4;
+    if (S > kWave) S = kWave;
+}
+
+inline tvi_status resolve_tiling(const tvi_options *o, int &S, int &T)
+{
+    if (o->lanes == 0 && o->steps_per_lane == 0) {
+        choose_tiling(o->chunk, S, T);
+    } else {
+        S = o->lanes;
+        T = o->steps_per_lane;
+        if (!(S == 1 || pow2_in(S, 4, kWave)) || !pow2_in(T, 1, 8)) return TVI_EINVAL;
+    }
+    if (o->chunk > 8 * kWave || (int64_t)S * T < o->chunk) return TVI_EINVAL;
+    return TVI_OK;
+}
+
+inline tvi_status check_options(const tvi_options *o)
+{
+    if (!o) return TVI_EINVAL;
+    if (o->chunk < 1 || o->chunk > blk::kMaxChunk) return TVI_EINVAL;
+    if (o->max_newton < 1) return TVI_EINVAL;
+    if (!(o->tol_a >= 0.0) || !(o->tol_r >= 0.0)) return TVI_EINVAL;
+    if (o->init != TVI_INIT_ZERO && o->init != TVI_INIT_EXTRAP && o->init != TVI_INIT_PREDICTOR) return TVI_EINVAL;
+    if (o->init == TVI_INIT_PREDICTOR &&
+        (!o->predictor || o->predictor_hidden < 1 || o->predictor_hidden > 256 || o->predictor_steps < o->chunk ||
+         (o->predictor_base != 0 && o->predictor_base != 1)))
+        return TVI_EINVAL;
+    if (o->scheme != TVI_BACKWARD_EULER && o->scheme != TVI_FORWARD_EULER) return TVI_EINVAL;
+    if (o->scheme == TVI_FORWARD_EULER && o->init == TVI_INIT_PREDICTOR) return TVI_EUNSUPPORTED;
+    if (o->jacobian != TVI_JACOBIAN_ANALYTIC && o->jacobian != TVI_JACOBIAN_FORWARD_AD) return TVI_EINVAL;
+    if (o->reference_residual != 0 && o->reference_residual != 1) return TVI_EINVAL;
+    if (o->jacobian == TVI_JACOBIAN_FORWARD_AD &&
+        (o->scheme != TVI_BACKWARD_EULER || o->init == TVI_INIT_PREDICTOR))
+        return TVI_EUNSUPPORTED;
+    return TVI_OK;
+}
+
+template <class IO>
+inline SolveArgs<IO> make_args(const tvi_options *opt, int64_t B, int64_t N, const int64_t *offsets, const void *times,
+                        const void *y0, const void *params, int params_shared)
+{
+    SolveArgs<IO> a;
+    memset(&a, 0, sizeof(a));
+    a.B = B;
+    a.N = N;
+    a.K = (N + opt->chunk - 1) / opt->chunk + 1;
+    a.offsets = offsets;
+    a.times = static_cast<const IO *>(times);
+    a.y0 = static_cast<const IO *>(y0);
+    a.params = static_cast<const IO *>(params);
+    a.params_shared = params_shared;
+    a.chunk = opt->chunk;
+    a.max_newton = opt->max_newton;
+    a.init = opt->init;
+    a.halving = opt->halving;
+    a.tol_a = opt->tol_a;
+    a.tol_r = opt->tol_r;
+    a.pred = static_cast<const float *>(opt->predictor);
+    a.pred_hidden = opt->predictor_hidden;
+    a.pred_steps = opt->predictor_steps;
+    a.pred_base = opt->predictor_base;
+    a.order = opt->order;
+    a.scheme = opt->scheme;
+    a.zero_ref = opt->reference_residual;
+    return a;
+}
+
+// The options a user model takes: the plain backward-Euler solver with the
+// zero or extrapolated start (its Jacobians come from automatic differentiation).
+inline tvi_status check_user_options(const tvi_options *o)
+{
+    tvi_status e = check_options(o);
+    if (e != TVI_OK) return e;
+    if (o->init == TVI_INIT_PREDICTOR || o->scheme != TVI_BACKWARD_EULER || o->reference_residual != 0)
+        return TVI_EUNSUPPORTED;
+    return TVI_OK;
+}
+
+}  // namespace api
+}  // namespace tvi

@@ -194,4 +194,20 @@ tvi_status predictor_train_step(int n_in, int H, int n_out, int64_t M, const flo
                                 float *params, float *grad, float *adam_m, float *adam_v, int64_t step, float lr,
                                 float *loss, void *ws, hipStream_t st);
 
+// Block solver (state sizes up to 40), csrc/block_*.hip: pass 0 forward,
+// 1 adjoint (stored trajectory), 2 model evaluation.
+namespace blk {
+struct BlockArgs;
+struct EvalArgs;
+}
+tvi_status launch_block_mds(int pass, int n, const blk::BlockArgs *ba, const blk::EvalArgs *ev, hipStream_t st);
+tvi_status launch_block_neuron(int pass, int n, const blk::BlockArgs *ba, const blk::EvalArgs *ev, hipStream_t st);
+tvi_status launch_block_fnode(int pass, int n, const blk::BlockArgs *ba, const blk::EvalArgs *ev, hipStream_t st);
+int block_params_mds(int n);
+int block_params_neuron(int n);
+int block_params_fnode(int n);
+int block_nf_mds(int n);
+int block_nf_neuron(int n);
+int block_nf_fnode(int n);
+
 } // namespace tvi

@@ -98,4 +98,37 @@ __device__ __forceinline__ Dual<K> pow_pos(const Dual<K> &x, double e)
     return lin1(pm1 * x.v, e * pm1, x);
 }
 
+// elementary functions for plain and dual arguments (the derivative rule of
+// each applied to every direction), for right-hand sides written once for both
+__device__ __forceinline__ double exp_t(double x) { return exp(x); }
+template <int K>
+__device__ __forceinline__ Dual<K> exp_t(const Dual<K> &x)
+{
+    const double e = exp(x.v);
+    return lin1(e, e, x);
+}
+__device__ __forceinline__ double log_t(double x) { return log(x); }
+template <int K>
+__device__ __forceinline__ Dual<K> log_t(const Dual<K> &x) { return lin1(log(x.v), 1.0 / x.v, x); }
+__device__ __forceinline__ double sqrt_t(double x) { return sqrt(x); }
+template <int K>
+__device__ __forceinline__ Dual<K> sqrt_t(const Dual<K> &x)
+{
+    const double r = sqrt(x.v);
+    return lin1(r, 0.5 / r, x);
+}
+__device__ __forceinline__ double sin_t(double x) { return sin(x); }
+template <int K>
+__device__ __forceinline__ Dual<K> sin_t(const Dual<K> &x) { return lin1(sin(x.v), cos(x.v), x); }
+__device__ __forceinline__ double cos_t(double x) { return cos(x); }
+template <int K>
+__device__ __forceinline__ Dual<K> cos_t(const Dual<K> &x) { return lin1(cos(x.v), -sin(x.v), x); }
+__device__ __forceinline__ double tanh_t(double x) { return tanh(x); }
+template <int K>
+__device__ __forceinline__ Dual<K> tanh_t(const Dual<K> &x)
+{
+    const double th = tanh(x.v);
+    return lin1(th, 1.0 - th * th, x);
+}
+
 } // namespace tvi

@@ -14,9 +14,22 @@
 
 namespace tvi {
 
+// Arithmetic precision: double for double storage, float for float storage
+// (an HBM-bound solve; the float path is the one the neural ODE's 8 x 8
+// blocks take).
+template <class IO>
+struct Compute {
+    using type = double;
+};
+template <>
+struct Compute<float> {
+    using type = float;
+};
+
 template <int N, class IO, int T>
 struct Rows {
-    double D[T][N][N], r[T][N];
+    using R = typename Compute<IO>::type;
+    R D[T][N][N], r[T][N];
 };
 
 // Non-temporal ("streamed") accesses only for 2x2 blocks.  A lane's block row is
@@ -57,11 +70,11 @@ __device__ __forceinline__ void load_rows(Rows<N, IO, T> &v, const IO *__restric
         for (int e = 0; e < N; ++e) {
 #pragma unroll
             for (int c = 0; c < N; ++c) {
-                const double val = (double)load_elem<N>(Db + ((int64_t)jj * N + e) * N + c);
+                const auto val = (typename Compute<IO>::type)load_elem<N>(Db + ((int64_t)jj * N + e) * N + c);
                 if (TR) v.D[i][c][e] = val;
                 else v.D[i][e][c] = val;
             }
-            v.r[i][e] = (double)load_elem<N>(rb + (int64_t)jj * N + e);
+            v.r[i][e] = (typename Compute<IO>::type)load_elem<N>(rb + (int64_t)jj * N + e);
         }
     }
 }
@@ -72,6 +85,7 @@ template <int N, class IO, int S, int T, bool TR>
 __global__ __launch_bounds__(kWave) void pcr_kernel(int64_t B, int m, const IO *__restrict__ D,
                                                    const IO *__restrict__ r, IO *__restrict__ x)
 {
+    using R = typename Compute<IO>::type;
     const int lane = lane_id();
     const int q = lane & (S - 1);
     const int64_t per_block = kWave / S;
@@ -92,8 +106,8 @@ __global__ __launch_bounds__(kWave) void pcr_kernel(int64_t B, int m, const IO *
             load_rows<N, IO, S, T, TR>(cur, D, r, b, m, q);
         }
 
-        double Fi[T][N][N], zi[T][N];  // I + Fi = D^{-1} (of the transposed block when TR)
-        AffineI<N, double> map;
+        R Fi[T][N][N], zi[T][N];  // I + Fi = D^{-1} (of the transposed block when TR)
+        AffineI<N, R> map;
         affine_identity(map);
         int ok = 1;
 #pragma unroll
@@ -102,9 +116,9 @@ __global__ __launch_bounds__(kWave) void pcr_kernel(int64_t B, int m, const IO *
             const int j = q * T + i;
             if (valid && j < m) {
                 ok &= invert_plus(cur.D[i], Fi[i]) ? 1 : 0;
-                const double zero[N] = {};
+                const R zero[N] = {};
                 apply_ip(Fi[i], cur.r[i], zero, zi[i]);
-                AffineI<N, double> stp;
+                AffineI<N, R> stp;
 #pragma unroll
                 for (int e = 0; e < N; ++e) {
 #pragma unroll
@@ -122,12 +136,12 @@ __global__ __launch_bounds__(kWave) void pcr_kernel(int64_t B, int m, const IO *
 #pragma unroll
             for (int e = 0; e < N; ++e) zi[0][e] = map.z[e];
         } else {
-            double din[N];
+            R din[N];
             if (!TR) vec_prev(map.z, din);
             else vec_next(map.z, din);
             if (q == (TR ? S - 1 : 0)) {
 #pragma unroll
-                for (int e = 0; e < N; ++e) din[e] = 0.0;
+                for (int e = 0; e < N; ++e) din[e] = R(0);
             }
 #pragma unroll
             for (int u = 0; u < T; ++u) {
@@ -141,7 +155,7 @@ __global__ __launch_bounds__(kWave) void pcr_kernel(int64_t B, int m, const IO *
             }
         }
         ok = seg_and<S>(ok);
-        const double nan = __builtin_nan("");
+        const R nan = R(__builtin_nan(""));
         IO *xb = x + (valid ? b : 0) * (int64_t)m * N;
 #pragma unroll
         for (int i = 0; i < T; ++i) {
@@ -205,6 +219,26 @@ static tvi_status pcr_launch(int64_t B, int m, const void *D, const void *r, voi
     }
 }
 
+// 8 x 8 blocks (float): one or two rows per lane (the registers of larger T)
+static tvi_status pcr_launch8(int64_t B, int m, const void *D, const void *r, void *x, int transpose, int S, int T,
+                              hipStream_t stream)
+{
+    if (T > 2) return TVI_EUNSUPPORTED;
+    switch (S) {
+    case 4: return T == 1 ? pcr_launch_st<8, float, 4, 1>(B, m, D, r, x, transpose, stream)
+                          : pcr_launch_st<8, float, 4, 2>(B, m, D, r, x, transpose, stream);
+    case 8: return T == 1 ? pcr_launch_st<8, float, 8, 1>(B, m, D, r, x, transpose, stream)
+                          : pcr_launch_st<8, float, 8, 2>(B, m, D, r, x, transpose, stream);
+    case 16: return T == 1 ? pcr_launch_st<8, float, 16, 1>(B, m, D, r, x, transpose, stream)
+                           : pcr_launch_st<8, float, 16, 2>(B, m, D, r, x, transpose, stream);
+    case 32: return T == 1 ? pcr_launch_st<8, float, 32, 1>(B, m, D, r, x, transpose, stream)
+                           : pcr_launch_st<8, float, 32, 2>(B, m, D, r, x, transpose, stream);
+    case 64: return T == 1 ? pcr_launch_st<8, float, 64, 1>(B, m, D, r, x, transpose, stream)
+                           : pcr_launch_st<8, float, 64, 2>(B, m, D, r, x, transpose, stream);
+    default: return TVI_EUNSUPPORTED;
+    }
+}
+
 tvi_status launch_pcr(int dtype, int n, int64_t B, int m, const void *D, const void *r, void *x, int transpose,
                       int S, int T, hipStream_t stream)
 {
@@ -216,6 +250,7 @@ tvi_status launch_pcr(int dtype, int n, int64_t B, int m, const void *D, const v
                        : pcr_launch<3, float>(B, m, D, r, x, transpose, S, T, stream);
     case 4: return f64 ? pcr_launch<4, double>(B, m, D, r, x, transpose, S, T, stream)
                        : pcr_launch<4, float>(B, m, D, r, x, transpose, S, T, stream);
+    case 8: return f64 ? TVI_EUNSUPPORTED : pcr_launch8(B, m, D, r, x, transpose, S, T, stream);
     default: return TVI_EUNSUPPORTED;
     }
 }

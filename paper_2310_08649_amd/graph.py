@@ -69,6 +69,12 @@ class CapturedStep:
         self.dLdp = torch.empty((P,) if shared else (B, P), dtype=dt, device=dev)
         self.dLdy0 = torch.empty((B, n), dtype=dt, device=dev)
         self.status_adj = torch.empty(B, dtype=torch.int32, device=dev)
+        # the block solver's forward scratch (larger state sizes)
+        fwb = lib.tvi_forward_workspace_bytes(ctypes.byref(self.model), ctypes.byref(self.opt), B)
+        self.fws = torch.empty(fwb, dtype=torch.uint8, device=dev) if fwb else None
+        if fwb:
+            self.opt.workspace = self.fws.data_ptr()
+            self.opt.workspace_bytes = fwb
         wsb = lib.tvi_adjoint_workspace_bytes(ctypes.byref(self.model), ctypes.byref(self.opt), B)
         self.ws = torch.empty(max(1, wsb), dtype=torch.uint8, device=dev)
         self.ws_bytes = wsb

@@ -25,7 +25,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtvi.so")
 
-KINDS = {"linear": 0, "vanderpol": 1, "robertson": 2, "mlp": 3, "chaboche": 4, "neuron": 5}
+KINDS = {"linear": 0, "vanderpol": 1, "robertson": 2, "mlp": 3, "chaboche": 4, "neuron": 5, "mds": 6, "fnode": 7}
 F32, F64 = 0, 1
 INIT = {"zero": 0, "extrap": 1, "predictor": 2}
 SCHEMES = {"backward_euler": 0, "forward_euler": 1}
@@ -49,7 +49,8 @@ class Options(ctypes.Structure):
                 ("predictor_hidden", ctypes.c_int32), ("predictor_steps", ctypes.c_int32),
                 ("predictor_base", ctypes.c_int32), ("order", ctypes.c_void_p), ("scheme", ctypes.c_int32),
                 ("jacobian", ctypes.c_int32),
-                ("reference_residual", ctypes.c_int32)]
+                ("reference_residual", ctypes.c_int32), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t)]
 
 
 _lib = None
@@ -78,6 +79,8 @@ def load():
         lib.tvi_pcr_solve.restype = i32
         lib.tvi_solve_forward.argtypes = [MP, OP, i64, i64, P, P, P, P, P, P, P, P, P]
         lib.tvi_solve_forward.restype = i32
+        lib.tvi_forward_workspace_bytes.argtypes = [MP, OP, i64]
+        lib.tvi_forward_workspace_bytes.restype = sz
         lib.tvi_adjoint_workspace_bytes.argtypes = [MP, OP, i64]
         lib.tvi_adjoint_workspace_bytes.restype = sz
         lib.tvi_solve_adjoint.argtypes = [MP, OP, i64, i64, P, P, P, P, P, P, P, P, P, P, sz, P]
@@ -119,6 +122,11 @@ def _io_dtype(t):
     if t.dtype == torch.float32:
         return F32
     raise TviError("floating-point arrays must be float32 or float64")
+
+
+def is_block(kind, n):
+    """Whether the model runs in the block solver (larger state sizes)."""
+    return kind in ("mds", "fnode") or (kind == "neuron" and n > 8)
 
 
 def param_count(kind, n, hidden=64):
@@ -238,6 +246,12 @@ def solve_forward(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e
     if checkpoints:
         K = (N + chunk - 1) // chunk + 1
         ck = torch.empty((B, K, n), dtype=torch.float64, device=dev)
+    wsb = load().tvi_forward_workspace_bytes(ctypes.byref(model), ctypes.byref(opt), B)
+    ws = None
+    if wsb:  # the block solver's scratch (larger state sizes)
+        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+        opt.workspace = ws.data_ptr()
+        opt.workspace_bytes = wsb
     _check(load().tvi_solve_forward(ctypes.byref(model), ctypes.byref(opt), B, N, _ptr(offsets), _ptr(times),
                                     _ptr(y0), _ptr(params), _ptr(y), _ptr(ck), _ptr(status), _ptr(it), _stream()),
            "tvi_solve_forward")
@@ -288,7 +302,7 @@ def solve_adjoint(kind, times, params, g, y=None, ckpt=None, offsets=None, chunk
                                              _ptr(dLdy0), _ptr(status), _stream()), "tvi_solve_adjoint_noalloc")
         return dLdp, dLdy0, status
     ws, wsb = None, 0
-    if y is None or kind == "mlp":
+    if y is None or kind == "mlp" or is_block(kind, n):
         wsb = lib.tvi_adjoint_workspace_bytes(ctypes.byref(model), ctypes.byref(opt), B)
         ws = torch.empty(max(1, wsb), dtype=torch.uint8, device=dev)
     _check(lib.tvi_solve_adjoint(ctypes.byref(model), ctypes.byref(opt), B, N, _ptr(offsets), _ptr(times),
@@ -352,3 +366,81 @@ def odeint_adjoint(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1
     chunk-boundary checkpoints for the backward pass, which re-solves each
     chunk's interior states (bitwise those of the forward pass)."""
     return _OdeintAdjoint.apply(y0, params, kind, times, offsets, chunk, tol, recompute, check, kw)
+
+
+class UserModel:
+    """A right-hand side of the caller's own, compiled with ``TVI_USER_MODEL(Type, name)``
+    (``include/tvi_user_model.hpp``) into the shared library at ``path``: its
+    ``name_solve_forward`` / ``name_solve_adjoint`` take the arguments of
+    ``tvi_solve_forward`` / ``tvi_solve_adjoint`` without the model (double
+    storage, per-series parameters [B, P])."""
+
+    def __init__(self, path, name, n, P):
+        if not os.path.exists(path):
+            raise TviError("%s is not built" % path)
+        self.lib = ctypes.CDLL(path)
+        self.n, self.P = int(n), int(P)
+        Pt, i64, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t
+        OP = ctypes.POINTER(Options)
+        self._fwd = getattr(self.lib, name + "_solve_forward")
+        self._fwd.argtypes = [OP, i64, i64, Pt, Pt, Pt, Pt, Pt, Pt, Pt, Pt, Pt]
+        self._fwd.restype = ctypes.c_int32
+        self._adj = getattr(self.lib, name + "_solve_adjoint")
+        self._adj.argtypes = [OP, i64, i64, Pt, Pt, Pt, Pt, Pt, Pt, Pt, Pt, Pt, Pt, sz, Pt]
+        self._adj.restype = ctypes.c_int32
+        self._wsb = getattr(self.lib, name + "_adjoint_workspace_bytes")
+        self._wsb.argtypes = [OP, i64]
+        self._wsb.restype = sz
+        self.name = name
+
+    def solve_forward(self, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e-6), max_newton=50, lanes=0,
+                      steps_per_lane=0, init="zero", halving=True, checkpoints=False, n_max=None, order=None):
+        """``(y, status, iters, ckpt)`` as ``solve_forward``."""
+        y0 = _dev(y0, torch.float64, "y0")
+        times = _dev(times, torch.float64, "times")
+        params = _dev(params, torch.float64, "params")
+        if offsets is not None:
+            offsets = _dev(offsets, torch.int64, "offsets")
+        B, n, N, yshape = _geometry(y0, times, offsets, n_max)
+        if n != self.n or params.shape != (B, self.P):
+            raise TviError("%s: y0 must be [B, %d] and params [B, %d]" % (self.name, self.n, self.P))
+        opt = make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, halving, order=order)
+        dev = y0.device
+        y = torch.empty(yshape, dtype=torch.float64, device=dev)
+        status = torch.empty(B, dtype=torch.int32, device=dev)
+        it = torch.empty(B, dtype=torch.int32, device=dev)
+        ck = None
+        if checkpoints:
+            ck = torch.empty((B, (N + chunk - 1) // chunk + 1, n), dtype=torch.float64, device=dev)
+        _check(self._fwd(ctypes.byref(opt), B, N, _ptr(offsets), _ptr(times), _ptr(y0), _ptr(params), _ptr(y),
+                         _ptr(ck), _ptr(status), _ptr(it), _stream()), self.name + "_solve_forward")
+        return y, status, it, ck
+
+    def solve_adjoint(self, times, params, g, y=None, ckpt=None, offsets=None, chunk=64, tol=(1e-8, 1e-6),
+                      max_newton=50, lanes=0, steps_per_lane=0, init="zero", halving=True, n_max=None, order=None):
+        """``(dLdp [B, P], dLdy0 [B, n], status)`` as ``solve_adjoint``."""
+        times = _dev(times, torch.float64, "times")
+        params = _dev(params, torch.float64, "params")
+        g = _dev(g, torch.float64, "g")
+        if y is not None:
+            y = _dev(y, torch.float64, "y")
+        if offsets is not None:
+            offsets = _dev(offsets, torch.int64, "offsets")
+        B = params.shape[0]
+        if offsets is None:
+            N = times.shape[0] - 1
+        else:
+            N = int(n_max) if n_max is not None else (int((offsets[1:] - offsets[:-1]).max().item()) - 1 if B else 0)
+        opt = make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, halving, order=order)
+        dev = g.device
+        dLdp = torch.empty((B, self.P), dtype=torch.float64, device=dev)
+        dLdy0 = torch.empty((B, self.n), dtype=torch.float64, device=dev)
+        status = torch.empty(B, dtype=torch.int32, device=dev)
+        ws, wsb = None, 0
+        if y is None:
+            wsb = self._wsb(ctypes.byref(opt), B)
+            ws = torch.empty(max(1, wsb), dtype=torch.uint8, device=dev)
+        _check(self._adj(ctypes.byref(opt), B, N, _ptr(offsets), _ptr(times), _ptr(params), _ptr(y), _ptr(ckpt),
+                         _ptr(g), _ptr(dLdp), _ptr(dLdy0), _ptr(status), _ptr(ws), wsb, _stream()),
+               self.name + "_solve_adjoint")
+        return dLdp, dLdy0, status

@@ -112,6 +112,8 @@ def test_adjoint_and_pcr_reject_bad_arguments(lib):
     assert lib.tvi_pcr_solve(tvi.F64, 2, 4, 0, f, f, f, 0, None) == -1
     assert lib.tvi_pcr_solve(tvi.F64, 2, 4, 513, f, f, f, 0, None) == -1
     assert lib.tvi_pcr_solve(tvi.F64, 9, 4, 8, f, f, f, 0, None) == -4
+    assert lib.tvi_pcr_solve(tvi.F64, 8, 4, 8, f, f, f, 0, None) == -4    # 8 x 8: float only
+    assert lib.tvi_pcr_solve(tvi.F32, 8, 4, 129, f, f, f, 0, None) == -4  # and m <= 128
     assert lib.tvi_pcr_solve(7, 2, 4, 8, f, f, f, 0, None) == -1
     assert lib.tvi_pcr_solve(tvi.F64, 2, 4, 8, None, f, f, 0, None) == -1
 
@@ -189,7 +191,56 @@ def test_paper_example_models_sizes(lib):
     assert fwd("chaboche", 2) == -1
     assert fwd("chaboche", 8) == -4
     assert fwd("neuron", 6) == -1
-    assert fwd("neuron", 12) == -4
+    # more neurons, the mass-damper-spring chain and the forced neural ODE: the
+    # block solver, up to n = 40, double storage, with its workspace
+    assert fwd("neuron", 12) == -1          # no workspace given
+    assert fwd("neuron", 44) == -4
+    assert fwd("mds", 7) == -1 and fwd("mds", 42) == -4 and fwd("fnode", 41) == -4
+    assert fwd("mds", 20, tvi.F32) == -4
+    assert tvi.param_count("mds", 20) == 32
+    assert tvi.param_count("fnode", 5) == 2 * 36 + 12 + 30 + 5 + 2
+
+
+def test_block_solver_options_and_workspace(lib):
+    """The block solver's checks: its workspace size, the segment length, chunk
+    up to 1024, and the options it does not take."""
+    from paper_2310_08649_amd import tvi
+    f = _fake()
+    m = tvi.Model(tvi.KINDS["mds"], 20, tvi.F64, 0, 64)
+
+    def ws(o, B=3, adjoint=False):
+        fn = lib.tvi_adjoint_workspace_bytes if adjoint else lib.tvi_forward_workspace_bytes
+        return fn(ctypes.byref(m), ctypes.byref(o), B)
+
+    thomas, pcr, hybrid = (tvi.make_options(chunk=1000, steps_per_lane=T) for T in (1000, 1, 8))
+    NP = 24  # n = 20 padded
+    blk = NP * NP
+    per = 1000 * blk + 1000 * NP + 1001 * NP      # step maps, offsets, iterate
+    assert ws(thomas) == 3 * 8 * per
+    assert ws(pcr) == 3 * 8 * (per + 1000 * blk + 1000 * NP)  # one more buffer of maps for the levels
+    assert ws(hybrid) == 3 * 8 * (per + 2 * 125 * (blk + NP))
+    assert ws(thomas, adjoint=True) == 3 * 8 * (per + 1000 * (5 * 10 + 3))  # plus the per-step factors
+    assert ws(tvi.make_options(chunk=1025)) == 0
+    assert lib.tvi_forward_workspace_bytes(ctypes.byref(tvi.Model(1, 2, tvi.F64, 0, 64)),
+                                           ctypes.byref(thomas), 3) == 0   # not a block model
+
+    def fwd(o, wsb=None):
+        o.workspace = 0x1000
+        o.workspace_bytes = ws(o) if wsb is None else wsb
+        return lib.tvi_solve_forward(ctypes.byref(m), ctypes.byref(o), 3, 10, None, f, f, f, f, None, f, None, None)
+
+    assert fwd(tvi.make_options(chunk=64), wsb=100) == -1                      # workspace too small
+    assert fwd(tvi.make_options(chunk=64, scheme="forward_euler")) == -4
+    assert fwd(tvi.make_options(chunk=64, jacobian="forward_ad")) == -4
+    assert fwd(tvi.make_options(chunk=64, reference="zero")) == -4
+    assert fwd(tvi.make_options(chunk=1025)) == -1
+    o = tvi.make_options(chunk=64)
+    o.steps_per_lane = -2
+    assert fwd(o) == -1
+    # the adjoint reads the stored trajectory: no recomputation from checkpoints
+    o = tvi.make_options(chunk=64)
+    assert lib.tvi_solve_adjoint(ctypes.byref(m), ctypes.byref(o), 3, 10, None, f, f, None, f, f, f, f, f, f,
+                                 ws(o, adjoint=True), None) == -4
 
 
 def test_jacobian_option_is_checked(lib):

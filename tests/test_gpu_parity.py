@@ -80,6 +80,21 @@ def test_pcr_solve_growing_chain(tvi, transpose):
         assert (np.abs(res).max(axis=(1, 2)) <= 1e-13 * scale * np.log2(m)).all(), m
 
 
+@pytest.mark.parametrize("transpose", [False, True])
+def test_pcr_solve_8x8_float(tvi, transpose):
+    """8 x 8 blocks (the neural ODE's), float storage and arithmetic, one and two
+    block rows per lane, against the dense solve in double."""
+    rng = np.random.default_rng(808)
+    for m in (1, 2, 3, 17, 63, 64, 65, 100, 127, 128):
+        B = 7
+        D = (1.6 * np.eye(8)[None, None] + (0.3 / np.sqrt(8)) * rng.standard_normal((B, m, 8, 8))).astype(np.float32)
+        r = rng.standard_normal((B, m, 8)).astype(np.float32)
+        ref = bb.dense_solve(D.astype(np.float64), r.astype(np.float64), transpose=transpose)
+        x = host(tvi.pcr_solve(dev(D, torch.float32), dev(r, torch.float32), transpose=transpose)).astype(np.float64)
+        err = np.abs(x - ref).max(axis=(1, 2)) / np.abs(ref).max(axis=(1, 2))
+        assert err.max() <= 1e-5, (m, float(err.max()))
+
+
 def test_pcr_solve_fp32_and_singular_block(tvi):
     rng = np.random.default_rng(7)
     B, m, n = 6, 96, 2

@@ -262,3 +262,35 @@ def test_bench_records_traffic_from_counter_csvs(monkeypatch, tmp_path):
     assert json.loads((tmp_path / "profiles" / "traffic.json").read_text())[kern]["dispatches"] == 2
     assert b.measured_traffic(kern) == rec["bytes_per_dispatch"]
     assert "__amd_rocclr_copyBuffer" not in table
+
+
+@pytest.mark.parametrize("nu,nb", [(1, 3), (5, 30), (10, 100)])
+def test_mds_workload_is_the_paper_table(nu, nb):
+    g = _golden("mds_parameters.json")
+    p = W.mds(nu, nb, n_time=_golden("chunk_study.json")["n_time"])
+    assert p["times"][-1] == g["t_max"] and p["times"].shape[0] == 2001 and p["n"] == 2 * nu
+    assert (p["y0"] == 0).all()
+    for b in range(nb):
+        row = p["params"][b]
+        np.testing.assert_array_equal(row[:nu], np.linspace(*g["K"]["linspace"], nu))
+        np.testing.assert_array_equal(row[nu:2 * nu], np.linspace(*g["C"]["linspace"], nu))
+        np.testing.assert_array_equal(row[2 * nu:3 * nu], np.linspace(*g["M"]["linspace"], nu))
+        assert row[3 * nu] == g["f_a"] and row[3 * nu + 1] == np.linspace(*g["T"]["linspace"], nb)[b]
+
+
+@pytest.mark.parametrize("nu,nb", [(1, 3), (25, 100)])
+def test_neural_ode_workload_is_the_paper_table(nu, nb):
+    g = _golden("neural_ode_parameters.json")
+    p = W.fnode(nu, nb)
+    m = nu + 1
+    assert p["times"][-1] == g["t_max"] and p["n"] == nu and (p["y0"] == 0).all()
+    P = 2 * m * m + 2 * m + nu * m + nu + 2
+    assert p["params"].shape == (nb, P)
+    w = p["params"][:, :-2]
+    assert (w == w[0]).all()                      # one set of layers for every series
+    assert np.abs(w).max() <= np.sqrt(1.0 / m)    # the uniform law's range
+    for b in range(nb):
+        assert p["params"][b, -2] == g["f_a"] and p["params"][b, -1] == np.linspace(*g["T"]["linspace"], nb)[b]
+    study = _golden("chunk_study.json")
+    assert study["n_unit"]["neural_ode"] == [1, 5, 10, 15, 20, 25]
+    assert study["n_unit"]["mass_damper_spring"] == [1, 2, 3, 5, 10]
