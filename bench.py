@@ -987,16 +987,15 @@ def run_predictor(ctx, steps):
 
 
 def _predictor_robertson(ctx):
-    """The same on the stiff kinetics: trained on ~1e5 chunks of 2000 other
-    ragged series, evaluated on the benchmark's ragged batch at its tuned
-    chunk and tiling."""
+    """The same on the stiff kinetics, as the predictor workload specifies it:
+    chunk 50, trained on 1e5 chunks drawn from 2000 other ragged series,
+    evaluated on the benchmark's ragged batch (64 lanes, one step per lane)."""
     import numpy as np
     import torch
     from paper_2310_08649_amd import predictor as pred
     from paper_2310_08649_amd import tvi, workloads
     dev = ctx["dev"]
-    b = ctx.get("rob_tuned") or {"chunk": 64, "lanes": 64, "steps_per_lane": 1}
-    C, S, T = b["chunk"], b["lanes"], b["steps_per_lane"]
+    C, S, T = 50, 64, 1
     d64 = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev)
     t0 = time.perf_counter()
     tr = workloads.robertson(seed=106)
@@ -1004,12 +1003,15 @@ def _predictor_robertson(ctx):
     y, st, _, _ = tvi.solve_forward("robertson", d64(tr["y0"]), d64(tr["times"]), d64(tr["params"]), offsets=off,
                                     chunk=C, lanes=S, steps_per_lane=T, tol=TIMING_TOL)
     x, ys, inc, dts, series = pred.chunk_samples_ragged(y, d64(tr["times"]), off, C)
-    ok = torch.isfinite(inc).all(dim=1)
+    ok = torch.nonzero(torch.isfinite(inc).all(dim=1)).flatten()
+    g = torch.Generator(device=dev)
+    g.manual_seed(106)
+    ok = ok[torch.randperm(ok.numel(), generator=g, device=dev)[:100000]]  # 1e5 training chunks
     d = pred.dims(3, C)
     # corrections to the zero start: on log-spaced grids the extrapolation overshoots
     net, hist = pred.fit_predictor(d, x[ok].contiguous(), inc[ok].float().contiguous(), epochs=20, seed=0)
     torch.cuda.synchronize()
-    res = {"chunk": C, "lanes": S, "steps_per_lane": T, "base": "zero", "train_chunks": int(ok.sum().item()),
+    res = {"chunk": C, "lanes": S, "steps_per_lane": T, "base": "zero", "train_chunks": int(ok.numel()),
            "train_seconds": time.perf_counter() - t0, "train_loss": [hist[0], hist[-1]]}
     ev = workloads.robertson()
     eoff = torch.as_tensor(ev["offsets"], device=dev)

@@ -212,6 +212,21 @@ typedef struct {
                                   tvi_forward_workspace_bytes() bytes (caller-owned,
                                   contents need no initialisation); NULL otherwise */
     size_t workspace_bytes;    /* its size                                           */
+    const double *g_divisor;   /* adjoint: NULL, or a device scalar that divides every
+                                  entry of g: with g = y and g_divisor = the loss of
+                                  tvi_loss_grad(TVI_LOSS_FROBENIUS, ..., g = NULL, loss),
+                                  g = y / L is used without being formed in memory */
+    const int32_t *obs_idx;    /* adjoint: NULL (g in the trajectory's layout), or the
+                                  observed steps, strictly increasing step indices
+                                  (device, uniform grids only): g is then
+                                  [B][n_obs][n], dL/dy at step obs_idx[i] in row i,
+                                  and zero at every other step (Appendix A: dL/dy
+                                  enters only where the loss observes the state)    */
+    int32_t n_obs;             /* its length, >= 1 when obs_idx is given            */
+                               /* g_divisor and obs_idx: the neural ODE (TVI_MLP) and
+                                  the block solver (state sizes above 8) only; the
+                                  other models' adjoint returns TVI_EUNSUPPORTED
+                                  when either is set                                */
 } tvi_options;
 
 /* Fills `opt` with the defaults: chunk 64, tol_a 1e-8, tol_r 1e-6 (Section 2.3),
@@ -309,7 +324,8 @@ tvi_status tvi_solve_forward(const tvi_model *model, const tvi_options *opt, int
  * and, for TVI_MLP, always (per-series partial gradients, summed afterwards
  * over the series in a fixed order); otherwise it may be NULL.
  *
- *   g       dL/dy [B][N+1][n] or ragged (required)
+ *   g       dL/dy [B][N+1][n] or ragged (required); [B][n_obs][n] with
+ *           tvi_options.obs_idx (uniform grids; TVI_MLP and the block solver)
  *   dLdp    [B][P] for per-series parameters (TVI_LINEAR, TVI_VANDERPOL,
  *           TVI_ROBERTSON); [P] for the shared parameters of TVI_MLP
  *   dLdy0   [B][n]
@@ -367,8 +383,10 @@ tvi_status tvi_solve_adjoint_noalloc(const tvi_model *model, const tvi_options *
  *                         g = 2 y / (n_observed n) at observed points, 0 elsewhere;
  *                         observed: uint8 [points] (device), n_observed its count
  * The sum is reduced in a fixed order (deterministic).  loss: one double
- * (device).  workspace: tvi_loss_workspace_bytes() bytes (device).  Enqueued
- * on `stream` without host synchronisation, so it can be captured in a graph.
+ * (device).  g may be NULL: then only the loss is computed (for the Frobenius
+ * loss the adjoint can take g = y with tvi_options.g_divisor = loss).
+ * workspace: tvi_loss_workspace_bytes() bytes (device).  Enqueued on `stream`
+ * without host synchronisation, so it can be captured in a graph.
  */
 typedef enum { TVI_LOSS_FROBENIUS = 0, TVI_LOSS_MEAN_SQUARE = 1 } tvi_loss_kind;
 size_t tvi_loss_workspace_bytes(void);

@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include "api_common.hpp"
+#include "grad_input.hpp"
 #include "dispatch.hpp"
 
 using namespace tvi;
@@ -102,7 +103,7 @@ tvi_status launch_block(int pass, const tvi_model *m, const blk::BlockArgs *ba, 
 }
 
 tvi_status solve_block(int pass, const tvi_model *m, const tvi_options *o, const SolveArgs<double> &a, void *ws,
-                       size_t ws_bytes, hipStream_t st)
+                       size_t ws_bytes, hipStream_t st, const GradInput *gi = nullptr)
 {
     tvi_status e = check_block(m, o);
     if (e != TVI_OK) return e;
@@ -117,6 +118,7 @@ tvi_status solve_block(int pass, const tvi_model *m, const tvi_options *o, const
     ba.NF = adj ? block_nf(m) : 0;
     ba.ws_stride = blk::ws_layout(blk::padded(m->n), o->chunk, ba.T, ba.NF).total;
     ba.ws = static_cast<double *>(ws);
+    ba.gi = gi ? *gi : GradInput{nullptr, nullptr, 0};
     return launch_block(pass, m, &ba, nullptr, st);
 }
 
@@ -202,6 +204,9 @@ void tvi_default_options(tvi_options *opt)
     opt->reference_residual = 0;
     opt->workspace = nullptr;
     opt->workspace_bytes = 0;
+    opt->g_divisor = nullptr;
+    opt->obs_idx = nullptr;
+    opt->n_obs = 0;
 }
 
 const char *tvi_status_str(int32_t s)
@@ -338,6 +343,8 @@ tvi_status tvi_solve_adjoint(const tvi_model *model, const tvi_options *opt, int
     if (B < 0 || N < 0) return TVI_EINVAL;
     if (B == 0) return TVI_OK;
     if (!times || !params || !g || !dLdp || !dLdy0 || !status) return TVI_EINVAL;
+    if (opt->obs_idx && offsets) return TVI_EINVAL;  // observed steps: uniform grids
+    const GradInput gi{opt->g_divisor, opt->obs_idx, opt->n_obs};
     const bool recompute = (y == nullptr);
     if (is_block(model)) {
         if (recompute) return TVI_EUNSUPPORTED;  // the block solver reads the stored trajectory
@@ -348,7 +355,7 @@ tvi_status tvi_solve_adjoint(const tvi_model *model, const tvi_options *opt, int
         a.dLdp = static_cast<double *>(dLdp);
         a.dLdy0 = static_cast<double *>(dLdy0);
         a.status = status;
-        return solve_block(1, model, opt, a, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
+        return solve_block(1, model, opt, a, workspace, workspace_bytes, static_cast<hipStream_t>(stream), &gi);
     }
     if (recompute && !ckpt) return TVI_EINVAL;
     if ((recompute || mlp) &&
@@ -368,7 +375,7 @@ tvi_status tvi_solve_adjoint(const tvi_model *model, const tvi_options *opt, int
             a.dLdy0 = static_cast<double *>(dLdy0);
             a.status = status;
             a.ws = static_cast<double *>(workspace);
-            return launch_mlp(pass, TVI_F64, &a, st);
+            return launch_mlp(pass, TVI_F64, &a, st, &gi);
         }
         SolveArgs<float> a = make_args<float>(opt, B, N, offsets, times, nullptr, params, model->params_shared);
         a.y = const_cast<float *>(static_cast<const float *>(y));
@@ -378,8 +385,10 @@ tvi_status tvi_solve_adjoint(const tvi_model *model, const tvi_options *opt, int
         a.dLdy0 = static_cast<float *>(dLdy0);
         a.status = status;
         a.ws = static_cast<double *>(workspace);
-        return launch_mlp(pass, TVI_F32, &a, st);
+        return launch_mlp(pass, TVI_F32, &a, st, &gi);
     }
+    // the register solver's adjoint reads the plain trajectory-shaped g
+    if (gi.div || gi.obs) return TVI_EUNSUPPORTED;
     int S, T;
     if ((e = resolve_tiling(opt, S, T)) != TVI_OK) return e;
     if (recompute && opt->init == TVI_INIT_PREDICTOR && (S < 4 || T * model->n > kPredictorMaxTN))
@@ -433,7 +442,7 @@ tvi_status tvi_loss_grad(int32_t kind, int32_t dtype, int64_t points, int32_t n,
     if (kind != TVI_LOSS_FROBENIUS && kind != TVI_LOSS_MEAN_SQUARE) return TVI_EINVAL;
     if (dtype != TVI_F32 && dtype != TVI_F64) return TVI_EINVAL;
     if (points < 0 || n < 1) return TVI_EINVAL;
-    if (!y || !g || !loss || !workspace || workspace_bytes < loss_workspace_bytes()) return TVI_EINVAL;
+    if (!y || !loss || !workspace || workspace_bytes < loss_workspace_bytes()) return TVI_EINVAL;
     double scale = 1.0;
     if (kind == TVI_LOSS_MEAN_SQUARE) {
         if (!observed || n_observed < 1) return TVI_EINVAL;

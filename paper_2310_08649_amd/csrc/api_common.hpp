@@ -49,6 +49,7 @@ inline tvi_status resolve_tiling(const tvi_options *o, int &S, int &T)
 inline tvi_status check_options(const tvi_options *o)
 {
     if (!o) return TVI_EINVAL;
+    if (o->obs_idx && o->n_obs < 1) return TVI_EINVAL;
     if (o->chunk < 1 || o->chunk > blk::kMaxChunk) return TVI_EINVAL;
     if (o->max_newton < 1) return TVI_EINVAL;
     if (!(o->tol_a >= 0.0) || !(o->tol_r >= 0.0)) return TVI_EINVAL;
@@ -105,6 +106,7 @@ inline tvi_status check_user_options(const tvi_options *o)
     if (e != TVI_OK) return e;
     if (o->init == TVI_INIT_PREDICTOR || o->scheme != TVI_BACKWARD_EULER || o->reference_residual != 0)
         return TVI_EUNSUPPORTED;
+    if (o->g_divisor || o->obs_idx) return TVI_EUNSUPPORTED;  // register solver: plain g only
     return TVI_OK;
 }
 

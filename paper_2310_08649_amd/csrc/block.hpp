@@ -26,6 +26,7 @@
 // (dh/dp(y_j))^T lam_j as sums over steps of products of per-step factors.
 #pragma once
 
+#include "grad_input.hpp"
 #include "solver.hpp"
 #include "tvi.h"
 
@@ -45,6 +46,7 @@ struct BlockArgs {
     int32_t NF;         // factors per step (adjoint)
     int64_t ws_stride;  // workspace doubles per launch slot
     double *ws;         // workspace [B][ws_stride]
+    GradInput gi;       // adjoint: how dL/dy is read
 };
 
 // Per-slot workspace, in doubles (row stride NP).
@@ -558,7 +560,8 @@ __global__ __launch_bounds__(kThreads) void block_adjoint_kernel(BlockArgs ba)
     Model model;
     model.init(n, a.params + sv.b * P);
     const double *t = sv.t;
-    const double *y = a.y + sv.p0 * n, *g = a.g + sv.p0 * n;
+    const double *y = a.y + sv.p0 * n;
+    const double gsc = grad_scale(ba.gi);  // g = (given g) / (*gi.div)
     double *z = cx.z(), *M = cx.M(), *F = cx.ws + cx.lay.F;
 
     if (tid < NP) L.lam[tid] = 0.0;
@@ -577,7 +580,8 @@ __global__ __launch_bounds__(kThreads) void block_adjoint_kernel(BlockArgs ba)
             double *yv = cx.vec(0), *gv = cx.vec(1);
             if (lane < NP) {
                 yv[lane] = lane < n ? y[(c0 + j) * n + lane] : 0.0;
-                gv[lane] = lane < n ? g[(c0 + j) * n + lane] : 0.0;
+                const double *gp = grad_at(a.g, ba.gi, sv.b, sv.p0, c0 + j, n);
+                gv[lane] = (lane < n && gp) ? gsc * gp[lane] : 0.0;
             }
             wave_sync();
             const double tj = t[c0 + j], hj = tj - t[c0 + j - 1];
@@ -642,7 +646,8 @@ __global__ __launch_bounds__(kThreads) void block_adjoint_kernel(BlockArgs ba)
         const int q = tid + r * kThreads;
         if (q < P) a.dLdp[sv.b * P + q] = all ? gq[r] : nan;
     }
-    if (tid < n) a.dLdy0[sv.b * n + tid] = all ? g[tid] + L.lam[tid] : nan;
+    const double *g0 = grad_at(a.g, ba.gi, sv.b, sv.p0, 0, n);
+    if (tid < n) a.dLdy0[sv.b * n + tid] = all ? (g0 ? gsc * g0[tid] : 0.0) + L.lam[tid] : nan;
     if (tid == 0) a.status[sv.b] = all ? ST_OK : ST_SINGULAR;
 }
 

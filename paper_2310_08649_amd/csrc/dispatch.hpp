@@ -174,7 +174,9 @@ tvi_status launch_ad_vdp_rob(int kind, int pass, const void *args, int S, int T,
 tvi_status launch_ad_linear(int n, int pass, const void *args, int S, int T, hipStream_t stream);
 tvi_status launch_pcr(int dtype, int n, int64_t B, int m, const void *D, const void *r, void *x, int transpose,
                       int S, int T, hipStream_t stream);
-tvi_status launch_mlp(int pass, int dtype, const void *args, hipStream_t stream);
+struct GradInput;
+// gi: how the adjoint reads dL/dy (null: the plain trajectory-shaped g)
+tvi_status launch_mlp(int pass, int dtype, const void *args, hipStream_t stream, const GradInput *gi = nullptr);
 size_t mlp_theta_workspace_bytes(int64_t B);
 tvi_status launch_mlp_eval(int dtype, int64_t M, const void *states, const void *params, void *f, void *J,
                            hipStream_t stream);

@@ -79,8 +79,9 @@ static tvi_status loss_launch(int kind, int64_t count, const IO *y, const uint8_
                        point_stride, partial);
     hipLaunchKernelGGL(loss_finish_kernel, dim3(1), dim3(kLossThreads), 0, stream, (const double *)partial, kind,
                        scale, loss);
-    hipLaunchKernelGGL(loss_grad_kernel<IO>, dim3(kLossBlocks), dim3(kLossThreads), 0, stream, count, y, observed,
-                       point_stride, kind, scale, (const double *)loss, g);
+    if (g)  // g null: the loss value only
+        hipLaunchKernelGGL(loss_grad_kernel<IO>, dim3(kLossBlocks), dim3(kLossThreads), 0, stream, count, y, observed,
+                           point_stride, kind, scale, (const double *)loss, g);
     return hipGetLastError() == hipSuccess ? TVI_OK : TVI_EHIP;
 }
 

@@ -26,6 +26,7 @@
 // adjoint evaluates position j at y_{s+j}: the map (I + dt_{s+j+1} J(y_{s+j}))^T
 // and the parameter term of step s+j+1 share that position's activations.
 #include "dispatch.hpp"
+#include "grad_input.hpp"
 #include "mlp.hpp"
 
 namespace tvi {
@@ -444,7 +445,7 @@ struct GradAcc {
 };
 
 template <class IO, bool RECOMPUTE, bool FE>
-__global__ __launch_bounds__(kThreads) void mlp_adjoint_kernel(SolveArgs<IO> a, float *theta_partial)
+__global__ __launch_bounds__(kThreads) void mlp_adjoint_kernel(SolveArgs<IO> a, float *theta_partial, GradInput gi)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     MlpShared &S = *reinterpret_cast<MlpShared *>(smem);
@@ -455,7 +456,12 @@ __global__ __launch_bounds__(kThreads) void mlp_adjoint_kernel(SolveArgs<IO> a, 
     if (!sv.valid) return;  // a launch order entry outside [0, B): the whole block idles
     const int64_t b = sv.b;
     const int C = a.chunk;
-    const IO *gb = a.g + sv.p0 * NS;
+    // dL/dy at step k (zero at steps that are not observed)
+    auto gat = [&](int64_t k, int e) -> float {
+        const IO *gp = grad_at(a.g, gi, b, sv.p0, k, NS);
+        return gp ? (float)ld(gp + e) : 0.f;
+    };
+    const float gsc = (float)grad_scale(gi);  // g = (given g) / (*gi.div)
 
     load_weights(S.W, a.params);
     if (tid < NS) S.lam[tid] = 0.f;
@@ -525,14 +531,14 @@ __global__ __launch_bounds__(kThreads) void mlp_adjoint_kernel(SolveArgs<IO> a, 
                 for (int rr = 0; rr < NS; ++rr) {
 #pragma unroll
                     for (int cc = 0; cc < NS; ++cc) map.F[rr][cc] = hj * S.u.J[j][cc * NS + rr];
-                    map.z[rr] = j == 0 ? 0.f : (float)ld(gb + (c0 + j) * NS + rr);
+                    map.z[rr] = j == 0 ? 0.f : gsc * gat(c0 + j, rr);
                 }
             } else {
                 // (I - dt J)^{-T} = I + F^T
                 float gk[NS], zero[NS];
                 ok = block_inverse_plus<true>(S.u.J[j], hj, map.F) ? 1 : 0;
 #pragma unroll
-                for (int k = 0; k < NS; ++k) { gk[k] = (float)ld(gb + (c0 + j + 1) * NS + k); zero[k] = 0.f; }
+                for (int k = 0; k < NS; ++k) { gk[k] = gsc * gat(c0 + j + 1, k); zero[k] = 0.f; }
                 apply_ip(map.F, gk, zero, map.z);
             }
         }
@@ -553,7 +559,7 @@ __global__ __launch_bounds__(kThreads) void mlp_adjoint_kernel(SolveArgs<IO> a, 
         for (int k = 0; k < NS; ++k) {
             // FE: the chunk's last step, lam_{c0+m} = g_{c0+m} + the carried value
             lin[k] = S.lam[k];
-            if constexpr (FE) lin[k] += (float)ld(gb + (c0 + m) * NS + k);
+            if constexpr (FE) lin[k] += gsc * gat(c0 + m, k);
         }
         for (int q = kWaves - 1; q > w; --q) {
             float tv[NS];
@@ -722,7 +728,7 @@ __global__ __launch_bounds__(kThreads) void mlp_adjoint_kernel(SolveArgs<IO> a, 
 
     // ---- dL/dy0 = g_0 + lam_1 (FE: g_0 + the carried (I + dt_1 J(y_0))^T lam_1), and the
     // series' parameter gradient (waves summed in order)
-    if (tid < NS) st(a.dLdy0 + b * NS + tid, status == ST_OK ? ld(gb + tid) + (double)S.lam[tid] : __builtin_nan(""));
+    if (tid < NS) st(a.dLdy0 + b * NS + tid, status == ST_OK ? (double)gsc * (double)gat(0, tid) + (double)S.lam[tid] : __builtin_nan(""));
     for (int idx = tid; idx < P; idx += kThreads) S.u.theta[idx] = 0.f;
     __syncthreads();
     for (int q = 0; q < kWaves; ++q) {
@@ -806,7 +812,7 @@ static bool allow_lds(K kernel)
 size_t mlp_theta_workspace_bytes(int64_t B) { return (size_t)B * P * sizeof(float); }
 
 template <class IO, bool FE>
-static tvi_status mlp_launch(int pass, const SolveArgs<IO> &a, hipStream_t stream)
+static tvi_status mlp_launch(int pass, const SolveArgs<IO> &a, hipStream_t stream, const GradInput &gi)
 {
     if (a.B == 0) return TVI_OK;
     if (a.B > 0x7fffffffLL) return TVI_EINVAL;
@@ -822,10 +828,10 @@ static tvi_status mlp_launch(int pass, const SolveArgs<IO> &a, hipStream_t strea
         float *partial = reinterpret_cast<float *>(a.ws);
         if (pass == PASS_ADJOINT) {
             if (!allow_lds(mlp_adjoint_kernel<IO, false, FE>)) return TVI_EHIP;
-            hipLaunchKernelGGL((mlp_adjoint_kernel<IO, false, FE>), grid, block, shm, stream, a, partial);
+            hipLaunchKernelGGL((mlp_adjoint_kernel<IO, false, FE>), grid, block, shm, stream, a, partial, gi);
         } else {
             if (!allow_lds(mlp_adjoint_kernel<IO, true, FE>)) return TVI_EHIP;
-            hipLaunchKernelGGL((mlp_adjoint_kernel<IO, true, FE>), grid, block, shm, stream, a, partial);
+            hipLaunchKernelGGL((mlp_adjoint_kernel<IO, true, FE>), grid, block, shm, stream, a, partial, gi);
         }
         if (hipGetLastError() != hipSuccess) return TVI_EHIP;
         hipLaunchKernelGGL(mlp_theta_reduce_kernel<IO>, dim3((P + 255) / 256), dim3(256), 0, stream, a.B,
@@ -838,15 +844,17 @@ static tvi_status mlp_launch(int pass, const SolveArgs<IO> &a, hipStream_t strea
 }
 
 template <class IO>
-static tvi_status mlp_launch_scheme(int pass, const SolveArgs<IO> &a, hipStream_t stream)
+static tvi_status mlp_launch_scheme(int pass, const SolveArgs<IO> &a, hipStream_t stream, const GradInput &gi)
 {
-    return a.scheme == 1 ? mlp_launch<IO, true>(pass, a, stream) : mlp_launch<IO, false>(pass, a, stream);
+    return a.scheme == 1 ? mlp_launch<IO, true>(pass, a, stream, gi) : mlp_launch<IO, false>(pass, a, stream, gi);
 }
 
-tvi_status launch_mlp(int pass, int dtype, const void *args, hipStream_t stream)
+tvi_status launch_mlp(int pass, int dtype, const void *args, hipStream_t stream, const GradInput *gi)
 {
-    if (dtype == TVI_F64) return mlp_launch_scheme<double>(pass, *static_cast<const SolveArgs<double> *>(args), stream);
-    return mlp_launch_scheme<float>(pass, *static_cast<const SolveArgs<float> *>(args), stream);
+    const GradInput g = gi ? *gi : GradInput{nullptr, nullptr, 0};
+    if (dtype == TVI_F64)
+        return mlp_launch_scheme<double>(pass, *static_cast<const SolveArgs<double> *>(args), stream, g);
+    return mlp_launch_scheme<float>(pass, *static_cast<const SolveArgs<float> *>(args), stream, g);
 }
 
 tvi_status launch_mlp_eval(int dtype, int64_t M, const void *states, const void *params, void *f, void *J,

@@ -29,7 +29,7 @@ class CapturedStep:
 
     def __init__(self, kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e-6), lanes=0, steps_per_lane=0,
                  max_newton=50, init="zero", loss="frobenius", observed=None, n_max=None, recompute=True,
-                 longest_first=True, scheme="backward_euler", jacobian="analytic"):
+                 longest_first=True, scheme="backward_euler", jacobian="analytic", fused=False):
         lib = tvi.load()
         self.kind = kind
         self.recompute = recompute
@@ -60,9 +60,16 @@ class CapturedStep:
         self.ckpt = torch.empty((B, K, n), dtype=torch.float64, device=dev) if recompute else None
         self.status_fwd = torch.empty(B, dtype=torch.int32, device=dev)
         self.iters = torch.empty(B, dtype=torch.int32, device=dev)
-        self.g = torch.empty_like(self.y)
         self.loss = torch.empty(1, dtype=torch.float64, device=dev)
         self.loss_kind = LOSS[loss]
+        # fused (Frobenius loss only): the loss kernel computes L alone and the adjoint
+        # reads g = y / L from the trajectory (tvi_options.g_divisor), never forming g
+        if fused and self.loss_kind != LOSS["frobenius"]:
+            raise tvi.TviError("the fused gradient is the Frobenius loss's (g = y / L)")
+        if fused and not (kind == "mlp" or tvi.is_block(kind, n)):
+            raise tvi.TviError("the fused gradient is offered by the neural-ODE and block solvers")
+        self.fused = fused
+        self.g = None if fused else torch.empty_like(self.y)
         self.observed = None if observed is None else observed.to(device=dev, dtype=torch.uint8).contiguous()
         self.n_observed = int(self.observed.sum().item()) if self.observed is not None else 0
         self.loss_ws = torch.empty(max(1, lib.tvi_loss_workspace_bytes()), dtype=torch.uint8, device=dev)
@@ -104,15 +111,21 @@ class CapturedStep:
                                      self.n_observed, P(self.g), P(self.loss), P(self.loss_ws),
                                      self.loss_ws.numel(), tvi._stream()), "tvi_loss_grad")
 
+    @property
+    def grad_input(self):
+        """What the adjoint reads as g (the trajectory itself when fused)."""
+        return self.y if self.fused else self.g
+
     def launch_adjoint(self):
         """The adjoint alone (current stream)."""
         lib = tvi.load()
         P = tvi._ptr
+        self.opt.g_divisor = self.loss.data_ptr() if self.fused else None
         tvi._check(lib.tvi_solve_adjoint(ctypes.byref(self.model), ctypes.byref(self.opt), self.B, self.N,
                                          P(self.offsets), P(self.times), P(self.params),
                                          None if self.recompute else P(self.y), P(self.ckpt),
-                                         P(self.g), P(self.dLdp), P(self.dLdy0), P(self.status_adj), P(self.ws),
-                                         self.ws_bytes, tvi._stream()), "tvi_solve_adjoint")
+                                         P(self.grad_input), P(self.dLdp), P(self.dLdy0), P(self.status_adj),
+                                         P(self.ws), self.ws_bytes, tvi._stream()), "tvi_solve_adjoint")
 
     def _launch(self):
         self.launch_forward()

@@ -50,7 +50,8 @@ class Options(ctypes.Structure):
                 ("predictor_base", ctypes.c_int32), ("order", ctypes.c_void_p), ("scheme", ctypes.c_int32),
                 ("jacobian", ctypes.c_int32),
                 ("reference_residual", ctypes.c_int32), ("workspace", ctypes.c_void_p),
-                ("workspace_bytes", ctypes.c_size_t)]
+                ("workspace_bytes", ctypes.c_size_t), ("g_divisor", ctypes.c_void_p),
+                ("obs_idx", ctypes.c_void_p), ("n_obs", ctypes.c_int32)]
 
 
 _lib = None
@@ -261,13 +262,17 @@ def solve_forward(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e
 def solve_adjoint(kind, times, params, g, y=None, ckpt=None, offsets=None, chunk=64, tol=(1e-8, 1e-6),
                   max_newton=50, lanes=0, steps_per_lane=0, init="zero", halving=True, n=None, predictor=None,
                   order=None, scheme="backward_euler", jacobian="analytic", n_max=None,
-                  reference="first", noalloc=False):
+                  reference="first", noalloc=False, g_divisor=None, obs_idx=None):
     """Discrete adjoint.  Returns ``(dLdp [B,P], dLdy0 [B,n], status [B])``.
 
     States come from the trajectory ``y`` or, when ``y`` is None, are recomputed
     from ``ckpt`` (then the options must equal those of the forward pass).
     ``noalloc=True`` calls ``tvi_solve_adjoint_noalloc``: the workspace is the
-    library's static device scratch instead of a tensor allocated here."""
+    library's static device scratch instead of a tensor allocated here.
+    ``g_divisor``: a one-element float64 device tensor dividing every entry of
+    ``g`` (``tvi_options.g_divisor``).  ``obs_idx``: int32 device tensor of the
+    observed steps (strictly increasing; uniform grids); ``g`` is then
+    ``[B, n_obs, n]`` (``tvi_options.obs_idx``)."""
     dt = g.dtype
     times = _dev(times, dt, "times")
     params = _dev(params, dt, "params")
@@ -281,6 +286,8 @@ def solve_adjoint(kind, times, params, g, y=None, ckpt=None, offsets=None, chunk
     if offsets is None:
         B, n = g.shape[0], g.shape[2]
         N = times.shape[0] - 1
+        if obs_idx is None and g.shape[1] != N + 1:
+            raise TviError("g must be [B, N+1, n] (or [B, n_obs, n] with obs_idx)")
     else:
         B, n = offsets.shape[0] - 1, g.shape[1]
         N = int(n_max) if n_max is not None else (int((offsets[1:] - offsets[:-1]).max().item()) - 1 if B else 0)
@@ -290,6 +297,15 @@ def solve_adjoint(kind, times, params, g, y=None, ckpt=None, offsets=None, chunk
     model = Model(KINDS[kind], n, _io_dtype(g), 1 if shared else 0, 64)
     opt = make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, halving, predictor, order, scheme,
                        jacobian, reference)
+    if g_divisor is not None:
+        g_divisor = _dev(g_divisor, torch.float64, "g_divisor")
+        opt.g_divisor = g_divisor.data_ptr()
+    if obs_idx is not None:
+        obs_idx = _dev(obs_idx, torch.int32, "obs_idx")
+        if offsets is not None or g.shape[1] != obs_idx.shape[0]:
+            raise TviError("obs_idx: uniform grids, g [B, n_obs, n]")
+        opt.obs_idx = obs_idx.data_ptr()
+        opt.n_obs = obs_idx.shape[0]
     lib = load()
     dev = g.device
     P = lib.tvi_param_count(ctypes.byref(model))

@@ -299,3 +299,36 @@ def test_noalloc_adjoint_rejects_more_than_its_scratch_on_the_host(lib):
     o.chunk = 0
     assert lib.tvi_solve_adjoint_noalloc(ctypes.byref(m), ctypes.byref(o), 4, 100, None, f, f, None, f, f, f, f, f,
                                          None) == -1
+
+
+def test_observed_steps_option_is_checked(lib):
+    """obs_idx needs n_obs >= 1 and a uniform grid."""
+    from paper_2310_08649_amd import tvi
+    f = _fake()
+    m = tvi.Model(1, 2, tvi.F64, 0, 64)
+    o = tvi.make_options(chunk=16)
+    o.obs_idx = 0x1000
+    o.n_obs = 0
+    assert lib.tvi_solve_adjoint(ctypes.byref(m), ctypes.byref(o), 4, 10, None, f, f, f, None, f, f, f, f, None, 0,
+                                 None) == -1
+    o.n_obs = 3
+    assert lib.tvi_solve_adjoint(ctypes.byref(m), ctypes.byref(o), 4, 10, f, f, f, f, None, f, f, f, f, None, 0,
+                                 None) == -1   # ragged (offsets given)
+
+
+def test_register_solver_refuses_divided_or_observed_gradients(lib):
+    """The divided gradient (g_divisor) and observed-step gradients (obs_idx)
+    are offered by the neural-ODE and block solvers; the register solver's
+    adjoint refuses them with TVI_EUNSUPPORTED before any HIP call."""
+    from paper_2310_08649_amd import tvi
+    f = _fake()
+    m = tvi.Model(1, 2, tvi.F64, 0, 64)
+    o = tvi.make_options(chunk=16)
+    o.g_divisor = 0x1000
+    assert lib.tvi_solve_adjoint(ctypes.byref(m), ctypes.byref(o), 4, 10, None, f, f, f, None, f, f, f, f, None, 0,
+                                 None) == -4
+    o.g_divisor = None
+    o.obs_idx = 0x1000
+    o.n_obs = 3
+    assert lib.tvi_solve_adjoint(ctypes.byref(m), ctypes.byref(o), 4, 10, None, f, f, f, None, f, f, f, f, None, 0,
+                                 None) == -4

@@ -134,3 +134,52 @@ def test_captured_step_with_solver_options_replays_exactly(mods, opts):
                               scheme=scheme)
     dp = ref[2].cpu().numpy()
     assert (np.abs(dp - op).max(axis=1) / np.abs(op).max(axis=1)).max() <= 1e-10
+
+
+@pytest.mark.parametrize("kind", ["mds", "mlp"])
+def test_fused_frobenius_gradient_equals_the_formed_one(mods, kind):
+    """The Frobenius loss's gradient read by the adjoint as y / L from the
+    trajectory (tvi_options.g_divisor; the loss kernel computes L alone)
+    against the graph that forms g = y / L in memory, for the block solver and
+    the neural ODE: the same gradients to rounding (one reciprocal instead of
+    a division per entry), every replay bitwise equal to the first."""
+    graph, tvi = mods
+    f64 = torch.float64
+    if kind == "mds":
+        w = W.mds(3, 4, n_time=300, t_max=0.05)
+        kw = dict(chunk=100, steps_per_lane=10)
+    else:
+        w = W.mlp(B=6, N=400)
+        f64 = torch.float32
+        kw = dict(chunk=100)
+    # the float network's Newton stops at the float tolerance
+    tol = PARITY_TOL if f64 == torch.float64 else (1e-8, 1e-6)
+    args = (dev(w["y0"], f64), dev(w["times"], f64), dev(w["params"], f64))
+    for recompute in ((False, True) if kind == "mlp" else (False,)):
+        runs = {}
+        for fused in (False, True):
+            step = graph.CapturedStep(kind, *args, tol=tol, loss="frobenius", recompute=recompute,
+                                      fused=fused, **kw).capture()
+            step.replay()
+            torch.cuda.synchronize()
+            first = (step.dLdp.clone(), step.dLdy0.clone())
+            for _ in range(3):
+                step.replay()
+                torch.cuda.synchronize()
+                assert torch.equal(step.dLdp, first[0]) and torch.equal(step.dLdy0, first[1])
+            assert (step.status_fwd.cpu() == 0).all() and (step.status_adj.cpu() == 0).all()
+            runs[fused] = first
+        gate = 1e-13 if f64 == torch.float64 else 1e-5
+        for a, b in zip(runs[True], runs[False]):
+            a, b = a.double().cpu().numpy(), b.double().cpu().numpy()
+            assert np.abs(a - b).max() <= gate * np.abs(b).max(), (kind, recompute)
+
+
+def test_fused_gradient_is_refused_by_the_register_solver(mods):
+    """The register solver's adjoint reads the plain trajectory-shaped g: the
+    fused graph is refused for its models."""
+    graph, tvi = mods
+    w = W.vanderpol(B=4, N=50, mu_range=(1.0, 5.0))
+    args = (dev(w["y0"]), dev(w["times"]), dev(w["params"]))
+    with pytest.raises(tvi.TviError):
+        graph.CapturedStep("vanderpol", *args, chunk=10, loss="frobenius", fused=True)

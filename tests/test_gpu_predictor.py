@@ -85,8 +85,10 @@ def test_predictor_training_reduces_loss(mods):
 def test_trained_predictor_gains_over_extrapolation(mods):
     """Train on chunks the solver itself computed, then solve held-out series
     from the zero start, the extrapolated start and the learned start: all
-    reach the same trajectory; the learned start is closer to the converged
-    chunk and needs fewer Newton iterations."""
+    reach the same trajectory and the learned start is closer to the converged
+    chunk.  The gain the method would need, fewer Newton corrections, is
+    asserted last and reported as an expected failure while it does not hold:
+    on this smooth problem every start needs exactly one correction per chunk."""
     pred, tvi = mods
     C, tol = 50, (1e-8, 1e-6)
     f32 = lambda a: torch.tensor(np.asarray(a, dtype=np.float32), device="cuda")
@@ -132,6 +134,9 @@ def test_trained_predictor_gains_over_extrapolation(mods):
         its0[init] = int(it.sum().item())
     print("with the zero-increment reference: extrapolation %d, predictor %d" % (its0["extrap"], its0["predictor"]))
     assert its0["predictor"] <= its0["extrap"] <= its["extrap"]
+    if not its["predictor"] < its["extrap"]:
+        pytest.xfail("the learned start saves no Newton correction (%d against %d from the extrapolated start): "
+                     "each start needs one correction per chunk" % (its["predictor"], its["extrap"]))
 
 
 def _dev64(a):
@@ -208,3 +213,6 @@ def test_predictor_on_robertson(mods):
     print("Robertson Newton corrections: zero %d, predictor %d; initial iterate MSE: zero %.3e, predictor %.3e"
           % (its["zero"], its["predictor"], err_zero, err_pred))
     assert err_pred < err_zero
+    if not its["predictor"] < its["zero"]:
+        pytest.xfail("the learned start needs no fewer Newton corrections than the zero start (%d against %d): the "
+                     "absolute tolerance binds on most chunks" % (its["predictor"], its["zero"]))
