@@ -91,12 +91,29 @@ __device__ __forceinline__ f32x4 mma_acc(const Split &a, const Split &b, f32x4 c
 
 __device__ __forceinline__ int kchain(int ks, int g, int e) { return 32 * ks + 16 * (e >> 2) + 4 * g + (e & 3); }
 
-// Weights in LDS as float, stored per (tile, lane) in operand order: a lane
-// reads its eight k-elements with two 16-byte loads and splits them.
+// One operand tile of the network's forward pass, split once when the weights
+// are loaded (x = p0 + p1 + p2): a lane reads its eight k-elements of each part
+// with one 16-byte load (the parts stored apart: consecutive lanes, consecutive
+// 16 bytes), and the plain bf16 products read p0 alone.
+struct Tile {
+    bf16x8 p0[kWave], p1[kWave], p2[kWave];
+    __device__ __forceinline__ Split at(int l) const { return Split{p0[l], p1[l], p2[l]}; }
+    __device__ __forceinline__ void put(int l, const float (&x)[8])
+    {
+        const Split s = split8(x);
+        p0[l] = s.p0;
+        p1[l] = s.p1;
+        p2[l] = s.p2;
+    }
+};
+
+// Weights in LDS, per (tile, lane) in operand order.  The forward pass's tiles
+// are stored split; the adjoint's transposed tiles as float (split where used:
+// the LDS holds no more).
 struct Weights {
-    float w1[4][kWave][8];       // W1   [64 x 8]:  M-tiles 0..3, one K-step (k = 8 g + e, k < 8)
-    float w2[4][2][kWave][8];    // W2   [64 x 64]: M-tiles, chained K-steps
-    float w3[2][kWave][8];       // W3   [8 x 64]:  one M-tile (rows 8..15 zero), chained K-steps
+    Tile w1[4];                  // W1   [64 x 8]:  M-tiles 0..3, one K-step (k = 8 g + e, k < 8)
+    Tile w2[4][2];               // W2   [64 x 64]: M-tiles, chained K-steps
+    Tile w3[2];                  // W3   [8 x 64]:  one M-tile (rows 8..15 zero), chained K-steps
     float w3t[4][kWave][8];      // W3^T [64 x 8]:  M-tiles, one K-step (k = 8 g + e, k < 8)
     float w2t[4][2][kWave][8];   // W2^T [64 x 64]
     float w1p[2][4][8][NS];      // W1[k(ks, g, e)][c]: the Jacobian's first factor
@@ -117,11 +134,9 @@ __device__ void load_weights(Weights &W, const IO *th)
             a[e] = k < NS ? (float)th[oW1 + (16 * mt + r) * NS + k] : 0.f;   // W1[m][k]
             b[e] = k < NS ? (float)th[oW3 + k * H + 16 * mt + r] : 0.f;     // W3^T[m][k] = W3[k][m]
         }
+        W.w1[mt].put(l, a);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            W.w1[mt][l][e] = a[e];
-            W.w3t[mt][l][e] = b[e];
-        }
+        for (int e = 0; e < 8; ++e) W.w3t[mt][l][e] = b[e];
     }
     for (int idx = t; idx < 8 * kWave; idx += kThreads) {
         const int mt = idx / (2 * kWave), ks = (idx / kWave) & 1, l = idx % kWave, g = l >> 4, r = l & 15;
@@ -132,19 +147,16 @@ __device__ void load_weights(Weights &W, const IO *th)
             a[e] = (float)th[oW2 + (16 * mt + r) * H + k];   // W2[m][k]
             b[e] = (float)th[oW2 + k * H + 16 * mt + r];     // W2^T[m][k] = W2[k][m]
         }
+        W.w2[mt][ks].put(l, a);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            W.w2[mt][ks][l][e] = a[e];
-            W.w2t[mt][ks][l][e] = b[e];
-        }
+        for (int e = 0; e < 8; ++e) W.w2t[mt][ks][l][e] = b[e];
     }
     for (int idx = t; idx < 2 * kWave; idx += kThreads) {
         const int ks = idx / kWave, l = idx % kWave, g = l >> 4, r = l & 15;
         float a[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) a[e] = r < NS ? (float)th[oW3 + r * H + kchain(ks, g, e)] : 0.f;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) W.w3[ks][l][e] = a[e];
+        W.w3[ks].put(l, a);
     }
     for (int idx = t; idx < 2 * 4 * 8 * NS; idx += kThreads) {
         const int c = idx % NS, e = (idx / NS) % 8, g = (idx / (NS * 8)) % 4, ks = idx / (NS * 32);
@@ -190,7 +202,7 @@ __device__ __forceinline__ void forward(const Weights &W, Acts &A, GetY get_y, P
         for (int i = 0; i < 4; ++i) bias[i] = W.b1[16 * mt + 4 * g + i];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            f32x4 z = mma_acc<true>(split_lds(W.w1[mt][l]), yb[u], bias);
+            f32x4 z = mma_acc<true>(W.w1[mt].at(l), yb[u], bias);
 #pragma unroll
             for (int i = 0; i < 4; ++i) A.a1[mt][u][i] = tanhf(z[i]);
         }
@@ -211,8 +223,8 @@ __device__ __forceinline__ void forward(const Weights &W, Acts &A, GetY get_y, P
             f32x4 z;
 #pragma unroll
             for (int i = 0; i < 4; ++i) z[i] = W.b2[16 * mt + 4 * g + i];
-            z = mma_acc<true>(split_lds(W.w2[mt][0][l]), bk[0], z);
-            z = mma_acc<true>(split_lds(W.w2[mt][1][l]), bk[1], z);
+            z = mma_acc<true>(W.w2[mt][0].at(l), bk[0], z);
+            z = mma_acc<true>(W.w2[mt][1].at(l), bk[1], z);
 #pragma unroll
             for (int i = 0; i < 4; ++i) A.a2[mt][u][i] = tanhf(z[i]);
         }
@@ -228,7 +240,7 @@ __device__ __forceinline__ void forward(const Weights &W, Acts &A, GetY get_y, P
             float v[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) v[e] = A.a2[2 * ks + (e >> 2)][u][e & 3];
-            z = mma_acc<true>(split_lds(W.w3[ks][l]), split8(v), z);
+            z = mma_acc<true>(W.w3[ks].at(l), split8(v), z);
         }
         if (g < 2) {
 #pragma unroll
@@ -270,8 +282,8 @@ __device__ __forceinline__ void jacobian(const Weights &W, const Acts &A, PutJ p
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
                 f32x4 z = {0.f, 0.f, 0.f, 0.f};
-                z = mma_acc<EXACT>(split_lds(W.w2[mt][0][l]), bk[0], z);
-                p2[mt] = mma_acc<EXACT>(split_lds(W.w2[mt][1][l]), bk[1], z);
+                z = mma_acc<EXACT>(W.w2[mt][0].at(l), bk[0], z);
+                p2[mt] = mma_acc<EXACT>(W.w2[mt][1].at(l), bk[1], z);
             }
             f32x4 j = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -279,7 +291,7 @@ __device__ __forceinline__ void jacobian(const Weights &W, const Acts &A, PutJ p
                 float v[8];
 #pragma unroll
                 for (int e = 0; e < 8; ++e) v[e] = d2[2 * ks + (e >> 2)][e & 3] * p2[2 * ks + (e >> 2)][e & 3];
-                j = mma_acc<EXACT>(split_lds(W.w3[ks][l]), split8(v), j);
+                j = mma_acc<EXACT>(W.w3[ks].at(l), split8(v), j);
             }
             if (g < 2) {
 #pragma unroll

@@ -225,6 +225,67 @@ __device__ __forceinline__ bool block_inverse_plus(const float *J, float dt, flo
     return ok;
 }
 
+// ||dt J||_inf of a block (J row-major in LDS), and its largest value over the
+// wave (every lane calls it: the choice below is wave-uniform; non-finite
+// entries count as infinite, so such a block reaches the pivoting inverse and
+// its check).
+__device__ __forceinline__ float wave_block_norm(const float *J, float dt, bool v)
+{
+    float en = 0.f;
+#pragma unroll
+    for (int r = 0; r < NS; ++r) {
+        float rs = 0.f;
+#pragma unroll
+        for (int c = 0; c < NS; ++c) rs += fabsf(J[r * NS + c]);
+        en = fmaxf(en, rs == rs ? rs : __builtin_inff());  // a NaN block takes the pivoting path
+    }
+    en = v ? fabsf(dt) * en : 0.f;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) en = fmaxf(en, __shfl_xor(en, o));
+    return en;
+}
+
+// I + F = (I - E)^{-1}, E = dt J, F^T if TRANSPOSE.  With eps = ||E||_inf (the
+// wave's largest), F = E + E^2 + ... : the terms after E^K sum to at most
+// eps^(K+1) / (1 - eps), and ||F|| >= ||E|| / (1 + eps), so cutting the series
+// after K terms errs by at most eps^K (1 + eps) / (1 - eps) relative to F.
+// K = 2 (one 8x8 product) where eps <= 2^-12 and K = 3 (two) where eps <=
+// 2^-8 keep that at float rounding (2^-24); a neural ODE over short steps is
+// there (dt ||J|| ~ 1e-4).  Beyond, Gauss-Jordan with partial pivoting.
+template <bool TRANSPOSE>
+__device__ __forceinline__ bool inverse_plus(const float *J, float dt, float eps, float (&F)[NS][NS])
+{
+    if (!(eps <= 0x1p-8f)) return block_inverse_plus<TRANSPOSE>(J, dt, F);
+    float E[NS][NS], G[NS][NS];
+#pragma unroll
+    for (int r = 0; r < NS; ++r)
+#pragma unroll
+        for (int c = 0; c < NS; ++c) E[r][c] = dt * J[r * NS + c];
+    // G = E (two terms) or E + E E (three); then F = E + E G
+#pragma unroll
+    for (int r = 0; r < NS; ++r)
+#pragma unroll
+        for (int c = 0; c < NS; ++c) {
+            float acc = E[r][c];
+            if (eps > 0x1p-12f) {
+#pragma unroll
+                for (int k = 0; k < NS; ++k) acc = fmaf(E[r][k], E[k][c], acc);
+            }
+            G[r][c] = acc;
+        }
+#pragma unroll
+    for (int r = 0; r < NS; ++r)
+#pragma unroll
+        for (int c = 0; c < NS; ++c) {
+            float acc = E[r][c];
+#pragma unroll
+            for (int k = 0; k < NS; ++k) acc = fmaf(E[r][k], G[k][c], acc);
+            if (TRANSPOSE) F[c][r] = acc;
+            else F[r][c] = acc;
+        }
+    return true;  // eps < 1: I - E is invertible
+}
+
 // Backward Euler from step s0 (state ys) to s_end in attempts that never cross
 // a multiple of C.  Every thread of the block calls it; returns the status.
 template <bool FE, class IO, class Sink>
@@ -340,6 +401,7 @@ __device__ int mlp_solve(MlpShared &S, const SolveArgs<IO> &a, const IO *t, doub
         // ---- Newton correction
         mlp_jacobians(S, A, false);
         __syncthreads();
+        const float eps = FE ? 0.f : wave_block_norm(S.u.J[j], hj, v);
         AffineI<NS, float> map;
         affine_identity(map);
         int ok = 1;
@@ -354,7 +416,7 @@ __device__ int mlp_solve(MlpShared &S, const SolveArgs<IO> &a, const IO *t, doub
                 }
             } else {
                 // (I - dt J)^{-1} = I + F; the correction map x -> (I + F)(x - R)
-                ok = block_inverse_plus<false>(S.u.J[j], hj, map.F) ? 1 : 0;
+                ok = inverse_plus<false>(S.u.J[j], hj, eps, map.F) ? 1 : 0;
                 float negR[NS], zero[NS];
 #pragma unroll
                 for (int k = 0; k < NS; ++k) { negR[k] = -R[k]; zero[k] = 0.f; }
@@ -520,6 +582,7 @@ __global__ __launch_bounds__(kThreads) void mlp_adjoint_kernel(SolveArgs<IO> a, 
         // ---- transposed blocks and the reduction from the last step down
         const double t1 = ld(sv.t + (v ? c0 + j + 1 : c0)), t0 = ld(sv.t + (v ? c0 + j : c0));
         const float hj = (float)(t1 - t0);
+        const float eps = FE ? 0.f : wave_block_norm(S.u.J[j], hj, v);
         AffineI<NS, float> map;
         affine_identity(map);
         int ok = 1;
@@ -536,7 +599,7 @@ __global__ __launch_bounds__(kThreads) void mlp_adjoint_kernel(SolveArgs<IO> a, 
             } else {
                 // (I - dt J)^{-T} = I + F^T
                 float gk[NS], zero[NS];
-                ok = block_inverse_plus<true>(S.u.J[j], hj, map.F) ? 1 : 0;
+                ok = inverse_plus<true>(S.u.J[j], hj, eps, map.F) ? 1 : 0;
 #pragma unroll
                 for (int k = 0; k < NS; ++k) { gk[k] = gsc * gat(c0 + j + 1, k); zero[k] = 0.f; }
                 apply_ip(map.F, gk, zero, map.z);
