@@ -245,45 +245,229 @@ __device__ __forceinline__ float wave_block_norm(const float *J, float dt, bool 
     return en;
 }
 
-// I + F = (I - E)^{-1}, E = dt J, F^T if TRANSPOSE.  With eps = ||E||_inf (the
-// wave's largest), F = E + E^2 + ... : the terms after E^K sum to at most
-// eps^(K+1) / (1 - eps), and ||F|| >= ||E|| / (1 + eps), so cutting the series
-// after K terms errs by at most eps^K (1 + eps) / (1 - eps) relative to F.
-// K = 2 (one 8x8 product) where eps <= 2^-12 and K = 3 (two) where eps <=
-// 2^-8 keep that at float rounding (2^-24); a neural ODE over short steps is
-// there (dt ||J|| ~ 1e-4).  Beyond, Gauss-Jordan with partial pivoting.
-template <bool TRANSPOSE>
-__device__ __forceinline__ bool inverse_plus(const float *J, float dt, float eps, float (&F)[NS][NS])
+// ---------------------------------------------------------------------------
+// Row halves of the chunk's affine maps.  Lanes l and l + 32 hold the same step
+// of the chunk; each keeps rows 4h..4h+3 (h = l / 32) of the step's map, with
+// the columns in the lane's order, its own block first: column p is natural
+// column p ^ 4h.  The other half's rows then index the same columns as p ^ 4,
+// so every register index stays static, and a composition costs each lane half
+// the products of a whole one.  Row i of a half is natural row i ^ 4h too, so
+// entry (i, p) of a lane's half is natural entry (i ^ 4h, p ^ 4h).
+// ---------------------------------------------------------------------------
+struct HalfMap {
+    float F[4][NS];
+    float z[4];
+};
+
+__device__ __forceinline__ bool upper_half() { return (lane_id() & 32) != 0; }
+__device__ __forceinline__ float other_half(float x) { return __shfl_xor(x, 32); }
+
+__device__ __forceinline__ void half_identity(HalfMap &a)
 {
-    if (!(eps <= 0x1p-8f)) return block_inverse_plus<TRANSPOSE>(J, dt, F);
-    float E[NS][NS], G[NS][NS];
 #pragma unroll
-    for (int r = 0; r < NS; ++r)
+    for (int i = 0; i < 4; ++i) {
 #pragma unroll
-        for (int c = 0; c < NS; ++c) E[r][c] = dt * J[r * NS + c];
-    // G = E (two terms) or E + E E (three); then F = E + E G
+        for (int p = 0; p < NS; ++p) a.F[i][p] = 0.f;
+        a.z[i] = 0.f;
+    }
+}
+
+// A natural-order vector in the lane's order.
+__device__ __forceinline__ void lane_order(const float (&x)[NS], float (&y)[NS], bool up)
+{
 #pragma unroll
-    for (int r = 0; r < NS; ++r)
+    for (int p = 0; p < NS; ++p) y[p] = up ? x[p ^ 4] : x[p];
+}
+
+// The natural-order vector whose rows 4h..4h+3 are `own` (the other half
+// holding the rest).  Every lane calls it.
+__device__ __forceinline__ void join_halves(const float (&own)[4], float (&x)[NS], bool up)
+{
+    float oth[4];
 #pragma unroll
-        for (int c = 0; c < NS; ++c) {
-            float acc = E[r][c];
+    for (int i = 0; i < 4; ++i) oth[i] = other_half(own[i]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        x[i] = up ? oth[i] : own[i];
+        x[4 + i] = up ? own[i] : oth[i];
+    }
+}
+
+// a <- a o b, b the map of another step: b its rows of this half, bo its rows
+// of the other half as that half keeps them.
+//   F = Fa + Fb + Fa Fb,  z = za + zb + Fa zb
+__device__ __forceinline__ void half_after(HalfMap &a, const HalfMap &b, const HalfMap &bo)
+{
+    float Fn[4][NS], zn[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        float t = a.z[i] + b.z[i];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) t = fmaf(a.F[i][k], b.z[k], t);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) t = fmaf(a.F[i][4 + k], bo.z[k], t);
+        zn[i] = t;
+#pragma unroll
+        for (int p = 0; p < NS; ++p) {
+            float u = a.F[i][p] + b.F[i][p];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) u = fmaf(a.F[i][k], b.F[k][p], u);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) u = fmaf(a.F[i][4 + k], bo.F[k][p ^ 4], u);
+            Fn[i][p] = u;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int p = 0; p < NS; ++p) a.F[i][p] = Fn[i][p];
+        a.z[i] = zn[i];
+    }
+}
+
+// b <- a moved by a DPP control (zero fill: the identity), bo <- the other
+// half's b.  Every lane calls it.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void half_move(const HalfMap &a, HalfMap &b, HalfMap &bo)
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int p = 0; p < NS; ++p) b.F[i][p] = dpp_zero<CTRL, ROWS>(a.F[i][p]);
+        b.z[i] = dpp_zero<CTRL, ROWS>(a.z[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int p = 0; p < NS; ++p) bo.F[i][p] = other_half(b.F[i][p]);
+        bo.z[i] = other_half(b.z[i]);
+    }
+}
+
+// Inclusive prefix composition over each 32-lane half, lowest lane first
+// (lane q ends with A_q o ... o A_0): row shifts inside 16-lane rows, then
+// rows 1 and 3 take the totals of rows 0 and 2 (lanes 15, 47).
+__device__ __forceinline__ void half_scan_up(HalfMap &a)
+{
+    HalfMap b, bo;
+    half_move<dpp::ROW_SHR + 1, 0xF>(a, b, bo);
+    half_after(a, b, bo);
+    half_move<dpp::ROW_SHR + 2, 0xF>(a, b, bo);
+    half_after(a, b, bo);
+    half_move<dpp::ROW_SHR + 4, 0xF>(a, b, bo);
+    half_after(a, b, bo);
+    half_move<dpp::ROW_SHR + 8, 0xF>(a, b, bo);
+    half_after(a, b, bo);
+    half_move<dpp::ROW_BCAST15, 0xA>(a, b, bo);
+    half_after(a, b, bo);
+}
+
+// Inclusive suffix composition, highest lane first (lane q ends with
+// A_q o ... o A_31): row shifts, then rows 0 and 2 take the totals of rows 1
+// and 3 (lanes 16, 48; read by lane broadcast).
+__device__ __forceinline__ void half_scan_down(HalfMap &a)
+{
+    HalfMap b, bo;
+    half_move<dpp::ROW_SHL + 1, 0xF>(a, b, bo);
+    half_after(a, b, bo);
+    half_move<dpp::ROW_SHL + 2, 0xF>(a, b, bo);
+    half_after(a, b, bo);
+    half_move<dpp::ROW_SHL + 4, 0xF>(a, b, bo);
+    half_after(a, b, bo);
+    half_move<dpp::ROW_SHL + 8, 0xF>(a, b, bo);
+    half_after(a, b, bo);
+    const bool up = upper_half(), take = (lane_id() & 16) == 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int p = 0; p < NS; ++p) {
+            const float lo = lane_bcast(a.F[i][p], 16), hi = lane_bcast(a.F[i][p], 48);
+            b.F[i][p] = take ? (up ? hi : lo) : 0.f;
+            bo.F[i][p] = take ? (up ? lo : hi) : 0.f;
+        }
+        const float lo = lane_bcast(a.z[i], 16), hi = lane_bcast(a.z[i], 48);
+        b.z[i] = take ? (up ? hi : lo) : 0.f;
+        bo.z[i] = take ? (up ? lo : hi) : 0.f;
+    }
+    half_after(a, b, bo);
+}
+
+// This half's rows of F, I + F = (I - E)^{-1} with E = dt J (its transpose if
+// TRANSPOSE), in the lane's order.  With eps = ||E||_inf (the wave's largest,
+// so the choice is wave-uniform), F = E + E^2 + ... : the terms after E^K sum
+// to at most eps^(K+1) / (1 - eps), and ||F|| >= ||E|| / (1 + eps), so cutting
+// the series after K terms errs by at most eps^K (1 + eps) / (1 - eps)
+// relative to F.  K = 2 (one product) where eps <= 2^-12 and K = 3 (two) where
+// eps <= 2^-8 keep that at float rounding (2^-24); a neural ODE over short
+// steps is there (dt ||J|| ~ 1e-4).  Beyond, Gauss-Jordan with partial pivoting.
+template <bool TRANSPOSE>
+__device__ __forceinline__ bool half_inverse_plus(const float *J, float dt, float eps, bool up, float (&Fo)[4][NS])
+{
+    const int m = up ? 4 : 0;
+    if (!(eps <= 0x1p-8f)) {
+        float F[NS][NS];
+        const bool ok = block_inverse_plus<TRANSPOSE>(J, dt, F);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int p = 0; p < NS; ++p) Fo[i][p] = up ? F[i ^ 4][p ^ 4] : F[i][p];
+        return ok;
+    }
+    // E (or E^T) = dt J in the lane's order: entry (a, b) is natural (a ^ m, b ^ m)
+    float E[NS][NS];
+#pragma unroll
+    for (int a = 0; a < NS; ++a)
+#pragma unroll
+        for (int b = 0; b < NS; ++b)
+            E[a][b] = dt * (TRANSPOSE ? J[(b ^ m) * NS + (a ^ m)] : J[(a ^ m) * NS + (b ^ m)]);
+    // Q = this half's rows of E E; F = E + Q (two terms) or E + Q + Q E (three)
+    float Q[4][NS];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int p = 0; p < NS; ++p) {
+            float t = 0.f;
+#pragma unroll
+            for (int k = 0; k < NS; ++k) t = fmaf(E[i][k], E[k][p], t);
+            Q[i][p] = t;
+        }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int p = 0; p < NS; ++p) {
+            float t = E[i][p] + Q[i][p];
             if (eps > 0x1p-12f) {
 #pragma unroll
-                for (int k = 0; k < NS; ++k) acc = fmaf(E[r][k], E[k][c], acc);
+                for (int k = 0; k < NS; ++k) t = fmaf(Q[i][k], E[k][p], t);
             }
-            G[r][c] = acc;
+            Fo[i][p] = t;
         }
+    return true;
+}
+
+// y = (I + F) x + c for this half's rows (x in the lane's order, c own rows).
+__device__ __forceinline__ void half_apply(const float (&Fo)[4][NS], const float (&xl)[NS], const float (&c)[4],
+                                           float (&y)[4])
+{
 #pragma unroll
-    for (int r = 0; r < NS; ++r)
+    for (int i = 0; i < 4; ++i) {
+        float t = c[i] + xl[i];
 #pragma unroll
-        for (int c = 0; c < NS; ++c) {
-            float acc = E[r][c];
+        for (int p = 0; p < NS; ++p) t = fmaf(Fo[i][p], xl[p], t);
+        y[i] = t;
+    }
+}
+
+// Writes a half map's rows into a natural-order (F row-major, then z) buffer.
+__device__ __forceinline__ void half_store(const HalfMap &a, float *dst, bool up)
+{
+    const int m = up ? 4 : 0;
 #pragma unroll
-            for (int k = 0; k < NS; ++k) acc = fmaf(E[r][k], G[k][c], acc);
-            if (TRANSPOSE) F[c][r] = acc;
-            else F[r][c] = acc;
-        }
-    return true;  // eps < 1: I - E is invertible
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int p = 0; p < NS; ++p) dst[(i ^ m) * NS + (p ^ m)] = a.F[i][p];
+        dst[NS * NS + (i ^ m)] = a.z[i];
+    }
 }
 
 // Backward Euler from step s0 (state ys) to s_end in attempts that never cross
@@ -402,37 +586,37 @@ __device__ int mlp_solve(MlpShared &S, const SolveArgs<IO> &a, const IO *t, doub
         mlp_jacobians(S, A, false);
         __syncthreads();
         const float eps = FE ? 0.f : wave_block_norm(S.u.J[j], hj, v);
-        AffineI<NS, float> map;
-        affine_identity(map);
+        const bool up = upper_half();
+        HalfMap map;
+        half_identity(map);
         int ok = 1;
+        float negR[NS];
+        {
+            float Rl[NS];
+            lane_order(R, Rl, up);
+#pragma unroll
+            for (int k = 0; k < NS; ++k) negR[k] = -Rl[k];
+        }
         if (v) {
             if constexpr (FE) {
                 // the correction map x -> (I + dt J(y_{j-1})) x - R
+                const int m = up ? 4 : 0;
 #pragma unroll
-                for (int rr = 0; rr < NS; ++rr) {
+                for (int i = 0; i < 4; ++i) {
 #pragma unroll
-                    for (int cc = 0; cc < NS; ++cc) map.F[rr][cc] = hj * S.u.J[j][rr * NS + cc];
-                    map.z[rr] = -R[rr];
+                    for (int p = 0; p < NS; ++p) map.F[i][p] = hj * S.u.J[j][(i ^ m) * NS + (p ^ m)];
+                    map.z[i] = negR[i];
                 }
             } else {
                 // (I - dt J)^{-1} = I + F; the correction map x -> (I + F)(x - R)
-                ok = inverse_plus<false>(S.u.J[j], hj, eps, map.F) ? 1 : 0;
-                float negR[NS], zero[NS];
-#pragma unroll
-                for (int k = 0; k < NS; ++k) { negR[k] = -R[k]; zero[k] = 0.f; }
-                apply_ip(map.F, negR, zero, map.z);
+                ok = half_inverse_plus<false>(S.u.J[j], hj, eps, up, map.F) ? 1 : 0;
+                const float zero[4] = {0.f, 0.f, 0.f, 0.f};
+                half_apply(map.F, negR, zero, map.z);
             }
         }
-        seg_scan_up<NS, kSPW>(map);
+        half_scan_up(map);
         ok = seg_and<kWave>(ok);
-        if (l == kSPW - 1) {
-#pragma unroll
-            for (int r = 0; r < NS; ++r) {
-#pragma unroll
-                for (int c = 0; c < NS; ++c) S.wmap[w][r * NS + c] = map.F[r][c];
-                S.wmap[w][NS * NS + r] = map.z[r];
-            }
-        }
+        if ((l & (kSPW - 1)) == kSPW - 1) half_store(map, S.wmap[w], up);
         if (l == 0) S.flag[w] = ok;
         __syncthreads();
         // the correction entering this wave: the maps of the earlier waves applied to 0
@@ -451,11 +635,15 @@ __device__ int mlp_solve(MlpShared &S, const SolveArgs<IO> &a, const IO *t, doub
 #pragma unroll
             for (int k = 0; k < NS; ++k) vin[k] = tv[k];
         }
-        if (v) {
-            float d[NS];
-            apply_ip(map.F, vin, map.z, d);
+        {
+            float vl[NS], dh[4], d[NS];
+            lane_order(vin, vl, up);
+            half_apply(map.F, vl, map.z, dh);
+            join_halves(dh, d, up);
+            if (v) {
 #pragma unroll
-            for (int k = 0; k < NS; ++k) dy[k] += d[k];
+                for (int k = 0; k < NS; ++k) dy[k] += d[k];
+            }
         }
         const int all_ok = S.flag[0] & S.flag[1] & S.flag[2] & S.flag[3];
         ++it;
@@ -583,39 +771,36 @@ __global__ __launch_bounds__(kThreads) void mlp_adjoint_kernel(SolveArgs<IO> a, 
         const double t1 = ld(sv.t + (v ? c0 + j + 1 : c0)), t0 = ld(sv.t + (v ? c0 + j : c0));
         const float hj = (float)(t1 - t0);
         const float eps = FE ? 0.f : wave_block_norm(S.u.J[j], hj, v);
-        AffineI<NS, float> map;
-        affine_identity(map);
+        const bool up = upper_half();
+        HalfMap map;
+        half_identity(map);
         int ok = 1;
         if (v) {
+            const int mo = up ? 4 : 0;
             if constexpr (FE) {
                 // u_j = (I + dt_{c0+j+1} J(y_{c0+j}))^T u_{j+1} + g_{c0+j}: u_j = lam_{c0+j} for
                 // j >= 1; u_0 (no g: it belongs to the earlier chunk) is carried
 #pragma unroll
-                for (int rr = 0; rr < NS; ++rr) {
+                for (int i = 0; i < 4; ++i) {
 #pragma unroll
-                    for (int cc = 0; cc < NS; ++cc) map.F[rr][cc] = hj * S.u.J[j][cc * NS + rr];
-                    map.z[rr] = j == 0 ? 0.f : gsc * gat(c0 + j, rr);
+                    for (int p = 0; p < NS; ++p) map.F[i][p] = hj * S.u.J[j][(p ^ mo) * NS + (i ^ mo)];
+                    map.z[i] = j == 0 ? 0.f : gsc * gat(c0 + j, i ^ mo);
                 }
             } else {
                 // (I - dt J)^{-T} = I + F^T
-                float gk[NS], zero[NS];
-                ok = inverse_plus<true>(S.u.J[j], hj, eps, map.F) ? 1 : 0;
+                float gk[NS], gl[NS];
+                ok = half_inverse_plus<true>(S.u.J[j], hj, eps, up, map.F) ? 1 : 0;
 #pragma unroll
-                for (int k = 0; k < NS; ++k) { gk[k] = gsc * gat(c0 + j + 1, k); zero[k] = 0.f; }
-                apply_ip(map.F, gk, zero, map.z);
+                for (int k = 0; k < NS; ++k) gk[k] = gsc * gat(c0 + j + 1, k);
+                lane_order(gk, gl, up);
+                const float zero[4] = {0.f, 0.f, 0.f, 0.f};
+                half_apply(map.F, gl, zero, map.z);
             }
         }
-        seg_scan_down<NS, kSPW>(map);
+        half_scan_down(map);
         ok = seg_and<kWave>(ok);
-        if (l == 0) {
-#pragma unroll
-            for (int rr = 0; rr < NS; ++rr) {
-#pragma unroll
-                for (int cc = 0; cc < NS; ++cc) S.wmap[w][rr * NS + cc] = map.F[rr][cc];
-                S.wmap[w][NS * NS + rr] = map.z[rr];
-            }
-            S.flag[w] = ok;
-        }
+        if ((l & (kSPW - 1)) == 0) half_store(map, S.wmap[w], up);
+        if (l == 0) S.flag[w] = ok;
         __syncthreads();
         float lin[NS];
 #pragma unroll
@@ -637,7 +822,12 @@ __global__ __launch_bounds__(kThreads) void mlp_adjoint_kernel(SolveArgs<IO> a, 
             for (int k = 0; k < NS; ++k) lin[k] = tv[k];
         }
         float lam_j[NS];
-        apply_ip(map.F, lin, map.z, lam_j);
+        {
+            float ll[NS], lh[4];
+            lane_order(lin, ll, up);
+            half_apply(map.F, ll, map.z, lh);
+            join_halves(lh, lam_j, up);
+        }
         // FE: the parameter term of step c0+j+1 takes lam_{c0+j+1}, the next position's value
         float lam_w[NS];
         if constexpr (FE) {
