@@ -68,12 +68,20 @@ def vdp_flops_per_step_iter(chunk):
 ROB_LEVEL, ROB_FACT, ROB_RES, ROB_JAC, ROB_REPLAY, ROB_VJP = 72, 72, 26, 24, 24, 12
 
 
+def _lane_levels(S):
+    """Map compositions per lane of the reduction across S lanes: log2(S) within a
+    wave; across waves (S > 64) the value entering a wave is applied to each
+    lane's composed map instead (ROB_REPLAY flops, no composition)."""
+    return levels(min(S, 64)), (ROB_REPLAY if S > 64 else 0)
+
+
 def rob_forward_flops_per_step(S, T):
     """Algorithmic flops per series-step of one Newton correction of the hybrid
     PCR/Thomas solve (Section 3.3): residual, Jacobian, factorization, the
     lane's serial compositions (T - 1 per T steps) and log2(S) reduction levels
     per lane (shared by its T steps), and the replay when T > 1."""
-    return (ROB_RES + ROB_JAC + ROB_FACT + ROB_LEVEL * ((T - 1) + levels(S)) / T
+    lv, cross = _lane_levels(S)
+    return (ROB_RES + ROB_JAC + ROB_FACT + (ROB_LEVEL * ((T - 1) + lv) + cross) / T
             + (ROB_REPLAY if T > 1 else 0))
 
 
@@ -81,7 +89,8 @@ def rob_adjoint_flops_per_step(S, T):
     """Per series-step of the adjoint (one transposed solve, no Newton loop):
     Jacobian, factorization, compositions and levels as above, the replay and
     the parameter product."""
-    return ROB_JAC + ROB_FACT + ROB_LEVEL * ((T - 1) + levels(S)) / T + ROB_REPLAY + ROB_VJP
+    lv, cross = _lane_levels(S)
+    return ROB_JAC + ROB_FACT + (ROB_LEVEL * ((T - 1) + lv) + cross) / T + ROB_REPLAY + ROB_VJP
 
 
 def csrc_hash(files=None):
@@ -226,6 +235,10 @@ def rob_inputs(dev):
 
 def kernel_names(S, T, init, recompute):
     """Demangled names of the solver kernels a Robertson step launches."""
+    if S > 64:  # chunks over S / 64 waves (wide.hpp)
+        W = S // 64
+        return ("tvi::wide::forward_kernel<tvi::Robertson, double, %d, %d>(tvi::SolveArgs<double>)" % (W, T),
+                "tvi::wide::adjoint_kernel<tvi::Robertson, double, %d, %d>(tvi::SolveArgs<double>)" % (W, T))
     pred = "true" if init == "predictor" else "false"
     fwd = "tvi::forward_kernel<tvi::Robertson, double, %d, %d, %s, false, false>(tvi::SolveArgs<double>)" % (
         S, T, pred)
@@ -275,7 +288,8 @@ def run_headline(args, dev, stream):
         cands = []
         for mode in ("stored", "recompute"):
             r = autotune.tune_forward("robertson", y0, times, sp, offsets=off, tol=TIMING_TOL, y_out=y_out,
-                                      use_cache=False, chunks=(32, 64, 128, 256, 512), inits=("zero", "extrap"),
+                                      use_cache=False, chunks=(32, 64, 128, 256, 512, 1024, 2048),
+                                      inits=("zero", "extrap"),
                                       adjoint=mode, order=order, n_max=nmax)
             for row in r["table"]:
                 cands.append(dict(row, adjoint=mode))
@@ -352,14 +366,26 @@ def run_headline(args, dev, stream):
         "newton_corrections": int(it.sum())}, "roofline": roofline, "peak_device_memory_bytes": peak_mem}
     del cs
 
-    # ---- the other adjoint state source at the same settings, and the chunk = 1 baseline
-    alt = capture(C, S, T, init, mode != "recompute")
+    # ---- the other adjoint state source (at the same settings where they hold it: the
+    # recomputing adjoint runs in one wave, so for chunks over several waves the best
+    # one-wave tiling the autotuner found for it), and the chunk = 1 baseline
+    other_mode = "recompute" if mode != "recompute" else "stored"
+    aC, aS, aT, ainit = C, S, T, init
+    if other_mode == "recompute" and S > 64:
+        rc = [r for r in (table or []) if r["adjoint"] == "recompute"]
+        if rc:
+            rb = min(rc, key=lambda r: (r["failed"], r["ms"]))
+            aC, aS, aT, ainit = rb["chunk"], rb["lanes"], rb["steps_per_lane"], rb["init"]
+        else:
+            aC, aS, aT = 512, 64, 8
+    alt = capture(aC, aS, aT, ainit, other_mode == "recompute")
     alt.replay()
     a_st = stats(time_launches(alt.replay, max(3, args.steps // 2), stream))
     a_ok = ((alt.status_fwd == 0) & (alt.status_adj == 0)).cpu().numpy()
-    head["other_adjoint_states"] = {"adjoint_states": "recompute" if mode != "recompute" else "stored",
+    head["other_adjoint_states"] = {"adjoint_states": other_mode,
                                     "value": int(lens[a_ok].sum()) / (a_st["mean_ms"] * 1e-3),
-                                    "ms_per_step": a_st["mean_ms"]}
+                                    "ms_per_step": a_st["mean_ms"], "chunk": aC, "lanes": aS, "steps_per_lane": aT,
+                                    "init": ainit}
     del alt
     log("chunk = 1 baseline")
     seq = capture(1, 1, 1, "zero", False)
@@ -1050,6 +1076,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--extras", default="", help="also run the side measurements and write them to this JSON file")
     ap.add_argument("--only", default="", help="comma-separated side measurements to run (with --extras)")
+    ap.add_argument("--extras-only", action="store_true",
+                    help="with --extras: run only the side measurements (no headline; for profiling them)")
     ap.add_argument("--probe-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH", "WRITE"),
@@ -1075,12 +1103,18 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
 
-    head, w = run_headline(args, dev, stream)
-    table = head.pop("_table")
-    out = compose_line(args, head)
+    if args.extras_only:
+        if not args.extras:
+            print("--extras-only needs --extras FILE", file=sys.stderr)
+            sys.exit(2)
+        head, w, table, out = None, None, None, {"extras": args.extras}
+    else:
+        head, w = run_headline(args, dev, stream)
+        table = head.pop("_table")
+        out = compose_line(args, head)
 
     if args.extras:
-        ext = {"headline_autotune_table": table}
+        ext = {"headline_autotune_table": table} if table is not None else {}
         only = set(filter(None, args.only.split(",")))
         want = lambda name: not only or name in only
         ctx = {"dev": dev, "stream": stream}
@@ -1088,8 +1122,9 @@ def main():
         if any(want(n) for n in [r[0] for r in vdp_runs] + ["forward_ad"]):
             log("Van der Pol context (autotune)")
             ctx = vdp_context(dev, stream, args.steps)
-        c = head["config"]
-        ctx["rob_tuned"] = {"chunk": c["chunk"], "lanes": c["lanes"], "steps_per_lane": c["steps_per_lane"]}
+        if head is not None:
+            c = head["config"]
+            ctx["rob_tuned"] = {"chunk": c["chunk"], "lanes": c["lanes"], "steps_per_lane": c["steps_per_lane"]}
         runs = vdp_runs + [("linear", run_linear), ("tiling_study", run_tiling_study),
                            ("saturated", run_saturated), ("pcr_roofline", run_pcr), ("mlp", run_mlp),
                            ("predictor", run_predictor), ("forward_euler", run_forward_euler),
@@ -1110,7 +1145,7 @@ def main():
         out["copy_probe_bytes"] = {"read": src.numel() * 8, "write": dst.numel() * 8}
         del src, dst
 
-    if not args.no_cpu:
+    if not args.no_cpu and w is not None:
         log("CPU oracle on the host cores")
         out["cpu_baseline"] = run_cpu_baseline(w)
 

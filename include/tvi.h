@@ -176,8 +176,16 @@ typedef struct {
 
 typedef struct {
     int32_t chunk;          /* steps solved together, >= 1 (Section 2.3)           */
-    int32_t lanes;          /* lanes of a wavefront per series S: 1,4,8,16,32,64;
-                               0 = choose from chunk                                 */
+    int32_t lanes;          /* lanes per series S: 1,4,8,16,32,64 (one wavefront;
+                               chunk <= 512), or 128, 256 (2 or 4 wavefronts, one
+                               workgroup per series, steps_per_lane 4 or 8, chunk
+                               <= 2048; TVI_VANDERPOL and TVI_ROBERTSON with
+                               TVI_F64 storage, backward Euler, analytic Jacobian,
+                               zero or extrapolated start, the forward pass and
+                               the adjoint from the stored trajectory;
+                               TVI_EUNSUPPORTED otherwise); 0 = choose from chunk
+                               (above 512 steps: 8 steps per lane over 2 or 4
+                               wavefronts)                                           */
     int32_t steps_per_lane; /* steps a lane composes serially T: 1,2,4,8; 0 = choose;
                                chunk <= lanes * steps_per_lane                       */
     int32_t max_newton;     /* Newton corrections per attempt, >= 1                   */

@@ -21,18 +21,23 @@ _CACHE_PATH = os.environ.get("TVI_CACHE", os.path.join(os.path.expanduser("~"), 
 _lock = threading.Lock()
 
 
-def tilings(chunk):
-    """(S, T) candidates with S * T >= chunk and less than half of the lanes idle."""
+# models with chunks over 2 or 4 waves (128 or 256 lanes, 4 or 8 steps per lane; double storage)
+WIDE_KINDS = ("robertson", "vanderpol")
+
+
+def tilings(chunk, wide=False):
+    """(S, T) candidates with S * T >= chunk and less than half of the lanes
+    idle; with ``wide`` also 128 and 256 lanes (chunks up to 2048)."""
     if chunk <= 1:
         return [(1, 1)]
     out = []
     for T in (1, 2, 4, 8):
-        for S in (4, 8, 16, 32, 64):
+        for S in (4, 8, 16, 32, 64) + ((128, 256) if wide and T >= 4 else ()):
             if S * T >= chunk and S * T < 2 * max(chunk, 4):
                 out.append((S, T))
-    if not out:
+    if not out and chunk <= 8 * 64:
         out = [(64, 8)]
-    return out
+    return out  # empty: no tiling holds the chunk (over 512 steps without the wide kernels)
 
 
 def source_hash():
@@ -120,8 +125,9 @@ def tune_forward(kind, y0, times, params, offsets=None, tol=(1e-8, 1e-6), chunks
         if hit:
             return hit
     table = []
+    wide = kind in WIDE_KINDS and y0.dtype == torch.float64 and not adjoint == "recompute"
     for C in chunks:
-        for S, T in tilings(C):
+        for S, T in tilings(C, wide):
             for init in inits:
                 res = {}
 

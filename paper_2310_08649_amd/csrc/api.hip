@@ -314,9 +314,10 @@ tvi_status tvi_solve_forward(const tvi_model *model, const tvi_options *opt, int
 
 size_t tvi_forward_workspace_bytes(const tvi_model *model, const tvi_options *opt, int64_t B)
 {
-    if (!model || !opt || B < 0 || opt->chunk < 1 || opt->chunk > blk::kMaxChunk || check_model(model) != TVI_OK)
+    if (!model || !opt || B < 0 || opt->chunk < 1 || opt->chunk > kMaxRegisterChunk || check_model(model) != TVI_OK)
         return 0;
-    return is_block(model) ? block_ws_bytes(model, opt, B, false) : 0;
+    if (!is_block(model) || opt->chunk > blk::kMaxChunk) return 0;
+    return block_ws_bytes(model, opt, B, false);
 }
 
 size_t tvi_adjoint_workspace_bytes(const tvi_model *model, const tvi_options *opt, int64_t B)

@@ -21,8 +21,14 @@ inline int next_pow2(int v)
     return p;
 }
 
+// Longest chunk of the register solver: one wave of 64 lanes x 8 steps, or a
+// workgroup of up to 4 such waves (wide.hpp: some models, backward Euler).
+constexpr int kMaxWaves = 4;
+constexpr int kMaxRegisterChunk = kMaxWaves * kWave * 8;  // 2048
+
 // Lanes per series S and steps per lane T for a chunk of C steps: the fewest
-// steps per lane that fit the chunk in one wavefront, then the fewest lanes.
+// steps per lane that fit the chunk in one wavefront, then the fewest lanes;
+// beyond 512 steps, 8 steps per lane over 2 or 4 waves.
 inline void choose_tiling(int C, int &S, int &T)
 {
     if (C <= 1) { S = 1; T = 1; return; }
@@ -30,7 +36,7 @@ inline void choose_tiling(int C, int &S, int &T)
     while (T < 8 && T * kWave < C) T <<= 1;
     S = next_pow2((C + T - 1) / T);
     if (S < 4) S = 4;
-    if (S > kWave) S = kWave;
+    if (S > kMaxWaves * kWave) S = kMaxWaves * kWave;
 }
 
 inline tvi_status resolve_tiling(const tvi_options *o, int &S, int &T)
@@ -40,9 +46,11 @@ inline tvi_status resolve_tiling(const tvi_options *o, int &S, int &T)
     } else {
         S = o->lanes;
         T = o->steps_per_lane;
-        if (!(S == 1 || pow2_in(S, 4, kWave)) || !pow2_in(T, 1, 8)) return TVI_EINVAL;
+        const bool one_wave = (S == 1 || pow2_in(S, 4, kWave)) && pow2_in(T, 1, 8);
+        const bool waves = pow2_in(S, 2 * kWave, kMaxWaves * kWave) && pow2_in(T, 4, 8);
+        if (!one_wave && !waves) return TVI_EINVAL;
     }
-    if (o->chunk > 8 * kWave || (int64_t)S * T < o->chunk) return TVI_EINVAL;
+    if (o->chunk > kMaxRegisterChunk || (int64_t)S * T < o->chunk) return TVI_EINVAL;
     return TVI_OK;
 }
 
@@ -50,7 +58,7 @@ inline tvi_status check_options(const tvi_options *o)
 {
     if (!o) return TVI_EINVAL;
     if (o->obs_idx && o->n_obs < 1) return TVI_EINVAL;
-    if (o->chunk < 1 || o->chunk > blk::kMaxChunk) return TVI_EINVAL;
+    if (o->chunk < 1 || o->chunk > kMaxRegisterChunk) return TVI_EINVAL;
     if (o->max_newton < 1) return TVI_EINVAL;
     if (!(o->tol_a >= 0.0) || !(o->tol_r >= 0.0)) return TVI_EINVAL;
     if (o->init != TVI_INIT_ZERO && o->init != TVI_INIT_EXTRAP && o->init != TVI_INIT_PREDICTOR) return TVI_EINVAL;

@@ -1,0 +1,13 @@
+// Kernel instances of the Robertson kinetics model for chunks over 2 or 4 waves (double storage).
+#include "dispatch.hpp"
+#include "wide.hpp"
+
+namespace tvi {
+
+tvi_status launch_robertson_wide(int pass, int dtype, const void *args, int S, int T, hipStream_t stream)
+{
+    if (dtype != TVI_F64) return TVI_EUNSUPPORTED;
+    return wide::launch<Robertson, double>(pass, *static_cast<const SolveArgs<double> *>(args), S, T, stream);
+}
+
+} // namespace tvi

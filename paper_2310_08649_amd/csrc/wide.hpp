@@ -1,0 +1,575 @@
+// Chunks longer than one wavefront can hold: W = 2 or 4 waves of 64 lanes per
+// series (one workgroup per series), T steps per lane, chunks up to 64 W T
+// steps.  The method is the register solver's (Algorithm 1 on the chunk's
+// block-bidiagonal system, Section 3.3's hybrid: T steps per lane by Thomas's
+// recurrence, PCR across the lanes); what changes is where the lanes of one
+// series live.  Each wave reduces its 64 lanes as before (DPP levels), and
+// one more level joins the waves through LDS:
+//   * sums (the residual norm, dL/dp): wave sums, then the W partial sums in a
+//     fixed order (every wave adds the same values in the same order, so all
+//     lanes hold the bitwise-same total);
+//   * the chunk recurrence: every wave publishes its composed map (its lanes'
+//     total); wave w applies the totals of waves 0..w-1 to the chunk's start
+//     value in order, which gives the value entering wave w, and its lanes'
+//     own prefix maps take it from there (the adjoint runs the same from the
+//     last wave down);
+//   * neighbour values across a wave edge (the previous step's increment, the
+//     next step's lam) and one lane's vector read by all: through LDS.
+// Every decision of the solve (convergence, halving, failure) depends only on
+// these workgroup-wide values, so all waves of a workgroup take the same
+// branches, and the barriers inside the exchanges are reached by all of them.
+// Longer chunks shorten the dependent chain of the longest series, which sets
+// the launch time of a ragged batch: fewer chunks, each a few Newton
+// corrections of the same per-lane depth plus one cross-wave level.
+//
+// Scope: backward Euler, hand-written Jacobians, the zero or extrapolated
+// start, the forward pass and the adjoint from the stored trajectory.
+#pragma once
+
+#include "solver.hpp"
+
+namespace tvi {
+namespace wide {
+
+// LDS of one workgroup: wave totals, boundary vectors, partial sums, flags.
+template <int W, int N>
+struct Xchg {
+    double tot[W][N * N + N];
+    double vec[W][N];
+    double red[W];
+    int flag[W];
+};
+
+__device__ __forceinline__ int wave_of() { return threadIdx.x / kWave; }
+
+// Sum over the workgroup's lanes (bitwise-same result in every lane).
+template <int W, int N>
+__device__ __forceinline__ double block_sum(Xchg<W, N> &X, double x)
+{
+    x = seg_sum<kWave>(x);
+    if (lane_id() == 0) X.red[wave_of()] = x;
+    __syncthreads();
+    double s = X.red[0];
+#pragma unroll
+    for (int w = 1; w < W; ++w) s += X.red[w];
+    __syncthreads();
+    return s;
+}
+
+// Logical and of x != 0 over the workgroup.
+template <int W, int N>
+__device__ __forceinline__ int block_and(Xchg<W, N> &X, int x)
+{
+    x = seg_and<kWave>(x);
+    if (lane_id() == 0) X.flag[wave_of()] = x;
+    __syncthreads();
+    int a = 1;
+#pragma unroll
+    for (int w = 0; w < W; ++w) a &= X.flag[w];
+    __syncthreads();
+    return a;
+}
+
+// The vector of thread q - 1 (0 for thread 0).
+template <int W, int N>
+__device__ __forceinline__ void vec_prev_w(Xchg<W, N> &X, const double (&v)[N], double (&out)[N])
+{
+    vec_prev(v, out);
+    const int w = wave_of(), l = lane_id();
+    if (l == kWave - 1) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) X.vec[w][i] = v[i];
+    }
+    __syncthreads();
+    if (l == 0 && w > 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) out[i] = X.vec[w - 1][i];
+    }
+    __syncthreads();
+}
+
+// The vector of thread q + 1 (0 for the last thread).
+template <int W, int N>
+__device__ __forceinline__ void vec_next_w(Xchg<W, N> &X, const double (&v)[N], double (&out)[N])
+{
+    vec_next(v, out);
+    const int w = wave_of(), l = lane_id();
+    if (l == 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) X.vec[w][i] = v[i];
+    }
+    __syncthreads();
+    if (l == kWave - 1 && w < W - 1) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) out[i] = X.vec[w + 1][i];
+    }
+    __syncthreads();
+}
+
+// The vector of thread src (workgroup-uniform), in every thread.
+template <int W, int N>
+__device__ __forceinline__ void vec_read_w(Xchg<W, N> &X, const double (&v)[N], int src, double (&out)[N])
+{
+    if ((int)threadIdx.x == src) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) X.vec[0][i] = v[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < N; ++i) out[i] = X.vec[0][i];
+    __syncthreads();
+}
+
+// Publishes the map of one lane per wave (its wave's total): lane `src` of
+// every wave writes.
+template <int W, int N>
+__device__ __forceinline__ void publish_total(Xchg<W, N> &X, const AffineI<N, double> &a, int src)
+{
+    if (lane_id() == src) {
+        double *d = X.tot[wave_of()];
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+#pragma unroll
+            for (int c = 0; c < N; ++c) d[r * N + c] = a.F[r][c];
+            d[N * N + r] = a.z[r];
+        }
+    }
+}
+
+// x <- (I + F_w) x + z_w for the published total of wave w.
+template <int W, int N>
+__device__ __forceinline__ void apply_total(const Xchg<W, N> &X, int w, double (&x)[N])
+{
+    const double *d = X.tot[w];
+    double t[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        double s = d[N * N + r];
+#pragma unroll
+        for (int c = 0; c < N; ++c) s = fma(d[r * N + c], x[c], s);
+        t[r] = s + x[r];
+    }
+#pragma unroll
+    for (int r = 0; r < N; ++r) x[r] = t[r];
+}
+
+// Forward chunk recurrence over the workgroup: after the in-wave prefix scan
+// (lane q holds A_q o ... o A_0 of its wave), z becomes the solution at the
+// lane's last owned step for the chunk started at 0.
+template <int W, int N>
+__device__ __forceinline__ void scan_up_w(Xchg<W, N> &X, AffineI<N, double> &a)
+{
+    seg_scan_up<N, kWave>(a);
+    publish_total(X, a, kWave - 1);
+    __syncthreads();
+    const int w = wave_of();
+    double x[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = 0.0;
+    for (int v = 0; v < w; ++v) apply_total(X, v, x);  // the value entering wave w
+    __syncthreads();
+    apply_ip(a.F, x, a.z, a.z);
+}
+
+// Adjoint: after the in-wave suffix scan, x_in is the value entering the
+// wave from above: the totals of waves W-1 .. w+1 applied to lam in turn.
+template <int W, int N>
+__device__ __forceinline__ void scan_down_w(Xchg<W, N> &X, AffineI<N, double> &a, const double (&lam)[N],
+                                            double (&x)[N])
+{
+    seg_scan_down<N, kWave>(a);
+    publish_total(X, a, 0);
+    __syncthreads();
+    const int w = wave_of();
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = lam[i];
+    for (int v = W - 1; v > w; --v) apply_total(X, v, x);
+    __syncthreads();
+}
+
+// Per-series state of the chunked Newton solve, W waves x 64 lanes x T steps.
+template <class Model, int W, int T>
+struct WideNewton {
+    static constexpr int n = Model::N;
+    static constexpr int S = W * kWave;
+
+    double ys[n];      // state at the chunk start
+    int64_t s, s_end;  // chunk start step; the solve ends at s_end
+    int64_t ck_next, ck_at;
+    int m, mcur, it, total;
+    double nrm0;
+    bool active, start, sing;
+    int status;
+    double dy[T][n];
+    double tt[T], hh[T];
+    double t_s;
+
+    __device__ __forceinline__ bool owned(int q, int i) const { return active && (q * T + i + 1 <= m); }
+
+    // Backward-Euler residual of the owned steps (R if KEEP) and the squared
+    // norm over the chunk.  Every thread calls it.
+    template <bool KEEP>
+    __device__ __forceinline__ double residual(Xchg<W, n> &X, const Model &model, int q, double (&R)[T][n]) const
+    {
+        double prev[n];
+        vec_prev_w(X, dy[T - 1], prev);
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < T; ++i) {
+            double yv[n], f[n];
+#pragma unroll
+            for (int k = 0; k < n; ++k) yv[k] = ys[k] + dy[i][k];
+            model.rhs(yv, tt[i], f);
+            const bool v = owned(q, i);
+#pragma unroll
+            for (int k = 0; k < n; ++k) {
+                const double dprev = (i == 0) ? (q > 0 ? prev[k] : 0.0) : dy[i - 1][k];
+                const double r = v ? (dy[i][k] - dprev) - hh[i] * f[k] : 0.0;
+                if (KEEP) R[i][k] = r;
+                acc = fma(r, r, acc);
+            }
+        }
+        return block_sum(X, acc);
+    }
+
+    __device__ __forceinline__ void extrapolate(const Model &model, int q, bool zero)
+    {
+        double slope[n];
+        if (zero) {
+#pragma unroll
+            for (int k = 0; k < n; ++k) slope[k] = 0.0;
+        } else {
+            model.rhs(ys, t_s, slope);
+        }
+#pragma unroll
+        for (int i = 0; i < T; ++i) {
+            const bool v = q * T + i + 1 <= m;
+#pragma unroll
+            for (int k = 0; k < n; ++k) dy[i][k] = v ? (tt[i] - t_s) * slope[k] : 0.0;
+        }
+    }
+
+    // Solve steps s..s_end from ys; attempts never cross a multiple of C (the
+    // checkpoints restart the same sequence).  Every thread calls it.
+    template <class IO, class Sink>
+    __device__ void run(Xchg<W, n> &X, const Model &model, const IO *t, int C, int max_newton, double tol_a,
+                        double tol_r, int init, bool halving, const Sink &sink)
+    {
+        const int q = threadIdx.x;
+        start = true;
+        sing = false;
+        it = 0;
+        nrm0 = 0.0;
+        m = 0;
+        mcur = C;
+        ck_next = s / C + 1;
+        ck_at = ck_next * C;
+        const double tol_a2 = tol_a * tol_a, tol_r2 = tol_r * tol_r;
+
+        while (active) {  // workgroup-uniform
+            if (start) {
+                const int64_t nom_end = min(ck_at, s_end);
+                m = (int)min((int64_t)mcur, nom_end - s);
+                t_s = ld(t + s);
+#pragma unroll
+                for (int i = 0; i < T; ++i) {
+                    const int j = q * T + i + 1;
+                    const bool v = j <= m;
+                    const int64_t kk = v ? s + j : s;
+                    tt[i] = ld(t + kk);
+                    const double tp = (i == 0) ? ld(t + (v ? kk - 1 : s)) : tt[i - 1];
+                    hh[i] = v ? tt[i] - tp : 0.0;
+                }
+                extrapolate(model, q, init == INIT_ZERO);
+                it = 0;
+                sing = false;
+                start = false;
+            }
+
+            double R[T][n];
+            const double nrm2 = residual<true>(X, model, q, R);
+
+            int act, code = ST_OK;  // 1 converged, 2 failed, 3 correct (workgroup-uniform)
+            if (it == 0) nrm0 = nrm2;
+            if (sing) { act = 2; code = ST_SINGULAR; }
+            else if (!finite(nrm2)) { act = 2; code = ST_NONFINITE; }
+            else if (nrm2 <= tol_a2 || nrm2 <= tol_r2 * nrm0) act = 1;
+            else if (it >= max_newton) { act = 2; code = ST_NOT_CONVERGED; }
+            else act = 3;
+
+            if (act == 1) {
+                // the state at the attempt's last step: the owner of step m publishes its increment
+                const int im = (m - 1) % T, qm = (m - 1) / T;
+                double cand[n];
+#pragma unroll
+                for (int k = 0; k < n; ++k) cand[k] = dy[0][k];
+#pragma unroll
+                for (int i = 1; i < T; ++i)
+#pragma unroll
+                    for (int k = 0; k < n; ++k) cand[k] = (i == im) ? dy[i][k] : cand[k];
+                double last[n];
+                vec_read_w(X, cand, qm, last);
+#pragma unroll
+                for (int i = 0; i < T; ++i) {
+                    if (owned(q, i)) {
+                        double v[n];
+#pragma unroll
+                        for (int k = 0; k < n; ++k) v[k] = ys[k] + dy[i][k];
+                        sink.put(s + q * T + i + 1, v);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < n; ++k) ys[k] += last[k];
+                s += m;
+                const bool at_ck = s == ck_at;
+                if (at_ck || s >= s_end) sink.boundary(ck_next, ys, q);
+                if (at_ck) {
+                    mcur = C;
+                    ++ck_next;
+                    ck_at += C;
+                }
+                if (s >= s_end) active = false;
+                start = true;
+                continue;
+            }
+            if (act == 2) {
+                if (halving && m > 1) {
+                    mcur = (m + 1) / 2;
+                    start = true;
+                } else {
+                    status = code;
+                    active = false;
+                    sink.template fail<S>(s, q);
+                }
+                continue;
+            }
+
+            // ---- Newton correction: blocks, in-lane composition, the scans, replay
+            double Fi[T][n][n], zi[T][n];
+            AffineI<n, double> map;
+            affine_identity(map);
+            int ok = 1;
+#pragma unroll
+            for (int i = 0; i < T; ++i) {
+                if (owned(q, i)) {
+                    double yv[n], J[n][n], D[n][n];
+#pragma unroll
+                    for (int k = 0; k < n; ++k) yv[k] = ys[k] + dy[i][k];
+                    model.jac(yv, tt[i], J);
+#pragma unroll
+                    for (int r = 0; r < n; ++r)
+#pragma unroll
+                        for (int c = 0; c < n; ++c) D[r][c] = ((r == c) ? 1.0 : 0.0) - hh[i] * J[r][c];
+                    ok &= invert_plus(D, Fi[i]) ? 1 : 0;
+                    const double zero[n] = {};
+                    double negR[n];
+#pragma unroll
+                    for (int k = 0; k < n; ++k) negR[k] = -R[i][k];
+                    apply_ip(Fi[i], negR, zero, zi[i]);
+                    AffineI<n, double> stp;
+#pragma unroll
+                    for (int r = 0; r < n; ++r) {
+#pragma unroll
+                        for (int c = 0; c < n; ++c) stp.F[r][c] = Fi[i][r][c];
+                        stp.z[r] = zi[i][r];
+                    }
+                    if (i > 0) affine_after(stp, map);
+                    map = stp;
+                }
+            }
+            scan_up_w(X, map);
+            if constexpr (T == 1) {
+                // the composed map's offset is the solution at the lane's step
+                if (owned(q, 0)) {
+#pragma unroll
+                    for (int k = 0; k < n; ++k) dy[0][k] += map.z[k];
+                }
+            } else {
+                double din[n];
+                vec_prev_w(X, map.z, din);
+                if (q == 0) {
+#pragma unroll
+                    for (int k = 0; k < n; ++k) din[k] = 0.0;
+                }
+#pragma unroll
+                for (int i = 0; i < T; ++i) {
+                    if (owned(q, i)) {
+                        apply_ip(Fi[i], din, zi[i], din);
+#pragma unroll
+                        for (int k = 0; k < n; ++k) dy[i][k] += din[k];
+                    }
+                }
+            }
+            ok = block_and(X, ok);
+            ++it;
+            ++total;
+            if (!ok) sing = true;
+        }
+    }
+};
+
+template <class Model, class IO, int W, int T>
+__global__ __launch_bounds__(W *kWave) void forward_kernel(SolveArgs<IO> a)
+{
+    constexpr int n = Model::N;
+    __shared__ Xchg<W, n> X;
+    const int q = threadIdx.x;
+    const SeriesView<IO> sv(a, blockIdx.x);
+    if (!sv.valid) return;  // the whole workgroup idles
+    Model model;
+    model.load(a.params + sv.b * Model::P);
+    WideNewton<Model, W, T> cn;
+#pragma unroll
+    for (int k = 0; k < n; ++k) cn.ys[k] = ld(a.y0 + sv.b * n + k);
+    TrajectorySink<IO, n> sink{a.y ? a.y + sv.p0 * n : nullptr, a.ckpt ? a.ckpt + sv.b * a.K * n : nullptr, sv.Nb,
+                               a.K, a.chunk};
+    if (q == 0) {
+        sink.put(0, cn.ys);
+        sink.boundary(0, cn.ys, 0);
+    }
+    cn.s = 0;
+    cn.s_end = sv.Nb;
+    cn.total = 0;
+    cn.status = ST_OK;
+    cn.active = sv.Nb > 0;
+    cn.run(X, model, sv.t, a.chunk, a.max_newton, a.tol_a, a.tol_r, a.init, a.halving != 0, sink);
+    if (q == 0) {
+        a.status[sv.b] = cn.status;
+        if (a.iters) a.iters[sv.b] = cn.total;
+    }
+}
+
+// Adjoint from the stored trajectory (Appendix A): nominal chunks in reverse,
+// the transposed recurrence lam_j = D_j^{-T} lam_{j+1} + D_j^{-T} g_j reduced
+// from the last step down, dL/dp = sum_j dt_j (dh/dp)^T lam_j.
+template <class Model, class IO, int W, int T>
+__global__ __launch_bounds__(W *kWave) void adjoint_kernel(SolveArgs<IO> a)
+{
+    constexpr int n = Model::N;
+    constexpr int P = Model::P;
+    __shared__ Xchg<W, n> X;
+    const int q = threadIdx.x;
+    const SeriesView<IO> sv(a, blockIdx.x);
+    if (!sv.valid) return;  // the whole workgroup idles
+    const int C = a.chunk;
+    Model model;
+    model.load(a.params + sv.b * P);
+
+    double lam[n], gp[P];
+#pragma unroll
+    for (int k = 0; k < n; ++k) lam[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < P; ++k) gp[k] = 0.0;
+    const IO *gb = a.g + sv.p0 * n;
+    const IO *yb = a.y + sv.p0 * n;
+    int status = ST_OK;
+
+    for (int64_t c = (sv.Nb + C - 1) / C - 1; c >= 0; --c) {  // workgroup-uniform
+        const int64_t s = c * C;
+        const int m = (int)min((int64_t)C, sv.Nb - s);
+        double Fi[T][n][n], wi[T][n], yl[T][n], hl[T], tl[T];  // I + Fi = D^{-1} (not transposed)
+        AffineI<n, double> map;
+        affine_identity(map);
+        int ok = 1;
+#pragma unroll
+        for (int i = T - 1; i >= 0; --i) {
+            const int j = q * T + i + 1;
+            const bool v = j <= m;
+            const int64_t k = s + (v ? j : 1);
+            double gk[n];
+#pragma unroll
+            for (int e = 0; e < n; ++e) {
+                yl[i][e] = v ? ld(yb + k * n + e) : 0.0;
+                gk[e] = v ? ld(gb + k * n + e) : 0.0;
+            }
+            tl[i] = v ? ld(sv.t + k) : 0.0;
+            hl[i] = v ? tl[i] - ld(sv.t + k - 1) : 0.0;
+            if (v) {
+                double J[n][n], D[n][n];
+                model.jac(yl[i], tl[i], J);
+#pragma unroll
+                for (int r = 0; r < n; ++r)
+#pragma unroll
+                    for (int cc = 0; cc < n; ++cc) D[r][cc] = ((r == cc) ? 1.0 : 0.0) - hl[i] * J[r][cc];
+                ok &= invert_plus(D, Fi[i]) ? 1 : 0;
+                const double zero[n] = {};
+                apply_ip_t(Fi[i], gk, zero, wi[i]);
+                AffineI<n, double> stp;
+#pragma unroll
+                for (int r = 0; r < n; ++r) {
+#pragma unroll
+                    for (int cc = 0; cc < n; ++cc) stp.F[r][cc] = Fi[i][cc][r];
+                    stp.z[r] = wi[i][r];
+                }
+                if (i < T - 1) affine_after(stp, map);
+                map = stp;
+            }
+        }
+        // lam at the first owned step of every lane, then the value entering from the right
+        double xin[n], vq[n], lin[n];
+        scan_down_w(X, map, lam, xin);
+        apply_ip(map.F, xin, map.z, vq);
+        vec_next_w(X, vq, lin);
+        if (q == W * kWave - 1) {
+#pragma unroll
+            for (int k = 0; k < n; ++k) lin[k] = lam[k];
+        }
+#pragma unroll
+        for (int i = T - 1; i >= 0; --i) {
+            const int j = q * T + i + 1;
+            if (j <= m) {
+                apply_ip_t(Fi[i], lin, wi[i], lin);
+                double w[n];
+#pragma unroll
+                for (int k = 0; k < n; ++k) w[k] = hl[i] * lin[k];
+                model.vjp_p(yl[i], tl[i], w, gp);
+            }
+        }
+        double first[n];
+        vec_read_w(X, vq, 0, first);
+        ok = block_and(X, ok);
+#pragma unroll
+        for (int k = 0; k < n; ++k) lam[k] = first[k];
+        if (!ok && status == ST_OK) status = ST_SINGULAR;
+    }
+
+    // dL/dy0 = g_0 + lam_1; dL/dp summed over the workgroup in a fixed order
+#pragma unroll
+    for (int k = 0; k < P; ++k) gp[k] = block_sum(X, gp[k]);
+    if (q == 0) {
+        const double nan = __builtin_nan("");
+#pragma unroll
+        for (int k = 0; k < n; ++k) st(a.dLdy0 + sv.b * n + k, status == ST_OK ? ld(gb + k) + lam[k] : nan);
+#pragma unroll
+        for (int k = 0; k < P; ++k) st(a.dLdp + sv.b * P + k, status == ST_OK ? gp[k] : nan);
+        a.status[sv.b] = status;
+    }
+}
+
+// Forward (pass 0) and stored-trajectory adjoint (pass 1) for S = 64 W lanes.
+template <class Model, class IO>
+tvi_status launch(int pass, const SolveArgs<IO> &a, int S, int T, hipStream_t stream)
+{
+    if (a.scheme != 0 || a.init == INIT_PREDICTOR || a.zero_ref != 0) return TVI_EUNSUPPORTED;
+    if (a.B > 0x7fffffffLL) return TVI_EINVAL;
+    const dim3 grid((unsigned)a.B);
+#define TVI_WIDE_CASE(WW, TT)                                                                                    \
+    if (S == (WW) * kWave && T == (TT)) {                                                                        \
+        if (pass == PASS_FORWARD)                                                                                \
+            hipLaunchKernelGGL((forward_kernel<Model, IO, WW, TT>), grid, dim3((WW) * kWave), 0, stream, a);     \
+        else if (pass == PASS_ADJOINT)                                                                           \
+            hipLaunchKernelGGL((adjoint_kernel<Model, IO, WW, TT>), grid, dim3((WW) * kWave), 0, stream, a);     \
+        else                                                                                                     \
+            return TVI_EUNSUPPORTED;                                                                             \
+        return hipGetLastError() == hipSuccess ? TVI_OK : TVI_EHIP;                                              \
+    }
+    TVI_WIDE_CASE(2, 4)
+    TVI_WIDE_CASE(2, 8)
+    TVI_WIDE_CASE(4, 4)
+    TVI_WIDE_CASE(4, 8)
+#undef TVI_WIDE_CASE
+    return TVI_EUNSUPPORTED;
+}
+
+} // namespace wide
+} // namespace tvi

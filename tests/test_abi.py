@@ -55,7 +55,7 @@ def _fake():
     return ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
 
 
-@pytest.mark.parametrize("field,value", [("chunk", 0), ("chunk", 513), ("max_newton", 0), ("tol_a", -1.0),
+@pytest.mark.parametrize("field,value", [("chunk", 0), ("chunk", 2049), ("max_newton", 0), ("tol_a", -1.0),
                                          ("init", 7), ("lanes", 3), ("steps_per_lane", 16)])
 def test_forward_rejects_bad_options(lib, field, value):
     from paper_2310_08649_amd import tvi
@@ -332,3 +332,30 @@ def test_register_solver_refuses_divided_or_observed_gradients(lib):
     o.n_obs = 3
     assert lib.tvi_solve_adjoint(ctypes.byref(m), ctypes.byref(o), 4, 10, None, f, f, f, None, f, f, f, f, None, 0,
                                  None) == -4
+
+
+def test_tilings_over_several_waves_are_checked(lib):
+    """128 or 256 lanes (2 or 4 waves) take 4 or 8 steps per lane and chunks up
+    to 2048; other combinations, and these tilings for models or options the
+    wide kernels do not cover, are refused on the host."""
+    from paper_2310_08649_amd import tvi
+    f = _fake()
+
+    def fwd(kind, n, **kw):
+        m = tvi.Model(tvi.KINDS[kind], n, tvi.F64, 0, 64)
+        o = tvi.make_options(**kw)
+        return lib.tvi_solve_forward(ctypes.byref(m), ctypes.byref(o), 4, 10, None, f, f, f, f, None, f, None, None)
+
+    for S, T, C in [(128, 2, 256), (512, 8, 2048), (256, 16, 2048), (96, 8, 512), (128, 8, 1025), (256, 8, 2049)]:
+        assert fwd("robertson", 3, chunk=C, lanes=S, steps_per_lane=T) == -1, (S, T, C)
+    # the register solver's other models stop at one wave
+    assert fwd("linear", 2, chunk=1024, lanes=128, steps_per_lane=8) == -4
+    assert fwd("chaboche", 3, chunk=1024, lanes=128, steps_per_lane=8) == -4
+    # options the wide kernels do not take
+    assert fwd("robertson", 3, chunk=1024, lanes=128, steps_per_lane=8, scheme="forward_euler") == -4
+    assert fwd("vanderpol", 2, chunk=2048, lanes=256, steps_per_lane=8, jacobian="forward_ad") == -4
+    assert fwd("robertson", 3, chunk=1024, lanes=128, steps_per_lane=8, init="extrap", reference="zero") == -4
+    m = tvi.Model(tvi.KINDS["robertson"], 3, tvi.F32, 0, 64)
+    o = tvi.make_options(chunk=1024, lanes=128, steps_per_lane=8)
+    assert lib.tvi_solve_forward(ctypes.byref(m), ctypes.byref(o), 4, 10, None, f, f, f, f, None, f, None,
+                                 None) == -4                         # double storage only

@@ -1,0 +1,162 @@
+"""Chunks over 2 or 4 waves per series (128 or 256 lanes, 4 or 8 steps per
+lane, chunks up to 2048) against the oracle: ragged Robertson and Van der Pol
+trajectories, the adjoint from the stored trajectory, edge cases (empty and
+one-step series, series shorter than a lane's share, halving), and the full
+ragged batch in the tilings the benchmark's autotuner may choose."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2310_08649_amd import workloads as W
+from tests.helpers import PARITY_TOL, series_rel_err
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+TILINGS = [(1024, 128, 8), (1024, 256, 4), (2048, 256, 8), (700, 128, 8), (512, 128, 4)]
+
+
+@pytest.fixture(scope="module")
+def tvi():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2310_08649_amd import tvi as t
+    t.load()
+    return t
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def _ragged_robertson():
+    """96 ragged series of 100-6000 steps plus an empty series, a one-step one
+    and one shorter than a lane's share of a chunk."""
+    w = W.robertson(B=96, n_range=(100, 6000), seed=140)
+    Nb = list(np.diff(w["offsets"]) - 1) + [0, 1, 5]
+    B = len(Nb)
+    off = np.zeros(B + 1, dtype=np.int64)
+    off[1:] = np.cumsum(np.array(Nb) + 1)
+    times = np.empty(int(off[-1]))
+    for b in range(B):
+        k = np.arange(Nb[b] + 1, dtype=np.float64)
+        times[off[b]:off[b + 1]] = 10.0 ** (-5.0 + 9.0 * k / max(Nb[b], 1))
+    y0 = np.tile([1.0, 0.0, 0.0], (B, 1))
+    params = np.concatenate([w["params"], np.array([[1.0, 1.0, 1.0], [0.7, 1.3, 2.0], [1.9, 0.6, 0.8]])])
+    return dict(y0=y0, times=times, params=params, offsets=off)
+
+
+@pytest.mark.parametrize("C,S,T", TILINGS)
+def test_wide_robertson_ragged_forward_and_adjoint(tvi, C, S, T):
+    w = _ragged_robertson()
+    off = w["offsets"]
+    yo, so, _ = oracle.forward("robertson", w["y0"], w["times"], w["params"], offsets=off, tol=PARITY_TOL)
+    assert (so == 0).all()
+    offd = dev(off, torch.int64)
+    kw = dict(offsets=offd, chunk=C, lanes=S, steps_per_lane=T, tol=PARITY_TOL, order=tvi.order_longest_first(offd))
+    print("robertson ragged B=%d chunk=%d lanes=%d steps_per_lane=%d" % (len(off) - 1, C, S, T), flush=True)
+    y, st, it, ck = tvi.solve_forward("robertson", dev(w["y0"]), dev(w["times"]), dev(w["params"]), checkpoints=True,
+                                      **kw)
+    yh, st = host(y), host(st)
+    assert (st == 0).all()
+    assert series_rel_err(yh, yo, off).max() <= 1e-10
+    assert np.abs(yh.sum(axis=1) - 1.0).max() <= 1e-12
+    # checkpoints: the state at every multiple of the chunk and at the end
+    ckh = host(ck)
+    for b in range(len(off) - 1):
+        Nb = off[b + 1] - off[b] - 1
+        for c in range(ckh.shape[1]):
+            k = min(c * C, Nb)
+            if c * C <= Nb or (c > 0 and (c - 1) * C < Nb):
+                assert np.array_equal(ckh[b, c], yh[off[b] + k]), (b, c)
+    g = yh / np.sqrt(np.sum(yh ** 2))
+    dp, dy0, sa = tvi.solve_adjoint("robertson", dev(w["times"]), dev(w["params"]), dev(g), y=y, **kw)
+    assert (host(sa) == 0).all()
+    op, oy0, _ = oracle.adjoint("robertson", yh, w["times"], w["params"], g, offsets=off)
+    for a, b in ((host(dp), op), (host(dy0), oy0)):
+        err = np.abs(a - b).max(axis=1) / np.maximum(np.abs(b).max(axis=1), 1e-300)
+        assert err.max() <= 1e-10, err.max()
+
+
+@pytest.mark.parametrize("C,S,T", [(1024, 128, 8), (2048, 256, 8), (1024, 256, 4)])
+def test_wide_vanderpol_forward_and_adjoint(tvi, C, S, T):
+    """Uniform grid, mu up to 30, series of 3000 steps: chunks with a ragged
+    tail, both starts."""
+    w = W.vanderpol(B=24, N=3000, mu_range=(1.0, 30.0), t_end=6.0)
+    yo, so, _ = oracle.forward("vanderpol", w["y0"], w["times"], w["params"], tol=PARITY_TOL)
+    assert (so == 0).all()
+    for init in ("zero", "extrap"):
+        kw = dict(chunk=C, lanes=S, steps_per_lane=T, tol=PARITY_TOL, init=init)
+        print("vanderpol 24 x 3000 chunk=%d lanes=%d steps_per_lane=%d init=%s" % (C, S, T, init), flush=True)
+        y, st, _, _ = tvi.solve_forward("vanderpol", dev(w["y0"]), dev(w["times"]), dev(w["params"]), **kw)
+        yh, st = host(y), host(st)
+        assert (st == 0).all()
+        assert series_rel_err(yh, yo).max() <= 1e-10
+        g = yh / np.sqrt(np.sum(yh ** 2))
+        dp, dy0, sa = tvi.solve_adjoint("vanderpol", dev(w["times"]), dev(w["params"]), dev(g), y=y, **kw)
+        assert (host(sa) == 0).all()
+        op, oy0, _ = oracle.adjoint("vanderpol", yh, w["times"], w["params"], g)
+        for a, b in ((host(dp), op), (host(dy0), oy0)):
+            err = np.abs(a - b).max(axis=1) / np.maximum(np.abs(b).max(axis=1), 1e-300)
+            assert err.max() <= 1e-10, err.max()
+
+
+def test_wide_halving_and_timing_tolerance(tvi):
+    """The stiff start of the kinetics at the timing tolerance with the longest
+    chunk: attempts are halved where Newton fails (the trajectory satisfies
+    backward Euler at every step), against the oracle at the same tolerance."""
+    w = W.robertson(B=32, n_range=(1000, 4000), seed=141)
+    off = w["offsets"]
+    offd = dev(off, torch.int64)
+    tol = (1e-8, 1e-6)
+    y, st, it, _ = tvi.solve_forward("robertson", dev(w["y0"]), dev(w["times"]), dev(w["params"]), offsets=offd,
+                                     chunk=2048, lanes=256, steps_per_lane=8, tol=tol, max_newton=8)
+    yh, st = host(y), host(st)
+    assert (st == 0).all()
+    yo, so, _ = oracle.forward("robertson", w["y0"], w["times"], w["params"], offsets=off, tol=PARITY_TOL)
+    # both satisfy the Newton tolerance: the trajectories agree to what it allows
+    assert series_rel_err(yh, yo, off).max() <= 1e-5
+    assert np.abs(yh.sum(axis=1) - 1.0).max() <= 1e-9
+
+
+def test_wide_refuses_what_it_does_not_cover(tvi):
+    w = W.robertson(B=4, n_range=(100, 200))
+    offd = dev(w["offsets"], torch.int64)
+    args = (dev(w["y0"]), dev(w["times"]), dev(w["params"]))
+    y, st, _, ck = tvi.solve_forward("robertson", *args, offsets=offd, chunk=1024, lanes=128, steps_per_lane=8,
+                                     checkpoints=True)
+    assert (host(st) == 0).all()
+    with pytest.raises(tvi.TviError):  # recomputation from checkpoints: one wave only
+        tvi.solve_adjoint("robertson", args[1], args[2], y, ckpt=ck, offsets=offd, chunk=1024, lanes=128,
+                          steps_per_lane=8)
+    with pytest.raises(tvi.TviError):
+        tvi.solve_forward("robertson", *args, offsets=offd, chunk=1024, lanes=128, steps_per_lane=8,
+                          scheme="forward_euler")
+
+
+def test_wide_full_size_robertson(tvi):
+    """The 2000 ragged series (7.7 M steps) at chunk 2048 over 4 waves, longest
+    first: every element against the oracle, and the adjoint from the stored
+    trajectory against the oracle's on every series."""
+    w = W.robertson()
+    off = w["offsets"]
+    yo, so, _ = oracle.forward("robertson", w["y0"], w["times"], w["params"], offsets=off, tol=PARITY_TOL)
+    assert (so == 0).all()
+    offd = dev(off, torch.int64)
+    kw = dict(offsets=offd, chunk=2048, lanes=256, steps_per_lane=8, tol=PARITY_TOL,
+              order=tvi.order_longest_first(offd))
+    y, st, _, _ = tvi.solve_forward("robertson", dev(w["y0"]), dev(w["times"]), dev(w["params"]), **kw)
+    yh = host(y)
+    assert (host(st) == 0).all()
+    assert series_rel_err(yh, yo, off).max() <= 1e-10
+    g = yh / np.sqrt(np.sum(yh ** 2))
+    dp, dy0, sa = tvi.solve_adjoint("robertson", dev(w["times"]), dev(w["params"]), dev(g), y=y, **kw)
+    assert (host(sa) == 0).all()
+    op, oy0, _ = oracle.adjoint("robertson", yh, w["times"], w["params"], g, offsets=off)
+    for a, b in ((host(dp), op), (host(dy0), oy0)):
+        err = np.abs(a - b).max(axis=1) / np.abs(b).max(axis=1)
+        assert err.max() <= 1e-10, err.max()
