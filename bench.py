@@ -278,8 +278,10 @@ def run_headline(args, dev, stream):
 
     # ---- autotune (untimed): chunk, tiling, start, and where the adjoint takes its states
     if args.config:
-        C, S, T, init, mode = args.config.split(",")
-        best = {"chunk": int(C), "lanes": int(S), "steps_per_lane": int(T), "init": init, "adjoint": mode}
+        parts = args.config.split(",")
+        C, S, T, init, mode = parts[:5]
+        best = {"chunk": int(C), "lanes": int(S), "steps_per_lane": int(T), "init": init, "adjoint": mode,
+                "max_newton_chunk": int(parts[5]) if len(parts) > 5 else 0}
         table = None
         log("configuration given: %s" % args.config)
     else:
@@ -289,23 +291,25 @@ def run_headline(args, dev, stream):
         for mode in ("stored", "recompute"):
             r = autotune.tune_forward("robertson", y0, times, sp, offsets=off, tol=TIMING_TOL, y_out=y_out,
                                       use_cache=False, chunks=(32, 64, 128, 256, 512, 1024, 2048),
-                                      inits=("zero", "extrap"),
+                                      inits=("zero", "extrap"), caps=(0, 8),
                                       adjoint=mode, order=order, n_max=nmax)
             for row in r["table"]:
                 cands.append(dict(row, adjoint=mode))
         del y_out
         best = min(cands, key=lambda r: (r["failed"], r["ms"]))
         table = cands
-        log("chosen chunk=%d lanes=%d steps_per_lane=%d init=%s adjoint=%s (%.3f ms)" % (
-            best["chunk"], best["lanes"], best["steps_per_lane"], best["init"], best["adjoint"], best["ms"]))
+        log("chosen chunk=%d lanes=%d steps_per_lane=%d init=%s adjoint=%s cap=%d (%.3f ms)" % (
+            best["chunk"], best["lanes"], best["steps_per_lane"], best["init"], best["adjoint"],
+            best["max_newton_chunk"], best["ms"]))
     C, S, T, init, mode = best["chunk"], best["lanes"], best["steps_per_lane"], best["init"], best["adjoint"]
+    cap = best.get("max_newton_chunk", 0)
 
-    def capture(chunk, lanes, spl, start, recompute):
+    def capture(chunk, lanes, spl, start, recompute, mnc=0):
         return graph.CapturedStep("robertson", y0, times, sp, offsets=off, chunk=chunk, lanes=lanes,
                                   steps_per_lane=spl, tol=TIMING_TOL, init=start, loss="frobenius", n_max=nmax,
-                                  recompute=recompute).capture()
+                                  recompute=recompute, max_newton_chunk=mnc).capture()
 
-    cs = capture(C, S, T, init, mode == "recompute")
+    cs = capture(C, S, T, init, mode == "recompute", cap)
     for _ in range(args.warmup):
         cs.replay()
     torch.cuda.synchronize()
@@ -361,7 +365,8 @@ def run_headline(args, dev, stream):
         "workload": "robertson n=3 B=2000 ragged N_b=round(exp U(ln 100, ln 2e4)) log-spaced t=[1e-5,1e4] "
                     "y0=(1,0,0) s_i=10^U(log 0.5, log 2) f64 tol=(1e-8,1e-6) fwd + Frobenius-loss gradient + "
                     "adjoint (dL/dp, dL/dy0) in one captured graph, longest first",
-        "chunk": C, "lanes": S, "steps_per_lane": T, "init": init, "adjoint_states": mode, "series": B,
+        "chunk": C, "lanes": S, "steps_per_lane": T, "init": init, "max_newton_chunk": cap, "adjoint_states": mode,
+        "series": B,
         "series_steps": total, "series_failed": int((~ok).sum()), "series_steps_counted": good_steps,
         "newton_corrections": int(it.sum())}, "roofline": roofline, "peak_device_memory_bytes": peak_mem}
     del cs
@@ -370,15 +375,15 @@ def run_headline(args, dev, stream):
     # recomputing adjoint runs in one wave, so for chunks over several waves the best
     # one-wave tiling the autotuner found for it), and the chunk = 1 baseline
     other_mode = "recompute" if mode != "recompute" else "stored"
-    aC, aS, aT, ainit = C, S, T, init
+    aC, aS, aT, ainit, acap = C, S, T, init, cap
     if other_mode == "recompute" and S > 64:
         rc = [r for r in (table or []) if r["adjoint"] == "recompute"]
         if rc:
             rb = min(rc, key=lambda r: (r["failed"], r["ms"]))
-            aC, aS, aT, ainit = rb["chunk"], rb["lanes"], rb["steps_per_lane"], rb["init"]
+            aC, aS, aT, ainit, acap = rb["chunk"], rb["lanes"], rb["steps_per_lane"], rb["init"], rb["max_newton_chunk"]
         else:
             aC, aS, aT = 512, 64, 8
-    alt = capture(aC, aS, aT, ainit, other_mode == "recompute")
+    alt = capture(aC, aS, aT, ainit, other_mode == "recompute", acap)
     alt.replay()
     a_st = stats(time_launches(alt.replay, max(3, args.steps // 2), stream))
     a_ok = ((alt.status_fwd == 0) & (alt.status_adj == 0)).cpu().numpy()
@@ -403,7 +408,7 @@ def run_headline(args, dev, stream):
     del seq
     if table is not None:
         head["autotune_best"] = {k: best[k] for k in ("chunk", "lanes", "steps_per_lane", "init", "adjoint",
-                                                       "failed", "ms")}
+                                                       "max_newton_chunk", "failed", "ms")}
         head["autotune_candidates"] = len(table)
     head["_table"] = table
     return head, w
@@ -482,14 +487,16 @@ def vdp_context(dev, stream, steps):
     y0, times, mu = d(w["y0"]), d(w["times"]), d(w["params"])
     y_out = torch.empty((B, N + 1, 2), dtype=torch.float64, device=dev)
     tuned = autotune.tune_forward("vanderpol", y0, times, mu, tol=TIMING_TOL, y_out=y_out, use_cache=False,
-                                  chunks=(10, 16, 32, 50, 64, 100, 128, 200, 256, 500), inits=("zero", "extrap"))
+                                  chunks=(10, 16, 32, 50, 64, 100, 128, 200, 256, 500, 1024, 2048),
+                                  inits=("zero", "extrap"), caps=(0, 5, 10))
     b = tuned["best"]
-    C, S, T, init = b["chunk"], b["lanes"], b["steps_per_lane"], b["init"]
+    C, S, T, init, cap = b["chunk"], b["lanes"], b["steps_per_lane"], b["init"], b["max_newton_chunk"]
     fn = lambda: tvi.solve_forward("vanderpol", y0, times, mu, chunk=C, lanes=S, steps_per_lane=T, tol=TIMING_TOL,
-                                   y_out=y_out, init=init)
+                                   y_out=y_out, init=init, max_newton_chunk=cap)
     _, st, it, _ = fn()
     kst = stats(time_launches(fn, steps, stream))
     return dict(dev=dev, stream=stream, y0=y0, times=times, mu=mu, y_out=y_out, B=B, N=N, C=C, S=S, T=T, init=init,
+                cap=cap,
                 ms_per_step=kst["mean_ms"], failed=int((st != 0).sum().item()), iters=it, kst=kst)
 
 
@@ -506,7 +513,7 @@ def run_vanderpol(ctx, steps):
     seq()
     ms1 = float(np.mean(time_launches(seq, max(3, steps // 3), ctx["stream"])))
     return {"value": B * N / (kms * 1e-3), "unit": "series*steps/s", "ms": kms, "chunk": C, "lanes": S,
-            "steps_per_lane": T, "init": ctx["init"], "failed": ctx["failed"],
+            "steps_per_lane": T, "init": ctx["init"], "max_newton_chunk": ctx["cap"], "failed": ctx["failed"],
             "achieved_tflops": flops / (kms * 1e-3) / 1e12,
             "frac_fp64_peak": flops / (kms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
             "chunk1": {"value": B * N / (ms1 * 1e-3), "ms": ms1, "speedup_of_chunked": ms1 / kms}}

@@ -235,6 +235,13 @@ typedef struct {
                                   the block solver (state sizes above 8) only; the
                                   other models' adjoint returns TVI_EUNSUPPORTED
                                   when either is set                                */
+    int32_t max_newton_chunk;  /* corrections an attempt of more than one step may take
+                                  before it is halved (0: max_newton); a single step
+                                  still takes up to max_newton.  A failing long
+                                  attempt then costs less; the converged result is
+                                  the same fixed point (the register and wide
+                                  solvers; the neural ODE and the block solver
+                                  ignore it)                                       */
 } tvi_options;
 
 /* Fills `opt` with the defaults: chunk 64, tol_a 1e-8, tol_r 1e-6 (Section 2.3),

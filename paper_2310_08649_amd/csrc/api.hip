@@ -207,6 +207,7 @@ void tvi_default_options(tvi_options *opt)
     opt->g_divisor = nullptr;
     opt->obs_idx = nullptr;
     opt->n_obs = 0;
+    opt->max_newton_chunk = 0;
 }
 
 const char *tvi_status_str(int32_t s)

@@ -59,7 +59,7 @@ inline tvi_status check_options(const tvi_options *o)
     if (!o) return TVI_EINVAL;
     if (o->obs_idx && o->n_obs < 1) return TVI_EINVAL;
     if (o->chunk < 1 || o->chunk > kMaxRegisterChunk) return TVI_EINVAL;
-    if (o->max_newton < 1) return TVI_EINVAL;
+    if (o->max_newton < 1 || o->max_newton_chunk < 0) return TVI_EINVAL;
     if (!(o->tol_a >= 0.0) || !(o->tol_r >= 0.0)) return TVI_EINVAL;
     if (o->init != TVI_INIT_ZERO && o->init != TVI_INIT_EXTRAP && o->init != TVI_INIT_PREDICTOR) return TVI_EINVAL;
     if (o->init == TVI_INIT_PREDICTOR &&
@@ -92,6 +92,7 @@ inline SolveArgs<IO> make_args(const tvi_options *opt, int64_t B, int64_t N, con
     a.params_shared = params_shared;
     a.chunk = opt->chunk;
     a.max_newton = opt->max_newton;
+    a.max_newton_chunk = opt->max_newton_chunk;
     a.init = opt->init;
     a.halving = opt->halving;
     a.tol_a = opt->tol_a;

@@ -48,6 +48,7 @@ struct SolveArgs {
     double *ckpt;              // [B][K][n] or null
     int32_t *status, *iters;
     int32_t chunk, max_newton, init, halving;
+    int32_t max_newton_chunk;  // corrections per attempt of more than one step (0: max_newton)
     double tol_a, tol_r;
     const IO *g;               // adjoint: dL/dy
     IO *dLdp, *dLdy0;
@@ -304,7 +305,8 @@ struct ChunkNewton {
     // ZREF: the relative test measures against ||R(dy = 0)|| (instances of their own: the extra
     // residual evaluation would otherwise sit in every solver's loop)
     template <bool PRED, bool ZREF, class IO, class Sink>
-    __device__ void run(const Model &model, const IO *t, int C, int max_newton, double tol_a, double tol_r,
+    __device__ void run(const Model &model, const IO *t, int C, int max_newton, int max_newton_chunk, double tol_a,
+                        double tol_r,
                         int init, bool halving, const Sink &sink, const PredictorRef &pr)
     {
         // the reference of the relative test differs from the first iterate's only for a nonzero start
@@ -392,7 +394,10 @@ struct ChunkNewton {
                 if (sing) { act = 2; code = ST_SINGULAR; }
                 else if (!finite(nrm2)) { act = 2; code = ST_NONFINITE; }
                 else if (nrm2 <= tol_a2 || nrm2 <= tol_r2 * nrm0) act = 1;
-                else if (it >= max_newton) { act = 2; code = ST_NOT_CONVERGED; }
+                else if (it >= ((m > 1 && max_newton_chunk > 0) ? max_newton_chunk : max_newton)) {
+                    act = 2;  // a longer attempt is halved sooner; a single step gets max_newton
+                    code = ST_NOT_CONVERGED;
+                }
                 else act = 3;
             }
 
@@ -564,7 +569,8 @@ __global__ __launch_bounds__(kWave) void forward_kernel(SolveArgs<IO> a)
     cn.status = ST_OK;
     cn.active = sv.valid && sv.Nb > 0;
     extern __shared__ float pred_lds[];
-    cn.template run<PRED, ZREF>(model, sv.t, a.chunk, a.max_newton, a.tol_a, a.tol_r, a.init, a.halving != 0, sink,
+    cn.template run<PRED, ZREF>(model, sv.t, a.chunk, a.max_newton, a.max_newton_chunk, a.tol_a, a.tol_r, a.init,
+                                a.halving != 0, sink,
            PredictorRef{a.pred, a.pred_hidden, a.pred_steps, a.pred_base, pred_lds});
     if (sv.valid && q == 0) {
         a.status[sv.b] = cn.status;
@@ -626,7 +632,8 @@ __global__ __launch_bounds__(kWave) void adjoint_kernel(SolveArgs<IO> a)
             for (int k = 0; k < n; ++k) cn.ys[k] = have_ckpt ? a.ckpt[(sv.b * a.K + c) * n + k] : 0.0;
             WorkspaceSink<n> wsink{wsb, s};
             extern __shared__ float pred_lds[];
-            cn.template run<PRED, ZREF>(model, sv.t, C, a.max_newton, a.tol_a, a.tol_r, a.init, a.halving != 0,
+            cn.template run<PRED, ZREF>(model, sv.t, C, a.max_newton, a.max_newton_chunk, a.tol_a, a.tol_r, a.init,
+                                        a.halving != 0,
                    wsink, PredictorRef{a.pred, a.pred_hidden, a.pred_steps, a.pred_base, pred_lds});
             if (active && cn.status != ST_OK) status = cn.status;
             __syncthreads(); // one wave per block: makes the workspace writes visible to the wave

@@ -252,8 +252,8 @@ struct WideNewton {
     // Solve steps s..s_end from ys; attempts never cross a multiple of C (the
     // checkpoints restart the same sequence).  Every thread calls it.
     template <class IO, class Sink>
-    __device__ void run(Xchg<W, n> &X, const Model &model, const IO *t, int C, int max_newton, double tol_a,
-                        double tol_r, int init, bool halving, const Sink &sink)
+    __device__ void run(Xchg<W, n> &X, const Model &model, const IO *t, int C, int max_newton, int max_newton_chunk,
+                        double tol_a, double tol_r, int init, bool halving, const Sink &sink)
     {
         const int q = threadIdx.x;
         start = true;
@@ -294,7 +294,10 @@ struct WideNewton {
             if (sing) { act = 2; code = ST_SINGULAR; }
             else if (!finite(nrm2)) { act = 2; code = ST_NONFINITE; }
             else if (nrm2 <= tol_a2 || nrm2 <= tol_r2 * nrm0) act = 1;
-            else if (it >= max_newton) { act = 2; code = ST_NOT_CONVERGED; }
+            else if (it >= ((m > 1 && max_newton_chunk > 0) ? max_newton_chunk : max_newton)) {
+                act = 2;
+                code = ST_NOT_CONVERGED;
+            }
             else act = 3;
 
             if (act == 1) {
@@ -432,7 +435,8 @@ __global__ __launch_bounds__(W *kWave) void forward_kernel(SolveArgs<IO> a)
     cn.total = 0;
     cn.status = ST_OK;
     cn.active = sv.Nb > 0;
-    cn.run(X, model, sv.t, a.chunk, a.max_newton, a.tol_a, a.tol_r, a.init, a.halving != 0, sink);
+    cn.run(X, model, sv.t, a.chunk, a.max_newton, a.max_newton_chunk, a.tol_a, a.tol_r, a.init, a.halving != 0,
+           sink);
     if (q == 0) {
         a.status[sv.b] = cn.status;
         if (a.iters) a.iters[sv.b] = cn.total;

@@ -29,7 +29,8 @@ class CapturedStep:
 
     def __init__(self, kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e-6), lanes=0, steps_per_lane=0,
                  max_newton=50, init="zero", loss="frobenius", observed=None, n_max=None, recompute=True,
-                 longest_first=True, scheme="backward_euler", jacobian="analytic", fused=False):
+                 longest_first=True, scheme="backward_euler", jacobian="analytic", fused=False,
+                 max_newton_chunk=0):
         lib = tvi.load()
         self.kind = kind
         self.recompute = recompute
@@ -52,7 +53,7 @@ class CapturedStep:
         # ragged series launch longest first (computed once: the lengths are inputs)
         self.order = tvi.order_longest_first(self.offsets) if self.offsets is not None and longest_first else None
         self.opt = tvi.make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, True, order=self.order,
-                                    scheme=scheme, jacobian=jacobian)
+                                    scheme=scheme, jacobian=jacobian, max_newton_chunk=max_newton_chunk)
         P = lib.tvi_param_count(ctypes.byref(self.model))
         K = (N + chunk - 1) // chunk + 1
         self.y = torch.empty(yshape, dtype=dt, device=dev)

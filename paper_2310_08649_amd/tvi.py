@@ -51,7 +51,7 @@ class Options(ctypes.Structure):
                 ("jacobian", ctypes.c_int32),
                 ("reference_residual", ctypes.c_int32), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t), ("g_divisor", ctypes.c_void_p),
-                ("obs_idx", ctypes.c_void_p), ("n_obs", ctypes.c_int32)]
+                ("obs_idx", ctypes.c_void_p), ("n_obs", ctypes.c_int32), ("max_newton_chunk", ctypes.c_int32)]
 
 
 _lib = None
@@ -137,16 +137,19 @@ def param_count(kind, n, hidden=64):
 
 def make_options(chunk=64, tol=(1e-8, 1e-6), max_newton=50, lanes=0, steps_per_lane=0, init="zero",
                  halving=True, predictor=None, order=None, scheme="backward_euler",
-                 jacobian="analytic", reference="first"):
+                 jacobian="analytic", reference="first", max_newton_chunk=0):
     """``predictor``: (packed params, hidden, steps[, base]) of a trained chunk
     predictor, as made by ``predictor.solver_args`` (base 0: corrections to the
     zero start, 1: to the extrapolated start).  ``scheme``: "backward_euler" or
     "forward_euler".  ``jacobian``: "analytic" or "forward_ad".
     ``reference``: the R0 of the relative stopping test, "first" (the attempt's
-    first iterate) or "zero" (the residual at dy = 0, Algorithm 1's n0)."""
+    first iterate) or "zero" (the residual at dy = 0, Algorithm 1's n0).
+    ``max_newton_chunk``: corrections an attempt of more than one step may take
+    before it is halved (0: ``max_newton``)."""
     o = Options()
     load().tvi_default_options(ctypes.byref(o))
     o.chunk = int(chunk)
+    o.max_newton_chunk = int(max_newton_chunk)
     o.tol_a, o.tol_r = float(tol[0]), float(tol[1])
     o.max_newton = int(max_newton)
     o.lanes, o.steps_per_lane = int(lanes), int(steps_per_lane)
@@ -225,7 +228,7 @@ def _geometry(y0, times, offsets, n_max=None):
 def solve_forward(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e-6), max_newton=50, lanes=0,
                   steps_per_lane=0, init="zero", halving=True, checkpoints=False, y_out=None, iters=True,
                   predictor=None, order=None, scheme="backward_euler", jacobian="analytic",
-                  n_max=None, reference="first"):
+                  n_max=None, reference="first", max_newton_chunk=0):
     """Chunked backward Euler (or forward Euler, ``scheme="forward_euler"``).  Returns ``(y, status, iters, ckpt)`` (device tensors;
     ``iters`` and ``ckpt`` may be None).  Asynchronous: nothing is synchronised, except that ragged series
     without ``n_max`` (the longest series' step count) read it from ``offsets``."""
@@ -238,7 +241,7 @@ def solve_forward(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e
     B, n, N, yshape = _geometry(y0, times, offsets, n_max)
     model = Model(KINDS[kind], n, _io_dtype(y0), 1 if params.dim() == 1 else 0, 64)
     opt = make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, halving, predictor, order, scheme,
-                       jacobian, reference)
+                       jacobian, reference, max_newton_chunk)
     dev = y0.device
     y = y_out if y_out is not None else torch.empty(yshape, dtype=dt, device=dev)
     status = torch.empty(B, dtype=torch.int32, device=dev)
@@ -262,7 +265,7 @@ def solve_forward(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e
 def solve_adjoint(kind, times, params, g, y=None, ckpt=None, offsets=None, chunk=64, tol=(1e-8, 1e-6),
                   max_newton=50, lanes=0, steps_per_lane=0, init="zero", halving=True, n=None, predictor=None,
                   order=None, scheme="backward_euler", jacobian="analytic", n_max=None,
-                  reference="first", noalloc=False, g_divisor=None, obs_idx=None):
+                  reference="first", noalloc=False, g_divisor=None, obs_idx=None, max_newton_chunk=0):
     """Discrete adjoint.  Returns ``(dLdp [B,P], dLdy0 [B,n], status [B])``.
 
     States come from the trajectory ``y`` or, when ``y`` is None, are recomputed
@@ -296,7 +299,7 @@ def solve_adjoint(kind, times, params, g, y=None, ckpt=None, offsets=None, chunk
         raise TviError("parameters must be per series [B, P] or shared [P]")
     model = Model(KINDS[kind], n, _io_dtype(g), 1 if shared else 0, 64)
     opt = make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, halving, predictor, order, scheme,
-                       jacobian, reference)
+                       jacobian, reference, max_newton_chunk)
     if g_divisor is not None:
         g_divisor = _dev(g_divisor, torch.float64, "g_divisor")
         opt.g_divisor = g_divisor.data_ptr()

@@ -56,7 +56,8 @@ def _fake():
 
 
 @pytest.mark.parametrize("field,value", [("chunk", 0), ("chunk", 2049), ("max_newton", 0), ("tol_a", -1.0),
-                                         ("init", 7), ("lanes", 3), ("steps_per_lane", 16)])
+                                         ("init", 7), ("lanes", 3), ("steps_per_lane", 16),
+                                         ("max_newton_chunk", -1)])
 def test_forward_rejects_bad_options(lib, field, value):
     from paper_2310_08649_amd import tvi
     m = tvi.Model(tvi.KINDS["vanderpol"], 2, tvi.F64, 0, 64)

@@ -184,15 +184,17 @@ def classify_vdp(y, st, w, yo, so, sens, gate, resid_gate):
     return match, cond, alt, bad, res
 
 
-@pytest.mark.parametrize("chunk", [1, 10, 50, 100, 500])
-def test_vanderpol_full_size_parity(tvi, vdp_oracle, chunk):
+@pytest.mark.parametrize("chunk,cap", [(1, 0), (10, 0), (50, 0), (100, 0), (500, 0), (50, 8), (500, 8)])
+def test_vanderpol_full_size_parity(tvi, vdp_oracle, chunk, cap):
+    """cap: corrections an attempt of more than one step may take before it is
+    halved (max_newton_chunk; single steps keep max_newton)."""
     w, yo, so, sens = vdp_oracle
     y, st, it, _ = tvi.solve_forward("vanderpol", dev(w["y0"]), dev(w["times"]), dev(w["params"]), chunk=chunk,
-                                     tol=PARITY_TOL)
+                                     tol=PARITY_TOL, max_newton_chunk=cap)
     y, st = host(y), host(st)
     match, cond, alt, bad, res = classify_vdp(y, st, w, yo, so, sens, 1e-10, 1e-9)
-    print("chunk %d: %d within 1e-10, %d within the oracle's rounding sensitivity, %d certified alternate "
-          "roots, %d GPU / %d oracle failures" % (chunk, match.sum(), cond.sum(), alt.sum(), (st != 0).sum(),
+    print("chunk %d cap %d: %d within 1e-10, %d within the oracle's rounding sensitivity, %d certified alternate "
+          "roots, %d GPU / %d oracle failures" % (chunk, cap, match.sum(), cond.sum(), alt.sum(), (st != 0).sum(),
                                                   (so != 0).sum()))
     assert not bad.any(), [(int(b), float(series_rel_err(y[b:b + 1], yo[b:b + 1])[0]), float(sens[b]))
                            for b in np.nonzero(bad)[0][:10]]

@@ -74,6 +74,7 @@ def test_option_marshalling():
     assert (o.tol_a, o.tol_r) == (1e-9, 1e-7)
     assert (o.scheme, o.jacobian, o.reference_residual) == (1, 1, 1)
     assert tvi.make_options(init="predictor").init == 2 and tvi.make_options(init="zero").init == 0
+    assert tvi.make_options().max_newton_chunk == 0 and tvi.make_options(max_newton_chunk=9).max_newton_chunk == 9
 
 
 def _golden(name):
