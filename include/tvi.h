@@ -232,9 +232,11 @@ typedef struct {
                                   enters only where the loss observes the state)    */
     int32_t n_obs;             /* its length, >= 1 when obs_idx is given            */
                                /* g_divisor and obs_idx: the neural ODE (TVI_MLP) and
-                                  the block solver (state sizes above 8) only; the
-                                  other models' adjoint returns TVI_EUNSUPPORTED
-                                  when either is set                                */
+                                  the block solver (state sizes above 8); g_divisor
+                                  also in the stored-trajectory adjoint over several
+                                  waves (Robertson and Van der Pol, TVI_F64, lanes
+                                  128 or 256).  Elsewhere the adjoint returns
+                                  TVI_EUNSUPPORTED when either is set              */
     int32_t max_newton_chunk;  /* corrections an attempt of more than one step may take
                                   before it is halved (0: max_newton); a single step
                                   still takes up to max_newton.  A failing long
@@ -285,8 +287,11 @@ tvi_status tvi_model_eval(const tvi_model *model, int64_t M, const void *states,
  *   transpose = 0:  D_1 x_1 = r_1,          D_j x_j - x_{j-1} = r_j  (j = 2..m)
  *   transpose = 1:  D_m^T x_m = r_m,        D_j^T x_j - x_{j+1} = r_j (j = m-1..1)
  * by parallel cyclic reduction: every block is inverted (Gauss-Jordan with
- * partial pivoting), a lane composes `steps_per_lane` consecutive rows, and
- * ceil(log2(lanes)) reduction levels run across the lanes of the system.
+ * partial pivoting), a lane composes T consecutive rows, and log2(S)
+ * reduction levels run across the S lanes of the system.  The tiling is the
+ * library's: the fewest rows per lane that hold m rows in one wave, raised
+ * for 3 x 3 and larger blocks (to 2 rows per lane, 8 for float 4 x 4) while
+ * at least four lanes share a system.
  *
  *   D  [B][m][n][n]   r, x  [B][m][n]     (dtype float or double, device)
  *   n in {2, 3, 4}, 1 <= m <= 512; n = 8 (the neural ODE's blocks) with

@@ -263,8 +263,7 @@ tvi_status tvi_pcr_solve(int32_t dtype, int32_t n, int64_t B, int64_t m, const v
     if (B == 0) return TVI_OK;
     if (!D || !r || !x) return TVI_EINVAL;
     int S, T;
-    choose_tiling((int)m, S, T);
-    if (m == 1) { S = 4; T = 1; }
+    pcr_tiling(n, dtype == TVI_F64, (int)m, S, T);
     return launch_pcr(dtype, n, B, (int)m, D, r, x, transpose ? 1 : 0, S, T, static_cast<hipStream_t>(stream));
 }
 
@@ -389,10 +388,26 @@ tvi_status tvi_solve_adjoint(const tvi_model *model, const tvi_options *opt, int
         a.ws = static_cast<double *>(workspace);
         return launch_mlp(pass, TVI_F32, &a, st, &gi);
     }
-    // the register solver's adjoint reads the plain trajectory-shaped g
-    if (gi.div || gi.obs) return TVI_EUNSUPPORTED;
+    // the register solver's adjoint reads the plain trajectory-shaped g; the
+    // stored-trajectory adjoint over several waves also takes the divisor
+    if (gi.obs) return TVI_EUNSUPPORTED;
     int S, T;
     if ((e = resolve_tiling(opt, S, T)) != TVI_OK) return e;
+    if (gi.div) {
+        const bool wide_kind = model->kind == TVI_ROBERTSON || model->kind == TVI_VANDERPOL;
+        if (recompute || S <= kWave || !wide_kind || model->dtype != TVI_F64 ||
+            opt->jacobian != TVI_JACOBIAN_ANALYTIC)
+            return TVI_EUNSUPPORTED;
+        SolveArgs<double> a = make_args<double>(opt, B, N, offsets, times, nullptr, params, model->params_shared);
+        a.y = const_cast<double *>(static_cast<const double *>(y));
+        a.g = static_cast<const double *>(g);
+        a.dLdp = static_cast<double *>(dLdp);
+        a.dLdy0 = static_cast<double *>(dLdy0);
+        a.status = status;
+        const hipStream_t st = static_cast<hipStream_t>(stream);
+        return model->kind == TVI_ROBERTSON ? launch_robertson_wide(PASS_ADJOINT, TVI_F64, &a, S, T, st, gi.div)
+                                            : launch_vanderpol_wide(PASS_ADJOINT, TVI_F64, &a, S, T, st, gi.div);
+    }
     if (recompute && opt->init == TVI_INIT_PREDICTOR && (S < 4 || T * model->n > kPredictorMaxTN))
         return TVI_EUNSUPPORTED;
     const int pass = recompute ? PASS_ADJOINT_RECOMPUTE : PASS_ADJOINT;

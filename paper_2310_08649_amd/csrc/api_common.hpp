@@ -39,6 +39,22 @@ inline void choose_tiling(int C, int &S, int &T)
     if (S > kMaxWaves * kWave) S = kMaxWaves * kWave;
 }
 
+// Lane tiling of the standalone block-bidiagonal solve: at least the rows per
+// lane that m needs in one wave, raised towards the count that runs fastest
+// for the block size (a lane's own rows cost one composition each, a
+// reduction level one per lane, so more rows per lane cut the compositions
+// per row; for 2 x 2 blocks the loads, not the arithmetic, set the time, and
+// one row per lane keeps them contiguous across the wave), while at least
+// four lanes share a system.
+inline void pcr_tiling(int n, bool f64, int m, int &S, int &T)
+{
+    choose_tiling(m, S, T);
+    const int pref = n == 2 ? 1 : (n == 4 && !f64) ? 8 : 2;
+    while (T < pref && (m + 2 * T - 1) / (2 * T) >= 4) T <<= 1;
+    S = next_pow2((m + T - 1) / T);
+    if (S < 4) S = 4;
+}
+
 inline tvi_status resolve_tiling(const tvi_options *o, int &S, int &T)
 {
     if (o->lanes == 0 && o->steps_per_lane == 0) {

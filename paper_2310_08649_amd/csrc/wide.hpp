@@ -447,7 +447,7 @@ __global__ __launch_bounds__(W *kWave) void forward_kernel(SolveArgs<IO> a)
 // the transposed recurrence lam_j = D_j^{-T} lam_{j+1} + D_j^{-T} g_j reduced
 // from the last step down, dL/dp = sum_j dt_j (dh/dp)^T lam_j.
 template <class Model, class IO, int W, int T>
-__global__ __launch_bounds__(W *kWave) void adjoint_kernel(SolveArgs<IO> a)
+__global__ __launch_bounds__(W *kWave) void adjoint_kernel(SolveArgs<IO> a, const double *g_div)
 {
     constexpr int n = Model::N;
     constexpr int P = Model::P;
@@ -466,6 +466,9 @@ __global__ __launch_bounds__(W *kWave) void adjoint_kernel(SolveArgs<IO> a)
     for (int k = 0; k < P; ++k) gp[k] = 0.0;
     const IO *gb = a.g + sv.p0 * n;
     const IO *yb = a.y + sv.p0 * n;
+    // g_div: every entry of g divided by a device scalar (g = y / L of the
+    // Frobenius loss read from the trajectory); multiplying by 1 is exact
+    const double gsc = g_div ? 1.0 / *g_div : 1.0;
     int status = ST_OK;
 
     for (int64_t c = (sv.Nb + C - 1) / C - 1; c >= 0; --c) {  // workgroup-uniform
@@ -484,7 +487,7 @@ __global__ __launch_bounds__(W *kWave) void adjoint_kernel(SolveArgs<IO> a)
 #pragma unroll
             for (int e = 0; e < n; ++e) {
                 yl[i][e] = v ? ld(yb + k * n + e) : 0.0;
-                gk[e] = v ? ld(gb + k * n + e) : 0.0;
+                gk[e] = v ? ld(gb + k * n + e) * gsc : 0.0;
             }
             tl[i] = v ? ld(sv.t + k) : 0.0;
             hl[i] = v ? tl[i] - ld(sv.t + k - 1) : 0.0;
@@ -543,16 +546,18 @@ __global__ __launch_bounds__(W *kWave) void adjoint_kernel(SolveArgs<IO> a)
     if (q == 0) {
         const double nan = __builtin_nan("");
 #pragma unroll
-        for (int k = 0; k < n; ++k) st(a.dLdy0 + sv.b * n + k, status == ST_OK ? ld(gb + k) + lam[k] : nan);
+        for (int k = 0; k < n; ++k) st(a.dLdy0 + sv.b * n + k, status == ST_OK ? ld(gb + k) * gsc + lam[k] : nan);
 #pragma unroll
         for (int k = 0; k < P; ++k) st(a.dLdp + sv.b * P + k, status == ST_OK ? gp[k] : nan);
         a.status[sv.b] = status;
     }
 }
 
-// Forward (pass 0) and stored-trajectory adjoint (pass 1) for S = 64 W lanes.
+// Forward (pass 0) and stored-trajectory adjoint (pass 1) for S = 64 W lanes;
+// g_div (adjoint only, may be null): the device scalar dividing g.
 template <class Model, class IO>
-tvi_status launch(int pass, const SolveArgs<IO> &a, int S, int T, hipStream_t stream)
+tvi_status launch(int pass, const SolveArgs<IO> &a, int S, int T, hipStream_t stream,
+                  const double *g_div = nullptr)
 {
     if (a.scheme != 0 || a.init == INIT_PREDICTOR || a.zero_ref != 0) return TVI_EUNSUPPORTED;
     if (a.B > 0x7fffffffLL) return TVI_EINVAL;
@@ -562,7 +567,8 @@ tvi_status launch(int pass, const SolveArgs<IO> &a, int S, int T, hipStream_t st
         if (pass == PASS_FORWARD)                                                                                \
             hipLaunchKernelGGL((forward_kernel<Model, IO, WW, TT>), grid, dim3((WW) * kWave), 0, stream, a);     \
         else if (pass == PASS_ADJOINT)                                                                           \
-            hipLaunchKernelGGL((adjoint_kernel<Model, IO, WW, TT>), grid, dim3((WW) * kWave), 0, stream, a);     \
+            hipLaunchKernelGGL((adjoint_kernel<Model, IO, WW, TT>), grid, dim3((WW) * kWave), 0, stream, a,  \
+                               g_div);                                                                   \
         else                                                                                                     \
             return TVI_EUNSUPPORTED;                                                                             \
         return hipGetLastError() == hipSuccess ? TVI_OK : TVI_EHIP;                                              \

@@ -67,8 +67,11 @@ class CapturedStep:
         # reads g = y / L from the trajectory (tvi_options.g_divisor), never forming g
         if fused and self.loss_kind != LOSS["frobenius"]:
             raise tvi.TviError("the fused gradient is the Frobenius loss's (g = y / L)")
-        if fused and not (kind == "mlp" or tvi.is_block(kind, n)):
-            raise tvi.TviError("the fused gradient is offered by the neural-ODE and block solvers")
+        wide_stored = (kind in ("robertson", "vanderpol") and dt == torch.float64 and not recompute
+                       and lanes > 64 and jacobian == "analytic")
+        if fused and not (kind == "mlp" or tvi.is_block(kind, n) or wide_stored):
+            raise tvi.TviError("the fused gradient is offered by the neural-ODE and block solvers and by the "
+                               "stored-trajectory adjoint over several waves (lanes 128 or 256)")
         self.fused = fused
         self.g = None if fused else torch.empty_like(self.y)
         self.observed = None if observed is None else observed.to(device=dev, dtype=torch.uint8).contiguous()

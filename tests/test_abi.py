@@ -319,8 +319,11 @@ def test_observed_steps_option_is_checked(lib):
 
 def test_register_solver_refuses_divided_or_observed_gradients(lib):
     """The divided gradient (g_divisor) and observed-step gradients (obs_idx)
-    are offered by the neural-ODE and block solvers; the register solver's
-    adjoint refuses them with TVI_EUNSUPPORTED before any HIP call."""
+    are offered by the neural-ODE and block solvers, and the divided gradient
+    by the stored-trajectory adjoint over several waves (Robertson and Van der
+    Pol in double); the one-wave register solver's adjoint, the recomputing
+    adjoint and the other models refuse them with TVI_EUNSUPPORTED before any
+    HIP call."""
     from paper_2310_08649_amd import tvi
     f = _fake()
     m = tvi.Model(1, 2, tvi.F64, 0, 64)
@@ -333,6 +336,20 @@ def test_register_solver_refuses_divided_or_observed_gradients(lib):
     o.n_obs = 3
     assert lib.tvi_solve_adjoint(ctypes.byref(m), ctypes.byref(o), 4, 10, None, f, f, f, None, f, f, f, f, None, 0,
                                  None) == -4
+
+    def adj(kind, n, dtype=tvi.F64, stored=True, **kw):
+        mm = tvi.Model(tvi.KINDS[kind], n, dtype, 0, 64)
+        oo = tvi.make_options(**kw)
+        oo.g_divisor = 0x1000
+        return lib.tvi_solve_adjoint(ctypes.byref(mm), ctypes.byref(oo), 4, 10, None, f, f, f if stored else None,
+                                     f, f, f, f, f, f, 1 << 30, None)
+
+    wide = dict(chunk=1024, lanes=128, steps_per_lane=8)
+    assert adj("robertson", 3, stored=False, **wide) == -4      # recomputing adjoint
+    assert adj("linear", 2, **wide) == -4                       # no wide kernels for this model
+    assert adj("vanderpol", 2, dtype=tvi.F32, **wide) == -4     # double storage only
+    assert adj("robertson", 3, jacobian="forward_ad", **wide) == -4
+    assert adj("robertson", 3, chunk=512, lanes=64, steps_per_lane=8) == -4   # one wave
 
 
 def test_tilings_over_several_waves_are_checked(lib):

@@ -95,6 +95,23 @@ def test_pcr_solve_8x8_float(tvi, transpose):
         assert err.max() <= 1e-5, (m, float(err.max()))
 
 
+@pytest.mark.parametrize("n", [2, 3, 4])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_pcr_solve_float_matches_dense(tvi, n, transpose):
+    """Float storage and arithmetic for 2 x 2 to 4 x 4 blocks over the row
+    counts whose lane tilings differ (one to eight rows per lane, 4 to 64
+    lanes, ragged tails), against the dense solve in double."""
+    rng = np.random.default_rng(300 + n)
+    for m in (1, 2, 3, 5, 8, 9, 15, 16, 17, 31, 33, 63, 64, 65, 100, 129, 255, 256, 300, 511, 512):
+        B = 6
+        D = (1.6 * np.eye(n)[None, None] + (0.3 / np.sqrt(n)) * rng.standard_normal((B, m, n, n))).astype(np.float32)
+        r = rng.standard_normal((B, m, n)).astype(np.float32)
+        ref = bb.dense_solve(D.astype(np.float64), r.astype(np.float64), transpose=transpose)
+        x = host(tvi.pcr_solve(dev(D, torch.float32), dev(r, torch.float32), transpose=transpose)).astype(np.float64)
+        err = np.abs(x - ref).max(axis=(1, 2)) / np.abs(ref).max(axis=(1, 2))
+        assert err.max() <= 1e-5, (m, float(err.max()))
+
+
 def test_pcr_solve_fp32_and_singular_block(tvi):
     rng = np.random.default_rng(7)
     B, m, n = 6, 96, 2

@@ -160,3 +160,55 @@ def test_wide_full_size_robertson(tvi):
     for a, b in ((host(dp), op), (host(dy0), oy0)):
         err = np.abs(a - b).max(axis=1) / np.abs(b).max(axis=1)
         assert err.max() <= 1e-10, err.max()
+
+
+@pytest.mark.parametrize("kind,C,S,T", [("robertson", 1024, 128, 8), ("robertson", 512, 128, 4),
+                                        ("vanderpol", 1024, 256, 4)])
+def test_wide_fused_frobenius_gradient_equals_the_formed_one(tvi, kind, C, S, T):
+    """The stored-trajectory adjoint over several waves reading g = y / L from
+    the trajectory (tvi_options.g_divisor; the loss kernel computes L alone)
+    against the graph that forms g in memory: the same gradients to rounding
+    (one reciprocal instead of a division per entry), every replay bitwise
+    equal to the first, and both against the oracle's adjoint."""
+    from paper_2310_08649_amd import graph
+    if kind == "robertson":
+        w = _ragged_robertson()
+        off = w["offsets"]
+        extra = dict(offsets=dev(off, torch.int64))
+    else:
+        w = W.vanderpol(B=12, N=3000, mu_range=(1.0, 30.0), t_end=6.0)
+        off = None
+        extra = {}
+    args = (dev(w["y0"]), dev(w["times"]), dev(w["params"]))
+    runs = {}
+    for fused in (False, True):
+        print("%s fused=%s chunk=%d lanes=%d steps_per_lane=%d" % (kind, fused, C, S, T), flush=True)
+        step = graph.CapturedStep(kind, *args, chunk=C, lanes=S, steps_per_lane=T, tol=PARITY_TOL, loss="frobenius",
+                                  recompute=False, fused=fused, **extra).capture()
+        step.replay()
+        torch.cuda.synchronize()
+        first = (step.dLdp.clone(), step.dLdy0.clone())
+        for _ in range(3):
+            step.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(step.dLdp, first[0]) and torch.equal(step.dLdy0, first[1])
+        assert (step.status_fwd.cpu() == 0).all() and (step.status_adj.cpu() == 0).all()
+        runs[fused] = (host(first[0]), host(first[1]))
+        yh = host(step.y)
+    for a, b in zip(runs[True], runs[False]):
+        assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max(), kind
+    # the oracle's adjoint on the GPU trajectory with g = y / ||y||_F
+    g = yh / np.sqrt(np.sum(yh ** 2))
+    op, oy0, _ = oracle.adjoint(kind, yh, w["times"], w["params"], g, offsets=off)
+    for a, b in ((runs[True][0], op), (runs[True][1], oy0)):
+        err = np.abs(a - b).max(axis=1) / np.maximum(np.abs(b).max(axis=1), 1e-300)
+        assert err.max() <= 1e-10, err.max()
+
+
+def test_wide_fused_gradient_needs_the_stored_trajectory(tvi):
+    from paper_2310_08649_amd import graph
+    w = W.robertson(B=4, n_range=(100, 200))
+    args = (dev(w["y0"]), dev(w["times"]), dev(w["params"]))
+    with pytest.raises(tvi.TviError):
+        graph.CapturedStep("robertson", *args, offsets=dev(w["offsets"], torch.int64), chunk=1024, lanes=128,
+                           steps_per_lane=8, loss="frobenius", recompute=True, fused=True)
