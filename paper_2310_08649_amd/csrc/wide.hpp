@@ -251,9 +251,12 @@ struct WideNewton {
 
     // Solve steps s..s_end from ys; attempts never cross a multiple of C (the
     // checkpoints restart the same sequence).  Every thread calls it.
+    // fis: LDS for the steps' block inverses between the composition and the
+    // replay, [T][n][n][S] (lane-contiguous: conflict-free), each lane reading
+    // back only what it wrote; keeps them out of the registers
     template <class IO, class Sink>
-    __device__ void run(Xchg<W, n> &X, const Model &model, const IO *t, int C, int max_newton, int max_newton_chunk,
-                        double tol_a, double tol_r, int init, bool halving, const Sink &sink)
+    __device__ void run(Xchg<W, n> &X, double *fis, const Model &model, const IO *t, int C, int max_newton,
+                        int max_newton_chunk, double tol_a, double tol_r, int init, bool halving, const Sink &sink)
     {
         const int q = threadIdx.x;
         start = true;
@@ -348,14 +351,14 @@ struct WideNewton {
             }
 
             // ---- Newton correction: blocks, in-lane composition, the scans, replay
-            double Fi[T][n][n], zi[T][n];
+            double zi[T][n];
             AffineI<n, double> map;
             affine_identity(map);
             int ok = 1;
 #pragma unroll
             for (int i = 0; i < T; ++i) {
                 if (owned(q, i)) {
-                    double yv[n], J[n][n], D[n][n];
+                    double yv[n], J[n][n], D[n][n], Fi[n][n];
 #pragma unroll
                     for (int k = 0; k < n; ++k) yv[k] = ys[k] + dy[i][k];
                     model.jac(yv, tt[i], J);
@@ -363,17 +366,21 @@ struct WideNewton {
                     for (int r = 0; r < n; ++r)
 #pragma unroll
                         for (int c = 0; c < n; ++c) D[r][c] = ((r == c) ? 1.0 : 0.0) - hh[i] * J[r][c];
-                    ok &= invert_plus(D, Fi[i]) ? 1 : 0;
+                    ok &= invert_plus(D, Fi) ? 1 : 0;
+#pragma unroll
+                    for (int r = 0; r < n; ++r)
+#pragma unroll
+                        for (int c = 0; c < n; ++c) fis[((i * n + r) * n + c) * S + q] = Fi[r][c];
                     const double zero[n] = {};
                     double negR[n];
 #pragma unroll
                     for (int k = 0; k < n; ++k) negR[k] = -R[i][k];
-                    apply_ip(Fi[i], negR, zero, zi[i]);
+                    apply_ip(Fi, negR, zero, zi[i]);
                     AffineI<n, double> stp;
 #pragma unroll
                     for (int r = 0; r < n; ++r) {
 #pragma unroll
-                        for (int c = 0; c < n; ++c) stp.F[r][c] = Fi[i][r][c];
+                        for (int c = 0; c < n; ++c) stp.F[r][c] = Fi[r][c];
                         stp.z[r] = zi[i][r];
                     }
                     if (i > 0) affine_after(stp, map);
@@ -397,7 +404,12 @@ struct WideNewton {
 #pragma unroll
                 for (int i = 0; i < T; ++i) {
                     if (owned(q, i)) {
-                        apply_ip(Fi[i], din, zi[i], din);
+                        double Fi[n][n];
+#pragma unroll
+                        for (int r = 0; r < n; ++r)
+#pragma unroll
+                            for (int c = 0; c < n; ++c) Fi[r][c] = fis[((i * n + r) * n + c) * S + q];
+                        apply_ip(Fi, din, zi[i], din);
 #pragma unroll
                         for (int k = 0; k < n; ++k) dy[i][k] += din[k];
                     }
@@ -412,10 +424,11 @@ struct WideNewton {
 };
 
 template <class Model, class IO, int W, int T>
-__global__ __launch_bounds__(W *kWave) void forward_kernel(SolveArgs<IO> a)
+__global__ __launch_bounds__(W *kWave) __attribute__((amdgpu_waves_per_eu(T == 4 ? 2 : 1))) void forward_kernel(SolveArgs<IO> a)
 {
     constexpr int n = Model::N;
     __shared__ Xchg<W, n> X;
+    __shared__ double fis[T * n * n * W * kWave];
     const int q = threadIdx.x;
     const SeriesView<IO> sv(a, blockIdx.x);
     if (!sv.valid) return;  // the whole workgroup idles
@@ -435,8 +448,8 @@ __global__ __launch_bounds__(W *kWave) void forward_kernel(SolveArgs<IO> a)
     cn.total = 0;
     cn.status = ST_OK;
     cn.active = sv.Nb > 0;
-    cn.run(X, model, sv.t, a.chunk, a.max_newton, a.max_newton_chunk, a.tol_a, a.tol_r, a.init, a.halving != 0,
-           sink);
+    cn.run(X, fis, model, sv.t, a.chunk, a.max_newton, a.max_newton_chunk, a.tol_a, a.tol_r, a.init,
+           a.halving != 0, sink);
     if (q == 0) {
         a.status[sv.b] = cn.status;
         if (a.iters) a.iters[sv.b] = cn.total;
