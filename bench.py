@@ -496,15 +496,16 @@ def vdp_context(dev, stream, steps):
     y_out = torch.empty((B, N + 1, 2), dtype=torch.float64, device=dev)
     tuned = autotune.tune_forward("vanderpol", y0, times, mu, tol=TIMING_TOL, y_out=y_out, use_cache=False,
                                   chunks=(10, 16, 32, 50, 64, 100, 128, 200, 256, 500, 1024, 2048),
-                                  inits=("zero", "extrap"), caps=(0, 5, 10))
+                                  inits=("zero", "extrap"), caps=(0, 5, 10), limits=(50, 200, 400))
     b = tuned["best"]
-    C, S, T, init, cap = b["chunk"], b["lanes"], b["steps_per_lane"], b["init"], b["max_newton_chunk"]
+    C, S, T, init, cap, mn = (b["chunk"], b["lanes"], b["steps_per_lane"], b["init"], b["max_newton_chunk"],
+                              b["max_newton"])
     fn = lambda: tvi.solve_forward("vanderpol", y0, times, mu, chunk=C, lanes=S, steps_per_lane=T, tol=TIMING_TOL,
-                                   y_out=y_out, init=init, max_newton_chunk=cap)
+                                   y_out=y_out, init=init, max_newton=mn, max_newton_chunk=cap)
     _, st, it, _ = fn()
     kst = stats(time_launches(fn, steps, stream))
     return dict(dev=dev, stream=stream, y0=y0, times=times, mu=mu, y_out=y_out, B=B, N=N, C=C, S=S, T=T, init=init,
-                cap=cap,
+                cap=cap, mn=mn,
                 ms_per_step=kst["mean_ms"], failed=int((st != 0).sum().item()), iters=it, kst=kst)
 
 
@@ -517,14 +518,17 @@ def run_vanderpol(ctx, steps):
     kms = ctx["kst"]["mean_ms"]
     flops = float(ctx["iters"].sum().item()) * C * vdp_flops_per_step_iter(C)
     seq = lambda: tvi.solve_forward("vanderpol", ctx["y0"], ctx["times"], ctx["mu"], chunk=1, lanes=1,
-                                    steps_per_lane=1, tol=TIMING_TOL, y_out=ctx["y_out"], iters=False)
-    seq()
+                                    steps_per_lane=1, tol=TIMING_TOL, y_out=ctx["y_out"], iters=False,
+                                    max_newton=ctx["mn"])
+    st1 = seq()[1]
     ms1 = float(np.mean(time_launches(seq, max(3, steps // 3), ctx["stream"])))
     return {"value": B * N / (kms * 1e-3), "unit": "series*steps/s", "ms": kms, "chunk": C, "lanes": S,
-            "steps_per_lane": T, "init": ctx["init"], "max_newton_chunk": ctx["cap"], "failed": ctx["failed"],
+            "steps_per_lane": T, "init": ctx["init"], "max_newton": ctx["mn"], "max_newton_chunk": ctx["cap"],
+            "failed": ctx["failed"],
             "achieved_tflops": flops / (kms * 1e-3) / 1e12,
             "frac_fp64_peak": flops / (kms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
-            "chunk1": {"value": B * N / (ms1 * 1e-3), "ms": ms1, "speedup_of_chunked": ms1 / kms}}
+            "chunk1": {"value": B * N / (ms1 * 1e-3), "ms": ms1, "speedup_of_chunked": ms1 / kms,
+                       "failed": int((st1 != 0).sum().item())}}
 
 
 def run_vdp_fp32(ctx, steps):
@@ -538,7 +542,8 @@ def run_vdp_fp32(ctx, steps):
     res = {}
     for C, S, T in ((ctx["C"], ctx["S"], ctx["T"]), (1, 1, 1)):
         fn = lambda: tvi.solve_forward("vanderpol", y0, times, mu, chunk=C, lanes=S, steps_per_lane=T,
-                                       tol=TIMING_TOL, y_out=y, iters=False)
+                                       tol=TIMING_TOL, y_out=y, iters=False, max_newton=ctx["mn"],
+                                       init=ctx["init"] if C > 1 else "zero", max_newton_chunk=ctx["cap"])
         st = fn()[1]
         ms = float(np.mean(time_launches(fn, max(3, steps // 2), ctx["stream"])))
         res["chunk%d" % C] = {"value": ctx["B"] * ctx["N"] / (ms * 1e-3), "ms": ms,
@@ -639,7 +644,8 @@ def run_vdp_fwd_adjoint(ctx, steps):
     for recompute in (False, True):
         cs = graph.CapturedStep("vanderpol", ctx["y0"], ctx["times"], ctx["mu"], chunk=ctx["C"], lanes=ctx["S"],
                                 steps_per_lane=ctx["T"], tol=TIMING_TOL, init=ctx["init"], loss="mean_square",
-                                observed=obs.reshape(-1), recompute=recompute).capture()
+                                observed=obs.reshape(-1), recompute=recompute, max_newton=ctx["mn"],
+                                max_newton_chunk=ctx["cap"]).capture()
         for _ in range(2):
             cs.replay()
         d = time_launches(cs.replay, max(5, steps), torch.cuda.current_stream())
@@ -944,7 +950,8 @@ def run_forward_ad(ctx, steps):
 
     res["vanderpol"] = pair(lambda jac: lambda: tvi.solve_forward(
         "vanderpol", ctx["y0"], ctx["times"], ctx["mu"], chunk=ctx["C"], lanes=ctx["S"], steps_per_lane=ctx["T"],
-        tol=TIMING_TOL, init=ctx["init"], y_out=ctx["y_out"], iters=False, jacobian=jac), max(3, steps // 2))
+        tol=TIMING_TOL, init=ctx["init"], y_out=ctx["y_out"], iters=False, jacobian=jac, max_newton=ctx["mn"],
+        max_newton_chunk=ctx["cap"]), max(3, steps // 2))
     # inputs resident on the device before the timed launches
     w = workloads.linear(B=512, N=5000, n=4, seed=114)
     yl = torch.empty((512, 5001, 4), dtype=torch.float64, device=dev)

@@ -104,8 +104,9 @@ def _time(fn, reps):
 
 
 def tune_forward(kind, y0, times, params, offsets=None, tol=(1e-8, 1e-6), chunks=(10, 50, 100, 200, 500),
-                 reps=3, y_out=None, use_cache=True, inits=("zero",), adjoint=None, caps=(0,), **kw):
-    """Returns {"best": {chunk, lanes, steps_per_lane, init, failed, ms}, "table": [...]}.
+                 reps=3, y_out=None, use_cache=True, inits=("zero",), adjoint=None, caps=(0,), limits=None, **kw):
+    """Returns {"best": {chunk, lanes, steps_per_lane, init, max_newton, max_newton_chunk, failed, ms},
+    "table": [...]}.
 
     Candidates are ranked by the number of series that failed to converge
     (forward, or forward or adjoint when the adjoint is timed), then by time:
@@ -117,11 +118,15 @@ def tune_forward(kind, y0, times, params, offsets=None, tol=(1e-8, 1e-6), chunks
     options (scheme, jacobian, order, max_newton, n_max, ...) are passed to
     both solves and are part of the cache key.  ``caps``: values of
     max_newton_chunk tried (corrections before a multi-step attempt is halved;
-    0 = max_newton)."""
+    0 = max_newton).  ``limits``: values of max_newton tried (the corrections a
+    single step may take before its series is given up), or None for the one
+    in ``kw`` (default 50)."""
     opts = ",".join("%s=%s" % (k, "tensor" if isinstance(v, torch.Tensor) else v) for k, v in sorted(kw.items()))
-    key = _key(kind, y0, times, offsets, "tol=%g,%g|chunks=%s|inits=%s|adjoint=%s|caps=%s|%s"
+    kw_limit = kw.pop("max_newton", 50)
+    lims = tuple(limits) if limits else (kw_limit,)
+    key = _key(kind, y0, times, offsets, "tol=%g,%g|chunks=%s|inits=%s|adjoint=%s|caps=%s|limits=%s|%s"
                % (tol[0], tol[1], ",".join(map(str, chunks)), ",".join(inits), adjoint,
-                  ",".join(map(str, caps)), opts))
+                  ",".join(map(str, caps)), ",".join(map(str, lims)), opts))
     if use_cache:
         with _lock:
             hit = _load_cache().get(key)
@@ -130,28 +135,29 @@ def tune_forward(kind, y0, times, params, offsets=None, tol=(1e-8, 1e-6), chunks
     table = []
     wide = kind in WIDE_KINDS and y0.dtype == torch.float64 and not adjoint == "recompute"
     for C in chunks:
-        for S, T, init, cap in [(S, T, i, c) for S, T in tilings(C, wide) for i in inits for c in caps]:
+        for S, T, init, cap, lim in [(S, T, i, c, l) for S, T in tilings(C, wide) for i in inits for c in caps
+                                     for l in lims]:
             res = {}
 
             def fn():
                 y, st, _, ck = tvi.solve_forward(kind, y0, times, params, offsets=offsets, chunk=C, lanes=S,
                                                  steps_per_lane=T, tol=tol, y_out=y_out, init=init,
                                                  iters=False, checkpoints=adjoint == "recompute",
-                                                 max_newton_chunk=cap, **kw)
+                                                 max_newton=lim, max_newton_chunk=cap, **kw)
                 res["st"] = st
                 if adjoint:
                     g = y if "g" not in res else res["g"]
                     res["g"] = g
                     src = dict(ckpt=ck) if adjoint == "recompute" else dict(y=y)
                     _, _, sa = tvi.solve_adjoint(kind, times, params, g, offsets=offsets, chunk=C, lanes=S,
-                                                 steps_per_lane=T, tol=tol, init=init,
+                                                 steps_per_lane=T, tol=tol, init=init, max_newton=lim,
                                                  max_newton_chunk=cap, **src, **kw)
                     res["sa"] = sa
             ms = _time(fn, reps)
             bad = res["st"] != 0
             if adjoint:
                 bad = bad | (res["sa"] != 0)
-            table.append({"chunk": C, "lanes": S, "steps_per_lane": T, "init": init,
+            table.append({"chunk": C, "lanes": S, "steps_per_lane": T, "init": init, "max_newton": lim,
                           "max_newton_chunk": cap, "failed": int(bad.sum().item()), "ms": ms})
     best = min(table, key=lambda r: (r["failed"], r["ms"]))
     res = {"best": best, "table": table}

@@ -201,18 +201,22 @@ def classify_vdp(y, st, w, yo, so, sens, gate, resid_gate):
     return match, cond, alt, bad, res
 
 
-@pytest.mark.parametrize("chunk,cap", [(1, 0), (10, 0), (50, 0), (100, 0), (500, 0), (50, 8), (500, 8)])
-def test_vanderpol_full_size_parity(tvi, vdp_oracle, chunk, cap):
+# the last case is the launch configuration the benchmark's tuner picks for this
+# workload (64 lanes x 1 step, extrapolated start, single steps up to 400 corrections)
+@pytest.mark.parametrize("chunk,cap,init,limit", [(1, 0, "zero", 50), (10, 0, "zero", 50), (50, 0, "zero", 50),
+                                                  (100, 0, "zero", 50), (500, 0, "zero", 50), (50, 8, "zero", 50),
+                                                  (500, 8, "zero", 50), (64, 5, "extrap", 400)])
+def test_vanderpol_full_size_parity(tvi, vdp_oracle, chunk, cap, init, limit):
     """cap: corrections an attempt of more than one step may take before it is
-    halved (max_newton_chunk; single steps keep max_newton)."""
+    halved (max_newton_chunk; single steps keep max_newton = limit)."""
     w, yo, so, sens = vdp_oracle
     y, st, it, _ = tvi.solve_forward("vanderpol", dev(w["y0"]), dev(w["times"]), dev(w["params"]), chunk=chunk,
-                                     tol=PARITY_TOL, max_newton_chunk=cap)
+                                     tol=PARITY_TOL, max_newton_chunk=cap, init=init, max_newton=limit)
     y, st = host(y), host(st)
     match, cond, alt, bad, res = classify_vdp(y, st, w, yo, so, sens, 1e-10, 1e-9)
-    print("chunk %d cap %d: %d within 1e-10, %d within the oracle's rounding sensitivity, %d certified alternate "
-          "roots, %d GPU / %d oracle failures" % (chunk, cap, match.sum(), cond.sum(), alt.sum(), (st != 0).sum(),
-                                                  (so != 0).sum()))
+    print("chunk %d cap %d %s start, limit %d: %d within 1e-10, %d within the oracle's rounding sensitivity, %d "
+          "certified alternate roots, %d GPU / %d oracle failures" % (
+              chunk, cap, init, limit, match.sum(), cond.sum(), alt.sum(), (st != 0).sum(), (so != 0).sum()))
     assert not bad.any(), [(int(b), float(series_rel_err(y[b:b + 1], yo[b:b + 1])[0]), float(sens[b]))
                            for b in np.nonzero(bad)[0][:10]]
     assert match.sum() >= 0.85 * len(st)
@@ -241,7 +245,7 @@ def test_vanderpol_fp32_storage(tvi):
     assert (rel[ok & ~alt] <= 1e-5).all()
 
 
-# (50, 64, 1) is the launch configuration the benchmark's tuner picks for this workload
+# (50, 64, 1) is the tuner's choice for this workload with the zero start and the default limits
 @pytest.mark.parametrize("C,S,T", [(100, 0, 0), (50, 64, 1), (50, 16, 4), (64, 8, 8)])
 def test_vanderpol_timing_tolerance_residual_invariant(tvi, vdp_oracle, C, S, T):
     w, yo, so, _ = vdp_oracle
