@@ -178,7 +178,7 @@ typedef struct {
     int32_t chunk;          /* steps solved together, >= 1 (Section 2.3)           */
     int32_t lanes;          /* lanes per series S: 1,4,8,16,32,64 (one wavefront;
                                chunk <= 512), or 128, 256 (2 or 4 wavefronts, one
-                               workgroup per series, steps_per_lane 4 or 8, chunk
+                               workgroup per series, steps_per_lane 2, 4 or 8, chunk
                                <= 2048; TVI_VANDERPOL and TVI_ROBERTSON with
                                TVI_F64 storage, backward Euler, analytic Jacobian,
                                zero or extrapolated start, the forward pass and

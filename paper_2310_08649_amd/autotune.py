@@ -21,7 +21,7 @@ _CACHE_PATH = os.environ.get("TVI_CACHE", os.path.join(os.path.expanduser("~"), 
 _lock = threading.Lock()
 
 
-# models with chunks over 2 or 4 waves (128 or 256 lanes, 4 or 8 steps per lane; double storage)
+# models with chunks over 2 or 4 waves (128 or 256 lanes, 2, 4 or 8 steps per lane; double storage)
 WIDE_KINDS = ("robertson", "vanderpol")
 
 
@@ -32,7 +32,7 @@ def tilings(chunk, wide=False):
         return [(1, 1)]
     out = []
     for T in (1, 2, 4, 8):
-        for S in (4, 8, 16, 32, 64) + ((128, 256) if wide and T >= 4 else ()):
+        for S in (4, 8, 16, 32, 64) + ((128, 256) if wide and T >= 2 else ()):
             if S * T >= chunk and S * T < 2 * max(chunk, 4):
                 out.append((S, T))
     if not out and chunk <= 8 * 64:

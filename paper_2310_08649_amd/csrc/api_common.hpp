@@ -63,7 +63,7 @@ inline tvi_status resolve_tiling(const tvi_options *o, int &S, int &T)
         S = o->lanes;
         T = o->steps_per_lane;
         const bool one_wave = (S == 1 || pow2_in(S, 4, kWave)) && pow2_in(T, 1, 8);
-        const bool waves = pow2_in(S, 2 * kWave, kMaxWaves * kWave) && pow2_in(T, 4, 8);
+        const bool waves = pow2_in(S, 2 * kWave, kMaxWaves * kWave) && pow2_in(T, 2, 8);
         if (!one_wave && !waves) return TVI_EINVAL;
     }
     if (o->chunk > kMaxRegisterChunk || (int64_t)S * T < o->chunk) return TVI_EINVAL;

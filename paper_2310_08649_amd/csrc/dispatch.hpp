@@ -158,7 +158,7 @@ tvi_status launch_solver(int pass, const SolveArgs<IO> &a, int S, int T, hipStre
 // One entry per model family, defined in its own translation unit.
 tvi_status launch_vanderpol(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
 tvi_status launch_robertson(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
-// chunks over 2 or 4 waves (S = 128, 256; T = 4, 8), csrc/model_{vanderpol,robertson}_wide.hip;
+// chunks over 2 or 4 waves (S = 128, 256; T = 2, 4, 8), csrc/model_{vanderpol,robertson}_wide.hip;
 // g_div (stored-trajectory adjoint only, may be null): device scalar dividing every entry of g
 tvi_status launch_vanderpol_wide(int pass, int dtype, const void *args, int S, int T, hipStream_t stream,
                                  const double *g_div = nullptr);

@@ -424,7 +424,7 @@ struct WideNewton {
 };
 
 template <class Model, class IO, int W, int T>
-__global__ __launch_bounds__(W *kWave) __attribute__((amdgpu_waves_per_eu(T == 4 ? 2 : 1))) void forward_kernel(SolveArgs<IO> a)
+__global__ __launch_bounds__(W *kWave) __attribute__((amdgpu_waves_per_eu(T <= 4 ? 2 : 1))) void forward_kernel(SolveArgs<IO> a)
 {
     constexpr int n = Model::N;
     __shared__ Xchg<W, n> X;
@@ -586,8 +586,10 @@ tvi_status launch(int pass, const SolveArgs<IO> &a, int S, int T, hipStream_t st
             return TVI_EUNSUPPORTED;                                                                             \
         return hipGetLastError() == hipSuccess ? TVI_OK : TVI_EHIP;                                              \
     }
+    TVI_WIDE_CASE(2, 2)
     TVI_WIDE_CASE(2, 4)
     TVI_WIDE_CASE(2, 8)
+    TVI_WIDE_CASE(4, 2)
     TVI_WIDE_CASE(4, 4)
     TVI_WIDE_CASE(4, 8)
 #undef TVI_WIDE_CASE

@@ -1,4 +1,4 @@
-"""Chunks over 2 or 4 waves per series (128 or 256 lanes, 4 or 8 steps per
+"""Chunks over 2 or 4 waves per series (128 or 256 lanes, 2, 4 or 8 steps per
 lane, chunks up to 2048) against the oracle: ragged Robertson and Van der Pol
 trajectories, the adjoint from the stored trajectory, edge cases (empty and
 one-step series, series shorter than a lane's share, halving), and the full
@@ -13,7 +13,8 @@ from tests.helpers import PARITY_TOL, series_rel_err
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-TILINGS = [(1024, 128, 8), (1024, 256, 4), (2048, 256, 8), (700, 128, 8), (512, 128, 4)]
+TILINGS = [(1024, 128, 8), (1024, 256, 4), (2048, 256, 8), (700, 128, 8), (512, 128, 4), (256, 128, 2),
+           (512, 256, 2), (300, 256, 2)]
 
 
 @pytest.fixture(scope="module")
@@ -82,7 +83,7 @@ def test_wide_robertson_ragged_forward_and_adjoint(tvi, C, S, T):
         assert err.max() <= 1e-10, err.max()
 
 
-@pytest.mark.parametrize("C,S,T", [(1024, 128, 8), (2048, 256, 8), (1024, 256, 4)])
+@pytest.mark.parametrize("C,S,T", [(1024, 128, 8), (2048, 256, 8), (1024, 256, 4), (512, 256, 2)])
 def test_wide_vanderpol_forward_and_adjoint(tvi, C, S, T):
     """Uniform grid, mu up to 30, series of 3000 steps: chunks with a ragged
     tail, both starts."""
@@ -163,7 +164,7 @@ def test_wide_full_size_robertson(tvi):
 
 
 @pytest.mark.parametrize("kind,C,S,T", [("robertson", 1024, 128, 8), ("robertson", 512, 128, 4),
-                                        ("vanderpol", 1024, 256, 4)])
+                                        ("robertson", 512, 256, 2), ("vanderpol", 1024, 256, 4)])
 def test_wide_fused_frobenius_gradient_equals_the_formed_one(tvi, kind, C, S, T):
     """The stored-trajectory adjoint over several waves reading g = y / L from
     the trajectory (tvi_options.g_divisor; the loss kernel computes L alone)
