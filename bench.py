@@ -349,7 +349,8 @@ def run_headline(args, dev, stream):
     if mode == "recompute":
         fwd_bytes += 3 * 8 * int(np.sum(chunks_b + 1))     # checkpoints
         adj_flops += fwd_flops                             # the adjoint re-solves every chunk
-    loss_bytes = points * (1 if fused else 2) * 3 * 8     # read y (and write g)
+    # fused: L from the forward pass's per-series sums (read B doubles); else read y, write g
+    loss_bytes = B * 8 if fused else points * 2 * 3 * 8
     kern = {
         "forward": {"kernel": fwd_name, "flops": fwd_flops, "bytes": fwd_bytes, **stages["forward"]},
         "adjoint": {"kernel": adj_name, "flops": adj_flops, "bytes": adj_bytes, **stages["adjoint"]},
@@ -374,7 +375,8 @@ def run_headline(args, dev, stream):
                     "y0=(1,0,0) s_i=10^U(log 0.5, log 2) f64 tol=(1e-8,1e-6) fwd + Frobenius-loss gradient + "
                     "adjoint (dL/dp, dL/dy0) in one captured graph, longest first",
         "chunk": C, "lanes": S, "steps_per_lane": T, "init": init, "max_newton_chunk": cap, "adjoint_states": mode,
-        "gradient": "g = y / L read by the adjoint" if fused else "g formed by the loss kernel", "series": B,
+        "gradient": ("g = y / L read by the adjoint, L from the forward pass's per-series sums" if fused
+                     else "g formed by the loss kernel"), "series": B,
         "series_steps": total, "series_failed": int((~ok).sum()), "series_steps_counted": good_steps,
         "newton_corrections": int(it.sum())}, "roofline": roofline, "peak_device_memory_bytes": peak_mem}
     del cs

@@ -244,6 +244,15 @@ typedef struct {
                                   the same fixed point (the register and wide
                                   solvers; the neural ODE and the block solver
                                   ignore it)                                       */
+    double *series_sumsq;      /* forward: NULL, or [B] (device, written): each
+                                  series' sum of squares of its states y_0 .. y_N as
+                                  they are committed (a failed series: those before
+                                  its failure), summed in a fixed order.  The
+                                  Frobenius loss then needs no pass over the
+                                  trajectory (tvi_loss_from_sums).  The forward
+                                  pass over several waves only (lanes 128 or 256,
+                                  Robertson and Van der Pol, TVI_F64);
+                                  TVI_EUNSUPPORTED elsewhere                        */
 } tvi_options;
 
 /* Fills `opt` with the defaults: chunk 64, tol_a 1e-8, tol_r 1e-6 (Section 2.3),
@@ -413,6 +422,17 @@ size_t tvi_loss_workspace_bytes(void);
 tvi_status tvi_loss_grad(int32_t kind, int32_t dtype, int64_t points, int32_t n, const void *y,
                          const uint8_t *observed, int64_t n_observed, void *g, double *loss, void *workspace,
                          size_t workspace_bytes, void *stream);
+
+/*
+ * tvi_loss_from_sums -- the Frobenius loss L = sqrt(sum_b sums[b]) of the
+ * timing loss (Section 5.2) from per-series sums of squares (sums [B], device,
+ * as tvi_options.series_sumsq writes them), summed in a fixed order; loss: one
+ * double (device).  With it a captured step needs no pass over the trajectory
+ * before the adjoint reads g = y / L (tvi_options.g_divisor = loss).  Enqueued
+ * on `stream` without host synchronisation; TVI_EINVAL for B < 1 or NULL
+ * pointers.
+ */
+tvi_status tvi_loss_from_sums(const double *sums, int64_t B, double *loss, void *stream);
 
 /*
  * Learned chunk predictor: x -> GELU(W1 x + b1) -> GELU(W2 . + b2) -> W3 . + b3,

@@ -208,6 +208,7 @@ void tvi_default_options(tvi_options *opt)
     opt->obs_idx = nullptr;
     opt->n_obs = 0;
     opt->max_newton_chunk = 0;
+    opt->series_sumsq = nullptr;
 }
 
 const char *tvi_status_str(int32_t s)
@@ -278,6 +279,8 @@ tvi_status tvi_solve_forward(const tvi_model *model, const tvi_options *opt, int
     if (B == 0) return TVI_OK;
     if (!times || !y0 || !params || !status || (!y_out && !ckpt)) return TVI_EINVAL;
     int S = 0, T = 0;
+    // per-series sums of squares: the forward pass over several waves only
+    if (opt->series_sumsq && (is_block(model) || model->kind == TVI_MLP)) return TVI_EUNSUPPORTED;
     if (is_block(model)) {
         if ((e = check_block(model, opt)) != TVI_OK) return e;
         SolveArgs<double> a = make_args<double>(opt, B, N, offsets, times, y0, params, model->params_shared);
@@ -292,6 +295,21 @@ tvi_status tvi_solve_forward(const tvi_model *model, const tvi_options *opt, int
             return TVI_EUNSUPPORTED;
     } else if ((e = resolve_tiling(opt, S, T)) != TVI_OK) {
         return e;
+    }
+    if (opt->series_sumsq) {
+        const bool wide_kind = model->kind == TVI_ROBERTSON || model->kind == TVI_VANDERPOL;
+        if (S <= kWave || !wide_kind || model->dtype != TVI_F64 || opt->jacobian != TVI_JACOBIAN_ANALYTIC)
+            return TVI_EUNSUPPORTED;
+        SolveArgs<double> a = make_args<double>(opt, B, N, offsets, times, y0, params, model->params_shared);
+        a.y = static_cast<double *>(y_out);
+        a.ckpt = static_cast<double *>(ckpt);
+        a.status = status;
+        a.iters = iters;
+        WideExtras x;
+        x.sumsq = opt->series_sumsq;
+        const hipStream_t st = static_cast<hipStream_t>(stream);
+        return model->kind == TVI_ROBERTSON ? launch_robertson_wide(PASS_FORWARD, TVI_F64, &a, S, T, st, x)
+                                            : launch_vanderpol_wide(PASS_FORWARD, TVI_F64, &a, S, T, st, x);
     } else if (opt->init == TVI_INIT_PREDICTOR && (S < 4 || T * model->n > kPredictorMaxTN)) {
         return TVI_EUNSUPPORTED;  // the network is shared by a segment's lanes; register budget
     }
@@ -405,8 +423,10 @@ tvi_status tvi_solve_adjoint(const tvi_model *model, const tvi_options *opt, int
         a.dLdy0 = static_cast<double *>(dLdy0);
         a.status = status;
         const hipStream_t st = static_cast<hipStream_t>(stream);
-        return model->kind == TVI_ROBERTSON ? launch_robertson_wide(PASS_ADJOINT, TVI_F64, &a, S, T, st, gi.div)
-                                            : launch_vanderpol_wide(PASS_ADJOINT, TVI_F64, &a, S, T, st, gi.div);
+        WideExtras x;
+        x.g_div = gi.div;
+        return model->kind == TVI_ROBERTSON ? launch_robertson_wide(PASS_ADJOINT, TVI_F64, &a, S, T, st, x)
+                                            : launch_vanderpol_wide(PASS_ADJOINT, TVI_F64, &a, S, T, st, x);
     }
     if (recompute && opt->init == TVI_INIT_PREDICTOR && (S < 4 || T * model->n > kPredictorMaxTN))
         return TVI_EUNSUPPORTED;
@@ -467,6 +487,12 @@ tvi_status tvi_loss_grad(int32_t kind, int32_t dtype, int64_t points, int32_t n,
     }
     return launch_loss(kind, dtype, points * n, y, kind == TVI_LOSS_MEAN_SQUARE ? observed : nullptr, n, scale, g,
                        loss, static_cast<double *>(workspace), static_cast<hipStream_t>(stream));
+}
+
+tvi_status tvi_loss_from_sums(const double *sums, int64_t B, double *loss, void *stream)
+{
+    if (!sums || !loss || B < 1) return TVI_EINVAL;
+    return launch_loss_from_sums(sums, B, loss, static_cast<hipStream_t>(stream));
 }
 
 static bool pred_ok(const tvi_predictor *p)

@@ -132,6 +132,7 @@ inline tvi_status check_user_options(const tvi_options *o)
     if (o->init == TVI_INIT_PREDICTOR || o->scheme != TVI_BACKWARD_EULER || o->reference_residual != 0)
         return TVI_EUNSUPPORTED;
     if (o->g_divisor || o->obs_idx) return TVI_EUNSUPPORTED;  // register solver: plain g only
+    if (o->series_sumsq) return TVI_EUNSUPPORTED;               // the wide forward only
     return TVI_OK;
 }
 

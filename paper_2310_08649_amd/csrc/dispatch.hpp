@@ -158,12 +158,15 @@ tvi_status launch_solver(int pass, const SolveArgs<IO> &a, int S, int T, hipStre
 // One entry per model family, defined in its own translation unit.
 tvi_status launch_vanderpol(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
 tvi_status launch_robertson(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
-// chunks over 2 or 4 waves (S = 128, 256; T = 2, 4, 8), csrc/model_{vanderpol,robertson}_wide.hip;
-// g_div (stored-trajectory adjoint only, may be null): device scalar dividing every entry of g
+// chunks over 2 or 4 waves (S = 128, 256; T = 2, 4, 8), csrc/model_{vanderpol,robertson}_wide.hip
+struct WideExtras {
+    const double *g_div = nullptr;  // stored-trajectory adjoint: device scalar dividing every entry of g
+    double *sumsq = nullptr;        // forward: [B] per-series sums of squares of the stored states
+};
 tvi_status launch_vanderpol_wide(int pass, int dtype, const void *args, int S, int T, hipStream_t stream,
-                                 const double *g_div = nullptr);
+                                 const WideExtras &x = WideExtras{});
 tvi_status launch_robertson_wide(int pass, int dtype, const void *args, int S, int T, hipStream_t stream,
-                                 const double *g_div = nullptr);
+                                 const WideExtras &x = WideExtras{});
 tvi_status launch_linear2(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
 tvi_status launch_linear3(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
 tvi_status launch_linear4(int pass, int dtype, const void *args, int S, int T, hipStream_t stream);
@@ -189,6 +192,7 @@ tvi_status launch_mlp_eval(int dtype, int64_t M, const void *states, const void 
 tvi_status launch_eval(int kind, int n, int dtype, int64_t M, const void *states, const void *times,
                        const void *params, int shared, void *f, void *J, hipStream_t stream);
 tvi_status launch_order(const int64_t *offsets, int64_t B, int32_t *order, hipStream_t stream);
+tvi_status launch_loss_from_sums(const double *sums, int64_t B, double *loss, hipStream_t stream);
 tvi_status launch_loss(int kind, int dtype, int64_t count, const void *y, const uint8_t *observed,
                        int64_t point_stride, double scale, void *g, double *loss, double *partial,
                        hipStream_t stream);

@@ -85,6 +85,22 @@ static tvi_status loss_launch(int kind, int64_t count, const IO *y, const uint8_
     return hipGetLastError() == hipSuccess ? TVI_OK : TVI_EHIP;
 }
 
+// The Frobenius loss from per-series sums of squares (one workgroup, fixed order).
+__global__ __launch_bounds__(kLossThreads) void sums_finish_kernel(const double *sums, int64_t B, double *loss)
+{
+    __shared__ double sh[kLossThreads];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < B; i += kLossThreads) acc += sums[i];
+    const double s = block_sum<kLossThreads>(acc, sh);
+    if (threadIdx.x == 0) loss[0] = sqrt(s);
+}
+
+tvi_status launch_loss_from_sums(const double *sums, int64_t B, double *loss, hipStream_t stream)
+{
+    hipLaunchKernelGGL(sums_finish_kernel, dim3(1), dim3(kLossThreads), 0, stream, sums, B, loss);
+    return hipGetLastError() == hipSuccess ? TVI_OK : TVI_EHIP;
+}
+
 tvi_status launch_loss(int kind, int dtype, int64_t count, const void *y, const uint8_t *observed,
                        int64_t point_stride, double scale, void *g, double *loss, double *partial,
                        hipStream_t stream)

@@ -5,10 +5,10 @@
 namespace tvi {
 
 tvi_status launch_vanderpol_wide(int pass, int dtype, const void *args, int S, int T, hipStream_t stream,
-                                 const double *g_div)
+                                 const WideExtras &x)
 {
     if (dtype != TVI_F64) return TVI_EUNSUPPORTED;
-    return wide::launch<VanDerPol, double>(pass, *static_cast<const SolveArgs<double> *>(args), S, T, stream, g_div);
+    return wide::launch<VanDerPol, double>(pass, *static_cast<const SolveArgs<double> *>(args), S, T, stream, x);
 }
 
 } // namespace tvi

@@ -26,6 +26,7 @@
 // start, the forward pass and the adjoint from the stored trajectory.
 #pragma once
 
+#include "dispatch.hpp"
 #include "solver.hpp"
 
 namespace tvi {
@@ -203,6 +204,7 @@ struct WideNewton {
     double dy[T][n];
     double tt[T], hh[T];
     double t_s;
+    double sq;  // the lane's sum of squares of the states it stored
 
     __device__ __forceinline__ bool owned(int q, int i) const { return active && (q * T + i + 1 <= m); }
 
@@ -322,6 +324,8 @@ struct WideNewton {
 #pragma unroll
                         for (int k = 0; k < n; ++k) v[k] = ys[k] + dy[i][k];
                         sink.put(s + q * T + i + 1, v);
+#pragma unroll
+                        for (int k = 0; k < n; ++k) sq = fma(v[k], v[k], sq);
                     }
                 }
 #pragma unroll
@@ -424,7 +428,8 @@ struct WideNewton {
 };
 
 template <class Model, class IO, int W, int T>
-__global__ __launch_bounds__(W *kWave) __attribute__((amdgpu_waves_per_eu(T <= 4 ? 2 : 1))) void forward_kernel(SolveArgs<IO> a)
+__global__ __launch_bounds__(W *kWave) __attribute__((amdgpu_waves_per_eu(T <= 4 ? 2 : 1))) void forward_kernel(
+    SolveArgs<IO> a, double *sumsq)
 {
     constexpr int n = Model::N;
     __shared__ Xchg<W, n> X;
@@ -439,9 +444,12 @@ __global__ __launch_bounds__(W *kWave) __attribute__((amdgpu_waves_per_eu(T <= 4
     for (int k = 0; k < n; ++k) cn.ys[k] = ld(a.y0 + sv.b * n + k);
     TrajectorySink<IO, n> sink{a.y ? a.y + sv.p0 * n : nullptr, a.ckpt ? a.ckpt + sv.b * a.K * n : nullptr, sv.Nb,
                                a.K, a.chunk};
+    cn.sq = 0.0;
     if (q == 0) {
         sink.put(0, cn.ys);
         sink.boundary(0, cn.ys, 0);
+#pragma unroll
+        for (int k = 0; k < n; ++k) cn.sq = fma(cn.ys[k], cn.ys[k], cn.sq);
     }
     cn.s = 0;
     cn.s_end = sv.Nb;
@@ -453,6 +461,10 @@ __global__ __launch_bounds__(W *kWave) __attribute__((amdgpu_waves_per_eu(T <= 4
     if (q == 0) {
         a.status[sv.b] = cn.status;
         if (a.iters) a.iters[sv.b] = cn.total;
+    }
+    if (sumsq) {  // workgroup-uniform: every thread meets block_sum's barriers
+        const double t = block_sum(X, cn.sq);
+        if (q == 0) sumsq[sv.b] = t;
     }
 }
 
@@ -567,10 +579,9 @@ __global__ __launch_bounds__(W *kWave) void adjoint_kernel(SolveArgs<IO> a, cons
 }
 
 // Forward (pass 0) and stored-trajectory adjoint (pass 1) for S = 64 W lanes;
-// g_div (adjoint only, may be null): the device scalar dividing g.
+// x.g_div (adjoint) and x.sumsq (forward) may be null.
 template <class Model, class IO>
-tvi_status launch(int pass, const SolveArgs<IO> &a, int S, int T, hipStream_t stream,
-                  const double *g_div = nullptr)
+tvi_status launch(int pass, const SolveArgs<IO> &a, int S, int T, hipStream_t stream, const WideExtras &x)
 {
     if (a.scheme != 0 || a.init == INIT_PREDICTOR || a.zero_ref != 0) return TVI_EUNSUPPORTED;
     if (a.B > 0x7fffffffLL) return TVI_EINVAL;
@@ -578,10 +589,11 @@ tvi_status launch(int pass, const SolveArgs<IO> &a, int S, int T, hipStream_t st
 #define TVI_WIDE_CASE(WW, TT)                                                                                    \
     if (S == (WW) * kWave && T == (TT)) {                                                                        \
         if (pass == PASS_FORWARD)                                                                                \
-            hipLaunchKernelGGL((forward_kernel<Model, IO, WW, TT>), grid, dim3((WW) * kWave), 0, stream, a);     \
+            hipLaunchKernelGGL((forward_kernel<Model, IO, WW, TT>), grid, dim3((WW) * kWave), 0, stream, a,  \
+                               x.sumsq);                                                                 \
         else if (pass == PASS_ADJOINT)                                                                           \
             hipLaunchKernelGGL((adjoint_kernel<Model, IO, WW, TT>), grid, dim3((WW) * kWave), 0, stream, a,  \
-                               g_div);                                                                   \
+                               x.g_div);                                                                 \
         else                                                                                                     \
             return TVI_EUNSUPPORTED;                                                                             \
         return hipGetLastError() == hipSuccess ? TVI_OK : TVI_EHIP;                                              \

@@ -74,6 +74,9 @@ class CapturedStep:
                                "stored-trajectory adjoint over several waves (lanes 128 or 256)")
         self.fused = fused
         self.g = None if fused else torch.empty_like(self.y)
+        # fused over several waves: the forward pass also sums each series' squares, so
+        # the loss needs no pass over the trajectory (tvi_loss_from_sums)
+        self.sums = torch.empty(B, dtype=torch.float64, device=dev) if fused and wide_stored else None
         self.observed = None if observed is None else observed.to(device=dev, dtype=torch.uint8).contiguous()
         self.n_observed = int(self.observed.sum().item()) if self.observed is not None else 0
         self.loss_ws = torch.empty(max(1, lib.tvi_loss_workspace_bytes()), dtype=torch.uint8, device=dev)
@@ -101,15 +104,22 @@ class CapturedStep:
         """The forward solve alone (current stream)."""
         lib = tvi.load()
         P = tvi._ptr
+        self.opt.series_sumsq = self.sums.data_ptr() if self.sums is not None else None
         tvi._check(lib.tvi_solve_forward(ctypes.byref(self.model), ctypes.byref(self.opt), self.B, self.N,
                                          P(self.offsets), P(self.times), P(self.y0), P(self.params), P(self.y),
                                          P(self.ckpt), P(self.status_fwd), P(self.iters), tvi._stream()),
                    "tvi_solve_forward")
+        self.opt.series_sumsq = None
 
     def launch_loss(self):
-        """The loss value and its gradient g = dL/dy alone (current stream)."""
+        """The loss value and its gradient g = dL/dy alone (current stream); fused over
+        several waves, the loss alone from the forward pass's per-series sums."""
         lib = tvi.load()
         P = tvi._ptr
+        if self.sums is not None:
+            tvi._check(lib.tvi_loss_from_sums(P(self.sums), self.B, P(self.loss), tvi._stream()),
+                       "tvi_loss_from_sums")
+            return
         points = self.y.numel() // self.n
         tvi._check(lib.tvi_loss_grad(self.loss_kind, self.model.dtype, points, self.n, P(self.y), P(self.observed),
                                      self.n_observed, P(self.g), P(self.loss), P(self.loss_ws),

@@ -51,7 +51,8 @@ class Options(ctypes.Structure):
                 ("jacobian", ctypes.c_int32),
                 ("reference_residual", ctypes.c_int32), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t), ("g_divisor", ctypes.c_void_p),
-                ("obs_idx", ctypes.c_void_p), ("n_obs", ctypes.c_int32), ("max_newton_chunk", ctypes.c_int32)]
+                ("obs_idx", ctypes.c_void_p), ("n_obs", ctypes.c_int32), ("max_newton_chunk", ctypes.c_int32),
+                ("series_sumsq", ctypes.c_void_p)]
 
 
 _lib = None
@@ -92,6 +93,8 @@ def load():
         lib.tvi_loss_workspace_bytes.restype = sz
         lib.tvi_loss_grad.argtypes = [i32, i32, i64, i32, P, P, i64, P, P, P, sz, P]
         lib.tvi_loss_grad.restype = i32
+        lib.tvi_loss_from_sums.argtypes = [P, i64, P, P]
+        lib.tvi_loss_from_sums.restype = i32
         _lib = lib
     return _lib
 
@@ -228,10 +231,12 @@ def _geometry(y0, times, offsets, n_max=None):
 def solve_forward(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e-6), max_newton=50, lanes=0,
                   steps_per_lane=0, init="zero", halving=True, checkpoints=False, y_out=None, iters=True,
                   predictor=None, order=None, scheme="backward_euler", jacobian="analytic",
-                  n_max=None, reference="first", max_newton_chunk=0):
+                  n_max=None, reference="first", max_newton_chunk=0, sumsq=None):
     """Chunked backward Euler (or forward Euler, ``scheme="forward_euler"``).  Returns ``(y, status, iters, ckpt)`` (device tensors;
     ``iters`` and ``ckpt`` may be None).  Asynchronous: nothing is synchronised, except that ragged series
-    without ``n_max`` (the longest series' step count) read it from ``offsets``."""
+    without ``n_max`` (the longest series' step count) read it from ``offsets``.  ``sumsq``: a float64
+    [B] device tensor receiving each series' sum of squares of its states (the forward pass over
+    several waves only)."""
     dt = y0.dtype
     y0 = _dev(y0, dt, "y0")
     times = _dev(times, dt, "times")
@@ -256,6 +261,10 @@ def solve_forward(kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e
         ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
         opt.workspace = ws.data_ptr()
         opt.workspace_bytes = wsb
+    if sumsq is not None:
+        if sumsq.dtype != torch.float64 or sumsq.shape != (B,) or not sumsq.is_contiguous():
+            raise TviError("sumsq must be a contiguous float64 [B] tensor")
+        opt.series_sumsq = _dev(sumsq, torch.float64, "sumsq").data_ptr()
     _check(load().tvi_solve_forward(ctypes.byref(model), ctypes.byref(opt), B, N, _ptr(offsets), _ptr(times),
                                     _ptr(y0), _ptr(params), _ptr(y), _ptr(ck), _ptr(status), _ptr(it), _stream()),
            "tvi_solve_forward")
@@ -463,3 +472,11 @@ class UserModel:
                          _ptr(g), _ptr(dLdp), _ptr(dLdy0), _ptr(status), _ptr(ws), wsb, _stream()),
                self.name + "_solve_adjoint")
         return dLdp, dLdy0, status
+
+
+def loss_from_sums(sums, out=None):
+    """The Frobenius loss sqrt(sum of per-series sums of squares) on the device (one float64)."""
+    sums = _dev(sums, torch.float64, "sums")
+    loss = out if out is not None else torch.empty(1, dtype=torch.float64, device=sums.device)
+    _check(load().tvi_loss_from_sums(_ptr(sums), sums.shape[0], _ptr(loss), _stream()), "tvi_loss_from_sums")
+    return loss

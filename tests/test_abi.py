@@ -352,6 +352,30 @@ def test_register_solver_refuses_divided_or_observed_gradients(lib):
     assert adj("robertson", 3, chunk=512, lanes=64, steps_per_lane=8) == -4   # one wave
 
 
+def test_series_sums_are_checked(lib):
+    """Per-series sums of squares (tvi_options.series_sumsq) come from the
+    forward pass over several waves only; the loss from sums checks its
+    arguments; both before any HIP call."""
+    from paper_2310_08649_amd import tvi
+    f = _fake()
+
+    def fwd(kind, n, dtype=tvi.F64, **kw):
+        m = tvi.Model(tvi.KINDS[kind], n, dtype, 1 if kind == "mlp" else 0, 64)
+        o = tvi.make_options(**kw)
+        o.series_sumsq = 0x1000
+        return lib.tvi_solve_forward(ctypes.byref(m), ctypes.byref(o), 4, 10, None, f, f, f, f, None, f, None, None)
+
+    wide = dict(chunk=1024, lanes=128, steps_per_lane=8)
+    assert fwd("robertson", 3, chunk=512, lanes=64, steps_per_lane=8) == -4     # one wave
+    assert fwd("linear", 2, **wide) == -4
+    assert fwd("vanderpol", 2, dtype=tvi.F32, **wide) == -4
+    assert fwd("robertson", 3, jacobian="forward_ad", **wide) == -4
+    assert fwd("mlp", 8, dtype=tvi.F32, chunk=100) == -4
+    assert lib.tvi_loss_from_sums(None, 4, f, None) == -1
+    assert lib.tvi_loss_from_sums(f, 0, f, None) == -1
+    assert lib.tvi_loss_from_sums(f, 4, None, None) == -1
+
+
 def test_tilings_over_several_waves_are_checked(lib):
     """128 or 256 lanes (2 or 4 waves) take 2, 4 or 8 steps per lane and chunks up
     to 2048; other combinations, and these tilings for models or options the

@@ -181,7 +181,7 @@ def test_wide_fused_frobenius_gradient_equals_the_formed_one(tvi, kind, C, S, T)
         off = None
         extra = {}
     args = (dev(w["y0"]), dev(w["times"]), dev(w["params"]))
-    runs = {}
+    runs, losses = {}, {}
     for fused in (False, True):
         print("%s fused=%s chunk=%d lanes=%d steps_per_lane=%d" % (kind, fused, C, S, T), flush=True)
         step = graph.CapturedStep(kind, *args, chunk=C, lanes=S, steps_per_lane=T, tol=PARITY_TOL, loss="frobenius",
@@ -195,9 +195,13 @@ def test_wide_fused_frobenius_gradient_equals_the_formed_one(tvi, kind, C, S, T)
             assert torch.equal(step.dLdp, first[0]) and torch.equal(step.dLdy0, first[1])
         assert (step.status_fwd.cpu() == 0).all() and (step.status_adj.cpu() == 0).all()
         runs[fused] = (host(first[0]), host(first[1]))
+        losses[fused] = float(step.loss.item())
         yh = host(step.y)
     for a, b in zip(runs[True], runs[False]):
         assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max(), kind
+    # the loss from the forward pass's per-series sums against the pass over the trajectory
+    assert abs(losses[True] - losses[False]) <= 1e-14 * losses[False]
+    assert abs(losses[True] - np.sqrt(np.sum(yh ** 2))) <= 1e-13 * losses[False]
     # the oracle's adjoint on the GPU trajectory with g = y / ||y||_F
     g = yh / np.sqrt(np.sum(yh ** 2))
     op, oy0, _ = oracle.adjoint(kind, yh, w["times"], w["params"], g, offsets=off)
@@ -213,3 +217,24 @@ def test_wide_fused_gradient_needs_the_stored_trajectory(tvi):
     with pytest.raises(tvi.TviError):
         graph.CapturedStep("robertson", *args, offsets=dev(w["offsets"], torch.int64), chunk=1024, lanes=128,
                            steps_per_lane=8, loss="frobenius", recompute=True, fused=True)
+
+
+@pytest.mark.parametrize("C,S,T", [(1024, 128, 8), (512, 256, 2)])
+def test_wide_forward_series_sums(tvi, C, S, T):
+    """Each series' sum of squares of its states, from the forward pass over
+    several waves (tvi_options.series_sumsq), against numpy's on the returned
+    trajectory, ragged series (empty, one-step) included; the loss from the sums
+    is their total's square root."""
+    w = _ragged_robertson()
+    off = w["offsets"]
+    offd = dev(off, torch.int64)
+    sums = torch.full((len(off) - 1,), float("nan"), dtype=torch.float64, device="cuda")
+    print("robertson sums chunk=%d lanes=%d steps_per_lane=%d" % (C, S, T), flush=True)
+    y, st, _, _ = tvi.solve_forward("robertson", dev(w["y0"]), dev(w["times"]), dev(w["params"]), offsets=offd,
+                                    chunk=C, lanes=S, steps_per_lane=T, tol=PARITY_TOL, sumsq=sums)
+    yh, st, sh = host(y), host(st), host(sums)
+    assert (st == 0).all()
+    ref = np.array([np.sum(yh[off[b]:off[b + 1]] ** 2) for b in range(len(off) - 1)])
+    assert (np.abs(sh - ref) <= 1e-14 * ref * np.log2(off[1:] - off[:-1] + 2)).all()
+    L = host(tvi.loss_from_sums(sums))[0]
+    assert abs(L - np.sqrt(ref.sum())) <= 1e-14 * L
