@@ -282,6 +282,8 @@ def run_headline(args, dev, stream):
         C, S, T, init, mode = parts[:5]
         best = {"chunk": int(C), "lanes": int(S), "steps_per_lane": int(T), "init": init, "adjoint": mode,
                 "max_newton_chunk": int(parts[5]) if len(parts) > 5 else 0}
+        if len(parts) > 8:
+            best["adjoint_tiling"] = tuple(int(v) for v in parts[6:9])
         table = None
         log("configuration given: %s" % args.config)
     else:
@@ -303,19 +305,36 @@ def run_headline(args, dev, stream):
             best["max_newton_chunk"], best["ms"]))
     C, S, T, init, mode = best["chunk"], best["lanes"], best["steps_per_lane"], best["init"], best["adjoint"]
     cap = best.get("max_newton_chunk", 0)
+    adj_table = None
+    if mode == "stored" and "adjoint_tiling" not in best:
+        # the stored-trajectory adjoint is a linear solve: its own chunk and tiling
+        log("autotuning the adjoint's chunk / tiling")
+        y_t, st_t, _, _ = tvi.solve_forward("robertson", y0, times, sp, offsets=off, chunk=C, lanes=S,
+                                            steps_per_lane=T, tol=TIMING_TOL, init=init, max_newton_chunk=cap,
+                                            order=order, n_max=nmax)
+        ra = autotune.tune_adjoint("robertson", times, sp, y_t, y_t, offsets=off, tol=TIMING_TOL, order=order,
+                                   n_max=nmax)
+        ab = ra["best"]
+        best["adjoint_tiling"] = (ab["chunk"], ab["lanes"], ab["steps_per_lane"])
+        adj_table = ra["table"]
+        del y_t, st_t
+        log("adjoint: chunk=%d lanes=%d steps_per_lane=%d (%.3f ms)" % (ab["chunk"], ab["lanes"],
+                                                                      ab["steps_per_lane"], ab["ms"]))
+    aTil = best.get("adjoint_tiling", (C, S, T))
 
-    def fusable(lanes, recompute):
+    def fusable(adj_lanes, recompute):
         # the stored-trajectory adjoint over several waves reads g = y / L from the
         # trajectory (no gradient array is formed: one streaming kernel less)
-        return lanes > 64 and not recompute
+        return adj_lanes > 64 and not recompute
 
-    def capture(chunk, lanes, spl, start, recompute, mnc=0):
+    def capture(chunk, lanes, spl, start, recompute, mnc=0, adj=None):
+        al = adj[1] if adj is not None else lanes
         return graph.CapturedStep("robertson", y0, times, sp, offsets=off, chunk=chunk, lanes=lanes,
                                   steps_per_lane=spl, tol=TIMING_TOL, init=start, loss="frobenius", n_max=nmax,
-                                  recompute=recompute, max_newton_chunk=mnc,
-                                  fused=fusable(lanes, recompute)).capture()
+                                  recompute=recompute, max_newton_chunk=mnc, adjoint_tiling=adj,
+                                  fused=fusable(al, recompute)).capture()
 
-    cs = capture(C, S, T, init, mode == "recompute", cap)
+    cs = capture(C, S, T, init, mode == "recompute", cap, aTil if mode == "stored" else None)
     for _ in range(args.warmup):
         cs.replay()
     torch.cuda.synchronize()
@@ -337,13 +356,14 @@ def run_headline(args, dev, stream):
 
     # ---- per-kernel durations with HIP events on the launch stream (eager launches of the same step)
     stages = time_stages(cs, args.steps, stream)
-    fwd_name, adj_name = kernel_names(S, T, init, mode == "recompute")
+    fwd_name = kernel_names(S, T, init, mode == "recompute")[0]
+    adj_name = kernel_names(aTil[1], aTil[2], init, mode == "recompute")[1]
     chunks_b = np.maximum(1, (lens + C - 1) // C)
     fwd_flops = float(np.sum(it * lens / chunks_b)) * rob_forward_flops_per_step(S, T)
-    adj_flops = float(total) * rob_adjoint_flops_per_step(S, T)
+    adj_flops = float(total) * rob_adjoint_flops_per_step(aTil[1], aTil[2])
     points = int(times.shape[0])
     fwd_bytes = points * (3 * 8 + 8)                      # write y, read t
-    fused = fusable(S, mode == "recompute")
+    fused = fusable(aTil[1], mode == "recompute")
     # read y, g (g is y itself when fused), t; write dL/dp, dL/dy0
     adj_bytes = points * (3 * 8 + (0 if fused else 3 * 8) + 8) + B * 6 * 8
     if mode == "recompute":
@@ -375,6 +395,7 @@ def run_headline(args, dev, stream):
                     "y0=(1,0,0) s_i=10^U(log 0.5, log 2) f64 tol=(1e-8,1e-6) fwd + Frobenius-loss gradient + "
                     "adjoint (dL/dp, dL/dy0) in one captured graph, longest first",
         "chunk": C, "lanes": S, "steps_per_lane": T, "init": init, "max_newton_chunk": cap, "adjoint_states": mode,
+        "adjoint_tiling": list(aTil),
         "gradient": ("g = y / L read by the adjoint, L from the forward pass's per-series sums" if fused
                      else "g formed by the loss kernel"), "series": B,
         "series_steps": total, "series_failed": int((~ok).sum()), "series_steps_counted": good_steps,
@@ -421,6 +442,7 @@ def run_headline(args, dev, stream):
                                                        "max_newton_chunk", "failed", "ms")}
         head["autotune_candidates"] = len(table)
     head["_table"] = table
+    head["_adjoint_table"] = adj_table
     return head, w
 
 
@@ -1096,7 +1118,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="",
-                    help="chunk,lanes,steps_per_lane,init,adjoint (stored | recompute): skip the autotuner")
+                    help="chunk,lanes,steps_per_lane,init,adjoint (stored | recompute)[,cap[,adjoint chunk,"
+                         "lanes,steps_per_lane]]: skip the autotuner")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--extras", default="", help="also run the side measurements and write them to this JSON file")
     ap.add_argument("--only", default="", help="comma-separated side measurements to run (with --extras)")
@@ -1135,10 +1158,13 @@ def main():
     else:
         head, w = run_headline(args, dev, stream)
         table = head.pop("_table")
+        adj_table = head.pop("_adjoint_table")
         out = compose_line(args, head)
 
     if args.extras:
         ext = {"headline_autotune_table": table} if table is not None else {}
+        if head is not None and adj_table is not None:
+            ext["headline_adjoint_autotune_table"] = adj_table
         only = set(filter(None, args.only.split(",")))
         want = lambda name: not only or name in only
         ctx = {"dev": dev, "stream": stream}

@@ -167,3 +167,30 @@ def tune_forward(kind, y0, times, params, offsets=None, tol=(1e-8, 1e-6), chunks
             cache[key] = res
             _store_cache(cache)
     return res
+
+
+def tune_adjoint(kind, times, params, y, g, offsets=None, tol=(1e-8, 1e-6), chunks=(256, 512, 1024, 2048), reps=3,
+                 **kw):
+    """The stored-trajectory adjoint's own chunk and lane tiling.
+
+    The adjoint system is linear (Appendix A): one reduction per chunk, no
+    Newton iteration, so its chunking changes only the rounding order, not
+    the gradient, and it need not match the forward pass's.  Times the adjoint
+    alone (trajectory ``y``, gradient ``g``) for every (C, S, T) candidate,
+    ranks failed series first, then time.  Returns {"best": {chunk, lanes,
+    steps_per_lane, failed, ms}, "table": [...]} (not cached)."""
+    wide = kind in WIDE_KINDS and y.dtype == torch.float64
+    table = []
+    for C in chunks:
+        for S, T in tilings(C, wide):
+            res = {}
+
+            def fn():
+                _, _, sa = tvi.solve_adjoint(kind, times, params, g, y=y, offsets=offsets, chunk=C, lanes=S,
+                                             steps_per_lane=T, tol=tol, **kw)
+                res["sa"] = sa
+            ms = _time(fn, reps)
+            table.append({"chunk": C, "lanes": S, "steps_per_lane": T, "failed": int((res["sa"] != 0).sum().item()),
+                          "ms": ms})
+    best = min(table, key=lambda r: (r["failed"], r["ms"]))
+    return {"best": best, "table": table}

@@ -24,13 +24,16 @@ class CapturedStep:
     """forward -> loss gradient -> adjoint, captured once, replayed many times.
 
     Inputs (y0, times, params, offsets) are the graph's own copies: call
-    ``set_inputs`` to change their values between replays.
+    ``set_inputs`` to change their values between replays.  ``adjoint_tiling``
+    (chunk, lanes, steps_per_lane), with the stored trajectory only: the
+    adjoint's own chunking (its system is linear, so the chunking changes only
+    the rounding order); default the forward pass's.
     """
 
     def __init__(self, kind, y0, times, params, offsets=None, chunk=64, tol=(1e-8, 1e-6), lanes=0, steps_per_lane=0,
                  max_newton=50, init="zero", loss="frobenius", observed=None, n_max=None, recompute=True,
                  longest_first=True, scheme="backward_euler", jacobian="analytic", fused=False,
-                 max_newton_chunk=0):
+                 max_newton_chunk=0, adjoint_tiling=None):
         lib = tvi.load()
         self.kind = kind
         self.recompute = recompute
@@ -54,6 +57,11 @@ class CapturedStep:
         self.order = tvi.order_longest_first(self.offsets) if self.offsets is not None and longest_first else None
         self.opt = tvi.make_options(chunk, tol, max_newton, lanes, steps_per_lane, init, True, order=self.order,
                                     scheme=scheme, jacobian=jacobian, max_newton_chunk=max_newton_chunk)
+        if adjoint_tiling is not None and recompute:
+            raise tvi.TviError("an adjoint tiling of its own needs the stored trajectory")
+        a_chunk, a_lanes, a_spl = adjoint_tiling if adjoint_tiling is not None else (chunk, lanes, steps_per_lane)
+        self.opt_adj = tvi.make_options(a_chunk, tol, max_newton, a_lanes, a_spl, init, True, order=self.order,
+                                        scheme=scheme, jacobian=jacobian, max_newton_chunk=max_newton_chunk)
         P = lib.tvi_param_count(ctypes.byref(self.model))
         K = (N + chunk - 1) // chunk + 1
         self.y = torch.empty(yshape, dtype=dt, device=dev)
@@ -67,16 +75,17 @@ class CapturedStep:
         # reads g = y / L from the trajectory (tvi_options.g_divisor), never forming g
         if fused and self.loss_kind != LOSS["frobenius"]:
             raise tvi.TviError("the fused gradient is the Frobenius loss's (g = y / L)")
-        wide_stored = (kind in ("robertson", "vanderpol") and dt == torch.float64 and not recompute
-                       and lanes > 64 and jacobian == "analytic")
-        if fused and not (kind == "mlp" or tvi.is_block(kind, n) or wide_stored):
+        wide = kind in ("robertson", "vanderpol") and dt == torch.float64 and jacobian == "analytic"
+        wide_fwd = wide and lanes > 64
+        wide_adj = wide and not recompute and a_lanes > 64
+        if fused and not (kind == "mlp" or tvi.is_block(kind, n) or wide_adj):
             raise tvi.TviError("the fused gradient is offered by the neural-ODE and block solvers and by the "
                                "stored-trajectory adjoint over several waves (lanes 128 or 256)")
         self.fused = fused
         self.g = None if fused else torch.empty_like(self.y)
-        # fused over several waves: the forward pass also sums each series' squares, so
-        # the loss needs no pass over the trajectory (tvi_loss_from_sums)
-        self.sums = torch.empty(B, dtype=torch.float64, device=dev) if fused and wide_stored else None
+        # fused with a forward pass over several waves: it also sums each series' squares,
+        # so the loss needs no pass over the trajectory (tvi_loss_from_sums)
+        self.sums = torch.empty(B, dtype=torch.float64, device=dev) if fused and wide_fwd else None
         self.observed = None if observed is None else observed.to(device=dev, dtype=torch.uint8).contiguous()
         self.n_observed = int(self.observed.sum().item()) if self.observed is not None else 0
         self.loss_ws = torch.empty(max(1, lib.tvi_loss_workspace_bytes()), dtype=torch.uint8, device=dev)
@@ -89,7 +98,7 @@ class CapturedStep:
         if fwb:
             self.opt.workspace = self.fws.data_ptr()
             self.opt.workspace_bytes = fwb
-        wsb = lib.tvi_adjoint_workspace_bytes(ctypes.byref(self.model), ctypes.byref(self.opt), B)
+        wsb = lib.tvi_adjoint_workspace_bytes(ctypes.byref(self.model), ctypes.byref(self.opt_adj), B)
         self.ws = torch.empty(max(1, wsb), dtype=torch.uint8, device=dev)
         self.ws_bytes = wsb
         self.graph = None
@@ -134,8 +143,8 @@ class CapturedStep:
         """The adjoint alone (current stream)."""
         lib = tvi.load()
         P = tvi._ptr
-        self.opt.g_divisor = self.loss.data_ptr() if self.fused else None
-        tvi._check(lib.tvi_solve_adjoint(ctypes.byref(self.model), ctypes.byref(self.opt), self.B, self.N,
+        self.opt_adj.g_divisor = self.loss.data_ptr() if self.fused else None
+        tvi._check(lib.tvi_solve_adjoint(ctypes.byref(self.model), ctypes.byref(self.opt_adj), self.B, self.N,
                                          P(self.offsets), P(self.times), P(self.params),
                                          None if self.recompute else P(self.y), P(self.ckpt),
                                          P(self.grad_input), P(self.dLdp), P(self.dLdy0), P(self.status_adj),

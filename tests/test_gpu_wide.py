@@ -238,3 +238,35 @@ def test_wide_forward_series_sums(tvi, C, S, T):
     assert (np.abs(sh - ref) <= 1e-14 * ref * np.log2(off[1:] - off[:-1] + 2)).all()
     L = host(tvi.loss_from_sums(sums))[0]
     assert abs(L - np.sqrt(ref.sum())) <= 1e-14 * L
+
+
+@pytest.mark.parametrize("adj", [(1024, 256, 4), (512, 64, 8), (256, 128, 2)])
+def test_wide_graph_with_an_adjoint_tiling_of_its_own(tvi, adj):
+    """The stored-trajectory adjoint's chunking is its own (its system is
+    linear: chunking changes only the rounding order): a captured step whose
+    adjoint runs another tiling than its forward pass gives the gradients of
+    the step that runs one tiling, to rounding, every replay bitwise equal."""
+    from paper_2310_08649_amd import graph
+    w = _ragged_robertson()
+    offd = dev(w["offsets"], torch.int64)
+    args = (dev(w["y0"]), dev(w["times"]), dev(w["params"]))
+    kw = dict(offsets=offd, chunk=512, lanes=128, steps_per_lane=4, tol=PARITY_TOL, loss="frobenius",
+              recompute=False)
+    print("robertson graph forward 512/128/4, adjoint %s" % (adj,), flush=True)
+    one = graph.CapturedStep("robertson", *args, **kw).capture()
+    one.replay()
+    two = graph.CapturedStep("robertson", *args, adjoint_tiling=adj, fused=adj[1] > 64, **kw).capture()
+    two.replay()
+    torch.cuda.synchronize()
+    first = (two.dLdp.clone(), two.dLdy0.clone())
+    for _ in range(2):
+        two.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(two.dLdp, first[0]) and torch.equal(two.dLdy0, first[1])
+    assert (two.status_adj.cpu() == 0).all() and (one.status_adj.cpu() == 0).all()
+    for a, b in ((two.dLdp, one.dLdp), (two.dLdy0, one.dLdy0)):
+        a, b = host(a), host(b)
+        assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max()
+    with pytest.raises(tvi.TviError):
+        graph.CapturedStep("robertson", *args, offsets=offd, chunk=512, lanes=128, steps_per_lane=4,
+                           recompute=True, adjoint_tiling=adj)
