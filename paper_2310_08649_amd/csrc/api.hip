@@ -295,6 +295,8 @@ tvi_status tvi_solve_forward(const tvi_model *model, const tvi_options *opt, int
             return TVI_EUNSUPPORTED;
     } else if ((e = resolve_tiling(opt, S, T)) != TVI_OK) {
         return e;
+    } else if (opt->init == TVI_INIT_PREDICTOR && (S < 4 || T * model->n > kPredictorMaxTN)) {
+        return TVI_EUNSUPPORTED;  // the network is shared by a segment's lanes; register budget
     }
     if (opt->series_sumsq) {
         const bool wide_kind = model->kind == TVI_ROBERTSON || model->kind == TVI_VANDERPOL;
@@ -310,8 +312,6 @@ tvi_status tvi_solve_forward(const tvi_model *model, const tvi_options *opt, int
         const hipStream_t st = static_cast<hipStream_t>(stream);
         return model->kind == TVI_ROBERTSON ? launch_robertson_wide(PASS_FORWARD, TVI_F64, &a, S, T, st, x)
                                             : launch_vanderpol_wide(PASS_FORWARD, TVI_F64, &a, S, T, st, x);
-    } else if (opt->init == TVI_INIT_PREDICTOR && (S < 4 || T * model->n > kPredictorMaxTN)) {
-        return TVI_EUNSUPPORTED;  // the network is shared by a segment's lanes; register budget
     }
     const hipStream_t st = static_cast<hipStream_t>(stream);
     if (model->dtype == TVI_F64) {
