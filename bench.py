@@ -130,8 +130,12 @@ def measured_traffic(kernel):
     return rec["bytes_per_dispatch"]
 
 
-# Files each solver kernel is built from: its traffic record goes stale when one changes.
-KERNEL_SOURCES = {"Robertson": ["model_robertson.hip", "solver.hpp", "device.hpp", "models.hpp", "dual.hpp",
+# Files each solver kernel is built from: its traffic record goes stale when one changes
+# (the first key found in the kernel's name decides; no key: every source file).
+WIDE_SOURCES = ["wide.hpp", "model_robertson_wide.hip", "model_vanderpol_wide.hip", "solver.hpp", "device.hpp",
+                "models.hpp", "dual.hpp", "dispatch.hpp"]
+KERNEL_SOURCES = {"wide::": WIDE_SOURCES,
+                  "Robertson": ["model_robertson.hip", "solver.hpp", "device.hpp", "models.hpp", "dual.hpp",
                                 "dispatch.hpp"],
                   "VanDerPol": ["model_vanderpol.hip", "solver.hpp", "device.hpp", "models.hpp", "dual.hpp",
                                 "dispatch.hpp"],
@@ -179,6 +183,8 @@ def record_traffic(fetch_path, write_path, copy_bytes):
             table = json.load(f)
     except (OSError, ValueError):
         table = {}
+    # records of earlier runs stay while their kernel's sources still match
+    table = {k: v for k, v in table.items() if v.get("source_hash") == csrc_hash(v.get("sources"))}
     for name in fetch:
         if name not in write or not name.startswith("tvi::"):
             continue
@@ -237,8 +243,9 @@ def kernel_names(S, T, init, recompute):
     """Demangled names of the solver kernels a Robertson step launches."""
     if S > 64:  # chunks over S / 64 waves (wide.hpp)
         W = S // 64
-        return ("tvi::wide::forward_kernel<tvi::Robertson, double, %d, %d>(tvi::SolveArgs<double>)" % (W, T),
-                "tvi::wide::adjoint_kernel<tvi::Robertson, double, %d, %d>(tvi::SolveArgs<double>)" % (W, T))
+        return ("tvi::wide::forward_kernel<tvi::Robertson, double, %d, %d>(tvi::SolveArgs<double>, double*)" % (W, T),
+                "tvi::wide::adjoint_kernel<tvi::Robertson, double, %d, %d>(tvi::SolveArgs<double>, double const*)"
+                % (W, T))
     pred = "true" if init == "predictor" else "false"
     fwd = "tvi::forward_kernel<tvi::Robertson, double, %d, %d, %s, false, false>(tvi::SolveArgs<double>)" % (
         S, T, pred)

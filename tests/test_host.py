@@ -158,8 +158,8 @@ def test_bench_robertson_flop_counts():
     # applied to each lane's composed map (24 flops), no seventh composition
     assert b.rob_forward_flops_per_step(256, 4) == 26 + 24 + 72 + (72 * (3 + 6) + 24) / 4 + 24
     fwd, adj = b.kernel_names(256, 4, "zero", False)
-    assert fwd == "tvi::wide::forward_kernel<tvi::Robertson, double, 4, 4>(tvi::SolveArgs<double>)"
-    assert adj == "tvi::wide::adjoint_kernel<tvi::Robertson, double, 4, 4>(tvi::SolveArgs<double>)"
+    assert fwd == "tvi::wide::forward_kernel<tvi::Robertson, double, 4, 4>(tvi::SolveArgs<double>, double*)"
+    assert adj == "tvi::wide::adjoint_kernel<tvi::Robertson, double, 4, 4>(tvi::SolveArgs<double>, double const*)"
 
 
 def test_bench_traffic_is_reported_only_for_matching_kernel_code(monkeypatch, tmp_path):
