@@ -105,6 +105,12 @@ def _end_to_end(tvi, kind, w, kw, offsets=None, tol=PARITY_TOL):
     g = y / torch.sqrt((y * y).sum())
     dp, dy0, sa = tvi.solve_adjoint(kind, dev(w["times"]), dev(w["params"]), g, y=y, offsets=off, tol=tol, **kw)
     assert (host(sa) == 0).all()
+    _against_oracle_pipeline(kind, w, offsets, host(dp), host(dy0))
+
+
+def _against_oracle_pipeline(kind, w, offsets, dp, dy0):
+    """dL/dp and dL/dy0 of the Frobenius loss against the oracle's forward +
+    adjoint on its own trajectory, gated by the oracle's own sensitivity."""
     def oracle_grad(tol):
         yo, so, _ = oracle.forward(kind, w["y0"], w["times"], w["params"], offsets=offsets, tol=tol)
         assert (so == 0).all()
@@ -119,7 +125,7 @@ def _end_to_end(tvi, kind, w, kw, offsets=None, tol=PARITY_TOL):
     # stopping test moved (1e-12): trajectories that both satisfy the parity
     # tolerance differ in their small components, and the gradient follows
     op2, oy02 = oracle_grad((1e-12, 1e-12))
-    for a, b, b2 in ((host(dp), op, op2), (host(dy0), oy0, oy02)):
+    for a, b, b2 in ((dp, op, op2), (dy0, oy0, oy02)):
         err, sens = rel(a, b), rel(b2, b)
         gate = np.maximum(5e-10, 10.0 * sens)
         print("%s: %d of %d series within 1e-10 end to end, max error %.2e, max oracle sensitivity %.2e"
@@ -133,6 +139,29 @@ def test_robertson_full_size_gradient_end_to_end(tvi):
     off = dev(w["offsets"], torch.int64)
     kw = dict(chunk=512, lanes=64, steps_per_lane=8, order=tvi.order_longest_first(off))
     _end_to_end(tvi, "robertson", w, kw, offsets=w["offsets"])
+
+
+def test_robertson_headline_graph_end_to_end(tvi):
+    """The benchmark's timed step at full size in its launch configuration: one
+    captured graph of the forward pass at chunk 512 over two waves (128 lanes x
+    4 steps) summing each series' squares, the Frobenius loss from those sums,
+    and the adjoint at its own tiling (chunk 1024 over four waves) reading g =
+    y / L from the trajectory; its gradients against the oracle's forward +
+    adjoint on its own trajectory, and its loss against the trajectory's."""
+    from paper_2310_08649_amd import graph
+    w = W.robertson()
+    off = dev(w["offsets"], torch.int64)
+    print("robertson headline graph 512/128/4, adjoint 1024/256/4, fused", flush=True)
+    step = graph.CapturedStep("robertson", dev(w["y0"]), dev(w["times"]), dev(w["params"]), offsets=off,
+                              chunk=512, lanes=128, steps_per_lane=4, tol=PARITY_TOL, loss="frobenius",
+                              recompute=False, fused=True, adjoint_tiling=(1024, 256, 4)).capture()
+    step.replay()
+    torch.cuda.synchronize()
+    assert (host(step.status_fwd) == 0).all() and (host(step.status_adj) == 0).all()
+    yh = host(step.y)
+    L = float(step.loss.item())
+    assert abs(L - np.sqrt(np.sum(yh ** 2))) <= 1e-13 * L
+    _against_oracle_pipeline("robertson", w, w["offsets"], host(step.dLdp), host(step.dLdy0))
 
 
 @pytest.mark.parametrize("C", [1, 32, 100, 500])
