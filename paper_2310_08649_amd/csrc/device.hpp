@@ -212,7 +212,11 @@ __device__ __forceinline__ void matTvec_add(const R (&A)[N][N], const R (&x)[N],
 // pivot position by conditional (select) row exchanges, so every register
 // index stays static.  A is destroyed.  Returns false if a pivot is zero or
 // not finite.
-template <int N, class R>
+//
+// SKIP: the exchange's selects run only where some lane of the wave exchanges
+// (blocks I - dt j rarely need one); by default for blocks of 4 x 4 and more,
+// where the selects outnumber the test and branch.
+template <int N, class R, bool SKIP = (N >= 4)>
 __device__ __forceinline__ bool gj_solve(R (&A)[N][N], R (&X)[N][N])
 {
     bool ok = true;
@@ -221,9 +225,7 @@ __device__ __forceinline__ bool gj_solve(R (&A)[N][N], R (&X)[N][N])
 #pragma unroll
         for (int r = c + 1; r < N; ++r) {
             const bool sw = fabs(A[r][c]) > fabs(A[c][c]);
-            // larger blocks: the exchange's selects run only where some lane of
-            // the wave exchanges (blocks I - dt j rarely need one)
-            if (N < 4 || wave_any(sw)) {
+            if (!SKIP || wave_any(sw)) {
 #pragma unroll
                 for (int k = c; k < N; ++k) {
                     const R a = A[r][k], b = A[c][k];
@@ -259,11 +261,11 @@ __device__ __forceinline__ bool gj_solve(R (&A)[N][N], R (&X)[N][N])
 }
 
 // X = A^{-1} (A destroyed).
-template <int N, class R>
+template <int N, class R, bool SKIP = (N >= 4)>
 __device__ __forceinline__ bool invert(R (&A)[N][N], R (&X)[N][N])
 {
     set_identity(X);
-    return gj_solve(A, X);
+    return gj_solve<N, R, SKIP>(A, X);
 }
 
 // ---------------------------------------------------------------------------
@@ -463,7 +465,7 @@ __device__ __forceinline__ void seg_scan_down(AffineI<N, R> &a)
 
 // F of the inverse of the block D: I + F = D^{-1}, via Gauss-Jordan on D
 // (partial pivoting).  Returns false on a zero or non-finite pivot.
-template <int N, class R>
+template <int N, class R, bool SKIP = (N >= 4)>
 __device__ __forceinline__ bool invert_plus(R (&D)[N][N], R (&F)[N][N])
 {
     if constexpr (N == 2) {
@@ -477,7 +479,7 @@ __device__ __forceinline__ bool invert_plus(R (&D)[N][N], R (&F)[N][N])
         F[1][1] = fma(D[0][0], id, R(-1));
         return det != R(0) && finite(det) && finite(id);
     } else {
-        const bool ok = invert(D, F);
+        const bool ok = invert<N, R, SKIP>(D, F);
 #pragma unroll
         for (int i = 0; i < N; ++i) F[i][i] -= R(1);
         return ok;

@@ -370,7 +370,10 @@ struct WideNewton {
                     for (int r = 0; r < n; ++r)
 #pragma unroll
                         for (int c = 0; c < n; ++c) D[r][c] = ((r == c) ? 1.0 : 0.0) - hh[i] * J[r][c];
-                    ok &= invert_plus(D, Fi) ? 1 : 0;
+                    // the stiff blocks here (I - dt j of kinetics and oscillators) take
+                    // their pivots on the diagonal: the exchanges' selects are skipped
+                    // unless some lane of the wave needs one
+                    ok &= invert_plus<n, double, true>(D, Fi) ? 1 : 0;
 #pragma unroll
                     for (int r = 0; r < n; ++r)
 #pragma unroll
@@ -523,7 +526,7 @@ __global__ __launch_bounds__(W *kWave) void adjoint_kernel(SolveArgs<IO> a, cons
                 for (int r = 0; r < n; ++r)
 #pragma unroll
                     for (int cc = 0; cc < n; ++cc) D[r][cc] = ((r == cc) ? 1.0 : 0.0) - hl[i] * J[r][cc];
-                ok &= invert_plus(D, Fi[i]) ? 1 : 0;
+                ok &= invert_plus<n, double, true>(D, Fi[i]) ? 1 : 0;  // selects as in the forward pass
                 const double zero[n] = {};
                 apply_ip_t(Fi[i], gk, zero, wi[i]);
                 AffineI<n, double> stp;
