@@ -361,7 +361,9 @@ struct WideNewton {
             int ok = 1;
 #pragma unroll
             for (int i = 0; i < T; ++i) {
-                if (owned(q, i)) {
+                // wave-uniform: a lane past the attempt's end has h = 0 and R = 0 there,
+                // so it composes the identity exactly (F = 0, z = 0) with no selects
+                if (wave_any(owned(q, i))) {
                     double yv[n], J[n][n], D[n][n], Fi[n][n];
 #pragma unroll
                     for (int k = 0; k < n; ++k) yv[k] = ys[k] + dy[i][k];
