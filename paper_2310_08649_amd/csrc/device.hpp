@@ -215,8 +215,23 @@ __device__ __forceinline__ void matTvec_add(const R (&A)[N][N], const R (&x)[N],
 //
 // SKIP: the exchange's selects run only where some lane of the wave exchanges
 // (blocks I - dt j rarely need one); by default for blocks of 4 x 4 and more,
-// where the selects outnumber the test and branch.
-template <int N, class R, bool SKIP = (N >= 4)>
+// where the selects outnumber the test and branch.  RCP takes the pivot's
+// reciprocal in double from the hardware estimate and one Newton step
+// (r <- r + r (1 - p r)), within an ulp or so of 1/p, for a few instructions
+// instead of a correctly rounded division; a zero or non-finite pivot is
+// reported all the same.
+template <class R>
+__device__ __forceinline__ R pivot_reciprocal(R p)
+{
+    if constexpr (sizeof(R) == 8) {
+        const double r0 = __builtin_amdgcn_rcp(p);
+        return fma(r0, fma(-p, r0, 1.0), r0);
+    } else {
+        return R(1) / p;
+    }
+}
+
+template <int N, class R, bool SKIP = (N >= 4), bool RCP = false>
 __device__ __forceinline__ bool gj_solve(R (&A)[N][N], R (&X)[N][N])
 {
     bool ok = true;
@@ -242,7 +257,7 @@ __device__ __forceinline__ bool gj_solve(R (&A)[N][N], R (&X)[N][N])
         }
         const R piv = A[c][c];
         ok = ok && (piv != R(0)) && finite(piv);
-        const R ip = R(1) / piv;
+        const R ip = RCP ? pivot_reciprocal(piv) : R(1) / piv;
 #pragma unroll
         for (int k = c; k < N; ++k) A[c][k] *= ip;
 #pragma unroll
@@ -261,11 +276,11 @@ __device__ __forceinline__ bool gj_solve(R (&A)[N][N], R (&X)[N][N])
 }
 
 // X = A^{-1} (A destroyed).
-template <int N, class R, bool SKIP = (N >= 4)>
+template <int N, class R, bool SKIP = (N >= 4), bool RCP = false>
 __device__ __forceinline__ bool invert(R (&A)[N][N], R (&X)[N][N])
 {
     set_identity(X);
-    return gj_solve<N, R, SKIP>(A, X);
+    return gj_solve<N, R, SKIP, RCP>(A, X);
 }
 
 // ---------------------------------------------------------------------------
@@ -465,21 +480,21 @@ __device__ __forceinline__ void seg_scan_down(AffineI<N, R> &a)
 
 // F of the inverse of the block D: I + F = D^{-1}, via Gauss-Jordan on D
 // (partial pivoting).  Returns false on a zero or non-finite pivot.
-template <int N, class R, bool SKIP = (N >= 4)>
+template <int N, class R, bool SKIP = (N >= 4), bool RCP = false>
 __device__ __forceinline__ bool invert_plus(R (&D)[N][N], R (&F)[N][N])
 {
     if constexpr (N == 2) {
         // 2 x 2: the adjugate over the determinant (one division).  Elimination
         // with the pivot D00 forms the same determinant, D00 D11 - D01 D10.
         const R det = fma(D[0][0], D[1][1], -(D[0][1] * D[1][0]));
-        const R id = R(1) / det;
+        const R id = RCP ? pivot_reciprocal(det) : R(1) / det;
         F[0][0] = fma(D[1][1], id, R(-1));
         F[0][1] = -D[0][1] * id;
         F[1][0] = -D[1][0] * id;
         F[1][1] = fma(D[0][0], id, R(-1));
         return det != R(0) && finite(det) && finite(id);
     } else {
-        const bool ok = invert<N, R, SKIP>(D, F);
+        const bool ok = invert<N, R, SKIP, RCP>(D, F);
 #pragma unroll
         for (int i = 0; i < N; ++i) F[i][i] -= R(1);
         return ok;

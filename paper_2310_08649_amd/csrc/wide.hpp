@@ -375,7 +375,7 @@ struct WideNewton {
                     // the stiff blocks here (I - dt j of kinetics and oscillators) take
                     // their pivots on the diagonal: the exchanges' selects are skipped
                     // unless some lane of the wave needs one
-                    ok &= invert_plus<n, double, true>(D, Fi) ? 1 : 0;
+                    ok &= invert_plus<n, double, true, true>(D, Fi) ? 1 : 0;
 #pragma unroll
                     for (int r = 0; r < n; ++r)
 #pragma unroll
@@ -528,7 +528,7 @@ __global__ __launch_bounds__(W *kWave) void adjoint_kernel(SolveArgs<IO> a, cons
                 for (int r = 0; r < n; ++r)
 #pragma unroll
                     for (int cc = 0; cc < n; ++cc) D[r][cc] = ((r == cc) ? 1.0 : 0.0) - hl[i] * J[r][cc];
-                ok &= invert_plus<n, double, true>(D, Fi[i]) ? 1 : 0;  // selects as in the forward pass
+                ok &= invert_plus<n, double, true, true>(D, Fi[i]) ? 1 : 0;  // as in the forward pass
                 const double zero[n] = {};
                 apply_ip_t(Fi[i], gk, zero, wi[i]);
                 AffineI<n, double> stp;
