@@ -499,6 +499,7 @@ __global__ __launch_bounds__(W *kWave) void adjoint_kernel(SolveArgs<IO> a, cons
     // g_div: every entry of g divided by a device scalar (g = y / L of the
     // Frobenius loss read from the trajectory); multiplying by 1 is exact
     const double gsc = g_div ? 1.0 / *g_div : 1.0;
+    const bool g_is_y = a.g == a.y;  // g = y / L: the trajectory is read once
     int status = ST_OK;
 
     for (int64_t c = (sv.Nb + C - 1) / C - 1; c >= 0; --c) {  // workgroup-uniform
@@ -517,7 +518,7 @@ __global__ __launch_bounds__(W *kWave) void adjoint_kernel(SolveArgs<IO> a, cons
 #pragma unroll
             for (int e = 0; e < n; ++e) {
                 yl[i][e] = v ? ld(yb + k * n + e) : 0.0;
-                gk[e] = v ? ld(gb + k * n + e) * gsc : 0.0;
+                gk[e] = v ? (g_is_y ? yl[i][e] : ld(gb + k * n + e)) * gsc : 0.0;
             }
             tl[i] = v ? ld(sv.t + k) : 0.0;
             hl[i] = v ? tl[i] - ld(sv.t + k - 1) : 0.0;
