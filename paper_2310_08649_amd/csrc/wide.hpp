@@ -501,6 +501,7 @@ __global__ __launch_bounds__(W *kWave) void adjoint_kernel(SolveArgs<IO> a, cons
     const double gsc = g_div ? 1.0 / *g_div : 1.0;
     const bool g_is_y = a.g == a.y;  // g = y / L: the trajectory is read once
     int status = ST_OK;
+    int ok_all = 1;  // this lane's blocks were all invertible (reduced once, after the last chunk)
 
     for (int64_t c = (sv.Nb + C - 1) / C - 1; c >= 0; --c) {  // workgroup-uniform
         const int64_t s = c * C;
@@ -565,11 +566,11 @@ __global__ __launch_bounds__(W *kWave) void adjoint_kernel(SolveArgs<IO> a, cons
         }
         double first[n];
         vec_read_w(X, vq, 0, first);
-        ok = block_and(X, ok);
+        ok_all &= ok;
 #pragma unroll
         for (int k = 0; k < n; ++k) lam[k] = first[k];
-        if (!ok && status == ST_OK) status = ST_SINGULAR;
     }
+    if (!block_and(X, ok_all)) status = ST_SINGULAR;
 
     // dL/dy0 = g_0 + lam_1; dL/dp summed over the workgroup in a fixed order
 #pragma unroll
