@@ -1122,8 +1122,8 @@ def _predictor_robertson(ctx):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--config", default="",
                     help="chunk,lanes,steps_per_lane,init,adjoint (stored | recompute)[,cap[,adjoint chunk,"
                          "lanes,steps_per_lane]]: skip the autotuner")
