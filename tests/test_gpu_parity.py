@@ -671,3 +671,33 @@ def test_pcr_grid_stride(tvi, n, dtype, m, B):
         err = np.abs(x - ref).max(axis=(1, 2)) / np.abs(ref).max(axis=(1, 2))
         gate = 1e-12 if dtype == torch.float64 else 1e-5
         assert err.max() <= gate, (transpose, int(err.argmax()), float(err.max()))
+
+
+# --------------------------------------------------------------------------
+# PCR at the benchmark's size: 4 GiB of blocks and right-hand sides per launch,
+# 64 block rows, the benchmark's input recipe; sampled systems against the
+# oracle's block substitution
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n,dtype", [(2, torch.float64), (3, torch.float64), (4, torch.float64),
+                                     (2, torch.float32), (3, torch.float32), (4, torch.float32),
+                                     (8, torch.float32)])
+def test_pcr_full_size_sampled(tvi, n, dtype):
+    m = 64
+    es = torch.finfo(dtype).bits // 8
+    nb = (4 << 30) // (m * (n * n + 2 * n) * es)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    print("pcr full size n=%d %s systems=%d" % (n, dtype, nb), flush=True)
+    D = torch.eye(n, dtype=dtype, device="cuda").expand(nb, m, n, n).contiguous()
+    D.add_(torch.randn(D.shape, generator=gen, dtype=dtype, device="cuda"), alpha=0.2 / n)
+    r = torch.randn((nb, m, n), generator=gen, dtype=dtype, device="cuda")
+    x = tvi.pcr_solve(D, r)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(17 + n)
+    pick = torch.as_tensor(np.unique(np.concatenate([[0, nb - 1], rng.integers(0, nb, 200)])), device="cuda")
+    Dh, rh, xh = (host(t.index_select(0, pick)).astype(np.float64) for t in (D, r, x))
+    del D, r, x
+    torch.cuda.empty_cache()
+    ref = bb.thomas(Dh, rh)
+    err = np.abs(xh - ref).max(axis=(1, 2)) / np.abs(ref).max(axis=(1, 2))
+    assert err.max() <= (1e-12 if dtype == torch.float64 else 1e-4), float(err.max())
