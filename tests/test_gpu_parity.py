@@ -701,3 +701,35 @@ def test_pcr_full_size_sampled(tvi, n, dtype):
     ref = bb.thomas(Dh, rh)
     err = np.abs(xh - ref).max(axis=(1, 2)) / np.abs(ref).max(axis=(1, 2))
     assert err.max() <= (1e-12 if dtype == torch.float64 else 1e-4), float(err.max())
+
+
+# --------------------------------------------------------------------------
+# The chip-filling Van der Pol batch (65,536 series x 1000 steps on [0, 2]) in
+# the benchmark's tilings: sampled series against the oracle
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("C,S,T", [(50, 64, 1), (50, 16, 4), (50, 8, 8)])
+def test_vanderpol_chip_filling_sampled(tvi, C, S, T):
+    """Classified as the full-size test: within 1e-10 of the oracle, within 100x
+    the oracle's own rounding sensitivity, or a certified alternate root of one
+    step; none otherwise."""
+    w = W.vanderpol(B=65536, N=1000, t_end=2.0, seed=121)
+    print("vanderpol 65536 x 1000 chunk=%d lanes=%d steps_per_lane=%d" % (C, S, T), flush=True)
+    y, st, _, _ = tvi.solve_forward("vanderpol", dev(w["y0"]), dev(w["times"]), dev(w["params"]), chunk=C, lanes=S,
+                                    steps_per_lane=T, tol=PARITY_TOL)
+    rng = np.random.default_rng(21)
+    pick = np.unique(np.concatenate([[0, 65535], rng.integers(0, 65536, 254)]))
+    ws = dict(y0=w["y0"][pick], times=w["times"], params=w["params"][pick])
+    yo, so, _ = oracle.forward("vanderpol", ws["y0"], ws["times"], ws["params"], tol=PARITY_TOL)
+    y0p = ws["y0"] * (1.0 + 1e-13 * rng.choice([-1.0, 1.0], size=ws["y0"].shape))
+    yp, _, _ = oracle.forward("vanderpol", y0p, ws["times"], ws["params"], tol=PARITY_TOL)
+    yt, _, _ = oracle.forward("vanderpol", ws["y0"], ws["times"], ws["params"], tol=(1e-12, 1e-12))
+    clean = lambda a: np.nan_to_num(a, nan=0.0)
+    sens = np.maximum(series_rel_err(clean(yp), clean(yo)), series_rel_err(clean(yt), clean(yo)))
+    yh, sh = host(y)[pick], host(st)[pick]
+    match, cond, alt, bad, res = classify_vdp(yh, sh, ws, yo, so, sens, 1e-10, 1e-9)
+    print("%d within 1e-10, %d within the oracle's sensitivity, %d alternate roots, %d GPU / %d oracle failures"
+          % (match.sum(), cond.sum(), alt.sum(), (sh != 0).sum(), (so != 0).sum()), flush=True)
+    assert not bad.any()
+    assert match.sum() >= 0.85 * len(pick)
+    assert (sh != 0).sum() <= (so != 0).sum() + 2
+    assert (res[sh == 0] <= 1e-9).all()
