@@ -203,7 +203,11 @@ typedef struct {
                                   order[i] is solved in launch slot i.  Must be a
                                   permutation of 0..B-1 (entries outside [0, B)
                                   leave their slot idle; repeated entries give
-                                  undefined results).  See tvi_order_longest_first */
+                                  undefined results; a series no entry names is
+                                  not solved: its outputs are left unwritten, and
+                                  a shared-parameter gradient (the neural ODE's
+                                  dL/dtheta) is undefined).  See
+                                  tvi_order_longest_first                          */
     int32_t scheme;            /* tvi_scheme                                        */
     int32_t jacobian;          /* tvi_jacobian: how the state Jacobian j is formed   */
     int32_t reference_residual;/* the R0 of the relative test ||R|| <= tol_r ||R0||:
